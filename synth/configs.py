@@ -1,0 +1,154 @@
+"""Workload definitions and seeded input generators.
+
+Parameter values are the paper's (Janoschek, Toschi & Harting,
+arXiv:1005.2594) converted to lattice units, or the workload's own:
+
+* tau = 1, rho0 = 1 (Sec. IV: tau is always 1 and the density is 1 in
+  lattice units).
+* eps-bar = eps-bar_w = 0.05: 1.47e-15 J (Sec. IV) divided by the energy unit
+  dm dx^2/dt^2 with dx = 2/3 um, dt = 6.80e-8 s, dm = 3.05e-16 kg.
+* sigma = (12/11) R: the paper's ratio R_par/sigma_par = 11/12 (Sec. IV) with
+  the same aspect ratio for the cell-fluid and the cell-cell shapes.
+* sigma_w = 1/2 (Sec. III).
+* cell mass density rho_p: the paper gives none.  With the explicit
+  (leap-frog) coupling a flat (2.5, 1.0) cell at rho_p = rho0 is unstable:
+  its broadside added mass (8/3 a^3 ~ 42) exceeds its mass (26).  The
+  channel with 20 cells runs at rho_p = 2 (the smallest stable value tried,
+  closest to "equal to the fluid"); dense random suspensions need
+  rho_p >= 12 for 500 steps, so they use rho_p = 16.
+
+Random cells: positions uniform in the box, orientations uniform on SO(3)
+(normalised 4-D Gaussian quaternions), fluid at rest.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+EPS_LU = 0.05          # 1.47e-15 J in lattice units
+SIGMA_OVER_R = 12.0 / 11.0
+RHO_P_DILUTE = 2.0
+RHO_P_DENSE = 16.0
+
+
+def params(nx, ny, nz, **kw) -> dict:
+    """Base parameter dictionary (numbers only)."""
+    R_perp = kw.pop("R_perp", 2.5)
+    R_par = kw.pop("R_par", 1.0)
+    p = dict(
+        nx=int(nx), ny=int(ny), nz=int(nz), tau=1.0, rho0=1.0, wall_y=0,
+        wall_v_bot=(0.0, 0.0, 0.0), wall_v_top=(0.0, 0.0, 0.0),
+        force_mode=0, g=(0.0, 0.0, 0.0), f0=0.0, force_on_particles=1,
+        R_perp=R_perp, R_par=R_par,
+        sig_perp=SIGMA_OVER_R * R_perp, sig_par=SIGMA_OVER_R * R_par, sig_w=0.5,
+        eps=EPS_LU, eps_w=EPS_LU, r_cut=1.5 * max(R_perp, R_par), rho_p=1.0,
+    )
+    p.update(kw)
+    return p
+
+
+def random_quaternions(rng: np.random.Generator, n: int) -> np.ndarray:
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    return q
+
+
+def uniform_positions(rng, n, box, y_range=None) -> np.ndarray:
+    X = rng.random((n, 3)) * np.asarray(box, dtype=np.float64)
+    if y_range is not None:
+        X[:, 1] = y_range[0] + rng.random(n) * (y_range[1] - y_range[0])
+    return X
+
+
+def rsa_positions(rng, n, box, min_dist, y_range=None, periodic_y=True, max_tries=100000):
+    """Random sequential addition: uniform draws, rejected while a centre lies
+    closer than ``min_dist`` (minimum image) to an accepted one."""
+    box = np.asarray(box, dtype=np.float64)
+    out = np.empty((0, 3))
+    tries = 0
+    while out.shape[0] < n:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("random sequential addition did not converge")
+        x = uniform_positions(rng, 1, box, y_range)[0]
+        if out.shape[0]:
+            d = out - x
+            for a in range(3):
+                if a == 1 and not periodic_y:
+                    continue
+                d[:, a] -= box[a] * np.round(d[:, a] / box[a])
+            if np.min(np.einsum("ij,ij->i", d, d)) < min_dist * min_dist:
+                continue
+        out = np.vstack([out, x])
+    return out
+
+
+def cell_count(hematocrit, n_sites, R_perp, R_par) -> int:
+    """Number of cells whose nominal ellipsoid volume fills the given fraction."""
+    v_cell = 4.0 / 3.0 * math.pi * R_perp * R_perp * R_par
+    return int(round(hematocrit * n_sites / v_cell))
+
+
+def channel_walls(nx, ny, nz) -> np.ndarray:
+    m = np.zeros((nz, ny, nx), dtype=np.uint8)
+    m[:, 0, :] = 1
+    m[:, ny - 1, :] = 1
+    return m.reshape(-1)
+
+
+# ---------------------------------------------------------------- workloads
+def config1(seed=1):
+    """24x24x48 wall-bounded channel, 20 cells (2.5, 1.0), g = 1e-6 z, FP64,
+    100 steps.  Non-overlapping placement: bounding spheres of radius
+    sigma_perp kept apart, and clear of the wall planes by sigma_perp+sigma_w."""
+    p = params(24, 24, 48, wall_y=1, force_mode=1, g=(0.0, 0.0, 1e-6), rho_p=RHO_P_DILUTE)
+    rng = np.random.default_rng(seed)
+    clear = p["sig_perp"] + p["sig_w"]
+    X = rsa_positions(rng, 20, (24, 24, 48), 2.0 * p["sig_perp"], y_range=(clear, 23.0 - clear),
+                      periodic_y=False)
+    q = random_quaternions(rng, 20)
+    return dict(params=p, X=X, q=q, steps=100, precision="p64", name="channel 24x24x48, 20 cells")
+
+
+def kolmogorov(n, seed, hematocrit=0.4, f0=1e-6, steps=500, precision="p32"):
+    """n^3 periodic box, f_z = f0 sin(2 pi y / n), random overlapping cells."""
+    p = params(n, n, n, force_mode=2, f0=f0, rho_p=RHO_P_DENSE)
+    N = cell_count(hematocrit, n ** 3, p["R_perp"], p["R_par"])
+    rng = np.random.default_rng(seed)
+    X = uniform_positions(rng, N, (n, n, n))
+    q = random_quaternions(rng, N)
+    return dict(params=p, X=X, q=q, steps=steps, precision=precision,
+                name=f"kolmogorov {n}^3 Ht={hematocrit}")
+
+
+def config2(seed=2, n=256):
+    return kolmogorov(n, seed, precision="p32")
+
+
+def config3(seed=2, n=256):
+    return kolmogorov(n, seed, precision="pmx16")
+
+
+def config3_companion(seed=3, n=64):
+    return kolmogorov(n, seed, precision="pmx16")
+
+
+def config4(seed=4, n_channels=64):
+    """Uneven wall-bounded channels (W, W, Lz): W ~ U{32..96}, Lz ~ U{64..192},
+    Ht ~ U[0.1, 0.5], g ~ logU[1e-7, 1e-5]."""
+    rng = np.random.default_rng(seed)
+    chans = []
+    for c in range(n_channels):
+        W = int(rng.integers(32, 97))
+        Lz = int(rng.integers(64, 193))
+        Ht = float(rng.uniform(0.1, 0.5))
+        g = float(10.0 ** rng.uniform(-7.0, -5.0))
+        p = params(W, W, Lz, wall_y=1, force_mode=1, g=(0.0, 0.0, g), rho_p=RHO_P_DENSE)
+        n_fluid = W * (W - 2) * Lz
+        N = cell_count(Ht, n_fluid, p["R_perp"], p["R_par"])
+        clear = p["R_perp"]
+        X = uniform_positions(rng, N, (W, W, Lz), y_range=(clear, W - 1 - clear))
+        q = random_quaternions(rng, N)
+        chans.append(dict(params=p, X=X, q=q, hematocrit=Ht, g=g, width=W, length=Lz))
+    return chans
