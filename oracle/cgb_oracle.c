@@ -106,14 +106,19 @@ static void force_at(const orc_params* P, double y, double* g) {
     else if (P->force_mode == 2) { g[2] = P->f0 * sin(2.0 * M_PI * y / (double)P->ny); }
 }
 
-/* ---- equilibrium, Eq. 5 with c_s^2 = 1/3, written as n^eq - w*rho0 ---- */
-static void feq_dev(double rho0, double rho, const double* u, double* out) {
+/* ---- equilibrium, Eq. 5 with c_s^2 = 1/3, written as n^eq - w*rho0 ----
+ * drho = rho - rho0 is passed separately: it is the deviation sum itself,
+ * which forming rho - rho0 from the rounded rho would truncate to ulp(rho0) */
+static void feq_dev2(double drho, double rho, const double* u, double* out) {
     double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     for (int r = 0; r < 19; r++) {
         double cu = CV[r][0] * u[0] + CV[r][1] * u[1] + CV[r][2] * u[2];
         double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq + 4.5 * cu * cu * cu - 4.5 * usq * cu;
-        out[r] = WR[r] * ((rho - rho0) + rho * poly);
+        out[r] = WR[r] * (drho + rho * poly);
     }
+}
+static void feq_dev(double rho0, double rho, const double* u, double* out) {
+    feq_dev2(rho - rho0, rho, u, out);
 }
 
 void orc_equilibrium(double rho, const double* u, double* neq) {
@@ -145,7 +150,7 @@ static double collide(const orc_params* P, const double* d, const double* g, dou
     double rho = P->rho0 + drho;
     double u[3] = {(j[0] + 0.5 * g[0]) / rho, (j[1] + 0.5 * g[1]) / rho, (j[2] + 0.5 * g[2]) / rho};
     double eq[19];
-    feq_dev(P->rho0, rho, u, eq);
+    feq_dev2(drho, rho, u, eq);
     double pref = 1.0 - 0.5 / P->tau;
     for (int r = 0; r < 19; r++) {
         double cu = CV[r][0] * u[0] + CV[r][1] * u[1] + CV[r][2] * u[2];
