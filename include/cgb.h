@@ -1,0 +1,150 @@
+/*
+ * cgb.h -- C ABI of the MI355X (gfx950) implementation of the time step of the
+ * coarse-grained blood model of Janoschek, Toschi & Harting, "A simplified
+ * particulate model for coarse-grained hemodynamics simulations"
+ * (arXiv:1005.2594): a D3Q19 BGK lattice-Boltzmann plasma (Sec. II, Eqs. 1-8)
+ * coupled by mid-link / moving bounce-back (Eqs. 9-11) and momentum exchange
+ * (Eq. 12) to rigid oblate ellipsoidal cells that interact through
+ * Berne-Pechukas-scaled Hookean repulsions (Sec. III, Eqs. 15-20).
+ *
+ * Conventions
+ *  - Every call returns an int status: CGB_OK (0) or a negative CGB_E* code;
+ *    cgb_last_error() gives a message.  Nothing throws or aborts across the ABI.
+ *  - Lattice units.  Site index = x + nx*(y + ny*z).
+ *  - D3Q19 order (fixed): 0 rest; 1..6 = +x,-x,+y,-y,+z,-z; 7..18 = the face
+ *    diagonals (+x+y),(-x-y),(+x-y),(-x+y),(+x+z),(-x-z),(+x-z),(-x+z),
+ *    (+y+z),(-y-z),(+y-z),(-y+z).  Opposite directions are adjacent pairs.
+ *  - Populations cross the ABI as FP64 deviations d_r = n*_r - w_r*rho0 of the
+ *    post-collision populations, whatever the storage precision.
+ *  - All pointer arguments of cgb_set_* / cgb_get_* are HOST pointers owned by
+ *    the caller, with the sizes stated.  Device memory is owned by the handle.
+ *  - cgb_step is asynchronous on the handle's stream; device-side failures
+ *    (instability, overflow of a work list) surface at the next cgb_sync or
+ *    cgb_get_* call.
+ */
+#ifndef CGB_H
+#define CGB_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CGB_OK 0
+#define CGB_EINVAL (-1)    /* bad argument or unsupported size            */
+#define CGB_ENOMEM (-2)    /* device or host allocation failed            */
+#define CGB_EDEVICE (-3)   /* HIP runtime error                           */
+#define CGB_EUNSTABLE (-4) /* non-finite state, |u| > 0.4 or |V_a| >= 0.5 */
+#define CGB_ESTATE (-5)    /* call out of order (e.g. step before init)   */
+
+/* storage precision of the populations */
+#define CGB_P64 0      /* FP64 storage, FP64 collision                          */
+#define CGB_P32 1      /* FP32 storage, FP32 collision                          */
+#define CGB_PMX16 2    /* FP16 scaled deviations, FP32 collision                */
+#define CGB_PMXBF16 3  /* BF16 scaled deviations, FP32 collision                */
+/* In every precision the momentum exchange, the per-cell force/torque sums,
+ * the pair forces and the rigid-body integrator run in FP64. */
+
+typedef struct cgb_params {
+    int32_t nx, ny, nz;
+    double tau;           /* BGK relaxation time, Eq. 4; nu = (2 tau - 1)/6   */
+    double rho0;          /* reference density rho-bar (Sec. II)              */
+    int32_t wall_y;       /* 1: wall planes at y = 0 and y = ny-1             */
+    double wall_v_bot[3]; /* velocity of the plane y = 0 (Eq. 10)             */
+    double wall_v_top[3]; /* velocity of the plane y = ny-1 (Eq. 10)          */
+    int32_t force_mode;   /* 0 none, 1 constant g, 2 f0 sin(2 pi y/ny) e_z    */
+    double g[3];
+    double f0;
+    int32_t force_on_particles; /* 1: cells feel M f(Y) too                  */
+    double R_perp, R_par;       /* discretised ellipsoid half axes (Sec. II)  */
+    double sig_perp, sig_par;   /* potential size parameters (Eq. 18)         */
+    double sig_w;               /* wall sphere radius (Sec. III)              */
+    double eps, eps_w;          /* potential strengths                        */
+    double r_cut;               /* pair cut-off (hard truncation of Eq. 15)   */
+    double rho_p;               /* cell mass density                          */
+    int32_t precision;          /* CGB_P64 ... CGB_PMXBF16                    */
+    double pmx_scale;           /* PMX: stored value = d_r / w_r * pmx_scale;
+                                   0 selects 32768                            */
+} cgb_params;
+
+typedef struct cgb_sim cgb_sim;
+
+/* Fills *p with a 32^3 periodic box and the paper's parameters in lattice
+ * units (tau = 1, rho0 = 1, eps = eps_w = 0.05, sigma_w = 1/2). */
+int cgb_params_default(cgb_params* p);
+
+/* Creates a lattice.  wall_mask: nullable host array of nx*ny*nz bytes,
+ * nonzero = wall node (added to the planes selected by wall_y).
+ * stream: a hipStream_t to run on, or NULL to create a private stream.
+ * All lattice nodes start as fluid at rest with rho0. */
+int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_sim** out);
+void cgb_destroy(cgb_sim* s);
+const char* cgb_last_error(const cgb_sim* s);
+/* device bytes held by the handle */
+int64_t cgb_device_bytes(const cgb_sim* s);
+
+/* Cells (Sec. II): X n*3 centres, q n*4 unit quaternions (scalar first; the
+ * symmetry axis is R(q) e_z), V n*3 and L n*3 (space-frame angular momentum)
+ * at t-1/2 (nullable: zero), fixed n bytes (nullable; 1 = held at rest).
+ * Rasterises the cells from scratch: overlaps go to the lowest index, newly
+ * covered fluid is dropped, freed nodes get rest fluid at rho0. */
+int cgb_set_particles(cgb_sim* s, int32_t n, const double* X, const double* q,
+                      const double* V, const double* L, const uint8_t* fixed);
+
+/* Fluid at equilibrium (Eq. 5) with density rho (nullable: rho0, nsites) and
+ * velocity u (nullable: 0, nsites*3) on every non-wall node. */
+int cgb_init_fluid(cgb_sim* s, const double* rho, const double* u);
+/* Overwrites the stored post-collision deviations (19*nsites FP64), encoded
+ * to the storage precision. */
+int cgb_set_populations(cgb_sim* s, const double* d);
+
+/* Advances nsteps time steps (asynchronous).  One step: cell axes and angular
+ * velocities -> rasterisation with single occupancy -> cover/uncover with
+ * momentum bookkeeping (Sec. II) -> fused pull stream + bounce-back with the
+ * moving-boundary correction (Eqs. 9-11) + BGK collision with Guo forcing +
+ * momentum exchange per cell (Eq. 12, solid links Eqs. 13-14 folded in
+ * exactly) -> cell list -> pair and wall potentials (Eqs. 15-20) -> FP64
+ * leap-frog with quaternion rotation. */
+int cgb_step(cgb_sim* s, int32_t nsteps);
+/* Waits for the stream; returns CGB_EUNSTABLE if any step tripped the
+ * instability check (the first such step is in cgb_get_observables out[12]). */
+int cgb_sync(cgb_sim* s);
+
+/* Read-out (synchronises first).  Sizes: d 19*nsites; rho nsites; u nsites*3
+ * (u = (sum n* c - g/2)/rho, zero on non-fluid nodes); X,V,L n*3; q n*4;
+ * forces n*3 each (hydrodynamic incl. cover/uncover, and potential) of the
+ * last step; owner nsites (-2 wall, -1 fluid, p >= 0 cell); link mask
+ * nsites (bit r set: fluid node whose source x - c_r is not fluid). */
+int cgb_get_populations(cgb_sim* s, double* d);
+int cgb_get_fields(cgb_sim* s, double* rho, double* u);
+int cgb_get_particles(cgb_sim* s, double* X, double* q, double* V, double* L);
+int cgb_get_forces(cgb_sim* s, double* F_hyd, double* T_hyd, double* F_pot, double* T_pot);
+int cgb_get_owner(cgb_sim* s, int32_t* owner);
+int cgb_get_link_mask(cgb_sim* s, uint32_t* mask);
+/* Pair set {i<j : |X_i - X_j|^2 < r_cut^2} (minimum image) at the current
+ * positions, sorted.  ij holds up to cap pairs; *n receives the count. */
+int cgb_get_pairs(cgb_sim* s, int32_t* ij, int64_t cap, int64_t* n);
+/* out[0] fluid mass, out[1..3] sum over fluid of sum_r n*_r c_r,
+ * out[4..6] cell momentum sum M V, out[7] fluid node count,
+ * out[8..10] body force added to fluid + cells in the last step,
+ * out[11] step counter, out[12] first unstable step or -1. */
+int cgb_get_observables(cgb_sim* s, double* out /* 13 */);
+/* mean over non-wall nodes of the z velocity of the mixture, per y plane
+ * (fluid u_z, or the rigid velocity of the owning cell): prof[ny]. */
+int cgb_get_profile_z(cgb_sim* s, double* prof);
+
+/* Kernel timing with HIP events on the handle's stream.  enable = 1 starts
+ * recording, 0 stops.  cgb_kernel_times: for each of up to cap kernel names
+ * (NUL-separated into names, 64 bytes each) total milliseconds and launches
+ * since enabling; *n receives the number of entries. */
+int cgb_profile(cgb_sim* s, int enable);
+int cgb_kernel_times(cgb_sim* s, char* names, double* ms, int64_t* count, int32_t cap, int32_t* n);
+
+/* Checkpoint: stored populations (as stored), owner, cell state and the step
+ * counter.  Resume is bit-identical to an uninterrupted run. */
+int cgb_save(cgb_sim* s, const char* path);
+int cgb_load(cgb_sim* s, const char* path);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,251 @@
+"""ctypes binding of libcgb.so (``include/cgb.h``): argument marshalling only.
+
+Every step of the method runs in the HIP kernels of the library; there is no
+host fallback.  Importing this module on a machine without the built library
+raises ``ImportError``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcgb.so")
+
+P64, P32, PMX16, PMXBF16 = 0, 1, 2, 3
+PRECISIONS = {"p64": P64, "p32": P32, "pmx16": PMX16, "pmxbf16": PMXBF16}
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSTABLE", -5: "ESTATE"}
+
+
+class CgbParams(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("tau", C.c_double), ("rho0", C.c_double),
+        ("wall_y", C.c_int32),
+        ("wall_v_bot", C.c_double * 3), ("wall_v_top", C.c_double * 3),
+        ("force_mode", C.c_int32), ("g", C.c_double * 3), ("f0", C.c_double),
+        ("force_on_particles", C.c_int32),
+        ("R_perp", C.c_double), ("R_par", C.c_double),
+        ("sig_perp", C.c_double), ("sig_par", C.c_double), ("sig_w", C.c_double),
+        ("eps", C.c_double), ("eps_w", C.c_double),
+        ("r_cut", C.c_double), ("rho_p", C.c_double),
+        ("precision", C.c_int32), ("pmx_scale", C.c_double),
+    ]
+
+
+class CgbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cgb {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+VP = C.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1005_2594_amd.build")
+    L = C.CDLL(LIB_PATH)
+    L.cgb_params_default.argtypes = [C.POINTER(CgbParams)]
+    L.cgb_create.argtypes = [C.POINTER(CgbParams), VP, VP, C.POINTER(VP)]
+    L.cgb_destroy.argtypes = [VP]
+    L.cgb_destroy.restype = None
+    L.cgb_last_error.argtypes = [VP]
+    L.cgb_last_error.restype = C.c_char_p
+    L.cgb_device_bytes.argtypes = [VP]
+    L.cgb_device_bytes.restype = C.c_int64
+    L.cgb_set_particles.argtypes = [VP, C.c_int32, VP, VP, VP, VP, VP]
+    L.cgb_init_fluid.argtypes = [VP, VP, VP]
+    L.cgb_set_populations.argtypes = [VP, VP]
+    L.cgb_step.argtypes = [VP, C.c_int32]
+    L.cgb_sync.argtypes = [VP]
+    L.cgb_get_populations.argtypes = [VP, VP]
+    L.cgb_get_fields.argtypes = [VP, VP, VP]
+    L.cgb_get_particles.argtypes = [VP, VP, VP, VP, VP]
+    L.cgb_get_forces.argtypes = [VP, VP, VP, VP, VP]
+    L.cgb_get_owner.argtypes = [VP, VP]
+    L.cgb_get_link_mask.argtypes = [VP, VP]
+    L.cgb_get_pairs.argtypes = [VP, VP, C.c_int64, C.POINTER(C.c_int64)]
+    L.cgb_get_observables.argtypes = [VP, VP]
+    L.cgb_get_profile_z.argtypes = [VP, VP]
+    L.cgb_profile.argtypes = [VP, C.c_int]
+    L.cgb_kernel_times.argtypes = [VP, VP, VP, VP, C.c_int32, C.POINTER(C.c_int32)]
+    L.cgb_save.argtypes = [VP, C.c_char_p]
+    L.cgb_load.argtypes = [VP, C.c_char_p]
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(VP)
+
+
+def _f64(a, shape=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a.reshape(shape) if shape is not None else a
+
+
+def make_params(d: dict, precision=None) -> CgbParams:
+    p = CgbParams()
+    lib().cgb_params_default(C.byref(p))
+    for name, _ in CgbParams._fields_:
+        if name not in d:
+            continue
+        v = d[name]
+        if isinstance(v, (list, tuple, np.ndarray)):
+            arr = getattr(p, name)
+            for i, x in enumerate(v):
+                arr[i] = float(x)
+        else:
+            setattr(p, name, v)
+    if precision is not None:
+        p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return p
+
+
+class Sim:
+    """One lattice with its cells on the GPU (one ``cgb_sim`` handle)."""
+
+    def __init__(self, params: dict, wall_mask=None, precision=None, stream=None):
+        self._p = make_params(params, precision)
+        self.nx, self.ny, self.nz = self._p.nx, self._p.ny, self._p.nz
+        self.ns = self.nx * self.ny * self.nz
+        self.n = 0
+        h = VP()
+        wm = None if wall_mask is None else np.ascontiguousarray(wall_mask, dtype=np.uint8).reshape(-1)
+        st = None if stream is None else VP(int(stream))
+        rc = lib().cgb_create(C.byref(self._p), _ptr(wm), st, C.byref(h))
+        if rc != 0:
+            raise CgbError(rc, "cgb_create failed")
+        self.h = h
+
+    # -- lifecycle
+    def close(self):
+        if getattr(self, "h", None):
+            lib().cgb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc):
+        if rc != 0:
+            raise CgbError(rc, lib().cgb_last_error(self.h).decode())
+
+    @property
+    def device_bytes(self):
+        return int(lib().cgb_device_bytes(self.h))
+
+    # -- set-up
+    def set_particles(self, X, q, V=None, L=None, fixed=None):
+        X = _f64(X, (-1, 3)); q = _f64(q, (-1, 4))
+        n = X.shape[0]
+        V = _f64(V, (n, 3)); L = _f64(L, (n, 3))
+        fx = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+        self._check(lib().cgb_set_particles(self.h, n, _ptr(X), _ptr(q), _ptr(V), _ptr(L), _ptr(fx)))
+        self.n = n
+
+    def init_fluid(self, rho=None, u=None):
+        rho = _f64(rho, (-1,)); u = _f64(u, (-1, 3))
+        self._check(lib().cgb_init_fluid(self.h, _ptr(rho), _ptr(u)))
+
+    def set_populations(self, d):
+        d = _f64(d, (19, self.ns))
+        self._check(lib().cgb_set_populations(self.h, _ptr(d)))
+
+    # -- stepping
+    def step(self, n=1):
+        self._check(lib().cgb_step(self.h, int(n)))
+
+    def sync(self):
+        self._check(lib().cgb_sync(self.h))
+
+    # -- read-out
+    def populations(self):
+        d = np.empty((19, self.ns))
+        self._check(lib().cgb_get_populations(self.h, _ptr(d)))
+        return d
+
+    def fields(self):
+        rho = np.empty(self.ns); u = np.empty((self.ns, 3))
+        self._check(lib().cgb_get_fields(self.h, _ptr(rho), _ptr(u)))
+        return rho, u
+
+    def particles(self):
+        n = self.n
+        X = np.empty((n, 3)); q = np.empty((n, 4)); V = np.empty((n, 3)); L = np.empty((n, 3))
+        self._check(lib().cgb_get_particles(self.h, _ptr(X), _ptr(q), _ptr(V), _ptr(L)))
+        return X, q, V, L
+
+    def forces(self):
+        a = [np.empty((self.n, 3)) for _ in range(4)]
+        self._check(lib().cgb_get_forces(self.h, *[_ptr(x) for x in a]))
+        return tuple(a)
+
+    def owner(self):
+        o = np.empty(self.ns, dtype=np.int32)
+        self._check(lib().cgb_get_owner(self.h, _ptr(o)))
+        return o
+
+    def link_mask(self):
+        m = np.empty(self.ns, dtype=np.uint32)
+        self._check(lib().cgb_get_link_mask(self.h, _ptr(m)))
+        return m
+
+    def pairs(self):
+        n = C.c_int64()
+        self._check(lib().cgb_get_pairs(self.h, None, 0, C.byref(n)))
+        ij = np.empty((max(n.value, 1), 2), dtype=np.int32)
+        self._check(lib().cgb_get_pairs(self.h, _ptr(ij), n.value, C.byref(n)))
+        return ij[: n.value]
+
+    def observables(self):
+        o = np.empty(13)
+        self._check(lib().cgb_get_observables(self.h, _ptr(o)))
+        return {"mass": o[0], "fluid_momentum": o[1:4].copy(), "particle_momentum": o[4:7].copy(),
+                "n_fluid": int(o[7]), "body_force_last": o[8:11].copy(), "step": int(o[11]),
+                "bad_step": int(o[12])}
+
+    def profile_z(self):
+        p = np.empty(self.ny)
+        self._check(lib().cgb_get_profile_z(self.h, _ptr(p)))
+        return p
+
+    # -- timing
+    def profile(self, enable=True):
+        self._check(lib().cgb_profile(self.h, 1 if enable else 0))
+
+    def kernel_times(self):
+        cap = 32
+        names = C.create_string_buffer(64 * cap)
+        ms = np.zeros(cap); cnt = np.zeros(cap, dtype=np.int64); n = C.c_int32()
+        self._check(lib().cgb_kernel_times(self.h, names, _ptr(ms), _ptr(cnt), cap, C.byref(n)))
+        out = {}
+        for k in range(n.value):
+            nm = names.raw[64 * k: 64 * (k + 1)].split(b"\0", 1)[0].decode()
+            out[nm] = (float(ms[k]), int(cnt[k]))
+        return out
+
+    # -- checkpoint
+    def save(self, path):
+        self._check(lib().cgb_save(self.h, str(path).encode()))
+
+    def load(self, path):
+        self._check(lib().cgb_load(self.h, str(path).encode()))

@@ -1,0 +1,248 @@
+// cgb_dev.h -- device-side definitions shared by the HIP kernels of libcgb.
+//
+// D3Q19 tables (Sec. II: 19 velocities, weights 1/3, 1/18, 1/36 by |c|, Eq. 6),
+// storage codecs for the population deviations, and the argument block every
+// kernel receives by value.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/cgb.h"
+
+namespace cgb {
+
+// velocity components, order: rest, +-x, +-y, +-z, then the face diagonals
+// with opposites adjacent
+__host__ __device__ constexpr int CX(int r) {
+    constexpr int v[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return v[r];
+}
+__host__ __device__ constexpr int CY(int r) {
+    constexpr int v[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return v[r];
+}
+__host__ __device__ constexpr int CZ(int r) {
+    constexpr int v[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    return v[r];
+}
+__host__ __device__ constexpr int OPP(int r) { return r == 0 ? 0 : ((r & 1) ? r + 1 : r - 1); }
+__host__ __device__ constexpr double WD(int r) { return r == 0 ? 1.0 / 3.0 : (r <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+// node flag word: bit 31 = node is not fluid (cell or wall); bit r (1..18) =
+// fluid node whose pull source x - c_r is not fluid
+constexpr uint32_t NONFLUID = 0x80000000u;
+constexpr uint32_t LINKBITS = 0x0007FFFEu;
+constexpr int32_t OWN_WALL = -2;
+constexpr int32_t OWN_FLUID = -1;
+constexpr int32_t NO_CAND = 0x7fffffff;
+
+// status word bits
+constexpr int ST_UNSTABLE = 1;
+constexpr int ST_TRANS_OVERFLOW = 2;
+constexpr int ST_PAIR_OVERFLOW = 4;
+
+struct DevArgs {
+    // lattice
+    int nx, ny, nz;
+    long long ns;       // sites
+    long long pstride;  // elements between direction planes
+    int wall_y;
+    int moving_walls;
+    double wvb[3], wvt[3];
+    double tau, rho0;
+    int force_mode;
+    double g[3];
+    double f0;
+    int force_on_particles;
+    // storage
+    int precision;
+    float pmx_scale, pmx_inv;  // PMX: stored = d / w * scale
+    void* A;        // populations read this step  [19][pstride]
+    void* B;        // populations written this step
+    void* rhoA;     // density deviation field read (for Eq. 10)
+    void* rhoB;     // density deviation field written
+    int32_t* owner;
+    uint32_t* flags;
+    int32_t* cand;
+    // particles
+    int n;
+    double* X;      // n*3
+    double* q;      // n*4
+    double* V;      // n*3
+    double* L;      // n*3
+    uint8_t* fixed;
+    double* Xprev;  // n*3, position of the last rasterisation
+    double* kin;    // n*12: X, V, Omega, axis (gathered by the LB kernel)
+    double* FTh;    // n*6 hydrodynamic force, torque (accumulated)
+    double* FTp;    // n*6 potential force, torque
+    double M, Ipar, Iperp;
+    double iRpar2, iRperp2, Rb;
+    // transitions
+    int* trans;     // 3 ints per transition: site, old, new
+    int* ntrans;
+    int trans_cap;
+    // cell list
+    int nb[3];
+    double bedge[3];
+    int* pbin;      // n
+    int* bin_count; // nbins
+    int* bin_start; // nbins+1
+    int* bin_fill;  // nbins
+    int* bin_idx;   // n
+    int* wall_start;// nbins+1 (surface wall nodes per bin)
+    int* wall_idx;  // site indices
+    int nbins;
+    double r_cut2;
+    double wall_range2;
+    double sig_perp, sig_par, sig_w, eps, eps_w;
+    // bookkeeping
+    int* status;
+    int* bad_step;
+    long long step;
+    double* body_part; // 3: body force added to cells this step
+};
+
+__host__ __device__ inline int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// ------------------------------------------------------------ codecs
+// P64 / P32: plain values.  PMX: d / w_r * scale stored in FP16 or BF16 with
+// round-to-nearest-even; decode multiplies by w_r / scale.
+__device__ inline uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN stays NaN
+    uint32_t rounding = 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)((u + rounding) >> 16);
+}
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+template <int P> struct Codec;
+template <> struct Codec<CGB_P64> {
+    using T = double;
+    using R = double;
+    __device__ static R dec(T v, R) { return v; }
+    __device__ static T enc(R v, R) { return v; }
+};
+template <> struct Codec<CGB_P32> {
+    using T = float;
+    using R = float;
+    __device__ static R dec(T v, R) { return v; }
+    __device__ static T enc(R v, R) { return v; }
+};
+template <> struct Codec<CGB_PMX16> {
+    using T = _Float16;
+    using R = float;
+    __device__ static R dec(T v, R s) { return (float)v * s; }
+    __device__ static T enc(R v, R s) { return (_Float16)(v * s); }
+};
+template <> struct Codec<CGB_PMXBF16> {
+    using T = uint16_t;
+    using R = float;
+    __device__ static R dec(T v, R s) { return bf16_to_f32(v) * s; }
+    __device__ static T enc(R v, R s) { return f32_to_bf16_rne(v * s); }
+};
+
+// per-direction decode / encode scales
+template <int P>
+__device__ inline typename Codec<P>::R dec_scale(const DevArgs& a, int r) {
+    using R = typename Codec<P>::R;
+    if constexpr (P == CGB_PMX16 || P == CGB_PMXBF16) return (R)(WD(r) * (double)a.pmx_inv);
+    else return (R)1;
+}
+template <int P>
+__device__ inline typename Codec<P>::R enc_scale(const DevArgs& a, int r) {
+    using R = typename Codec<P>::R;
+    if constexpr (P == CGB_PMX16 || P == CGB_PMXBF16) return (R)((double)a.pmx_scale / WD(r));
+    else return (R)1;
+}
+template <int P>
+__device__ inline typename Codec<P>::R rho_dec_scale(const DevArgs& a) {
+    using R = typename Codec<P>::R;
+    if constexpr (P == CGB_PMX16 || P == CGB_PMXBF16) return (R)a.pmx_inv;
+    else return (R)1;
+}
+template <int P>
+__device__ inline typename Codec<P>::R rho_enc_scale(const DevArgs& a) {
+    using R = typename Codec<P>::R;
+    if constexpr (P == CGB_PMX16 || P == CGB_PMXBF16) return (R)a.pmx_scale;
+    else return (R)1;
+}
+
+// ------------------------------------------------------------ geometry
+// Axis o = R(q) e_z and the inside test are evaluated without contraction so
+// that node ownership is bit-identical to any reference that evaluates the
+// same expressions in the same order.
+__device__ inline void axis_of(const double* q, double* o) {
+#pragma clang fp contract(off)
+    o[0] = 2.0 * (q[1] * q[3] + q[0] * q[2]);
+    o[1] = 2.0 * (q[2] * q[3] - q[0] * q[1]);
+    o[2] = q[0] * q[0] - q[1] * q[1] - q[2] * q[2] + q[3] * q[3];
+}
+
+__device__ inline double min_image(double d, double L) {
+    if (d >= 0.5 * L) d -= L;
+    else if (d < -0.5 * L) d += L;
+    return d;
+}
+
+// displacement node - X (minimum image on periodic axes)
+__device__ inline void node_disp(const DevArgs& a, int x, int y, int z, const double* X, double* d) {
+#pragma clang fp contract(off)
+    d[0] = min_image((double)x - X[0], (double)a.nx);
+    d[1] = a.wall_y ? ((double)y - X[1]) : min_image((double)y - X[1], (double)a.ny);
+    d[2] = min_image((double)z - X[2], (double)a.nz);
+}
+
+__device__ inline bool inside_test(const DevArgs& a, const double* d, const double* o) {
+#pragma clang fp contract(off)
+    double dp = d[0] * o[0] + d[1] * o[1] + d[2] * o[2];
+    double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    double val = dp * dp * a.iRpar2 + (dd - dp * dp) * a.iRperp2;
+    return val < 1.0;
+}
+
+__device__ inline void body_force(const DevArgs& a, double y, double* g) {
+    g[0] = g[1] = g[2] = 0.0;
+    if (a.force_mode == 1) { g[0] = a.g[0]; g[1] = a.g[1]; g[2] = a.g[2]; }
+    else if (a.force_mode == 2) g[2] = a.f0 * sin(2.0 * M_PI * y / (double)a.ny);
+}
+
+__device__ inline void cross3(const double* a, const double* b, double* c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// 64-lane sum of a double (all lanes receive the total)
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace cgb
+
+// host-side launchers implemented in the kernel translation units
+namespace cgb {
+struct LaunchCfg {
+    int bx, by;  // LB tile: threads along x and y
+};
+hipError_t launch_lb(const DevArgs& a, LaunchCfg cfg, hipStream_t st);
+hipError_t launch_prep(const DevArgs& a, hipStream_t st);
+hipError_t launch_kin(const DevArgs& a, hipStream_t st);
+hipError_t launch_clear_cells(const DevArgs& a, hipStream_t st);
+hipError_t launch_raster(const DevArgs& a, hipStream_t st, bool fresh);
+hipError_t launch_transitions(const DevArgs& a, hipStream_t st, bool bookkeeping);
+hipError_t launch_cells(const DevArgs& a, hipStream_t st);
+hipError_t launch_potentials(const DevArgs& a, hipStream_t st);
+hipError_t launch_integrate(const DevArgs& a, hipStream_t st);
+hipError_t launch_flags_rebuild(const DevArgs& a, hipStream_t st);
+hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st);
+hipError_t launch_fill_f64(double* p, long long n, double v, hipStream_t st);
+hipError_t launch_encode(const DevArgs& a, const double* d, hipStream_t st);
+hipError_t launch_decode(const DevArgs& a, double* d, hipStream_t st);
+hipError_t launch_equilibrium_fill(const DevArgs& a, const double* rho, const double* u, hipStream_t st);
+hipError_t launch_fields(const DevArgs& a, double* rho, double* u, hipStream_t st);
+hipError_t launch_observables(const DevArgs& a, double* partial, int nblk, hipStream_t st);
+hipError_t launch_profile_z(const DevArgs& a, double* prof, double* cnt, hipStream_t st);
+hipError_t launch_pairs(const DevArgs& a, int* out, int* count, int cap, hipStream_t st);
+}  // namespace cgb

@@ -1,0 +1,187 @@
+// fields.hip -- population codec, equilibrium initialisation and read-out
+// reductions (moments of Eqs. 7-8, mass, momentum, velocity profile).
+#include "cgb_dev.h"
+
+namespace cgb {
+
+// FP64 deviations [19][ns] -> storage, and the density deviation field
+template <int P>
+__global__ void encode_kernel(DevArgs a, const double* d) {
+    using Cd = Codec<P>;
+    using T = typename Cd::T;
+    using R = typename Cd::R;
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (s >= a.ns) return;
+    T* A = (T*)a.A;
+    R rs = 0;
+    for (int r = 0; r < 19; r++) {
+        const T v = Cd::enc((R)d[r * a.ns + s], enc_scale<P>(a, r));
+        A[r * a.pstride + s] = v;
+        rs += Cd::dec(v, dec_scale<P>(a, r));
+    }
+    ((T*)a.rhoA)[s] = Cd::enc(rs, rho_enc_scale<P>(a));
+}
+
+template <int P>
+__global__ void decode_kernel(DevArgs a, double* d) {
+    using Cd = Codec<P>;
+    using T = typename Cd::T;
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (s >= a.ns) return;
+    const T* A = (const T*)a.A;
+    for (int r = 0; r < 19; r++) d[r * a.ns + s] = (double)Cd::dec(A[r * a.pstride + s], dec_scale<P>(a, r));
+}
+
+// Eq. 5 at (rho, u) on every non-wall node, written as n^eq - w rho0
+template <int P>
+__global__ void equilibrium_kernel(DevArgs a, const double* rho, const double* u) {
+    using Cd = Codec<P>;
+    using T = typename Cd::T;
+    using R = typename Cd::R;
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (s >= a.ns) return;
+    T* A = (T*)a.A;
+    const bool wall = a.owner[s] == OWN_WALL;
+    const double rr = rho ? rho[s] : a.rho0;
+    const double ux = u ? u[3 * s] : 0.0, uy = u ? u[3 * s + 1] : 0.0, uz = u ? u[3 * s + 2] : 0.0;
+    const double usq = ux * ux + uy * uy + uz * uz;
+    R rs = 0;
+    for (int r = 0; r < 19; r++) {
+        const double cu = CX(r) * ux + CY(r) * uy + CZ(r) * uz;
+        const double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq + 4.5 * cu * cu * cu - 4.5 * usq * cu;
+        const double eq = wall ? 0.0 : WD(r) * ((rr - a.rho0) + rr * poly);
+        const T v = Cd::enc((R)eq, enc_scale<P>(a, r));
+        A[r * a.pstride + s] = v;
+        rs += Cd::dec(v, dec_scale<P>(a, r));
+    }
+    ((T*)a.rhoA)[s] = Cd::enc(rs, rho_enc_scale<P>(a));
+}
+
+// rho = rho0 + sum d, u = (sum d c - g/2) / rho on fluid nodes
+template <int P>
+__global__ void fields_kernel(DevArgs a, double* rho, double* u) {
+    using Cd = Codec<P>;
+    using T = typename Cd::T;
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (s >= a.ns) return;
+    if (a.owner[s] != OWN_FLUID) {
+        if (rho) rho[s] = 0.0;
+        if (u) { u[3 * s] = 0.0; u[3 * s + 1] = 0.0; u[3 * s + 2] = 0.0; }
+        return;
+    }
+    const T* A = (const T*)a.A;
+    double drho = 0, j[3] = {0, 0, 0};
+    for (int r = 0; r < 19; r++) {
+        const double v = (double)Cd::dec(A[r * a.pstride + s], dec_scale<P>(a, r));
+        drho += v;
+        j[0] += v * CX(r); j[1] += v * CY(r); j[2] += v * CZ(r);
+    }
+    const double rr = a.rho0 + drho;
+    double g[3];
+    body_force(a, (double)((s / a.nx) % a.ny), g);
+    if (rho) rho[s] = rr;
+    if (u) for (int c = 0; c < 3; c++) u[3 * s + c] = (j[c] - 0.5 * g[c]) / rr;
+}
+
+// per-block partial sums: mass, momentum (3), fluid count, body force (3)
+template <int P>
+__global__ void __launch_bounds__(256) observables_kernel(DevArgs a, double* partial) {
+    using Cd = Codec<P>;
+    using T = typename Cd::T;
+    __shared__ double red[8][256];
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const T* A = (const T*)a.A;
+    for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < a.ns; s += (long long)gridDim.x * blockDim.x) {
+        if (a.owner[s] != OWN_FLUID) continue;
+        double drho = 0;
+        for (int r = 0; r < 19; r++) {
+            const double v = (double)Cd::dec(A[r * a.pstride + s], dec_scale<P>(a, r));
+            drho += v;
+            acc[1] += v * CX(r); acc[2] += v * CY(r); acc[3] += v * CZ(r);
+        }
+        acc[0] += a.rho0 + drho;
+        acc[4] += 1.0;
+        double g[3];
+        body_force(a, (double)((s / a.nx) % a.ny), g);
+        acc[5] += g[0]; acc[6] += g[1]; acc[7] += g[2];
+    }
+    for (int k = 0; k < 8; k++) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int off = 128; off >= 1; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int k = 0; k < 8; k++) red[k][threadIdx.x] += red[k][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 8; k++) partial[8 * blockIdx.x + k] = red[k][0];
+}
+
+// mixture z velocity summed per y plane, and the node count per plane
+template <int P>
+__global__ void profile_kernel(DevArgs a, double* prof, double* cnt) {
+    using Cd = Codec<P>;
+    using T = typename Cd::T;
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (s >= a.ns) return;
+    const int o = a.owner[s];
+    if (o == OWN_WALL) return;
+    const int x = (int)(s % a.nx), y = (int)((s / a.nx) % a.ny), z = (int)(s / ((long long)a.nx * a.ny));
+    double uz;
+    if (o == OWN_FLUID) {
+        const T* A = (const T*)a.A;
+        double drho = 0, jz = 0;
+        for (int r = 0; r < 19; r++) {
+            const double v = (double)Cd::dec(A[r * a.pstride + s], dec_scale<P>(a, r));
+            drho += v;
+            jz += v * CZ(r);
+        }
+        double g[3];
+        body_force(a, (double)y, g);
+        uz = (jz - 0.5 * g[2]) / (a.rho0 + drho);
+    } else {
+        const double* k = a.kin + 12 * (long long)o;
+        double d[3];
+        node_disp(a, x, y, z, k, d);
+        uz = k[5] + (k[6] * d[1] - k[7] * d[0]);
+    }
+    unsafeAtomicAdd(prof + y, uz);
+    unsafeAtomicAdd(cnt + y, 1.0);
+}
+
+#define CGB_DISPATCH(KERNEL, GRID, BLOCK, ...)                                                       \
+    switch (a.precision) {                                                                           \
+        case CGB_P64: hipLaunchKernelGGL(KERNEL<CGB_P64>, GRID, BLOCK, 0, st, __VA_ARGS__); break;   \
+        case CGB_P32: hipLaunchKernelGGL(KERNEL<CGB_P32>, GRID, BLOCK, 0, st, __VA_ARGS__); break;   \
+        case CGB_PMX16: hipLaunchKernelGGL(KERNEL<CGB_PMX16>, GRID, BLOCK, 0, st, __VA_ARGS__); break; \
+        case CGB_PMXBF16: hipLaunchKernelGGL(KERNEL<CGB_PMXBF16>, GRID, BLOCK, 0, st, __VA_ARGS__); break; \
+        default: return hipErrorInvalidValue;                                                        \
+    }
+
+static dim3 site_grid(const DevArgs& a) { return dim3((unsigned)((a.ns + 255) / 256)); }
+
+hipError_t launch_encode(const DevArgs& a, const double* d, hipStream_t st) {
+    CGB_DISPATCH(encode_kernel, site_grid(a), dim3(256), a, d);
+    return hipGetLastError();
+}
+hipError_t launch_decode(const DevArgs& a, double* d, hipStream_t st) {
+    CGB_DISPATCH(decode_kernel, site_grid(a), dim3(256), a, d);
+    return hipGetLastError();
+}
+hipError_t launch_equilibrium_fill(const DevArgs& a, const double* rho, const double* u, hipStream_t st) {
+    CGB_DISPATCH(equilibrium_kernel, site_grid(a), dim3(256), a, rho, u);
+    return hipGetLastError();
+}
+hipError_t launch_fields(const DevArgs& a, double* rho, double* u, hipStream_t st) {
+    CGB_DISPATCH(fields_kernel, site_grid(a), dim3(256), a, rho, u);
+    return hipGetLastError();
+}
+hipError_t launch_observables(const DevArgs& a, double* partial, int nblk, hipStream_t st) {
+    CGB_DISPATCH(observables_kernel, dim3(nblk), dim3(256), a, partial);
+    return hipGetLastError();
+}
+hipError_t launch_profile_z(const DevArgs& a, double* prof, double* cnt, hipStream_t st) {
+    CGB_DISPATCH(profile_kernel, site_grid(a), dim3(256), a, prof, cnt);
+    return hipGetLastError();
+}
+
+}  // namespace cgb

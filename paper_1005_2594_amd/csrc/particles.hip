@@ -1,0 +1,638 @@
+// particles.hip -- cell-side kernels of the time step.
+//
+//  prep         axis o = R(q) e_z and space-frame angular velocity of each cell
+//  raster       two passes over each cell's bounding box: (1) every node inside
+//               the discretised ellipsoid (Sec. II: half axes R_par along o,
+//               R_perp across) records the lowest covering index; (2) each
+//               node is resolved once, by its current owner or by the lowest
+//               coverer of a fluid node: the owner keeps a node while it is
+//               still inside it (single occupancy, first arrival keeps the
+//               node), otherwise the lowest coverer takes it, otherwise it
+//               becomes fluid.  Changes go to a transition list.
+//  transitions  apply owner changes, update node flags, and balance the deleted
+//               (covered) or created (freed, Eq. 5 at rho0 and the rigid-body
+//               velocity) fluid momentum with a force and torque on the cell.
+//  cells        cell list with bin edge >= cut-off (counting sort, bins sorted
+//               by index for a deterministic order).
+//  potentials   Berne-Pechukas pair forces (Eqs. 15-18) and cell-wall forces
+//               (Eqs. 19-20), one thread per cell over its 27 neighbour bins.
+//  integrate    FP64 leap-frog: V += F/M, X += V, L += T, quaternion rotation
+//               by an explicit midpoint step.
+#include "cgb_dev.h"
+
+namespace cgb {
+
+// ------------------------------------------------------------------ prep
+__global__ void prep_kernel(DevArgs a, int zero_forces) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    double q[4] = {a.q[4 * p], a.q[4 * p + 1], a.q[4 * p + 2], a.q[4 * p + 3]};
+    double o[3];
+    axis_of(q, o);
+    const double* L = a.L + 3 * p;
+    const double oL = o[0] * L[0] + o[1] * L[1] + o[2] * L[2];
+    const double kk = 1.0 / a.Ipar - 1.0 / a.Iperp;
+    double* k = a.kin + 12 * (long long)p;
+    for (int c = 0; c < 3; c++) {
+        k[c] = a.X[3 * p + c];
+        k[3 + c] = a.V[3 * p + c];
+        k[6 + c] = L[c] / a.Iperp + kk * oL * o[c];
+        k[9 + c] = o[c];
+    }
+    if (zero_forces)
+        for (int c = 0; c < 6; c++) { a.FTh[6 * p + c] = 0.0; a.FTp[6 * p + c] = 0.0; }
+}
+
+hipError_t launch_prep(const DevArgs& a, hipStream_t st) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(prep_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_kin(const DevArgs& a, hipStream_t st) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(prep_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a, 0);
+    return hipGetLastError();
+}
+
+// all cell nodes become fluid at rest (rho0); used before a fresh rasterisation
+template <int P>
+__global__ void clear_cells_kernel(DevArgs a) {
+    using Cd = Codec<P>;
+    using T = typename Cd::T;
+    using R = typename Cd::R;
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (s >= a.ns) return;
+    a.cand[s] = NO_CAND;
+    if (a.owner[s] < 0) return;
+    a.owner[s] = OWN_FLUID;
+    T* A = (T*)a.A;
+    for (int r = 0; r < 19; r++) A[r * a.pstride + s] = Cd::enc((R)0, enc_scale<P>(a, r));
+    ((T*)a.rhoA)[s] = Cd::enc((R)0, rho_enc_scale<P>(a));
+}
+
+hipError_t launch_clear_cells(const DevArgs& a, hipStream_t st) {
+    dim3 g((unsigned)((a.ns + 255) / 256)), b(256);
+    switch (a.precision) {
+        case CGB_P64: hipLaunchKernelGGL(clear_cells_kernel<CGB_P64>, g, b, 0, st, a); break;
+        case CGB_P32: hipLaunchKernelGGL(clear_cells_kernel<CGB_P32>, g, b, 0, st, a); break;
+        case CGB_PMX16: hipLaunchKernelGGL(clear_cells_kernel<CGB_PMX16>, g, b, 0, st, a); break;
+        case CGB_PMXBF16: hipLaunchKernelGGL(clear_cells_kernel<CGB_PMXBF16>, g, b, 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ raster
+// union of the bounding boxes at the previous and the current position
+__device__ inline void union_box(const DevArgs& a, int p, int* lo, int* ext) {
+    for (int c = 0; c < 3; c++) {
+        double x0 = a.Xprev[3 * p + c];
+        const double x1 = a.X[3 * p + c];
+        if (c != 1 || !a.wall_y) {
+            // a cell that crossed the periodic boundary: unwrap the old position
+            const double Lb = c == 0 ? a.nx : (c == 1 ? a.ny : a.nz);
+            const double d = x0 - x1;
+            if (d > 0.5 * Lb) x0 -= Lb;
+            else if (d < -0.5 * Lb) x0 += Lb;
+        }
+        const double mn = x0 < x1 ? x0 : x1, mx = x0 < x1 ? x1 : x0;
+        lo[c] = (int)floor(mn - a.Rb);
+        ext[c] = (int)ceil(mx + a.Rb) - lo[c] + 1;
+    }
+}
+
+__device__ inline bool box_node(const DevArgs& a, const int* lo, const int* ext, int k, int* x, int* y, int* z) {
+    const int ix = k % ext[0];
+    const int iy = (k / ext[0]) % ext[1];
+    const int iz = k / (ext[0] * ext[1]);
+    int yy = lo[1] + iy;
+    if (a.wall_y) {
+        if (yy < 0 || yy >= a.ny) return false;
+    } else {
+        yy = ((yy % a.ny) + a.ny) % a.ny;
+    }
+    *x = ((lo[0] + ix) % a.nx + a.nx) % a.nx;
+    *y = yy;
+    *z = ((lo[2] + iz) % a.nz + a.nz) % a.nz;
+    return true;
+}
+
+__device__ inline bool covers(const DevArgs& a, int p, int x, int y, int z) {
+    double d[3], o[3];
+    const double* k = a.kin + 12 * (long long)p;
+    node_disp(a, x, y, z, k, d);
+    o[0] = k[9]; o[1] = k[10]; o[2] = k[11];
+    return inside_test(a, d, o);
+}
+
+// one wave per cell
+__global__ void __launch_bounds__(64) raster_cover_kernel(DevArgs a) {
+    const int p = blockIdx.x;
+    if (p >= a.n) return;
+    int lo[3], ext[3];
+    union_box(a, p, lo, ext);
+    const int tot = ext[0] * ext[1] * ext[2];
+    for (int k = threadIdx.x; k < tot; k += 64) {
+        int x, y, z;
+        if (!box_node(a, lo, ext, k, &x, &y, &z)) continue;
+        const long long s = x + (long long)a.nx * (y + (long long)a.ny * z);
+        if (a.owner[s] == OWN_WALL) continue;
+        if (covers(a, p, x, y, z)) atomicMin(a.cand + s, p);
+    }
+}
+
+__global__ void __launch_bounds__(64) raster_resolve_kernel(DevArgs a) {
+    const int p = blockIdx.x;
+    if (p >= a.n) return;
+    int lo[3], ext[3];
+    union_box(a, p, lo, ext);
+    const int tot = ext[0] * ext[1] * ext[2];
+    for (int k = threadIdx.x; k < tot; k += 64) {
+        int x, y, z;
+        if (!box_node(a, lo, ext, k, &x, &y, &z)) continue;
+        const long long s = x + (long long)a.nx * (y + (long long)a.ny * z);
+        const int o = a.owner[s];
+        if (o == OWN_WALL) continue;
+        const int c = a.cand[s];
+        const bool mine = (o == p) || (o == OWN_FLUID && c == p);
+        if (!mine) continue;
+        const bool keep = (o == p) && covers(a, p, x, y, z);
+        const int nw = keep ? p : (c != NO_CAND ? c : OWN_FLUID);
+        a.cand[s] = NO_CAND;
+        if (nw != o) {
+            const int t = atomicAdd(a.ntrans, 1);
+            if (t < a.trans_cap) {
+                a.trans[3 * t] = (int)s;
+                a.trans[3 * t + 1] = o;
+                a.trans[3 * t + 2] = nw;
+            } else {
+                atomicOr(a.status, ST_TRANS_OVERFLOW);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) a.Xprev[3 * p + threadIdx.x] = a.X[3 * p + threadIdx.x];
+}
+
+__global__ void zero_int_kernel(int* p) { *p = 0; }
+
+hipError_t launch_raster(const DevArgs& a, hipStream_t st, bool) {
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, a.ntrans);
+    if (a.n == 0) return hipGetLastError();
+    hipLaunchKernelGGL(raster_cover_kernel, dim3(a.n), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(raster_resolve_kernel, dim3(a.n), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ transitions
+template <int P>
+__device__ void transition_one(const DevArgs& a, int t, bool book) {
+    using Cd = Codec<P>;
+    using T = typename Cd::T;
+    using R = typename Cd::R;
+    const long long s = a.trans[3 * t];
+    const int o = a.trans[3 * t + 1], nw = a.trans[3 * t + 2];
+    const int x = (int)(s % a.nx), y = (int)((s / a.nx) % a.ny), z = (int)(s / ((long long)a.nx * a.ny));
+    T* A = (T*)a.A;
+    a.owner[s] = nw;
+    const bool was_fluid = (o == OWN_FLUID), is_fluid = (nw == OWN_FLUID);
+    if (was_fluid != is_fluid) {
+        atomicXor(a.flags + s, NONFLUID);
+        for (int r = 1; r < 19; r++) {
+            const int xn = wrap(x + CX(r), a.nx), yn = wrap(y + CY(r), a.ny), zn = wrap(z + CZ(r), a.nz);
+            const long long tn = xn + (long long)a.nx * (yn + (long long)a.ny * zn);
+            atomicXor(a.flags + tn, 1u << r);
+        }
+    }
+    if (was_fluid && !is_fluid) {
+        if (!book) return;
+        // covered: the deleted fluid momentum goes to the cell
+        double m[3] = {0, 0, 0};
+        for (int r = 0; r < 19; r++) {
+            const double v = (double)Cd::dec(A[r * a.pstride + s], dec_scale<P>(a, r));
+            m[0] += v * CX(r); m[1] += v * CY(r); m[2] += v * CZ(r);
+        }
+        double d[3], tq[3];
+        node_disp(a, x, y, z, a.kin + 12 * (long long)nw, d);
+        cross3(d, m, tq);
+        double* F = a.FTh + 6 * (long long)nw;
+        for (int c = 0; c < 3; c++) { unsafeAtomicAdd(F + c, m[c]); unsafeAtomicAdd(F + 3 + c, tq[c]); }
+    } else if (!was_fluid && is_fluid) {
+        if (!book) {
+            for (int r = 0; r < 19; r++) A[r * a.pstride + s] = Cd::enc((R)0, enc_scale<P>(a, r));
+            ((T*)a.rhoA)[s] = Cd::enc((R)0, rho_enc_scale<P>(a));
+            return;
+        }
+        // freed: fluid at rho0 with the rigid-body velocity of the cell
+        const double* k = a.kin + 12 * (long long)o;
+        double d[3], us[3];
+        node_disp(a, x, y, z, k, d);
+        cross3(k + 6, d, us);
+        for (int c = 0; c < 3; c++) us[c] += k[3 + c];
+        const double usq = us[0] * us[0] + us[1] * us[1] + us[2] * us[2];
+        double m[3] = {0, 0, 0};
+        R rs = 0;
+        for (int r = 0; r < 19; r++) {
+            const double cu = CX(r) * us[0] + CY(r) * us[1] + CZ(r) * us[2];
+            const double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq + 4.5 * cu * cu * cu - 4.5 * usq * cu;
+            const double eq = WD(r) * (0.0 + a.rho0 * poly);
+            const T stv = Cd::enc((R)eq, enc_scale<P>(a, r));
+            A[r * a.pstride + s] = stv;
+            const R back = Cd::dec(stv, dec_scale<P>(a, r));
+            rs += back;
+            m[0] += (double)back * CX(r); m[1] += (double)back * CY(r); m[2] += (double)back * CZ(r);
+        }
+        ((T*)a.rhoA)[s] = Cd::enc(rs, rho_enc_scale<P>(a));
+        double tq[3];
+        cross3(d, m, tq);
+        double* F = a.FTh + 6 * (long long)o;
+        for (int c = 0; c < 3; c++) { unsafeAtomicAdd(F + c, -m[c]); unsafeAtomicAdd(F + 3 + c, -tq[c]); }
+    }
+}
+
+template <int P>
+__global__ void transitions_kernel(DevArgs a, int book) {
+    const int cnt = min(*a.ntrans, a.trans_cap);
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x)
+        transition_one<P>(a, t, book != 0);
+}
+
+hipError_t launch_transitions(const DevArgs& a, hipStream_t st, bool book) {
+    dim3 g(512), b(256);
+    switch (a.precision) {
+        case CGB_P64: hipLaunchKernelGGL(transitions_kernel<CGB_P64>, g, b, 0, st, a, (int)book); break;
+        case CGB_P32: hipLaunchKernelGGL(transitions_kernel<CGB_P32>, g, b, 0, st, a, (int)book); break;
+        case CGB_PMX16: hipLaunchKernelGGL(transitions_kernel<CGB_PMX16>, g, b, 0, st, a, (int)book); break;
+        case CGB_PMXBF16: hipLaunchKernelGGL(transitions_kernel<CGB_PMXBF16>, g, b, 0, st, a, (int)book); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ flags
+__global__ void flags_rebuild_kernel(DevArgs a) {
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (s >= a.ns) return;
+    const int x = (int)(s % a.nx), y = (int)((s / a.nx) % a.ny), z = (int)(s / ((long long)a.nx * a.ny));
+    uint32_t f = (a.owner[s] != OWN_FLUID) ? NONFLUID : 0u;
+    for (int r = 1; r < 19; r++) {
+        const int xs = wrap(x - CX(r), a.nx), ys = wrap(y - CY(r), a.ny), zs = wrap(z - CZ(r), a.nz);
+        if (a.owner[xs + (long long)a.nx * (ys + (long long)a.ny * zs)] != OWN_FLUID) f |= 1u << r;
+    }
+    a.flags[s] = f;
+}
+
+hipError_t launch_flags_rebuild(const DevArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(flags_rebuild_kernel, dim3((unsigned)((a.ns + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ fills
+__global__ void fill_i32_kernel(int* p, long long n, int v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void fill_f64_kernel(double* p, long long n, double v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) p[i] = v;
+}
+hipError_t launch_fill_i32(int* p, long long n, int v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    long long nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)nb), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+hipError_t launch_fill_f64(double* p, long long n, double v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    long long nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)nb), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ cell list
+__device__ inline int bin_coord(const DevArgs& a, int c, double v) {
+    int b = (int)floor(v / a.bedge[c]);
+    if (b < 0) b = 0;
+    if (b >= a.nb[c]) b = a.nb[c] - 1;
+    return b;
+}
+
+__global__ void bin_count_kernel(DevArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const int bx = bin_coord(a, 0, a.X[3 * p]), by = bin_coord(a, 1, a.X[3 * p + 1]), bz = bin_coord(a, 2, a.X[3 * p + 2]);
+    const int b = bx + a.nb[0] * (by + a.nb[1] * bz);
+    a.pbin[p] = b;
+    atomicAdd(a.bin_count + b, 1);
+}
+
+// exclusive scan of bin_count into bin_start[0..nbins] by one block of 1024
+// threads: each thread scans a contiguous chunk, the chunk totals are scanned
+// in LDS, then each chunk is written with its offset
+__global__ void __launch_bounds__(1024) bin_scan_kernel(DevArgs a) {
+    __shared__ int tot[1024];
+    const int n = a.nbins;
+    const int chunk = (n + 1023) / 1024;
+    const int t = threadIdx.x;
+    const int b0 = t * chunk, b1 = min(n, b0 + chunk);
+    int s = 0;
+    for (int b = b0; b < b1; b++) s += a.bin_count[b];
+    tot[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int v = t >= off ? tot[t - off] : 0;
+        __syncthreads();
+        tot[t] += v;
+        __syncthreads();
+    }
+    int run = t ? tot[t - 1] : 0;
+    for (int b = b0; b < b1; b++) {
+        a.bin_start[b] = run;
+        run += a.bin_count[b];
+        a.bin_fill[b] = 0;
+    }
+    if (t == 1023) a.bin_start[n] = tot[1023];
+}
+
+__global__ void bin_fill_kernel(DevArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const int b = a.pbin[p];
+    const int pos = a.bin_start[b] + atomicAdd(a.bin_fill + b, 1);
+    a.bin_idx[pos] = p;
+}
+
+__global__ void bin_sort_kernel(DevArgs a) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.nbins) return;
+    const int s = a.bin_start[b], e = a.bin_start[b + 1];
+    for (int i = s + 1; i < e; i++) {
+        const int v = a.bin_idx[i];
+        int j = i - 1;
+        while (j >= s && a.bin_idx[j] > v) { a.bin_idx[j + 1] = a.bin_idx[j]; j--; }
+        a.bin_idx[j + 1] = v;
+    }
+}
+
+hipError_t launch_cells(const DevArgs& a, hipStream_t st) {
+    if (a.n == 0) return hipSuccess;
+    hipError_t e = launch_fill_i32(a.bin_count, a.nbins, 0, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bin_count_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL(bin_fill_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(bin_sort_kernel, dim3((a.nbins + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// neighbour bin offsets along one axis (deduplicated for fewer than 3 bins;
+// clipped at the wall planes)
+__device__ inline int axis_bins(const DevArgs& a, int c, int b, int* out) {
+    const int nb = a.nb[c];
+    const bool periodic = !(c == 1 && a.wall_y);
+    int k = 0;
+    if (!periodic) {
+        for (int d = -1; d <= 1; d++) if (b + d >= 0 && b + d < nb) out[k++] = b + d;
+        return k;
+    }
+    if (nb >= 3) { out[0] = wrap(b - 1, nb); out[1] = b; out[2] = wrap(b + 1, nb); return 3; }
+    for (int i = 0; i < nb; i++) out[k++] = i;
+    return k;
+}
+
+// squared length evaluated exactly as written (pair membership is decided
+// bit-identically to a reference evaluating the same expression)
+__device__ inline double dist2_exact(const double* rv) {
+#pragma clang fp contract(off)
+    return rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
+}
+
+// ------------------------------------------------------------------ potentials
+// Berne-Pechukas pair term for rvec = X_i - X_j.  U = eps (1 - r/sigma)^2,
+// eps = eps-bar / sqrt(1 - chi^2 g^2) (Eq. 16), sigma = sigma-bar /
+// sqrt(1 - chi/2 [(a+b)^2/(1+chi g) + (a-b)^2/(1-chi g)]) (Eq. 17) with
+// a = r.o_i, b = r.o_j, g = o_i.o_j.  Returns -dU/dX_i and -o_i x dU/do_i.
+__device__ void pair_term(const DevArgs& a, const double* rv, const double* oi, const double* oj,
+                          double* F, double* Ti) {
+    const double r2 = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
+    if (r2 == 0.0) return;
+    const double r = sqrt(r2);
+    const double ir = 1.0 / r;
+    const double e[3] = {rv[0] * ir, rv[1] * ir, rv[2] * ir};
+    const double sp2 = a.sig_perp * a.sig_perp, sl2 = a.sig_par * a.sig_par;
+    const double chi = (sl2 - sp2) / (sl2 + sp2);
+    const double sbar = 2.0 * a.sig_perp;
+    const double ca = e[0] * oi[0] + e[1] * oi[1] + e[2] * oi[2];
+    const double cb = e[0] * oj[0] + e[1] * oj[1] + e[2] * oj[2];
+    const double g = oi[0] * oj[0] + oi[1] * oj[1] + oi[2] * oj[2];
+    const double ip = 1.0 / (1.0 + chi * g), iq = 1.0 / (1.0 - chi * g);
+    const double sp = ca + cb, sm = ca - cb;
+    const double S = sp * sp * ip + sm * sm * iq;
+    const double sigma = sbar / sqrt(1.0 - 0.5 * chi * S);
+    if (r >= sigma) return;
+    const double e1 = 1.0 - chi * chi * g * g;
+    const double eps = a.eps / sqrt(e1);
+    const double s = 1.0 - r / sigma;
+    const double dUdr = -2.0 * eps * s / sigma;
+    // dU/dS through sigma: (2 eps s r / sigma^2) * chi sigma^3 / (4 sbar^2)
+    const double K = (2.0 * eps * s * r / (sigma * sigma)) * (0.25 * chi * sigma * sigma * sigma / (sbar * sbar));
+    const double Sa = 2.0 * sp * ip + 2.0 * sm * iq;
+    const double Sb = 2.0 * sp * ip - 2.0 * sm * iq;
+    const double Sg = -chi * sp * sp * ip * ip + chi * sm * sm * iq * iq;
+    const double deps = a.eps * chi * chi * g / (e1 * sqrt(e1));
+    for (int c = 0; c < 3; c++)
+        F[c] -= dUdr * e[c] + K * (Sa * (oi[c] - ca * e[c]) + Sb * (oj[c] - cb * e[c])) * ir;
+    double gi[3];
+    for (int c = 0; c < 3; c++) gi[c] = K * (Sa * e[c] + Sg * oj[c]) + s * s * deps * oj[c];
+    double t[3];
+    cross3(oi, gi, t);
+    for (int c = 0; c < 3; c++) Ti[c] -= t[c];
+}
+
+// cell-wall term for rvec = X_i - x_wall (Eqs. 19-20)
+__device__ void wall_term(const DevArgs& a, const double* rv, const double* o, double* F, double* Ti) {
+    const double r2 = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
+    if (r2 == 0.0) return;
+    const double r = sqrt(r2);
+    const double ir = 1.0 / r;
+    const double e[3] = {rv[0] * ir, rv[1] * ir, rv[2] * ir};
+    const double sp2 = a.sig_perp * a.sig_perp, sl2 = a.sig_par * a.sig_par, sw2 = a.sig_w * a.sig_w;
+    const double sbw = sqrt(sp2 + sw2);
+    const double chiw = (sl2 - sp2) / (sl2 + sw2);
+    const double ca = e[0] * o[0] + e[1] * o[1] + e[2] * o[2];
+    const double den = 1.0 - chiw * ca * ca;
+    if (den <= 0.0) return;
+    const double sigma = sbw / sqrt(den);
+    if (r >= sigma) return;
+    const double s = 1.0 - r / sigma;
+    const double dUdr = -2.0 * a.eps_w * s / sigma;
+    const double K = (2.0 * a.eps_w * s * r / (sigma * sigma)) * (chiw * ca * sigma * sigma * sigma / (sbw * sbw));
+    for (int c = 0; c < 3; c++) F[c] -= dUdr * e[c] + K * (o[c] - ca * e[c]) * ir;
+    double ke[3] = {K * e[0], K * e[1], K * e[2]}, t[3];
+    cross3(o, ke, t);
+    for (int c = 0; c < 3; c++) Ti[c] -= t[c];
+}
+
+__global__ void potentials_kernel(DevArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const double Xi[3] = {a.X[3 * i], a.X[3 * i + 1], a.X[3 * i + 2]};
+    const double* ki = a.kin + 12 * (long long)i;
+    const double oi[3] = {ki[9], ki[10], ki[11]};
+    double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+    const int b = a.pbin[i];
+    const int bxi = b % a.nb[0], byi = (b / a.nb[0]) % a.nb[1], bzi = b / (a.nb[0] * a.nb[1]);
+    int lx[3], ly[3], lz[3];
+    const int nxb = axis_bins(a, 0, bxi, lx), nyb = axis_bins(a, 1, byi, ly), nzb = axis_bins(a, 2, bzi, lz);
+    for (int iz = 0; iz < nzb; iz++)
+        for (int iy = 0; iy < nyb; iy++)
+            for (int ix = 0; ix < nxb; ix++) {
+                const int bb = lx[ix] + a.nb[0] * (ly[iy] + a.nb[1] * lz[iz]);
+                for (int t = a.bin_start[bb]; t < a.bin_start[bb + 1]; t++) {
+                    const int j = a.bin_idx[t];
+                    if (j == i) continue;
+                    double rv[3];
+                    rv[0] = min_image(Xi[0] - a.X[3 * j], (double)a.nx);
+                    rv[1] = a.wall_y ? (Xi[1] - a.X[3 * j + 1]) : min_image(Xi[1] - a.X[3 * j + 1], (double)a.ny);
+                    rv[2] = min_image(Xi[2] - a.X[3 * j + 2], (double)a.nz);
+                    if (!(dist2_exact(rv) < a.r_cut2)) continue;
+                    const double* kj = a.kin + 12 * (long long)j;
+                    const double oj[3] = {kj[9], kj[10], kj[11]};
+                    pair_term(a, rv, oi, oj, F, T);
+                }
+                for (int t = a.wall_start[bb]; t < a.wall_start[bb + 1]; t++) {
+                    const long long w = a.wall_idx[t];
+                    const int wx = (int)(w % a.nx), wy = (int)((w / a.nx) % a.ny), wz = (int)(w / ((long long)a.nx * a.ny));
+                    double nd[3];
+                    node_disp(a, wx, wy, wz, Xi, nd);
+                    const double rv[3] = {-nd[0], -nd[1], -nd[2]};
+                    const double r2 = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
+                    if (!(r2 < a.wall_range2)) continue;
+                    wall_term(a, rv, oi, F, T);
+                }
+            }
+    for (int c = 0; c < 3; c++) { a.FTp[6 * i + c] = F[c]; a.FTp[6 * i + 3 + c] = T[c]; }
+}
+
+hipError_t launch_potentials(const DevArgs& a, hipStream_t st) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(potentials_kernel, dim3((a.n + 127) / 128), dim3(128), 0, st, a);
+    return hipGetLastError();
+}
+
+__global__ void pairs_kernel(DevArgs a, int* out, int* count, int cap) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const double Xi[3] = {a.X[3 * i], a.X[3 * i + 1], a.X[3 * i + 2]};
+    const int b = a.pbin[i];
+    const int bxi = b % a.nb[0], byi = (b / a.nb[0]) % a.nb[1], bzi = b / (a.nb[0] * a.nb[1]);
+    int lx[3], ly[3], lz[3];
+    const int nxb = axis_bins(a, 0, bxi, lx), nyb = axis_bins(a, 1, byi, ly), nzb = axis_bins(a, 2, bzi, lz);
+    for (int iz = 0; iz < nzb; iz++)
+        for (int iy = 0; iy < nyb; iy++)
+            for (int ix = 0; ix < nxb; ix++) {
+                const int bb = lx[ix] + a.nb[0] * (ly[iy] + a.nb[1] * lz[iz]);
+                for (int t = a.bin_start[bb]; t < a.bin_start[bb + 1]; t++) {
+                    const int j = a.bin_idx[t];
+                    if (j <= i) continue;
+                    double rv[3];
+                    rv[0] = min_image(Xi[0] - a.X[3 * j], (double)a.nx);
+                    rv[1] = a.wall_y ? (Xi[1] - a.X[3 * j + 1]) : min_image(Xi[1] - a.X[3 * j + 1], (double)a.ny);
+                    rv[2] = min_image(Xi[2] - a.X[3 * j + 2], (double)a.nz);
+                    if (!(dist2_exact(rv) < a.r_cut2)) continue;
+                    const int pos = atomicAdd(count, 1);
+                    if (pos < cap) { out[2 * pos] = i; out[2 * pos + 1] = j; }
+                }
+            }
+}
+
+hipError_t launch_pairs(const DevArgs& a, int* out, int* count, int cap, hipStream_t st) {
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, count);
+    if (a.n == 0) return hipGetLastError();
+    hipLaunchKernelGGL(pairs_kernel, dim3((a.n + 127) / 128), dim3(128), 0, st, a, out, count, cap);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ integrate
+__device__ inline void qmul(const double* a, const double* b, double* c) {
+    c[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+    c[1] = a[0] * b[1] + b[0] * a[1] + a[2] * b[3] - a[3] * b[2];
+    c[2] = a[0] * b[2] + b[0] * a[2] + a[3] * b[1] - a[1] * b[3];
+    c[3] = a[0] * b[3] + b[0] * a[3] + a[1] * b[2] - a[2] * b[1];
+}
+__device__ inline void qrot(const double* w, double h, double* dq) {
+    const double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    if (wn == 0.0) { dq[0] = 1; dq[1] = dq[2] = dq[3] = 0; return; }
+    const double ang = 0.5 * wn * h;
+    const double sn = sin(ang) / wn;
+    dq[0] = cos(ang); dq[1] = sn * w[0]; dq[2] = sn * w[1]; dq[3] = sn * w[2];
+}
+__device__ inline void qnormalise(double* q) {
+    const double n = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int c = 0; c < 4; c++) q[c] /= n;
+}
+__device__ inline void omega_sym(const DevArgs& a, const double* o, const double* L, double* w) {
+    const double oL = o[0] * L[0] + o[1] * L[1] + o[2] * L[2];
+    const double kk = 1.0 / a.Ipar - 1.0 / a.Iperp;
+    for (int c = 0; c < 3; c++) w[c] = L[c] / a.Iperp + kk * oL * o[c];
+}
+
+__global__ void integrate_kernel(DevArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    if (a.fixed[p]) {
+        for (int c = 0; c < 3; c++) { a.V[3 * p + c] = 0.0; a.L[3 * p + c] = 0.0; }
+        return;
+    }
+    double gb[3] = {0, 0, 0};
+    if (a.force_on_particles) body_force(a, a.X[3 * p + 1], gb);
+    bool bad = false;
+    double Lnew[3];
+    for (int c = 0; c < 3; c++) {
+        const double F = a.FTh[6 * p + c] + a.FTp[6 * p + c] + a.M * gb[c];
+        const double v = a.V[3 * p + c] + F / a.M;
+        a.V[3 * p + c] = v;
+        Lnew[c] = a.L[3 * p + c] + (a.FTh[6 * p + 3 + c] + a.FTp[6 * p + 3 + c]);
+        a.L[3 * p + c] = Lnew[c];
+        if (!(fabs(v) < 0.5)) bad = true;
+        double xn = a.X[3 * p + c] + v;
+        if (!(c == 1 && a.wall_y)) {
+            const double Lb = c == 0 ? a.nx : (c == 1 ? a.ny : a.nz);
+            if (xn >= Lb) xn -= Lb;
+            else if (xn < 0.0) xn += Lb;
+        }
+        a.X[3 * p + c] = xn;
+    }
+    if (a.force_on_particles && a.force_mode) {
+        unsafeAtomicAdd(a.body_part + 0, a.M * gb[0]);
+        unsafeAtomicAdd(a.body_part + 1, a.M * gb[1]);
+        unsafeAtomicAdd(a.body_part + 2, a.M * gb[2]);
+    }
+    // quaternion: half-step predictor, then full step with the midpoint rate
+    double q[4] = {a.q[4 * p], a.q[4 * p + 1], a.q[4 * p + 2], a.q[4 * p + 3]};
+    double o[3], w[3], dq[4], qh[4], qn[4];
+    axis_of(q, o);
+    omega_sym(a, o, Lnew, w);
+    qrot(w, 0.5, dq);
+    qmul(dq, q, qh);
+    qnormalise(qh);
+    axis_of(qh, o);
+    omega_sym(a, o, Lnew, w);
+    qrot(w, 1.0, dq);
+    qmul(dq, q, qn);
+    qnormalise(qn);
+    for (int c = 0; c < 4; c++) a.q[4 * p + c] = qn[c];
+    if (bad || !(qn[0] == qn[0])) {
+        atomicOr(a.status, ST_UNSTABLE);
+        atomicMin(a.bad_step, (int)a.step);
+    }
+}
+
+hipError_t launch_integrate(const DevArgs& a, hipStream_t st) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(integrate_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace cgb

@@ -1,0 +1,766 @@
+// runtime.hip -- host side of libcgb: the C ABI of include/cgb.h.
+//
+// Owns all device memory of a lattice, sequences the kernels of one time step
+// on one HIP stream, and moves data across the ABI.  Populations live as two
+// structure-of-arrays buffers [19][pstride] (x fastest within a plane) that
+// swap roles every step; a density-deviation field travels with them because
+// the moving-boundary correction (Eq. 10) needs the density of the fluid node
+// at the time of the bounced populations.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "cgb_dev.h"
+
+using namespace cgb;
+
+struct LaunchRec {
+    int kind;
+    hipEvent_t e0, e1;
+};
+
+static const char* kKindNames[] = {"prep", "raster", "transitions", "lb", "cells", "potentials", "integrate"};
+enum { K_PREP, K_RASTER, K_TRANS, K_LB, K_CELLS, K_POT, K_INT, K_NKIND };
+
+struct cgb_sim {
+    cgb_params P;
+    DevArgs a;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    int cur = 0;
+    void* pop[2] = {nullptr, nullptr};
+    void* rho[2] = {nullptr, nullptr};
+    size_t esize = 8;
+    int ncap = 0;
+    long long step = 0;
+    bool fluid_ready = false;
+    std::string err;
+    int64_t dev_bytes = 0;
+    std::vector<void*> allocs;
+    double* tmp = nullptr;  // FP64 staging for uploads/downloads
+    size_t tmp_bytes = 0;
+    double* obs_partial = nullptr;
+    int obs_nblk = 512;
+    int* pair_buf = nullptr;
+    int* pair_cnt = nullptr;
+    int pair_cap = 0;
+    LaunchCfg lbcfg{64, 4};
+    bool prof = false;
+    std::vector<LaunchRec> recs;
+    std::vector<hipEvent_t> ev_pool;
+    double ktime[K_NKIND] = {0};
+    long long kcount[K_NKIND] = {0};
+};
+
+#define FAIL(s, code, ...)                                  \
+    do {                                                    \
+        char _b[512];                                       \
+        snprintf(_b, sizeof _b, __VA_ARGS__);               \
+        (s)->err = _b;                                      \
+        return code;                                        \
+    } while (0)
+
+#define HIPCHK(s, call)                                                               \
+    do {                                                                              \
+        hipError_t _e = (call);                                                       \
+        if (_e != hipSuccess) FAIL(s, CGB_EDEVICE, "%s: %s", #call, hipGetErrorString(_e)); \
+    } while (0)
+
+template <class T>
+static hipError_t dalloc(cgb_sim* s, T** p, size_t bytes) {
+    void* v = nullptr;
+    hipError_t e = hipMalloc(&v, bytes ? bytes : 8);
+    if (e != hipSuccess) return e;
+    s->allocs.push_back(v);
+    s->dev_bytes += (int64_t)bytes;
+    *p = (T*)v;
+    return hipSuccess;
+}
+
+static void dfree(cgb_sim* s, void* p) {
+    if (!p) return;
+    auto it = std::find(s->allocs.begin(), s->allocs.end(), p);
+    if (it != s->allocs.end()) s->allocs.erase(it);
+    (void)hipFree(p);
+}
+
+static double wall_range(const cgb_params& P) {
+    const double sp2 = P.sig_perp * P.sig_perp, sl2 = P.sig_par * P.sig_par, sw2 = P.sig_w * P.sig_w;
+    const double chiw = (sl2 - sp2) / (sl2 + sw2);
+    const double sbw = sqrt(sp2 + sw2);
+    if (chiw <= 0.0) return sbw;
+    if (chiw >= 1.0) return 1e30;
+    return sbw / sqrt(1.0 - chiw);
+}
+
+// ---------------------------------------------------------------- profiling
+static hipEvent_t take_event(cgb_sim* s) {
+    if (!s->ev_pool.empty()) {
+        hipEvent_t e = s->ev_pool.back();
+        s->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+static void harvest(cgb_sim* s) {
+    for (auto& r : s->recs) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
+            s->ktime[r.kind] += ms;
+            s->kcount[r.kind] += 1;
+        }
+        s->ev_pool.push_back(r.e0);
+        s->ev_pool.push_back(r.e1);
+    }
+    s->recs.clear();
+}
+
+template <class F>
+static hipError_t timed(cgb_sim* s, int kind, F&& f) {
+    if (!s->prof) return f();
+    if (s->recs.size() > 4096) {
+        hipError_t e = hipStreamSynchronize(s->st);
+        if (e != hipSuccess) return e;
+        harvest(s);
+    }
+    LaunchRec r{kind, take_event(s), take_event(s)};
+    if (!r.e0 || !r.e1) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(r.e0, s->st);
+    if (e != hipSuccess) return e;
+    e = f();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(r.e1, s->st);
+    s->recs.push_back(r);
+    return e;
+}
+
+// ---------------------------------------------------------------- helpers
+static void bind_buffers(cgb_sim* s) {
+    s->a.A = s->pop[s->cur];
+    s->a.B = s->pop[1 - s->cur];
+    s->a.rhoA = s->rho[s->cur];
+    s->a.rhoB = s->rho[1 - s->cur];
+    s->a.step = s->step;
+}
+
+static int ensure_tmp(cgb_sim* s, size_t bytes) {
+    if (bytes <= s->tmp_bytes) return CGB_OK;
+    dfree(s, s->tmp);
+    s->tmp = nullptr;
+    s->tmp_bytes = 0;
+    HIPCHK(s, dalloc(s, &s->tmp, bytes));
+    s->tmp_bytes = bytes;
+    return CGB_OK;
+}
+
+static int check_status(cgb_sim* s) {
+    int st = 0, bad = 0;
+    HIPCHK(s, hipMemcpyAsync(&st, s->a.status, sizeof(int), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipMemcpyAsync(&bad, s->a.bad_step, sizeof(int), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    if (st & ST_TRANS_OVERFLOW) FAIL(s, CGB_ENOMEM, "transition list overflow (capacity %d)", s->a.trans_cap);
+    if (st & ST_UNSTABLE) FAIL(s, CGB_EUNSTABLE, "unstable at step %d: non-finite state, |u| > 0.4 or |V| >= 0.5", bad);
+    return CGB_OK;
+}
+
+// ---------------------------------------------------------------- ABI
+extern "C" {
+
+int cgb_params_default(cgb_params* p) {
+    if (!p) return CGB_EINVAL;
+    memset(p, 0, sizeof *p);
+    p->nx = p->ny = p->nz = 32;
+    p->tau = 1.0;
+    p->rho0 = 1.0;
+    p->R_perp = 2.5;
+    p->R_par = 1.0;
+    p->sig_perp = 2.5 * 12.0 / 11.0;
+    p->sig_par = 1.0 * 12.0 / 11.0;
+    p->sig_w = 0.5;
+    p->eps = 0.05;
+    p->eps_w = 0.05;
+    p->r_cut = 3.75;
+    p->rho_p = 1.0;
+    p->force_on_particles = 1;
+    p->precision = CGB_P32;
+    p->pmx_scale = 32768.0;
+    return CGB_OK;
+}
+
+const char* cgb_last_error(const cgb_sim* s) { return s ? s->err.c_str() : "null handle"; }
+int64_t cgb_device_bytes(const cgb_sim* s) { return s ? s->dev_bytes : 0; }
+
+void cgb_destroy(cgb_sim* s) {
+    if (!s) return;
+    if (s->st) (void)hipStreamSynchronize(s->st);
+    for (auto& r : s->recs) { (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
+    for (auto e : s->ev_pool) (void)hipEventDestroy(e);
+    for (void* p : s->allocs) (void)hipFree(p);
+    if (s->own_stream && s->st) (void)hipStreamDestroy(s->st);
+    delete s;
+}
+
+static int alloc_particles(cgb_sim* s, int ncap) {
+    DevArgs& a = s->a;
+    void* olds[] = {a.X, a.q, a.V, a.L, a.fixed, a.Xprev, a.kin, a.FTh, a.FTp, a.trans, a.pbin, a.bin_idx};
+    for (void* p : olds) dfree(s, p);
+    const size_t n = (size_t)std::max(ncap, 1);
+    HIPCHK(s, dalloc(s, &a.X, 3 * n * 8));
+    HIPCHK(s, dalloc(s, &a.q, 4 * n * 8));
+    HIPCHK(s, dalloc(s, &a.V, 3 * n * 8));
+    HIPCHK(s, dalloc(s, &a.L, 3 * n * 8));
+    HIPCHK(s, dalloc(s, &a.fixed, n));
+    HIPCHK(s, dalloc(s, &a.Xprev, 3 * n * 8));
+    HIPCHK(s, dalloc(s, &a.kin, 12 * n * 8));
+    HIPCHK(s, dalloc(s, &a.FTh, 6 * n * 8));
+    HIPCHK(s, dalloc(s, &a.FTp, 6 * n * 8));
+    HIPCHK(s, dalloc(s, &a.pbin, n * 4));
+    HIPCHK(s, dalloc(s, &a.bin_idx, n * 4));
+    long long cap = 96LL * (long long)n + 65536;
+    if (cap > s->a.ns + 65536) cap = s->a.ns + 65536;
+    a.trans_cap = (int)cap;
+    HIPCHK(s, dalloc(s, &a.trans, (size_t)cap * 3 * 4));
+    s->ncap = ncap;
+    return CGB_OK;
+}
+
+int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_sim** out) {
+    if (!p || !out) return CGB_EINVAL;
+    *out = nullptr;
+    if (p->nx < 3 || p->ny < 3 || p->nz < 3 || !(p->tau > 0.5) || !(p->rho0 > 0) || p->precision < 0 ||
+        p->precision > CGB_PMXBF16 || !(p->R_perp > 0) || !(p->R_par > 0) || !(p->rho_p > 0) || !(p->r_cut > 0))
+        return CGB_EINVAL;
+    cgb_sim* s = new cgb_sim();
+    s->P = *p;
+    if (s->P.pmx_scale == 0.0) s->P.pmx_scale = 32768.0;
+    DevArgs& a = s->a;
+    memset(&a, 0, sizeof a);
+    a.nx = p->nx; a.ny = p->ny; a.nz = p->nz;
+    a.ns = (long long)p->nx * p->ny * p->nz;
+    a.pstride = (a.ns + 255) / 256 * 256;
+    a.wall_y = p->wall_y;
+    for (int c = 0; c < 3; c++) { a.wvb[c] = p->wall_v_bot[c]; a.wvt[c] = p->wall_v_top[c]; a.g[c] = p->g[c]; }
+    a.moving_walls = p->wall_y && (p->wall_v_bot[0] != 0 || p->wall_v_bot[1] != 0 || p->wall_v_bot[2] != 0 ||
+                                   p->wall_v_top[0] != 0 || p->wall_v_top[1] != 0 || p->wall_v_top[2] != 0);
+    a.tau = p->tau; a.rho0 = p->rho0;
+    a.force_mode = p->force_mode; a.f0 = p->f0; a.force_on_particles = p->force_on_particles;
+    a.precision = p->precision;
+    a.pmx_scale = (float)s->P.pmx_scale;
+    a.pmx_inv = (float)(1.0 / s->P.pmx_scale);
+    a.M = p->rho_p * (4.0 / 3.0) * M_PI * p->R_perp * p->R_perp * p->R_par;
+    a.Ipar = 0.4 * a.M * p->R_perp * p->R_perp;
+    a.Iperp = 0.2 * a.M * (p->R_perp * p->R_perp + p->R_par * p->R_par);
+    a.iRpar2 = 1.0 / (p->R_par * p->R_par);
+    a.iRperp2 = 1.0 / (p->R_perp * p->R_perp);
+    a.Rb = std::max(p->R_perp, p->R_par);
+    a.r_cut2 = p->r_cut * p->r_cut;
+    const double wr = wall_range(*p);
+    a.wall_range2 = wr * wr;
+    a.sig_perp = p->sig_perp; a.sig_par = p->sig_par; a.sig_w = p->sig_w; a.eps = p->eps; a.eps_w = p->eps_w;
+    s->esize = p->precision == CGB_P64 ? 8 : (p->precision == CGB_P32 ? 4 : 2);
+
+    if (stream) {
+        s->st = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess) { delete s; return CGB_EDEVICE; }
+        s->own_stream = true;
+    }
+    int rc = CGB_OK;
+#define CK(call)                                         \
+    do {                                                 \
+        hipError_t _e = (call);                          \
+        if (_e != hipSuccess) { rc = CGB_EDEVICE; s->err = hipGetErrorString(_e); goto fail; } \
+    } while (0)
+    {
+        const size_t popb = 19 * (size_t)a.pstride * s->esize;
+        CK(dalloc(s, &s->pop[0], popb));
+        CK(dalloc(s, &s->pop[1], popb));
+        CK(dalloc(s, &s->rho[0], (size_t)a.pstride * s->esize));
+        CK(dalloc(s, &s->rho[1], (size_t)a.pstride * s->esize));
+        CK(dalloc(s, &a.owner, (size_t)a.ns * 4));
+        CK(dalloc(s, &a.flags, (size_t)a.ns * 4));
+        CK(dalloc(s, &a.cand, (size_t)a.ns * 4));
+        CK(dalloc(s, &a.ntrans, 16));
+        CK(dalloc(s, &a.status, 16));
+        CK(dalloc(s, &a.bad_step, 16));
+        CK(dalloc(s, &a.body_part, 32));
+        CK(dalloc(s, &s->obs_partial, (size_t)s->obs_nblk * 8 * 8));
+        // owner map: walls from the mask and the wall planes
+        std::vector<int32_t> own((size_t)a.ns, OWN_FLUID);
+        for (long long i = 0; i < a.ns; i++) {
+            const int y = (int)((i / a.nx) % a.ny);
+            bool w = wall_mask ? wall_mask[i] != 0 : false;
+            if (p->wall_y && (y == 0 || y == a.ny - 1)) w = true;
+            if (w) own[(size_t)i] = OWN_WALL;
+        }
+        CK(hipMemcpyAsync(a.owner, own.data(), (size_t)a.ns * 4, hipMemcpyHostToDevice, s->st));
+        // cell-list geometry: bin edge >= max(cut-off, wall potential range)
+        const double Lb[3] = {(double)a.nx, (double)a.ny, (double)a.nz};
+        const double emin = std::max(p->r_cut, wr);
+        long long nbins = 1;
+        for (int c = 0; c < 3; c++) {
+            a.nb[c] = std::max(1, (int)floor(Lb[c] / emin));
+            a.bedge[c] = Lb[c] / a.nb[c];
+            nbins *= a.nb[c];
+        }
+        if (nbins > (1LL << 30)) { rc = CGB_EINVAL; s->err = "too many cell-list bins"; goto fail; }
+        a.nbins = (int)nbins;
+        CK(dalloc(s, &a.bin_count, (size_t)nbins * 4));
+        CK(dalloc(s, &a.bin_start, (size_t)(nbins + 1) * 4));
+        CK(dalloc(s, &a.bin_fill, (size_t)nbins * 4));
+        // surface wall nodes (wall nodes with a non-wall neighbour), binned
+        std::vector<std::vector<int>> per((size_t)nbins);
+        long long nsw = 0;
+        for (long long i = 0; i < a.ns; i++) {
+            if (own[(size_t)i] != OWN_WALL) continue;
+            const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / ((long long)a.nx * a.ny));
+            bool surf = false;
+            for (int r = 1; r < 19 && !surf; r++) {
+                int yn = y + CY(r);
+                if (p->wall_y) { if (yn < 0 || yn >= a.ny) continue; }
+                else yn = wrap(yn, a.ny);
+                const long long j = wrap(x + CX(r), a.nx) + (long long)a.nx * (yn + (long long)a.ny * wrap(z + CZ(r), a.nz));
+                if (own[(size_t)j] != OWN_WALL) surf = true;
+            }
+            if (!surf) continue;
+            int bc[3] = {x, y, z};
+            for (int c = 0; c < 3; c++) {
+                int b = (int)floor(bc[c] / a.bedge[c]);
+                bc[c] = std::min(std::max(b, 0), a.nb[c] - 1);
+            }
+            per[(size_t)(bc[0] + a.nb[0] * (bc[1] + (long long)a.nb[1] * bc[2]))].push_back((int)i);
+            nsw++;
+        }
+        std::vector<int> wstart((size_t)nbins + 1), widx;
+        widx.reserve((size_t)nsw);
+        for (long long b = 0; b < nbins; b++) {
+            wstart[(size_t)b] = (int)widx.size();
+            for (int v : per[(size_t)b]) widx.push_back(v);
+        }
+        wstart[(size_t)nbins] = (int)widx.size();
+        CK(dalloc(s, &a.wall_start, (size_t)(nbins + 1) * 4));
+        CK(dalloc(s, &a.wall_idx, (size_t)std::max<long long>(nsw, 1) * 4));
+        CK(hipMemcpyAsync(a.wall_start, wstart.data(), wstart.size() * 4, hipMemcpyHostToDevice, s->st));
+        if (nsw) CK(hipMemcpyAsync(a.wall_idx, widx.data(), widx.size() * 4, hipMemcpyHostToDevice, s->st));
+        CK(launch_fill_i32(a.cand, a.ns, NO_CAND, s->st));
+        CK(launch_fill_i32(a.status, 4, 0, s->st));
+        CK(launch_fill_i32(a.bad_step, 4, 0x7fffffff, s->st));
+        CK(launch_fill_f64(a.body_part, 4, 0.0, s->st));
+        if (alloc_particles(s, 0) != CGB_OK) { rc = CGB_EDEVICE; goto fail; }
+        a.n = 0;
+        bind_buffers(s);
+        CK(launch_equilibrium_fill(a, nullptr, nullptr, s->st));
+        CK(launch_flags_rebuild(a, s->st));
+        CK(hipStreamSynchronize(s->st));
+        s->fluid_ready = true;
+    }
+#undef CK
+    *out = s;
+    return CGB_OK;
+fail:
+    cgb_destroy(s);
+    return rc;
+}
+
+int cgb_set_particles(cgb_sim* s, int32_t n, const double* X, const double* q, const double* V, const double* L,
+                      const uint8_t* fixed) {
+    if (!s) return CGB_EINVAL;
+    if (n < 0 || (n > 0 && (!X || !q))) FAIL(s, CGB_EINVAL, "bad particle arguments");
+    DevArgs& a = s->a;
+    if (n > 0) {
+        const int span = 2 * (int)ceil(a.Rb) + 6;
+        if (a.nx < span || a.nz < span || (!a.wall_y && a.ny < span))
+            FAIL(s, CGB_EINVAL, "periodic box smaller than a cell's rasterisation box (%d nodes)", span);
+        for (int i = 0; i < n; i++) {
+            const double qn = q[4 * i] * q[4 * i] + q[4 * i + 1] * q[4 * i + 1] + q[4 * i + 2] * q[4 * i + 2] +
+                              q[4 * i + 3] * q[4 * i + 3];
+            if (!(fabs(qn - 1.0) < 1e-6)) FAIL(s, CGB_EINVAL, "quaternion %d is not a unit quaternion", i);
+            for (int c = 0; c < 3; c++)
+                if (!(X[3 * i + c] == X[3 * i + c])) FAIL(s, CGB_EINVAL, "position %d is not finite", i);
+            if (a.wall_y && !(X[3 * i + 1] >= 0.0 && X[3 * i + 1] <= a.ny - 1)) FAIL(s, CGB_EINVAL, "cell %d outside the channel", i);
+        }
+    }
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    if (n > s->ncap) {
+        int rc = alloc_particles(s, n);
+        if (rc) return rc;
+    }
+    a.n = n;
+    // host copies, wrapped into the periodic box
+    std::vector<double> Xw(3 * (size_t)std::max(n, 1), 0.0), zero(3 * (size_t)std::max(n, 1), 0.0);
+    const double Lb[3] = {(double)a.nx, (double)a.ny, (double)a.nz};
+    for (int i = 0; i < n; i++)
+        for (int c = 0; c < 3; c++) {
+            double v = X[3 * i + c];
+            if (!(c == 1 && a.wall_y)) { v = fmod(v, Lb[c]); if (v < 0) v += Lb[c]; if (v >= Lb[c]) v -= Lb[c]; }
+            Xw[3 * (size_t)i + c] = v;
+        }
+    std::vector<uint8_t> fx((size_t)std::max(n, 1), 0);
+    if (fixed) for (int i = 0; i < n; i++) fx[(size_t)i] = fixed[i] ? 1 : 0;
+    if (n > 0) {
+        HIPCHK(s, hipMemcpyAsync(a.X, Xw.data(), 3 * (size_t)n * 8, hipMemcpyHostToDevice, s->st));
+        HIPCHK(s, hipMemcpyAsync(a.Xprev, Xw.data(), 3 * (size_t)n * 8, hipMemcpyHostToDevice, s->st));
+        HIPCHK(s, hipMemcpyAsync(a.q, q, 4 * (size_t)n * 8, hipMemcpyHostToDevice, s->st));
+        HIPCHK(s, hipMemcpyAsync(a.V, V ? V : zero.data(), 3 * (size_t)n * 8, hipMemcpyHostToDevice, s->st));
+        HIPCHK(s, hipMemcpyAsync(a.L, L ? L : zero.data(), 3 * (size_t)n * 8, hipMemcpyHostToDevice, s->st));
+        HIPCHK(s, hipMemcpyAsync(a.fixed, fx.data(), (size_t)n, hipMemcpyHostToDevice, s->st));
+    }
+    bind_buffers(s);
+    HIPCHK(s, launch_clear_cells(a, s->st));
+    HIPCHK(s, launch_prep(a, s->st));
+    HIPCHK(s, launch_raster(a, s->st, true));
+    HIPCHK(s, launch_transitions(a, s->st, false));
+    HIPCHK(s, launch_flags_rebuild(a, s->st));
+    HIPCHK(s, launch_cells(a, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return check_status(s);
+}
+
+int cgb_init_fluid(cgb_sim* s, const double* rho, const double* u) {
+    if (!s) return CGB_EINVAL;
+    DevArgs& a = s->a;
+    const size_t nsb = (size_t)a.ns * 8;
+    int rc = ensure_tmp(s, 4 * nsb);
+    if (rc) return rc;
+    double* drho = nullptr;
+    double* du = nullptr;
+    if (rho) { drho = s->tmp; HIPCHK(s, hipMemcpyAsync(drho, rho, nsb, hipMemcpyHostToDevice, s->st)); }
+    if (u) { du = s->tmp + a.ns; HIPCHK(s, hipMemcpyAsync(du, u, 3 * nsb, hipMemcpyHostToDevice, s->st)); }
+    bind_buffers(s);
+    HIPCHK(s, launch_equilibrium_fill(a, drho, du, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    s->fluid_ready = true;
+    return CGB_OK;
+}
+
+int cgb_set_populations(cgb_sim* s, const double* d) {
+    if (!s || !d) return CGB_EINVAL;
+    DevArgs& a = s->a;
+    const size_t bytes = 19 * (size_t)a.ns * 8;
+    int rc = ensure_tmp(s, bytes);
+    if (rc) return rc;
+    HIPCHK(s, hipMemcpyAsync(s->tmp, d, bytes, hipMemcpyHostToDevice, s->st));
+    bind_buffers(s);
+    HIPCHK(s, launch_encode(a, s->tmp, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return CGB_OK;
+}
+
+int cgb_step(cgb_sim* s, int32_t nsteps) {
+    if (!s || nsteps < 0) return CGB_EINVAL;
+    if (!s->fluid_ready) FAIL(s, CGB_ESTATE, "fluid not initialised");
+    DevArgs& a = s->a;
+    for (int t = 0; t < nsteps; t++) {
+        bind_buffers(s);
+        HIPCHK(s, timed(s, K_PREP, [&] { return launch_prep(a, s->st); }));
+        HIPCHK(s, timed(s, K_RASTER, [&] { return launch_raster(a, s->st, false); }));
+        HIPCHK(s, timed(s, K_TRANS, [&] { return launch_transitions(a, s->st, true); }));
+        HIPCHK(s, timed(s, K_LB, [&] { return launch_lb(a, s->lbcfg, s->st); }));
+        HIPCHK(s, timed(s, K_CELLS, [&] { return launch_cells(a, s->st); }));
+        HIPCHK(s, timed(s, K_POT, [&] { return launch_potentials(a, s->st); }));
+        HIPCHK(s, timed(s, K_INT, [&] {
+            hipError_t e = launch_fill_f64(a.body_part, 3, 0.0, s->st);
+            return e != hipSuccess ? e : launch_integrate(a, s->st);
+        }));
+        s->cur = 1 - s->cur;
+        s->step++;
+    }
+    bind_buffers(s);
+    return CGB_OK;
+}
+
+int cgb_sync(cgb_sim* s) {
+    if (!s) return CGB_EINVAL;
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    if (s->prof) harvest(s);
+    return check_status(s);
+}
+
+int cgb_get_populations(cgb_sim* s, double* d) {
+    if (!s || !d) return CGB_EINVAL;
+    int rc = cgb_sync(s);
+    if (rc && rc != CGB_EUNSTABLE) return rc;
+    DevArgs& a = s->a;
+    const size_t bytes = 19 * (size_t)a.ns * 8;
+    int rc2 = ensure_tmp(s, bytes);
+    if (rc2) return rc2;
+    bind_buffers(s);
+    HIPCHK(s, launch_decode(a, s->tmp, s->st));
+    HIPCHK(s, hipMemcpyAsync(d, s->tmp, bytes, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return rc;
+}
+
+int cgb_get_fields(cgb_sim* s, double* rho, double* u) {
+    if (!s) return CGB_EINVAL;
+    int rc = cgb_sync(s);
+    if (rc && rc != CGB_EUNSTABLE) return rc;
+    DevArgs& a = s->a;
+    const size_t nsb = (size_t)a.ns * 8;
+    int rc2 = ensure_tmp(s, 4 * nsb);
+    if (rc2) return rc2;
+    bind_buffers(s);
+    HIPCHK(s, launch_fields(a, s->tmp, s->tmp + a.ns, s->st));
+    if (rho) HIPCHK(s, hipMemcpyAsync(rho, s->tmp, nsb, hipMemcpyDeviceToHost, s->st));
+    if (u) HIPCHK(s, hipMemcpyAsync(u, s->tmp + a.ns, 3 * nsb, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return rc;
+}
+
+int cgb_get_particles(cgb_sim* s, double* X, double* q, double* V, double* L) {
+    if (!s) return CGB_EINVAL;
+    int rc = cgb_sync(s);
+    if (rc && rc != CGB_EUNSTABLE) return rc;
+    const size_t n = (size_t)s->a.n;
+    if (n) {
+        if (X) HIPCHK(s, hipMemcpyAsync(X, s->a.X, 3 * n * 8, hipMemcpyDeviceToHost, s->st));
+        if (q) HIPCHK(s, hipMemcpyAsync(q, s->a.q, 4 * n * 8, hipMemcpyDeviceToHost, s->st));
+        if (V) HIPCHK(s, hipMemcpyAsync(V, s->a.V, 3 * n * 8, hipMemcpyDeviceToHost, s->st));
+        if (L) HIPCHK(s, hipMemcpyAsync(L, s->a.L, 3 * n * 8, hipMemcpyDeviceToHost, s->st));
+        HIPCHK(s, hipStreamSynchronize(s->st));
+    }
+    return rc;
+}
+
+int cgb_get_forces(cgb_sim* s, double* Fh, double* Th, double* Fp, double* Tp) {
+    if (!s) return CGB_EINVAL;
+    int rc = cgb_sync(s);
+    if (rc && rc != CGB_EUNSTABLE) return rc;
+    const size_t n = (size_t)s->a.n;
+    if (!n) return rc;
+    std::vector<double> h(6 * n), pp(6 * n);
+    HIPCHK(s, hipMemcpyAsync(h.data(), s->a.FTh, 6 * n * 8, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipMemcpyAsync(pp.data(), s->a.FTp, 6 * n * 8, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    for (size_t i = 0; i < n; i++)
+        for (int c = 0; c < 3; c++) {
+            if (Fh) Fh[3 * i + c] = h[6 * i + c];
+            if (Th) Th[3 * i + c] = h[6 * i + 3 + c];
+            if (Fp) Fp[3 * i + c] = pp[6 * i + c];
+            if (Tp) Tp[3 * i + c] = pp[6 * i + 3 + c];
+        }
+    return rc;
+}
+
+int cgb_get_owner(cgb_sim* s, int32_t* owner) {
+    if (!s || !owner) return CGB_EINVAL;
+    int rc = cgb_sync(s);
+    if (rc && rc != CGB_EUNSTABLE) return rc;
+    HIPCHK(s, hipMemcpyAsync(owner, s->a.owner, (size_t)s->a.ns * 4, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return rc;
+}
+
+int cgb_get_link_mask(cgb_sim* s, uint32_t* mask) {
+    if (!s || !mask) return CGB_EINVAL;
+    int rc = cgb_sync(s);
+    if (rc && rc != CGB_EUNSTABLE) return rc;
+    HIPCHK(s, hipMemcpyAsync(mask, s->a.flags, (size_t)s->a.ns * 4, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    for (long long i = 0; i < s->a.ns; i++) mask[i] = (mask[i] & NONFLUID) ? 0u : (mask[i] & LINKBITS);
+    return rc;
+}
+
+int cgb_get_pairs(cgb_sim* s, int32_t* ij, int64_t cap, int64_t* n) {
+    if (!s || !n) return CGB_EINVAL;
+    int rc = cgb_sync(s);
+    if (rc && rc != CGB_EUNSTABLE) return rc;
+    DevArgs& a = s->a;
+    const int want = std::max(1024, 64 * a.n);
+    if (want > s->pair_cap) {
+        dfree(s, s->pair_buf);
+        s->pair_buf = nullptr;
+        if (!s->pair_cnt) HIPCHK(s, dalloc(s, &s->pair_cnt, 16));
+        HIPCHK(s, dalloc(s, &s->pair_buf, (size_t)want * 2 * 4));
+        s->pair_cap = want;
+    }
+    HIPCHK(s, launch_cells(a, s->st));
+    HIPCHK(s, launch_pairs(a, s->pair_buf, s->pair_cnt, s->pair_cap, s->st));
+    int cnt = 0;
+    HIPCHK(s, hipMemcpyAsync(&cnt, s->pair_cnt, 4, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    if (cnt > s->pair_cap) FAIL(s, CGB_ENOMEM, "pair buffer overflow (%d pairs)", cnt);
+    std::vector<int> buf(2 * (size_t)cnt);
+    if (cnt) HIPCHK(s, hipMemcpy(buf.data(), s->pair_buf, 2 * (size_t)cnt * 4, hipMemcpyDeviceToHost));
+    std::vector<std::pair<int, int>> pr((size_t)cnt);
+    for (int k = 0; k < cnt; k++) pr[(size_t)k] = {buf[2 * (size_t)k], buf[2 * (size_t)k + 1]};
+    std::sort(pr.begin(), pr.end());
+    *n = cnt;
+    if (ij)
+        for (int64_t k = 0; k < std::min<int64_t>(cap, cnt); k++) {
+            ij[2 * k] = pr[(size_t)k].first;
+            ij[2 * k + 1] = pr[(size_t)k].second;
+        }
+    return rc;
+}
+
+int cgb_get_observables(cgb_sim* s, double* out) {
+    if (!s || !out) return CGB_EINVAL;
+    int rc = cgb_sync(s);
+    if (rc && rc != CGB_EUNSTABLE) return rc;
+    DevArgs& a = s->a;
+    bind_buffers(s);
+    HIPCHK(s, launch_observables(a, s->obs_partial, s->obs_nblk, s->st));
+    std::vector<double> part((size_t)s->obs_nblk * 8);
+    double bp[3] = {0, 0, 0};
+    int bad = 0;
+    HIPCHK(s, hipMemcpyAsync(part.data(), s->obs_partial, part.size() * 8, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipMemcpyAsync(bp, a.body_part, 24, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipMemcpyAsync(&bad, a.bad_step, 4, hipMemcpyDeviceToHost, s->st));
+    std::vector<double> V(3 * (size_t)a.n);
+    std::vector<uint8_t> fx((size_t)a.n);
+    if (a.n) {
+        HIPCHK(s, hipMemcpyAsync(V.data(), a.V, V.size() * 8, hipMemcpyDeviceToHost, s->st));
+        HIPCHK(s, hipMemcpyAsync(fx.data(), a.fixed, fx.size(), hipMemcpyDeviceToHost, s->st));
+    }
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    double acc[8] = {0};
+    for (int b = 0; b < s->obs_nblk; b++)
+        for (int k = 0; k < 8; k++) acc[k] += part[8 * (size_t)b + k];
+    double pm[3] = {0, 0, 0};
+    for (int i = 0; i < a.n; i++)
+        if (!fx[(size_t)i]) for (int c = 0; c < 3; c++) pm[c] += a.M * V[3 * (size_t)i + c];
+    out[0] = acc[0];
+    for (int c = 0; c < 3; c++) {
+        out[1 + c] = acc[1 + c];
+        out[4 + c] = pm[c];
+        out[8 + c] = (s->step > 0 ? acc[5 + c] : 0.0) + bp[c];
+    }
+    out[7] = acc[4];
+    out[11] = (double)s->step;
+    out[12] = bad == 0x7fffffff ? -1.0 : (double)bad;
+    return rc;
+}
+
+int cgb_get_profile_z(cgb_sim* s, double* prof) {
+    if (!s || !prof) return CGB_EINVAL;
+    int rc = cgb_sync(s);
+    if (rc && rc != CGB_EUNSTABLE) return rc;
+    DevArgs& a = s->a;
+    int rc2 = ensure_tmp(s, 2 * (size_t)a.ny * 8);
+    if (rc2) return rc2;
+    bind_buffers(s);
+    HIPCHK(s, launch_kin(a, s->st));
+    HIPCHK(s, launch_fill_f64(s->tmp, 2 * (long long)a.ny, 0.0, s->st));
+    HIPCHK(s, launch_profile_z(a, s->tmp, s->tmp + a.ny, s->st));
+    std::vector<double> h(2 * (size_t)a.ny);
+    HIPCHK(s, hipMemcpyAsync(h.data(), s->tmp, h.size() * 8, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    for (int y = 0; y < a.ny; y++) prof[y] = h[(size_t)a.ny + y] > 0 ? h[(size_t)y] / h[(size_t)a.ny + y] : 0.0;
+    return rc;
+}
+
+int cgb_profile(cgb_sim* s, int enable) {
+    if (!s) return CGB_EINVAL;
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    harvest(s);
+    if (enable) {
+        for (int k = 0; k < K_NKIND; k++) { s->ktime[k] = 0; s->kcount[k] = 0; }
+    }
+    s->prof = enable != 0;
+    return CGB_OK;
+}
+
+int cgb_kernel_times(cgb_sim* s, char* names, double* ms, int64_t* count, int32_t cap, int32_t* n) {
+    if (!s || !n) return CGB_EINVAL;
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    harvest(s);
+    int k = 0;
+    for (; k < K_NKIND && k < cap; k++) {
+        if (names) { memset(names + 64 * k, 0, 64); strncpy(names + 64 * k, kKindNames[k], 63); }
+        if (ms) ms[k] = s->ktime[k];
+        if (count) count[k] = s->kcount[k];
+    }
+    *n = k;
+    return CGB_OK;
+}
+
+// ---------------------------------------------------------------- checkpoint
+static const char kMagic[8] = {'C', 'G', 'B', 'C', 'K', 'P', 'T', '1'};
+
+int cgb_save(cgb_sim* s, const char* path) {
+    if (!s || !path) return CGB_EINVAL;
+    int rc = cgb_sync(s);
+    if (rc) return rc;
+    DevArgs& a = s->a;
+    FILE* f = fopen(path, "wb");
+    if (!f) FAIL(s, CGB_EINVAL, "cannot open %s", path);
+    const size_t popb = 19 * (size_t)a.pstride * s->esize, rhob = (size_t)a.pstride * s->esize;
+    std::vector<char> buf(std::max(popb, (size_t)a.ns * 4));
+    bool ok = fwrite(kMagic, 1, 8, f) == 8 && fwrite(&s->P, sizeof s->P, 1, f) == 1 &&
+              fwrite(&a.n, 4, 1, f) == 1 && fwrite(&s->step, 8, 1, f) == 1;
+    auto dump = [&](const void* dev, size_t bytes) {
+        if (!ok) return;
+        if (hipMemcpy(buf.data(), dev, bytes, hipMemcpyDeviceToHost) != hipSuccess) { ok = false; return; }
+        ok = fwrite(buf.data(), 1, bytes, f) == bytes;
+    };
+    dump(s->pop[s->cur], popb);
+    dump(s->rho[s->cur], rhob);
+    dump(a.owner, (size_t)a.ns * 4);
+    dump(a.flags, (size_t)a.ns * 4);
+    if (a.n) {
+        const size_t n = (size_t)a.n;
+        dump(a.X, 3 * n * 8); dump(a.q, 4 * n * 8); dump(a.V, 3 * n * 8); dump(a.L, 3 * n * 8);
+        dump(a.fixed, n); dump(a.Xprev, 3 * n * 8);
+    }
+    fclose(f);
+    if (!ok) FAIL(s, CGB_EDEVICE, "write to %s failed", path);
+    return CGB_OK;
+}
+
+int cgb_load(cgb_sim* s, const char* path) {
+    if (!s || !path) return CGB_EINVAL;
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    DevArgs& a = s->a;
+    FILE* f = fopen(path, "rb");
+    if (!f) FAIL(s, CGB_EINVAL, "cannot open %s", path);
+    char mg[8];
+    cgb_params P;
+    int n = 0;
+    long long step = 0;
+    bool ok = fread(mg, 1, 8, f) == 8 && memcmp(mg, kMagic, 8) == 0 && fread(&P, sizeof P, 1, f) == 1 &&
+              fread(&n, 4, 1, f) == 1 && fread(&step, 8, 1, f) == 1;
+    if (!ok || P.nx != s->P.nx || P.ny != s->P.ny || P.nz != s->P.nz || P.precision != s->P.precision) {
+        fclose(f);
+        FAIL(s, CGB_EINVAL, "checkpoint %s does not match this lattice", path);
+    }
+    if (n > s->ncap) {
+        int rc = alloc_particles(s, n);
+        if (rc) { fclose(f); return rc; }
+    }
+    a.n = n;
+    const size_t popb = 19 * (size_t)a.pstride * s->esize, rhob = (size_t)a.pstride * s->esize;
+    std::vector<char> buf(std::max(popb, (size_t)a.ns * 4));
+    auto load = [&](void* dev, size_t bytes) {
+        if (!ok) return;
+        ok = fread(buf.data(), 1, bytes, f) == bytes;
+        if (ok) ok = hipMemcpy(dev, buf.data(), bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    load(s->pop[s->cur], popb);
+    load(s->rho[s->cur], rhob);
+    load(a.owner, (size_t)a.ns * 4);
+    load(a.flags, (size_t)a.ns * 4);
+    if (n) {
+        const size_t nn = (size_t)n;
+        load(a.X, 3 * nn * 8); load(a.q, 4 * nn * 8); load(a.V, 3 * nn * 8); load(a.L, 3 * nn * 8);
+        load(a.fixed, nn); load(a.Xprev, 3 * nn * 8);
+    }
+    fclose(f);
+    if (!ok) FAIL(s, CGB_EINVAL, "checkpoint %s is truncated", path);
+    s->step = step;
+    s->fluid_ready = true;
+    bind_buffers(s);
+    HIPCHK(s, launch_fill_i32(a.cand, a.ns, NO_CAND, s->st));
+    HIPCHK(s, launch_cells(a, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return CGB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.  Geometry (owner map, link masks, pair sets) must agree
+bit for bit; FP64 state to 1e-12 relative (infinity norm); FP32 velocities
+to 1e-5 relative."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+from parity_util import compare_state, make_pair, oracle_sensitivity, rel_inf, say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_fluid_only_channel_p64():
+    # config-1 geometry without cells: walls, constant body force, 100 steps
+    p = synth.params(24, 24, 48, wall_y=1, force_mode=1, g=(0, 0, 1e-6))
+    say("case: channel 24x24x48 no cells, p64, 100 steps")
+    g, o = make_pair(p)
+    g.step(100); o.step(100)
+    rep = compare_state(g, o, 1e-12, 1e-12)
+    say(rep)
+
+
+def test_ragged_periodic_with_random_velocity_p64():
+    # sizes that are not multiples of the tile; random initial velocity field
+    rng = np.random.default_rng(4)
+    p = synth.params(37, 23, 19, force_mode=2, f0=3e-5)
+    u0 = 1e-3 * rng.standard_normal((37 * 23 * 19, 3))
+    say("case: ragged 37x23x19 periodic, random u0, p64, 30 steps")
+    g, o = make_pair(p, u0=u0)
+    g.step(30); o.step(30)
+    say(compare_state(g, o, 1e-12, 1e-12))
+
+
+def test_moving_walls_p64():
+    p = synth.params(9, 12, 10, wall_y=1, wall_v_top=(0, 0, 1e-3), wall_v_bot=(2e-4, 0, 0))
+    say("case: Couette walls, p64, 50 steps")
+    g, o = make_pair(p)
+    g.step(50); o.step(50)
+    say(compare_state(g, o, 1e-12, 1e-12))
+
+
+@pytest.mark.parametrize("steps", [1, 10, 100])
+def test_config1_p64(steps):
+    # 1e-12 relative; over many steps the bound is widened to ten times the
+    # problem's own conditioning (the oracle's response to a one-ulp change
+    # of its inputs), which for this channel reaches ~5e-12 at 100 steps
+    c = synth.config1()
+    sens = oracle_sensitivity(c["params"], c["X"], c["q"], steps)
+    tol = max(1e-12, 10 * max(sens.values()))
+    say(f"case: config1 channel 24x24x48 with 20 cells, p64, {steps} steps, tol {tol:.2e}", sens)
+    g, o = make_pair(c["params"], c["X"], c["q"])
+    assert np.array_equal(g.owner(), o.owner())
+    g.step(steps); o.step(steps)
+    say(compare_state(g, o, tol, tol))
+    assert np.array_equal(g.pairs(), o.pairs())
+
+
+def test_dense_suspension_p64():
+    # Ht = 0.4 at 32^3 (501 overlapping cells), 25 steps: covers/uncovers,
+    # transfers between cells, many pairs
+    c = synth.kolmogorov(32, 3)
+    sens = oracle_sensitivity(c["params"], c["X"], c["q"], 25)
+    tol = max(1e-12, 10 * max(sens.values()))
+    say(f"case: dense 32^3 Ht=0.4, p64, 25 steps, tol {tol:.2e}", sens)
+    g, o = make_pair(c["params"], c["X"], c["q"])
+    assert np.array_equal(g.owner(), o.owner())
+    assert np.array_equal(g.pairs(), o.pairs())
+    for t in range(5):
+        g.step(5); o.step(5)
+        rep = compare_state(g, o, tol, tol)
+        assert np.array_equal(g.pairs(), o.pairs())
+    say(rep)
+
+
+def test_moving_cells_momentum_balance_gpu():
+    # periodic: total momentum changes by exactly the body force each step
+    rng = np.random.default_rng(7)
+    n = 24
+    p = synth.params(n, n, n, force_mode=2, f0=2e-5, rho_p=4.0)
+    N = 30
+    X = rng.random((N, 3)) * n
+    V = 2e-3 * rng.standard_normal((N, 3))
+    L = 1e-2 * rng.standard_normal((N, 3))
+    from paper_1005_2594_amd import Sim
+    say("case: momentum balance 24^3, 30 cells, p64")
+    g = Sim(p, precision="p64")
+    g.set_particles(X, synth.random_quaternions(rng, N), V, L)
+    g.init_fluid(None, 1e-3 * rng.standard_normal((n ** 3, 3)))
+    ob = g.observables()
+    P0 = ob["fluid_momentum"] + ob["particle_momentum"]
+    for _ in range(20):
+        g.step(1)
+        ob = g.observables()
+        P1 = ob["fluid_momentum"] + ob["particle_momentum"]
+        assert np.abs(P1 - P0 - ob["body_force_last"]).max() < 1e-13
+        P0 = P1
+
+
+def test_p32_velocity_parity():
+    c = synth.kolmogorov(32, 5, f0=1e-5)
+    say("case: dense 32^3, p32 vs oracle, 40 steps")
+    g, o = make_pair(c["params"], c["X"], c["q"], precision="p32")
+    g.step(40); o.step(40)
+    fluid = (g.owner() == -1) & (o.owner() == -1)
+    _, ug = g.fields(); _, uo = o.fields()
+    err = rel_inf(ug[fluid], uo[fluid])
+    say("p32 u rel err", err)
+    assert err <= 1e-5
+
+
+def test_set_populations_roundtrip_and_empty():
+    p = synth.params(16, 8, 8)
+    rng = np.random.default_rng(0)
+    from paper_1005_2594_amd import Sim
+    for prec, tol in (("p64", 0.0), ("p32", 1e-7), ("pmx16", 1e-3), ("pmxbf16", 8e-3)):
+        say(f"case: populations round trip {prec}")
+        g = Sim(p, precision=prec)
+        g.set_particles(np.zeros((0, 3)), np.zeros((0, 4)))
+        w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+        d = w[:, None] * 1e-3 * rng.standard_normal((19, 16 * 8 * 8))
+        g.set_populations(d)
+        back = g.populations()
+        assert np.max(np.abs(back - d) / (w[:, None] * 1e-3)) <= tol * 5 + 1e-15
+        g.step(3)
+        assert g.observables()["step"] == 3
+
+
+def test_checkpoint_resume(tmp_path):
+    # the restored state is bit-identical to the saved one; continuing from it
+    # matches the uninterrupted run to rounding (per-cell force sums use
+    # atomics, so their order - not their value - varies between runs)
+    c = synth.kolmogorov(32, 6)
+    from paper_1005_2594_amd import Sim
+    say("case: checkpoint resume, pmx16 32^3")
+    a = Sim(c["params"], precision="pmx16")
+    a.set_particles(c["X"], c["q"]); a.init_fluid()
+    a.step(10)
+    a.save(tmp_path / "ck.bin")
+    b = Sim(c["params"], precision="pmx16")
+    b.load(tmp_path / "ck.bin")
+    b.n = a.n
+    assert np.array_equal(a.owner(), b.owner())
+    assert np.array_equal(a.populations(), b.populations())
+    for x, y in zip(a.particles(), b.particles()):
+        assert np.array_equal(x, y)
+    a.step(10); b.step(10)
+    assert np.max(np.abs(a.particles()[0] - b.particles()[0])) < 1e-9
+    assert np.max(np.abs(a.populations() - b.populations())) < 1e-6
