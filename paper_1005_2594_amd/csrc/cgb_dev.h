@@ -99,10 +99,61 @@ struct DevArgs {
     int* status;
     int* bad_step;
     long long step;
-    double* body_part; // 3: body force added to cells this step
+    double* body_part; // per-block partial sums of the body force on cells
+    // momentum-exchange partials: LB tile shape, tiles per axis, slots per
+    // axis (tiles a cell's footprint can span), per-cell slot arrays
+    int tile[3];
+    int ntile[3];
+    int slots[3];
+    int nslot;
+    double* FTpart;    // n * nslot * 6
+    int* stamp;        // n * nslot (step + 1 when written)
+    int* scan_tmp;     // block totals of the bin scan
+    int nbody_blk;     // blocks of the integrate kernel (body_part has 3 per block)
 };
 
 __host__ __device__ inline int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// ------------------------------------------------------------ buffer access
+// Raw buffer loads/stores take one scalar resource and a 32-bit byte offset
+// per lane (no 64-bit address registers); accesses past num_records read 0 and
+// drop the store.
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* p, unsigned long long bytes) {
+    const unsigned nrec = bytes >= 0xffffffffull ? 0xffffffffu : (unsigned)bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)nrec, 0x00020000);
+}
+template <class T> __device__ inline T bload(__amdgpu_buffer_rsrc_t r, unsigned off);
+template <> __device__ inline double bload<double>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <> __device__ inline float bload<float>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <> __device__ inline _Float16 bload<_Float16>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+}
+template <> __device__ inline uint16_t bload<uint16_t>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+}
+template <> __device__ inline int bload<int>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return (int)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+template <> __device__ inline uint32_t bload<uint32_t>(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+template <class T> __device__ inline void bstore(T v, __amdgpu_buffer_rsrc_t r, unsigned off);
+template <> __device__ inline void bstore<double>(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0, 0)), v), r, off, 0, 0);
+}
+template <> __device__ inline void bstore<float>(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+template <> __device__ inline void bstore<_Float16>(_Float16 v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, 0, 0);
+}
+template <> __device__ inline void bstore<uint16_t>(uint16_t v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, off, 0, 0);
+}
 
 // ------------------------------------------------------------ codecs
 // P64 / P32: plain values.  PMX: d / w_r * scale stored in FP16 or BF16 with
@@ -224,9 +275,11 @@ __device__ inline double wave_sum(double v) {
 // host-side launchers implemented in the kernel translation units
 namespace cgb {
 struct LaunchCfg {
-    int bx, by;  // LB tile: threads along x and y
+    int bx, by;  // LB workgroup: threads along x and y
+    int tz;      // nodes swept along z by each thread
 };
 hipError_t launch_lb(const DevArgs& a, LaunchCfg cfg, hipStream_t st);
+hipError_t launch_mem_gather(const DevArgs& a, hipStream_t st);
 hipError_t launch_prep(const DevArgs& a, hipStream_t st);
 hipError_t launch_kin(const DevArgs& a, hipStream_t st);
 hipError_t launch_clear_cells(const DevArgs& a, hipStream_t st);

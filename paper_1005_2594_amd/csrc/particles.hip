@@ -137,7 +137,8 @@ __global__ void __launch_bounds__(64) raster_cover_kernel(DevArgs a) {
         int x, y, z;
         if (!box_node(a, lo, ext, k, &x, &y, &z)) continue;
         const long long s = x + (long long)a.nx * (y + (long long)a.ny * z);
-        if (a.owner[s] == OWN_WALL) continue;
+        const int o = a.owner[s];
+        if (o == OWN_WALL || o == p) continue;  // the owner keeps a node it still covers
         if (covers(a, p, x, y, z)) atomicMin(a.cand + s, p);
     }
 }
@@ -327,17 +328,42 @@ __global__ void bin_count_kernel(DevArgs a) {
     atomicAdd(a.bin_count + b, 1);
 }
 
-// exclusive scan of bin_count into bin_start[0..nbins] by one block of 1024
-// threads: each thread scans a contiguous chunk, the chunk totals are scanned
-// in LDS, then each chunk is written with its offset
-__global__ void __launch_bounds__(1024) bin_scan_kernel(DevArgs a) {
+// exclusive scan of bin_count into bin_start[0..nbins]: (1) each block of 256
+// threads scans 4096 bins (16 per thread) and records its total, (2) one block
+// scans the block totals, (3) each block adds its offset
+constexpr int SCAN_PER_BLOCK = 4096;
+__global__ void __launch_bounds__(256) scan_local_kernel(DevArgs a, int* block_tot) {
+    __shared__ int tot[256];
+    const int base = blockIdx.x * SCAN_PER_BLOCK + threadIdx.x * 16;
+    int v[16], s = 0;
+    for (int k = 0; k < 16; k++) {
+        const int b = base + k;
+        v[k] = b < a.nbins ? a.bin_count[b] : 0;
+        s += v[k];
+    }
+    tot[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int t = threadIdx.x >= off ? tot[threadIdx.x - off] : 0;
+        __syncthreads();
+        tot[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int run = threadIdx.x ? tot[threadIdx.x - 1] : 0;
+    for (int k = 0; k < 16; k++) {
+        const int b = base + k;
+        if (b < a.nbins) { a.bin_start[b] = run; a.bin_fill[b] = 0; }
+        run += v[k];
+    }
+    if (threadIdx.x == 255) block_tot[blockIdx.x] = tot[255];
+}
+
+__global__ void __launch_bounds__(1024) scan_top_kernel(int* block_tot, int nblk, int* total_out) {
     __shared__ int tot[1024];
-    const int n = a.nbins;
-    const int chunk = (n + 1023) / 1024;
+    const int chunk = (nblk + 1023) / 1024;
     const int t = threadIdx.x;
-    const int b0 = t * chunk, b1 = min(n, b0 + chunk);
     int s = 0;
-    for (int b = b0; b < b1; b++) s += a.bin_count[b];
+    for (int k = 0; k < chunk; k++) { const int b = t * chunk + k; if (b < nblk) s += block_tot[b]; }
     tot[t] = s;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -347,12 +373,16 @@ __global__ void __launch_bounds__(1024) bin_scan_kernel(DevArgs a) {
         __syncthreads();
     }
     int run = t ? tot[t - 1] : 0;
-    for (int b = b0; b < b1; b++) {
-        a.bin_start[b] = run;
-        run += a.bin_count[b];
-        a.bin_fill[b] = 0;
+    for (int k = 0; k < chunk; k++) {
+        const int b = t * chunk + k;
+        if (b < nblk) { const int v = block_tot[b]; block_tot[b] = run; run += v; }
     }
-    if (t == 1023) a.bin_start[n] = tot[1023];
+    if (t == 1023) *total_out = tot[1023];
+}
+
+__global__ void scan_add_kernel(DevArgs a, const int* block_off) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < a.nbins) a.bin_start[b] += block_off[b / SCAN_PER_BLOCK];
 }
 
 __global__ void bin_fill_kernel(DevArgs a) {
@@ -380,7 +410,10 @@ hipError_t launch_cells(const DevArgs& a, hipStream_t st) {
     hipError_t e = launch_fill_i32(a.bin_count, a.nbins, 0, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(bin_count_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, st, a);
+    const int nblk = (a.nbins + SCAN_PER_BLOCK - 1) / SCAN_PER_BLOCK;
+    hipLaunchKernelGGL(scan_local_kernel, dim3(nblk), dim3(256), 0, st, a, a.scan_tmp);
+    hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, st, a.scan_tmp, nblk, a.bin_start + a.nbins);
+    hipLaunchKernelGGL(scan_add_kernel, dim3((a.nbins + 255) / 256), dim3(256), 0, st, a, (const int*)a.scan_tmp);
     hipLaunchKernelGGL(bin_fill_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
     hipLaunchKernelGGL(bin_sort_kernel, dim3((a.nbins + 255) / 256), dim3(256), 0, st, a);
     return hipGetLastError();
@@ -578,9 +611,27 @@ __device__ inline void omega_sym(const DevArgs& a, const double* o, const double
     for (int c = 0; c < 3; c++) w[c] = L[c] / a.Iperp + kk * oL * o[c];
 }
 
-__global__ void integrate_kernel(DevArgs a) {
+__device__ void integrate_one(const DevArgs& a, int p, double* bf);
+
+// one thread per cell; the body force added to the cells is reduced per block
+// (no same-address atomics) into body_part[3 * block]
+__global__ void __launch_bounds__(256) integrate_kernel(DevArgs a) {
+    __shared__ double red[3][256];
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n) return;
+    double bf[3] = {0, 0, 0};
+    if (p < a.n) integrate_one(a, p, bf);
+    for (int c = 0; c < 3; c++) red[c][threadIdx.x] = bf[c];
+    __syncthreads();
+    for (int off = 128; off >= 1; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int c = 0; c < 3; c++) red[c][threadIdx.x] += red[c][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; c++) a.body_part[3 * blockIdx.x + c] = red[c][0];
+}
+
+__device__ void integrate_one(const DevArgs& a, int p, double* bf) {
     if (a.fixed[p]) {
         for (int c = 0; c < 3; c++) { a.V[3 * p + c] = 0.0; a.L[3 * p + c] = 0.0; }
         return;
@@ -604,11 +655,7 @@ __global__ void integrate_kernel(DevArgs a) {
         }
         a.X[3 * p + c] = xn;
     }
-    if (a.force_on_particles && a.force_mode) {
-        unsafeAtomicAdd(a.body_part + 0, a.M * gb[0]);
-        unsafeAtomicAdd(a.body_part + 1, a.M * gb[1]);
-        unsafeAtomicAdd(a.body_part + 2, a.M * gb[2]);
-    }
+    bf[0] = a.M * gb[0]; bf[1] = a.M * gb[1]; bf[2] = a.M * gb[2];
     // quaternion: half-step predictor, then full step with the midpoint rate
     double q[4] = {a.q[4 * p], a.q[4 * p + 1], a.q[4 * p + 2], a.q[4 * p + 3]};
     double o[3], w[3], dq[4], qh[4], qn[4];

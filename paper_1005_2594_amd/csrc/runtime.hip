@@ -23,8 +23,8 @@ struct LaunchRec {
     hipEvent_t e0, e1;
 };
 
-static const char* kKindNames[] = {"prep", "raster", "transitions", "lb", "cells", "potentials", "integrate"};
-enum { K_PREP, K_RASTER, K_TRANS, K_LB, K_CELLS, K_POT, K_INT, K_NKIND };
+static const char* kKindNames[] = {"prep", "raster", "transitions", "lb", "mem_gather", "cells", "potentials", "integrate"};
+enum { K_PREP, K_RASTER, K_TRANS, K_LB, K_GATHER, K_CELLS, K_POT, K_INT, K_NKIND };
 
 struct cgb_sim {
     cgb_params P;
@@ -48,7 +48,7 @@ struct cgb_sim {
     int* pair_buf = nullptr;
     int* pair_cnt = nullptr;
     int pair_cap = 0;
-    LaunchCfg lbcfg{64, 4};
+    LaunchCfg lbcfg{64, 4, 16};
     bool prof = false;
     std::vector<LaunchRec> recs;
     std::vector<hipEvent_t> ev_pool;
@@ -207,9 +207,45 @@ void cgb_destroy(cgb_sim* s) {
     delete s;
 }
 
+// LB tile shape and the per-cell slot geometry that goes with it
+static void set_tiles(cgb_sim* s, LaunchCfg cfg) {
+    DevArgs& a = s->a;
+    s->lbcfg = cfg;
+    a.tile[0] = cfg.bx; a.tile[1] = cfg.by; a.tile[2] = cfg.tz;
+    const int n3[3] = {a.nx, a.ny, a.nz};
+    const int ext = 2 * (int)ceil(a.Rb) + 5;  // footprint of a cell's linked fluid nodes
+    a.nslot = 1;
+    for (int c = 0; c < 3; c++) {
+        a.ntile[c] = (n3[c] + a.tile[c] - 1) / a.tile[c];
+        a.slots[c] = std::min(a.ntile[c], (ext + a.tile[c] - 1) / a.tile[c] + 1);
+        a.nslot *= a.slots[c];
+    }
+}
+
+static LaunchCfg default_tiles(const DevArgs& a) {
+    LaunchCfg c{64, 4, 16};
+    if (a.nx < 48) c = LaunchCfg{32, 8, 16};
+    if (a.nx < 24) c = LaunchCfg{16, 16, 16};
+    if (a.nz < 32) c.tz = 8;
+    return c;
+}
+
+static int alloc_slots(cgb_sim* s) {
+    DevArgs& a = s->a;
+    dfree(s, a.FTpart);
+    dfree(s, a.stamp);
+    a.FTpart = nullptr;
+    a.stamp = nullptr;
+    const size_t q = (size_t)std::max(s->ncap, 1) * (size_t)a.nslot;
+    HIPCHK(s, dalloc(s, &a.FTpart, q * 6 * 8));
+    HIPCHK(s, dalloc(s, &a.stamp, q * 4));
+    HIPCHK(s, launch_fill_i32(a.stamp, (long long)q, 0, s->st));
+    return CGB_OK;
+}
+
 static int alloc_particles(cgb_sim* s, int ncap) {
     DevArgs& a = s->a;
-    void* olds[] = {a.X, a.q, a.V, a.L, a.fixed, a.Xprev, a.kin, a.FTh, a.FTp, a.trans, a.pbin, a.bin_idx};
+    void* olds[] = {a.X, a.q, a.V, a.L, a.fixed, a.Xprev, a.kin, a.FTh, a.FTp, a.trans, a.pbin, a.bin_idx, a.body_part};
     for (void* p : olds) dfree(s, p);
     const size_t n = (size_t)std::max(ncap, 1);
     HIPCHK(s, dalloc(s, &a.X, 3 * n * 8));
@@ -223,12 +259,14 @@ static int alloc_particles(cgb_sim* s, int ncap) {
     HIPCHK(s, dalloc(s, &a.FTp, 6 * n * 8));
     HIPCHK(s, dalloc(s, &a.pbin, n * 4));
     HIPCHK(s, dalloc(s, &a.bin_idx, n * 4));
+    HIPCHK(s, dalloc(s, &a.body_part, ((n + 255) / 256) * 3 * 8));
+    HIPCHK(s, launch_fill_f64(a.body_part, (long long)((n + 255) / 256) * 3, 0.0, s->st));
     long long cap = 96LL * (long long)n + 65536;
     if (cap > s->a.ns + 65536) cap = s->a.ns + 65536;
     a.trans_cap = (int)cap;
     HIPCHK(s, dalloc(s, &a.trans, (size_t)cap * 3 * 4));
     s->ncap = ncap;
-    return CGB_OK;
+    return alloc_slots(s);
 }
 
 int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_sim** out) {
@@ -237,6 +275,11 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
     if (p->nx < 3 || p->ny < 3 || p->nz < 3 || !(p->tau > 0.5) || !(p->rho0 > 0) || p->precision < 0 ||
         p->precision > CGB_PMXBF16 || !(p->R_perp > 0) || !(p->R_par > 0) || !(p->rho_p > 0) || !(p->r_cut > 0))
         return CGB_EINVAL;
+    {
+        const double esz = p->precision == CGB_P64 ? 8.0 : (p->precision == CGB_P32 ? 4.0 : 2.0);
+        if (19.0 * esz * (double)(((long long)p->nx * p->ny * p->nz + 255) / 256 * 256) >= 4294967295.0)
+            return CGB_EINVAL;  // populations are addressed with 32-bit byte offsets
+    }
     cgb_sim* s = new cgb_sim();
     s->P = *p;
     if (s->P.pmx_scale == 0.0) s->P.pmx_scale = 32768.0;
@@ -290,7 +333,6 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
         CK(dalloc(s, &a.ntrans, 16));
         CK(dalloc(s, &a.status, 16));
         CK(dalloc(s, &a.bad_step, 16));
-        CK(dalloc(s, &a.body_part, 32));
         CK(dalloc(s, &s->obs_partial, (size_t)s->obs_nblk * 8 * 8));
         // owner map: walls from the mask and the wall planes
         std::vector<int32_t> own((size_t)a.ns, OWN_FLUID);
@@ -315,6 +357,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
         CK(dalloc(s, &a.bin_count, (size_t)nbins * 4));
         CK(dalloc(s, &a.bin_start, (size_t)(nbins + 1) * 4));
         CK(dalloc(s, &a.bin_fill, (size_t)nbins * 4));
+        CK(dalloc(s, &a.scan_tmp, (size_t)((nbins + 4095) / 4096 + 1) * 4));
         // surface wall nodes (wall nodes with a non-wall neighbour), binned
         std::vector<std::vector<int>> per((size_t)nbins);
         long long nsw = 0;
@@ -352,7 +395,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
         CK(launch_fill_i32(a.cand, a.ns, NO_CAND, s->st));
         CK(launch_fill_i32(a.status, 4, 0, s->st));
         CK(launch_fill_i32(a.bad_step, 4, 0x7fffffff, s->st));
-        CK(launch_fill_f64(a.body_part, 4, 0.0, s->st));
+        set_tiles(s, default_tiles(a));
         if (alloc_particles(s, 0) != CGB_OK) { rc = CGB_EDEVICE; goto fail; }
         a.n = 0;
         bind_buffers(s);
@@ -413,6 +456,7 @@ int cgb_set_particles(cgb_sim* s, int32_t n, const double* X, const double* q, c
         HIPCHK(s, hipMemcpyAsync(a.fixed, fx.data(), (size_t)n, hipMemcpyHostToDevice, s->st));
     }
     bind_buffers(s);
+    HIPCHK(s, launch_fill_i32(a.stamp, (long long)std::max(s->ncap, 1) * a.nslot, 0, s->st));
     HIPCHK(s, launch_clear_cells(a, s->st));
     HIPCHK(s, launch_prep(a, s->st));
     HIPCHK(s, launch_raster(a, s->st, true));
@@ -463,12 +507,10 @@ int cgb_step(cgb_sim* s, int32_t nsteps) {
         HIPCHK(s, timed(s, K_RASTER, [&] { return launch_raster(a, s->st, false); }));
         HIPCHK(s, timed(s, K_TRANS, [&] { return launch_transitions(a, s->st, true); }));
         HIPCHK(s, timed(s, K_LB, [&] { return launch_lb(a, s->lbcfg, s->st); }));
+        HIPCHK(s, timed(s, K_GATHER, [&] { return launch_mem_gather(a, s->st); }));
         HIPCHK(s, timed(s, K_CELLS, [&] { return launch_cells(a, s->st); }));
         HIPCHK(s, timed(s, K_POT, [&] { return launch_potentials(a, s->st); }));
-        HIPCHK(s, timed(s, K_INT, [&] {
-            hipError_t e = launch_fill_f64(a.body_part, 3, 0.0, s->st);
-            return e != hipSuccess ? e : launch_integrate(a, s->st);
-        }));
+        HIPCHK(s, timed(s, K_INT, [&] { return launch_integrate(a, s->st); }));
         s->cur = 1 - s->cur;
         s->step++;
     }
@@ -609,10 +651,12 @@ int cgb_get_observables(cgb_sim* s, double* out) {
     bind_buffers(s);
     HIPCHK(s, launch_observables(a, s->obs_partial, s->obs_nblk, s->st));
     std::vector<double> part((size_t)s->obs_nblk * 8);
+    const int nbb = (a.n + 255) / 256;
+    std::vector<double> bpart(3 * (size_t)std::max(nbb, 1), 0.0);
     double bp[3] = {0, 0, 0};
     int bad = 0;
     HIPCHK(s, hipMemcpyAsync(part.data(), s->obs_partial, part.size() * 8, hipMemcpyDeviceToHost, s->st));
-    HIPCHK(s, hipMemcpyAsync(bp, a.body_part, 24, hipMemcpyDeviceToHost, s->st));
+    if (nbb) HIPCHK(s, hipMemcpyAsync(bpart.data(), a.body_part, 3 * (size_t)nbb * 8, hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipMemcpyAsync(&bad, a.bad_step, 4, hipMemcpyDeviceToHost, s->st));
     std::vector<double> V(3 * (size_t)a.n);
     std::vector<uint8_t> fx((size_t)a.n);
@@ -621,6 +665,8 @@ int cgb_get_observables(cgb_sim* s, double* out) {
         HIPCHK(s, hipMemcpyAsync(fx.data(), a.fixed, fx.size(), hipMemcpyDeviceToHost, s->st));
     }
     HIPCHK(s, hipStreamSynchronize(s->st));
+    for (int b = 0; b < nbb; b++)
+        for (int c = 0; c < 3; c++) bp[c] += bpart[3 * (size_t)b + c];
     double acc[8] = {0};
     for (int b = 0; b < s->obs_nblk; b++)
         for (int k = 0; k < 8; k++) acc[k] += part[8 * (size_t)b + k];
@@ -758,6 +804,7 @@ int cgb_load(cgb_sim* s, const char* path) {
     s->fluid_ready = true;
     bind_buffers(s);
     HIPCHK(s, launch_fill_i32(a.cand, a.ns, NO_CAND, s->st));
+    HIPCHK(s, launch_fill_i32(a.stamp, (long long)std::max(s->ncap, 1) * a.nslot, 0, s->st));
     HIPCHK(s, launch_cells(a, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     return CGB_OK;
