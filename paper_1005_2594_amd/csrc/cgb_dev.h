@@ -72,6 +72,7 @@ struct DevArgs {
     double* L;      // n*3
     uint8_t* fixed;
     double* Xprev;  // n*3, position of the last rasterisation
+    double* Hprev;  // n*3, axis-aligned half extents at the last rasterisation
     double* kin;    // n*12: X, V, Omega, axis (gathered by the LB kernel)
     double* FTh;    // n*6 hydrodynamic force, torque (accumulated)
     double* FTp;    // n*6 potential force, torque

@@ -275,10 +275,52 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
     }
 }
 
+// One cell's share of a fluid node's links (mask = its link bits): with
+// C_r = 6 w_r rho (c_r . U), U the rigid-body velocity at the node,
+//   sum_r C_r     = 6 rho (sum w_r c_r) . U,
+//   sum_r C_r c_r = 6 rho (sum w_r c_r c_r^T) U,
+// and the momentum to the cell is -(2 sum own_r c_r + sum C_r c_r), where
+// own_r is the node's bounced population.  sown = sum own_r c_r over mask.
+template <int P>
+__device__ inline void cell_links(const DevArgs& a, int x, int y, int z, int p, uint32_t mask, double rho_x,
+                                  const double* sown, double* cm /* dC rho, dC j */, double* F, double* Tq,
+                                  double* lev) {
+    const double* k = a.kin + 12 * (size_t)p;
+    const double l0 = min_image((double)x - k[0], (double)a.nx);
+    const double l1 = a.wall_y ? ((double)y - k[1]) : min_image((double)y - k[1], (double)a.ny);
+    const double l2 = min_image((double)z - k[2], (double)a.nz);
+    const double U0 = k[3] + (k[7] * l2 - k[8] * l1);
+    const double U1 = k[4] + (k[8] * l0 - k[6] * l2);
+    const double U2 = k[5] + (k[6] * l1 - k[7] * l0);
+    // geometric sums over the link set (constants of the lattice)
+    double a0 = 0, a1 = 0, a2 = 0, mxx = 0, myy = 0, mzz = 0, mxy = 0, mxz = 0, myz = 0;
+#pragma unroll
+    for (int r = 1; r < 19; r++) {
+        if ((mask >> r) & 1u) {
+            const double w = WD(r);
+            a0 += w * CX(r); a1 += w * CY(r); a2 += w * CZ(r);
+            mxx += w * (CX(r) * CX(r)); myy += w * (CY(r) * CY(r)); mzz += w * (CZ(r) * CZ(r));
+            mxy += w * (CX(r) * CY(r)); mxz += w * (CX(r) * CZ(r)); myz += w * (CY(r) * CZ(r));
+        }
+    }
+    const double rc = 6.0 * rho_x;
+    const double sc = rc * (a0 * U0 + a1 * U1 + a2 * U2);
+    const double c0 = rc * (mxx * U0 + mxy * U1 + mxz * U2);
+    const double c1 = rc * (mxy * U0 + myy * U1 + myz * U2);
+    const double c2 = rc * (mxz * U0 + myz * U1 + mzz * U2);
+    cm[0] += sc; cm[1] += c0; cm[2] += c1; cm[3] += c2;
+    F[0] = -(2.0 * sown[0] + c0);
+    F[1] = -(2.0 * sown[1] + c1);
+    F[2] = -(2.0 * sown[2] + c2);
+    Tq[0] = l1 * F[2] - l2 * F[1];
+    Tq[1] = l2 * F[0] - l0 * F[2];
+    Tq[2] = l0 * F[1] - l1 * F[0];
+    lev[0] = l0; lev[1] = l1; lev[2] = l2;
+}
+
 // tau = 1 (the paper's operating point, Sec. IV): the post-collision state is
 // n^eq(rho, u) plus the forcing term, a function of the moments alone, so the
 // pulled populations are folded into rho and j as they arrive and never held.
-// Momentum exchange re-reads the node's own bounced population.
 template <int P, int TZ>
 __global__ void __launch_bounds__(256) lb_kernel_tau1(DevArgs a) {
     using Cd = Codec<P>;
@@ -324,83 +366,104 @@ __global__ void __launch_bounds__(256) lb_kernel_tau1(DevArgs a) {
         if (f & NONFLUID) continue;
         const int oz[3] = {z == a.nz - 1 ? -(int)((a.nz - 1) * plane) : (int)plane, 0,
                            z == 0 ? (int)((a.nz - 1) * plane) : -(int)plane};
+#define SRC(r) (i + (unsigned)(ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1]))
 
-        // moments of the pulled populations (non-fluid source: bounce-back)
+        // owners behind the links: the first cell p1 and its links, other cells
+        const uint32_t links = f & LINKBITS;
+        int p1 = -1;
+        uint32_t pm1 = 0, pmo = 0;
+        if (links) {
+#pragma unroll
+            for (int r = 1; r < 19; r++) {
+                if ((links >> r) & 1u) {
+                    const int o = bload<int>(rOwn, 4u * SRC(r));
+                    if (o >= 0) {
+                        if (p1 < 0) p1 = o;
+                        if (o == p1) pm1 |= 1u << r;
+                        else pmo |= 1u << r;
+                    }
+                }
+            }
+        }
+
+        // moments of the pulled populations (non-fluid source: bounce-back);
+        // sum of own_r c_r over p1's links on the way
         R drho = 0, jx = 0, jy = 0, jz = 0;
+        double so0 = 0.0, so1 = 0.0, so2 = 0.0;
 #pragma unroll
         for (int r = 0; r < 19; r++) {
             const bool bb = (f >> r) & 1u;
-            const unsigned src = i + (unsigned)(ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1]);
-            const T v = bload<T>(rA, ES * (bb ? (unsigned)OPP(r) * ps + i : (unsigned)r * ps + src));
+            const T v = bload<T>(rA, ES * (bb ? (unsigned)OPP(r) * ps + i : (unsigned)r * ps + SRC(r)));
             const R dv = Cd::dec(v, dec_scale<P>(a, r));
             drho += dv;
             if (CX(r)) jx += CX(r) * dv;
             if (CY(r)) jy += CY(r) * dv;
             if (CZ(r)) jz += CZ(r) * dv;
+            if (r > 0 && ((pm1 >> r) & 1u)) {
+                const double dd = (double)dv;
+                if (CX(r)) so0 += CX(r) * dd;
+                if (CY(r)) so1 += CY(r) * dd;
+                if (CZ(r)) so2 += CZ(r) * dd;
+            }
         }
 
-        const uint32_t links = f & LINKBITS;
         if (links) {
-            uint32_t pmask = 0;
-            for (uint32_t m = links; m; m &= m - 1) {
-                const int r = __builtin_ctz(m);
-                if (bload<int>(rOwn, 4u * (i + (unsigned)(ox[1 + cxr(r)] + oy[1 + cyr(r)] + oz[1 + czr(r)]))) >= 0) pmask |= 1u << r;
-            }
-            const uint32_t wl = a.moving_walls ? (links & ~pmask) : 0u;
+            const uint32_t wl = a.moving_walls ? (links & ~(pm1 | pmo)) : 0u;
             double rho_x = 0.0;
-            if (pmask | wl) rho_x = a.rho0 + (double)Cd::dec(bload<T>(rRA, ES * i), rho_dec_scale<P>(a));
-            double cr = 0.0, cjx = 0.0, cjy = 0.0, cjz = 0.0;  // moments of the corrections C
-            while (pmask) {
-                const int r0 = __builtin_ctz(pmask);
-                const int p = bload<int>(rOwn, 4u * (i + (unsigned)(ox[1 + cxr(r0)] + oy[1 + cyr(r0)] + oz[1 + czr(r0)])));
-                const double* k = a.kin + 12 * (size_t)p;
-                const double l0 = min_image((double)x - k[0], (double)a.nx);
-                const double l1 = a.wall_y ? ((double)y - k[1]) : min_image((double)y - k[1], (double)a.ny);
-                const double l2 = min_image((double)z - k[2], (double)a.nz);
-                const double U0 = k[3] + (k[7] * l2 - k[8] * l1);
-                const double U1 = k[4] + (k[8] * l0 - k[6] * l2);
-                const double U2 = k[5] + (k[6] * l1 - k[7] * l0);
-                const double rc = 6.0 * rho_x;
-                double F0 = 0.0, F1 = 0.0, F2 = 0.0;
-                for (uint32_t m = pmask; m; m &= m - 1) {
-                    const int r = __builtin_ctz(m);
-                    const int cx = cxr(r), cy = cyr(r), cz = czr(r);
-                    if (r != r0 && bload<int>(rOwn, 4u * (i + (unsigned)(ox[1 + cx] + oy[1 + cy] + oz[1 + cz]))) != p) continue;
-                    pmask &= ~(1u << r);
-                    const int rb = r + ((r & 1) ? 1 : -1);
-                    const double own = (double)Cd::dec(bload<T>(rA, ES * ((unsigned)rb * ps + i)), dec_scale<P>(a, r));
-                    const double w = r <= 6 ? (1.0 / 18.0) : (1.0 / 36.0);
-                    const double C = w * rc * (cx * U0 + cy * U1 + cz * U2);
-                    const double dyn = 2.0 * own + C;
-                    F0 -= dyn * cx; F1 -= dyn * cy; F2 -= dyn * cz;
-                    cr += C; cjx += C * cx; cjy += C * cy; cjz += C * cz;
-                }
+            if (pm1 | wl) rho_x = a.rho0 + (double)Cd::dec(bload<T>(rRA, ES * i), rho_dec_scale<P>(a));
+            double cm[4] = {0, 0, 0, 0};
+            int p = p1;
+            uint32_t mask = pm1;
+            double sown[3] = {so0, so1, so2};
+            while (mask) {
+                double F[3], Tq[3], lev[3];
+                cell_links<P>(a, x, y, z, p, mask, rho_x, sown, cm, F, Tq, lev);
                 if (p != spid) {
                     if (spid >= 0) table_add(tb, a, spid, acc);
                     spid = p;
 #pragma unroll
                     for (int c = 0; c < 6; c++) acc[c] = 0.0;
                 }
-                acc[0] += F0; acc[1] += F1; acc[2] += F2;
-                acc[3] += l1 * F2 - l2 * F1;
-                acc[4] += l2 * F0 - l0 * F2;
-                acc[5] += l0 * F1 - l1 * F0;
+                acc[0] += F[0]; acc[1] += F[1]; acc[2] += F[2];
+                acc[3] += Tq[0]; acc[4] += Tq[1]; acc[5] += Tq[2];
+                // next cell among the remaining links (rare): reload from cache
+                mask = 0;
+                if (pmo) {
+                    p = bload<int>(rOwn, 4u * (i + (unsigned)(ox[1 + cxr(__builtin_ctz(pmo))] + oy[1 + cyr(__builtin_ctz(pmo))] +
+                                                               oz[1 + czr(__builtin_ctz(pmo))])));
+                    sown[0] = sown[1] = sown[2] = 0.0;
+                    for (uint32_t m = pmo; m; m &= m - 1) {
+                        const int r = __builtin_ctz(m);
+                        const int cx = cxr(r), cy = cyr(r), cz = czr(r);
+                        if (bload<int>(rOwn, 4u * (i + (unsigned)(ox[1 + cx] + oy[1 + cy] + oz[1 + cz]))) != p) continue;
+                        mask |= 1u << r;
+                        const unsigned rb = (unsigned)(r + ((r & 1) ? 1 : -1));
+                        const double dd = (double)Cd::dec(bload<T>(rA, ES * (rb * ps + i)), dec_scale<P>(a, r));
+                        sown[0] += cx * dd; sown[1] += cy * dd; sown[2] += cz * dd;
+                    }
+                    pmo &= ~mask;
+                }
             }
-            for (uint32_t m = wl; m; m &= m - 1) {
-                const int r = __builtin_ctz(m);
-                const int cx = cxr(r), cy = cyr(r), cz = czr(r);
-                const int ys = y - cy;
-                const bool bot = a.wall_y && ys == 0, top = a.wall_y && ys == a.ny - 1;
-                if (!(bot || top)) continue;
-                const double w0 = bot ? a.wvb[0] : a.wvt[0];
-                const double w1 = bot ? a.wvb[1] : a.wvt[1];
-                const double w2 = bot ? a.wvb[2] : a.wvt[2];
-                const double w = r <= 6 ? (1.0 / 18.0) : (1.0 / 36.0);
-                const double C = 6.0 * w * rho_x * (cx * w0 + cy * w1 + cz * w2);
-                cr += C; cjx += C * cx; cjy += C * cy; cjz += C * cz;
+            if (wl) {
+                // moving wall planes: same sums with the wall velocity
+#pragma unroll
+                for (int r = 1; r < 19; r++) {
+                    if ((wl >> r) & 1u) {
+                        const int ys = y - CY(r);
+                        const bool bot = a.wall_y && ys == 0, top = a.wall_y && ys == a.ny - 1;
+                        if (bot || top) {
+                            const double w0 = bot ? a.wvb[0] : a.wvt[0];
+                            const double w1 = bot ? a.wvb[1] : a.wvt[1];
+                            const double w2 = bot ? a.wvb[2] : a.wvt[2];
+                            const double C = 6.0 * WD(r) * rho_x * (CX(r) * w0 + CY(r) * w1 + CZ(r) * w2);
+                            cm[0] += C; cm[1] += C * CX(r); cm[2] += C * CY(r); cm[3] += C * CZ(r);
+                        }
+                    }
+                }
             }
-            drho += (R)cr; jx += (R)cjx; jy += (R)cjy; jz += (R)cjz;
+            drho += (R)cm[0]; jx += (R)cm[1]; jy += (R)cm[2]; jz += (R)cm[3];
         }
+#undef SRC
 
         // n* = n^eq(rho, u) + Guo term (tau = 1)
         const R rho = (R)a.rho0 + drho;

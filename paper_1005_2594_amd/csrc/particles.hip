@@ -84,37 +84,42 @@ hipError_t launch_clear_cells(const DevArgs& a, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ raster
-// union of the bounding boxes at the previous and the current position
-__device__ inline void union_box(const DevArgs& a, int p, int* lo, int* ext) {
+// Axis-aligned half extents of the ellipsoid with axis o: along axis a every
+// inside node has |x_a - X_a| < sqrt(R_perp^2 - (R_perp^2 - R_par^2) o_a^2);
+// a small margin keeps nodes whose inside test rounds the other way.
+__device__ inline void half_extents(const DevArgs& a, const double* o, double* h) {
+    const double rp2 = 1.0 / a.iRperp2, rl2 = 1.0 / a.iRpar2;
+    for (int c = 0; c < 3; c++) h[c] = sqrt(fmax(rp2 - (rp2 - rl2) * o[c] * o[c], 0.0)) + 1e-6;
+}
+
+// union of the boxes at the previous rasterisation (Xprev, Hprev) and now.
+// Returns false (and flags instability) for a box that is not finite or wider
+// than a cell moving less than half a node per step can span, so that no
+// state of the cells can send the walk outside the lattice.
+__device__ inline bool union_box(const DevArgs& a, int p, int* lo, int* ext) {
+    const double* k = a.kin + 12 * (long long)p;
+    double h[3];
+    half_extents(a, k + 9, h);
+    const int maxext = 2 * (int)ceil(a.Rb) + 6;
     for (int c = 0; c < 3; c++) {
         double x0 = a.Xprev[3 * p + c];
-        const double x1 = a.X[3 * p + c];
+        const double x1 = k[c];
+        const double Lb = c == 0 ? a.nx : (c == 1 ? a.ny : a.nz);
         if (c != 1 || !a.wall_y) {
             // a cell that crossed the periodic boundary: unwrap the old position
-            const double Lb = c == 0 ? a.nx : (c == 1 ? a.ny : a.nz);
             const double d = x0 - x1;
             if (d > 0.5 * Lb) x0 -= Lb;
             else if (d < -0.5 * Lb) x0 += Lb;
         }
-        const double mn = x0 < x1 ? x0 : x1, mx = x0 < x1 ? x1 : x0;
-        lo[c] = (int)floor(mn - a.Rb);
-        ext[c] = (int)ceil(mx + a.Rb) - lo[c] + 1;
+        const double hp = a.Hprev[3 * p + c];
+        const double mn = fmin(x0 - hp, x1 - h[c]), mx = fmax(x0 + hp, x1 + h[c]);
+        if (!(mn > -Lb && mx < 2.0 * Lb && mx - mn < (double)maxext)) {
+            atomicOr(a.status, ST_UNSTABLE);
+            return false;
+        }
+        lo[c] = (int)floor(mn);
+        ext[c] = (int)ceil(mx) - lo[c] + 1;
     }
-}
-
-__device__ inline bool box_node(const DevArgs& a, const int* lo, const int* ext, int k, int* x, int* y, int* z) {
-    const int ix = k % ext[0];
-    const int iy = (k / ext[0]) % ext[1];
-    const int iz = k / (ext[0] * ext[1]);
-    int yy = lo[1] + iy;
-    if (a.wall_y) {
-        if (yy < 0 || yy >= a.ny) return false;
-    } else {
-        yy = ((yy % a.ny) + a.ny) % a.ny;
-    }
-    *x = ((lo[0] + ix) % a.nx + a.nx) % a.nx;
-    *y = yy;
-    *z = ((lo[2] + iz) % a.nz + a.nz) % a.nz;
     return true;
 }
 
@@ -126,54 +131,63 @@ __device__ inline bool covers(const DevArgs& a, int p, int x, int y, int z) {
     return inside_test(a, d, o);
 }
 
-// one wave per cell
-__global__ void __launch_bounds__(64) raster_cover_kernel(DevArgs a) {
+// one wave per cell: lane (ix, iy) of an 8 x 8 footprint walks z
+template <bool RESOLVE>
+__global__ void __launch_bounds__(64) raster_kernel(DevArgs a) {
     const int p = blockIdx.x;
     if (p >= a.n) return;
     int lo[3], ext[3];
-    union_box(a, p, lo, ext);
-    const int tot = ext[0] * ext[1] * ext[2];
-    for (int k = threadIdx.x; k < tot; k += 64) {
-        int x, y, z;
-        if (!box_node(a, lo, ext, k, &x, &y, &z)) continue;
-        const long long s = x + (long long)a.nx * (y + (long long)a.ny * z);
-        const int o = a.owner[s];
-        if (o == OWN_WALL || o == p) continue;  // the owner keeps a node it still covers
-        if (covers(a, p, x, y, z)) atomicMin(a.cand + s, p);
-    }
-}
-
-__global__ void __launch_bounds__(64) raster_resolve_kernel(DevArgs a) {
-    const int p = blockIdx.x;
-    if (p >= a.n) return;
-    int lo[3], ext[3];
-    union_box(a, p, lo, ext);
-    const int tot = ext[0] * ext[1] * ext[2];
-    for (int k = threadIdx.x; k < tot; k += 64) {
-        int x, y, z;
-        if (!box_node(a, lo, ext, k, &x, &y, &z)) continue;
-        const long long s = x + (long long)a.nx * (y + (long long)a.ny * z);
-        const int o = a.owner[s];
-        if (o == OWN_WALL) continue;
-        const int c = a.cand[s];
-        const bool mine = (o == p) || (o == OWN_FLUID && c == p);
-        if (!mine) continue;
-        const bool keep = (o == p) && covers(a, p, x, y, z);
-        const int nw = keep ? p : (c != NO_CAND ? c : OWN_FLUID);
-        a.cand[s] = NO_CAND;
-        if (nw != o) {
-            const int t = atomicAdd(a.ntrans, 1);
-            if (t < a.trans_cap) {
-                a.trans[3 * t] = (int)s;
-                a.trans[3 * t + 1] = o;
-                a.trans[3 * t + 2] = nw;
+    if (!union_box(a, p, lo, ext)) return;
+    for (int bx = 0; bx < ext[0]; bx += 8)
+        for (int by = 0; by < ext[1]; by += 8) {
+            const int ix = bx + (threadIdx.x & 7), iy = by + (threadIdx.x >> 3);
+            if (ix >= ext[0] || iy >= ext[1]) continue;
+            int x = lo[0] + ix;
+            x = x < 0 ? x + a.nx : (x >= a.nx ? x - a.nx : x);
+            int y = lo[1] + iy;
+            if (a.wall_y) {
+                if (y < 0 || y >= a.ny) continue;
             } else {
-                atomicOr(a.status, ST_TRANS_OVERFLOW);
+                y = y < 0 ? y + a.ny : (y >= a.ny ? y - a.ny : y);
+            }
+            for (int iz = 0; iz < ext[2]; iz++) {
+                int z = lo[2] + iz;
+                z = z < 0 ? z + a.nz : (z >= a.nz ? z - a.nz : z);
+                const long long s = x + (long long)a.nx * (y + (long long)a.ny * z);
+                const int o = a.owner[s];
+                if (o == OWN_WALL) continue;
+                if (!RESOLVE) {
+                    // the owner keeps a node it still covers: no claim needed
+                    if (o != p && covers(a, p, x, y, z)) atomicMin(a.cand + s, p);
+                    continue;
+                }
+                const bool mine = (o == p) || (o == OWN_FLUID && a.cand[s] == p);
+                if (!mine) continue;
+                const int c = a.cand[s];
+                const bool keep = (o == p) && covers(a, p, x, y, z);
+                const int nw = keep ? p : (c != NO_CAND ? c : OWN_FLUID);
+                if (c != NO_CAND) a.cand[s] = NO_CAND;
+                if (nw != o) {
+                    const int t = atomicAdd(a.ntrans, 1);
+                    if (t < a.trans_cap) {
+                        a.trans[3 * t] = (int)s;
+                        a.trans[3 * t + 1] = o;
+                        a.trans[3 * t + 2] = nw;
+                    } else {
+                        atomicOr(a.status, ST_TRANS_OVERFLOW);
+                    }
+                }
             }
         }
+    if (RESOLVE) {
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            double h[3];
+            half_extents(a, a.kin + 12 * (long long)p + 9, h);
+            a.Xprev[3 * p + threadIdx.x] = a.kin[12 * (long long)p + threadIdx.x];
+            a.Hprev[3 * p + threadIdx.x] = h[threadIdx.x];
+        }
     }
-    __syncthreads();
-    if (threadIdx.x < 3) a.Xprev[3 * p + threadIdx.x] = a.X[3 * p + threadIdx.x];
 }
 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
@@ -181,8 +195,8 @@ __global__ void zero_int_kernel(int* p) { *p = 0; }
 hipError_t launch_raster(const DevArgs& a, hipStream_t st, bool) {
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, a.ntrans);
     if (a.n == 0) return hipGetLastError();
-    hipLaunchKernelGGL(raster_cover_kernel, dim3(a.n), dim3(64), 0, st, a);
-    hipLaunchKernelGGL(raster_resolve_kernel, dim3(a.n), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(raster_kernel<false>, dim3(a.n), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(raster_kernel<true>, dim3(a.n), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 
@@ -639,15 +653,23 @@ __device__ void integrate_one(const DevArgs& a, int p, double* bf) {
     double gb[3] = {0, 0, 0};
     if (a.force_on_particles) body_force(a, a.X[3 * p + 1], gb);
     bool bad = false;
-    double Lnew[3];
+    double Lnew[3], Vn[3];
     for (int c = 0; c < 3; c++) {
         const double F = a.FTh[6 * p + c] + a.FTp[6 * p + c] + a.M * gb[c];
-        const double v = a.V[3 * p + c] + F / a.M;
-        a.V[3 * p + c] = v;
+        Vn[c] = a.V[3 * p + c] + F / a.M;
         Lnew[c] = a.L[3 * p + c] + (a.FTh[6 * p + 3 + c] + a.FTp[6 * p + 3 + c]);
+        if (!(fabs(Vn[c]) < 0.5) || !(fabs(Lnew[c]) < 1e30)) bad = true;
+    }
+    if (bad) {
+        // unstable: flag it and leave the cell where it is, inside the box
+        atomicOr(a.status, ST_UNSTABLE);
+        atomicMin(a.bad_step, (int)a.step);
+        return;
+    }
+    for (int c = 0; c < 3; c++) {
+        a.V[3 * p + c] = Vn[c];
         a.L[3 * p + c] = Lnew[c];
-        if (!(fabs(v) < 0.5)) bad = true;
-        double xn = a.X[3 * p + c] + v;
+        double xn = a.X[3 * p + c] + Vn[c];
         if (!(c == 1 && a.wall_y)) {
             const double Lb = c == 0 ? a.nx : (c == 1 ? a.ny : a.nz);
             if (xn >= Lb) xn -= Lb;
@@ -670,7 +692,7 @@ __device__ void integrate_one(const DevArgs& a, int p, double* bf) {
     qmul(dq, q, qn);
     qnormalise(qn);
     for (int c = 0; c < 4; c++) a.q[4 * p + c] = qn[c];
-    if (bad || !(qn[0] == qn[0])) {
+    if (!(qn[0] == qn[0])) {
         atomicOr(a.status, ST_UNSTABLE);
         atomicMin(a.bad_step, (int)a.step);
     }

@@ -245,7 +245,7 @@ static int alloc_slots(cgb_sim* s) {
 
 static int alloc_particles(cgb_sim* s, int ncap) {
     DevArgs& a = s->a;
-    void* olds[] = {a.X, a.q, a.V, a.L, a.fixed, a.Xprev, a.kin, a.FTh, a.FTp, a.trans, a.pbin, a.bin_idx, a.body_part};
+    void* olds[] = {a.X, a.q, a.V, a.L, a.fixed, a.Xprev, a.Hprev, a.kin, a.FTh, a.FTp, a.trans, a.pbin, a.bin_idx, a.body_part};
     for (void* p : olds) dfree(s, p);
     const size_t n = (size_t)std::max(ncap, 1);
     HIPCHK(s, dalloc(s, &a.X, 3 * n * 8));
@@ -254,6 +254,7 @@ static int alloc_particles(cgb_sim* s, int ncap) {
     HIPCHK(s, dalloc(s, &a.L, 3 * n * 8));
     HIPCHK(s, dalloc(s, &a.fixed, n));
     HIPCHK(s, dalloc(s, &a.Xprev, 3 * n * 8));
+    HIPCHK(s, dalloc(s, &a.Hprev, 3 * n * 8));
     HIPCHK(s, dalloc(s, &a.kin, 12 * n * 8));
     HIPCHK(s, dalloc(s, &a.FTh, 6 * n * 8));
     HIPCHK(s, dalloc(s, &a.FTp, 6 * n * 8));
@@ -450,6 +451,7 @@ int cgb_set_particles(cgb_sim* s, int32_t n, const double* X, const double* q, c
     if (n > 0) {
         HIPCHK(s, hipMemcpyAsync(a.X, Xw.data(), 3 * (size_t)n * 8, hipMemcpyHostToDevice, s->st));
         HIPCHK(s, hipMemcpyAsync(a.Xprev, Xw.data(), 3 * (size_t)n * 8, hipMemcpyHostToDevice, s->st));
+        HIPCHK(s, launch_fill_f64(a.Hprev, 3 * (long long)n, a.Rb + 1e-6, s->st));
         HIPCHK(s, hipMemcpyAsync(a.q, q, 4 * (size_t)n * 8, hipMemcpyHostToDevice, s->st));
         HIPCHK(s, hipMemcpyAsync(a.V, V ? V : zero.data(), 3 * (size_t)n * 8, hipMemcpyHostToDevice, s->st));
         HIPCHK(s, hipMemcpyAsync(a.L, L ? L : zero.data(), 3 * (size_t)n * 8, hipMemcpyHostToDevice, s->st));
@@ -754,7 +756,7 @@ int cgb_save(cgb_sim* s, const char* path) {
     if (a.n) {
         const size_t n = (size_t)a.n;
         dump(a.X, 3 * n * 8); dump(a.q, 4 * n * 8); dump(a.V, 3 * n * 8); dump(a.L, 3 * n * 8);
-        dump(a.fixed, n); dump(a.Xprev, 3 * n * 8);
+        dump(a.fixed, n); dump(a.Xprev, 3 * n * 8); dump(a.Hprev, 3 * n * 8);
     }
     fclose(f);
     if (!ok) FAIL(s, CGB_EDEVICE, "write to %s failed", path);
@@ -796,7 +798,7 @@ int cgb_load(cgb_sim* s, const char* path) {
     if (n) {
         const size_t nn = (size_t)n;
         load(a.X, 3 * nn * 8); load(a.q, 4 * nn * 8); load(a.V, 3 * nn * 8); load(a.L, 3 * nn * 8);
-        load(a.fixed, nn); load(a.Xprev, 3 * nn * 8);
+        load(a.fixed, nn); load(a.Xprev, 3 * nn * 8); load(a.Hprev, 3 * nn * 8);
     }
     fclose(f);
     if (!ok) FAIL(s, CGB_EINVAL, "checkpoint %s is truncated", path);
