@@ -109,7 +109,8 @@ int cgb_step(cgb_sim* s, int32_t nsteps);
  * instability check (the first such step is in cgb_get_observables out[12]). */
 int cgb_sync(cgb_sim* s);
 
-/* Read-out (synchronises first).  Sizes: d 19*nsites; rho nsites; u nsites*3
+/* Read-out (synchronises first; returns the current state and CGB_OK even
+ * after an instability, which cgb_sync reports).  Sizes: d 19*nsites; rho nsites; u nsites*3
  * (u = (sum n* c - g/2)/rho, zero on non-fluid nodes); X,V,L n*3; q n*4;
  * forces n*3 each (hydrodynamic incl. cover/uncover, and potential) of the
  * last step; owner nsites (-2 wall, -1 fluid, p >= 0 cell); link mask

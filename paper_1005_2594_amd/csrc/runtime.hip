@@ -539,7 +539,7 @@ int cgb_get_populations(cgb_sim* s, double* d) {
     HIPCHK(s, launch_decode(a, s->tmp, s->st));
     HIPCHK(s, hipMemcpyAsync(d, s->tmp, bytes, hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
-    return rc;
+    return CGB_OK;
 }
 
 int cgb_get_fields(cgb_sim* s, double* rho, double* u) {
@@ -555,7 +555,7 @@ int cgb_get_fields(cgb_sim* s, double* rho, double* u) {
     if (rho) HIPCHK(s, hipMemcpyAsync(rho, s->tmp, nsb, hipMemcpyDeviceToHost, s->st));
     if (u) HIPCHK(s, hipMemcpyAsync(u, s->tmp + a.ns, 3 * nsb, hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
-    return rc;
+    return CGB_OK;
 }
 
 int cgb_get_particles(cgb_sim* s, double* X, double* q, double* V, double* L) {
@@ -570,7 +570,7 @@ int cgb_get_particles(cgb_sim* s, double* X, double* q, double* V, double* L) {
         if (L) HIPCHK(s, hipMemcpyAsync(L, s->a.L, 3 * n * 8, hipMemcpyDeviceToHost, s->st));
         HIPCHK(s, hipStreamSynchronize(s->st));
     }
-    return rc;
+    return CGB_OK;
 }
 
 int cgb_get_forces(cgb_sim* s, double* Fh, double* Th, double* Fp, double* Tp) {
@@ -578,7 +578,7 @@ int cgb_get_forces(cgb_sim* s, double* Fh, double* Th, double* Fp, double* Tp) {
     int rc = cgb_sync(s);
     if (rc && rc != CGB_EUNSTABLE) return rc;
     const size_t n = (size_t)s->a.n;
-    if (!n) return rc;
+    if (!n) return CGB_OK;
     std::vector<double> h(6 * n), pp(6 * n);
     HIPCHK(s, hipMemcpyAsync(h.data(), s->a.FTh, 6 * n * 8, hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipMemcpyAsync(pp.data(), s->a.FTp, 6 * n * 8, hipMemcpyDeviceToHost, s->st));
@@ -590,7 +590,7 @@ int cgb_get_forces(cgb_sim* s, double* Fh, double* Th, double* Fp, double* Tp) {
             if (Fp) Fp[3 * i + c] = pp[6 * i + c];
             if (Tp) Tp[3 * i + c] = pp[6 * i + 3 + c];
         }
-    return rc;
+    return CGB_OK;
 }
 
 int cgb_get_owner(cgb_sim* s, int32_t* owner) {
@@ -599,7 +599,7 @@ int cgb_get_owner(cgb_sim* s, int32_t* owner) {
     if (rc && rc != CGB_EUNSTABLE) return rc;
     HIPCHK(s, hipMemcpyAsync(owner, s->a.owner, (size_t)s->a.ns * 4, hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
-    return rc;
+    return CGB_OK;
 }
 
 int cgb_get_link_mask(cgb_sim* s, uint32_t* mask) {
@@ -609,7 +609,7 @@ int cgb_get_link_mask(cgb_sim* s, uint32_t* mask) {
     HIPCHK(s, hipMemcpyAsync(mask, s->a.flags, (size_t)s->a.ns * 4, hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     for (long long i = 0; i < s->a.ns; i++) mask[i] = (mask[i] & NONFLUID) ? 0u : (mask[i] & LINKBITS);
-    return rc;
+    return CGB_OK;
 }
 
 int cgb_get_pairs(cgb_sim* s, int32_t* ij, int64_t cap, int64_t* n) {
@@ -642,7 +642,7 @@ int cgb_get_pairs(cgb_sim* s, int32_t* ij, int64_t cap, int64_t* n) {
             ij[2 * k] = pr[(size_t)k].first;
             ij[2 * k + 1] = pr[(size_t)k].second;
         }
-    return rc;
+    return CGB_OK;
 }
 
 int cgb_get_observables(cgb_sim* s, double* out) {
@@ -684,7 +684,7 @@ int cgb_get_observables(cgb_sim* s, double* out) {
     out[7] = acc[4];
     out[11] = (double)s->step;
     out[12] = bad == 0x7fffffff ? -1.0 : (double)bad;
-    return rc;
+    return CGB_OK;
 }
 
 int cgb_get_profile_z(cgb_sim* s, double* prof) {
@@ -702,7 +702,7 @@ int cgb_get_profile_z(cgb_sim* s, double* prof) {
     HIPCHK(s, hipMemcpyAsync(h.data(), s->tmp, h.size() * 8, hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     for (int y = 0; y < a.ny; y++) prof[y] = h[(size_t)a.ny + y] > 0 ? h[(size_t)y] / h[(size_t)a.ny + y] : 0.0;
-    return rc;
+    return CGB_OK;
 }
 
 int cgb_profile(cgb_sim* s, int enable) {
