@@ -64,33 +64,43 @@ def run_gpu(cfg, prec, steps, warmup, profile=True):
     return out
 
 
-def velocity_error_64(seed=3, steps=500):
+def velocity_error_64(seed=3, horizons=(100, 500)):
     """Mixed and FP32 paths against the FP64 path of the same kernels on the
-    64^3 companion workload (same cell density; the FP64 path itself matches
-    the oracle to 1e-12 in the parity tests)."""
+    64^3 companion workload (same cell density; the FP64 path matches the
+    oracle to ~1e-14 over 250 steps in the parity runs).  Pointwise errors are
+    reported at a short horizon, before discrete events (a node changing
+    owner, a pair crossing the cut-off) happen at different steps in different
+    precisions; the mixture velocity profile u_z(y) is the long-horizon
+    measure."""
     from paper_1005_2594_amd import Sim
     cfg = synth.config3_companion(seed=seed)
-    res = {}
-    u = {}
-    X = {}
-    for prec in ("p64", "p32", "pmx16"):
-        s = Sim(cfg["params"], precision=prec)
+    sims = {p: Sim(cfg["params"], precision=p) for p in ("p64", "p32", "pmx16")}
+    for s in sims.values():
         s.set_particles(cfg["X"], cfg["q"])
         s.init_fluid()
-        s.step(steps)
-        own = s.owner()
-        _, uu = s.fields()
-        u[prec] = (own, uu)
-        X[prec] = s.particles()[0]
+    res = {p: {} for p in ("p32", "pmx16")}
+    done = 0
+    for t in horizons:
+        for s in sims.values():
+            s.step(t - done)
+        done = t
+        own64 = sims["p64"].owner()
+        _, u64 = sims["p64"].fields()
+        X64 = sims["p64"].particles()[0]
+        pr64 = sims["p64"].profile_z()
+        for p in ("p32", "pmx16"):
+            own = sims[p].owner()
+            _, u = sims[p].fields()
+            X = sims[p].particles()[0]
+            m = (own == -1) & (own64 == -1)
+            pr = sims[p].profile_z()
+            res[p][f"step{t}"] = dict(
+                rel_l2_u=float(np.linalg.norm(u[m] - u64[m]) / np.linalg.norm(u64[m])),
+                rel_l2_profile=float(np.linalg.norm(pr - pr64) / np.linalg.norm(pr64)),
+                pos_rms=float(np.sqrt(np.mean(np.sum((X - X64) ** 2, axis=1)))),
+                owner_flips=int((own != own64).sum()))
+    for s in sims.values():
         s.close()
-    own64, u64 = u["p64"]
-    for prec in ("p32", "pmx16"):
-        own, uu = u[prec]
-        m = (own == -1) & (own64 == -1)
-        res[prec] = dict(
-            rel_l2_u=float(np.linalg.norm(uu[m] - u64[m]) / np.linalg.norm(u64[m])),
-            pos_rms=float(np.sqrt(np.mean(np.sum((X[prec] - X["p64"]) ** 2, axis=1)))),
-        )
     return res
 
 
@@ -176,7 +186,7 @@ def main():
         line["config"]["p32_lb_frac"] = round(lb_algorithmic_bytes(r32["n_fluid"], ns, "p32") /
                                               (l32 / max(c32, 1) / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     if not args.no_error:
-        line["config"]["error_vs_p64_64cube_500steps"] = velocity_error_64()
+        line["config"]["error_vs_p64_64cube"] = velocity_error_64()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
     print(json.dumps(line), flush=True)

@@ -148,3 +148,33 @@ def test_checkpoint_resume(tmp_path):
     a.step(10); b.step(10)
     assert np.max(np.abs(a.particles()[0] - b.particles()[0])) < 1e-9
     assert np.max(np.abs(a.populations() - b.populations())) < 1e-6
+
+
+@pytest.mark.parametrize("prec,tol", [("p64", 1e-12), ("p32", 1e-5)])
+def test_transitions_parity(prec, tol):
+    # moving, rotating cells cover and free nodes every few steps: the
+    # occupancy rule and the cover/uncover momentum bookkeeping are checked
+    # against the oracle step by step
+    c = synth.kolmogorov(32, 9)
+    rng = np.random.default_rng(9)
+    N = len(c["X"])
+    V = 4e-3 * rng.standard_normal((N, 3))
+    L = 0.3 * rng.standard_normal((N, 3))
+    say(f"case: transitions 32^3 dense, moving cells, {prec}")
+    g, o = make_pair(c["params"], c["X"], c["q"], precision=prec, V=V, L=L)
+    moved = 0
+    for t in range(6):
+        own0 = o.owner()
+        g.step(5); o.step(5)
+        moved += int((o.owner() != own0).sum())
+        assert np.array_equal(g.owner(), o.owner()), f"owner maps differ after {5 * (t + 1)} steps"
+        fl = o.owner() == -1
+        _, ug = g.fields(); _, uo = o.fields()
+        err_u = rel_inf(ug[fl], uo[fl])
+        Fg = g.forces()[0]; Fo = o.forces()[0]
+        err_F = rel_inf(Fg, Fo)
+        Vg = g.particles()[2]; Vo = o.particles()[2]
+        err_V = rel_inf(Vg, Vo)
+        say(f"  step {5 * (t + 1)}: u {err_u:.2e} Fh {err_F:.2e} V {err_V:.2e} transitions so far {moved}")
+        assert err_u <= tol and err_V <= tol
+    assert moved > 100
