@@ -145,6 +145,44 @@ int cgb_kernel_times(cgb_sim* s, char* names, double* ms, int64_t* count, int32_
 int cgb_save(cgb_sim* s, const char* path);
 int cgb_load(cgb_sim* s, const char* path);
 
+/* Launch shape of the fused LB kernel: bx*by threads per block (a multiple
+ * of 64, at most 256) covering a bx x by patch of an x-y plane, each thread
+ * sweeping tz consecutive z nodes (tz in {4, 8, 16, 32}).  Results do not
+ * depend on the shape except for the summation order of the per-cell FP64
+ * force sums.  cgb_get_tiles: t[3] = (bx, by, tz). */
+int cgb_set_tiles(cgb_sim* s, int32_t bx, int32_t by, int32_t tz);
+int cgb_get_tiles(cgb_sim* s, int32_t* t);
+
+/* ---- Ensemble of independent channels (uneven sizes) advanced together.
+ * Each channel is a full cgb_sim with its own stream and device memory,
+ * created from ch[c] (host array of nch parameter sets, copied).  Set the
+ * cells and the fluid of each channel through cgb_batch_channel() and the
+ * single-lattice calls; do not destroy those handles (the batch owns them). */
+typedef struct cgb_batch cgb_batch;
+int cgb_batch_create(int32_t nch, const cgb_params* ch, cgb_batch** out);
+void cgb_batch_destroy(cgb_batch* b);
+const char* cgb_batch_last_error(const cgb_batch* b);
+int cgb_batch_channel(cgb_batch* b, int32_t c, cgb_sim** sim);
+/* Times the fused LB kernel over `reps` launches for a fixed set of tile
+ * shapes on the first channel of each width class (nx < 48, < 80, >= 80) and
+ * applies the fastest to the class.  The state is unchanged.  chosen:
+ * nullable host array nch*3 receiving (bx, by, tz) per channel. */
+int cgb_batch_autotune(cgb_batch* b, int32_t reps, int32_t* chosen);
+/* Records `steps` (even, >= 2) time steps of every channel into one HIP graph
+ * (fork/join over the channel streams).  Nothing is executed.  Every channel
+ * must be initialised; cell sets and tiles must not change afterwards
+ * without capturing again. */
+int cgb_batch_capture(cgb_batch* b, int32_t steps);
+/* Replays the graph nsteps / steps times on the batch's stream
+ * (asynchronous; nsteps a multiple of the captured count).  The result is
+ * identical to cgb_step(channel, nsteps) on each channel. */
+int cgb_batch_run(cgb_batch* b, int32_t nsteps);
+/* Waits for the replays and checks every channel (CGB_EUNSTABLE as cgb_sync). */
+int cgb_batch_sync(cgb_batch* b);
+/* ubar[nch]: mean z velocity of the mixture over the non-wall nodes of each
+ * channel (the plane average of cgb_get_profile_z). */
+int cgb_batch_mean_velocity(cgb_batch* b, double* ubar);
+
 #ifdef __cplusplus
 }
 #endif

@@ -78,6 +78,19 @@ def lib():
     L.cgb_kernel_times.argtypes = [VP, VP, VP, VP, C.c_int32, C.POINTER(C.c_int32)]
     L.cgb_save.argtypes = [VP, C.c_char_p]
     L.cgb_load.argtypes = [VP, C.c_char_p]
+    L.cgb_set_tiles.argtypes = [VP, C.c_int32, C.c_int32, C.c_int32]
+    L.cgb_get_tiles.argtypes = [VP, VP]
+    L.cgb_batch_create.argtypes = [C.c_int32, VP, C.POINTER(VP)]
+    L.cgb_batch_destroy.argtypes = [VP]
+    L.cgb_batch_destroy.restype = None
+    L.cgb_batch_last_error.argtypes = [VP]
+    L.cgb_batch_last_error.restype = C.c_char_p
+    L.cgb_batch_channel.argtypes = [VP, C.c_int32, C.POINTER(VP)]
+    L.cgb_batch_autotune.argtypes = [VP, C.c_int32, VP]
+    L.cgb_batch_capture.argtypes = [VP, C.c_int32]
+    L.cgb_batch_run.argtypes = [VP, C.c_int32]
+    L.cgb_batch_sync.argtypes = [VP]
+    L.cgb_batch_mean_velocity.argtypes = [VP, VP]
     _lib = L
     return L
 
@@ -114,11 +127,15 @@ def make_params(d: dict, precision=None) -> CgbParams:
 class Sim:
     """One lattice with its cells on the GPU (one ``cgb_sim`` handle)."""
 
-    def __init__(self, params: dict, wall_mask=None, precision=None, stream=None):
+    def __init__(self, params: dict, wall_mask=None, precision=None, stream=None, _handle=None):
         self._p = make_params(params, precision)
         self.nx, self.ny, self.nz = self._p.nx, self._p.ny, self._p.nz
         self.ns = self.nx * self.ny * self.nz
         self.n = 0
+        self._owned = _handle is None
+        if _handle is not None:
+            self.h = _handle
+            return
         h = VP()
         wm = None if wall_mask is None else np.ascontiguousarray(wall_mask, dtype=np.uint8).reshape(-1)
         st = None if stream is None else VP(int(stream))
@@ -130,7 +147,8 @@ class Sim:
     # -- lifecycle
     def close(self):
         if getattr(self, "h", None):
-            lib().cgb_destroy(self.h)
+            if self._owned:
+                lib().cgb_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -228,6 +246,15 @@ class Sim:
         self._check(lib().cgb_get_profile_z(self.h, _ptr(p)))
         return p
 
+    # -- launch shape of the fused LB kernel
+    def set_tiles(self, bx, by, tz):
+        self._check(lib().cgb_set_tiles(self.h, int(bx), int(by), int(tz)))
+
+    def tiles(self):
+        t = np.zeros(3, dtype=np.int32)
+        self._check(lib().cgb_get_tiles(self.h, _ptr(t)))
+        return tuple(int(x) for x in t)
+
     # -- timing
     def profile(self, enable=True):
         self._check(lib().cgb_profile(self.h, 1 if enable else 0))
@@ -249,3 +276,68 @@ class Sim:
 
     def load(self, path):
         self._check(lib().cgb_load(self.h, str(path).encode()))
+
+
+class Batch:
+    """Independent channels of uneven size advanced together by one replayed
+    HIP graph (``cgb_batch``).  ``channels[c]`` is a :class:`Sim` view of
+    channel c (owned by the batch) for set-up and read-out."""
+
+    def __init__(self, params_list, precision=None):
+        ps = [make_params(d, precision) for d in params_list]
+        arr = (CgbParams * len(ps))(*ps)
+        h = VP()
+        rc = lib().cgb_batch_create(len(ps), C.cast(arr, VP), C.byref(h))
+        if rc != 0:
+            raise CgbError(rc, "cgb_batch_create failed")
+        self.h = h
+        self.channels = []
+        for c, d in enumerate(params_list):
+            sh = VP()
+            self._check(lib().cgb_batch_channel(self.h, c, C.byref(sh)))
+            self.channels.append(Sim(d, precision=precision, _handle=sh))
+
+    def close(self):
+        if getattr(self, "h", None):
+            for s in self.channels:
+                s.close()
+            lib().cgb_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __len__(self):
+        return len(self.channels)
+
+    def _check(self, rc):
+        if rc != 0:
+            raise CgbError(rc, lib().cgb_batch_last_error(self.h).decode())
+
+    def autotune(self, reps=10):
+        t = np.zeros((len(self), 3), dtype=np.int32)
+        self._check(lib().cgb_batch_autotune(self.h, int(reps), _ptr(t)))
+        return t
+
+    def capture(self, steps=2):
+        self._check(lib().cgb_batch_capture(self.h, int(steps)))
+
+    def run(self, nsteps):
+        self._check(lib().cgb_batch_run(self.h, int(nsteps)))
+
+    def sync(self):
+        self._check(lib().cgb_batch_sync(self.h))
+
+    def mean_velocity(self):
+        u = np.empty(len(self))
+        self._check(lib().cgb_batch_mean_velocity(self.h, _ptr(u)))
+        return u

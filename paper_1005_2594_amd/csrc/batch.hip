@@ -1,0 +1,285 @@
+// batch.hip -- ensemble of independent, uneven lattices advanced together.
+//
+// Each channel is a full lattice handle with its own stream.  The time steps
+// of all channels are captured once into a HIP graph: a fork event on the
+// master stream fans out to the channel streams, each channel enqueues its
+// step sequence, and join events fan back in, so the replayed graph runs the
+// channels concurrently with one launch.  An even number of steps is captured
+// so that the two population buffers of every channel are back in their
+// starting roles after each replay; the step index lives in device memory,
+// so replays advance it.  The autotuner times the fused LB kernel for a set
+// of tile shapes on one channel of each width class and applies the fastest.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "sim.h"
+
+using namespace cgb;
+
+struct cgb_batch {
+    std::vector<cgb_sim*> ch;
+    hipStream_t master = nullptr;
+    hipEvent_t fork = nullptr, done = nullptr;  // captured fork; end of replays
+    std::vector<hipEvent_t> join, pre;          // captured joins; eager work before a replay
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_steps = 0;
+    // Per channel, the device arguments and launch shape baked into the
+    // graph; a replay is refused once any channel's differ (buffers swapped
+    // by an odd number of eager steps, arrays reallocated by a new cell set
+    // or a new tile shape).
+    std::vector<DevArgs> cap_args;
+    std::vector<LaunchCfg> cap_cfg;
+    std::string err;
+};
+
+static bool same_args(const DevArgs& live, const DevArgs& snap) {
+    DevArgs t;
+    memcpy(&t, &live, sizeof t);
+    t.step = snap.step;  // host-side step index, not used by the kernels
+    return memcmp(&t, &snap, sizeof t) == 0;
+}
+
+#define BFAIL(b, code, ...)                         \
+    do {                                            \
+        char _m[512];                               \
+        snprintf(_m, sizeof _m, __VA_ARGS__);       \
+        (b)->err = _m;                              \
+        return code;                                \
+    } while (0)
+#define BCHK(b, call)                                                                    \
+    do {                                                                                 \
+        hipError_t _e = (call);                                                          \
+        if (_e != hipSuccess) BFAIL(b, CGB_EDEVICE, "%s: %s", #call, hipGetErrorString(_e)); \
+    } while (0)
+
+static void drop_graph(cgb_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->graph_steps = 0;
+}
+
+extern "C" {
+
+void cgb_batch_destroy(cgb_batch* b) {
+    if (!b) return;
+    if (b->master) (void)hipStreamSynchronize(b->master);
+    drop_graph(b);
+    for (cgb_sim* s : b->ch) cgb_destroy(s);
+    for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+    for (hipEvent_t e : b->pre) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->done) (void)hipEventDestroy(b->done);
+    if (b->master) (void)hipStreamDestroy(b->master);
+    delete b;
+}
+
+const char* cgb_batch_last_error(const cgb_batch* b) { return b ? b->err.c_str() : "null handle"; }
+
+int cgb_batch_create(int32_t nch, const cgb_params* ch, cgb_batch** out) {
+    if (!out || nch < 1 || !ch) return CGB_EINVAL;
+    *out = nullptr;
+    cgb_batch* b = new cgb_batch();
+    if (hipStreamCreateWithFlags(&b->master, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+        cgb_batch_destroy(b);
+        return CGB_EDEVICE;
+    }
+    for (int c = 0; c < nch; c++) {
+        cgb_sim* s = nullptr;
+        const int rc = cgb_create(&ch[c], nullptr, nullptr, &s);
+        if (rc) {
+            cgb_batch_destroy(b);
+            return rc;
+        }
+        b->ch.push_back(s);
+        hipEvent_t e1, e2;
+        if (hipEventCreateWithFlags(&e1, hipEventDisableTiming) != hipSuccess) {
+            cgb_batch_destroy(b);
+            return CGB_EDEVICE;
+        }
+        b->join.push_back(e1);
+        if (hipEventCreateWithFlags(&e2, hipEventDisableTiming) != hipSuccess) {
+            cgb_batch_destroy(b);
+            return CGB_EDEVICE;
+        }
+        b->pre.push_back(e2);
+    }
+    *out = b;
+    return CGB_OK;
+}
+
+int cgb_batch_channel(cgb_batch* b, int32_t c, cgb_sim** out) {
+    if (!b || !out || c < 0 || c >= (int)b->ch.size()) return CGB_EINVAL;
+    *out = b->ch[(size_t)c];
+    return CGB_OK;
+}
+
+// Times the fused LB kernel (which only reads the current state and writes
+// buffers every step rewrites) for candidate tile shapes on the first channel
+// of each width class and applies the fastest to the whole class.
+// chosen: nullable, nch*3 ints (bx, by, tz).
+int cgb_batch_autotune(cgb_batch* b, int32_t reps, int32_t* chosen) {
+    if (!b || reps < 1) return CGB_EINVAL;
+    drop_graph(b);
+    static const LaunchCfg cand[] = {{64, 4, 8}, {64, 4, 16}, {32, 8, 8}, {32, 8, 16}, {16, 16, 16}, {64, 2, 16}, {32, 4, 16}};
+    std::map<int, std::vector<int>> classes;  // width class -> channels
+    for (size_t c = 0; c < b->ch.size(); c++) {
+        const int w = b->ch[c]->a.nx;
+        classes[w < 48 ? 0 : (w < 80 ? 1 : 2)].push_back((int)c);
+    }
+    hipEvent_t e0, e1;
+    BCHK(b, hipEventCreate(&e0));
+    BCHK(b, hipEventCreate(&e1));
+    int rc = CGB_OK;
+    for (auto& kv : classes) {
+        cgb_sim* s = b->ch[(size_t)kv.second[0]];
+        LaunchCfg best = s->lbcfg;
+        float best_ms = 1e30f;
+        // the LB kernel may add straight into the per-cell force sums when
+        // its block table fills up: keep the last step's sums
+        const size_t ftb = 6 * sizeof(double) * (size_t)std::max(s->a.n, 1);
+        void* keep = nullptr;
+        if (hipMalloc(&keep, ftb) != hipSuccess) { rc = CGB_ENOMEM; break; }
+        if (hipMemcpyAsync(keep, s->a.FTh, ftb, hipMemcpyDeviceToDevice, s->st) != hipSuccess) rc = CGB_EDEVICE;
+        for (const LaunchCfg& cf : cand) {
+            if (rc || (rc = sim_set_tiles(s, cf)) != CGB_OK) break;
+            sim_bind(s);
+            for (int k = 0; k < 2; k++) (void)launch_lb(s->a, s->lbcfg, s->st);
+            (void)hipEventRecord(e0, s->st);
+            for (int k = 0; k < reps; k++) (void)launch_lb(s->a, s->lbcfg, s->st);
+            (void)hipEventRecord(e1, s->st);
+            if (hipEventSynchronize(e1) != hipSuccess) { rc = CGB_EDEVICE; break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) { best_ms = ms; best = cf; }
+        }
+        if (hipMemcpyAsync(s->a.FTh, keep, ftb, hipMemcpyDeviceToDevice, s->st) != hipSuccess ||
+            hipStreamSynchronize(s->st) != hipSuccess)
+            rc = rc ? rc : CGB_EDEVICE;
+        (void)hipFree(keep);
+        if (rc) break;
+        for (int c : kv.second) {
+            if ((rc = sim_set_tiles(b->ch[(size_t)c], best)) != CGB_OK) break;
+            if (chosen) { chosen[3 * c] = best.bx; chosen[3 * c + 1] = best.by; chosen[3 * c + 2] = best.tz; }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) BFAIL(b, rc, "autotune failed: %s", cgb_last_error(b->ch[0]));
+    return CGB_OK;
+}
+
+// Captures `steps` (even) time steps of every channel into one graph.
+int cgb_batch_capture(cgb_batch* b, int32_t steps) {
+    if (!b || steps < 2 || (steps & 1)) return CGB_EINVAL;
+    drop_graph(b);
+    for (cgb_sim* s : b->ch) {
+        if (!s->fluid_ready) BFAIL(b, CGB_ESTATE, "channel not initialised");
+        BCHK(b, hipStreamSynchronize(s->st));
+        if (s->prof) cgb_profile(s, 0);
+    }
+    std::vector<int> cur(b->ch.size());
+    std::vector<long long> stp(b->ch.size());
+    for (size_t c = 0; c < b->ch.size(); c++) { cur[c] = b->ch[c]->cur; stp[c] = b->ch[c]->step; }
+    BCHK(b, hipStreamBeginCapture(b->master, hipStreamCaptureModeRelaxed));
+    hipError_t e = hipEventRecord(b->fork, b->master);
+    int rc = CGB_OK;
+    for (size_t c = 0; c < b->ch.size() && e == hipSuccess && rc == CGB_OK; c++) {
+        cgb_sim* s = b->ch[c];
+        e = hipStreamWaitEvent(s->st, b->fork, 0);
+        if (e != hipSuccess) break;
+        rc = cgb_step(s, steps);
+        if (rc) break;
+        e = hipEventRecord(b->join[c], s->st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->master, b->join[c], 0);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b->master, &g);
+    for (size_t c = 0; c < b->ch.size(); c++) {
+        b->ch[c]->cur = cur[c];
+        b->ch[c]->step = stp[c];
+        sim_bind(b->ch[c]);
+    }
+    if (rc) { if (g) (void)hipGraphDestroy(g); BFAIL(b, rc, "capture: %s", cgb_last_error(b->ch[0])); }
+    if (e != hipSuccess) { if (g) (void)hipGraphDestroy(g); BFAIL(b, CGB_EDEVICE, "capture: %s", hipGetErrorString(e)); }
+    if (e2 != hipSuccess) BFAIL(b, CGB_EDEVICE, "end capture: %s", hipGetErrorString(e2));
+    b->graph = g;
+    BCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->graph_steps = steps;
+    b->cap_args.resize(b->ch.size());
+    b->cap_cfg.resize(b->ch.size());
+    for (size_t c = 0; c < b->ch.size(); c++) {
+        memcpy(&b->cap_args[c], &b->ch[c]->a, sizeof(DevArgs));
+        b->cap_cfg[c] = b->ch[c]->lbcfg;
+    }
+    return CGB_OK;
+}
+
+// Replays the captured graph nsteps / graph_steps times (asynchronous).
+int cgb_batch_run(cgb_batch* b, int32_t nsteps) {
+    if (!b || nsteps < 0) return CGB_EINVAL;
+    if (!b->exec) BFAIL(b, CGB_ESTATE, "no captured graph");
+    if (nsteps % b->graph_steps) BFAIL(b, CGB_EINVAL, "steps must be a multiple of %d", b->graph_steps);
+    for (size_t c = 0; c < b->ch.size(); c++) {
+        cgb_sim* s = b->ch[c];
+        const LaunchCfg& k = b->cap_cfg[c];
+        if (!same_args(s->a, b->cap_args[c]) || s->lbcfg.bx != k.bx || s->lbcfg.by != k.by || s->lbcfg.tz != k.tz)
+            BFAIL(b, CGB_ESTATE, "channel %zu changed since the capture (odd eager steps, new cells or tiles); capture again", c);
+        // the channel streams may hold eager work issued since the last replay
+        BCHK(b, hipEventRecord(b->pre[c], s->st));
+        BCHK(b, hipStreamWaitEvent(b->master, b->pre[c], 0));
+    }
+    for (int k = 0; k < nsteps / b->graph_steps; k++) BCHK(b, hipGraphLaunch(b->exec, b->master));
+    // later eager work on a channel stream waits for the replays
+    BCHK(b, hipEventRecord(b->done, b->master));
+    for (cgb_sim* s : b->ch) {
+        BCHK(b, hipStreamWaitEvent(s->st, b->done, 0));
+        s->step += nsteps;
+    }
+    return CGB_OK;
+}
+
+int cgb_batch_sync(cgb_batch* b) {
+    if (!b) return CGB_EINVAL;
+    BCHK(b, hipStreamSynchronize(b->master));
+    for (size_t c = 0; c < b->ch.size(); c++) {
+        const int rc = cgb_sync(b->ch[c]);
+        if (rc) BFAIL(b, rc, "channel %zu: %s", c, cgb_last_error(b->ch[c]));
+    }
+    return CGB_OK;
+}
+
+// Mean z velocity of the mixture (fluid u_z or rigid velocity of the owning
+// cell) over the non-wall nodes of each channel: ubar[nch].
+int cgb_batch_mean_velocity(cgb_batch* b, double* ubar) {
+    if (!b || !ubar) return CGB_EINVAL;
+    BCHK(b, hipStreamSynchronize(b->master));
+    for (size_t c = 0; c < b->ch.size(); c++) {
+        cgb_sim* s = b->ch[c];
+        std::vector<double> prof((size_t)s->a.ny);
+        const int rc = cgb_get_profile_z(s, prof.data());
+        if (rc) BFAIL(b, rc, "channel %zu: %s", c, cgb_last_error(s));
+        double sum = 0.0;
+        int cnt = 0;
+        for (int y = 0; y < s->a.ny; y++) {
+            if (s->a.wall_y && (y == 0 || y == s->a.ny - 1)) continue;
+            sum += prof[(size_t)y];
+            cnt++;
+        }
+        ubar[c] = cnt ? sum / cnt : 0.0;
+    }
+    return CGB_OK;
+}
+
+}  // extern "C"

@@ -99,6 +99,7 @@ struct DevArgs {
     // bookkeeping
     int* status;
     int* bad_step;
+    int* dstep;        // device-side index of the current step
     long long step;
     double* body_part; // per-block partial sums of the body force on cells
     // momentum-exchange partials: LB tile shape, tiles per axis, slots per

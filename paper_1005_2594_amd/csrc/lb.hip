@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
         ((T*)a.rhoB)[i] = Cd::enc(rsum, rho_enc_scale<P>(a));
         if (!(usq <= (R)0.16)) {
             atomicOr(a.status, ST_UNSTABLE);
-            atomicMin(a.bad_step, (int)a.step);
+            atomicMin(a.bad_step, *a.dstep);
         }
     }
     if (spid >= 0) table_add(tb, a, spid, acc);
@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
 
     // table -> per-cell slots (plain stores)
     const int tile[3] = {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z};
-    const int stamp = (int)a.step + 1;
+    const int stamp = *a.dstep + 1;
     for (int e = tid; e < TAB_CAP; e += nthr) {
         const int p = tb.key[e];
         if (p < 0) continue;
@@ -578,7 +578,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
         bstore<T>(Cd::enc(drho, rho_enc_scale<P>(a)), rRB, ES * i);
         if (!(usq <= (R)0.16)) {
             atomicOr(a.status, ST_UNSTABLE);
-            atomicMin(a.bad_step, (int)a.step);
+            atomicMin(a.bad_step, *a.dstep);
         }
     }
     if (spa >= 0) { const M ev[6] = {aa0, aa1, aa2, aa3, aa4, aa5}; table_add_m<M>(tb, a, spa, ev); }
@@ -587,7 +587,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
     __syncthreads();
 
     const int tile[3] = {(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z};
-    const int stamp = (int)a.step + 1;
+    const int stamp = *a.dstep + 1;
     for (int e = tid; e < TAB_CAP; e += nthr) {
         const int p = tb.key[e];
         if (p < 0) continue;
@@ -627,7 +627,7 @@ __global__ void mem_gather_kernel(DevArgs a) {
         }
         cnt[c] = m < a.slots[c] ? m : a.slots[c];
     }
-    const int stamp = (int)a.step + 1;
+    const int stamp = *a.dstep + 1;
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int oz = 0; oz < cnt[2]; oz++)
         for (int oy = 0; oy < cnt[1]; oy++)

@@ -192,8 +192,16 @@ __global__ void __launch_bounds__(64) raster_kernel(DevArgs a) {
 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
 
-hipError_t launch_raster(const DevArgs& a, hipStream_t st, bool) {
-    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, st, a.ntrans);
+// start of a time step: clear the transition list and advance the device-side
+// step index (kernels read the step from device memory, so a captured step
+// sequence stays correct when it is replayed)
+__global__ void step_begin_kernel(int* ntrans, int* dstep, int advance) {
+    *ntrans = 0;
+    if (advance) *dstep += 1;
+}
+
+hipError_t launch_raster(const DevArgs& a, hipStream_t st, bool fresh) {
+    hipLaunchKernelGGL(step_begin_kernel, dim3(1), dim3(1), 0, st, a.ntrans, a.dstep, fresh ? 0 : 1);
     if (a.n == 0) return hipGetLastError();
     hipLaunchKernelGGL(raster_kernel<false>, dim3(a.n), dim3(64), 0, st, a);
     hipLaunchKernelGGL(raster_kernel<true>, dim3(a.n), dim3(64), 0, st, a);
@@ -663,7 +671,7 @@ __device__ void integrate_one(const DevArgs& a, int p, double* bf) {
     if (bad) {
         // unstable: flag it and leave the cell where it is, inside the box
         atomicOr(a.status, ST_UNSTABLE);
-        atomicMin(a.bad_step, (int)a.step);
+        atomicMin(a.bad_step, *a.dstep);
         return;
     }
     for (int c = 0; c < 3; c++) {
@@ -694,7 +702,7 @@ __device__ void integrate_one(const DevArgs& a, int p, double* bf) {
     for (int c = 0; c < 4; c++) a.q[4 * p + c] = qn[c];
     if (!(qn[0] == qn[0])) {
         atomicOr(a.status, ST_UNSTABLE);
-        atomicMin(a.bad_step, (int)a.step);
+        atomicMin(a.bad_step, *a.dstep);
     }
 }
 

@@ -15,46 +15,11 @@
 #include <vector>
 
 #include "cgb_dev.h"
+#include "sim.h"
 
 using namespace cgb;
 
-struct LaunchRec {
-    int kind;
-    hipEvent_t e0, e1;
-};
-
 static const char* kKindNames[] = {"prep", "raster", "transitions", "lb", "mem_gather", "cells", "potentials", "integrate"};
-enum { K_PREP, K_RASTER, K_TRANS, K_LB, K_GATHER, K_CELLS, K_POT, K_INT, K_NKIND };
-
-struct cgb_sim {
-    cgb_params P;
-    DevArgs a;
-    hipStream_t st = nullptr;
-    bool own_stream = false;
-    int cur = 0;
-    void* pop[2] = {nullptr, nullptr};
-    void* rho[2] = {nullptr, nullptr};
-    size_t esize = 8;
-    int ncap = 0;
-    long long step = 0;
-    bool fluid_ready = false;
-    std::string err;
-    int64_t dev_bytes = 0;
-    std::vector<void*> allocs;
-    double* tmp = nullptr;  // FP64 staging for uploads/downloads
-    size_t tmp_bytes = 0;
-    double* obs_partial = nullptr;
-    int obs_nblk = 512;
-    int* pair_buf = nullptr;
-    int* pair_cnt = nullptr;
-    int pair_cap = 0;
-    LaunchCfg lbcfg{64, 4, 16};
-    bool prof = false;
-    std::vector<LaunchRec> recs;
-    std::vector<hipEvent_t> ev_pool;
-    double ktime[K_NKIND] = {0};
-    long long kcount[K_NKIND] = {0};
-};
 
 #define FAIL(s, code, ...)                                  \
     do {                                                    \
@@ -334,6 +299,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
         CK(dalloc(s, &a.ntrans, 16));
         CK(dalloc(s, &a.status, 16));
         CK(dalloc(s, &a.bad_step, 16));
+        CK(dalloc(s, &a.dstep, 16));
         CK(dalloc(s, &s->obs_partial, (size_t)s->obs_nblk * 8 * 8));
         // owner map: walls from the mask and the wall planes
         std::vector<int32_t> own((size_t)a.ns, OWN_FLUID);
@@ -396,6 +362,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
         CK(launch_fill_i32(a.cand, a.ns, NO_CAND, s->st));
         CK(launch_fill_i32(a.status, 4, 0, s->st));
         CK(launch_fill_i32(a.bad_step, 4, 0x7fffffff, s->st));
+        CK(launch_fill_i32(a.dstep, 1, -1, s->st));
         set_tiles(s, default_tiles(a));
         if (alloc_particles(s, 0) != CGB_OK) { rc = CGB_EDEVICE; goto fail; }
         a.n = 0;
@@ -730,6 +697,22 @@ int cgb_kernel_times(cgb_sim* s, char* names, double* ms, int64_t* count, int32_
     return CGB_OK;
 }
 
+// ---------------------------------------------------------------- tiles
+int cgb_set_tiles(cgb_sim* s, int32_t bx, int32_t by, int32_t tz) {
+    if (!s) return CGB_EINVAL;
+    if (bx < 1 || by < 1 || bx * by > 256 || (bx * by) % 64 != 0 || !(tz == 4 || tz == 8 || tz == 16 || tz == 32))
+        FAIL(s, CGB_EINVAL, "tile %dx%dx%d: need bx*by a multiple of 64, at most 256, tz in {4,8,16,32}", bx, by, tz);
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    set_tiles(s, LaunchCfg{bx, by, tz});
+    return alloc_slots(s);
+}
+
+int cgb_get_tiles(cgb_sim* s, int32_t* t) {
+    if (!s || !t) return CGB_EINVAL;
+    t[0] = s->lbcfg.bx; t[1] = s->lbcfg.by; t[2] = s->lbcfg.tz;
+    return CGB_OK;
+}
+
 // ---------------------------------------------------------------- checkpoint
 static const char kMagic[8] = {'C', 'G', 'B', 'C', 'K', 'P', 'T', '1'};
 
@@ -805,6 +788,7 @@ int cgb_load(cgb_sim* s, const char* path) {
     s->step = step;
     s->fluid_ready = true;
     bind_buffers(s);
+    HIPCHK(s, launch_fill_i32(a.dstep, 1, (int)step - 1, s->st));
     HIPCHK(s, launch_fill_i32(a.cand, a.ns, NO_CAND, s->st));
     HIPCHK(s, launch_fill_i32(a.stamp, (long long)std::max(s->ncap, 1) * a.nslot, 0, s->st));
     HIPCHK(s, launch_cells(a, s->st));
@@ -813,3 +797,8 @@ int cgb_load(cgb_sim* s, const char* path) {
 }
 
 }  // extern "C"
+
+namespace cgb {
+int sim_set_tiles(cgb_sim* s, LaunchCfg cfg) { return cgb_set_tiles(s, cfg.bx, cfg.by, cfg.tz); }
+void sim_bind(cgb_sim* s) { bind_buffers(s); }
+}  // namespace cgb

@@ -1,0 +1,51 @@
+// sim.h -- internal definition of the lattice handle shared by the runtime
+// translation units (runtime.hip, batch.hip).
+#pragma once
+#include <string>
+#include <vector>
+
+#include "cgb_dev.h"
+
+struct LaunchRec {
+    int kind;
+    hipEvent_t e0, e1;
+};
+
+enum { K_PREP, K_RASTER, K_TRANS, K_LB, K_GATHER, K_CELLS, K_POT, K_INT, K_NKIND };
+
+struct cgb_sim {
+    cgb_params P;
+    cgb::DevArgs a;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    int cur = 0;
+    void* pop[2] = {nullptr, nullptr};
+    void* rho[2] = {nullptr, nullptr};
+    size_t esize = 8;
+    int ncap = 0;
+    long long step = 0;
+    bool fluid_ready = false;
+    std::string err;
+    int64_t dev_bytes = 0;
+    std::vector<void*> allocs;
+    double* tmp = nullptr;  // FP64 staging for uploads/downloads
+    size_t tmp_bytes = 0;
+    double* obs_partial = nullptr;
+    int obs_nblk = 512;
+    int* pair_buf = nullptr;
+    int* pair_cnt = nullptr;
+    int pair_cap = 0;
+    cgb::LaunchCfg lbcfg{64, 4, 16};
+    bool prof = false;
+    std::vector<LaunchRec> recs;
+    std::vector<hipEvent_t> ev_pool;
+    double ktime[K_NKIND] = {0};
+    long long kcount[K_NKIND] = {0};
+};
+
+
+namespace cgb {
+// internal entry points of runtime.hip used by the batch
+int sim_set_tiles(cgb_sim* s, LaunchCfg cfg);
+void sim_bind(cgb_sim* s);
+}  // namespace cgb

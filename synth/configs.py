@@ -134,14 +134,15 @@ def config3_companion(seed=3, n=64):
     return kolmogorov(n, seed, precision="pmx16")
 
 
-def config4(seed=4, n_channels=64):
+def config4(seed=4, n_channels=64, w_range=(32, 96), lz_range=(64, 192)):
     """Uneven wall-bounded channels (W, W, Lz): W ~ U{32..96}, Lz ~ U{64..192},
-    Ht ~ U[0.1, 0.5], g ~ logU[1e-7, 1e-5]."""
+    Ht ~ U[0.1, 0.5], g ~ logU[1e-7, 1e-5] (ranges inclusive; smaller ranges
+    give the same recipe at test sizes)."""
     rng = np.random.default_rng(seed)
     chans = []
     for c in range(n_channels):
-        W = int(rng.integers(32, 97))
-        Lz = int(rng.integers(64, 193))
+        W = int(rng.integers(w_range[0], w_range[1] + 1))
+        Lz = int(rng.integers(lz_range[0], lz_range[1] + 1))
         Ht = float(rng.uniform(0.1, 0.5))
         g = float(10.0 ** rng.uniform(-7.0, -5.0))
         p = params(W, W, Lz, wall_y=1, force_mode=1, g=(0.0, 0.0, g), rho_p=RHO_P_DENSE)

@@ -1,0 +1,160 @@
+"""Ensemble of uneven channels advanced by one replayed HIP graph: every
+replay equals eager stepping of the same channels, the autotuned launch
+shapes keep the results, and one channel agrees with the oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+from parity_util import rel_inf, say
+
+pytestmark = pytest.mark.gpu
+
+# FP64 storage: the cover/uncover sums use device atomics, so two runs of the
+# same steps agree to the rounding of a few FP64 additions, not bit for bit.
+TOL_REPLAY = 1e-12
+
+
+def small_channels(n=5, seed=41):
+    return synth.config4(seed=seed, n_channels=n, w_range=(20, 40), lz_range=(24, 48))
+
+
+def setup(sim, ch):
+    sim.set_particles(ch["X"], ch["q"])
+    sim.init_fluid()
+
+
+def state(sim):
+    X, q, V, L = sim.particles()
+    return {"pop": sim.populations(), "X": X, "q": q, "V": V, "L": L, "owner": sim.owner(),
+            "step": sim.observables()["step"]}
+
+
+def compare(a, b, tol, tag):
+    assert a["step"] == b["step"], (tag, a["step"], b["step"])
+    np.testing.assert_array_equal(a["owner"], b["owner"], err_msg=tag)
+    for k in ("pop", "X", "q", "V", "L"):
+        e = rel_inf(a[k], b[k])
+        assert e <= tol, (tag, k, e)
+
+
+def make(chans, precision="p64"):
+    from paper_1005_2594_amd import Batch, Sim
+    b = Batch([c["params"] for c in chans], precision=precision)
+    for s, c in zip(b.channels, chans):
+        setup(s, c)
+    ref = []
+    for c in chans:
+        s = Sim(c["params"], precision=precision)
+        setup(s, c)
+        ref.append(s)
+    return b, ref
+
+
+def test_batch_replays_match_eager():
+    chans = small_channels()
+    say("batch: channels", [(c["width"], c["length"], len(c["X"])) for c in chans])
+    b, ref = make(chans)
+    try:
+        b.capture(2)
+        for rep in range(3):
+            b.run(2)
+            for s in ref:
+                s.step(2)
+            b.sync()
+            for c, (g, r) in enumerate(zip(b.channels, ref)):
+                compare(state(g), state(r), TOL_REPLAY, f"replay {rep} channel {c}")
+            say("batch: replay", rep, "ok")
+        # an even number of eager steps between replays keeps the graph valid
+        for g in b.channels:
+            g.step(2)
+        for s in ref:
+            s.step(2)
+        b.run(4)
+        for s in ref:
+            s.step(4)
+        b.sync()
+        for c, (g, r) in enumerate(zip(b.channels, ref)):
+            compare(state(g), state(r), TOL_REPLAY, f"after eager channel {c}")
+    finally:
+        b.close()
+        for s in ref:
+            s.close()
+
+
+def test_batch_refuses_stale_graph():
+    from paper_1005_2594_amd import CgbError
+    chans = small_channels(n=2, seed=42)
+    b, ref = make(chans)
+    try:
+        with pytest.raises(CgbError, match="EINVAL"):
+            b.capture(3)
+        with pytest.raises(CgbError, match="ESTATE"):
+            b.run(2)
+        b.capture(2)
+        with pytest.raises(CgbError, match="EINVAL"):
+            b.run(3)
+        b.channels[0].step(1)  # buffer roles swapped
+        with pytest.raises(CgbError, match="ESTATE"):
+            b.run(2)
+        b.channels[0].step(1)
+        b.run(2)
+        b.sync()
+    finally:
+        b.close()
+        for s in ref:
+            s.close()
+
+
+def test_batch_autotune_keeps_results():
+    chans = small_channels(n=4, seed=43)
+    b, ref = make(chans)
+    try:
+        tiles = b.autotune(reps=3)
+        say("batch: tiles", tiles.tolist())
+        for t, g in zip(tiles, b.channels):
+            bx, by, tz = (int(x) for x in t)
+            assert bx * by % 64 == 0 and bx * by <= 256 and tz in (4, 8, 16, 32)
+            assert g.tiles() == (bx, by, tz)
+        b.capture(2)
+        b.run(6)
+        for s in ref:
+            s.step(6)
+        b.sync()
+        for c, (g, r) in enumerate(zip(b.channels, ref)):
+            # a different launch shape changes only the order of the per-cell sums
+            compare(state(g), state(r), 1e-11, f"autotuned channel {c}")
+    finally:
+        b.close()
+        for s in ref:
+            s.close()
+
+
+def test_batch_mean_velocity_and_oracle():
+    chans = small_channels(n=3, seed=44)
+    b, ref = make(chans)
+    try:
+        b.capture(2)
+        b.run(4)
+        b.sync()
+        ub = b.mean_velocity()
+        for c, g in enumerate(b.channels):
+            pr = g.profile_z()
+            assert ub[c] == pytest.approx(pr[1:-1].mean(), rel=1e-12, abs=1e-300)
+        c = 0
+        o = O.Oracle(chans[c]["params"])
+        o.set_particles(chans[c]["X"], chans[c]["q"])
+        o.init_fluid()
+        o.step(4)
+        g = b.channels[c]
+        fl = o.owner() == -1
+        np.testing.assert_array_equal(g.owner(), o.owner())
+        e = rel_inf(g.populations()[:, fl], o.deviations()[:, fl])
+        say("batch: channel 0 vs oracle, pop", e)
+        assert e <= 1e-11
+        for name, x, y in zip(("X", "q", "V", "L"), g.particles(), o.particles()):
+            assert rel_inf(x, y) <= 1e-11, name
+    finally:
+        b.close()
+        for s in ref:
+            s.close()
