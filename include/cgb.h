@@ -152,6 +152,11 @@ int cgb_load(cgb_sim* s, const char* path);
  * force sums.  cgb_get_tiles: t[3] = (bx, by, tz). */
 int cgb_set_tiles(cgb_sim* s, int32_t bx, int32_t by, int32_t tz);
 int cgb_get_tiles(cgb_sim* s, int32_t* t);
+/* Average duration in milliseconds (HIP events on the handle's stream) of
+ * the fused LB kernel over `reps` launches on the current state, after two
+ * untimed launches.  The state, including the force read-out of the last
+ * step, is unchanged.  Synchronous. */
+int cgb_time_lb(cgb_sim* s, int32_t reps, double* ms_avg);
 
 /* ---- Ensemble of independent channels (uneven sizes) advanced together.
  * Each channel is a full cgb_sim with its own stream and device memory,

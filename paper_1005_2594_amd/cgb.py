@@ -80,6 +80,7 @@ def lib():
     L.cgb_load.argtypes = [VP, C.c_char_p]
     L.cgb_set_tiles.argtypes = [VP, C.c_int32, C.c_int32, C.c_int32]
     L.cgb_get_tiles.argtypes = [VP, VP]
+    L.cgb_time_lb.argtypes = [VP, C.c_int32, C.POINTER(C.c_double)]
     L.cgb_batch_create.argtypes = [C.c_int32, VP, C.POINTER(VP)]
     L.cgb_batch_destroy.argtypes = [VP]
     L.cgb_batch_destroy.restype = None
@@ -254,6 +255,12 @@ class Sim:
         t = np.zeros(3, dtype=np.int32)
         self._check(lib().cgb_get_tiles(self.h, _ptr(t)))
         return tuple(int(x) for x in t)
+
+    def time_lb(self, reps=10):
+        """Average milliseconds of the fused LB kernel on the current state."""
+        ms = C.c_double()
+        self._check(lib().cgb_time_lb(self.h, int(reps), C.byref(ms)))
+        return ms.value
 
     # -- timing
     def profile(self, enable=True):

@@ -137,36 +137,17 @@ int cgb_batch_autotune(cgb_batch* b, int32_t reps, int32_t* chosen) {
         const int w = b->ch[c]->a.nx;
         classes[w < 48 ? 0 : (w < 80 ? 1 : 2)].push_back((int)c);
     }
-    hipEvent_t e0, e1;
-    BCHK(b, hipEventCreate(&e0));
-    BCHK(b, hipEventCreate(&e1));
     int rc = CGB_OK;
     for (auto& kv : classes) {
         cgb_sim* s = b->ch[(size_t)kv.second[0]];
         LaunchCfg best = s->lbcfg;
-        float best_ms = 1e30f;
-        // the LB kernel may add straight into the per-cell force sums when
-        // its block table fills up: keep the last step's sums
-        const size_t ftb = 6 * sizeof(double) * (size_t)std::max(s->a.n, 1);
-        void* keep = nullptr;
-        if (hipMalloc(&keep, ftb) != hipSuccess) { rc = CGB_ENOMEM; break; }
-        if (hipMemcpyAsync(keep, s->a.FTh, ftb, hipMemcpyDeviceToDevice, s->st) != hipSuccess) rc = CGB_EDEVICE;
+        double best_ms = 1e30;
         for (const LaunchCfg& cf : cand) {
-            if (rc || (rc = sim_set_tiles(s, cf)) != CGB_OK) break;
-            sim_bind(s);
-            for (int k = 0; k < 2; k++) (void)launch_lb(s->a, s->lbcfg, s->st);
-            (void)hipEventRecord(e0, s->st);
-            for (int k = 0; k < reps; k++) (void)launch_lb(s->a, s->lbcfg, s->st);
-            (void)hipEventRecord(e1, s->st);
-            if (hipEventSynchronize(e1) != hipSuccess) { rc = CGB_EDEVICE; break; }
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
+            if ((rc = sim_set_tiles(s, cf)) != CGB_OK) break;
+            double ms = 0.0;
+            if ((rc = cgb_time_lb(s, reps, &ms)) != CGB_OK) break;
             if (ms < best_ms) { best_ms = ms; best = cf; }
         }
-        if (hipMemcpyAsync(s->a.FTh, keep, ftb, hipMemcpyDeviceToDevice, s->st) != hipSuccess ||
-            hipStreamSynchronize(s->st) != hipSuccess)
-            rc = rc ? rc : CGB_EDEVICE;
-        (void)hipFree(keep);
         if (rc) break;
         for (int c : kv.second) {
             if ((rc = sim_set_tiles(b->ch[(size_t)c], best)) != CGB_OK) break;
@@ -174,8 +155,6 @@ int cgb_batch_autotune(cgb_batch* b, int32_t reps, int32_t* chosen) {
         }
         if (rc) break;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     if (rc) BFAIL(b, rc, "autotune failed: %s", cgb_last_error(b->ch[0]));
     return CGB_OK;
 }

@@ -73,7 +73,7 @@ struct DevArgs {
     uint8_t* fixed;
     double* Xprev;  // n*3, position of the last rasterisation
     double* Hprev;  // n*3, axis-aligned half extents at the last rasterisation
-    double* kin;    // n*12: X, V, Omega, axis (gathered by the LB kernel)
+    double* kin;    // n*12: X, V, Omega, axis at the start of the step
     double* FTh;    // n*6 hydrodynamic force, torque (accumulated)
     double* FTp;    // n*6 potential force, torque
     double M, Ipar, Iperp;
@@ -102,19 +102,31 @@ struct DevArgs {
     int* dstep;        // device-side index of the current step
     long long step;
     double* body_part; // per-block partial sums of the body force on cells
-    // momentum-exchange partials: LB tile shape, tiles per axis, slots per
-    // axis (tiles a cell's footprint can span), per-cell slot arrays
-    int tile[3];
-    int ntile[3];
-    int slots[3];
-    int nslot;
-    double* FTpart;    // n * nslot * 6
-    int* stamp;        // n * nslot (step + 1 when written)
+    // moving bounce-back and momentum exchange (element type: FP64 for P64,
+    // FP32 otherwise)
+    void* usol;        // [pstride][4]: velocity (x, y, z, -) of every non-fluid
+                       // node: the rigid-body velocity of its cell at the node,
+                       // or the wall velocity
+    void* mlink;       // [18][pstride]: plane r-1 at a non-fluid node s holds
+                       // the momentum, along c_r, that the link to the fluid
+                       // node s + c_r transferred this step
+    void* crec;        // [n] CellRec, in cell-list order (per-cell kernels)
+    int tile[3];       // LB launch shape the kernels were configured for
     int* scan_tmp;     // block totals of the bin scan
     int nbody_blk;     // blocks of the integrate kernel (body_part has 3 per block)
 };
 
 __host__ __device__ inline int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// what the per-cell wave kernels need of a cell, gathered once per step in
+// cell-list order (one 128-byte record per wave): position, axis, velocity,
+// angular velocity, the cell's index and the node box to walk (the union of
+// the boxes at the previous and the current rasterisation)
+struct CellRec {
+    double X[3], o[3], V[3], W[3];
+    int p, ok, lo[3], ext[3];
+};
+static_assert(sizeof(CellRec) == 128, "cell record layout");
 
 // ------------------------------------------------------------ buffer access
 // Raw buffer loads/stores take one scalar resource and a 32-bit byte offset
@@ -281,11 +293,13 @@ struct LaunchCfg {
     int tz;      // nodes swept along z by each thread
 };
 hipError_t launch_lb(const DevArgs& a, LaunchCfg cfg, hipStream_t st);
-hipError_t launch_mem_gather(const DevArgs& a, hipStream_t st);
+hipError_t launch_mem_reduce(const DevArgs& a, hipStream_t st);
+hipError_t launch_usol_walls(const DevArgs& a, hipStream_t st);
 hipError_t launch_prep(const DevArgs& a, hipStream_t st);
 hipError_t launch_kin(const DevArgs& a, hipStream_t st);
 hipError_t launch_clear_cells(const DevArgs& a, hipStream_t st);
 hipError_t launch_raster(const DevArgs& a, hipStream_t st, bool fresh);
+hipError_t launch_cellrec(const DevArgs& a, hipStream_t st);
 hipError_t launch_transitions(const DevArgs& a, hipStream_t st, bool bookkeeping);
 hipError_t launch_cells(const DevArgs& a, hipStream_t st);
 hipError_t launch_potentials(const DevArgs& a, hipStream_t st);

@@ -123,71 +123,288 @@ __device__ inline bool union_box(const DevArgs& a, int p, int* lo, int* ext) {
     return true;
 }
 
-__device__ inline bool covers(const DevArgs& a, int p, int x, int y, int z) {
-    double d[3], o[3];
-    const double* k = a.kin + 12 * (long long)p;
-    node_disp(a, x, y, z, k, d);
-    o[0] = k[9]; o[1] = k[10]; o[2] = k[11];
-    return inside_test(a, d, o);
+__device__ inline bool covers(const DevArgs& a, const CellRec& c, int x, int y, int z) {
+    double d[3];
+    node_disp(a, x, y, z, c.X, d);
+    return inside_test(a, d, c.o);
 }
 
-// one wave per cell: lane (ix, iy) of an 8 x 8 footprint walks z
+// cell records in cell-list order (the order of the previous cell list; any
+// permutation of the cells is correct)
+__global__ void cellrec_kernel(DevArgs a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const int p = a.bin_idx[k];
+    const double* kp = a.kin + 12 * (long long)p;
+    CellRec c;
+    for (int i = 0; i < 3; i++) { c.X[i] = kp[i]; c.V[i] = kp[3 + i]; c.W[i] = kp[6 + i]; c.o[i] = kp[9 + i]; }
+    c.p = p;
+    c.ok = union_box(a, p, c.lo, c.ext) ? 1 : 0;
+    if (!c.ok) for (int i = 0; i < 3; i++) { c.lo[i] = 0; c.ext[i] = 0; }
+    ((CellRec*)a.crec)[k] = c;
+}
+
+hipError_t launch_cellrec(const DevArgs& a, hipStream_t st) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(cellrec_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// rigid-body velocity V + Omega x (s - X) of cell p at node s, in the link
+// type of the storage mode (the moving-boundary term of Eq. 10 and the link
+// momenta use it)
+__device__ inline void store_usol(const DevArgs& a, long long s, int x, int y, int z, int p, const CellRec& cr) {
+    double X[3], V[3], W[3];
+    if (p == cr.p) {
+        for (int c = 0; c < 3; c++) { X[c] = cr.X[c]; V[c] = cr.V[c]; W[c] = cr.W[c]; }
+    } else {
+        const double* k = a.kin + 12 * (long long)p;
+        for (int c = 0; c < 3; c++) { X[c] = k[c]; V[c] = k[3 + c]; W[c] = k[6 + c]; }
+    }
+    double d[3], u[3];
+    node_disp(a, x, y, z, X, d);
+    cross3(W, d, u);
+    for (int c = 0; c < 3; c++) u[c] += V[c];
+    if (a.precision == CGB_P64) {
+        double* U = (double*)a.usol + 4 * s;
+        U[0] = u[0]; U[1] = u[1]; U[2] = u[2];
+    } else {
+        float* U = (float*)a.usol + 4 * s;
+        U[0] = (float)u[0]; U[1] = (float)u[1]; U[2] = (float)u[2];
+    }
+}
+
+// one wave per cell, CPW cells (waves) per workgroup: lane (ix, iy) of an
+// 8 x 8 footprint walks z in slabs of ZB nodes whose loads are issued
+// together.  The waves of a workgroup work independently.
+constexpr int ZB = 8;
+constexpr int CPW = 4;
+
 template <bool RESOLVE>
-__global__ void __launch_bounds__(64) raster_kernel(DevArgs a) {
-    const int p = blockIdx.x;
-    if (p >= a.n) return;
-    int lo[3], ext[3];
-    if (!union_box(a, p, lo, ext)) return;
+__global__ void __launch_bounds__(64 * CPW) raster_kernel(DevArgs a) {
+    const unsigned nx = (unsigned)a.nx, plane = (unsigned)a.nx * (unsigned)a.ny;
+    const int lane = threadIdx.x & 63;
+    const int k = __builtin_amdgcn_readfirstlane(blockIdx.x * CPW + (int)(threadIdx.x >> 6));
+    if (k >= a.n) return;
+    // cells in cell-list order: neighbouring waves touch neighbouring nodes
+    const CellRec cr = ((const CellRec*)a.crec)[k];
+    if (!cr.ok) return;  // the record kernel has flagged the state as unstable
+    const int p = cr.p;
+    const int* lo = cr.lo;
+    const int* ext = cr.ext;
     for (int bx = 0; bx < ext[0]; bx += 8)
         for (int by = 0; by < ext[1]; by += 8) {
-            const int ix = bx + (threadIdx.x & 7), iy = by + (threadIdx.x >> 3);
-            if (ix >= ext[0] || iy >= ext[1]) continue;
-            int x = lo[0] + ix;
-            x = x < 0 ? x + a.nx : (x >= a.nx ? x - a.nx : x);
+            const int ix = bx + (lane & 7), iy = by + (lane >> 3);
+            bool col = ix < ext[0] && iy < ext[1];
+            const int x = wrap(lo[0] + ix, a.nx);
             int y = lo[1] + iy;
-            if (a.wall_y) {
-                if (y < 0 || y >= a.ny) continue;
-            } else {
-                y = y < 0 ? y + a.ny : (y >= a.ny ? y - a.ny : y);
-            }
-            for (int iz = 0; iz < ext[2]; iz++) {
-                int z = lo[2] + iz;
-                z = z < 0 ? z + a.nz : (z >= a.nz ? z - a.nz : z);
-                const long long s = x + (long long)a.nx * (y + (long long)a.ny * z);
-                const int o = a.owner[s];
-                if (o == OWN_WALL) continue;
-                if (!RESOLVE) {
-                    // the owner keeps a node it still covers: no claim needed
-                    if (o != p && covers(a, p, x, y, z)) atomicMin(a.cand + s, p);
-                    continue;
+            if (a.wall_y) col = col && y >= 0 && y < a.ny;
+            else y = wrap(y, a.ny);
+            for (int z0 = 0; z0 < ext[2]; z0 += ZB) {
+                unsigned sj[ZB];
+                int ow[ZB], cd[ZB];
+#pragma unroll
+                for (int j = 0; j < ZB; j++) {
+                    const bool ok = col && z0 + j < ext[2];
+                    sj[j] = (unsigned)x + nx * (unsigned)y + plane * (unsigned)wrap(lo[2] + z0 + j, a.nz);
+                    ow[j] = ok ? a.owner[sj[j]] : OWN_WALL;
+                    if (RESOLVE) cd[j] = ok ? a.cand[sj[j]] : NO_CAND;
                 }
-                const bool mine = (o == p) || (o == OWN_FLUID && a.cand[s] == p);
-                if (!mine) continue;
-                const int c = a.cand[s];
-                const bool keep = (o == p) && covers(a, p, x, y, z);
-                const int nw = keep ? p : (c != NO_CAND ? c : OWN_FLUID);
-                if (c != NO_CAND) a.cand[s] = NO_CAND;
-                if (nw != o) {
-                    const int t = atomicAdd(a.ntrans, 1);
-                    if (t < a.trans_cap) {
-                        a.trans[3 * t] = (int)s;
-                        a.trans[3 * t + 1] = o;
-                        a.trans[3 * t + 2] = nw;
-                    } else {
-                        atomicOr(a.status, ST_TRANS_OVERFLOW);
+#pragma unroll
+                for (int j = 0; j < ZB; j++) {
+                    const int o = ow[j];
+                    const unsigned s = sj[j];
+                    const int z = wrap(lo[2] + z0 + j, a.nz);
+                    if (!RESOLVE) {
+                        // the owner keeps a node it still covers: no claim needed
+                        if (o != OWN_WALL && o != p && covers(a, cr, x, y, z)) atomicMin(a.cand + s, p);
+                        continue;
+                    }
+                    const int c = cd[j];
+                    const bool mine = o != OWN_WALL && ((o == p) || (o == OWN_FLUID && c == p));
+                    int nw = o;
+                    if (mine) {
+                        const bool keep = (o == p) && covers(a, cr, x, y, z);
+                        nw = keep ? p : (c != NO_CAND ? c : OWN_FLUID);
+                        if (c != NO_CAND) a.cand[s] = NO_CAND;
+                        // every node that is a cell node after this step is decided
+                        // by exactly one pass: store the rigid-body velocity of its cell
+                        if (nw >= 0) store_usol(a, s, x, y, z, nw, cr);
+                    }
+                    // transitions: one list reservation per wave and slab
+                    const bool tr = nw != o;
+                    const unsigned long long m = __ballot(tr);
+                    if (m) {
+                        const int first = __ffsll((long long)m) - 1;
+                        int base = 0;
+                        if (lane == first) base = atomicAdd(a.ntrans, __popcll(m));
+                        base = __shfl(base, first, 64);
+                        if (tr) {
+                            const int t = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                            if (t < a.trans_cap) {
+                                a.trans[3 * t] = (int)s;
+                                a.trans[3 * t + 1] = o;
+                                a.trans[3 * t + 2] = nw;
+                            } else {
+                                atomicOr(a.status, ST_TRANS_OVERFLOW);
+                            }
+                        }
                     }
                 }
             }
         }
     if (RESOLVE) {
-        __syncthreads();
-        if (threadIdx.x < 3) {
+        // the wave read this cell's previous box at its start; record the new one
+        if (lane < 3) {
             double h[3];
-            half_extents(a, a.kin + 12 * (long long)p + 9, h);
-            a.Xprev[3 * p + threadIdx.x] = a.kin[12 * (long long)p + threadIdx.x];
-            a.Hprev[3 * p + threadIdx.x] = h[threadIdx.x];
+            half_extents(a, cr.o, h);
+            a.Xprev[3 * p + lane] = cr.X[lane];
+            a.Hprev[3 * p + lane] = h[lane];
         }
     }
+}
+
+static inline unsigned cell_grid(int n) { return (unsigned)((n + CPW - 1) / CPW); }
+
+// ------------------------------------------------------------------ momentum exchange
+// Force and torque on each cell from the link momenta the LB kernel stored
+// at the cell's nodes (Eq. 12): F = sum over the cell's nodes s and the
+// directions r with a fluid node at s + c_r of mlink[r][s] c_r, and
+// T = sum (s - X) x (same); the lever point may be any point of the link
+// line (the transferred momentum is parallel to c_r) and s is one.
+// One wave per cell: lanes cover an 8 x 8 patch of the cell's box and sweep
+// z; the cell's nodes are compacted in lane order (deterministic) and then
+// processed 64 at a time with the 18 loads of a node issued together.
+constexpr int MR_CAP = 64 * ZB;
+
+// wave-local ordering of LDS accesses (the waves of a workgroup do not meet)
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class M>
+__global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
+    __shared__ unsigned lst_sa[CPW][MR_CAP];
+    __shared__ uint32_t lst_fa[CPW][MR_CAP];
+    const unsigned ps = (unsigned)a.pstride;
+    const unsigned nx = (unsigned)a.nx, plane = (unsigned)a.nx * (unsigned)a.ny;
+    const auto rM = make_rsrc(a.mlink, 18ull * ps * sizeof(M));
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    unsigned* lst_s = lst_sa[wv];
+    uint32_t* lst_f = lst_fa[wv];
+    const int kk = __builtin_amdgcn_readfirstlane(blockIdx.x * CPW + wv);
+    if (kk >= a.n) return;
+    // the record's box (previous and current rasterisation) holds every node of the cell
+    const CellRec cr = ((const CellRec*)a.crec)[kk];
+    if (!cr.ok) return;  // the record kernel has flagged the state as unstable
+    const int p = cr.p;
+    const int* lo = cr.lo;
+    const int* ext = cr.ext;
+    double F0 = 0, F1 = 0, F2 = 0, T0 = 0, T1 = 0, T2 = 0;
+    for (int bx = 0; bx < ext[0]; bx += 8)
+        for (int by = 0; by < ext[1]; by += 8) {
+            const int ix = bx + (lane & 7), iy = by + (lane >> 3);
+            bool col = ix < ext[0] && iy < ext[1];
+            const int x = wrap(lo[0] + ix, a.nx);
+            int y = lo[1] + iy;
+            if (a.wall_y) col = col && y >= 0 && y < a.ny;
+            else y = wrap(y, a.ny);
+            for (int z0 = 0; z0 < ext[2]; z0 += ZB) {
+                // the slab's nodes of cell p, compacted in (z, lane) order
+                unsigned sj[ZB];
+                int ow[ZB];
+                uint32_t fl[ZB];
+#pragma unroll
+                for (int j = 0; j < ZB; j++) {
+                    const bool ok = col && z0 + j < ext[2];
+                    sj[j] = (unsigned)x + nx * (unsigned)y + plane * (unsigned)wrap(lo[2] + z0 + j, a.nz);
+                    ow[j] = ok ? a.owner[sj[j]] : OWN_WALL;
+                    fl[j] = ok ? a.flags[sj[j]] : 0u;
+                }
+                int cnt = 0;
+#pragma unroll
+                for (int j = 0; j < ZB; j++) {
+                    const bool mine = ow[j] == p;
+                    const unsigned long long m = __ballot(mine);
+                    if (mine) {
+                        const int e = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                        lst_s[e] = sj[j];
+                        lst_f[e] = fl[j];
+                    }
+                    cnt += __popcll(m);
+                }
+                wave_sync();
+                for (int base = 0; base < cnt; base += 64) {
+                    const int e = base + lane;
+                    if (e < cnt) {
+                        const unsigned s = lst_s[e];
+                        const uint32_t f = lst_f[e];
+                        M mv[19];
+#pragma unroll
+                        for (int r = 1; r < 19; r++) {
+                            // fluid at s + c_r: bit OPP(r) of s's flags (source s - c_OPP(r)) is clear
+                            const bool lk = !((f >> OPP(r)) & 1u);
+                            mv[r] = bload<M>(rM, lk ? (unsigned)sizeof(M) * ((unsigned)(r - 1) * ps + s) : 0xfffffff0u);
+                        }
+                        M m0 = 0, m1 = 0, m2 = 0;
+#pragma unroll
+                        for (int r = 1; r < 19; r++) {
+                            if (CX(r)) m0 += CX(r) * mv[r];
+                            if (CY(r)) m1 += CY(r) * mv[r];
+                            if (CZ(r)) m2 += CZ(r) * mv[r];
+                        }
+                        const int sx = (int)(s % nx), sy = (int)((s / nx) % (unsigned)a.ny), sz = (int)(s / plane);
+                        double d[3];
+                        node_disp(a, sx, sy, sz, cr.X, d);
+                        const double g0 = (double)m0, g1 = (double)m1, g2 = (double)m2;
+                        F0 += g0; F1 += g1; F2 += g2;
+                        T0 += d[1] * g2 - d[2] * g1;
+                        T1 += d[2] * g0 - d[0] * g2;
+                        T2 += d[0] * g1 - d[1] * g0;
+                    }
+                }
+                wave_sync();
+            }
+        }
+    F0 = wave_sum(F0); F1 = wave_sum(F1); F2 = wave_sum(F2);
+    T0 = wave_sum(T0); T1 = wave_sum(T1); T2 = wave_sum(T2);
+    if (lane == 0) {
+        double* FT = a.FTh + 6 * (long long)p;
+        FT[0] += F0; FT[1] += F1; FT[2] += F2; FT[3] += T0; FT[4] += T1; FT[5] += T2;
+    }
+}
+
+hipError_t launch_mem_reduce(const DevArgs& a, hipStream_t st) {
+    if (a.n == 0) return hipSuccess;
+    if (a.precision == CGB_P64) hipLaunchKernelGGL(mem_reduce_kernel<double>, dim3(cell_grid(a.n)), dim3(64 * CPW), 0, st, a);
+    else hipLaunchKernelGGL(mem_reduce_kernel<float>, dim3(cell_grid(a.n)), dim3(64 * CPW), 0, st, a);
+    return hipGetLastError();
+}
+
+// wall nodes carry their plane velocity (Eq. 10; zero for resting walls),
+// every other node starts at rest
+template <class M>
+__global__ void usol_walls_kernel(DevArgs a) {
+    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (s >= a.ns) return;
+    const int y = (int)((s / a.nx) % a.ny);
+    double u[3] = {0, 0, 0};
+    if (a.owner[s] == OWN_WALL && a.wall_y) {
+        if (y == 0) { u[0] = a.wvb[0]; u[1] = a.wvb[1]; u[2] = a.wvb[2]; }
+        else if (y == a.ny - 1) { u[0] = a.wvt[0]; u[1] = a.wvt[1]; u[2] = a.wvt[2]; }
+    }
+    M* U = (M*)a.usol + 4 * s;
+    U[0] = (M)u[0]; U[1] = (M)u[1]; U[2] = (M)u[2]; U[3] = (M)0;
+}
+
+hipError_t launch_usol_walls(const DevArgs& a, hipStream_t st) {
+    const dim3 g((unsigned)((a.ns + 255) / 256)), b(256);
+    if (a.precision == CGB_P64) hipLaunchKernelGGL(usol_walls_kernel<double>, g, b, 0, st, a);
+    else hipLaunchKernelGGL(usol_walls_kernel<float>, g, b, 0, st, a);
+    return hipGetLastError();
 }
 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
@@ -203,8 +420,9 @@ __global__ void step_begin_kernel(int* ntrans, int* dstep, int advance) {
 hipError_t launch_raster(const DevArgs& a, hipStream_t st, bool fresh) {
     hipLaunchKernelGGL(step_begin_kernel, dim3(1), dim3(1), 0, st, a.ntrans, a.dstep, fresh ? 0 : 1);
     if (a.n == 0) return hipGetLastError();
-    hipLaunchKernelGGL(raster_kernel<false>, dim3(a.n), dim3(64), 0, st, a);
-    hipLaunchKernelGGL(raster_kernel<true>, dim3(a.n), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(cellrec_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(raster_kernel<false>, dim3(cell_grid(a.n)), dim3(64 * CPW), 0, st, a);
+    hipLaunchKernelGGL(raster_kernel<true>, dim3(cell_grid(a.n)), dim3(64 * CPW), 0, st, a);
     return hipGetLastError();
 }
 
@@ -335,6 +553,7 @@ hipError_t launch_fill_f64(double* p, long long n, double v, hipStream_t st) {
 
 // ------------------------------------------------------------------ cell list
 __device__ inline int bin_coord(const DevArgs& a, int c, double v) {
+    if (!(v == v)) return 0;
     int b = (int)floor(v / a.bedge[c]);
     if (b < 0) b = 0;
     if (b >= a.nb[c]) b = a.nb[c] - 1;
@@ -530,8 +749,9 @@ __device__ void wall_term(const DevArgs& a, const double* rv, const double* o, d
 }
 
 __global__ void potentials_kernel(DevArgs a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n) return;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const int i = a.bin_idx[k];  // cell-list order: neighbouring threads share neighbour bins
     const double Xi[3] = {a.X[3 * i], a.X[3 * i + 1], a.X[3 * i + 2]};
     const double* ki = a.kin + 12 * (long long)i;
     const double oi[3] = {ki[9], ki[10], ki[11]};

@@ -19,7 +19,7 @@
 
 using namespace cgb;
 
-static const char* kKindNames[] = {"prep", "raster", "transitions", "lb", "mem_gather", "cells", "potentials", "integrate"};
+static const char* kKindNames[] = {"prep", "raster", "transitions", "lb", "mem_reduce", "cells", "potentials", "integrate"};
 
 #define FAIL(s, code, ...)                                  \
     do {                                                    \
@@ -172,19 +172,11 @@ void cgb_destroy(cgb_sim* s) {
     delete s;
 }
 
-// LB tile shape and the per-cell slot geometry that goes with it
+// LB launch shape
 static void set_tiles(cgb_sim* s, LaunchCfg cfg) {
     DevArgs& a = s->a;
     s->lbcfg = cfg;
     a.tile[0] = cfg.bx; a.tile[1] = cfg.by; a.tile[2] = cfg.tz;
-    const int n3[3] = {a.nx, a.ny, a.nz};
-    const int ext = 2 * (int)ceil(a.Rb) + 5;  // footprint of a cell's linked fluid nodes
-    a.nslot = 1;
-    for (int c = 0; c < 3; c++) {
-        a.ntile[c] = (n3[c] + a.tile[c] - 1) / a.tile[c];
-        a.slots[c] = std::min(a.ntile[c], (ext + a.tile[c] - 1) / a.tile[c] + 1);
-        a.nslot *= a.slots[c];
-    }
 }
 
 static LaunchCfg default_tiles(const DevArgs& a) {
@@ -195,22 +187,9 @@ static LaunchCfg default_tiles(const DevArgs& a) {
     return c;
 }
 
-static int alloc_slots(cgb_sim* s) {
-    DevArgs& a = s->a;
-    dfree(s, a.FTpart);
-    dfree(s, a.stamp);
-    a.FTpart = nullptr;
-    a.stamp = nullptr;
-    const size_t q = (size_t)std::max(s->ncap, 1) * (size_t)a.nslot;
-    HIPCHK(s, dalloc(s, &a.FTpart, q * 6 * 8));
-    HIPCHK(s, dalloc(s, &a.stamp, q * 4));
-    HIPCHK(s, launch_fill_i32(a.stamp, (long long)q, 0, s->st));
-    return CGB_OK;
-}
-
 static int alloc_particles(cgb_sim* s, int ncap) {
     DevArgs& a = s->a;
-    void* olds[] = {a.X, a.q, a.V, a.L, a.fixed, a.Xprev, a.Hprev, a.kin, a.FTh, a.FTp, a.trans, a.pbin, a.bin_idx, a.body_part};
+    void* olds[] = {a.X, a.q, a.V, a.L, a.fixed, a.Xprev, a.Hprev, a.kin, a.crec, a.FTh, a.FTp, a.trans, a.pbin, a.bin_idx, a.body_part};
     for (void* p : olds) dfree(s, p);
     const size_t n = (size_t)std::max(ncap, 1);
     HIPCHK(s, dalloc(s, &a.X, 3 * n * 8));
@@ -221,6 +200,7 @@ static int alloc_particles(cgb_sim* s, int ncap) {
     HIPCHK(s, dalloc(s, &a.Xprev, 3 * n * 8));
     HIPCHK(s, dalloc(s, &a.Hprev, 3 * n * 8));
     HIPCHK(s, dalloc(s, &a.kin, 12 * n * 8));
+    HIPCHK(s, dalloc(s, &a.crec, n * sizeof(CellRec)));
     HIPCHK(s, dalloc(s, &a.FTh, 6 * n * 8));
     HIPCHK(s, dalloc(s, &a.FTp, 6 * n * 8));
     HIPCHK(s, dalloc(s, &a.pbin, n * 4));
@@ -232,7 +212,7 @@ static int alloc_particles(cgb_sim* s, int ncap) {
     a.trans_cap = (int)cap;
     HIPCHK(s, dalloc(s, &a.trans, (size_t)cap * 3 * 4));
     s->ncap = ncap;
-    return alloc_slots(s);
+    return CGB_OK;
 }
 
 int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_sim** out) {
@@ -242,9 +222,11 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
         p->precision > CGB_PMXBF16 || !(p->R_perp > 0) || !(p->R_par > 0) || !(p->rho_p > 0) || !(p->r_cut > 0))
         return CGB_EINVAL;
     {
+        // populations and link momenta are addressed with 32-bit byte offsets
         const double esz = p->precision == CGB_P64 ? 8.0 : (p->precision == CGB_P32 ? 4.0 : 2.0);
-        if (19.0 * esz * (double)(((long long)p->nx * p->ny * p->nz + 255) / 256 * 256) >= 4294967295.0)
-            return CGB_EINVAL;  // populations are addressed with 32-bit byte offsets
+        const double msz = p->precision == CGB_P64 ? 8.0 : 4.0;
+        const double pst = (double)(((long long)p->nx * p->ny * p->nz + 255) / 256 * 256);
+        if (19.0 * esz * pst >= 4294901760.0 || 18.0 * msz * pst >= 4294901760.0) return CGB_EINVAL;
     }
     cgb_sim* s = new cgb_sim();
     s->P = *p;
@@ -294,6 +276,9 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
         CK(dalloc(s, &s->rho[0], (size_t)a.pstride * s->esize));
         CK(dalloc(s, &s->rho[1], (size_t)a.pstride * s->esize));
         CK(dalloc(s, &a.owner, (size_t)a.ns * 4));
+        const size_t msz = p->precision == CGB_P64 ? 8 : 4;
+        CK(dalloc(s, &a.usol, 4 * (size_t)a.pstride * msz));
+        CK(dalloc(s, &a.mlink, 18 * (size_t)a.pstride * msz));
         CK(dalloc(s, &a.flags, (size_t)a.ns * 4));
         CK(dalloc(s, &a.cand, (size_t)a.ns * 4));
         CK(dalloc(s, &a.ntrans, 16));
@@ -310,6 +295,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
             if (w) own[(size_t)i] = OWN_WALL;
         }
         CK(hipMemcpyAsync(a.owner, own.data(), (size_t)a.ns * 4, hipMemcpyHostToDevice, s->st));
+        CK(launch_usol_walls(a, s->st));
         // cell-list geometry: bin edge >= max(cut-off, wall potential range)
         const double Lb[3] = {(double)a.nx, (double)a.ny, (double)a.nz};
         const double emin = std::max(p->r_cut, wr);
@@ -425,13 +411,12 @@ int cgb_set_particles(cgb_sim* s, int32_t n, const double* X, const double* q, c
         HIPCHK(s, hipMemcpyAsync(a.fixed, fx.data(), (size_t)n, hipMemcpyHostToDevice, s->st));
     }
     bind_buffers(s);
-    HIPCHK(s, launch_fill_i32(a.stamp, (long long)std::max(s->ncap, 1) * a.nslot, 0, s->st));
     HIPCHK(s, launch_clear_cells(a, s->st));
     HIPCHK(s, launch_prep(a, s->st));
+    HIPCHK(s, launch_cells(a, s->st));  // the per-cell kernels walk the cells in cell-list order
     HIPCHK(s, launch_raster(a, s->st, true));
     HIPCHK(s, launch_transitions(a, s->st, false));
     HIPCHK(s, launch_flags_rebuild(a, s->st));
-    HIPCHK(s, launch_cells(a, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     return check_status(s);
 }
@@ -476,7 +461,7 @@ int cgb_step(cgb_sim* s, int32_t nsteps) {
         HIPCHK(s, timed(s, K_RASTER, [&] { return launch_raster(a, s->st, false); }));
         HIPCHK(s, timed(s, K_TRANS, [&] { return launch_transitions(a, s->st, true); }));
         HIPCHK(s, timed(s, K_LB, [&] { return launch_lb(a, s->lbcfg, s->st); }));
-        HIPCHK(s, timed(s, K_GATHER, [&] { return launch_mem_gather(a, s->st); }));
+        HIPCHK(s, timed(s, K_MEM, [&] { return launch_mem_reduce(a, s->st); }));
         HIPCHK(s, timed(s, K_CELLS, [&] { return launch_cells(a, s->st); }));
         HIPCHK(s, timed(s, K_POT, [&] { return launch_potentials(a, s->st); }));
         HIPCHK(s, timed(s, K_INT, [&] { return launch_integrate(a, s->st); }));
@@ -704,7 +689,34 @@ int cgb_set_tiles(cgb_sim* s, int32_t bx, int32_t by, int32_t tz) {
         FAIL(s, CGB_EINVAL, "tile %dx%dx%d: need bx*by a multiple of 64, at most 256, tz in {4,8,16,32}", bx, by, tz);
     HIPCHK(s, hipStreamSynchronize(s->st));
     set_tiles(s, LaunchCfg{bx, by, tz});
-    return alloc_slots(s);
+    return CGB_OK;
+}
+
+// Times the fused LB kernel alone on the current state: it reads the current
+// populations, flags and boundary velocities and writes only buffers that the
+// next step rewrites before reading (the other population buffer, its density
+// field and the link momenta), so the state is unchanged.
+int cgb_time_lb(cgb_sim* s, int32_t reps, double* ms_avg) {
+    if (!s || reps < 1 || !ms_avg) return CGB_EINVAL;
+    if (!s->fluid_ready) FAIL(s, CGB_ESTATE, "fluid not initialised");
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    if (s->prof) harvest(s);
+    bind_buffers(s);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    for (int k = 0; k < 2 && e == hipSuccess; k++) e = launch_lb(s->a, s->lbcfg, s->st);
+    if (e == hipSuccess) e = hipEventRecord(e0, s->st);
+    for (int k = 0; k < reps && e == hipSuccess; k++) e = launch_lb(s->a, s->lbcfg, s->st);
+    if (e == hipSuccess) e = hipEventRecord(e1, s->st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    HIPCHK(s, e);
+    *ms_avg = (double)ms / reps;
+    return CGB_OK;
 }
 
 int cgb_get_tiles(cgb_sim* s, int32_t* t) {
@@ -790,7 +802,6 @@ int cgb_load(cgb_sim* s, const char* path) {
     bind_buffers(s);
     HIPCHK(s, launch_fill_i32(a.dstep, 1, (int)step - 1, s->st));
     HIPCHK(s, launch_fill_i32(a.cand, a.ns, NO_CAND, s->st));
-    HIPCHK(s, launch_fill_i32(a.stamp, (long long)std::max(s->ncap, 1) * a.nslot, 0, s->st));
     HIPCHK(s, launch_cells(a, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     return CGB_OK;

@@ -11,7 +11,7 @@ struct LaunchRec {
     hipEvent_t e0, e1;
 };
 
-enum { K_PREP, K_RASTER, K_TRANS, K_LB, K_GATHER, K_CELLS, K_POT, K_INT, K_NKIND };
+enum { K_PREP, K_RASTER, K_TRANS, K_LB, K_MEM, K_CELLS, K_POT, K_INT, K_NKIND };
 
 struct cgb_sim {
     cgb_params P;
