@@ -60,6 +60,7 @@ struct orc_sim {
     uint8_t* fixed;
     double M, Ipar, Iperp;
     double *o, *Om;
+    double *Xl, *Vl;     /* X(t) and V(t-1/2) of the last step: the kinematics its bounce-back used */
     double *Fh, *Th, *Fp, *Tp;
     int64_t *Aint, *Bint;
     int32_t* pairs;
@@ -268,9 +269,9 @@ int orc_create(const orc_params* p, const uint8_t* wall_mask, orc_sim** out) {
 
 static void free_particles(orc_sim* s) {
     free(s->X); free(s->q); free(s->V); free(s->L); free(s->fixed);
-    free(s->o); free(s->Om); free(s->Fh); free(s->Th); free(s->Fp); free(s->Tp);
+    free(s->o); free(s->Om); free(s->Xl); free(s->Vl); free(s->Fh); free(s->Th); free(s->Fp); free(s->Tp);
     free(s->Aint); free(s->Bint); free(s->pairs);
-    s->X = s->q = s->V = s->L = s->o = s->Om = s->Fh = s->Th = s->Fp = s->Tp = NULL;
+    s->X = s->q = s->V = s->L = s->o = s->Om = s->Xl = s->Vl = s->Fh = s->Th = s->Fp = s->Tp = NULL;
     s->fixed = NULL; s->Aint = s->Bint = NULL; s->pairs = NULL;
     s->n = 0; s->npairs = 0; s->pcap = 0;
 }
@@ -345,6 +346,8 @@ int orc_set_particles(orc_sim* s, int32_t n, const double* X, const double* q,
     s->fixed = (uint8_t*)xcalloc((size_t)n, 1);
     s->o = (double*)xcalloc((size_t)3 * n, sizeof(double));
     s->Om = (double*)xcalloc((size_t)3 * n, sizeof(double));
+    s->Xl = (double*)xcalloc((size_t)3 * n, sizeof(double));
+    s->Vl = (double*)xcalloc((size_t)3 * n, sizeof(double));
     s->Fh = (double*)xcalloc((size_t)3 * n, sizeof(double));
     s->Th = (double*)xcalloc((size_t)3 * n, sizeof(double));
     s->Fp = (double*)xcalloc((size_t)3 * n, sizeof(double));
@@ -359,6 +362,8 @@ int orc_set_particles(orc_sim* s, int32_t n, const double* X, const double* q,
         if (fixed) memcpy(s->fixed, fixed, (size_t)n);
     }
     compute_axes(s);
+    memcpy(s->Xl, s->X, sizeof(double) * 3 * n);
+    memcpy(s->Vl, s->V, sizeof(double) * 3 * n);
     /* fresh occupancy: lowest covering index; nodes freed by this call get
      * rest fluid at rho0 */
     cover_scan(s);
@@ -645,6 +650,8 @@ static int one_step(orc_sim* s) {
 
     /* 1. axes at X(t), q(t); angular velocity at t-1/2 */
     compute_axes(s);
+    memcpy(s->Xl, s->X, sizeof(double) * 3 * s->n);
+    memcpy(s->Vl, s->V, sizeof(double) * 3 * s->n);
     for (int a = 0; a < 3 * s->n; a++) { s->Fh[a] = s->Th[a] = s->Fp[a] = s->Tp[a] = 0.0; s->Aint[a] = s->Bint[a] = 0; }
 
     /* 2. rasterise and apply the occupancy rule */
@@ -860,6 +867,47 @@ int orc_step(orc_sim* s, int32_t nsteps) {
 }
 
 /* ---- read-out ---- */
+
+/* Mixture z velocity after the last step, summed over the non-wall nodes
+ * (the observable behind the apparent-viscosity estimators; the paper
+ * defines the apparent viscosity from the mean flow, Sec. V, and these sums
+ * are that mean flow for body-force driving):
+ *   fluid node: u_z = (sum n* c_z - g_z/2)/rho, the velocity of the last
+ *               collision (the forcing adds exactly g to sum n* c);
+ *   cell node:  the rigid-body velocity of its cell at the node, V + Omega x
+ *               (x - X), with the X, V, Omega the last step's bounce-back used.
+ * out[0] = sum u_z sin(2 pi y / ny), out[1] = sum u_z, out[2] = node count. */
+int orc_mixture_sums(const orc_sim* s, double* out) {
+    const orc_params* P = &s->P;
+    double ssin = 0.0, sone = 0.0, cnt = 0.0;
+    for (int64_t i = 0; i < s->ns; i++) {
+        if (s->wall[i]) continue;
+        int x = (int)(i % P->nx), y = (int)((i / P->nx) % P->ny), z = (int)(i / ((int64_t)P->nx * P->ny));
+        double uz;
+        int32_t o = s->owner[i];
+        if (o == -1) {
+            double drho = 0.0, jz = 0.0;
+            for (int r = 0; r < 19; r++) {
+                double v = s->dA[r * s->ns + i];
+                drho += v;
+                jz += v * CV[r][2];
+            }
+            double g[3];
+            force_at(P, (double)y, g);
+            uz = (jz - 0.5 * g[2]) / (P->rho0 + drho);
+        } else {
+            double node[3] = {x, y, z}, d[3], w[3]; int k[3];
+            disp(s, node, &s->Xl[3 * o], d, k);
+            cross(&s->Om[3 * o], d, w);
+            uz = s->Vl[3 * o + 2] + w[2];
+        }
+        ssin += uz * sin(2.0 * M_PI * y / P->ny);
+        sone += uz;
+        cnt += 1.0;
+    }
+    out[0] = ssin; out[1] = sone; out[2] = cnt;
+    return ORC_OK;
+}
 int orc_get_deviations(const orc_sim* s, double* d) {
     memcpy(d, s->dA, sizeof(double) * 19 * s->ns);
     return ORC_OK;

@@ -72,6 +72,11 @@ int  orc_get_link_static(const orc_sim* s, int64_t* A /* n*3 */, int64_t* B /* n
  * out[11]=step counter */
 int  orc_get_observables(const orc_sim* s, double* out /* 12 */);
 int  orc_mass_props(const orc_sim* s, double* out /* M, I_par, I_perp */);
+/* sums over the non-wall nodes of the mixture z velocity after the last step
+ * (fluid: velocity of the last collision; cell node: rigid-body velocity of
+ * its cell as the last bounce-back used it): out[0] weighted by
+ * sin(2 pi y/ny), out[1] unweighted, out[2] node count */
+int  orc_mixture_sums(const orc_sim* s, double* out /* 3 */);
 
 /* Pure functions for pins */
 void orc_d3q19(int32_t* c /* 19*3 */, double* w /* 19 */, int32_t* opp /* 19 */);

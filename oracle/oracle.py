@@ -90,6 +90,7 @@ def lib():
         L.orc_get_link_static.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_get_observables.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_mass_props.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_mixture_sums.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_d3q19.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_equilibrium.argtypes = [C.c_double, C.c_void_p, C.c_void_p]
         L.orc_bp_pair.argtypes = [C.POINTER(OrcParams)] + [C.c_void_p] * 7
@@ -228,6 +229,22 @@ class Oracle:
         lib().orc_mass_props(self.h, _ptr(o))
         return {"M": o[0], "I_par": o[1], "I_perp": o[2]}
 
+    def mixture(self):
+        """(A, ubar) after the last step: A = (2/N) sum u_z sin(2 pi y/ny), the
+        sine amplitude of the plane-averaged mixture velocity, and ubar = the
+        mean mixture z velocity, over the N non-wall nodes."""
+        o = np.empty(3)
+        lib().orc_mixture_sums(self.h, _ptr(o))
+        return 2.0 * o[0] / o[2], o[1] / o[2]
+
+    def track(self, nsteps):
+        """Steps nsteps times, recording mixture() after every step: (nsteps, 2)."""
+        out = np.empty((nsteps, 2))
+        for t in range(nsteps):
+            self.step(1)
+            out[t] = self.mixture()
+        return out
+
 
 # ---- pure functions ----
 def d3q19():
@@ -278,3 +295,41 @@ def inside(params: dict, X, o, node):
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+# ---- apparent viscosity estimators (body-force driven flows) ----
+def mu_rel_kolmogorov(A, f0, rho0, ny, first):
+    """Relative apparent viscosity from the mode amplitudes A_t of a
+    Kolmogorov flow driven by f0 sin(k y), k = 2 pi / ny, at tau = 1.
+
+    At tau = 1 one step maps the amplitude of a pure shear mode exactly as
+    A_{t+1} = lam A_t + (1 + lam) f0 / (2 rho0), lam = (2 + cos k)/3 (the
+    third-order terms of Eq. 5 and the Guo term contribute nothing odd in
+    c_z for a pure shear flow); the decay per step (1 - lam) A_t =
+    (1 - cos k)/3 A_t is the viscous term nu k^2 A at nu = 1/6.  Writing the
+    mixture's decay as mu_rel times the plasma's gives, per step,
+      mu_rel(t) = [f0 (5 + cos k)/(6 rho0) - (A_{t+1} - A_t)] / [A_t (1 - cos k)/3],
+    identically 1 for the particle-free fluid.  Returned: the mean of
+    mu_rel(t) over t = first .. len(A) - 2."""
+    A = np.asarray(A, dtype=np.float64)
+    k = 2.0 * np.pi / ny
+    t = np.arange(first, len(A) - 1)
+    mu = (f0 * (5.0 + np.cos(k)) / (6.0 * rho0) - (A[t + 1] - A[t])) / (A[t] * (1.0 - np.cos(k)) / 3.0)
+    return float(np.mean(mu))
+
+
+def mu_rel_slit(ubar, g, tau, ny, first):
+    """Relative apparent viscosity of a body-force driven slit between
+    mid-link walls (wall nodes y = 0 and ny - 1, N_f = ny - 2 fluid planes):
+    the mean over t = first .. end of the mixture's mean velocity ubar_t,
+    compared with the plasma's discrete steady state.  That state is the
+    parabola with the slip of mid-link bounce-back,
+    u(y) = g/(2 nu) [N_f^2/4 + (16 L - 3)/12 - (y - (N_f + 1)/2)^2],
+    L = (tau - 1/2)^2, whose mean over the fluid planes is
+    g (N_f^2 + 8 L - 1) / (12 nu) (= g (N_f^2 + 1)/(12 nu) at tau = 1), so
+    mu_rel = g (N_f^2 + 8 L - 1) / (12 nu <ubar>), nu = (2 tau - 1)/6."""
+    u = float(np.mean(np.asarray(ubar, dtype=np.float64)[first:]))
+    nf = ny - 2
+    nu = (2.0 * tau - 1.0) / 6.0
+    lam = (tau - 0.5) ** 2
+    return g * (nf * nf + 8.0 * lam - 1.0) / (12.0 * nu * u)
