@@ -140,6 +140,35 @@ int cgb_get_profile_z(cgb_sim* s, double* prof);
 int cgb_profile(cgb_sim* s, int enable);
 int cgb_kernel_times(cgb_sim* s, char* names, double* ms, int64_t* count, int32_t cap, int32_t* n);
 
+/* ---- Apparent viscosity (Sec. V defines it from the mean flow; for the
+ * body-force driven flows here the mean flow is the mixture velocity).
+ * cgb_track: after every following step, record on the device the sums over
+ * the N non-wall nodes of the mixture z velocity u_z -- fluid nodes: the
+ * velocity of the step's collision, (sum n* c_z - g_z/2)/rho; cell nodes: the
+ * rigid-body velocity of their cell that the step's bounce-back used --
+ * weighted by sin(2 pi y/ny) and by 1, for up to cap steps (cap = 0 stops).
+ * Replaces any earlier record.
+ * cgb_get_track: out[2k] = A_k = (2/N) sum u_z sin(2 pi y/ny) (the sine
+ * amplitude of the plane-averaged profile), out[2k+1] = ubar_k = (1/N) sum
+ * u_z, for k < min(cap, recorded); *n = steps recorded (at most the record's
+ * capacity). */
+int cgb_track(cgb_sim* s, int32_t cap);
+int cgb_get_track(cgb_sim* s, double* out, int32_t cap, int32_t* n);
+/* Estimators (host arithmetic on a recorded series).
+ * Kolmogorov flow f0 sin(2 pi y/ny) e_z at tau = 1: one step maps a pure
+ * shear mode exactly as A' = lam A + (1 + lam) f0/(2 rho0), lam = (2 + cos
+ * k)/3, the decay (1 - cos k)/3 A being nu k^2 A at nu = 1/6, so
+ *   mu_rel(t) = [f0 (5 + cos k)/(6 rho0) - (A_{t+1} - A_t)] / [A_t (1 - cos k)/3],
+ * averaged over t = first .. n-2 (1 for the plasma).
+ * Slit (walls y = 0, ny-1, constant g along z): the plasma's discrete steady
+ * mean velocity is g (N_f^2 + 8 (tau - 1/2)^2 - 1)/(12 nu), N_f = ny - 2, nu =
+ * (2 tau - 1)/6; mu_rel = that / mean(ubar[first .. n-1]).
+ * cgb_mu_rel picks the estimator from the handle's driving (CGB_EINVAL for
+ * any other) and applies it to the handle's record. */
+int cgb_mu_rel_kolmogorov(const double* A, int32_t n, int32_t first, double f0, double rho0, int32_t ny, double* mu);
+int cgb_mu_rel_slit(const double* ubar, int32_t n, int32_t first, double g, double tau, int32_t ny, double* mu);
+int cgb_mu_rel(cgb_sim* s, int32_t first, double* mu);
+
 /* Checkpoint: stored populations (as stored), owner, cell state and the step
  * counter.  Resume is bit-identical to an uninterrupted run. */
 int cgb_save(cgb_sim* s, const char* path);
@@ -184,9 +213,11 @@ int cgb_batch_capture(cgb_batch* b, int32_t steps);
 int cgb_batch_run(cgb_batch* b, int32_t nsteps);
 /* Waits for the replays and checks every channel (CGB_EUNSTABLE as cgb_sync). */
 int cgb_batch_sync(cgb_batch* b);
-/* ubar[nch]: mean z velocity of the mixture over the non-wall nodes of each
- * channel (the plane average of cgb_get_profile_z). */
-int cgb_batch_mean_velocity(cgb_batch* b, double* ubar);
+/* cgb_track on every channel (drops a captured graph: capture afterwards so
+ * that the replays record too). */
+int cgb_batch_track(cgb_batch* b, int32_t cap);
+/* mu[nch]: cgb_mu_rel of every channel. */
+int cgb_batch_mu_rel(cgb_batch* b, int32_t first, double* mu);
 
 #ifdef __cplusplus
 }

@@ -91,7 +91,13 @@ def lib():
     L.cgb_batch_capture.argtypes = [VP, C.c_int32]
     L.cgb_batch_run.argtypes = [VP, C.c_int32]
     L.cgb_batch_sync.argtypes = [VP]
-    L.cgb_batch_mean_velocity.argtypes = [VP, VP]
+    L.cgb_batch_track.argtypes = [VP, C.c_int32]
+    L.cgb_batch_mu_rel.argtypes = [VP, C.c_int32, VP]
+    L.cgb_track.argtypes = [VP, C.c_int32]
+    L.cgb_get_track.argtypes = [VP, VP, C.c_int32, C.POINTER(C.c_int32)]
+    L.cgb_mu_rel_kolmogorov.argtypes = [VP, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double)]
+    L.cgb_mu_rel_slit.argtypes = [VP, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double)]
+    L.cgb_mu_rel.argtypes = [VP, C.c_int32, C.POINTER(C.c_double)]
     _lib = L
     return L
 
@@ -256,6 +262,24 @@ class Sim:
         self._check(lib().cgb_get_tiles(self.h, _ptr(t)))
         return tuple(int(x) for x in t)
 
+    # -- mixture record and apparent viscosity
+    def track(self, cap):
+        """Record the mixture sums after each of the next cap steps."""
+        self._check(lib().cgb_track(self.h, int(cap)))
+
+    def get_track(self):
+        """(n, 2): per recorded step (A, ubar)."""
+        n = C.c_int32()
+        self._check(lib().cgb_get_track(self.h, None, 0, C.byref(n)))
+        out = np.empty((max(n.value, 1), 2))
+        self._check(lib().cgb_get_track(self.h, _ptr(out), n.value, C.byref(n)))
+        return out[: n.value]
+
+    def mu_rel(self, first=0):
+        mu = C.c_double()
+        self._check(lib().cgb_mu_rel(self.h, int(first), C.byref(mu)))
+        return mu.value
+
     def time_lb(self, reps=10):
         """Average milliseconds of the fused LB kernel on the current state."""
         ms = C.c_double()
@@ -344,7 +368,28 @@ class Batch:
     def sync(self):
         self._check(lib().cgb_batch_sync(self.h))
 
-    def mean_velocity(self):
-        u = np.empty(len(self))
-        self._check(lib().cgb_batch_mean_velocity(self.h, _ptr(u)))
-        return u
+    def track(self, cap):
+        self._check(lib().cgb_batch_track(self.h, int(cap)))
+
+    def mu_rel(self, first=0):
+        mu = np.empty(len(self))
+        self._check(lib().cgb_batch_mu_rel(self.h, int(first), _ptr(mu)))
+        return mu
+
+
+def mu_rel_kolmogorov(A, f0, rho0, ny, first):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    mu = C.c_double()
+    rc = lib().cgb_mu_rel_kolmogorov(_ptr(A), len(A), int(first), float(f0), float(rho0), int(ny), C.byref(mu))
+    if rc:
+        raise CgbError(rc, "cgb_mu_rel_kolmogorov")
+    return mu.value
+
+
+def mu_rel_slit(ubar, g, tau, ny, first):
+    u = np.ascontiguousarray(ubar, dtype=np.float64)
+    mu = C.c_double()
+    rc = lib().cgb_mu_rel_slit(_ptr(u), len(u), int(first), float(g), float(tau), int(ny), C.byref(mu))
+    if rc:
+        raise CgbError(rc, "cgb_mu_rel_slit")
+    return mu.value

@@ -239,24 +239,25 @@ int cgb_batch_sync(cgb_batch* b) {
     return CGB_OK;
 }
 
-// Mean z velocity of the mixture (fluid u_z or rigid velocity of the owning
-// cell) over the non-wall nodes of each channel: ubar[nch].
-int cgb_batch_mean_velocity(cgb_batch* b, double* ubar) {
-    if (!b || !ubar) return CGB_EINVAL;
+// Per-step mixture record on every channel (cgb_track); captured graphs
+// record too, so capture after enabling it.
+int cgb_batch_track(cgb_batch* b, int32_t cap) {
+    if (!b || cap < 0) return CGB_EINVAL;
+    drop_graph(b);
+    for (size_t c = 0; c < b->ch.size(); c++) {
+        const int rc = cgb_track(b->ch[c], cap);
+        if (rc) BFAIL(b, rc, "channel %zu: %s", c, cgb_last_error(b->ch[c]));
+    }
+    return CGB_OK;
+}
+
+// Apparent relative viscosity of every channel from its record (cgb_mu_rel).
+int cgb_batch_mu_rel(cgb_batch* b, int32_t first, double* mu) {
+    if (!b || !mu) return CGB_EINVAL;
     BCHK(b, hipStreamSynchronize(b->master));
     for (size_t c = 0; c < b->ch.size(); c++) {
-        cgb_sim* s = b->ch[c];
-        std::vector<double> prof((size_t)s->a.ny);
-        const int rc = cgb_get_profile_z(s, prof.data());
-        if (rc) BFAIL(b, rc, "channel %zu: %s", c, cgb_last_error(s));
-        double sum = 0.0;
-        int cnt = 0;
-        for (int y = 0; y < s->a.ny; y++) {
-            if (s->a.wall_y && (y == 0 || y == s->a.ny - 1)) continue;
-            sum += prof[(size_t)y];
-            cnt++;
-        }
-        ubar[c] = cnt ? sum / cnt : 0.0;
+        const int rc = cgb_mu_rel(b->ch[c], first, mu + c);
+        if (rc) BFAIL(b, rc, "channel %zu: %s", c, cgb_last_error(b->ch[c]));
     }
     return CGB_OK;
 }

@@ -111,6 +111,12 @@ struct DevArgs {
                        // the momentum, along c_r, that the link to the fluid
                        // node s + c_r transferred this step
     void* crec;        // [n] CellRec, in cell-list order (per-cell kernels)
+    // per-step record of the mixture velocity (apparent viscosity)
+    double* track;      // [track_cap][2]: sums of u_z sin(2 pi y/ny) and of u_z
+    int* track_n;       // steps recorded (keeps counting past track_cap)
+    int track_cap;
+    double* track_part; // per-block partial sums [TRACK_BLOCKS][2]
+    double* ysin;       // [ny] sin(2 pi y / ny)
     int tile[3];       // LB launch shape the kernels were configured for
     int* scan_tmp;     // block totals of the bin scan
     int nbody_blk;     // blocks of the integrate kernel (body_part has 3 per block)
@@ -313,5 +319,7 @@ hipError_t launch_equilibrium_fill(const DevArgs& a, const double* rho, const do
 hipError_t launch_fields(const DevArgs& a, double* rho, double* u, hipStream_t st);
 hipError_t launch_observables(const DevArgs& a, double* partial, int nblk, hipStream_t st);
 hipError_t launch_profile_z(const DevArgs& a, double* prof, double* cnt, hipStream_t st);
+constexpr int TRACK_BLOCKS = 1024;
+hipError_t launch_track(const DevArgs& a, hipStream_t st);
 hipError_t launch_pairs(const DevArgs& a, int* out, int* count, int cap, hipStream_t st);
 }  // namespace cgb

@@ -159,6 +159,92 @@ __global__ void profile_kernel(DevArgs a, double* prof, double* cnt) {
 
 static dim3 site_grid(const DevArgs& a) { return dim3((unsigned)((a.ns + 255) / 256)); }
 
+// Mixture z velocity of the state just written (B, rhoB) summed over the
+// non-wall nodes, weighted by sin(2 pi y/ny) and by 1: fluid nodes carry the
+// velocity of the collision, u_z = (sum n* c_z - g_z/2)/rho (the forcing adds
+// exactly g to sum n* c), cell nodes the rigid-body velocity of their cell
+// that the bounce-back used (the boundary velocity field).  Fixed grid and
+// fixed per-thread site sets, block partials reduced in a fixed order: the
+// sums are deterministic.
+template <int P>
+__global__ void __launch_bounds__(256) track_kernel(DevArgs a) {
+    using Cd = Codec<P>;
+    using T = typename Cd::T;
+    using M = typename Cd::R;
+    __shared__ double red[2][256];
+    const T* B = (const T*)a.B;
+    const T* RB = (const T*)a.rhoB;
+    const M* U = (const M*)a.usol;
+    double ss = 0.0, s1 = 0.0;
+    for (long long s = blockIdx.x * 256LL + threadIdx.x; s < a.ns; s += (long long)TRACK_BLOCKS * 256) {
+        const int o = a.owner[s];
+        if (o == OWN_WALL) continue;
+        const int y = (int)((s / a.nx) % a.ny);
+        double uz;
+        if (o == OWN_FLUID) {
+            double jz = 0.0;
+#pragma unroll
+            for (int r = 5; r < 19; r++)
+                if (CZ(r)) jz += CZ(r) * (double)Cd::dec(B[r * a.pstride + s], dec_scale<P>(a, r));
+            const double drho = (double)Cd::dec(RB[s], rho_dec_scale<P>(a));
+            const double gz = a.force_mode == 1 ? a.g[2] : (a.force_mode == 2 ? a.f0 * a.ysin[y] : 0.0);
+            uz = (jz - 0.5 * gz) / (a.rho0 + drho);
+        } else {
+            uz = (double)U[4 * s + 2];
+        }
+        ss += uz * a.ysin[y];
+        s1 += uz;
+    }
+    red[0][threadIdx.x] = ss;
+    red[1][threadIdx.x] = s1;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + off];
+            red[1][threadIdx.x] += red[1][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        a.track_part[2 * blockIdx.x] = red[0][0];
+        a.track_part[2 * blockIdx.x + 1] = red[1][0];
+    }
+}
+
+__global__ void __launch_bounds__(256) track_finish_kernel(DevArgs a) {
+    __shared__ double red[2][256];
+    double ss = 0.0, s1 = 0.0;
+    for (int b = threadIdx.x; b < TRACK_BLOCKS; b += 256) {
+        ss += a.track_part[2 * b];
+        s1 += a.track_part[2 * b + 1];
+    }
+    red[0][threadIdx.x] = ss;
+    red[1][threadIdx.x] = s1;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + off];
+            red[1][threadIdx.x] += red[1][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int n = *a.track_n;
+        if (n < a.track_cap) {
+            a.track[2 * n] = red[0][0];
+            a.track[2 * n + 1] = red[1][0];
+        }
+        *a.track_n = n + 1;
+    }
+}
+
+hipError_t launch_track(const DevArgs& a, hipStream_t st) {
+    if (!a.track) return hipSuccess;
+    CGB_DISPATCH(track_kernel, dim3(TRACK_BLOCKS), dim3(256), a);
+    hipLaunchKernelGGL(track_finish_kernel, dim3(1), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_encode(const DevArgs& a, const double* d, hipStream_t st) {
     CGB_DISPATCH(encode_kernel, site_grid(a), dim3(256), a, d);
     return hipGetLastError();

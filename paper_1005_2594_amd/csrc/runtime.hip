@@ -19,7 +19,7 @@
 
 using namespace cgb;
 
-static const char* kKindNames[] = {"prep", "raster", "transitions", "lb", "mem_reduce", "cells", "potentials", "integrate"};
+static const char* kKindNames[] = {"prep", "raster", "transitions", "lb", "mem_reduce", "cells", "potentials", "integrate", "track"};
 
 #define FAIL(s, code, ...)                                  \
     do {                                                    \
@@ -296,6 +296,16 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
         }
         CK(hipMemcpyAsync(a.owner, own.data(), (size_t)a.ns * 4, hipMemcpyHostToDevice, s->st));
         CK(launch_usol_walls(a, s->st));
+        for (long long i = 0; i < a.ns; i++) s->n_nonwall += own[(size_t)i] != OWN_WALL ? 1.0 : 0.0;
+        {
+            std::vector<double> ys((size_t)a.ny);
+            for (int y = 0; y < a.ny; y++) ys[(size_t)y] = sin(2.0 * M_PI * y / (double)a.ny);
+            CK(dalloc(s, &a.ysin, (size_t)a.ny * 8));
+            CK(hipMemcpyAsync(a.ysin, ys.data(), (size_t)a.ny * 8, hipMemcpyHostToDevice, s->st));
+            CK(hipStreamSynchronize(s->st));  // ys is a host temporary
+        }
+        CK(dalloc(s, &a.track_part, (size_t)TRACK_BLOCKS * 2 * 8));
+        CK(dalloc(s, &a.track_n, 16));
         // cell-list geometry: bin edge >= max(cut-off, wall potential range)
         const double Lb[3] = {(double)a.nx, (double)a.ny, (double)a.nz};
         const double emin = std::max(p->r_cut, wr);
@@ -462,6 +472,7 @@ int cgb_step(cgb_sim* s, int32_t nsteps) {
         HIPCHK(s, timed(s, K_TRANS, [&] { return launch_transitions(a, s->st, true); }));
         HIPCHK(s, timed(s, K_LB, [&] { return launch_lb(a, s->lbcfg, s->st); }));
         HIPCHK(s, timed(s, K_MEM, [&] { return launch_mem_reduce(a, s->st); }));
+        if (a.track) HIPCHK(s, timed(s, K_TRACK, [&] { return launch_track(a, s->st); }));
         HIPCHK(s, timed(s, K_CELLS, [&] { return launch_cells(a, s->st); }));
         HIPCHK(s, timed(s, K_POT, [&] { return launch_potentials(a, s->st); }));
         HIPCHK(s, timed(s, K_INT, [&] { return launch_integrate(a, s->st); }));
@@ -716,6 +727,81 @@ int cgb_time_lb(cgb_sim* s, int32_t reps, double* ms_avg) {
     if (e1) (void)hipEventDestroy(e1);
     HIPCHK(s, e);
     *ms_avg = (double)ms / reps;
+    return CGB_OK;
+}
+
+// ---------------------------------------------------------------- mixture record
+int cgb_track(cgb_sim* s, int32_t cap) {
+    if (!s || cap < 0) return CGB_EINVAL;
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    DevArgs& a = s->a;
+    dfree(s, a.track);
+    a.track = nullptr;
+    a.track_cap = 0;
+    if (cap > 0) {
+        HIPCHK(s, dalloc(s, &a.track, 2 * (size_t)cap * 8));
+        a.track_cap = cap;
+    }
+    HIPCHK(s, launch_fill_i32(a.track_n, 1, 0, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return CGB_OK;
+}
+
+int cgb_get_track(cgb_sim* s, double* out, int32_t cap, int32_t* n) {
+    if (!s || !n || cap < 0 || (cap > 0 && !out)) return CGB_EINVAL;
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    const DevArgs& a = s->a;
+    int cnt = 0;
+    HIPCHK(s, hipMemcpy(&cnt, a.track_n, 4, hipMemcpyDeviceToHost));
+    const int m = std::min(std::min(cnt, a.track_cap), (int)cap);
+    *n = std::min(cnt, a.track_cap);
+    if (m > 0) {
+        HIPCHK(s, hipMemcpy(out, a.track, 2 * (size_t)m * 8, hipMemcpyDeviceToHost));
+        for (int k = 0; k < m; k++) {
+            out[2 * k] *= 2.0 / s->n_nonwall;
+            out[2 * k + 1] /= s->n_nonwall;
+        }
+    }
+    return CGB_OK;
+}
+
+int cgb_mu_rel_kolmogorov(const double* A, int32_t n, int32_t first, double f0, double rho0, int32_t ny, double* mu) {
+    if (!A || !mu || first < 0 || n - 1 <= first || ny < 3 || !(rho0 > 0)) return CGB_EINVAL;
+    const double k = 2.0 * M_PI / ny, ck = cos(k);
+    double sum = 0.0;
+    for (int t = first; t < n - 1; t++)
+        sum += (f0 * (5.0 + ck) / (6.0 * rho0) - (A[t + 1] - A[t])) / (A[t] * (1.0 - ck) / 3.0);
+    *mu = sum / (n - 1 - first);
+    return CGB_OK;
+}
+
+int cgb_mu_rel_slit(const double* ubar, int32_t n, int32_t first, double g, double tau, int32_t ny, double* mu) {
+    if (!ubar || !mu || first < 0 || n <= first || ny < 3 || !(tau > 0.5)) return CGB_EINVAL;
+    double u = 0.0;
+    for (int t = first; t < n; t++) u += ubar[t];
+    u /= (n - first);
+    const double nf = ny - 2, nu = (2.0 * tau - 1.0) / 6.0, lam = (tau - 0.5) * (tau - 0.5);
+    *mu = g * (nf * nf + 8.0 * lam - 1.0) / (12.0 * nu * u);
+    return CGB_OK;
+}
+
+int cgb_mu_rel(cgb_sim* s, int32_t first, double* mu) {
+    if (!s || !mu) return CGB_EINVAL;
+    const cgb_params& P = s->P;
+    const bool kolm = P.force_mode == 2 && !P.wall_y;
+    const bool slit = P.force_mode == 1 && P.wall_y && P.g[0] == 0.0 && P.g[1] == 0.0 && P.g[2] != 0.0;
+    if (!kolm && !slit) FAIL(s, CGB_EINVAL, "no apparent-viscosity estimator for this driving");
+    int n = 0;
+    int rc = cgb_get_track(s, nullptr, 0, &n);
+    if (rc) return rc;
+    std::vector<double> tr(2 * (size_t)std::max(n, 1));
+    rc = cgb_get_track(s, tr.data(), n, &n);
+    if (rc) return rc;
+    std::vector<double> series((size_t)std::max(n, 1));
+    for (int k = 0; k < n; k++) series[(size_t)k] = tr[2 * (size_t)k + (kolm ? 0 : 1)];
+    rc = kolm ? cgb_mu_rel_kolmogorov(series.data(), n, first, P.f0, P.rho0, P.ny, mu)
+              : cgb_mu_rel_slit(series.data(), n, first, P.g[2], P.tau, P.ny, mu);
+    if (rc) FAIL(s, rc, "too few recorded steps (%d) after step %d", n, first);
     return CGB_OK;
 }
 

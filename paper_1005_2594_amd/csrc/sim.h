@@ -11,9 +11,10 @@ struct LaunchRec {
     hipEvent_t e0, e1;
 };
 
-enum { K_PREP, K_RASTER, K_TRANS, K_LB, K_MEM, K_CELLS, K_POT, K_INT, K_NKIND };
+enum { K_PREP, K_RASTER, K_TRANS, K_LB, K_MEM, K_CELLS, K_POT, K_INT, K_TRACK, K_NKIND };
 
 struct cgb_sim {
+    double n_nonwall = 0;  // non-wall nodes (normalisation of the tracked sums)
     cgb_params P;
     cgb::DevArgs a;
     hipStream_t st = nullptr;

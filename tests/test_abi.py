@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -36,3 +37,15 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(cgb, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(ImportError):
         cgb.lib()
+
+
+def test_estimators_match_the_oracle():
+    # host-side estimator functions of the library against the oracle's
+    from oracle import oracle as O
+    from paper_1005_2594_amd import cgb
+    rng = np.random.default_rng(3)
+    A = 1e-6 * (1.0 + 0.1 * rng.random(50))
+    assert cgb.mu_rel_kolmogorov(A, 1e-6, 1.0, 64, 7) == pytest.approx(O.mu_rel_kolmogorov(A, 1e-6, 1.0, 64, 7), rel=1e-13)
+    u = 1e-4 * (1.0 + 0.1 * rng.random(50))
+    for tau in (1.0, 0.8):
+        assert cgb.mu_rel_slit(u, 1e-6, tau, 40, 9) == pytest.approx(O.mu_rel_slit(u, 1e-6, tau, 40, 9), rel=1e-13)

@@ -130,22 +130,26 @@ def test_batch_autotune_keeps_results():
             s.close()
 
 
-def test_batch_mean_velocity_and_oracle():
+def test_batch_mu_rel_and_oracle():
     chans = small_channels(n=3, seed=44)
     b, ref = make(chans)
     try:
+        b.track(8)
+        for s in ref:
+            s.track(8)
         b.capture(2)
-        b.run(4)
+        b.run(8)
+        for s in ref:
+            s.step(8)
         b.sync()
-        ub = b.mean_velocity()
-        for c, g in enumerate(b.channels):
-            pr = g.profile_z()
-            assert ub[c] == pytest.approx(pr[1:-1].mean(), rel=1e-12, abs=1e-300)
+        mu = b.mu_rel(first=2)
+        for c, s in enumerate(ref):
+            assert mu[c] == pytest.approx(s.mu_rel(first=2), rel=1e-9)
         c = 0
         o = O.Oracle(chans[c]["params"])
         o.set_particles(chans[c]["X"], chans[c]["q"])
         o.init_fluid()
-        o.step(4)
+        to = o.track(8)
         g = b.channels[c]
         fl = o.owner() == -1
         np.testing.assert_array_equal(g.owner(), o.owner())
@@ -154,6 +158,9 @@ def test_batch_mean_velocity_and_oracle():
         assert e <= 1e-11
         for name, x, y in zip(("X", "q", "V", "L"), g.particles(), o.particles()):
             assert rel_inf(x, y) <= 1e-11, name
+        mo = O.mu_rel_slit(to[:, 1], chans[c]["params"]["g"][2], 1.0, chans[c]["params"]["ny"], 2)
+        say("batch: channel 0 mu_rel", mu[0], "oracle", mo)
+        assert mu[0] == pytest.approx(mo, rel=1e-8)
     finally:
         b.close()
         for s in ref:

@@ -1,0 +1,80 @@
+"""Apparent viscosity on the GPU: the per-step mixture record against the
+oracle's (same seeded cells, every step), the estimators on it, and the
+plasma pin on the GPU alone."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+from parity_util import make_pair, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _series_err(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("precision,tol", [("p64", 1e-11), ("p32", 2e-5)])
+def test_track_kolmogorov_matches_oracle(precision, tol):
+    cfg = synth.kolmogorov(32, seed=21, hematocrit=0.3)
+    say("track kolmogorov 32^3", len(cfg["X"]), "cells", precision)
+    g, o = make_pair(cfg["params"], cfg["X"], cfg["q"], precision=precision)
+    steps = 40
+    g.track(steps + 5)
+    g.step(steps)
+    tg = g.get_track()
+    to = o.track(steps)
+    assert tg.shape == (steps, 2)
+    eA, eu = _series_err(tg[:, 0], to[:, 0]), _series_err(tg[:, 1], to[:, 1])
+    say("  A err", eA, "ubar err", eu)
+    assert eA <= tol and eu <= tol
+    mg = g.mu_rel(first=5)
+    mo = O.mu_rel_kolmogorov(to[:, 0], cfg["params"]["f0"], 1.0, 32, 5)
+    say("  mu_rel gpu", mg, "oracle", mo)
+    assert mg == pytest.approx(mo, rel=100 * tol)
+    g.close()
+
+
+def test_track_slit_matches_oracle():
+    cfg = synth.config1()
+    g, o = make_pair(cfg["params"], cfg["X"], cfg["q"], precision="p64")
+    steps = 30
+    g.track(steps)
+    g.step(steps)
+    tg = g.get_track()
+    to = o.track(steps)
+    eA, eu = _series_err(tg[:, 0], to[:, 0]), _series_err(tg[:, 1], to[:, 1])
+    say("track slit config1: A err", eA, "ubar err", eu)
+    assert eu <= 1e-11
+    mg = g.mu_rel(first=10)
+    mo = O.mu_rel_slit(to[:, 1], cfg["params"]["g"][2], 1.0, 24, 10)
+    assert mg == pytest.approx(mo, rel=1e-9)
+    g.close()
+
+
+def test_track_capacity_and_reset():
+    from paper_1005_2594_amd import Sim
+    p = synth.params(8, 16, 8, force_mode=2, f0=1e-6)
+    s = Sim(p, precision="p64")
+    s.init_fluid()
+    s.track(5)
+    s.step(8)
+    assert s.get_track().shape == (5, 2)
+    s.track(3)  # a new record starts empty
+    assert s.get_track().shape == (0, 2)
+    s.step(2)
+    assert s.get_track().shape == (2, 2)
+    s.close()
+
+
+def test_kolmogorov_plasma_is_one_on_gpu():
+    # the estimator reads exactly 1 for the particle-free fluid at tau = 1
+    from paper_1005_2594_amd import Sim
+    L, f0 = 32, 1e-6
+    s = Sim(synth.params(4, L, 4, force_mode=2, f0=f0), precision="p64")
+    s.init_fluid()
+    s.track(60)
+    s.step(60)
+    assert s.mu_rel(first=1) == pytest.approx(1.0, abs=1e-9)
+    s.close()
