@@ -830,9 +830,15 @@ static int one_step(orc_sim* s) {
         }
         double gb[3] = {0, 0, 0};
         if (P->force_on_particles) force_at(P, s->X[3 * p + 1], gb);
+        /* C14: the body force acts on the cells too; mode 2 gives them the
+         * force on the plasma they displace (rho0 times their volume), so
+         * that a cell made heavier for the stability of the explicit coupling
+         * is still driven as a neutrally buoyant one */
+        const double Md = P->force_on_particles == 2
+                              ? P->rho0 * (4.0 / 3.0) * M_PI * P->R_perp * P->R_perp * P->R_par : s->M;
         for (int a = 0; a < 3; a++) {
-            bodyf[a] += s->M * gb[a];
-            double F = s->Fh[3 * p + a] + s->Fp[3 * p + a] + s->M * gb[a];
+            bodyf[a] += Md * gb[a];
+            double F = s->Fh[3 * p + a] + s->Fp[3 * p + a] + Md * gb[a];
             s->V[3 * p + a] += F / s->M;
             s->L[3 * p + a] += s->Th[3 * p + a] + s->Tp[3 * p + a];
         }

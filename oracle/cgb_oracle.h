@@ -30,7 +30,9 @@ typedef struct orc_params {
     int32_t force_mode;  /* 0 none, 1 constant g, 2 f0*sin(2 pi y/ny) along z    */
     double g[3];
     double f0;
-    int32_t force_on_particles; /* 1: body force also acts on cells, M*f(Y)      */
+    int32_t force_on_particles; /* 1: body force also acts on cells, M*f(Y);
+                                   2: rho0*V_cell*f(Y) (driven as the displaced
+                                   plasma, whatever the inertial mass M)        */
     double R_perp, R_par;       /* half axes of the discretised ellipsoid (Sec. II) */
     double sig_perp, sig_par;   /* potential size parameters (Sec. III, Eq. 18)     */
     double sig_w;               /* wall sphere radius (Sec. III, 1/2)               */
