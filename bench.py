@@ -5,15 +5,21 @@ hematocrit 0.4 (256,337 cells with half axes (2.5, 1.0)), tau = 1.  The
 headline number is the mixed-precision path (populations stored as FP16
 scaled deviations, FP32 collision, FP64 momentum exchange and integration);
 the FP32-storage path runs beside it.  One step = every kernel of the time
-step (rasterisation, cover/uncover, fused LB + momentum exchange, cell list,
-pair and wall forces, integration).  Inputs are resident in HBM before the
-timed region.
+step (rasterisation, cover/uncover, fused LB, momentum-exchange reduction,
+cell list, pair and wall forces, integration).  Inputs are resident in HBM
+before the timed region.
+
+Also reported (in "config"): the error of the mixed and FP32 paths against
+the FP64 path on the 64^3 companion workload, the batched ensemble of 64
+uneven channels (one replayed HIP graph, autotuned LB tiles, apparent
+viscosity per channel), and the oracle on the host cores ("cpu_baseline").
 
 Prints one JSON line.  --gpus N > 1 exits: this build runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -29,14 +35,32 @@ import synth  # noqa: E402
 METRIC = "MLUPS at 256³ Ht=0.4, mixed vs FP32 at stated error; % of HBM peak"
 HBM_PEAK_GBS = 8000.0
 STORE_BYTES = {"p64": 8, "p32": 4, "pmx16": 2, "pmxbf16": 2}
+LB_SOURCE = os.path.join(ROOT, "paper_1005_2594_amd", "csrc", "lb.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lb_traffic_pmx16_256.txt")
 
 
-def lb_algorithmic_bytes(n_fluid: int, n_sites: int, prec: str) -> float:
+def lb_algorithmic_bytes(n_fluid: float, n_sites: int, prec: str) -> float:
     """Bytes one LB launch must move: for every fluid node 19 populations read
-    and written plus its density deviation written and read (for Eq. 10), and
-    one 4-byte flag word per site."""
+    and written plus its density deviation written and read (the density in
+    the moving-boundary term of Eq. 10), and one 4-byte flag word per site."""
     s = STORE_BYTES[prec]
     return n_fluid * (2 * 19 * s + 2 * s) + 4.0 * n_sites
+
+
+def measured_traffic(prec: str):
+    """HBM bytes per LB launch from the committed rocprofv3 counter summary,
+    or None when it was taken on another version of the kernel source."""
+    if prec != "pmx16" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src = hashlib.sha256(open(LB_SOURCE, "rb").read()).hexdigest()
+    if kv.get("lb_source_sha256") != src or "hbm_bytes_per_launch" not in kv:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
 
 
 def run_gpu(cfg, prec, steps, warmup, profile=True):
@@ -60,24 +84,26 @@ def run_gpu(cfg, prec, steps, warmup, profile=True):
         sim.profile(False)
     ob = sim.observables()
     nf = 0.5 * (nf0 + ob["n_fluid"])
-    out = dict(seconds=t1 - t0, n_fluid=nf, kernel_times=kt, obs=ob, sim=sim)
-    return out
+    return dict(seconds=t1 - t0, n_fluid=nf, kernel_times=kt, obs=ob, sim=sim)
 
 
-def velocity_error_64(seed=3, horizons=(100, 500)):
+def error_report_64(seed=3, horizons=(100, 250, 500)):
     """Mixed and FP32 paths against the FP64 path of the same kernels on the
     64^3 companion workload (same cell density; the FP64 path matches the
-    oracle to ~1e-14 over 250 steps in the parity runs).  Pointwise errors are
-    reported at a short horizon, before discrete events (a node changing
-    owner, a pair crossing the cut-off) happen at different steps in different
-    precisions; the mixture velocity profile u_z(y) is the long-horizon
-    measure."""
+    oracle to ~1e-14 in the parity tests).  Pointwise velocity errors are
+    taken at the first horizon, before discrete events (a node changing
+    owner, a pair crossing the cut-off) happen at different steps in
+    different precisions; the plane-averaged mixture velocity profile and
+    the apparent viscosity (Kolmogorov estimator, last half of the run) are
+    the long-horizon measures."""
     from paper_1005_2594_amd import Sim
     cfg = synth.config3_companion(seed=seed)
-    sims = {p: Sim(cfg["params"], precision=p) for p in ("p64", "p32", "pmx16")}
+    precs = ("p64", "p32", "pmx16")
+    sims = {p: Sim(cfg["params"], precision=p) for p in precs}
     for s in sims.values():
         s.set_particles(cfg["X"], cfg["q"])
         s.init_fluid()
+        s.track(horizons[-1])
     res = {p: {} for p in ("p32", "pmx16")}
     done = 0
     for t in horizons:
@@ -94,14 +120,61 @@ def velocity_error_64(seed=3, horizons=(100, 500)):
             X = sims[p].particles()[0]
             m = (own == -1) & (own64 == -1)
             pr = sims[p].profile_z()
+            d = np.sqrt(np.sum((X - X64) ** 2, axis=1))
             res[p][f"step{t}"] = dict(
                 rel_l2_u=float(np.linalg.norm(u[m] - u64[m]) / np.linalg.norm(u64[m])),
                 rel_l2_profile=float(np.linalg.norm(pr - pr64) / np.linalg.norm(pr64)),
-                pos_rms=float(np.sqrt(np.mean(np.sum((X - X64) ** 2, axis=1)))),
+                pos_rms=float(np.sqrt(np.mean(d ** 2))),
                 owner_flips=int((own != own64).sum()))
+    first = horizons[-1] // 2
+    mu = {p: sims[p].mu_rel(first=first) for p in precs}
+    for p in ("p32", "pmx16"):
+        res[p]["mu_rel"] = mu[p]
+        res[p]["mu_rel_rel_err"] = abs(mu[p] - mu["p64"]) / abs(mu["p64"])
+    res["p64_mu_rel"] = mu["p64"]
+    res["mu_rel_window"] = [first, horizons[-1] - 1]
     for s in sims.values():
         s.close()
     return res
+
+
+def batch_leg(steps=2000, seed=4, prec="pmx16"):
+    """64 uneven wall-bounded channels advanced together by one replayed HIP
+    graph with autotuned LB tiles; apparent viscosity per channel from the
+    mean mixture velocity over steps steps/2 + 1 .. steps."""
+    from paper_1005_2594_amd import Batch
+    chans = synth.config4(seed=seed)
+    t0 = time.perf_counter()
+    b = Batch([c["params"] for c in chans], precision=prec)
+    for s, c in zip(b.channels, chans):
+        s.set_particles(c["X"], c["q"])
+        s.init_fluid()
+    tiles = b.autotune(reps=5)
+    b.track(steps)
+    b.capture(2)
+    b.sync()
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    b.run(steps)
+    b.sync()
+    dt = time.perf_counter() - t0
+    mu = b.mu_rel(first=steps // 2)
+    sites = sum(c["params"]["nx"] * c["params"]["ny"] * c["params"]["nz"] for c in chans)
+    shapes = {}
+    for t in tiles:
+        k = "x".join(str(int(v)) for v in t)
+        shapes[k] = shapes.get(k, 0) + 1
+    b.close()
+    return {
+        "workload": f"{len(chans)} channels (W, W, Lz), W~U{{32..96}}, Lz~U{{64..192}}, Ht~U[0.1,0.5], "
+                    f"g~logU[1e-7,1e-5], walls y=0,W-1; populations {prec}; one graph of 2 steps replayed",
+        "channels": len(chans), "sites": sites, "cells": int(sum(len(c["X"]) for c in chans)),
+        "steps": steps, "seconds": round(dt, 3), "ms_per_step": round(dt / steps * 1e3, 4),
+        "mlups": round(sites * steps / dt / 1e6, 1), "setup_seconds": round(t_setup, 2),
+        "tiles": shapes,
+        "mu_rel": {"window": [steps // 2, steps - 1], "mean": float(np.mean(mu)), "min": float(np.min(mu)),
+                   "max": float(np.max(mu)), "per_channel": [round(float(m), 5) for m in mu]},
+    }
 
 
 def cpu_baseline(cfg, steps):
@@ -114,9 +187,22 @@ def cpu_baseline(cfg, steps):
     o.step(steps)
     dt = time.perf_counter() - t0
     ns = cfg["params"]["nx"] * cfg["params"]["ny"] * cfg["params"]["nz"]
-    return {"value": ns * steps / dt / 1e6, "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
+    return {"value": round(ns * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
             "sample": f"{steps} steps of the 256^3 Ht=0.4 workload in FP64 (all sites), set-up excluded",
-            "seconds": dt}
+            "seconds": round(dt, 2)}
+
+
+def copy_calibration(nbytes=1 << 31, reps=4):
+    """A plain device-to-device copy of known size, for scaling rocprofv3's
+    FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"# copy calibration: {reps} copies of {nbytes} bytes", flush=True)
 
 
 def main():
@@ -126,14 +212,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256, help="box edge")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--only", default=None, help="run only this precision (profiling)")
+    ap.add_argument("--copy-calibrate", action="store_true", help="also run a copy of known size (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+    if args.copy_calibrate:
+        copy_calibration()
 
     cfg = synth.config3(n=args.n)
     ns = args.n ** 3
@@ -142,7 +233,8 @@ def main():
         r = run_gpu(cfg, prec, args.steps, args.warmup)
         results[prec] = r
         print(f"# {prec}: {r['seconds'] * 1e3 / args.steps:.3f} ms/step, "
-              f"{ns * args.steps / r['seconds'] / 1e6:.0f} MLUPS, kernels {r['kernel_times']}", flush=True)
+              f"{ns * args.steps / r['seconds'] / 1e6:.0f} MLUPS, kernels "
+              f"{ {k: round(v[0] / max(v[1], 1), 4) for k, v in r['kernel_times'].items()} }", flush=True)
         r["sim"].close()
 
     head = args.only or "pmx16"
@@ -152,6 +244,7 @@ def main():
     lb_avg_s = lb_ms / max(lb_cnt, 1) / 1e3
     algo = lb_algorithmic_bytes(r["n_fluid"], ns, head)
     achieved = algo / lb_avg_s / 1e9
+    traffic = measured_traffic(head) if args.n == 256 else None
     line = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -169,12 +262,16 @@ def main():
             "workload": f"kolmogorov {args.n}^3 periodic, Ht=0.4 ({len(cfg['X'])} cells (2.5,1.0)), tau=1, "
                         f"f0=1e-6; populations stored as {head}",
             "sites": ns, "cells": len(cfg["X"]), "precision": head,
+            "fluid_sites": round(r["n_fluid"]),
+            "fluid_mlups": round(r["n_fluid"] * args.steps / r["seconds"] / 1e6, 1),
             "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in r["kernel_times"].items()},
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "lb_kernel", "algorithmic_bytes_per_launch": algo,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic / lb_avg_s / 1e9, 1),
+            "kernel": "lb_kernel_tau1", "algorithmic_bytes_per_launch": algo,
+            "hbm_bytes_per_launch": traffic,
             "avg_launch_ms": round(lb_avg_s * 1e3, 5),
         },
     }
@@ -186,7 +283,9 @@ def main():
         line["config"]["p32_lb_frac"] = round(lb_algorithmic_bytes(r32["n_fluid"], ns, "p32") /
                                               (l32 / max(c32, 1) / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     if not args.no_error:
-        line["config"]["error_vs_p64_64cube"] = velocity_error_64()
+        line["config"]["error_vs_p64_64cube"] = error_report_64()
+    if not args.no_batch:
+        line["config"]["batch"] = batch_leg(steps=args.batch_steps)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
     print(json.dumps(line), flush=True)

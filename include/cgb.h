@@ -54,7 +54,10 @@ typedef struct cgb_params {
     int32_t force_mode;   /* 0 none, 1 constant g, 2 f0 sin(2 pi y/ny) e_z    */
     double g[3];
     double f0;
-    int32_t force_on_particles; /* 1: cells feel M f(Y) too                  */
+    int32_t force_on_particles; /* 0: body force on the plasma only; 1: cells
+                                   feel M f(Y) too; 2: cells feel rho0 V f(Y),
+                                   V their volume (driven as the plasma they
+                                   displace, whatever their inertial mass)   */
     double R_perp, R_par;       /* discretised ellipsoid half axes (Sec. II)  */
     double sig_perp, sig_par;   /* potential size parameters (Eq. 18)         */
     double sig_w;               /* wall sphere radius (Sec. III)              */

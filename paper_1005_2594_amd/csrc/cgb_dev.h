@@ -77,6 +77,7 @@ struct DevArgs {
     double* FTh;    // n*6 hydrodynamic force, torque (accumulated)
     double* FTp;    // n*6 potential force, torque
     double M, Ipar, Iperp;
+    double Mdrive;   // mass the body force acts on: M, or rho0 times the cell volume
     double iRpar2, iRperp2, Rb;
     // transitions
     int* trans;     // 3 ints per transition: site, old, new
@@ -107,9 +108,10 @@ struct DevArgs {
     void* usol;        // [pstride][4]: velocity (x, y, z, -) of every non-fluid
                        // node: the rigid-body velocity of its cell at the node,
                        // or the wall velocity
-    void* mlink;       // [18][pstride]: plane r-1 at a non-fluid node s holds
+    void* mlink;       // [pstride][18]: entry r-1 of a non-fluid node s holds
                        // the momentum, along c_r, that the link to the fluid
-                       // node s + c_r transferred this step
+                       // node s + c_r transferred this step (the 18 entries
+                       // of a node are contiguous for the per-cell sums)
     void* crec;        // [n] CellRec, in cell-list order (per-cell kernels)
     // per-step record of the mixture velocity (apparent viscosity)
     double* track;      // [track_cap][2]: sums of u_z sin(2 pi y/ny) and of u_z
@@ -300,7 +302,7 @@ struct LaunchCfg {
 };
 hipError_t launch_lb(const DevArgs& a, LaunchCfg cfg, hipStream_t st);
 hipError_t launch_mem_reduce(const DevArgs& a, hipStream_t st);
-hipError_t launch_usol_walls(const DevArgs& a, hipStream_t st);
+hipError_t launch_usol(const DevArgs& a, hipStream_t st);
 hipError_t launch_prep(const DevArgs& a, hipStream_t st);
 hipError_t launch_kin(const DevArgs& a, hipStream_t st);
 hipError_t launch_clear_cells(const DevArgs& a, hipStream_t st);

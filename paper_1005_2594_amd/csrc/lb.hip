@@ -16,7 +16,7 @@
 // Momentum exchange (Eq. 12): every link transfers (2 n*_rbar + C_r) c_rbar
 // to the body behind it.  The kernel stores the part that depends on the
 // deviations d = n* - w rho0, m_r = -(2 d_rbar + C_r) (momentum m_r c_r), at
-// the source node, mlink[r][s]; the link (s, r) is unique, so no two threads
+// the source node, mlink[s][r-1]; the link (s, r) is unique, so no two threads
 // write one entry, and a per-cell kernel sums the entries of the cell's
 // nodes.  The constant part 2 w rho0 c_rbar, together with the link forces of
 // Eqs. 13-14 between cells and from walls, sums to exactly zero over the
@@ -105,7 +105,17 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
         if (z >= a.nz) break;
         const unsigned i = (unsigned)x + nx * (unsigned)y + plane * (unsigned)z;
         const uint32_t f = inb ? a.flags[i] : NONFLUID;
-        if (f & NONFLUID) continue;
+        if (f & NONFLUID) {
+            // write the node too, so that every line of B is written whole
+            // (no read-modify-write of partly written lines); the values of
+            // non-fluid nodes are never read
+            if (inb) {
+#pragma unroll
+                for (int r = 0; r < 19; r++) bstore<T>(Cd::enc((R)0, (R)1), rB, ES * ((unsigned)r * ps + i));
+                bstore<T>(Cd::enc((R)0, (R)1), rRB, ES * i);
+            }
+            continue;
+        }
         const int oz[3] = {z == a.nz - 1 ? -(int)((a.nz - 1) * plane) : (int)plane, 0,
                            z == 0 ? (int)((a.nz - 1) * plane) : -(int)plane};
         auto src = [&](int r) { return i + (unsigned)(ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1]); };
@@ -131,7 +141,7 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
             for (int r = 1; r < 19; r++) {
                 const bool lk = (links >> r) & 1u;
                 const M C = (M)(6.0 * WD(r)) * rho_x * link_cu<M>(lv, r);
-                bstore<M>(-((M)2 * (M)d[r] + C), rM, lk ? (unsigned)sizeof(M) * ((unsigned)(r - 1) * ps + src(r)) : OOB);
+                bstore<M>(-((M)2 * (M)d[r] + C), rM, lk ? (unsigned)sizeof(M) * (18u * src(r) + (unsigned)(r - 1)) : OOB);
                 d[r] += (R)C;
             }
         }
@@ -211,7 +221,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
         const unsigned i = (unsigned)x + nx * (unsigned)y + plane * (unsigned)z;
         const uint32_t f = fnext;
         fnext = (inb && zz + 1 < TZ && z + 1 < a.nz) ? bload<uint32_t>(rFl, 4u * (i + plane)) : NONFLUID;
-        if (f & NONFLUID) continue;
+        if (f & NONFLUID) {
+            // write the node too, so that every line of B is written whole
+            // (no read-modify-write of partly written lines); the values of
+            // non-fluid nodes are never read
+            if (inb) {
+#pragma unroll
+                for (int r = 0; r < 19; r++) bstore<T>(Cd::enc((R)0, (R)1), rB, ES * ((unsigned)r * ps + i));
+                bstore<T>(Cd::enc((R)0, (R)1), rRB, ES * i);
+            }
+            continue;
+        }
         const int oz[3] = {z == a.nz - 1 ? -(int)((a.nz - 1) * plane) : (int)plane, 0,
                            z == 0 ? (int)((a.nz - 1) * plane) : -(int)plane};
         auto src = [&](int r) { return i + (unsigned)(ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1]); };
@@ -252,7 +272,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
                 if (CY(r)) c2 += CY(r) * C;
                 if (CZ(r)) c3 += CZ(r) * C;
                 const M dv = (M)Cd::dec(v[r], dec_scale<P>(a, r));
-                bstore<M>(-((M)2 * dv + C), rM, lk ? (unsigned)sizeof(M) * ((unsigned)(r - 1) * ps + src(r)) : OOB);
+                bstore<M>(-((M)2 * dv + C), rM, lk ? (unsigned)sizeof(M) * (18u * src(r) + (unsigned)(r - 1)) : OOB);
             }
             drho += (R)c0; jx += (R)c1; jy += (R)c2; jz += (R)c3;
         }

@@ -150,30 +150,6 @@ hipError_t launch_cellrec(const DevArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-// rigid-body velocity V + Omega x (s - X) of cell p at node s, in the link
-// type of the storage mode (the moving-boundary term of Eq. 10 and the link
-// momenta use it)
-__device__ inline void store_usol(const DevArgs& a, long long s, int x, int y, int z, int p, const CellRec& cr) {
-    double X[3], V[3], W[3];
-    if (p == cr.p) {
-        for (int c = 0; c < 3; c++) { X[c] = cr.X[c]; V[c] = cr.V[c]; W[c] = cr.W[c]; }
-    } else {
-        const double* k = a.kin + 12 * (long long)p;
-        for (int c = 0; c < 3; c++) { X[c] = k[c]; V[c] = k[3 + c]; W[c] = k[6 + c]; }
-    }
-    double d[3], u[3];
-    node_disp(a, x, y, z, X, d);
-    cross3(W, d, u);
-    for (int c = 0; c < 3; c++) u[c] += V[c];
-    if (a.precision == CGB_P64) {
-        double* U = (double*)a.usol + 4 * s;
-        U[0] = u[0]; U[1] = u[1]; U[2] = u[2];
-    } else {
-        float* U = (float*)a.usol + 4 * s;
-        U[0] = (float)u[0]; U[1] = (float)u[1]; U[2] = (float)u[2];
-    }
-}
-
 // one wave per cell, CPW cells (waves) per workgroup: lane (ix, iy) of an
 // 8 x 8 footprint walks z in slabs of ZB nodes whose loads are issued
 // together.  The waves of a workgroup work independently.
@@ -227,9 +203,6 @@ __global__ void __launch_bounds__(64 * CPW) raster_kernel(DevArgs a) {
                         const bool keep = (o == p) && covers(a, cr, x, y, z);
                         nw = keep ? p : (c != NO_CAND ? c : OWN_FLUID);
                         if (c != NO_CAND) a.cand[s] = NO_CAND;
-                        // every node that is a cell node after this step is decided
-                        // by exactly one pass: store the rigid-body velocity of its cell
-                        if (nw >= 0) store_usol(a, s, x, y, z, nw, cr);
                     }
                     // transitions: one list reservation per wave and slab
                     const bool tr = nw != o;
@@ -269,7 +242,7 @@ static inline unsigned cell_grid(int n) { return (unsigned)((n + CPW - 1) / CPW)
 // ------------------------------------------------------------------ momentum exchange
 // Force and torque on each cell from the link momenta the LB kernel stored
 // at the cell's nodes (Eq. 12): F = sum over the cell's nodes s and the
-// directions r with a fluid node at s + c_r of mlink[r][s] c_r, and
+// directions r with a fluid node at s + c_r of mlink[s][r-1] c_r, and
 // T = sum (s - X) x (same); the lever point may be any point of the link
 // line (the transferred momentum is parallel to c_r) and s is one.
 // One wave per cell: lanes cover an 8 x 8 patch of the cell's box and sweep
@@ -347,7 +320,7 @@ __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
                         for (int r = 1; r < 19; r++) {
                             // fluid at s + c_r: bit OPP(r) of s's flags (source s - c_OPP(r)) is clear
                             const bool lk = !((f >> OPP(r)) & 1u);
-                            mv[r] = bload<M>(rM, lk ? (unsigned)sizeof(M) * ((unsigned)(r - 1) * ps + s) : 0xfffffff0u);
+                            mv[r] = bload<M>(rM, lk ? (unsigned)sizeof(M) * (18u * s + (unsigned)(r - 1)) : 0xfffffff0u);
                         }
                         M m0 = 0, m1 = 0, m2 = 0;
 #pragma unroll
@@ -384,15 +357,25 @@ hipError_t launch_mem_reduce(const DevArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-// wall nodes carry their plane velocity (Eq. 10; zero for resting walls),
-// every other node starts at rest
+// Boundary velocity of every node, written for all nodes so that every line
+// is written whole: a cell node gets the rigid-body velocity of its cell,
+// V + Omega x (s - X) (the moving-boundary term of Eq. 10 and the link
+// momenta use it), a wall node its plane velocity (zero for resting walls),
+// a fluid node zero.  Runs after the occupancy update of the step.
 template <class M>
-__global__ void usol_walls_kernel(DevArgs a) {
+__global__ void usol_kernel(DevArgs a) {
     const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (s >= a.ns) return;
-    const int y = (int)((s / a.nx) % a.ny);
+    const int o = a.owner[s];
+    const int x = (int)(s % a.nx), y = (int)((s / a.nx) % a.ny), z = (int)(s / ((long long)a.nx * a.ny));
     double u[3] = {0, 0, 0};
-    if (a.owner[s] == OWN_WALL && a.wall_y) {
+    if (o >= 0) {
+        const double* k = a.kin + 12 * (long long)o;
+        double d[3];
+        node_disp(a, x, y, z, k, d);
+        cross3(k + 6, d, u);
+        for (int c = 0; c < 3; c++) u[c] += k[3 + c];
+    } else if (o == OWN_WALL && a.wall_y) {
         if (y == 0) { u[0] = a.wvb[0]; u[1] = a.wvb[1]; u[2] = a.wvb[2]; }
         else if (y == a.ny - 1) { u[0] = a.wvt[0]; u[1] = a.wvt[1]; u[2] = a.wvt[2]; }
     }
@@ -400,10 +383,10 @@ __global__ void usol_walls_kernel(DevArgs a) {
     U[0] = (M)u[0]; U[1] = (M)u[1]; U[2] = (M)u[2]; U[3] = (M)0;
 }
 
-hipError_t launch_usol_walls(const DevArgs& a, hipStream_t st) {
+hipError_t launch_usol(const DevArgs& a, hipStream_t st) {
     const dim3 g((unsigned)((a.ns + 255) / 256)), b(256);
-    if (a.precision == CGB_P64) hipLaunchKernelGGL(usol_walls_kernel<double>, g, b, 0, st, a);
-    else hipLaunchKernelGGL(usol_walls_kernel<float>, g, b, 0, st, a);
+    if (a.precision == CGB_P64) hipLaunchKernelGGL(usol_kernel<double>, g, b, 0, st, a);
+    else hipLaunchKernelGGL(usol_kernel<float>, g, b, 0, st, a);
     return hipGetLastError();
 }
 
@@ -883,7 +866,7 @@ __device__ void integrate_one(const DevArgs& a, int p, double* bf) {
     bool bad = false;
     double Lnew[3], Vn[3];
     for (int c = 0; c < 3; c++) {
-        const double F = a.FTh[6 * p + c] + a.FTp[6 * p + c] + a.M * gb[c];
+        const double F = a.FTh[6 * p + c] + a.FTp[6 * p + c] + a.Mdrive * gb[c];
         Vn[c] = a.V[3 * p + c] + F / a.M;
         Lnew[c] = a.L[3 * p + c] + (a.FTh[6 * p + 3 + c] + a.FTp[6 * p + 3 + c]);
         if (!(fabs(Vn[c]) < 0.5) || !(fabs(Lnew[c]) < 1e30)) bad = true;
@@ -905,7 +888,7 @@ __device__ void integrate_one(const DevArgs& a, int p, double* bf) {
         }
         a.X[3 * p + c] = xn;
     }
-    bf[0] = a.M * gb[0]; bf[1] = a.M * gb[1]; bf[2] = a.M * gb[2];
+    bf[0] = a.Mdrive * gb[0]; bf[1] = a.Mdrive * gb[1]; bf[2] = a.Mdrive * gb[2];
     // quaternion: half-step predictor, then full step with the midpoint rate
     double q[4] = {a.q[4 * p], a.q[4 * p + 1], a.q[4 * p + 2], a.q[4 * p + 3]};
     double o[3], w[3], dq[4], qh[4], qn[4];

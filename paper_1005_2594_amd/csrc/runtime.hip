@@ -219,6 +219,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
     if (!p || !out) return CGB_EINVAL;
     *out = nullptr;
     if (p->nx < 3 || p->ny < 3 || p->nz < 3 || !(p->tau > 0.5) || !(p->rho0 > 0) || p->precision < 0 ||
+        p->force_on_particles < 0 || p->force_on_particles > 2 ||
         p->precision > CGB_PMXBF16 || !(p->R_perp > 0) || !(p->R_par > 0) || !(p->rho_p > 0) || !(p->r_cut > 0))
         return CGB_EINVAL;
     {
@@ -246,6 +247,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
     a.pmx_scale = (float)s->P.pmx_scale;
     a.pmx_inv = (float)(1.0 / s->P.pmx_scale);
     a.M = p->rho_p * (4.0 / 3.0) * M_PI * p->R_perp * p->R_perp * p->R_par;
+    a.Mdrive = p->force_on_particles == 2 ? p->rho0 * (4.0 / 3.0) * M_PI * p->R_perp * p->R_perp * p->R_par : a.M;
     a.Ipar = 0.4 * a.M * p->R_perp * p->R_perp;
     a.Iperp = 0.2 * a.M * (p->R_perp * p->R_perp + p->R_par * p->R_par);
     a.iRpar2 = 1.0 / (p->R_par * p->R_par);
@@ -295,7 +297,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
             if (w) own[(size_t)i] = OWN_WALL;
         }
         CK(hipMemcpyAsync(a.owner, own.data(), (size_t)a.ns * 4, hipMemcpyHostToDevice, s->st));
-        CK(launch_usol_walls(a, s->st));
+        CK(launch_usol(a, s->st));
         for (long long i = 0; i < a.ns; i++) s->n_nonwall += own[(size_t)i] != OWN_WALL ? 1.0 : 0.0;
         {
             std::vector<double> ys((size_t)a.ny);
@@ -426,6 +428,7 @@ int cgb_set_particles(cgb_sim* s, int32_t n, const double* X, const double* q, c
     HIPCHK(s, launch_cells(a, s->st));  // the per-cell kernels walk the cells in cell-list order
     HIPCHK(s, launch_raster(a, s->st, true));
     HIPCHK(s, launch_transitions(a, s->st, false));
+    HIPCHK(s, launch_usol(a, s->st));
     HIPCHK(s, launch_flags_rebuild(a, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     return check_status(s);
@@ -469,7 +472,10 @@ int cgb_step(cgb_sim* s, int32_t nsteps) {
         bind_buffers(s);
         HIPCHK(s, timed(s, K_PREP, [&] { return launch_prep(a, s->st); }));
         HIPCHK(s, timed(s, K_RASTER, [&] { return launch_raster(a, s->st, false); }));
-        HIPCHK(s, timed(s, K_TRANS, [&] { return launch_transitions(a, s->st, true); }));
+        HIPCHK(s, timed(s, K_TRANS, [&] {
+            hipError_t e = launch_transitions(a, s->st, true);
+            return e == hipSuccess ? launch_usol(a, s->st) : e;
+        }));
         HIPCHK(s, timed(s, K_LB, [&] { return launch_lb(a, s->lbcfg, s->st); }));
         HIPCHK(s, timed(s, K_MEM, [&] { return launch_mem_reduce(a, s->st); }));
         if (a.track) HIPCHK(s, timed(s, K_TRACK, [&] { return launch_track(a, s->st); }));

@@ -15,7 +15,14 @@ arXiv:1005.2594) converted to lattice units, or the workload's own:
   its broadside added mass (8/3 a^3 ~ 42) exceeds its mass (26).  The
   channel with 20 cells runs at rho_p = 2 (the smallest stable value tried,
   closest to "equal to the fluid"); dense random suspensions need
-  rho_p >= 12 for 500 steps, so they use rho_p = 16.
+  rho_p >= 12 for 500 steps and more for 2000 steps in narrow channels
+  (rho_p = 16 grows a gap mode among crowded cells within ~1000 steps in a
+  47-wide channel at Ht = 0.41, in the oracle as on the device), so they
+  use rho_p = 64.
+* body force on cells: force_on_particles = 2, i.e. rho0 times the cell
+  volume times f(Y) -- the force on the plasma the cell displaces -- so that
+  the heavier inertial mass does not also make the cells driven harder than
+  neutrally buoyant ones.
 
 Random cells: positions uniform in the box, orientations uniform on SO(3)
 (normalised 4-D Gaussian quaternions), fluid at rest.
@@ -29,7 +36,7 @@ import numpy as np
 EPS_LU = 0.05          # 1.47e-15 J in lattice units
 SIGMA_OVER_R = 12.0 / 11.0
 RHO_P_DILUTE = 2.0
-RHO_P_DENSE = 16.0
+RHO_P_DENSE = 64.0
 
 
 def params(nx, ny, nz, **kw) -> dict:
@@ -102,7 +109,7 @@ def config1(seed=1):
     """24x24x48 wall-bounded channel, 20 cells (2.5, 1.0), g = 1e-6 z, FP64,
     100 steps.  Non-overlapping placement: bounding spheres of radius
     sigma_perp kept apart, and clear of the wall planes by sigma_perp+sigma_w."""
-    p = params(24, 24, 48, wall_y=1, force_mode=1, g=(0.0, 0.0, 1e-6), rho_p=RHO_P_DILUTE)
+    p = params(24, 24, 48, wall_y=1, force_mode=1, g=(0.0, 0.0, 1e-6), rho_p=RHO_P_DILUTE, force_on_particles=2)
     rng = np.random.default_rng(seed)
     clear = p["sig_perp"] + p["sig_w"]
     X = rsa_positions(rng, 20, (24, 24, 48), 2.0 * p["sig_perp"], y_range=(clear, 23.0 - clear),
@@ -113,7 +120,7 @@ def config1(seed=1):
 
 def kolmogorov(n, seed, hematocrit=0.4, f0=1e-6, steps=500, precision="p32"):
     """n^3 periodic box, f_z = f0 sin(2 pi y / n), random overlapping cells."""
-    p = params(n, n, n, force_mode=2, f0=f0, rho_p=RHO_P_DENSE)
+    p = params(n, n, n, force_mode=2, f0=f0, rho_p=RHO_P_DENSE, force_on_particles=2)
     N = cell_count(hematocrit, n ** 3, p["R_perp"], p["R_par"])
     rng = np.random.default_rng(seed)
     X = uniform_positions(rng, N, (n, n, n))
@@ -145,7 +152,7 @@ def config4(seed=4, n_channels=64, w_range=(32, 96), lz_range=(64, 192)):
         Lz = int(rng.integers(lz_range[0], lz_range[1] + 1))
         Ht = float(rng.uniform(0.1, 0.5))
         g = float(10.0 ** rng.uniform(-7.0, -5.0))
-        p = params(W, W, Lz, wall_y=1, force_mode=1, g=(0.0, 0.0, g), rho_p=RHO_P_DENSE)
+        p = params(W, W, Lz, wall_y=1, force_mode=1, g=(0.0, 0.0, g), rho_p=RHO_P_DENSE, force_on_particles=2)
         n_fluid = W * (W - 2) * Lz
         N = cell_count(Ht, n_fluid, p["R_perp"], p["R_par"])
         clear = p["R_perp"]
