@@ -108,10 +108,6 @@ struct DevArgs {
     void* usol;        // [pstride][4]: velocity (x, y, z, -) of every non-fluid
                        // node: the rigid-body velocity of its cell at the node,
                        // or the wall velocity
-    void* mlink;       // [pstride][18]: entry r-1 of a non-fluid node s holds
-                       // the momentum, along c_r, that the link to the fluid
-                       // node s + c_r transferred this step (the 18 entries
-                       // of a node are contiguous for the per-cell sums)
     void* crec;        // [n] CellRec, in cell-list order (per-cell kernels)
     // per-step record of the mixture velocity (apparent viscosity)
     double* track;      // [track_cap][2]: sums of u_z sin(2 pi y/ny) and of u_z

@@ -1,5 +1,4 @@
-// lb.hip -- fused pull stream + bounce-back + BGK collision, with the link
-// momenta of the momentum exchange.
+// lb.hip -- fused pull stream + moving bounce-back + BGK collision.
 //
 // For a fluid node x and each direction r the pulled population is
 // n*_r(x - c_r) when the source is fluid (Eq. 2).  When the source
@@ -10,19 +9,13 @@
 // cell, v_b = V + Omega x (x - c_r/2 - X) at the link midpoint; because
 // c_r . (Omega x c_r) = 0, c_r . v_b equals c_r . u(s) with
 // u(s) = V + Omega x (s - X), the rigid-body velocity at the source node.
-// The rasteriser stores u(s) for every cell node and walls hold their plane
-// velocity, so a link needs no knowledge of which body is behind it.
+// A node-parallel kernel stores u(s) for every cell node after the
+// occupancy update and walls hold their plane velocity, so a link needs no
+// knowledge of which body is behind it.
 //
-// Momentum exchange (Eq. 12): every link transfers (2 n*_rbar + C_r) c_rbar
-// to the body behind it.  The kernel stores the part that depends on the
-// deviations d = n* - w rho0, m_r = -(2 d_rbar + C_r) (momentum m_r c_r), at
-// the source node, mlink[s][r-1]; the link (s, r) is unique, so no two threads
-// write one entry, and a per-cell kernel sums the entries of the cell's
-// nodes.  The constant part 2 w rho0 c_rbar, together with the link forces of
-// Eqs. 13-14 between cells and from walls, sums to exactly zero over the
-// closed surface of a cell's node set (the sums of w c and of (x - X) x w c
-// over the outward links of any node set vanish), so the deviation part is
-// the whole force.
+// Momentum exchange (Eq. 12) is summed per cell by a separate kernel from
+// the same stored populations and boundary velocities (the bounced
+// populations are the node's own, unchanged by this kernel).
 //
 // Collision: Eqs. 1, 4, 5 with the Guo forcing term, u = (sum n c + g/2)/rho.
 // Work decomposition: a workgroup of BX x BY threads covers a patch of an x-y
@@ -88,7 +81,6 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
     const auto rRA = make_rsrc(a.rhoA, (unsigned long long)ps * ES);
     const auto rRB = make_rsrc(a.rhoB, (unsigned long long)ps * ES);
     const auto rU = make_rsrc(a.usol, 4ull * ps * sizeof(M));
-    const auto rM = make_rsrc(a.mlink, 18ull * ps * sizeof(M));
     // offset from x to the pull source x - c along each axis (periodic wrap);
     // index 0: c = -1, 1: c = 0, 2: c = +1
     const int ox[3] = {x == a.nx - 1 ? -(a.nx - 1) : 1, 0, x == 0 ? a.nx - 1 : -1};
@@ -138,12 +130,7 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
         if (links) {
             const M rho_x = (M)a.rho0 + (M)Cd::dec(rstored, rho_dec_scale<P>(a));
 #pragma unroll
-            for (int r = 1; r < 19; r++) {
-                const bool lk = (links >> r) & 1u;
-                const M C = (M)(6.0 * WD(r)) * rho_x * link_cu<M>(lv, r);
-                bstore<M>(-((M)2 * (M)d[r] + C), rM, lk ? (unsigned)sizeof(M) * (18u * src(r) + (unsigned)(r - 1)) : OOB);
-                d[r] += (R)C;
-            }
+            for (int r = 1; r < 19; r++) d[r] += (R)((M)(6.0 * WD(r)) * rho_x * link_cu<M>(lv, r));
         }
 
         // BGK collision with Guo forcing
@@ -205,7 +192,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
     const auto rRB = make_rsrc(a.rhoB, (unsigned long long)ps * ES);
     const auto rFl = make_rsrc(a.flags, (unsigned long long)a.ns * 4);
     const auto rU = make_rsrc(a.usol, 4ull * ps * sizeof(M));
-    const auto rM = make_rsrc(a.mlink, 18ull * ps * sizeof(M));
     const int ox[3] = {x == a.nx - 1 ? -(a.nx - 1) : 1, 0, x == 0 ? a.nx - 1 : -1};
     const int oy[3] = {y == a.ny - 1 ? -(int)((a.ny - 1) * nx) : (int)nx, 0, y == 0 ? (int)((a.ny - 1) * nx) : -(int)nx};
     double gyd[3];
@@ -260,19 +246,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
         }
         if (links) {
             // moving-boundary corrections (zero for resting walls and for the
-            // directions that are not links) and the link momenta
+            // directions that are not links)
             const M rho_x = (M)a.rho0 + (M)Cd::dec(rstored, rho_dec_scale<P>(a));
             M c0 = 0, c1 = 0, c2 = 0, c3 = 0;
 #pragma unroll
             for (int r = 1; r < 19; r++) {
-                const bool lk = (links >> r) & 1u;
                 const M C = (M)(6.0 * WD(r)) * rho_x * link_cu<M>(lv, r);
                 c0 += C;
                 if (CX(r)) c1 += CX(r) * C;
                 if (CY(r)) c2 += CY(r) * C;
                 if (CZ(r)) c3 += CZ(r) * C;
-                const M dv = (M)Cd::dec(v[r], dec_scale<P>(a, r));
-                bstore<M>(-((M)2 * dv + C), rM, lk ? (unsigned)sizeof(M) * (18u * src(r) + (unsigned)(r - 1)) : OOB);
             }
             drho += (R)c0; jx += (R)c1; jy += (R)c2; jz += (R)c3;
         }

@@ -240,14 +240,20 @@ __global__ void __launch_bounds__(64 * CPW) raster_kernel(DevArgs a) {
 static inline unsigned cell_grid(int n) { return (unsigned)((n + CPW - 1) / CPW); }
 
 // ------------------------------------------------------------------ momentum exchange
-// Force and torque on each cell from the link momenta the LB kernel stored
-// at the cell's nodes (Eq. 12): F = sum over the cell's nodes s and the
-// directions r with a fluid node at s + c_r of mlink[s][r-1] c_r, and
-// T = sum (s - X) x (same); the lever point may be any point of the link
-// line (the transferred momentum is parallel to c_r) and s is one.
+// Force and torque on each cell from its links (Eq. 12).  A link joins a
+// node s of the cell to a fluid node x = s + c_r; the LB kernel bounced the
+// fluid node's own population n*_rbar(x) into direction r and added
+// C_r = 6 w_r rho(x) (c_r . u(s)), u(s) = V + Omega x (s - X) (Eq. 10), so
+// the link carried (2 n*_rbar(x) + C_r) c_rbar to the cell.  Only the part
+// that depends on the deviations d = n* - w rho0 is summed: the constant part
+// 2 w rho0 c_rbar, together with the link forces of Eqs. 13-14 between cells
+// and from walls, sums to zero over the closed surface of the cell's node
+// set (the sums of w c and (s - X) x w c over the outward links of any node
+// set vanish).  Torque: the transferred momentum is parallel to c_r, so any
+// point of the link line is a lever point; s is used.
 // One wave per cell: lanes cover an 8 x 8 patch of the cell's box and sweep
 // z; the cell's nodes are compacted in lane order (deterministic) and then
-// processed 64 at a time with the 18 loads of a node issued together.
+// processed 64 at a time with the loads of a node's 18 links issued together.
 constexpr int MR_CAP = 64 * ZB;
 
 // wave-local ordering of LDS accesses (the waves of a workgroup do not meet)
@@ -257,13 +263,18 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <class M>
+template <int P>
 __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
+    using Cd = Codec<P>;
+    using T = typename Cd::T;
+    using R = typename Cd::R;
+    constexpr unsigned ES = sizeof(T);
     __shared__ unsigned lst_sa[CPW][MR_CAP];
     __shared__ uint32_t lst_fa[CPW][MR_CAP];
     const unsigned ps = (unsigned)a.pstride;
     const unsigned nx = (unsigned)a.nx, plane = (unsigned)a.nx * (unsigned)a.ny;
-    const auto rM = make_rsrc(a.mlink, 18ull * ps * sizeof(M));
+    const auto rA = make_rsrc(a.A, 19ull * ps * ES);
+    const auto rRA = make_rsrc(a.rhoA, (unsigned long long)ps * ES);
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     unsigned* lst_s = lst_sa[wv];
@@ -315,23 +326,44 @@ __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
                     if (e < cnt) {
                         const unsigned s = lst_s[e];
                         const uint32_t f = lst_f[e];
-                        M mv[19];
+                        const int sx = (int)(s % nx), sy = (int)((s / nx) % (unsigned)a.ny), sz = (int)(s / plane);
+                        // the bounced population and the density of the fluid node
+                        // x = s + c_r of every link
+                        const int ox[3] = {sx == a.nx - 1 ? -(a.nx - 1) : 1, 0, sx == 0 ? a.nx - 1 : -1};
+                        const int oy[3] = {sy == a.ny - 1 ? -(int)((a.ny - 1) * nx) : (int)nx, 0,
+                                           sy == 0 ? (int)((a.ny - 1) * nx) : -(int)nx};
+                        const int oz[3] = {sz == a.nz - 1 ? -(int)((a.nz - 1) * plane) : (int)plane, 0,
+                                           sz == 0 ? (int)((a.nz - 1) * plane) : -(int)plane};
+                        T dv[19], rv[19];
 #pragma unroll
                         for (int r = 1; r < 19; r++) {
                             // fluid at s + c_r: bit OPP(r) of s's flags (source s - c_OPP(r)) is clear
                             const bool lk = !((f >> OPP(r)) & 1u);
-                            mv[r] = bload<M>(rM, lk ? (unsigned)sizeof(M) * (18u * s + (unsigned)(r - 1)) : 0xfffffff0u);
+                            // offsets index c = +1 at 0 and c = -1 at 2: x = s + c_r
+                            const unsigned xi = s + (unsigned)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)]);
+                            dv[r] = bload<T>(rA, lk ? ES * ((unsigned)OPP(r) * ps + xi) : 0xfffffff0u);
+                            rv[r] = bload<T>(rRA, lk ? ES * xi : 0xfffffff0u);
                         }
-                        M m0 = 0, m1 = 0, m2 = 0;
-#pragma unroll
-                        for (int r = 1; r < 19; r++) {
-                            if (CX(r)) m0 += CX(r) * mv[r];
-                            if (CY(r)) m1 += CY(r) * mv[r];
-                            if (CZ(r)) m2 += CZ(r) * mv[r];
-                        }
-                        const int sx = (int)(s % nx), sy = (int)((s / nx) % (unsigned)a.ny), sz = (int)(s / plane);
                         double d[3];
                         node_disp(a, sx, sy, sz, cr.X, d);
+                        double ud[3];
+                        cross3(cr.W, d, ud);
+                        const R u0 = (R)(ud[0] + cr.V[0]), u1 = (R)(ud[1] + cr.V[1]), u2 = (R)(ud[2] + cr.V[2]);
+                        R m0 = 0, m1 = 0, m2 = 0;
+#pragma unroll
+                        for (int r = 1; r < 19; r++) {
+                            const bool lk = !((f >> OPP(r)) & 1u);
+                            const R rho_x = (R)a.rho0 + Cd::dec(rv[r], rho_dec_scale<P>(a));
+                            R cu = 0;
+                            if (CX(r)) cu += (R)CX(r) * u0;
+                            if (CY(r)) cu += (R)CY(r) * u1;
+                            if (CZ(r)) cu += (R)CZ(r) * u2;
+                            const R C = (R)(6.0 * WD(r)) * rho_x * cu;
+                            const R m = lk ? -((R)2 * Cd::dec(dv[r], dec_scale<P>(a, OPP(r))) + C) : (R)0;
+                            if (CX(r)) m0 += CX(r) * m;
+                            if (CY(r)) m1 += CY(r) * m;
+                            if (CZ(r)) m2 += CZ(r) * m;
+                        }
                         const double g0 = (double)m0, g1 = (double)m1, g2 = (double)m2;
                         F0 += g0; F1 += g1; F2 += g2;
                         T0 += d[1] * g2 - d[2] * g1;
@@ -352,15 +384,20 @@ __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
 
 hipError_t launch_mem_reduce(const DevArgs& a, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
-    if (a.precision == CGB_P64) hipLaunchKernelGGL(mem_reduce_kernel<double>, dim3(cell_grid(a.n)), dim3(64 * CPW), 0, st, a);
-    else hipLaunchKernelGGL(mem_reduce_kernel<float>, dim3(cell_grid(a.n)), dim3(64 * CPW), 0, st, a);
+    const dim3 g(cell_grid(a.n)), b(64 * CPW);
+    switch (a.precision) {
+        case CGB_P64: hipLaunchKernelGGL(mem_reduce_kernel<CGB_P64>, g, b, 0, st, a); break;
+        case CGB_P32: hipLaunchKernelGGL(mem_reduce_kernel<CGB_P32>, g, b, 0, st, a); break;
+        case CGB_PMX16: hipLaunchKernelGGL(mem_reduce_kernel<CGB_PMX16>, g, b, 0, st, a); break;
+        case CGB_PMXBF16: hipLaunchKernelGGL(mem_reduce_kernel<CGB_PMXBF16>, g, b, 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 // Boundary velocity of every node, written for all nodes so that every line
 // is written whole: a cell node gets the rigid-body velocity of its cell,
-// V + Omega x (s - X) (the moving-boundary term of Eq. 10 and the link
-// momenta use it), a wall node its plane velocity (zero for resting walls),
+// V + Omega x (s - X) (the moving-boundary term of Eq. 10 uses it), a wall node its plane velocity (zero for resting walls),
 // a fluid node zero.  Runs after the occupancy update of the step.
 template <class M>
 __global__ void usol_kernel(DevArgs a) {

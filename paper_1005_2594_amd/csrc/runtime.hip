@@ -223,11 +223,11 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
         p->precision > CGB_PMXBF16 || !(p->R_perp > 0) || !(p->R_par > 0) || !(p->rho_p > 0) || !(p->r_cut > 0))
         return CGB_EINVAL;
     {
-        // populations and link momenta are addressed with 32-bit byte offsets
+        // populations and boundary velocities are addressed with 32-bit byte offsets
         const double esz = p->precision == CGB_P64 ? 8.0 : (p->precision == CGB_P32 ? 4.0 : 2.0);
         const double msz = p->precision == CGB_P64 ? 8.0 : 4.0;
         const double pst = (double)(((long long)p->nx * p->ny * p->nz + 255) / 256 * 256);
-        if (19.0 * esz * pst >= 4294901760.0 || 18.0 * msz * pst >= 4294901760.0) return CGB_EINVAL;
+        if (19.0 * esz * pst >= 4294901760.0 || 4.0 * msz * pst >= 4294901760.0) return CGB_EINVAL;
     }
     cgb_sim* s = new cgb_sim();
     s->P = *p;
@@ -280,7 +280,6 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
         CK(dalloc(s, &a.owner, (size_t)a.ns * 4));
         const size_t msz = p->precision == CGB_P64 ? 8 : 4;
         CK(dalloc(s, &a.usol, 4 * (size_t)a.pstride * msz));
-        CK(dalloc(s, &a.mlink, 18 * (size_t)a.pstride * msz));
         CK(dalloc(s, &a.flags, (size_t)a.ns * 4));
         CK(dalloc(s, &a.cand, (size_t)a.ns * 4));
         CK(dalloc(s, &a.ntrans, 16));
@@ -711,8 +710,8 @@ int cgb_set_tiles(cgb_sim* s, int32_t bx, int32_t by, int32_t tz) {
 
 // Times the fused LB kernel alone on the current state: it reads the current
 // populations, flags and boundary velocities and writes only buffers that the
-// next step rewrites before reading (the other population buffer, its density
-// field and the link momenta), so the state is unchanged.
+// next step rewrites before reading (the other population buffer and its
+// density field), so the state is unchanged.
 int cgb_time_lb(cgb_sim* s, int32_t reps, double* ms_avg) {
     if (!s || reps < 1 || !ms_avg) return CGB_EINVAL;
     if (!s->fluid_ready) FAIL(s, CGB_ESTATE, "fluid not initialised");
