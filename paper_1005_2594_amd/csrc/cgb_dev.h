@@ -41,6 +41,8 @@ constexpr int ST_UNSTABLE = 1;
 constexpr int ST_TRANS_OVERFLOW = 2;
 constexpr int ST_PAIR_OVERFLOW = 4;
 
+constexpr int TSEG = 64;  // segments of the transition list
+
 struct DevArgs {
     // lattice
     int nx, ny, nz;
@@ -81,8 +83,8 @@ struct DevArgs {
     double iRpar2, iRperp2, Rb;
     // transitions
     int* trans;     // 3 ints per transition: site, old, new
-    int* ntrans;
-    int trans_cap;
+    int* ntrans;    // TSEG counters: the list is split into TSEG segments of trans_cap
+    int trans_cap;  // entries each, so that reservations spread over TSEG addresses
     // cell list
     int nb[3];
     double bedge[3];

@@ -166,8 +166,8 @@ __global__ void __launch_bounds__(64 * CPW) raster_kernel(DevArgs a) {
     const CellRec cr = ((const CellRec*)a.crec)[k];
     if (!cr.ok) return;  // the record kernel has flagged the state as unstable
     const int p = cr.p;
-    const int* lo = cr.lo;
-    const int* ext = cr.ext;
+    const int lo[3] = {cr.lo[0], cr.lo[1], cr.lo[2]};
+    const int ext[3] = {cr.ext[0], cr.ext[1], cr.ext[2]};
     for (int bx = 0; bx < ext[0]; bx += 8)
         for (int by = 0; by < ext[1]; by += 8) {
             const int ix = bx + (lane & 7), iy = by + (lane >> 3);
@@ -210,14 +210,16 @@ __global__ void __launch_bounds__(64 * CPW) raster_kernel(DevArgs a) {
                     if (m) {
                         const int first = __ffsll((long long)m) - 1;
                         int base = 0;
-                        if (lane == first) base = atomicAdd(a.ntrans, __popcll(m));
+                        const int seg = (int)(blockIdx.x % TSEG);
+                        if (lane == first) base = atomicAdd(a.ntrans + seg, __popcll(m));
                         base = __shfl(base, first, 64);
                         if (tr) {
                             const int t = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
                             if (t < a.trans_cap) {
-                                a.trans[3 * t] = (int)s;
-                                a.trans[3 * t + 1] = o;
-                                a.trans[3 * t + 2] = nw;
+                                const long long e = (long long)seg * a.trans_cap + t;
+                                a.trans[3 * e] = (int)s;
+                                a.trans[3 * e + 1] = o;
+                                a.trans[3 * e + 2] = nw;
                             } else {
                                 atomicOr(a.status, ST_TRANS_OVERFLOW);
                             }
@@ -231,8 +233,9 @@ __global__ void __launch_bounds__(64 * CPW) raster_kernel(DevArgs a) {
         if (lane < 3) {
             double h[3];
             half_extents(a, cr.o, h);
-            a.Xprev[3 * p + lane] = cr.X[lane];
-            a.Hprev[3 * p + lane] = h[lane];
+            // lane-indexed values picked by selects (no dynamic indexing of locals)
+            a.Xprev[3 * p + lane] = lane == 0 ? cr.X[0] : (lane == 1 ? cr.X[1] : cr.X[2]);
+            a.Hprev[3 * p + lane] = lane == 0 ? h[0] : (lane == 1 ? h[1] : h[2]);
         }
     }
 }
@@ -285,8 +288,8 @@ __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
     const CellRec cr = ((const CellRec*)a.crec)[kk];
     if (!cr.ok) return;  // the record kernel has flagged the state as unstable
     const int p = cr.p;
-    const int* lo = cr.lo;
-    const int* ext = cr.ext;
+    const int lo[3] = {cr.lo[0], cr.lo[1], cr.lo[2]};
+    const int ext[3] = {cr.ext[0], cr.ext[1], cr.ext[2]};
     double F0 = 0, F1 = 0, F2 = 0, T0 = 0, T1 = 0, T2 = 0;
     for (int bx = 0; bx < ext[0]; bx += 8)
         for (int by = 0; by < ext[1]; by += 8) {
@@ -433,12 +436,12 @@ __global__ void zero_int_kernel(int* p) { *p = 0; }
 // step index (kernels read the step from device memory, so a captured step
 // sequence stays correct when it is replayed)
 __global__ void step_begin_kernel(int* ntrans, int* dstep, int advance) {
-    *ntrans = 0;
-    if (advance) *dstep += 1;
+    if (threadIdx.x < TSEG) ntrans[threadIdx.x] = 0;
+    if (threadIdx.x == 0 && advance) *dstep += 1;
 }
 
 hipError_t launch_raster(const DevArgs& a, hipStream_t st, bool fresh) {
-    hipLaunchKernelGGL(step_begin_kernel, dim3(1), dim3(1), 0, st, a.ntrans, a.dstep, fresh ? 0 : 1);
+    hipLaunchKernelGGL(step_begin_kernel, dim3(1), dim3(TSEG), 0, st, a.ntrans, a.dstep, fresh ? 0 : 1);
     if (a.n == 0) return hipGetLastError();
     hipLaunchKernelGGL(cellrec_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
     hipLaunchKernelGGL(raster_kernel<false>, dim3(cell_grid(a.n)), dim3(64 * CPW), 0, st, a);
@@ -512,15 +515,17 @@ __device__ void transition_one(const DevArgs& a, int t, bool book) {
     }
 }
 
+// TSEG x 8 blocks: block b takes segment b % TSEG
 template <int P>
 __global__ void transitions_kernel(DevArgs a, int book) {
-    const int cnt = min(*a.ntrans, a.trans_cap);
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x)
-        transition_one<P>(a, t, book != 0);
+    const int seg = blockIdx.x % TSEG, part = blockIdx.x / TSEG, nparts = gridDim.x / TSEG;
+    const int cnt = min(a.ntrans[seg], a.trans_cap);
+    for (int t = part * blockDim.x + threadIdx.x; t < cnt; t += nparts * blockDim.x)
+        transition_one<P>(a, (int)((long long)seg * a.trans_cap + t), book != 0);
 }
 
 hipError_t launch_transitions(const DevArgs& a, hipStream_t st, bool book) {
-    dim3 g(512), b(256);
+    dim3 g(TSEG * 8), b(256);
     switch (a.precision) {
         case CGB_P64: hipLaunchKernelGGL(transitions_kernel<CGB_P64>, g, b, 0, st, a, (int)book); break;
         case CGB_P32: hipLaunchKernelGGL(transitions_kernel<CGB_P32>, g, b, 0, st, a, (int)book); break;
@@ -680,19 +685,26 @@ hipError_t launch_cells(const DevArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// element i < 3 of a 3-array by selects (a dynamically indexed local array
+// would live in scratch memory)
+__device__ inline int pick3(const int* v, int i) { return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]); }
+
 // neighbour bin offsets along one axis (deduplicated for fewer than 3 bins;
 // clipped at the wall planes)
 __device__ inline int axis_bins(const DevArgs& a, int c, int b, int* out) {
+    // written with constant indices only, so that out[] stays in registers
     const int nb = a.nb[c];
     const bool periodic = !(c == 1 && a.wall_y);
-    int k = 0;
     if (!periodic) {
-        for (int d = -1; d <= 1; d++) if (b + d >= 0 && b + d < nb) out[k++] = b + d;
-        return k;
+        const bool lo = b - 1 >= 0, hi = b + 1 < nb;
+        out[0] = lo ? b - 1 : b;
+        out[1] = lo ? b : (hi ? b + 1 : b);
+        out[2] = b + 1;
+        return 1 + (lo ? 1 : 0) + (hi ? 1 : 0);
     }
     if (nb >= 3) { out[0] = wrap(b - 1, nb); out[1] = b; out[2] = wrap(b + 1, nb); return 3; }
-    for (int i = 0; i < nb; i++) out[k++] = i;
-    return k;
+    out[0] = 0; out[1] = 1; out[2] = 2;
+    return nb;
 }
 
 // squared length evaluated exactly as written (pair membership is decided
@@ -783,7 +795,7 @@ __global__ void potentials_kernel(DevArgs a) {
     for (int iz = 0; iz < nzb; iz++)
         for (int iy = 0; iy < nyb; iy++)
             for (int ix = 0; ix < nxb; ix++) {
-                const int bb = lx[ix] + a.nb[0] * (ly[iy] + a.nb[1] * lz[iz]);
+                const int bb = pick3(lx, ix) + a.nb[0] * (pick3(ly, iy) + a.nb[1] * pick3(lz, iz));
                 for (int t = a.bin_start[bb]; t < a.bin_start[bb + 1]; t++) {
                     const int j = a.bin_idx[t];
                     if (j == i) continue;
@@ -827,7 +839,7 @@ __global__ void pairs_kernel(DevArgs a, int* out, int* count, int cap) {
     for (int iz = 0; iz < nzb; iz++)
         for (int iy = 0; iy < nyb; iy++)
             for (int ix = 0; ix < nxb; ix++) {
-                const int bb = lx[ix] + a.nb[0] * (ly[iy] + a.nb[1] * lz[iz]);
+                const int bb = pick3(lx, ix) + a.nb[0] * (pick3(ly, iy) + a.nb[1] * pick3(lz, iz));
                 for (int t = a.bin_start[bb]; t < a.bin_start[bb + 1]; t++) {
                     const int j = a.bin_idx[t];
                     if (j <= i) continue;

@@ -130,7 +130,7 @@ static int check_status(cgb_sim* s) {
     HIPCHK(s, hipMemcpyAsync(&st, s->a.status, sizeof(int), hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipMemcpyAsync(&bad, s->a.bad_step, sizeof(int), hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
-    if (st & ST_TRANS_OVERFLOW) FAIL(s, CGB_ENOMEM, "transition list overflow (capacity %d)", s->a.trans_cap);
+    if (st & ST_TRANS_OVERFLOW) FAIL(s, CGB_ENOMEM, "transition list overflow (capacity %d per segment)", s->a.trans_cap);
     if (st & ST_UNSTABLE) FAIL(s, CGB_EUNSTABLE, "unstable at step %d: non-finite state, |u| > 0.4 or |V| >= 0.5", bad);
     return CGB_OK;
 }
@@ -209,8 +209,8 @@ static int alloc_particles(cgb_sim* s, int ncap) {
     HIPCHK(s, launch_fill_f64(a.body_part, (long long)((n + 255) / 256) * 3, 0.0, s->st));
     long long cap = 96LL * (long long)n + 65536;
     if (cap > s->a.ns + 65536) cap = s->a.ns + 65536;
-    a.trans_cap = (int)cap;
-    HIPCHK(s, dalloc(s, &a.trans, (size_t)cap * 3 * 4));
+    a.trans_cap = (int)(cap / TSEG + 4096);  // per segment
+    HIPCHK(s, dalloc(s, &a.trans, (size_t)a.trans_cap * TSEG * 3 * 4));
     s->ncap = ncap;
     return CGB_OK;
 }
@@ -282,7 +282,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
         CK(dalloc(s, &a.usol, 4 * (size_t)a.pstride * msz));
         CK(dalloc(s, &a.flags, (size_t)a.ns * 4));
         CK(dalloc(s, &a.cand, (size_t)a.ns * 4));
-        CK(dalloc(s, &a.ntrans, 16));
+        CK(dalloc(s, &a.ntrans, TSEG * 4));
         CK(dalloc(s, &a.status, 16));
         CK(dalloc(s, &a.bad_step, 16));
         CK(dalloc(s, &a.dstep, 16));
