@@ -172,6 +172,47 @@ int cgb_mu_rel_kolmogorov(const double* A, int32_t n, int32_t first, double f0, 
 int cgb_mu_rel_slit(const double* ubar, int32_t n, int32_t first, double g, double tau, int32_t ny, double* mu);
 int cgb_mu_rel(cgb_sim* s, int32_t first, double* mu);
 
+/* ---- Learned closure: ensemble of MLPs 3 -> 64 -> 64 -> 1 (SiLU) mapping
+ * (hematocrit, log shear rate, width / R_perp) to the relative apparent
+ * viscosity, trained and evaluated on the device.  A member has
+ * CGB_MLP_PARAMS FP32 master parameters in the order W1[64][3], b1[64],
+ * W2[64][64], b2[64], W3[64], b3; weights enter the arithmetic rounded to
+ * bfloat16, the 64 x 64 layer and its backward products run on the matrix
+ * cores with FP32 accumulation.  The network sees standardised inputs
+ * (x - in_mean)/in_std and predicts the standardised (log mu - out_mean)/
+ * out_std (cgb_mlp_set_norm; identity until set).  Host pointers unless
+ * stated; every call is synchronous except cgb_mlp_predict_device. */
+#define CGB_MLP_PARAMS 4481
+#define CGB_MLP_BATCH 128   /* training batch of one step */
+typedef struct cgb_mlp cgb_mlp;
+/* members in [1, 6]; parameters start at zero (set them before use) */
+int cgb_mlp_create(int32_t members, cgb_mlp** out);
+void cgb_mlp_destroy(cgb_mlp* h);
+const char* cgb_mlp_last_error(const cgb_mlp* h);
+/* p: members * CGB_MLP_PARAMS; setting resets the optimiser state */
+int cgb_mlp_set_params(cgb_mlp* h, const float* p);
+int cgb_mlp_get_params(cgb_mlp* h, float* p);
+int cgb_mlp_set_norm(cgb_mlp* h, const float* in_mean, const float* in_std, float out_mean, float out_std);
+/* raw outputs for standardised inputs xn[n][3]: y[members][n] */
+int cgb_mlp_forward(cgb_mlp* h, int64_t n, const float* xn, float* y);
+/* gradient of the mean squared error over one batch: the samples
+ * idx[members][CGB_MLP_BATCH] (member m uses its own row) of standardised
+ * inputs xn[n][3] and targets tn[n]; grad[members][CGB_MLP_PARAMS],
+ * loss[members] (nullable).  Parameters unchanged. */
+int cgb_mlp_grad(cgb_mlp* h, int32_t n, const float* xn, const float* tn, const int32_t* idx, float* grad, float* loss);
+/* `steps` Adam steps (beta 0.9, 0.999, eps 1e-8, rate lr) on physical samples
+ * x[n][3], mu[n] > 0 (standardised on the device with the handle's norm);
+ * step s of member m uses the samples idx[m][s][0 .. CGB_MLP_BATCH-1]
+ * (the caller draws them); loss[members][steps] (nullable) receives each
+ * step's batch loss. */
+int cgb_mlp_train(cgb_mlp* h, int32_t n, const float* x, const float* mu, int32_t steps, const int32_t* idx, float lr,
+                  float* loss);
+/* ensemble mean of mu and relative spread (sample standard deviation over
+ * members / mean) for physical inputs x[n][3] */
+int cgb_mlp_predict(cgb_mlp* h, int64_t n, const float* x, float* mean, float* spread);
+/* the same on device buffers, asynchronous on `stream` (NULL: the handle's) */
+int cgb_mlp_predict_device(cgb_mlp* h, int64_t n, const float* x, float* mean, float* spread, void* stream);
+
 /* Checkpoint: stored populations (as stored), owner, cell state and the step
  * counter.  Resume is bit-identical to an uninterrupted run. */
 int cgb_save(cgb_sim* s, const char* path);

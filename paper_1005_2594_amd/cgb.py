@@ -51,6 +51,14 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1005_2594_amd.build")
+    # PyTorch ships its own HIP runtime under the same soname: loading it
+    # first makes the library bind to that one, so that device memory and
+    # streams can pass between the two (two runtimes in one process do not
+    # share the device)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     L.cgb_params_default.argtypes = [C.POINTER(CgbParams)]
     L.cgb_create.argtypes = [C.POINTER(CgbParams), VP, VP, C.POINTER(VP)]
@@ -98,6 +106,19 @@ def lib():
     L.cgb_mu_rel_kolmogorov.argtypes = [VP, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double)]
     L.cgb_mu_rel_slit.argtypes = [VP, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double)]
     L.cgb_mu_rel.argtypes = [VP, C.c_int32, C.POINTER(C.c_double)]
+    L.cgb_mlp_create.argtypes = [C.c_int32, C.POINTER(VP)]
+    L.cgb_mlp_destroy.argtypes = [VP]
+    L.cgb_mlp_destroy.restype = None
+    L.cgb_mlp_last_error.argtypes = [VP]
+    L.cgb_mlp_last_error.restype = C.c_char_p
+    L.cgb_mlp_set_params.argtypes = [VP, VP]
+    L.cgb_mlp_get_params.argtypes = [VP, VP]
+    L.cgb_mlp_set_norm.argtypes = [VP, VP, VP, C.c_float, C.c_float]
+    L.cgb_mlp_forward.argtypes = [VP, C.c_int64, VP, VP]
+    L.cgb_mlp_grad.argtypes = [VP, C.c_int32, VP, VP, VP, VP, VP]
+    L.cgb_mlp_train.argtypes = [VP, C.c_int32, VP, VP, C.c_int32, VP, C.c_float, VP]
+    L.cgb_mlp_predict.argtypes = [VP, C.c_int64, VP, VP, VP]
+    L.cgb_mlp_predict_device.argtypes = [VP, C.c_int64, VP, VP, VP, VP]
     _lib = L
     return L
 
@@ -393,3 +414,86 @@ def mu_rel_slit(ubar, g, tau, ny, first):
     if rc:
         raise CgbError(rc, "cgb_mu_rel_slit")
     return mu.value
+
+
+MLP_PARAMS = 4481
+MLP_BATCH = 128
+
+
+def _f32(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a.reshape(shape) if shape is not None else a
+
+
+class Mlp:
+    """Ensemble of closure networks on the device (``cgb_mlp``)."""
+
+    def __init__(self, members=5):
+        h = VP()
+        rc = lib().cgb_mlp_create(int(members), C.byref(h))
+        if rc != 0:
+            raise CgbError(rc, "cgb_mlp_create failed")
+        self.h = h
+        self.members = int(members)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().cgb_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise CgbError(rc, lib().cgb_mlp_last_error(self.h).decode())
+
+    def set_params(self, p):
+        p = _f32(p, (self.members, MLP_PARAMS))
+        self._check(lib().cgb_mlp_set_params(self.h, _ptr(p)))
+
+    def params(self):
+        p = np.empty((self.members, MLP_PARAMS), dtype=np.float32)
+        self._check(lib().cgb_mlp_get_params(self.h, _ptr(p)))
+        return p
+
+    def set_norm(self, in_mean, in_std, out_mean, out_std):
+        m = _f32(in_mean, (3,)); s = _f32(in_std, (3,))
+        self._check(lib().cgb_mlp_set_norm(self.h, _ptr(m), _ptr(s), float(out_mean), float(out_std)))
+
+    def forward(self, xn):
+        xn = _f32(xn, (-1, 3))
+        y = np.empty((self.members, len(xn)), dtype=np.float32)
+        self._check(lib().cgb_mlp_forward(self.h, len(xn), _ptr(xn), _ptr(y)))
+        return y
+
+    def grad(self, xn, tn, idx):
+        xn = _f32(xn, (-1, 3)); tn = _f32(tn, (-1,))
+        idx = np.ascontiguousarray(idx, dtype=np.int32).reshape(self.members, MLP_BATCH)
+        g = np.empty((self.members, MLP_PARAMS), dtype=np.float32)
+        loss = np.empty(self.members, dtype=np.float32)
+        self._check(lib().cgb_mlp_grad(self.h, len(xn), _ptr(xn), _ptr(tn), _ptr(idx), _ptr(g), _ptr(loss)))
+        return g, loss
+
+    def train(self, x, mu, idx, lr):
+        """idx: [members][steps][MLP_BATCH] sample indices; returns the batch losses."""
+        x = _f32(x, (-1, 3)); mu = _f32(mu, (-1,))
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        steps = idx.shape[1]
+        loss = np.empty((self.members, steps), dtype=np.float32)
+        self._check(lib().cgb_mlp_train(self.h, len(x), _ptr(x), _ptr(mu), steps, _ptr(idx), float(lr), _ptr(loss)))
+        return loss
+
+    def predict(self, x):
+        x = _f32(x, (-1, 3))
+        mean = np.empty(len(x), dtype=np.float32); spread = np.empty(len(x), dtype=np.float32)
+        self._check(lib().cgb_mlp_predict(self.h, len(x), _ptr(x), _ptr(mean), _ptr(spread)))
+        return mean, spread
+
+    def predict_device(self, n, x_ptr, mean_ptr, spread_ptr, stream=None):
+        st = None if stream is None else VP(int(stream))
+        self._check(lib().cgb_mlp_predict_device(self.h, int(n), VP(int(x_ptr)), VP(int(mean_ptr)),
+                                                 VP(int(spread_ptr)), st))
