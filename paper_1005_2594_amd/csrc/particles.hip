@@ -266,128 +266,162 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Scan chunk t of a cell's box (8 x 8 columns, ZB planes) with the 64 lanes
+// and append the cell's nodes to the list in (z, lane) order; returns the count.
+__device__ inline int scan_chunk(const DevArgs& a, const CellRec& cr, int t, int lane, unsigned* lst_s, uint32_t* lst_f) {
+    const unsigned nx = (unsigned)a.nx, plane = (unsigned)a.nx * (unsigned)a.ny;
+    const int cx = (cr.ext[0] + 7) / 8, cy = (cr.ext[1] + 7) / 8;
+    const int bx = 8 * (t % cx), by = 8 * ((t / cx) % cy), z0 = ZB * (t / (cx * cy));
+    const int ix = bx + (lane & 7), iy = by + (lane >> 3);
+    bool col = ix < cr.ext[0] && iy < cr.ext[1];
+    const int x = wrap(cr.lo[0] + ix, a.nx);
+    int y = cr.lo[1] + iy;
+    if (a.wall_y) col = col && y >= 0 && y < a.ny;
+    else y = wrap(y, a.ny);
+    unsigned sj[ZB];
+    int ow[ZB];
+    uint32_t fl[ZB];
+#pragma unroll
+    for (int j = 0; j < ZB; j++) {
+        const bool ok = col && z0 + j < cr.ext[2];
+        sj[j] = (unsigned)x + nx * (unsigned)y + plane * (unsigned)wrap(cr.lo[2] + z0 + j, a.nz);
+        ow[j] = ok ? a.owner[sj[j]] : OWN_WALL;
+        fl[j] = ok ? a.flags[sj[j]] : 0u;
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < ZB; j++) {
+        const bool mine = ow[j] == cr.p;
+        const unsigned long long m = __ballot(mine);
+        if (mine) {
+            const int e = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            lst_s[e] = sj[j];
+            lst_f[e] = fl[j];
+        }
+        cnt += __popcll(m);
+    }
+    return cnt;
+}
+
+__device__ inline int cell_chunks(const CellRec& cr) {
+    return ((cr.ext[0] + 7) / 8) * ((cr.ext[1] + 7) / 8) * ((cr.ext[2] + ZB - 1) / ZB);
+}
+
+// Momentum (along x, y, z, in the compute precision) the links of node s
+// carried to its cell; X, V, W: the cell's position and rigid-body velocity.
 template <int P>
-__global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
+__device__ inline void node_links(const DevArgs& a, __amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rRA, unsigned s,
+                                  uint32_t f, const double* X, const double* V, const double* W, double* FT) {
     using Cd = Codec<P>;
     using T = typename Cd::T;
     using R = typename Cd::R;
     constexpr unsigned ES = sizeof(T);
-    __shared__ unsigned lst_sa[CPW][MR_CAP];
-    __shared__ uint32_t lst_fa[CPW][MR_CAP];
     const unsigned ps = (unsigned)a.pstride;
     const unsigned nx = (unsigned)a.nx, plane = (unsigned)a.nx * (unsigned)a.ny;
+    const int sx = (int)(s % nx), sy = (int)((s / nx) % (unsigned)a.ny), sz = (int)(s / plane);
+    // the bounced population and the density of the fluid node x = s + c_r of every link
+    const int ox[3] = {sx == a.nx - 1 ? -(a.nx - 1) : 1, 0, sx == 0 ? a.nx - 1 : -1};
+    const int oy[3] = {sy == a.ny - 1 ? -(int)((a.ny - 1) * nx) : (int)nx, 0, sy == 0 ? (int)((a.ny - 1) * nx) : -(int)nx};
+    const int oz[3] = {sz == a.nz - 1 ? -(int)((a.nz - 1) * plane) : (int)plane, 0,
+                       sz == 0 ? (int)((a.nz - 1) * plane) : -(int)plane};
+    T dv[19], rv[19];
+#pragma unroll
+    for (int r = 1; r < 19; r++) {
+        // fluid at s + c_r: bit OPP(r) of s's flags (source s - c_OPP(r)) is clear
+        const bool lk = !((f >> OPP(r)) & 1u);
+        // offsets index c = +1 at 0 and c = -1 at 2: x = s + c_r
+        const unsigned xi = s + (unsigned)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)]);
+        dv[r] = bload<T>(rA, lk ? ES * ((unsigned)OPP(r) * ps + xi) : 0xfffffff0u);
+        rv[r] = bload<T>(rRA, lk ? ES * xi : 0xfffffff0u);
+    }
+    double d[3];
+    node_disp(a, sx, sy, sz, X, d);
+    double ud[3];
+    cross3(W, d, ud);
+    const R u0 = (R)(ud[0] + V[0]), u1 = (R)(ud[1] + V[1]), u2 = (R)(ud[2] + V[2]);
+    R m0 = 0, m1 = 0, m2 = 0;
+#pragma unroll
+    for (int r = 1; r < 19; r++) {
+        const bool lk = !((f >> OPP(r)) & 1u);
+        const R rho_x = (R)a.rho0 + Cd::dec(rv[r], rho_dec_scale<P>(a));
+        R cu = 0;
+        if (CX(r)) cu += (R)CX(r) * u0;
+        if (CY(r)) cu += (R)CY(r) * u1;
+        if (CZ(r)) cu += (R)CZ(r) * u2;
+        const R C = (R)(6.0 * WD(r)) * rho_x * cu;
+        const R m = lk ? -((R)2 * Cd::dec(dv[r], dec_scale<P>(a, OPP(r))) + C) : (R)0;
+        if (CX(r)) m0 += CX(r) * m;
+        if (CY(r)) m1 += CY(r) * m;
+        if (CZ(r)) m2 += CZ(r) * m;
+    }
+    const double g0 = (double)m0, g1 = (double)m1, g2 = (double)m2;
+    FT[0] += g0; FT[1] += g1; FT[2] += g2;
+    FT[3] += d[1] * g2 - d[2] * g1;
+    FT[4] += d[2] * g0 - d[0] * g2;
+    FT[5] += d[0] * g1 - d[1] * g0;
+}
+
+// Two cells per wave: both boxes are scanned by all 64 lanes, then lanes
+// 0-31 take the first cell's nodes and lanes 32-63 the second's (a cell has
+// ~26 nodes), and each half reduces its sums.
+template <int P>
+__global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
+    using Cd = Codec<P>;
+    using T = typename Cd::T;
+    constexpr unsigned ES = sizeof(T);
+    __shared__ unsigned lst_sa[CPW][2][MR_CAP];
+    __shared__ uint32_t lst_fa[CPW][2][MR_CAP];
+    const unsigned ps = (unsigned)a.pstride;
     const auto rA = make_rsrc(a.A, 19ull * ps * ES);
     const auto rRA = make_rsrc(a.rhoA, (unsigned long long)ps * ES);
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
     const int wv = threadIdx.x >> 6;
-    unsigned* lst_s = lst_sa[wv];
-    uint32_t* lst_f = lst_fa[wv];
-    const int kk = __builtin_amdgcn_readfirstlane(blockIdx.x * CPW + wv);
-    if (kk >= a.n) return;
-    // the record's box (previous and current rasterisation) holds every node of the cell
-    const CellRec cr = ((const CellRec*)a.crec)[kk];
-    if (!cr.ok) return;  // the record kernel has flagged the state as unstable
-    const int p = cr.p;
-    const int lo[3] = {cr.lo[0], cr.lo[1], cr.lo[2]};
-    const int ext[3] = {cr.ext[0], cr.ext[1], cr.ext[2]};
-    double F0 = 0, F1 = 0, F2 = 0, T0 = 0, T1 = 0, T2 = 0;
-    for (int bx = 0; bx < ext[0]; bx += 8)
-        for (int by = 0; by < ext[1]; by += 8) {
-            const int ix = bx + (lane & 7), iy = by + (lane >> 3);
-            bool col = ix < ext[0] && iy < ext[1];
-            const int x = wrap(lo[0] + ix, a.nx);
-            int y = lo[1] + iy;
-            if (a.wall_y) col = col && y >= 0 && y < a.ny;
-            else y = wrap(y, a.ny);
-            for (int z0 = 0; z0 < ext[2]; z0 += ZB) {
-                // the slab's nodes of cell p, compacted in (z, lane) order
-                unsigned sj[ZB];
-                int ow[ZB];
-                uint32_t fl[ZB];
+    const int k0 = 2 * __builtin_amdgcn_readfirstlane(blockIdx.x * CPW + wv);
+    if (k0 >= a.n) return;
+    // the records' boxes (previous and current rasterisation) hold every node of the cells
+    const CellRec c0 = ((const CellRec*)a.crec)[k0];
+    CellRec c1 = c0;
+    const bool has1 = k0 + 1 < a.n;
+    if (has1) c1 = ((const CellRec*)a.crec)[k0 + 1];
+    const int n0 = c0.ok ? cell_chunks(c0) : 0, n1 = (has1 && c1.ok) ? cell_chunks(c1) : 0;
+    // this lane's cell (for processing)
+    double X[3], V[3], W[3];
 #pragma unroll
-                for (int j = 0; j < ZB; j++) {
-                    const bool ok = col && z0 + j < ext[2];
-                    sj[j] = (unsigned)x + nx * (unsigned)y + plane * (unsigned)wrap(lo[2] + z0 + j, a.nz);
-                    ow[j] = ok ? a.owner[sj[j]] : OWN_WALL;
-                    fl[j] = ok ? a.flags[sj[j]] : 0u;
-                }
-                int cnt = 0;
-#pragma unroll
-                for (int j = 0; j < ZB; j++) {
-                    const bool mine = ow[j] == p;
-                    const unsigned long long m = __ballot(mine);
-                    if (mine) {
-                        const int e = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                        lst_s[e] = sj[j];
-                        lst_f[e] = fl[j];
-                    }
-                    cnt += __popcll(m);
-                }
-                wave_sync();
-                for (int base = 0; base < cnt; base += 64) {
-                    const int e = base + lane;
-                    if (e < cnt) {
-                        const unsigned s = lst_s[e];
-                        const uint32_t f = lst_f[e];
-                        const int sx = (int)(s % nx), sy = (int)((s / nx) % (unsigned)a.ny), sz = (int)(s / plane);
-                        // the bounced population and the density of the fluid node
-                        // x = s + c_r of every link
-                        const int ox[3] = {sx == a.nx - 1 ? -(a.nx - 1) : 1, 0, sx == 0 ? a.nx - 1 : -1};
-                        const int oy[3] = {sy == a.ny - 1 ? -(int)((a.ny - 1) * nx) : (int)nx, 0,
-                                           sy == 0 ? (int)((a.ny - 1) * nx) : -(int)nx};
-                        const int oz[3] = {sz == a.nz - 1 ? -(int)((a.nz - 1) * plane) : (int)plane, 0,
-                                           sz == 0 ? (int)((a.nz - 1) * plane) : -(int)plane};
-                        T dv[19], rv[19];
-#pragma unroll
-                        for (int r = 1; r < 19; r++) {
-                            // fluid at s + c_r: bit OPP(r) of s's flags (source s - c_OPP(r)) is clear
-                            const bool lk = !((f >> OPP(r)) & 1u);
-                            // offsets index c = +1 at 0 and c = -1 at 2: x = s + c_r
-                            const unsigned xi = s + (unsigned)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)]);
-                            dv[r] = bload<T>(rA, lk ? ES * ((unsigned)OPP(r) * ps + xi) : 0xfffffff0u);
-                            rv[r] = bload<T>(rRA, lk ? ES * xi : 0xfffffff0u);
-                        }
-                        double d[3];
-                        node_disp(a, sx, sy, sz, cr.X, d);
-                        double ud[3];
-                        cross3(cr.W, d, ud);
-                        const R u0 = (R)(ud[0] + cr.V[0]), u1 = (R)(ud[1] + cr.V[1]), u2 = (R)(ud[2] + cr.V[2]);
-                        R m0 = 0, m1 = 0, m2 = 0;
-#pragma unroll
-                        for (int r = 1; r < 19; r++) {
-                            const bool lk = !((f >> OPP(r)) & 1u);
-                            const R rho_x = (R)a.rho0 + Cd::dec(rv[r], rho_dec_scale<P>(a));
-                            R cu = 0;
-                            if (CX(r)) cu += (R)CX(r) * u0;
-                            if (CY(r)) cu += (R)CY(r) * u1;
-                            if (CZ(r)) cu += (R)CZ(r) * u2;
-                            const R C = (R)(6.0 * WD(r)) * rho_x * cu;
-                            const R m = lk ? -((R)2 * Cd::dec(dv[r], dec_scale<P>(a, OPP(r))) + C) : (R)0;
-                            if (CX(r)) m0 += CX(r) * m;
-                            if (CY(r)) m1 += CY(r) * m;
-                            if (CZ(r)) m2 += CZ(r) * m;
-                        }
-                        const double g0 = (double)m0, g1 = (double)m1, g2 = (double)m2;
-                        F0 += g0; F1 += g1; F2 += g2;
-                        T0 += d[1] * g2 - d[2] * g1;
-                        T1 += d[2] * g0 - d[0] * g2;
-                        T2 += d[0] * g1 - d[1] * g0;
-                    }
-                }
-                wave_sync();
-            }
+    for (int c = 0; c < 3; c++) {
+        X[c] = half ? c1.X[c] : c0.X[c];
+        V[c] = half ? c1.V[c] : c0.V[c];
+        W[c] = half ? c1.W[c] : c0.W[c];
+    }
+    double FT[6] = {0, 0, 0, 0, 0, 0};
+    const int nch = n0 > n1 ? n0 : n1;
+    for (int t = 0; t < nch; t++) {
+        const int cnt0 = t < n0 ? scan_chunk(a, c0, t, lane, lst_sa[wv][0], lst_fa[wv][0]) : 0;
+        const int cnt1 = t < n1 ? scan_chunk(a, c1, t, lane, lst_sa[wv][1], lst_fa[wv][1]) : 0;
+        wave_sync();
+        const int mycnt = half ? cnt1 : cnt0;
+        const int rounds = ((cnt0 > cnt1 ? cnt0 : cnt1) + 31) / 32;
+        for (int rd = 0; rd < rounds; rd++) {
+            const int e = 32 * rd + hl;
+            if (e < mycnt) node_links<P>(a, rA, rRA, lst_sa[wv][half][e], lst_fa[wv][half][e], X, V, W, FT);
         }
-    F0 = wave_sum(F0); F1 = wave_sum(F1); F2 = wave_sum(F2);
-    T0 = wave_sum(T0); T1 = wave_sum(T1); T2 = wave_sum(T2);
-    if (lane == 0) {
-        double* FT = a.FTh + 6 * (long long)p;
-        FT[0] += F0; FT[1] += F1; FT[2] += F2; FT[3] += T0; FT[4] += T1; FT[5] += T2;
+        wave_sync();
+    }
+    // sums over each half of the wave
+#pragma unroll
+    for (int c = 0; c < 6; c++)
+#pragma unroll
+        for (int off = 16; off >= 1; off >>= 1) FT[c] += __shfl_xor(FT[c], off, 64);
+    if (hl == 0 && (half == 0 ? n0 > 0 : n1 > 0)) {
+        const int p = half ? c1.p : c0.p;
+        double* F = a.FTh + 6 * (long long)p;
+#pragma unroll
+        for (int c = 0; c < 6; c++) F[c] += FT[c];
     }
 }
 
 hipError_t launch_mem_reduce(const DevArgs& a, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
-    const dim3 g(cell_grid(a.n)), b(64 * CPW);
+    const dim3 g(cell_grid((a.n + 1) / 2)), b(64 * CPW);
     switch (a.precision) {
         case CGB_P64: hipLaunchKernelGGL(mem_reduce_kernel<CGB_P64>, g, b, 0, st, a); break;
         case CGB_P32: hipLaunchKernelGGL(mem_reduce_kernel<CGB_P32>, g, b, 0, st, a); break;
