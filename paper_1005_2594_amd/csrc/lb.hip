@@ -85,9 +85,11 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
     // index 0: c = -1, 1: c = 0, 2: c = +1
     const int ox[3] = {x == a.nx - 1 ? -(a.nx - 1) : 1, 0, x == 0 ? a.nx - 1 : -1};
     const int oy[3] = {y == a.ny - 1 ? -(int)((a.ny - 1) * nx) : (int)nx, 0, y == 0 ? (int)((a.ny - 1) * nx) : -(int)nx};
-    double gyd[3];
-    body_force(a, (double)y, gyd);
-    const R gx = (R)gyd[0], gy = (R)gyd[1], gz = (R)gyd[2];
+    // body force at this plane: constant, or f0 sin(2 pi y/ny) from the table
+    const int yc = y < a.ny ? y : a.ny - 1;
+    const R gx = a.force_mode == 1 ? (R)a.g[0] : (R)0;
+    const R gy = a.force_mode == 1 ? (R)a.g[1] : (R)0;
+    const R gz = a.force_mode == 1 ? (R)a.g[2] : (a.force_mode == 2 ? (R)(a.f0 * a.ysin[yc]) : (R)0);
     const R omega = (R)(1.0 / a.tau);
     const R pref = (R)(1.0 - 0.5 / a.tau);
 
@@ -194,9 +196,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
     const auto rU = make_rsrc(a.usol, 4ull * ps * sizeof(M));
     const int ox[3] = {x == a.nx - 1 ? -(a.nx - 1) : 1, 0, x == 0 ? a.nx - 1 : -1};
     const int oy[3] = {y == a.ny - 1 ? -(int)((a.ny - 1) * nx) : (int)nx, 0, y == 0 ? (int)((a.ny - 1) * nx) : -(int)nx};
-    double gyd[3];
-    body_force(a, (double)y, gyd);
-    const R gx = (R)gyd[0], gy = (R)gyd[1], gz = (R)gyd[2];
+    // body force at this plane: constant, or f0 sin(2 pi y/ny) from the table
+    const int yc = y < a.ny ? y : a.ny - 1;
+    const R gx = a.force_mode == 1 ? (R)a.g[0] : (R)0;
+    const R gy = a.force_mode == 1 ? (R)a.g[1] : (R)0;
+    const R gz = a.force_mode == 1 ? (R)a.g[2] : (a.force_mode == 2 ? (R)(a.f0 * a.ysin[yc]) : (R)0);
 
     // flags of the first node; each step prefetches the next node's flags
     uint32_t fnext = (inb && z0 < a.nz) ? bload<uint32_t>(rFl, 4u * ((unsigned)x + nx * (unsigned)y + plane * (unsigned)z0)) : NONFLUID;
