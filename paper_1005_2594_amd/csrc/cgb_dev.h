@@ -95,6 +95,7 @@ struct DevArgs {
     int* bin_idx;   // n
     int* wall_start;// nbins+1 (surface wall nodes per bin)
     int* wall_idx;  // site indices
+    int nsw;        // number of surface wall nodes
     int nbins;
     double r_cut2;
     double wall_range2;
@@ -300,7 +301,7 @@ struct LaunchCfg {
 };
 hipError_t launch_lb(const DevArgs& a, LaunchCfg cfg, hipStream_t st);
 hipError_t launch_mem_reduce(const DevArgs& a, hipStream_t st);
-hipError_t launch_usol(const DevArgs& a, hipStream_t st);
+hipError_t launch_usol(const DevArgs& a, hipStream_t st, bool all);
 hipError_t launch_prep(const DevArgs& a, hipStream_t st);
 hipError_t launch_kin(const DevArgs& a, hipStream_t st);
 hipError_t launch_clear_cells(const DevArgs& a, hipStream_t st);

@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(256) track_kernel(DevArgs a) {
     for (long long s = blockIdx.x * 256LL + threadIdx.x; s < a.ns; s += (long long)TRACK_BLOCKS * 256) {
         const int o = a.owner[s];
         if (o == OWN_WALL) continue;
-        const int y = (int)((s / a.nx) % a.ny);
+        const int y = (int)(((unsigned)s / (unsigned)a.nx) % (unsigned)a.ny);  // sites < 2^32 (checked at create)
         double uz;
         if (o == OWN_FLUID) {
             double jz = 0.0;

@@ -99,17 +99,15 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
         if (z >= a.nz) break;
         const unsigned i = (unsigned)x + nx * (unsigned)y + plane * (unsigned)z;
         const uint32_t f = inb ? a.flags[i] : NONFLUID;
-        if (f & NONFLUID) {
-            // write the node too, so that every line of B is written whole
-            // (no read-modify-write of partly written lines); the values of
-            // non-fluid nodes are never read
-            if (inb) {
+        // outputs of the node; a non-fluid node stores zeros.  The stores
+        // below are shared by all lanes of the wave, so that each wave store
+        // writes its lines whole (stores issued separately by the fluid and
+        // non-fluid lanes would each write part of the same lines)
+        T ob[19], orho;
 #pragma unroll
-                for (int r = 0; r < 19; r++) bstore<T>(Cd::enc((R)0, (R)1), rB, ES * ((unsigned)r * ps + i));
-                bstore<T>(Cd::enc((R)0, (R)1), rRB, ES * i);
-            }
-            continue;
-        }
+        for (int r = 0; r < 19; r++) ob[r] = Cd::enc((R)0, (R)1);
+        orho = Cd::enc((R)0, (R)1);
+        if (!(f & NONFLUID)) {
         const int oz[3] = {z == a.nz - 1 ? -(int)((a.nz - 1) * plane) : (int)plane, 0,
                            z == 0 ? (int)((a.nz - 1) * plane) : -(int)plane};
         auto src = [&](int r) { return i + (unsigned)(ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1]); };
@@ -160,13 +158,19 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
             const R Fr = pref * w * ((R)3 * (cg - ug) + (R)9 * cu * cg);
             const R out = d[r] - (d[r] - eq) * omega + Fr;
             const T st = Cd::enc(out, enc_scale<P>(a, r));
-            bstore<T>(st, rB, ES * ((unsigned)r * ps + i));
+            ob[r] = st;
             rsum += Cd::dec(st, dec_scale<P>(a, r));
         }
-        bstore<T>(Cd::enc(rsum, rho_enc_scale<P>(a)), rRB, ES * i);
+        orho = Cd::enc(rsum, rho_enc_scale<P>(a));
         if (!(usq <= (R)0.16)) {
             atomicOr(a.status, ST_UNSTABLE);
             atomicMin(a.bad_step, *a.dstep);
+        }
+        }
+        if (inb) {
+#pragma unroll
+            for (int r = 0; r < 19; r++) bstore<T>(ob[r], rB, ES * ((unsigned)r * ps + i));
+            bstore<T>(orho, rRB, ES * i);
         }
     }
 }
@@ -211,17 +215,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
         const unsigned i = (unsigned)x + nx * (unsigned)y + plane * (unsigned)z;
         const uint32_t f = fnext;
         fnext = (inb && zz + 1 < TZ && z + 1 < a.nz) ? bload<uint32_t>(rFl, 4u * (i + plane)) : NONFLUID;
-        if (f & NONFLUID) {
-            // write the node too, so that every line of B is written whole
-            // (no read-modify-write of partly written lines); the values of
-            // non-fluid nodes are never read
-            if (inb) {
+        // outputs of the node; a non-fluid node stores zeros.  The stores
+        // below are shared by all lanes of the wave, so that each wave store
+        // writes its lines whole (stores issued separately by the fluid and
+        // non-fluid lanes would each write part of the same lines)
+        T ob[19], orho;
 #pragma unroll
-                for (int r = 0; r < 19; r++) bstore<T>(Cd::enc((R)0, (R)1), rB, ES * ((unsigned)r * ps + i));
-                bstore<T>(Cd::enc((R)0, (R)1), rRB, ES * i);
-            }
-            continue;
-        }
+        for (int r = 0; r < 19; r++) ob[r] = Cd::enc((R)0, (R)1);
+        orho = Cd::enc((R)0, (R)1);
+        if (!(f & NONFLUID)) {
         const int oz[3] = {z == a.nz - 1 ? -(int)((a.nz - 1) * plane) : (int)plane, 0,
                            z == 0 ? (int)((a.nz - 1) * plane) : -(int)plane};
         auto src = [&](int r) { return i + (unsigned)(ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1]); };
@@ -275,7 +277,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
         {
             const R w0 = (R)(1.0 / 3.0);
             const R out0 = w0 * (drho - rho * (R)1.5 * usq) - (R)1.5 * w0 * ug;
-            bstore<T>(Cd::enc(out0, enc_scale<P>(a, 0)), rB, ES * i);
+            ob[0] = Cd::enc(out0, enc_scale<P>(a, 0));
         }
 #pragma unroll
         for (int r = 1; r < 19; r += 2) {
@@ -285,14 +287,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
             const R cu2 = cu * cu;
             const R ev = w * (drho + rho * ((R)4.5 * cu2 - (R)1.5 * usq)) + (R)0.5 * w * ((R)9 * cu * cg - (R)3 * ug);
             const R od = w * rho * cu * ((R)3 + (R)4.5 * cu2 - (R)4.5 * usq) + (R)1.5 * w * cg;
-            bstore<T>(Cd::enc(ev + od, enc_scale<P>(a, r)), rB, ES * ((unsigned)r * ps + i));
-            bstore<T>(Cd::enc(ev - od, enc_scale<P>(a, r + 1)), rB, ES * ((unsigned)(r + 1) * ps + i));
+            ob[r] = Cd::enc(ev + od, enc_scale<P>(a, r));
+            ob[r + 1] = Cd::enc(ev - od, enc_scale<P>(a, r + 1));
         }
         // the collision conserves mass: the density deviation of n* is drho
-        bstore<T>(Cd::enc(drho, rho_enc_scale<P>(a)), rRB, ES * i);
+        orho = Cd::enc(drho, rho_enc_scale<P>(a));
         if (!(usq <= (R)0.16)) {
             atomicOr(a.status, ST_UNSTABLE);
             atomicMin(a.bad_step, *a.dstep);
+        }
+        }
+        if (inb) {
+#pragma unroll
+            for (int r = 0; r < 19; r++) bstore<T>(ob[r], rB, ES * ((unsigned)r * ps + i));
+            bstore<T>(orho, rRB, ES * i);
         }
     }
 }

@@ -291,7 +291,8 @@ __device__ inline int scan_chunk(const DevArgs& a, const CellRec& cr, int t, int
     int cnt = 0;
 #pragma unroll
     for (int j = 0; j < ZB; j++) {
-        const bool mine = ow[j] == cr.p;
+        // a node whose 18 neighbours are all non-fluid carries no link
+        const bool mine = ow[j] == cr.p && (fl[j] & LINKBITS) != LINKBITS;
         const unsigned long long m = __ballot(mine);
         if (mine) {
             const int e = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -432,16 +433,34 @@ hipError_t launch_mem_reduce(const DevArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Boundary velocity of every node, written for all nodes so that every line
-// is written whole: a cell node gets the rigid-body velocity of its cell,
-// V + Omega x (s - X) (the moving-boundary term of Eq. 10 uses it), a wall node its plane velocity (zero for resting walls),
-// a fluid node zero.  Runs after the occupancy update of the step.
+// Boundary velocity field: a cell node gets the rigid-body velocity of its
+// cell, V + Omega x (s - X) (the moving-boundary term of Eq. 10 uses it), a
+// wall node its plane velocity (zero for resting walls), a fluid node zero.
+// Runs after the occupancy update of the step.
 template <class M>
-__global__ void usol_kernel(DevArgs a) {
-    const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (s >= a.ns) return;
-    const int o = a.owner[s];
-    const int x = (int)(s % a.nx), y = (int)((s / a.nx) % a.ny), z = (int)(s / ((long long)a.nx * a.ny));
+struct alignas(4 * sizeof(M)) Vel4 {
+    M v[4];
+};
+
+// ALL: every node (at set-up).  Otherwise only groups of 8 consecutive nodes
+// along x (one 128-byte line of the FP32 field) that hold a cell node are
+// written, whole: the field is read only at non-fluid nodes, and wall nodes
+// keep the values written at set-up.
+template <class M, bool ALL>
+__global__ void __launch_bounds__(256) usol_kernel(DevArgs a) {
+    const int lane = (int)(threadIdx.x & 63);
+    const int x = (int)blockIdx.x * 64 + lane;
+    const int y = (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+    const int z = (int)blockIdx.z;
+    const bool in = x < a.nx && y < a.ny;  // uniform over each wave in y, not in x
+    const unsigned s = (unsigned)x + (unsigned)a.nx * ((unsigned)y + (unsigned)a.ny * (unsigned)z);
+    const int o = in ? a.owner[s] : OWN_FLUID;
+    bool wr = in;
+    if (!ALL) {
+        const unsigned long long m = __ballot(o >= 0);
+        wr = in && ((m >> (lane & ~7)) & 0xffull) != 0ull;
+    }
+    if (!wr) return;
     double u[3] = {0, 0, 0};
     if (o >= 0) {
         const double* k = a.kin + 12 * (long long)o;
@@ -453,14 +472,20 @@ __global__ void usol_kernel(DevArgs a) {
         if (y == 0) { u[0] = a.wvb[0]; u[1] = a.wvb[1]; u[2] = a.wvb[2]; }
         else if (y == a.ny - 1) { u[0] = a.wvt[0]; u[1] = a.wvt[1]; u[2] = a.wvt[2]; }
     }
-    M* U = (M*)a.usol + 4 * s;
-    U[0] = (M)u[0]; U[1] = (M)u[1]; U[2] = (M)u[2]; U[3] = (M)0;
+    Vel4<M> v;
+    v.v[0] = (M)u[0]; v.v[1] = (M)u[1]; v.v[2] = (M)u[2]; v.v[3] = (M)0;
+    reinterpret_cast<Vel4<M>*>(a.usol)[s] = v;
 }
 
-hipError_t launch_usol(const DevArgs& a, hipStream_t st) {
-    const dim3 g((unsigned)((a.ns + 255) / 256)), b(256);
-    if (a.precision == CGB_P64) hipLaunchKernelGGL(usol_kernel<double>, g, b, 0, st, a);
-    else hipLaunchKernelGGL(usol_kernel<float>, g, b, 0, st, a);
+hipError_t launch_usol(const DevArgs& a, hipStream_t st, bool all) {
+    const dim3 g((unsigned)((a.nx + 63) / 64), (unsigned)((a.ny + 3) / 4), (unsigned)a.nz), b(256);
+    if (a.precision == CGB_P64) {
+        if (all) hipLaunchKernelGGL((usol_kernel<double, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((usol_kernel<double, false>), g, b, 0, st, a);
+    } else {
+        if (all) hipLaunchKernelGGL((usol_kernel<float, true>), g, b, 0, st, a);
+        else hipLaunchKernelGGL((usol_kernel<float, false>), g, b, 0, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -814,6 +839,25 @@ __device__ void wall_term(const DevArgs& a, const double* rv, const double* o, d
     for (int c = 0; c < 3; c++) Ti[c] -= t[c];
 }
 
+constexpr int POT_BLOCK = 128;
+
+__device__ inline void pair_vec(const DevArgs& a, const double* Xi, int j, double* rv) {
+    rv[0] = min_image(Xi[0] - a.X[3 * j], (double)a.nx);
+    rv[1] = a.wall_y ? (Xi[1] - a.X[3 * j + 1]) : min_image(Xi[1] - a.X[3 * j + 1], (double)a.ny);
+    rv[2] = min_image(Xi[2] - a.X[3 * j + 2], (double)a.nz);
+}
+
+__device__ inline void wall_vec(const DevArgs& a, const double* Xi, unsigned w, double* rv) {
+    // site indices are below 2^32 (checked at create)
+    const unsigned nx = (unsigned)a.nx, ny = (unsigned)a.ny;
+    const int wx = (int)(w % nx), wy = (int)((w / nx) % ny), wz = (int)(w / (nx * ny));
+    double nd[3];
+    node_disp(a, wx, wy, wz, Xi, nd);
+    rv[0] = -nd[0]; rv[1] = -nd[1]; rv[2] = -nd[2];
+}
+
+// Pair and wall forces (Eqs. 16-20), one thread per cell, cells in cell-list
+// order (neighbouring threads share neighbour bins).
 __global__ void potentials_kernel(DevArgs a) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.n) return;
@@ -856,9 +900,92 @@ __global__ void potentials_kernel(DevArgs a) {
     for (int c = 0; c < 3; c++) { a.FTp[6 * i + c] = F[c]; a.FTp[6 * i + 3 + c] = T[c]; }
 }
 
+// The same sums with PG lanes per cell, for lattices with walls: a cell
+// next to a wall screens some hundred wall nodes of its neighbour bins, which
+// one lane would walk alone.  Lane g of a group takes bins g, g + PG, ... and
+// lists its own partners (deterministic order); the group then evaluates the
+// lists and sums over its lanes in a fixed order.
+constexpr int PG = 8;
+constexpr int PG_LIST = 8;
+static_assert(PG >= 6 && PG <= 64 && (PG & (PG - 1)) == 0, "a group's lanes 0-5 write the six sums");
+
+__global__ void __launch_bounds__(POT_BLOCK) potentials_grp_kernel(DevArgs a) {
+    __shared__ int plist[PG_LIST][POT_BLOCK];
+    const int k = (int)((blockIdx.x * (unsigned)POT_BLOCK + threadIdx.x) / PG);
+    const int g = (int)(threadIdx.x % PG);
+    const bool live = k < a.n;  // uniform over each group; groups do not meet
+    const int i = live ? a.bin_idx[k] : 0;
+    const double Xi[3] = {a.X[3 * i], a.X[3 * i + 1], a.X[3 * i + 2]};
+    const double* ki = a.kin + 12 * (long long)i;
+    const double oi[3] = {ki[9], ki[10], ki[11]};
+    double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+    const int b = a.pbin[i];
+    const int bxi = b % a.nb[0], byi = (b / a.nb[0]) % a.nb[1], bzi = b / (a.nb[0] * a.nb[1]);
+    int lx[3], ly[3], lz[3];
+    const int nxb = axis_bins(a, 0, bxi, lx), nyb = axis_bins(a, 1, byi, ly), nzb = axis_bins(a, 2, bzi, lz);
+    const int nbb = live ? nxb * nyb * nzb : 0;
+    int np = 0;
+    for (int q = g; q < nbb; q += PG) {
+        const int ix = q % nxb, iy = (q / nxb) % nyb, iz = q / (nxb * nyb);
+        const int bb = pick3(lx, ix) + a.nb[0] * (pick3(ly, iy) + a.nb[1] * pick3(lz, iz));
+        for (int t = a.bin_start[bb]; t < a.bin_start[bb + 1]; t++) {
+            const int j = a.bin_idx[t];
+            if (j == i) continue;
+            double rv[3];
+            pair_vec(a, Xi, j, rv);
+            if (!(dist2_exact(rv) < a.r_cut2)) continue;
+            if (np < PG_LIST) {
+                plist[np][threadIdx.x] = j;
+            } else {
+                const double* kj = a.kin + 12 * (long long)j;
+                const double oj[3] = {kj[9], kj[10], kj[11]};
+                pair_term(a, rv, oi, oj, F, T);
+            }
+            np++;
+        }
+        for (int t = a.wall_start[bb]; t < a.wall_start[bb + 1]; t++) {
+            double rv[3];
+            wall_vec(a, Xi, (unsigned)a.wall_idx[t], rv);
+            const double r2 = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
+            if (!(r2 < a.wall_range2)) continue;
+            if (np < PG_LIST) plist[np][threadIdx.x] = ~t;
+            else wall_term(a, rv, oi, F, T);
+            np++;
+        }
+    }
+    const int nl = np < PG_LIST ? np : PG_LIST;
+    for (int q = 0; q < nl; q++) {
+        const int e = plist[q][threadIdx.x];
+        double rv[3];
+        if (e >= 0) {
+            pair_vec(a, Xi, e, rv);
+            const double* kj = a.kin + 12 * (long long)e;
+            const double oj[3] = {kj[9], kj[10], kj[11]};
+            pair_term(a, rv, oi, oj, F, T);
+        } else {
+            wall_vec(a, Xi, (unsigned)a.wall_idx[~e], rv);
+            wall_term(a, rv, oi, F, T);
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < PG; off <<= 1)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            F[c] += __shfl_xor(F[c], off, 64);
+            T[c] += __shfl_xor(T[c], off, 64);
+        }
+    if (live && g < 6) {
+        const double v = g == 0 ? F[0] : (g == 1 ? F[1] : (g == 2 ? F[2] : (g == 3 ? T[0] : (g == 4 ? T[1] : T[2]))));
+        a.FTp[6 * i + g] = v;
+    }
+}
+
 hipError_t launch_potentials(const DevArgs& a, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(potentials_kernel, dim3((a.n + 127) / 128), dim3(128), 0, st, a);
+    if (a.nsw > 0)
+        hipLaunchKernelGGL(potentials_grp_kernel, dim3((unsigned)(((long long)a.n * PG + POT_BLOCK - 1) / POT_BLOCK)), dim3(POT_BLOCK), 0, st, a);
+    else
+        hipLaunchKernelGGL(potentials_kernel, dim3((a.n + POT_BLOCK - 1) / POT_BLOCK), dim3(POT_BLOCK), 0, st, a);
     return hipGetLastError();
 }
 

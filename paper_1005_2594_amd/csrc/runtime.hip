@@ -296,7 +296,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
             if (w) own[(size_t)i] = OWN_WALL;
         }
         CK(hipMemcpyAsync(a.owner, own.data(), (size_t)a.ns * 4, hipMemcpyHostToDevice, s->st));
-        CK(launch_usol(a, s->st));
+        CK(launch_usol(a, s->st, true));
         for (long long i = 0; i < a.ns; i++) s->n_nonwall += own[(size_t)i] != OWN_WALL ? 1.0 : 0.0;
         {
             std::vector<double> ys((size_t)a.ny);
@@ -352,6 +352,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
             for (int v : per[(size_t)b]) widx.push_back(v);
         }
         wstart[(size_t)nbins] = (int)widx.size();
+        a.nsw = (int)nsw;
         CK(dalloc(s, &a.wall_start, (size_t)(nbins + 1) * 4));
         CK(dalloc(s, &a.wall_idx, (size_t)std::max<long long>(nsw, 1) * 4));
         CK(hipMemcpyAsync(a.wall_start, wstart.data(), wstart.size() * 4, hipMemcpyHostToDevice, s->st));
@@ -427,7 +428,7 @@ int cgb_set_particles(cgb_sim* s, int32_t n, const double* X, const double* q, c
     HIPCHK(s, launch_cells(a, s->st));  // the per-cell kernels walk the cells in cell-list order
     HIPCHK(s, launch_raster(a, s->st, true));
     HIPCHK(s, launch_transitions(a, s->st, false));
-    HIPCHK(s, launch_usol(a, s->st));
+    HIPCHK(s, launch_usol(a, s->st, true));
     HIPCHK(s, launch_flags_rebuild(a, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     return check_status(s);
@@ -473,7 +474,7 @@ int cgb_step(cgb_sim* s, int32_t nsteps) {
         HIPCHK(s, timed(s, K_RASTER, [&] { return launch_raster(a, s->st, false); }));
         HIPCHK(s, timed(s, K_TRANS, [&] {
             hipError_t e = launch_transitions(a, s->st, true);
-            return e == hipSuccess ? launch_usol(a, s->st) : e;
+            return e == hipSuccess ? launch_usol(a, s->st, false) : e;
         }));
         HIPCHK(s, timed(s, K_LB, [&] { return launch_lb(a, s->lbcfg, s->st); }));
         HIPCHK(s, timed(s, K_MEM, [&] { return launch_mem_reduce(a, s->st); }));
