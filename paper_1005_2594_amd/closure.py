@@ -156,15 +156,18 @@ def time_inference(net, X, n=1 << 20, seed=0, reps=5):
     q = torch.from_numpy(rng.uniform(lo, hi, (n, 3)).astype(np.float32)).cuda()
     mean = torch.empty(n, device="cuda")
     spread = torch.empty(n, device="cuda")
-    st = torch.cuda.current_stream()
-    net.predict_device(n, q.data_ptr(), mean.data_ptr(), spread.data_ptr(), st.cuda_stream)
+    # a stream of its own: handle 0 (torch's default stream) would mean the
+    # network's own stream to the library, not the stream the events are on
+    st = torch.cuda.Stream()
     torch.cuda.synchronize()
+    net.predict_device(n, q.data_ptr(), mean.data_ptr(), spread.data_ptr(), st.cuda_stream)
+    st.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
     for _ in range(reps):
         net.predict_device(n, q.data_ptr(), mean.data_ptr(), spread.data_ptr(), st.cuda_stream)
     e1.record(st)
-    torch.cuda.synchronize()
+    st.synchronize()
     ms = e0.elapsed_time(e1) / reps
     flop = 5 * n * 2 * (3 * 64 + 64 * 64 + 64)
     return dict(points=n, ms=ms, tflops=flop / (ms * 1e-3) / 1e12,

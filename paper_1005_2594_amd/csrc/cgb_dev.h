@@ -93,6 +93,7 @@ struct DevArgs {
     int* bin_start; // nbins+1
     int* bin_fill;  // nbins
     int* bin_idx;   // n
+    double* Xs;     // n*4 positions in cell-list order and the cell index
     int* wall_start;// nbins+1 (surface wall nodes per bin)
     int* wall_idx;  // site indices
     int nsw;        // number of surface wall nodes

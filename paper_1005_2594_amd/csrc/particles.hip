@@ -730,6 +730,19 @@ __global__ void bin_sort_kernel(DevArgs a) {
     }
 }
 
+// positions in cell-list order with the cell's index (exact in a double), so
+// that a candidate is one independent 32-byte load
+struct alignas(32) SortedPos {
+    double x, y, z, id;
+};
+
+__global__ void sorted_pos_kernel(DevArgs a) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n) return;
+    const int j = a.bin_idx[t];
+    ((SortedPos*)a.Xs)[t] = SortedPos{a.X[3 * j], a.X[3 * j + 1], a.X[3 * j + 2], (double)j};
+}
+
 hipError_t launch_cells(const DevArgs& a, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
     hipError_t e = launch_fill_i32(a.bin_count, a.nbins, 0, st);
@@ -741,6 +754,7 @@ hipError_t launch_cells(const DevArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(scan_add_kernel, dim3((a.nbins + 255) / 256), dim3(256), 0, st, a, (const int*)a.scan_tmp);
     hipLaunchKernelGGL(bin_fill_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
     hipLaunchKernelGGL(bin_sort_kernel, dim3((a.nbins + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(sorted_pos_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -841,10 +855,23 @@ __device__ void wall_term(const DevArgs& a, const double* rv, const double* o, d
 
 constexpr int POT_BLOCK = 128;
 
-__device__ inline void pair_vec(const DevArgs& a, const double* Xi, int j, double* rv) {
-    rv[0] = min_image(Xi[0] - a.X[3 * j], (double)a.nx);
-    rv[1] = a.wall_y ? (Xi[1] - a.X[3 * j + 1]) : min_image(Xi[1] - a.X[3 * j + 1], (double)a.ny);
-    rv[2] = min_image(Xi[2] - a.X[3 * j + 2], (double)a.nz);
+// The three x-neighbour bins of a bin row are contiguous in the cell list
+// unless they wrap: ranges [r[0], r[1]) and [r[2], r[3]) of x-bin indices
+// (the second empty when the row does not wrap).
+__device__ inline void row_xranges(const DevArgs& a, int bxi, int* r) {
+    int lx[3];
+    const int nxb = axis_bins(a, 0, bxi, lx);
+    r[2] = r[3] = 0;
+    if (nxb < 3) { r[0] = 0; r[1] = nxb; return; }
+    if (lx[0] < lx[2]) { r[0] = lx[0]; r[1] = lx[2] + 1; return; }
+    if (lx[1] == 0) { r[0] = 0; r[1] = 2; r[2] = lx[0]; r[3] = lx[0] + 1; }
+    else { r[0] = lx[0]; r[1] = lx[1] + 1; r[2] = 0; r[3] = 1; }
+}
+
+__device__ inline void pair_rv(const DevArgs& a, const double* Xi, const SortedPos& e, double* rv) {
+    rv[0] = min_image(Xi[0] - e.x, (double)a.nx);
+    rv[1] = a.wall_y ? (Xi[1] - e.y) : min_image(Xi[1] - e.y, (double)a.ny);
+    rv[2] = min_image(Xi[2] - e.z, (double)a.nz);
 }
 
 __device__ inline void wall_vec(const DevArgs& a, const double* Xi, unsigned w, double* rv) {
@@ -856,110 +883,126 @@ __device__ inline void wall_vec(const DevArgs& a, const double* Xi, unsigned w, 
     rv[0] = -nd[0]; rv[1] = -nd[1]; rv[2] = -nd[2];
 }
 
-// Pair and wall forces (Eqs. 16-20), one thread per cell, cells in cell-list
-// order (neighbouring threads share neighbour bins).
+// Pair forces (Eqs. 16-18) on lattices without walls: one thread per cell,
+// cells in cell-list order (neighbouring threads share neighbour bins).  The
+// candidates of a bin row are read CB at a time with independent loads.
+constexpr int CB = 2;
 __global__ void potentials_kernel(DevArgs a) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.n) return;
-    const int i = a.bin_idx[k];  // cell-list order: neighbouring threads share neighbour bins
-    const double Xi[3] = {a.X[3 * i], a.X[3 * i + 1], a.X[3 * i + 2]};
+    const SortedPos* S = (const SortedPos*)a.Xs;
+    const SortedPos me = S[k];
+    const int i = (int)me.id;
+    const double Xi[3] = {me.x, me.y, me.z};
     const double* ki = a.kin + 12 * (long long)i;
     const double oi[3] = {ki[9], ki[10], ki[11]};
     double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
     const int b = a.pbin[i];
     const int bxi = b % a.nb[0], byi = (b / a.nb[0]) % a.nb[1], bzi = b / (a.nb[0] * a.nb[1]);
-    int lx[3], ly[3], lz[3];
-    const int nxb = axis_bins(a, 0, bxi, lx), nyb = axis_bins(a, 1, byi, ly), nzb = axis_bins(a, 2, bzi, lz);
+    int xr[4], ly[3], lz[3];
+    row_xranges(a, bxi, xr);
+    const int nyb = axis_bins(a, 1, byi, ly), nzb = axis_bins(a, 2, bzi, lz);
     for (int iz = 0; iz < nzb; iz++)
-        for (int iy = 0; iy < nyb; iy++)
-            for (int ix = 0; ix < nxb; ix++) {
-                const int bb = pick3(lx, ix) + a.nb[0] * (pick3(ly, iy) + a.nb[1] * pick3(lz, iz));
-                for (int t = a.bin_start[bb]; t < a.bin_start[bb + 1]; t++) {
-                    const int j = a.bin_idx[t];
-                    if (j == i) continue;
-                    double rv[3];
-                    rv[0] = min_image(Xi[0] - a.X[3 * j], (double)a.nx);
-                    rv[1] = a.wall_y ? (Xi[1] - a.X[3 * j + 1]) : min_image(Xi[1] - a.X[3 * j + 1], (double)a.ny);
-                    rv[2] = min_image(Xi[2] - a.X[3 * j + 2], (double)a.nz);
-                    if (!(dist2_exact(rv) < a.r_cut2)) continue;
-                    const double* kj = a.kin + 12 * (long long)j;
-                    const double oj[3] = {kj[9], kj[10], kj[11]};
-                    pair_term(a, rv, oi, oj, F, T);
-                }
-                for (int t = a.wall_start[bb]; t < a.wall_start[bb + 1]; t++) {
-                    const long long w = a.wall_idx[t];
-                    const int wx = (int)(w % a.nx), wy = (int)((w / a.nx) % a.ny), wz = (int)(w / ((long long)a.nx * a.ny));
-                    double nd[3];
-                    node_disp(a, wx, wy, wz, Xi, nd);
-                    const double rv[3] = {-nd[0], -nd[1], -nd[2]};
-                    const double r2 = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
-                    if (!(r2 < a.wall_range2)) continue;
-                    wall_term(a, rv, oi, F, T);
+        for (int iy = 0; iy < nyb; iy++) {
+            const int row = a.nb[0] * (pick3(ly, iy) + a.nb[1] * pick3(lz, iz));
+            for (int h = 0; h < 2; h++) {
+                const int x0 = h ? xr[2] : xr[0], x1 = h ? xr[3] : xr[1];
+                if (x1 <= x0) continue;
+                const int t0 = a.bin_start[row + x0], t1 = a.bin_start[row + x1];
+                for (int t = t0; t < t1; t += CB) {
+                    SortedPos e[CB];
+#pragma unroll
+                    for (int q = 0; q < CB; q++) e[q] = S[t + q < t1 ? t + q : t1 - 1];
+#pragma unroll
+                    for (int q = 0; q < CB; q++) {
+                        const int j = (int)e[q].id;
+                        if (t + q >= t1 || j == i) continue;
+                        double rv[3];
+                        pair_rv(a, Xi, e[q], rv);
+                        if (!(dist2_exact(rv) < a.r_cut2)) continue;
+                        const double* kj = a.kin + 12 * (long long)j;
+                        const double oj[3] = {kj[9], kj[10], kj[11]};
+                        pair_term(a, rv, oi, oj, F, T);
+                    }
                 }
             }
+        }
     for (int c = 0; c < 3; c++) { a.FTp[6 * i + c] = F[c]; a.FTp[6 * i + 3 + c] = T[c]; }
 }
 
-// The same sums with PG lanes per cell, for lattices with walls: a cell
-// next to a wall screens some hundred wall nodes of its neighbour bins, which
-// one lane would walk alone.  Lane g of a group takes bins g, g + PG, ... and
-// lists its own partners (deterministic order); the group then evaluates the
-// lists and sums over its lanes in a fixed order.
+// Pair and wall forces (Eqs. 16-20) on lattices with walls, PG lanes per
+// cell: a cell next to a wall screens some hundred wall nodes of its
+// neighbour bins.  Lane g of a group takes every PG-th candidate (cell or
+// wall node) of each bin row and lists the ones in range (its own order, so
+// the sums are deterministic); the group then evaluates the lists and sums
+// over its lanes in a fixed order.  A list that overflows evaluates its
+// extra entries on the spot.
 constexpr int PG = 8;
 constexpr int PG_LIST = 8;
 static_assert(PG >= 6 && PG <= 64 && (PG & (PG - 1)) == 0, "a group's lanes 0-5 write the six sums");
 
 __global__ void __launch_bounds__(POT_BLOCK) potentials_grp_kernel(DevArgs a) {
+    // [slot][thread]: a partner j >= 0, or ~t for wall entry t
     __shared__ int plist[PG_LIST][POT_BLOCK];
     const int k = (int)((blockIdx.x * (unsigned)POT_BLOCK + threadIdx.x) / PG);
     const int g = (int)(threadIdx.x % PG);
     const bool live = k < a.n;  // uniform over each group; groups do not meet
-    const int i = live ? a.bin_idx[k] : 0;
-    const double Xi[3] = {a.X[3 * i], a.X[3 * i + 1], a.X[3 * i + 2]};
+    const SortedPos* S = (const SortedPos*)a.Xs;
+    const SortedPos me = S[live ? k : 0];
+    const int i = (int)me.id;
+    const double Xi[3] = {me.x, me.y, me.z};
     const double* ki = a.kin + 12 * (long long)i;
     const double oi[3] = {ki[9], ki[10], ki[11]};
     double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
     const int b = a.pbin[i];
     const int bxi = b % a.nb[0], byi = (b / a.nb[0]) % a.nb[1], bzi = b / (a.nb[0] * a.nb[1]);
-    int lx[3], ly[3], lz[3];
-    const int nxb = axis_bins(a, 0, bxi, lx), nyb = axis_bins(a, 1, byi, ly), nzb = axis_bins(a, 2, bzi, lz);
-    const int nbb = live ? nxb * nyb * nzb : 0;
+    int xr[4], ly[3], lz[3];
+    row_xranges(a, bxi, xr);
+    const int nyb = axis_bins(a, 1, byi, ly), nzb = live ? axis_bins(a, 2, bzi, lz) : 0;
     int np = 0;
-    for (int q = g; q < nbb; q += PG) {
-        const int ix = q % nxb, iy = (q / nxb) % nyb, iz = q / (nxb * nyb);
-        const int bb = pick3(lx, ix) + a.nb[0] * (pick3(ly, iy) + a.nb[1] * pick3(lz, iz));
-        for (int t = a.bin_start[bb]; t < a.bin_start[bb + 1]; t++) {
-            const int j = a.bin_idx[t];
-            if (j == i) continue;
-            double rv[3];
-            pair_vec(a, Xi, j, rv);
-            if (!(dist2_exact(rv) < a.r_cut2)) continue;
-            if (np < PG_LIST) {
-                plist[np][threadIdx.x] = j;
-            } else {
-                const double* kj = a.kin + 12 * (long long)j;
-                const double oj[3] = {kj[9], kj[10], kj[11]};
-                pair_term(a, rv, oi, oj, F, T);
+    for (int iz = 0; iz < nzb; iz++)
+        for (int iy = 0; iy < nyb; iy++) {
+            const int row = a.nb[0] * (pick3(ly, iy) + a.nb[1] * pick3(lz, iz));
+            for (int h = 0; h < 2; h++) {
+                const int x0 = h ? xr[2] : xr[0], x1 = h ? xr[3] : xr[1];
+                if (x1 <= x0) continue;
+                const int t0 = a.bin_start[row + x0], t1 = a.bin_start[row + x1];
+                for (int t = t0 + g; t < t1; t += PG) {
+                    const SortedPos e = S[t];
+                    const int j = (int)e.id;
+                    if (j == i) continue;
+                    double rv[3];
+                    pair_rv(a, Xi, e, rv);
+                    if (!(dist2_exact(rv) < a.r_cut2)) continue;
+                    if (np < PG_LIST) {
+                        plist[np][threadIdx.x] = t;
+                    } else {
+                        const double* kj = a.kin + 12 * (long long)j;
+                        const double oj[3] = {kj[9], kj[10], kj[11]};
+                        pair_term(a, rv, oi, oj, F, T);
+                    }
+                    np++;
+                }
+                const int w0 = a.wall_start[row + x0], w1 = a.wall_start[row + x1];
+                for (int t = w0 + g; t < w1; t += PG) {
+                    double rv[3];
+                    wall_vec(a, Xi, (unsigned)a.wall_idx[t], rv);
+                    const double r2 = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
+                    if (!(r2 < a.wall_range2)) continue;
+                    if (np < PG_LIST) plist[np][threadIdx.x] = ~t;
+                    else wall_term(a, rv, oi, F, T);
+                    np++;
+                }
             }
-            np++;
         }
-        for (int t = a.wall_start[bb]; t < a.wall_start[bb + 1]; t++) {
-            double rv[3];
-            wall_vec(a, Xi, (unsigned)a.wall_idx[t], rv);
-            const double r2 = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
-            if (!(r2 < a.wall_range2)) continue;
-            if (np < PG_LIST) plist[np][threadIdx.x] = ~t;
-            else wall_term(a, rv, oi, F, T);
-            np++;
-        }
-    }
     const int nl = np < PG_LIST ? np : PG_LIST;
     for (int q = 0; q < nl; q++) {
         const int e = plist[q][threadIdx.x];
         double rv[3];
         if (e >= 0) {
-            pair_vec(a, Xi, e, rv);
-            const double* kj = a.kin + 12 * (long long)e;
+            const SortedPos p = S[e];
+            pair_rv(a, Xi, p, rv);
+            const double* kj = a.kin + 12 * (long long)p.id;
             const double oj[3] = {kj[9], kj[10], kj[11]};
             pair_term(a, rv, oi, oj, F, T);
         } else {

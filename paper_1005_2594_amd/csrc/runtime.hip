@@ -189,7 +189,7 @@ static LaunchCfg default_tiles(const DevArgs& a) {
 
 static int alloc_particles(cgb_sim* s, int ncap) {
     DevArgs& a = s->a;
-    void* olds[] = {a.X, a.q, a.V, a.L, a.fixed, a.Xprev, a.Hprev, a.kin, a.crec, a.FTh, a.FTp, a.trans, a.pbin, a.bin_idx, a.body_part};
+    void* olds[] = {a.X, a.q, a.V, a.L, a.fixed, a.Xprev, a.Hprev, a.kin, a.crec, a.FTh, a.FTp, a.trans, a.pbin, a.bin_idx, a.Xs, a.body_part};
     for (void* p : olds) dfree(s, p);
     const size_t n = (size_t)std::max(ncap, 1);
     HIPCHK(s, dalloc(s, &a.X, 3 * n * 8));
@@ -205,6 +205,7 @@ static int alloc_particles(cgb_sim* s, int ncap) {
     HIPCHK(s, dalloc(s, &a.FTp, 6 * n * 8));
     HIPCHK(s, dalloc(s, &a.pbin, n * 4));
     HIPCHK(s, dalloc(s, &a.bin_idx, n * 4));
+    HIPCHK(s, dalloc(s, &a.Xs, n * 4 * 8));
     HIPCHK(s, dalloc(s, &a.body_part, ((n + 255) / 256) * 3 * 8));
     HIPCHK(s, launch_fill_f64(a.body_part, (long long)((n + 255) / 256) * 3, 0.0, s->st));
     long long cap = 96LL * (long long)n + 65536;
