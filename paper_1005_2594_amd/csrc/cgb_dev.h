@@ -109,7 +109,7 @@ struct DevArgs {
     double* body_part; // per-block partial sums of the body force on cells
     // moving bounce-back and momentum exchange (element type: FP64 for P64,
     // FP32 otherwise)
-    void* usol;        // [pstride][4]: velocity (x, y, z, -) of every non-fluid
+    void* usol;        // [3][pstride]: velocity planes (x, y, z) of every non-fluid
                        // node: the rigid-body velocity of its cell at the node,
                        // or the wall velocity
     void* crec;        // [n] CellRec, in cell-list order (per-cell kernels)

@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(256) track_kernel(DevArgs a) {
             const double gz = a.force_mode == 1 ? a.g[2] : (a.force_mode == 2 ? a.f0 * a.ysin[y] : 0.0);
             uz = (jz - 0.5 * gz) / (a.rho0 + drho);
         } else {
-            uz = (double)U[4 * s + 2];
+            uz = (double)U[2 * (long long)a.pstride + s];
         }
         ss += uz * a.ysin[y];
         s1 += uz;

@@ -36,20 +36,22 @@ constexpr unsigned OOB = 0xfffffff0u;  // byte offset past every buffer: loads r
 
 // source-node velocity components along the nonzero components of c_r, for
 // the link directions (the other directions load from the out-of-range
-// offset and read 0); u(s) is stored as [4] per node in the link type M
+// offset and read 0); u(s) is stored as three component planes [3][pstride]
+// in the link type M, so that the lanes of a wave gathering one component
+// from a row of source nodes touch few cache lines
 template <class M>
 struct LinkVel {
     M a[19], b[19];
 };
 
 template <class M, class SrcF>
-__device__ inline void issue_link_loads(__amdgpu_buffer_rsrc_t rU, uint32_t links, SrcF src, LinkVel<M>& lv) {
+__device__ inline void issue_link_loads(__amdgpu_buffer_rsrc_t rU, unsigned ps, uint32_t links, SrcF src, LinkVel<M>& lv) {
 #pragma unroll
     for (int r = 1; r < 19; r++) {
         const bool lk = (links >> r) & 1u;
-        const unsigned base = 4u * src(r);
-        lv.a[r] = bload<M>(rU, lk ? (unsigned)sizeof(M) * (base + comp1(r)) : OOB);
-        if (comp2(r) >= 0) lv.b[r] = bload<M>(rU, lk ? (unsigned)sizeof(M) * (base + comp2(r)) : OOB);
+        const unsigned sr = src(r);
+        lv.a[r] = bload<M>(rU, lk ? (unsigned)sizeof(M) * ((unsigned)comp1(r) * ps + sr) : OOB);
+        if (comp2(r) >= 0) lv.b[r] = bload<M>(rU, lk ? (unsigned)sizeof(M) * ((unsigned)comp2(r) * ps + sr) : OOB);
     }
 }
 
@@ -80,7 +82,7 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
     const auto rB = make_rsrc(a.B, 19ull * ps * ES);
     const auto rRA = make_rsrc(a.rhoA, (unsigned long long)ps * ES);
     const auto rRB = make_rsrc(a.rhoB, (unsigned long long)ps * ES);
-    const auto rU = make_rsrc(a.usol, 4ull * ps * sizeof(M));
+    const auto rU = make_rsrc(a.usol, 3ull * ps * sizeof(M));
     // offset from x to the pull source x - c along each axis (periodic wrap);
     // index 0: c = -1, 1: c = 0, 2: c = +1
     const int ox[3] = {x == a.nx - 1 ? -(a.nx - 1) : 1, 0, x == 0 ? a.nx - 1 : -1};
@@ -121,7 +123,7 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
             v[r] = bload<T>(rA, ES * (bb ? (unsigned)OPP(r) * ps + i : (unsigned)r * ps + src(r)));
         }
         LinkVel<M> lv;
-        issue_link_loads<M>(rU, links, src, lv);
+        issue_link_loads<M>(rU, ps, links, src, lv);
         const T rstored = bload<T>(rRA, links ? ES * i : OOB);
 
         R d[19];
@@ -197,7 +199,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
     const auto rRA = make_rsrc(a.rhoA, (unsigned long long)ps * ES);
     const auto rRB = make_rsrc(a.rhoB, (unsigned long long)ps * ES);
     const auto rFl = make_rsrc(a.flags, (unsigned long long)a.ns * 4);
-    const auto rU = make_rsrc(a.usol, 4ull * ps * sizeof(M));
+    const auto rU = make_rsrc(a.usol, 3ull * ps * sizeof(M));
     const int ox[3] = {x == a.nx - 1 ? -(a.nx - 1) : 1, 0, x == 0 ? a.nx - 1 : -1};
     const int oy[3] = {y == a.ny - 1 ? -(int)((a.ny - 1) * nx) : (int)nx, 0, y == 0 ? (int)((a.ny - 1) * nx) : -(int)nx};
     // body force at this plane: constant, or f0 sin(2 pi y/ny) from the table
@@ -238,7 +240,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
             v[r] = bload<T>(rA, ES * (bb ? (unsigned)OPP(r) * ps + i : (unsigned)r * ps + src(r)));
         }
         LinkVel<M> lv;
-        issue_link_loads<M>(rU, links, src, lv);
+        issue_link_loads<M>(rU, ps, links, src, lv);
         const T rstored = bload<T>(rRA, links ? ES * i : OOB);
 
         R drho = 0, jx = 0, jy = 0, jz = 0;

@@ -437,15 +437,10 @@ hipError_t launch_mem_reduce(const DevArgs& a, hipStream_t st) {
 // cell, V + Omega x (s - X) (the moving-boundary term of Eq. 10 uses it), a
 // wall node its plane velocity (zero for resting walls), a fluid node zero.
 // Runs after the occupancy update of the step.
-template <class M>
-struct alignas(4 * sizeof(M)) Vel4 {
-    M v[4];
-};
-
-// ALL: every node (at set-up).  Otherwise only groups of 8 consecutive nodes
-// along x (one 128-byte line of the FP32 field) that hold a cell node are
-// written, whole: the field is read only at non-fluid nodes, and wall nodes
-// keep the values written at set-up.
+// ALL: every node (at set-up).  Otherwise only groups of 32 consecutive nodes
+// along x (one 128-byte line of an FP32 component plane) that hold a cell
+// node are written, whole: the field is read only at non-fluid nodes, and
+// wall nodes keep the values written at set-up.  Layout [3][pstride].
 template <class M, bool ALL>
 __global__ void __launch_bounds__(256) usol_kernel(DevArgs a) {
     const int lane = (int)(threadIdx.x & 63);
@@ -458,7 +453,7 @@ __global__ void __launch_bounds__(256) usol_kernel(DevArgs a) {
     bool wr = in;
     if (!ALL) {
         const unsigned long long m = __ballot(o >= 0);
-        wr = in && ((m >> (lane & ~7)) & 0xffull) != 0ull;
+        wr = in && ((m >> (lane & ~31)) & 0xffffffffull) != 0ull;
     }
     if (!wr) return;
     double u[3] = {0, 0, 0};
@@ -472,9 +467,11 @@ __global__ void __launch_bounds__(256) usol_kernel(DevArgs a) {
         if (y == 0) { u[0] = a.wvb[0]; u[1] = a.wvb[1]; u[2] = a.wvb[2]; }
         else if (y == a.ny - 1) { u[0] = a.wvt[0]; u[1] = a.wvt[1]; u[2] = a.wvt[2]; }
     }
-    Vel4<M> v;
-    v.v[0] = (M)u[0]; v.v[1] = (M)u[1]; v.v[2] = (M)u[2]; v.v[3] = (M)0;
-    reinterpret_cast<Vel4<M>*>(a.usol)[s] = v;
+    M* U = (M*)a.usol;
+    const size_t ps = (size_t)a.pstride;
+    U[s] = (M)u[0];
+    U[ps + s] = (M)u[1];
+    U[2 * ps + s] = (M)u[2];
 }
 
 hipError_t launch_usol(const DevArgs& a, hipStream_t st, bool all) {

@@ -280,7 +280,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
         CK(dalloc(s, &s->rho[1], (size_t)a.pstride * s->esize));
         CK(dalloc(s, &a.owner, (size_t)a.ns * 4));
         const size_t msz = p->precision == CGB_P64 ? 8 : 4;
-        CK(dalloc(s, &a.usol, 4 * (size_t)a.pstride * msz));
+        CK(dalloc(s, &a.usol, 3 * (size_t)a.pstride * msz));
         CK(dalloc(s, &a.flags, (size_t)a.ns * 4));
         CK(dalloc(s, &a.cand, (size_t)a.ns * 4));
         CK(dalloc(s, &a.ntrans, TSEG * 4));
