@@ -109,7 +109,9 @@ struct DevArgs {
     double* body_part; // per-block partial sums of the body force on cells
     // moving bounce-back and momentum exchange (element type: FP64 for P64,
     // FP32 otherwise)
-    void* usol;        // [3][pstride]: velocity planes (x, y, z) of every non-fluid
+    void* lmom;        // tau = 1: [4][pstride] link moments of each fluid node
+                       // with links (sum w q, sum w c q; q = c . u(source))
+    void* usol;        // tau != 1: [3][pstride]: velocity planes (x, y, z) of every non-fluid
                        // node: the rigid-body velocity of its cell at the node,
                        // or the wall velocity
     void* crec;        // [n] CellRec, in cell-list order (per-cell kernels)
@@ -303,6 +305,7 @@ struct LaunchCfg {
 hipError_t launch_lb(const DevArgs& a, LaunchCfg cfg, hipStream_t st);
 hipError_t launch_mem_reduce(const DevArgs& a, hipStream_t st);
 hipError_t launch_usol(const DevArgs& a, hipStream_t st, bool all);
+hipError_t launch_lmom(const DevArgs& a, hipStream_t st);
 hipError_t launch_prep(const DevArgs& a, hipStream_t st);
 hipError_t launch_kin(const DevArgs& a, hipStream_t st);
 hipError_t launch_clear_cells(const DevArgs& a, hipStream_t st);

@@ -163,7 +163,7 @@ static dim3 site_grid(const DevArgs& a) { return dim3((unsigned)((a.ns + 255) / 
 // non-wall nodes, weighted by sin(2 pi y/ny) and by 1: fluid nodes carry the
 // velocity of the collision, u_z = (sum n* c_z - g_z/2)/rho (the forcing adds
 // exactly g to sum n* c), cell nodes the rigid-body velocity of their cell
-// that the bounce-back used (the boundary velocity field).  Fixed grid and
+// that the bounce-back used (from the cell's kinematics, FP64).  Fixed grid and
 // fixed per-thread site sets, block partials reduced in a fixed order: the
 // sums are deterministic.
 template <int P>
@@ -174,7 +174,6 @@ __global__ void __launch_bounds__(256) track_kernel(DevArgs a) {
     __shared__ double red[2][256];
     const T* B = (const T*)a.B;
     const T* RB = (const T*)a.rhoB;
-    const M* U = (const M*)a.usol;
     double ss = 0.0, s1 = 0.0;
     for (long long s = blockIdx.x * 256LL + threadIdx.x; s < a.ns; s += (long long)TRACK_BLOCKS * 256) {
         const int o = a.owner[s];
@@ -190,7 +189,12 @@ __global__ void __launch_bounds__(256) track_kernel(DevArgs a) {
             const double gz = a.force_mode == 1 ? a.g[2] : (a.force_mode == 2 ? a.f0 * a.ysin[y] : 0.0);
             uz = (jz - 0.5 * gz) / (a.rho0 + drho);
         } else {
-            uz = (double)U[2 * (long long)a.pstride + s];
+            // the rigid-body velocity of the node's cell
+            const double* k = a.kin + 12 * (long long)o;
+            const int x = (int)((unsigned)s % (unsigned)a.nx), z = (int)((unsigned)s / ((unsigned)a.nx * (unsigned)a.ny));
+            double d[3];
+            node_disp(a, x, y, z, k, d);
+            uz = k[5] + (k[6] * d[1] - k[7] * d[0]);
         }
         ss += uz * a.ysin[y];
         s1 += uz;

@@ -9,9 +9,14 @@
 // cell, v_b = V + Omega x (x - c_r/2 - X) at the link midpoint; because
 // c_r . (Omega x c_r) = 0, c_r . v_b equals c_r . u(s) with
 // u(s) = V + Omega x (s - X), the rigid-body velocity at the source node.
-// A node-parallel kernel stores u(s) for every cell node after the
-// occupancy update and walls hold their plane velocity, so a link needs no
-// knowledge of which body is behind it.
+// At tau = 1 the corrections enter only through their sums over the links,
+// sum C_r = 6 rho(x) sum w_r q_r and sum C_r c_r = 6 rho(x) sum w_r c_r q_r
+// (q_r = c_r . u(s_r)): a stencil kernel stores these moments at each fluid
+// node with links after the occupancy update, and the LB reads them with one
+// coalesced load.  For general tau the per-direction values are needed: a
+// node-parallel kernel stores u(s) for every cell node and walls hold their
+// plane velocity, and the LB gathers the velocity of each link's source.  In
+// neither case does a link need to know which body is behind it.
 //
 // Momentum exchange (Eq. 12) is summed per cell by a separate kernel from
 // the same stored populations and boundary velocities (the bounced
@@ -199,7 +204,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
     const auto rRA = make_rsrc(a.rhoA, (unsigned long long)ps * ES);
     const auto rRB = make_rsrc(a.rhoB, (unsigned long long)ps * ES);
     const auto rFl = make_rsrc(a.flags, (unsigned long long)a.ns * 4);
-    const auto rU = make_rsrc(a.usol, 3ull * ps * sizeof(M));
+    const auto rK = make_rsrc(a.lmom, 4ull * ps * sizeof(M));
     const int ox[3] = {x == a.nx - 1 ? -(a.nx - 1) : 1, 0, x == 0 ? a.nx - 1 : -1};
     const int oy[3] = {y == a.ny - 1 ? -(int)((a.ny - 1) * nx) : (int)nx, 0, y == 0 ? (int)((a.ny - 1) * nx) : -(int)nx};
     // body force at this plane: constant, or f0 sin(2 pi y/ny) from the table
@@ -231,16 +236,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
         auto src = [&](int r) { return i + (unsigned)(ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1]); };
         const uint32_t links = f & LINKBITS;
 
-        // issue the 19 pulls (non-fluid source: bounce-back), the source
-        // velocities of the links and the node's stored density together
+        // issue the 19 pulls (non-fluid source: bounce-back), the node's link
+        // moments and its stored density together
         T v[19];
 #pragma unroll
         for (int r = 0; r < 19; r++) {
             const bool bb = (f >> r) & 1u;
             v[r] = bload<T>(rA, ES * (bb ? (unsigned)OPP(r) * ps + i : (unsigned)r * ps + src(r)));
         }
-        LinkVel<M> lv;
-        issue_link_loads<M>(rU, ps, links, src, lv);
+        M km[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) km[c] = bload<M>(rK, links ? (unsigned)sizeof(M) * ((unsigned)c * ps + i) : OOB);
         const T rstored = bload<T>(rRA, links ? ES * i : OOB);
 
         R drho = 0, jx = 0, jy = 0, jz = 0;
@@ -253,19 +259,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
             if (CZ(r)) jz += CZ(r) * dv;
         }
         if (links) {
-            // moving-boundary corrections (zero for resting walls and for the
-            // directions that are not links)
-            const M rho_x = (M)a.rho0 + (M)Cd::dec(rstored, rho_dec_scale<P>(a));
-            M c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-#pragma unroll
-            for (int r = 1; r < 19; r++) {
-                const M C = (M)(6.0 * WD(r)) * rho_x * link_cu<M>(lv, r);
-                c0 += C;
-                if (CX(r)) c1 += CX(r) * C;
-                if (CY(r)) c2 += CY(r) * C;
-                if (CZ(r)) c3 += CZ(r) * C;
-            }
-            drho += (R)c0; jx += (R)c1; jy += (R)c2; jz += (R)c3;
+            // moving-boundary corrections summed over the links:
+            // sum C_r = 6 rho(x) K0, sum C_r c_r = 6 rho(x) (K1, K2, K3)
+            const M rho6 = (M)6 * ((M)a.rho0 + (M)Cd::dec(rstored, rho_dec_scale<P>(a)));
+            drho += (R)(rho6 * km[0]); jx += (R)(rho6 * km[1]); jy += (R)(rho6 * km[2]); jz += (R)(rho6 * km[3]);
         }
 
         // n* = n^eq(rho, u) + Guo term (tau = 1), for opposite pairs r, rbar:

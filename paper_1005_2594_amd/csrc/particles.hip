@@ -486,6 +486,140 @@ hipError_t launch_usol(const DevArgs& a, hipStream_t st, bool all) {
     return hipGetLastError();
 }
 
+// tau = 1: moments of the moving-boundary corrections of every fluid node
+// with links.  C_r = 6 w_r rho(x) (c_r . u(s_r)) (Eq. 10, u(s) the velocity of
+// the non-fluid source s_r = x - c_r) enters the tau = 1 collision only
+// through sum_r C_r and sum_r C_r c_r, and rho(x) factors out: the node needs
+// K = (sum_r w_r q_r, sum_r w_r c_r q_r), q_r = c_r . u(s_r), over its links.
+// A workgroup covers a 64 x 4 patch and sweeps LM_TZ planes; the velocity of
+// the patch and a one-node halo is built in LDS three planes at a time from
+// the owner map and the cells' kinematics (FP64, rounded to the link type as
+// the stored velocity field is), so the link sources are read from LDS.
+// Groups of 32 nodes along x (one 128-byte line of an FP32 plane) that hold a
+// node with links are written whole; layout [4][pstride].
+constexpr int LM_TX = 64, LM_TY = 4, LM_TZ = 16;
+constexpr int LM_HX = LM_TX + 2, LM_HY = LM_TY + 2;
+constexpr int LM_NP = LM_HX * LM_HY;  // halo'd plane positions, at most 2 per thread
+static_assert(LM_NP <= 512, "two positions per thread");
+
+// v in [-1, n + 63] reduced to [0, n)
+__device__ inline int wrap_halo(int v, int n) {
+    if (v < 0) v += n;
+    if (v >= n) v -= n;
+    if (v >= n) v %= n;  // lattices narrower than a patch
+    return v;
+}
+
+// site of halo'd plane position q (q < LM_NP) of the patch at (x0, y0), plane z
+__device__ inline unsigned lm_site(const DevArgs& a, int q, int x0, int y0, int z, int* x, int* y) {
+    const int hx = q % LM_HX, hy = q / LM_HX;
+    *x = wrap_halo(x0 - 1 + hx, a.nx);
+    *y = wrap_halo(y0 - 1 + hy, a.ny);
+    return (unsigned)*x + (unsigned)a.nx * ((unsigned)*y + (unsigned)a.ny * (unsigned)z);
+}
+
+// velocity of position q with owner o, written to the plane in slot sl
+template <class M>
+__device__ inline void lm_vel(const DevArgs& a, M (*U)[3][LM_HY][LM_HX], int sl, int q, int o, int x, int y, int z) {
+    double u[3] = {0, 0, 0};
+    if (o >= 0) {
+        const double* k = a.kin + 12 * (long long)o;
+        double d[3];
+        node_disp(a, x, y, z, k, d);
+        cross3(k + 6, d, u);
+        for (int c = 0; c < 3; c++) u[c] += k[3 + c];
+    } else if (o == OWN_WALL && a.wall_y) {
+        if (y == 0) { u[0] = a.wvb[0]; u[1] = a.wvb[1]; u[2] = a.wvb[2]; }
+        else if (y == a.ny - 1) { u[0] = a.wvt[0]; u[1] = a.wvt[1]; u[2] = a.wvt[2]; }
+    }
+    const int hx = q % LM_HX, hy = q / LM_HX;
+    U[sl][0][hy][hx] = (M)u[0];
+    U[sl][1][hy][hx] = (M)u[1];
+    U[sl][2][hy][hx] = (M)u[2];
+}
+
+// owners of the two positions of this thread in plane z (OWN_FLUID past the plane)
+__device__ inline void lm_owners(const DevArgs& a, int x0, int y0, int z, int* o0, int* o1) {
+    int x, y;
+    const int q0 = (int)threadIdx.x, q1 = (int)threadIdx.x + 256;
+    *o0 = a.owner[lm_site(a, q0, x0, y0, z, &x, &y)];
+    *o1 = q1 < LM_NP ? a.owner[lm_site(a, q1, x0, y0, z, &x, &y)] : OWN_FLUID;
+}
+
+template <class M>
+__device__ inline void lm_build(const DevArgs& a, M (*U)[3][LM_HY][LM_HX], int sl, int x0, int y0, int z, int o0, int o1) {
+    int x, y;
+    const int q0 = (int)threadIdx.x, q1 = (int)threadIdx.x + 256;
+    lm_site(a, q0, x0, y0, z, &x, &y);
+    lm_vel<M>(a, U, sl, q0, o0, x, y, z);
+    if (q1 < LM_NP) {
+        lm_site(a, q1, x0, y0, z, &x, &y);
+        lm_vel<M>(a, U, sl, q1, o1, x, y, z);
+    }
+}
+
+template <class M>
+__global__ void __launch_bounds__(256) lmom_kernel(DevArgs a) {
+    __shared__ M U[3][3][LM_HY][LM_HX];
+    const int tx = (int)(threadIdx.x & 63), ty = (int)(threadIdx.x >> 6);
+    const int x0 = (int)blockIdx.x * LM_TX, y0 = (int)blockIdx.y * LM_TY, z0 = (int)blockIdx.z * LM_TZ;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool in = x < a.nx && y < a.ny;
+    const int zend = a.nz - z0 < LM_TZ ? a.nz - z0 : LM_TZ;
+    M* K = (M*)a.lmom;
+    const size_t ps = (size_t)a.pstride;
+    // plane p lives in slot (p - z0 + 1) mod 3; owners are read one plane ahead
+    int o0, o1, n0, n1;
+    lm_owners(a, x0, y0, wrap_halo(z0 - 1, a.nz), &o0, &o1);
+    lm_owners(a, x0, y0, z0, &n0, &n1);
+    lm_build<M>(a, U, 0, x0, y0, wrap_halo(z0 - 1, a.nz), o0, o1);
+    lm_owners(a, x0, y0, wrap_halo(z0 + 1, a.nz), &o0, &o1);
+    lm_build<M>(a, U, 1, x0, y0, z0, n0, n1);
+    for (int zz = 0; zz < zend; zz++) {
+        const int z = z0 + zz;
+        const unsigned s = (unsigned)x + (unsigned)a.nx * ((unsigned)y + (unsigned)a.ny * (unsigned)z);
+        const uint32_t f = in ? a.flags[s] : NONFLUID;
+        if (zz + 1 < zend) lm_owners(a, x0, y0, wrap_halo(z + 2, a.nz), &n0, &n1);
+        lm_build<M>(a, U, (zz + 2) % 3, x0, y0, wrap_halo(z + 1, a.nz), o0, o1);
+        o0 = n0; o1 = n1;
+        __syncthreads();
+        const bool lk = !(f & NONFLUID) && (f & LINKBITS) != 0u;
+        const unsigned long long m = __ballot(lk);
+        if (in && ((m >> (tx & ~31)) & 0xffffffffull) != 0ull) {
+            // sums over the links (directions that are not links weigh 0)
+            M k0 = 0, k1 = 0, k2 = 0, k3 = 0;
+#pragma unroll
+            for (int r = 1; r < 19; r++) {
+                const int sl = (zz + 1 - CZ(r) + 3) % 3;
+                const int hx = tx + 1 - CX(r), hy = ty + 1 - CY(r);
+                M q = 0;
+                if (CX(r)) q += (M)CX(r) * U[sl][0][hy][hx];
+                if (CY(r)) q += (M)CY(r) * U[sl][1][hy][hx];
+                if (CZ(r)) q += (M)CZ(r) * U[sl][2][hy][hx];
+                const M wq = (lk && ((f >> r) & 1u)) ? (M)WD(r) * q : (M)0;
+                k0 += wq;
+                if (CX(r)) k1 += (M)CX(r) * wq;
+                if (CY(r)) k2 += (M)CY(r) * wq;
+                if (CZ(r)) k3 += (M)CZ(r) * wq;
+            }
+            K[s] = k0;
+            K[ps + s] = k1;
+            K[2 * ps + s] = k2;
+            K[3 * ps + s] = k3;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_lmom(const DevArgs& a, hipStream_t st) {
+    const dim3 g((unsigned)((a.nx + LM_TX - 1) / LM_TX), (unsigned)((a.ny + LM_TY - 1) / LM_TY),
+                 (unsigned)((a.nz + LM_TZ - 1) / LM_TZ)),
+        b(256);
+    if (a.precision == CGB_P64) hipLaunchKernelGGL(lmom_kernel<double>, g, b, 0, st, a);
+    else hipLaunchKernelGGL(lmom_kernel<float>, g, b, 0, st, a);
+    return hipGetLastError();
+}
+
 __global__ void zero_int_kernel(int* p) { *p = 0; }
 
 // start of a time step: clear the transition list and advance the device-side

@@ -280,7 +280,12 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
         CK(dalloc(s, &s->rho[1], (size_t)a.pstride * s->esize));
         CK(dalloc(s, &a.owner, (size_t)a.ns * 4));
         const size_t msz = p->precision == CGB_P64 ? 8 : 4;
-        CK(dalloc(s, &a.usol, 3 * (size_t)a.pstride * msz));
+        if (p->tau == 1.0) {
+            CK(dalloc(s, &a.lmom, 4 * (size_t)a.pstride * msz));
+            CK(hipMemsetAsync(a.lmom, 0, 4 * (size_t)a.pstride * msz, s->st));
+        } else {
+            CK(dalloc(s, &a.usol, 3 * (size_t)a.pstride * msz));
+        }
         CK(dalloc(s, &a.flags, (size_t)a.ns * 4));
         CK(dalloc(s, &a.cand, (size_t)a.ns * 4));
         CK(dalloc(s, &a.ntrans, TSEG * 4));
@@ -297,7 +302,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
             if (w) own[(size_t)i] = OWN_WALL;
         }
         CK(hipMemcpyAsync(a.owner, own.data(), (size_t)a.ns * 4, hipMemcpyHostToDevice, s->st));
-        CK(launch_usol(a, s->st, true));
+        if (a.usol) CK(launch_usol(a, s->st, true));
         for (long long i = 0; i < a.ns; i++) s->n_nonwall += own[(size_t)i] != OWN_WALL ? 1.0 : 0.0;
         {
             std::vector<double> ys((size_t)a.ny);
@@ -368,6 +373,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
         bind_buffers(s);
         CK(launch_equilibrium_fill(a, nullptr, nullptr, s->st));
         CK(launch_flags_rebuild(a, s->st));
+        if (a.lmom) CK(launch_lmom(a, s->st));
         CK(hipStreamSynchronize(s->st));
         s->fluid_ready = true;
     }
@@ -429,8 +435,8 @@ int cgb_set_particles(cgb_sim* s, int32_t n, const double* X, const double* q, c
     HIPCHK(s, launch_cells(a, s->st));  // the per-cell kernels walk the cells in cell-list order
     HIPCHK(s, launch_raster(a, s->st, true));
     HIPCHK(s, launch_transitions(a, s->st, false));
-    HIPCHK(s, launch_usol(a, s->st, true));
     HIPCHK(s, launch_flags_rebuild(a, s->st));
+    HIPCHK(s, a.lmom ? launch_lmom(a, s->st) : launch_usol(a, s->st, true));
     HIPCHK(s, hipStreamSynchronize(s->st));
     return check_status(s);
 }
@@ -475,7 +481,7 @@ int cgb_step(cgb_sim* s, int32_t nsteps) {
         HIPCHK(s, timed(s, K_RASTER, [&] { return launch_raster(a, s->st, false); }));
         HIPCHK(s, timed(s, K_TRANS, [&] {
             hipError_t e = launch_transitions(a, s->st, true);
-            return e == hipSuccess ? launch_usol(a, s->st, false) : e;
+            return e != hipSuccess ? e : (a.lmom ? launch_lmom(a, s->st) : launch_usol(a, s->st, false));
         }));
         HIPCHK(s, timed(s, K_LB, [&] { return launch_lb(a, s->lbcfg, s->st); }));
         HIPCHK(s, timed(s, K_MEM, [&] { return launch_mem_reduce(a, s->st); }));
@@ -896,6 +902,10 @@ int cgb_load(cgb_sim* s, const char* path) {
     HIPCHK(s, launch_fill_i32(a.dstep, 1, (int)step - 1, s->st));
     HIPCHK(s, launch_fill_i32(a.cand, a.ns, NO_CAND, s->st));
     HIPCHK(s, launch_cells(a, s->st));
+    // boundary data of the loaded state (the next step recomputes it; a timed
+    // LB launch before that step reads it)
+    HIPCHK(s, launch_kin(a, s->st));
+    HIPCHK(s, a.lmom ? launch_lmom(a, s->st) : launch_usol(a, s->st, true));
     HIPCHK(s, hipStreamSynchronize(s->st));
     return CGB_OK;
 }
