@@ -491,18 +491,20 @@ hipError_t launch_usol(const DevArgs& a, hipStream_t st, bool all) {
 // the non-fluid source s_r = x - c_r) enters the tau = 1 collision only
 // through sum_r C_r and sum_r C_r c_r, and rho(x) factors out: the node needs
 // K = (sum_r w_r q_r, sum_r w_r c_r q_r), q_r = c_r . u(s_r), over its links.
-// A workgroup covers a 64 x 4 patch and sweeps LM_TZ planes; the velocity of
-// the patch and a one-node halo is built in LDS three planes at a time from
+// A workgroup covers a TX x (256 / TX) patch and sweeps tz planes; the velocity
+// of the patch and a one-node halo is built in LDS three planes at a time from
 // the owner map and the cells' kinematics (FP64, rounded to the link type as
 // the stored velocity field is), so the link sources are read from LDS.
 // Groups of 32 nodes along x (one 128-byte line of an FP32 plane) that hold a
 // node with links are written whole; layout [4][pstride].
-constexpr int LM_TX = 64, LM_TY = 4, LM_TZ = 16;
-constexpr int LM_HX = LM_TX + 2, LM_HY = LM_TY + 2;
-constexpr int LM_NP = LM_HX * LM_HY;  // halo'd plane positions, at most 2 per thread
-static_assert(LM_NP <= 512, "two positions per thread");
+// patch: TX x (256 / TX) nodes of an x-y plane, swept over tz planes
+template <int TX>
+struct LmShape {
+    static constexpr int TY = 256 / TX, HX = TX + 2, HY = TY + 2, NP = HX * HY;
+    static_assert(NP <= 512, "two positions per thread");
+};
 
-// v in [-1, n + 63] reduced to [0, n)
+// v in [-1, n + TX - 1] reduced to [0, n)
 __device__ inline int wrap_halo(int v, int n) {
     if (v < 0) v += n;
     if (v >= n) v -= n;
@@ -510,17 +512,20 @@ __device__ inline int wrap_halo(int v, int n) {
     return v;
 }
 
-// site of halo'd plane position q (q < LM_NP) of the patch at (x0, y0), plane z
+// site of halo'd plane position q of the patch at (x0, y0), plane z
+template <int TX>
 __device__ inline unsigned lm_site(const DevArgs& a, int q, int x0, int y0, int z, int* x, int* y) {
-    const int hx = q % LM_HX, hy = q / LM_HX;
+    using S = LmShape<TX>;
+    const int hx = q % S::HX, hy = q / S::HX;
     *x = wrap_halo(x0 - 1 + hx, a.nx);
     *y = wrap_halo(y0 - 1 + hy, a.ny);
     return (unsigned)*x + (unsigned)a.nx * ((unsigned)*y + (unsigned)a.ny * (unsigned)z);
 }
 
 // velocity of position q with owner o, written to the plane in slot sl
-template <class M>
-__device__ inline void lm_vel(const DevArgs& a, M (*U)[3][LM_HY][LM_HX], int sl, int q, int o, int x, int y, int z) {
+template <class M, int TX>
+__device__ inline void lm_vel(const DevArgs& a, M* U, int sl, int q, int o, int x, int y, int z) {
+    using S = LmShape<TX>;
     double u[3] = {0, 0, 0};
     if (o >= 0) {
         const double* k = a.kin + 12 * (long long)o;
@@ -532,70 +537,72 @@ __device__ inline void lm_vel(const DevArgs& a, M (*U)[3][LM_HY][LM_HX], int sl,
         if (y == 0) { u[0] = a.wvb[0]; u[1] = a.wvb[1]; u[2] = a.wvb[2]; }
         else if (y == a.ny - 1) { u[0] = a.wvt[0]; u[1] = a.wvt[1]; u[2] = a.wvt[2]; }
     }
-    const int hx = q % LM_HX, hy = q / LM_HX;
-    U[sl][0][hy][hx] = (M)u[0];
-    U[sl][1][hy][hx] = (M)u[1];
-    U[sl][2][hy][hx] = (M)u[2];
+    M* P = U + (size_t)sl * 3 * S::NP;
+    P[q] = (M)u[0];
+    P[S::NP + q] = (M)u[1];
+    P[2 * S::NP + q] = (M)u[2];
 }
 
-// owners of the two positions of this thread in plane z (OWN_FLUID past the plane)
+// owners of the two positions of this thread in plane z
+template <int TX>
 __device__ inline void lm_owners(const DevArgs& a, int x0, int y0, int z, int* o0, int* o1) {
     int x, y;
     const int q0 = (int)threadIdx.x, q1 = (int)threadIdx.x + 256;
-    *o0 = a.owner[lm_site(a, q0, x0, y0, z, &x, &y)];
-    *o1 = q1 < LM_NP ? a.owner[lm_site(a, q1, x0, y0, z, &x, &y)] : OWN_FLUID;
+    *o0 = a.owner[lm_site<TX>(a, q0, x0, y0, z, &x, &y)];
+    *o1 = q1 < LmShape<TX>::NP ? a.owner[lm_site<TX>(a, q1, x0, y0, z, &x, &y)] : OWN_FLUID;
 }
 
-template <class M>
-__device__ inline void lm_build(const DevArgs& a, M (*U)[3][LM_HY][LM_HX], int sl, int x0, int y0, int z, int o0, int o1) {
+template <class M, int TX>
+__device__ inline void lm_build(const DevArgs& a, M* U, int sl, int x0, int y0, int z, int o0, int o1) {
     int x, y;
     const int q0 = (int)threadIdx.x, q1 = (int)threadIdx.x + 256;
-    lm_site(a, q0, x0, y0, z, &x, &y);
-    lm_vel<M>(a, U, sl, q0, o0, x, y, z);
-    if (q1 < LM_NP) {
-        lm_site(a, q1, x0, y0, z, &x, &y);
-        lm_vel<M>(a, U, sl, q1, o1, x, y, z);
+    lm_site<TX>(a, q0, x0, y0, z, &x, &y);
+    lm_vel<M, TX>(a, U, sl, q0, o0, x, y, z);
+    if (q1 < LmShape<TX>::NP) {
+        lm_site<TX>(a, q1, x0, y0, z, &x, &y);
+        lm_vel<M, TX>(a, U, sl, q1, o1, x, y, z);
     }
 }
 
-template <class M>
-__global__ void __launch_bounds__(256) lmom_kernel(DevArgs a) {
-    __shared__ M U[3][3][LM_HY][LM_HX];
-    const int tx = (int)(threadIdx.x & 63), ty = (int)(threadIdx.x >> 6);
-    const int x0 = (int)blockIdx.x * LM_TX, y0 = (int)blockIdx.y * LM_TY, z0 = (int)blockIdx.z * LM_TZ;
+template <class M, int TX>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(M) == 4 ? 8 : 5))) lmom_kernel(DevArgs a, int tz) {
+    using S = LmShape<TX>;
+    __shared__ M U[3 * 3 * S::NP];  // [slot][component][HY][HX]
+    const int tx = (int)(threadIdx.x % TX), ty = (int)(threadIdx.x / TX);
+    const int x0 = (int)blockIdx.x * TX, y0 = (int)blockIdx.y * S::TY, z0 = (int)blockIdx.z * tz;
     const int x = x0 + tx, y = y0 + ty;
     const bool in = x < a.nx && y < a.ny;
-    const int zend = a.nz - z0 < LM_TZ ? a.nz - z0 : LM_TZ;
+    const int zend = a.nz - z0 < tz ? a.nz - z0 : tz;
     M* K = (M*)a.lmom;
     const size_t ps = (size_t)a.pstride;
+    const int lane = (int)(threadIdx.x & 63);
     // plane p lives in slot (p - z0 + 1) mod 3; owners are read one plane ahead
     int o0, o1, n0, n1;
-    lm_owners(a, x0, y0, wrap_halo(z0 - 1, a.nz), &o0, &o1);
-    lm_owners(a, x0, y0, z0, &n0, &n1);
-    lm_build<M>(a, U, 0, x0, y0, wrap_halo(z0 - 1, a.nz), o0, o1);
-    lm_owners(a, x0, y0, wrap_halo(z0 + 1, a.nz), &o0, &o1);
-    lm_build<M>(a, U, 1, x0, y0, z0, n0, n1);
+    lm_owners<TX>(a, x0, y0, wrap_halo(z0 - 1, a.nz), &o0, &o1);
+    lm_owners<TX>(a, x0, y0, z0, &n0, &n1);
+    lm_build<M, TX>(a, U, 0, x0, y0, wrap_halo(z0 - 1, a.nz), o0, o1);
+    lm_owners<TX>(a, x0, y0, wrap_halo(z0 + 1, a.nz), &o0, &o1);
+    lm_build<M, TX>(a, U, 1, x0, y0, z0, n0, n1);
     for (int zz = 0; zz < zend; zz++) {
         const int z = z0 + zz;
         const unsigned s = (unsigned)x + (unsigned)a.nx * ((unsigned)y + (unsigned)a.ny * (unsigned)z);
         const uint32_t f = in ? a.flags[s] : NONFLUID;
-        if (zz + 1 < zend) lm_owners(a, x0, y0, wrap_halo(z + 2, a.nz), &n0, &n1);
-        lm_build<M>(a, U, (zz + 2) % 3, x0, y0, wrap_halo(z + 1, a.nz), o0, o1);
+        if (zz + 1 < zend) lm_owners<TX>(a, x0, y0, wrap_halo(z + 2, a.nz), &n0, &n1);
+        lm_build<M, TX>(a, U, (zz + 2) % 3, x0, y0, wrap_halo(z + 1, a.nz), o0, o1);
         o0 = n0; o1 = n1;
         __syncthreads();
         const bool lk = !(f & NONFLUID) && (f & LINKBITS) != 0u;
         const unsigned long long m = __ballot(lk);
-        if (in && ((m >> (tx & ~31)) & 0xffffffffull) != 0ull) {
+        if (in && ((m >> (lane & ~31)) & 0xffffffffull) != 0ull) {
             // sums over the links (directions that are not links weigh 0)
             M k0 = 0, k1 = 0, k2 = 0, k3 = 0;
 #pragma unroll
             for (int r = 1; r < 19; r++) {
-                const int sl = (zz + 1 - CZ(r) + 3) % 3;
-                const int hx = tx + 1 - CX(r), hy = ty + 1 - CY(r);
+                const M* P = U + (size_t)((zz + 1 - CZ(r) + 3) % 3) * 3 * S::NP + (ty + 1 - CY(r)) * S::HX + (tx + 1 - CX(r));
                 M q = 0;
-                if (CX(r)) q += (M)CX(r) * U[sl][0][hy][hx];
-                if (CY(r)) q += (M)CY(r) * U[sl][1][hy][hx];
-                if (CZ(r)) q += (M)CZ(r) * U[sl][2][hy][hx];
+                if (CX(r)) q += (M)CX(r) * P[0];
+                if (CY(r)) q += (M)CY(r) * P[S::NP];
+                if (CZ(r)) q += (M)CZ(r) * P[2 * S::NP];
                 const M wq = (lk && ((f >> r) & 1u)) ? (M)WD(r) * q : (M)0;
                 k0 += wq;
                 if (CX(r)) k1 += (M)CX(r) * wq;
@@ -611,12 +618,20 @@ __global__ void __launch_bounds__(256) lmom_kernel(DevArgs a) {
     }
 }
 
+// patch width 32 on lattices at most 48 wide; a short sweep when long sweeps
+// would leave the device with few workgroups
 hipError_t launch_lmom(const DevArgs& a, hipStream_t st) {
-    const dim3 g((unsigned)((a.nx + LM_TX - 1) / LM_TX), (unsigned)((a.ny + LM_TY - 1) / LM_TY),
-                 (unsigned)((a.nz + LM_TZ - 1) / LM_TZ)),
-        b(256);
-    if (a.precision == CGB_P64) hipLaunchKernelGGL(lmom_kernel<double>, g, b, 0, st, a);
-    else hipLaunchKernelGGL(lmom_kernel<float>, g, b, 0, st, a);
+    const int tx = a.nx <= 48 ? 32 : 64, ty = 256 / tx;
+    const long long patches = (long long)((a.nx + tx - 1) / tx) * ((a.ny + ty - 1) / ty);
+    const int tz = patches * ((a.nz + 15) / 16) >= 2048 ? 16 : 4;
+    const dim3 g((unsigned)((a.nx + tx - 1) / tx), (unsigned)((a.ny + ty - 1) / ty), (unsigned)((a.nz + tz - 1) / tz)), b(256);
+    if (a.precision == CGB_P64) {
+        if (tx == 32) hipLaunchKernelGGL((lmom_kernel<double, 32>), g, b, 0, st, a, tz);
+        else hipLaunchKernelGGL((lmom_kernel<double, 64>), g, b, 0, st, a, tz);
+    } else {
+        if (tx == 32) hipLaunchKernelGGL((lmom_kernel<float, 32>), g, b, 0, st, a, tz);
+        else hipLaunchKernelGGL((lmom_kernel<float, 64>), g, b, 0, st, a, tz);
+    }
     return hipGetLastError();
 }
 

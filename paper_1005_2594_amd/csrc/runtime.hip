@@ -180,7 +180,7 @@ static void set_tiles(cgb_sim* s, LaunchCfg cfg) {
 }
 
 static LaunchCfg default_tiles(const DevArgs& a) {
-    LaunchCfg c{a.nx >= 128 ? 128 : 64, a.nx >= 128 ? 2 : 4, 16};
+    LaunchCfg c{a.nx >= 256 ? 256 : (a.nx >= 128 ? 128 : 64), a.nx >= 256 ? 1 : (a.nx >= 128 ? 2 : 4), 16};
     if (a.nx < 48) c = LaunchCfg{32, 8, 16};
     if (a.nx < 24) c = LaunchCfg{16, 16, 16};
     if (a.nz < 32) c.tz = 8;
