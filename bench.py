@@ -34,7 +34,7 @@ import synth  # noqa: E402
 
 METRIC = "MLUPS at 256³ Ht=0.4, mixed vs FP32 at stated error; % of HBM peak"
 HBM_PEAK_GBS = 8000.0
-STORE_BYTES = {"p64": 8, "p32": 4, "pmx16": 2, "pmxbf16": 2}
+STORE_BYTES = {"p64": 8, "p32": 4, "pmx16": 2, "pmxbf16": 2, "pmx16s": 2}
 LB_SOURCE = os.path.join(ROOT, "paper_1005_2594_amd", "csrc", "lb.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lb_traffic_pmx16_256.txt")
 
@@ -98,13 +98,13 @@ def error_report_64(seed=3, horizons=(100, 250, 500)):
     the long-horizon measures."""
     from paper_1005_2594_amd import Sim
     cfg = synth.config3_companion(seed=seed)
-    precs = ("p64", "p32", "pmx16")
+    precs = ("p64", "p32", "pmx16", "pmx16s")
     sims = {p: Sim(cfg["params"], precision=p) for p in precs}
     for s in sims.values():
         s.set_particles(cfg["X"], cfg["q"])
         s.init_fluid()
         s.track(horizons[-1])
-    res = {p: {} for p in ("p32", "pmx16")}
+    res = {p: {} for p in precs[1:]}
     done = 0
     for t in horizons:
         for s in sims.values():
@@ -114,7 +114,7 @@ def error_report_64(seed=3, horizons=(100, 250, 500)):
         _, u64 = sims["p64"].fields()
         X64 = sims["p64"].particles()[0]
         pr64 = sims["p64"].profile_z()
-        for p in ("p32", "pmx16"):
+        for p in precs[1:]:
             own = sims[p].owner()
             _, u = sims[p].fields()
             X = sims[p].particles()[0]
@@ -128,7 +128,7 @@ def error_report_64(seed=3, horizons=(100, 250, 500)):
                 owner_flips=int((own != own64).sum()))
     first = horizons[-1] // 2
     mu = {p: sims[p].mu_rel(first=first) for p in precs}
-    for p in ("p32", "pmx16"):
+    for p in precs[1:]:
         res[p]["mu_rel"] = mu[p]
         res[p]["mu_rel_rel_err"] = abs(mu[p] - mu["p64"]) / abs(mu["p64"])
     res["p64_mu_rel"] = mu["p64"]
@@ -229,7 +229,7 @@ def main():
     cfg = synth.config3(n=args.n)
     ns = args.n ** 3
     results = {}
-    for prec in ([args.only] if args.only else ["pmx16", "p32"]):
+    for prec in ([args.only] if args.only else ["pmx16", "pmx16s", "p32"]):
         r = run_gpu(cfg, prec, args.steps, args.warmup)
         results[prec] = r
         print(f"# {prec}: {r['seconds'] * 1e3 / args.steps:.3f} ms/step, "
@@ -275,13 +275,18 @@ def main():
             "avg_launch_ms": round(lb_avg_s * 1e3, 5),
         },
     }
-    if "p32" in results and head != "p32":
-        r32 = results["p32"]
-        line["config"]["p32_mlups"] = round(ns * args.steps / r32["seconds"] / 1e6, 1)
-        line["config"]["p32_ms_per_step"] = round(r32["seconds"] * 1e3 / args.steps, 4)
-        l32, c32 = r32["kernel_times"].get("lb", (float("nan"), 1))
-        line["config"]["p32_lb_frac"] = round(lb_algorithmic_bytes(r32["n_fluid"], ns, "p32") /
-                                              (l32 / max(c32, 1) / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    # the other storage precisions of the same workload: FP32, and FP16 with
+    # the per-node density split out of the residuals
+    for other in ("p32", "pmx16s"):
+        if other not in results or other == head:
+            continue
+        ro = results[other]
+        line["config"][f"{other}_mlups"] = round(ns * args.steps / ro["seconds"] / 1e6, 1)
+        line["config"][f"{other}_ms_per_step"] = round(ro["seconds"] * 1e3 / args.steps, 4)
+        lo, co = ro["kernel_times"].get("lb", (float("nan"), 1))
+        line["config"][f"{other}_lb_ms"] = round(lo / max(co, 1), 5)
+        line["config"][f"{other}_lb_frac"] = round(lb_algorithmic_bytes(ro["n_fluid"], ns, other) /
+                                                   (lo / max(co, 1) / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     if not args.no_error:
         line["config"]["error_vs_p64_64cube"] = error_report_64()
     if not args.no_batch:

@@ -41,6 +41,14 @@ extern "C" {
 #define CGB_P32 1      /* FP32 storage, FP32 collision                          */
 #define CGB_PMX16 2    /* FP16 scaled deviations, FP32 collision                */
 #define CGB_PMXBF16 3  /* BF16 scaled deviations, FP32 collision                */
+#define CGB_PMX16S 4   /* FP16 deviations split per node, FP32 collision: the
+                          node's density deviation D = rho - rho0 is stored once
+                          (FP16, the density field every PMX mode keeps) and each
+                          direction stores the FP16 residual d_r / w_r - D, so
+                          d_r = w_r (D + residual).  The common part of the 19
+                          deviations (the density fluctuation) no longer sets the
+                          FP16 rounding of the velocity-carrying part; 2 bytes per
+                          population as in CGB_PMX16                         */
 /* In every precision the momentum exchange, the per-cell force/torque sums,
  * the pair forces and the rigid-body integrator run in FP64. */
 
@@ -64,9 +72,10 @@ typedef struct cgb_params {
     double eps, eps_w;          /* potential strengths                        */
     double r_cut;               /* pair cut-off (hard truncation of Eq. 15)   */
     double rho_p;               /* cell mass density                          */
-    int32_t precision;          /* CGB_P64 ... CGB_PMXBF16                    */
-    double pmx_scale;           /* PMX: stored value = d_r / w_r * pmx_scale;
-                                   0 selects 32768                            */
+    int32_t precision;          /* CGB_P64 ... CGB_PMX16S                     */
+    double pmx_scale;           /* PMX: stored value = d_r / w_r * pmx_scale
+                                   (PMX16S: (d_r / w_r - D) * pmx_scale, and the
+                                   density field D * pmx_scale); 0 selects 32768 */
 } cgb_params;
 
 typedef struct cgb_sim cgb_sim;

@@ -14,8 +14,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcgb.so")
 
-P64, P32, PMX16, PMXBF16 = 0, 1, 2, 3
-PRECISIONS = {"p64": P64, "p32": P32, "pmx16": PMX16, "pmxbf16": PMXBF16}
+P64, P32, PMX16, PMXBF16, PMX16S = 0, 1, 2, 3, 4
+PRECISIONS = {"p64": P64, "p32": P32, "pmx16": PMX16, "pmxbf16": PMXBF16, "pmx16s": PMX16S}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSTABLE", -5: "ESTATE"}
 
 

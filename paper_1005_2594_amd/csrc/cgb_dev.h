@@ -179,9 +179,22 @@ template <> __device__ inline void bstore<uint16_t>(uint16_t v, __amdgpu_buffer_
     __builtin_amdgcn_raw_buffer_store_b16(v, r, off, 0, 0);
 }
 
+// v in [-1, n + patch width - 1] reduced to [0, n)
+__device__ inline int wrap_halo(int v, int n) {
+    if (v < 0) v += n;
+    if (v >= n) v -= n;
+    if (v >= n) v %= n;  // lattices narrower than a patch
+    return v;
+}
+
 // ------------------------------------------------------------ codecs
 // P64 / P32: plain values.  PMX: d / w_r * scale stored in FP16 or BF16 with
-// round-to-nearest-even; decode multiplies by w_r / scale.
+// round-to-nearest-even; decode multiplies by w_r / scale.  PMX16S (split):
+// the node's density deviation D is stored once (the density field) and each
+// direction stores (d_r / w_r - D) * scale in FP16, so d_r = w_r (D + residual);
+// every reader of a population also reads the density field of the node that
+// wrote it.  The density field of every mode holds the density deviation of
+// the stored populations (Eq. 7 minus rho0).
 __device__ inline uint16_t f32_to_bf16_rne(float f) {
     uint32_t u = __float_as_uint(f);
     if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN stays NaN
@@ -194,52 +207,83 @@ template <int P> struct Codec;
 template <> struct Codec<CGB_P64> {
     using T = double;
     using R = double;
+    static constexpr bool SPLIT = false;
     __device__ static R dec(T v, R) { return v; }
     __device__ static T enc(R v, R) { return v; }
 };
 template <> struct Codec<CGB_P32> {
     using T = float;
     using R = float;
+    static constexpr bool SPLIT = false;
     __device__ static R dec(T v, R) { return v; }
     __device__ static T enc(R v, R) { return v; }
 };
 template <> struct Codec<CGB_PMX16> {
     using T = _Float16;
     using R = float;
+    static constexpr bool SPLIT = false;
     __device__ static R dec(T v, R s) { return (float)v * s; }
     __device__ static T enc(R v, R s) { return (_Float16)(v * s); }
 };
 template <> struct Codec<CGB_PMXBF16> {
     using T = uint16_t;
     using R = float;
+    static constexpr bool SPLIT = false;
     __device__ static R dec(T v, R s) { return bf16_to_f32(v) * s; }
     __device__ static T enc(R v, R s) { return f32_to_bf16_rne(v * s); }
 };
+template <> struct Codec<CGB_PMX16S> : Codec<CGB_PMX16> {
+    static constexpr bool SPLIT = true;
+};
+
+template <int P> constexpr bool is_pmx() { return P == CGB_PMX16 || P == CGB_PMXBF16 || P == CGB_PMX16S; }
 
 // per-direction decode / encode scales
 template <int P>
 __device__ inline typename Codec<P>::R dec_scale(const DevArgs& a, int r) {
     using R = typename Codec<P>::R;
-    if constexpr (P == CGB_PMX16 || P == CGB_PMXBF16) return (R)(WD(r) * (double)a.pmx_inv);
+    if constexpr (is_pmx<P>()) return (R)(WD(r) * (double)a.pmx_inv);
     else return (R)1;
 }
 template <int P>
 __device__ inline typename Codec<P>::R enc_scale(const DevArgs& a, int r) {
     using R = typename Codec<P>::R;
-    if constexpr (P == CGB_PMX16 || P == CGB_PMXBF16) return (R)((double)a.pmx_scale / WD(r));
+    if constexpr (is_pmx<P>()) return (R)((double)a.pmx_scale / WD(r));
     else return (R)1;
 }
 template <int P>
 __device__ inline typename Codec<P>::R rho_dec_scale(const DevArgs& a) {
     using R = typename Codec<P>::R;
-    if constexpr (P == CGB_PMX16 || P == CGB_PMXBF16) return (R)a.pmx_inv;
+    if constexpr (is_pmx<P>()) return (R)a.pmx_inv;
     else return (R)1;
 }
 template <int P>
 __device__ inline typename Codec<P>::R rho_enc_scale(const DevArgs& a) {
     using R = typename Codec<P>::R;
-    if constexpr (P == CGB_PMX16 || P == CGB_PMXBF16) return (R)a.pmx_scale;
+    if constexpr (is_pmx<P>()) return (R)a.pmx_scale;
     else return (R)1;
+}
+
+// density deviation D of a stored density value
+template <int P>
+__device__ inline typename Codec<P>::R rho_dec(const DevArgs& a, typename Codec<P>::T v) {
+    return Codec<P>::dec(v, rho_dec_scale<P>(a));
+}
+// deviation d_r of stored population v of direction r at a node whose stored
+// density deviation is D (D is ignored unless the codec splits)
+template <int P>
+__device__ inline typename Codec<P>::R pop_dec(const DevArgs& a, typename Codec<P>::T v, int r, typename Codec<P>::R D) {
+    using R = typename Codec<P>::R;
+    if constexpr (Codec<P>::SPLIT) return (R)WD(r) * (Codec<P>::dec(v, (R)a.pmx_inv) + D);
+    else return Codec<P>::dec(v, dec_scale<P>(a, r));
+}
+// stored value of deviation d of direction r at a node whose stored density
+// deviation decodes to D
+template <int P>
+__device__ inline typename Codec<P>::T pop_enc(const DevArgs& a, typename Codec<P>::R d, int r, typename Codec<P>::R D) {
+    using R = typename Codec<P>::R;
+    if constexpr (Codec<P>::SPLIT) return Codec<P>::enc(d - (R)WD(r) * D, enc_scale<P>(a, r));
+    else return Codec<P>::enc(d, enc_scale<P>(a, r));
 }
 
 // ------------------------------------------------------------ geometry

@@ -13,13 +13,22 @@ __global__ void encode_kernel(DevArgs a, const double* d) {
     const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (s >= a.ns) return;
     T* A = (T*)a.A;
+    R Dq = 0;
+    if constexpr (Cd::SPLIT) {
+        // the density first; the residuals are taken against its decoded value
+        double dr = 0;
+        for (int r = 0; r < 19; r++) dr += d[r * a.ns + s];
+        const T st = Cd::enc((R)dr, rho_enc_scale<P>(a));
+        ((T*)a.rhoA)[s] = st;
+        Dq = rho_dec<P>(a, st);
+    }
     R rs = 0;
     for (int r = 0; r < 19; r++) {
-        const T v = Cd::enc((R)d[r * a.ns + s], enc_scale<P>(a, r));
+        const T v = pop_enc<P>(a, (R)d[r * a.ns + s], r, Dq);
         A[r * a.pstride + s] = v;
-        rs += Cd::dec(v, dec_scale<P>(a, r));
+        rs += pop_dec<P>(a, v, r, Dq);
     }
-    ((T*)a.rhoA)[s] = Cd::enc(rs, rho_enc_scale<P>(a));
+    if constexpr (!Cd::SPLIT) ((T*)a.rhoA)[s] = Cd::enc(rs, rho_enc_scale<P>(a));
 }
 
 template <int P>
@@ -29,7 +38,8 @@ __global__ void decode_kernel(DevArgs a, double* d) {
     const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (s >= a.ns) return;
     const T* A = (const T*)a.A;
-    for (int r = 0; r < 19; r++) d[r * a.ns + s] = (double)Cd::dec(A[r * a.pstride + s], dec_scale<P>(a, r));
+    const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[s]);
+    for (int r = 0; r < 19; r++) d[r * a.ns + s] = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
 }
 
 // Eq. 5 at (rho, u) on every non-wall node, written as n^eq - w rho0
@@ -45,16 +55,23 @@ __global__ void equilibrium_kernel(DevArgs a, const double* rho, const double* u
     const double rr = rho ? rho[s] : a.rho0;
     const double ux = u ? u[3 * s] : 0.0, uy = u ? u[3 * s + 1] : 0.0, uz = u ? u[3 * s + 2] : 0.0;
     const double usq = ux * ux + uy * uy + uz * uz;
+    R Dq = 0;
+    if constexpr (Cd::SPLIT) {
+        // Eq. 5 conserves the density: the density deviation is rho - rho0
+        const T st = Cd::enc(wall ? (R)0 : (R)(rr - a.rho0), rho_enc_scale<P>(a));
+        ((T*)a.rhoA)[s] = st;
+        Dq = rho_dec<P>(a, st);
+    }
     R rs = 0;
     for (int r = 0; r < 19; r++) {
         const double cu = CX(r) * ux + CY(r) * uy + CZ(r) * uz;
         const double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq + 4.5 * cu * cu * cu - 4.5 * usq * cu;
         const double eq = wall ? 0.0 : WD(r) * ((rr - a.rho0) + rr * poly);
-        const T v = Cd::enc((R)eq, enc_scale<P>(a, r));
+        const T v = pop_enc<P>(a, (R)eq, r, Dq);
         A[r * a.pstride + s] = v;
-        rs += Cd::dec(v, dec_scale<P>(a, r));
+        rs += pop_dec<P>(a, v, r, Dq);
     }
-    ((T*)a.rhoA)[s] = Cd::enc(rs, rho_enc_scale<P>(a));
+    if constexpr (!Cd::SPLIT) ((T*)a.rhoA)[s] = Cd::enc(rs, rho_enc_scale<P>(a));
 }
 
 // rho = rho0 + sum d, u = (sum d c - g/2) / rho on fluid nodes
@@ -70,9 +87,10 @@ __global__ void fields_kernel(DevArgs a, double* rho, double* u) {
         return;
     }
     const T* A = (const T*)a.A;
+    const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[s]);
     double drho = 0, j[3] = {0, 0, 0};
     for (int r = 0; r < 19; r++) {
-        const double v = (double)Cd::dec(A[r * a.pstride + s], dec_scale<P>(a, r));
+        const double v = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
         drho += v;
         j[0] += v * CX(r); j[1] += v * CY(r); j[2] += v * CZ(r);
     }
@@ -93,9 +111,10 @@ __global__ void __launch_bounds__(256) observables_kernel(DevArgs a, double* par
     const T* A = (const T*)a.A;
     for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < a.ns; s += (long long)gridDim.x * blockDim.x) {
         if (a.owner[s] != OWN_FLUID) continue;
+        const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[s]);
         double drho = 0;
         for (int r = 0; r < 19; r++) {
-            const double v = (double)Cd::dec(A[r * a.pstride + s], dec_scale<P>(a, r));
+            const double v = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
             drho += v;
             acc[1] += v * CX(r); acc[2] += v * CY(r); acc[3] += v * CZ(r);
         }
@@ -129,9 +148,10 @@ __global__ void profile_kernel(DevArgs a, double* prof, double* cnt) {
     double uz;
     if (o == OWN_FLUID) {
         const T* A = (const T*)a.A;
+        const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[s]);
         double drho = 0, jz = 0;
         for (int r = 0; r < 19; r++) {
-            const double v = (double)Cd::dec(A[r * a.pstride + s], dec_scale<P>(a, r));
+            const double v = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
             drho += v;
             jz += v * CZ(r);
         }
@@ -154,6 +174,7 @@ __global__ void profile_kernel(DevArgs a, double* prof, double* cnt) {
         case CGB_P32: hipLaunchKernelGGL(KERNEL<CGB_P32>, GRID, BLOCK, 0, st, __VA_ARGS__); break;   \
         case CGB_PMX16: hipLaunchKernelGGL(KERNEL<CGB_PMX16>, GRID, BLOCK, 0, st, __VA_ARGS__); break; \
         case CGB_PMXBF16: hipLaunchKernelGGL(KERNEL<CGB_PMXBF16>, GRID, BLOCK, 0, st, __VA_ARGS__); break; \
+        case CGB_PMX16S: hipLaunchKernelGGL(KERNEL<CGB_PMX16S>, GRID, BLOCK, 0, st, __VA_ARGS__); break; \
         default: return hipErrorInvalidValue;                                                        \
     }
 
@@ -182,10 +203,11 @@ __global__ void __launch_bounds__(256) track_kernel(DevArgs a) {
         double uz;
         if (o == OWN_FLUID) {
             double jz = 0.0;
+            const M Ds = rho_dec<P>(a, RB[s]);
 #pragma unroll
             for (int r = 5; r < 19; r++)
-                if (CZ(r)) jz += CZ(r) * (double)Cd::dec(B[r * a.pstride + s], dec_scale<P>(a, r));
-            const double drho = (double)Cd::dec(RB[s], rho_dec_scale<P>(a));
+                if (CZ(r)) jz += CZ(r) * (double)pop_dec<P>(a, B[r * a.pstride + s], r, Ds);
+            const double drho = (double)Ds;
             const double gz = a.force_mode == 1 ? a.g[2] : (a.force_mode == 2 ? a.f0 * a.ysin[y] : 0.0);
             uz = (jz - 0.5 * gz) / (a.rho0 + drho);
         } else {

@@ -127,15 +127,26 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
             const bool bb = (f >> r) & 1u;
             v[r] = bload<T>(rA, ES * (bb ? (unsigned)OPP(r) * ps + i : (unsigned)r * ps + src(r)));
         }
+        // split codec: the density of each pulled population's source node
+        T vs[19];
+        if constexpr (Cd::SPLIT) {
+#pragma unroll
+            for (int r = 1; r < 19; r++) vs[r] = bload<T>(rRA, ((f >> r) & 1u) ? OOB : ES * src(r));
+        }
         LinkVel<M> lv;
         issue_link_loads<M>(rU, ps, links, src, lv);
-        const T rstored = bload<T>(rRA, links ? ES * i : OOB);
+        const T rstored = bload<T>(rRA, (links || Cd::SPLIT) ? ES * i : OOB);
+        const R Down = rho_dec<P>(a, rstored);
 
         R d[19];
 #pragma unroll
-        for (int r = 0; r < 19; r++) d[r] = Cd::dec(v[r], dec_scale<P>(a, r));
+        for (int r = 0; r < 19; r++) {
+            R Ds = Down;
+            if constexpr (Cd::SPLIT) if (r > 0 && !((f >> r) & 1u)) Ds = rho_dec<P>(a, vs[r]);
+            d[r] = pop_dec<P>(a, v[r], r, Ds);
+        }
         if (links) {
-            const M rho_x = (M)a.rho0 + (M)Cd::dec(rstored, rho_dec_scale<P>(a));
+            const M rho_x = (M)a.rho0 + (M)Down;
 #pragma unroll
             for (int r = 1; r < 19; r++) d[r] += (R)((M)(6.0 * WD(r)) * rho_x * link_cu<M>(lv, r));
         }
@@ -154,6 +165,14 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
         const R ux = (jx + (R)0.5 * gx) * irho, uy = (jy + (R)0.5 * gy) * irho, uz = (jz + (R)0.5 * gz) * irho;
         const R usq = ux * ux + uy * uy + uz * uz;
         const R ug = ux * gx + uy * gy + uz * gz;
+        // split codec: the density is stored first and the residuals are
+        // taken against its decoded value (the collision conserves mass);
+        // otherwise the density of the stored populations is stored
+        R Dq = 0;
+        if constexpr (Cd::SPLIT) {
+            orho = Cd::enc(drho, rho_enc_scale<P>(a));
+            Dq = rho_dec<P>(a, orho);
+        }
         R rsum = 0;
 #pragma unroll
         for (int r = 0; r < 19; r++) {
@@ -164,11 +183,11 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
             const R eq = w * (drho + rho * poly);
             const R Fr = pref * w * ((R)3 * (cg - ug) + (R)9 * cu * cg);
             const R out = d[r] - (d[r] - eq) * omega + Fr;
-            const T st = Cd::enc(out, enc_scale<P>(a, r));
+            const T st = pop_enc<P>(a, out, r, Dq);
             ob[r] = st;
-            rsum += Cd::dec(st, dec_scale<P>(a, r));
+            if constexpr (!Cd::SPLIT) rsum += Cd::dec(st, dec_scale<P>(a, r));
         }
-        orho = Cd::enc(rsum, rho_enc_scale<P>(a));
+        if constexpr (!Cd::SPLIT) orho = Cd::enc(rsum, rho_enc_scale<P>(a));
         if (!(usq <= (R)0.16)) {
             atomicOr(a.status, ST_UNSTABLE);
             atomicMin(a.bad_step, *a.dstep);
@@ -181,6 +200,43 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
         }
     }
 }
+
+// Split codec: every pulled population is decoded with the density of the
+// node it comes from.  The decoded density field of the block's patch plus a
+// one-node halo is kept in LDS for four consecutive planes (a ring: planes
+// z - 1, z, z + 1 are read while z + 2 is written), each plane filled once
+// from one coalesced pass and read 19 times from LDS.  Patches have at most
+// 256 nodes, so a halo'd plane has at most (256 + 2) x 3 positions and each
+// thread fills at most four of them.
+constexpr int RING_NP = 774;
+
+template <int P>
+struct DensRing {
+    using T = typename Codec<P>::T;
+    int hx, np, nthr, t, x0, y0;
+    T pre[4];
+    __device__ DensRing(int bx, int by, int tid, int x0_, int y0_)
+        : hx(bx + 2), np((bx + 2) * (by + 2)), nthr(bx * by), t(tid), x0(x0_), y0(y0_) {}
+    // issue the loads of plane pz (wrapped) into registers
+    __device__ void load(const DevArgs& a, __amdgpu_buffer_rsrc_t rRA, int pz) {
+        constexpr unsigned ES = sizeof(T);
+        const unsigned base = (unsigned)a.nx * (unsigned)a.ny * (unsigned)pz;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int q = t + k * nthr;
+            const int xs = wrap_halo(x0 - 1 + q % hx, a.nx), ys = wrap_halo(y0 - 1 + q / hx, a.ny);
+            pre[k] = bload<T>(rRA, q < np ? ES * (base + (unsigned)xs + (unsigned)a.nx * (unsigned)ys) : 0xfffffff0u);
+        }
+    }
+    // decode the loaded plane into ring slot sl
+    __device__ void put(const DevArgs& a, float* L, int sl) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int q = t + k * nthr;
+            if (q < np) L[sl * RING_NP + q] = (float)rho_dec<P>(a, pre[k]);
+        }
+    }
+};
 
 // tau = 1 (the paper's operating point, Sec. IV): the post-collision state is
 // n^eq(rho, u) plus the forcing term, a function of the moments alone, so the
@@ -213,12 +269,31 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
     const R gy = a.force_mode == 1 ? (R)a.g[1] : (R)0;
     const R gz = a.force_mode == 1 ? (R)a.g[2] : (a.force_mode == 2 ? (R)(a.f0 * a.ysin[yc]) : (R)0);
 
+    // split codec: density ring (planes z0 - 1 and z0 now, z0 + 1 in flight)
+    __shared__ float Lr[Cd::SPLIT ? 4 * RING_NP : 1];
+    const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, bxd = (int)blockDim.x;
+    DensRing<P> ring(bxd, (int)blockDim.y, tx + bxd * ty, (int)blockIdx.x * bxd, (int)blockIdx.y * (int)blockDim.y);
+    if constexpr (Cd::SPLIT) {
+        ring.load(a, rRA, wrap_halo(z0 - 1, a.nz));
+        ring.put(a, Lr, 0);
+        ring.load(a, rRA, wrap_halo(z0, a.nz));
+        ring.put(a, Lr, 1);
+        ring.load(a, rRA, wrap_halo(z0 + 1, a.nz));
+    }
+
     // flags of the first node; each step prefetches the next node's flags
     uint32_t fnext = (inb && z0 < a.nz) ? bload<uint32_t>(rFl, 4u * ((unsigned)x + nx * (unsigned)y + plane * (unsigned)z0)) : NONFLUID;
 #pragma unroll 1
     for (int zz = 0; zz < TZ; zz++) {
         const int z = z0 + zz;
-        if (z >= a.nz) break;
+        if (z >= a.nz) break;  // uniform over the block
+        if constexpr (Cd::SPLIT) {
+            // plane z + 1 into its slot, plane z + 2 in flight; the slot
+            // written here held plane z - 3, which no thread reads any more
+            ring.put(a, Lr, (zz + 2) & 3);
+            if (zz + 1 < TZ) ring.load(a, rRA, wrap_halo(z + 2, a.nz));
+            __syncthreads();
+        }
         const unsigned i = (unsigned)x + nx * (unsigned)y + plane * (unsigned)z;
         const uint32_t f = fnext;
         fnext = (inb && zz + 1 < TZ && z + 1 < a.nz) ? bload<uint32_t>(rFl, 4u * (i + plane)) : NONFLUID;
@@ -247,12 +322,31 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
         M km[4];
 #pragma unroll
         for (int c = 0; c < 4; c++) km[c] = bload<M>(rK, links ? (unsigned)sizeof(M) * ((unsigned)c * ps + i) : OOB);
-        const T rstored = bload<T>(rRA, links ? ES * i : OOB);
+        // the node's own stored density (split codec: from the ring)
+        R Down;
+        if constexpr (Cd::SPLIT) Down = (R)Lr[((zz + 1) & 3) * RING_NP + (ty + 1) * (bxd + 2) + tx + 1];
+        else Down = rho_dec<P>(a, bload<T>(rRA, links ? ES * i : OOB));
 
         R drho = 0, jx = 0, jy = 0, jz = 0;
+        if constexpr (Cd::SPLIT) {
+            // the density parts w_r D of the pulled populations: D of the
+            // source node, or the node's own D for a bounced population
+#pragma unroll
+            for (int r = 0; r < 19; r++) {
+                R Ds = Down;
+                if (r > 0 && !((f >> r) & 1u))
+                    Ds = (R)Lr[((zz + 1 - CZ(r)) & 3) * RING_NP + (ty + 1 - CY(r)) * (bxd + 2) + (tx + 1 - CX(r))];
+                const R wd = (R)WD(r) * Ds;
+                drho += wd;
+                if (CX(r)) jx += CX(r) * wd;
+                if (CY(r)) jy += CY(r) * wd;
+                if (CZ(r)) jz += CZ(r) * wd;
+            }
+        }
 #pragma unroll
         for (int r = 0; r < 19; r++) {
-            const R dv = Cd::dec(v[r], dec_scale<P>(a, r));
+            // split codec: the residual parts (the density parts are summed above)
+            const R dv = pop_dec<P>(a, v[r], r, (R)0);
             drho += dv;
             if (CX(r)) jx += CX(r) * dv;
             if (CY(r)) jy += CY(r) * dv;
@@ -261,7 +355,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
         if (links) {
             // moving-boundary corrections summed over the links:
             // sum C_r = 6 rho(x) K0, sum C_r c_r = 6 rho(x) (K1, K2, K3)
-            const M rho6 = (M)6 * ((M)a.rho0 + (M)Cd::dec(rstored, rho_dec_scale<P>(a)));
+            const M rho6 = (M)6 * ((M)a.rho0 + (M)Down);
             drho += (R)(rho6 * km[0]); jx += (R)(rho6 * km[1]); jy += (R)(rho6 * km[2]); jz += (R)(rho6 * km[3]);
         }
 
@@ -273,9 +367,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
         const R ux = (jx + (R)0.5 * gx) * irho, uy = (jy + (R)0.5 * gy) * irho, uz = (jz + (R)0.5 * gz) * irho;
         const R usq = ux * ux + uy * uy + uz * uz;
         const R ug = ux * gx + uy * gy + uz * gz;
+        // the collision conserves mass: the density deviation of n* is drho.
+        // Split codec: the stored outputs are n*_r - w_r (rho0 + Dq), with Dq
+        // the decoded stored density, so drho enters as drho - Dq
+        orho = Cd::enc(drho, rho_enc_scale<P>(a));
+        R dres = drho;
+        if constexpr (Cd::SPLIT) dres = drho - rho_dec<P>(a, orho);
         {
             const R w0 = (R)(1.0 / 3.0);
-            const R out0 = w0 * (drho - rho * (R)1.5 * usq) - (R)1.5 * w0 * ug;
+            const R out0 = w0 * (dres - rho * (R)1.5 * usq) - (R)1.5 * w0 * ug;
             ob[0] = Cd::enc(out0, enc_scale<P>(a, 0));
         }
 #pragma unroll
@@ -284,13 +384,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
             const R cu = CX(r) * ux + CY(r) * uy + CZ(r) * uz;
             const R cg = CX(r) * gx + CY(r) * gy + CZ(r) * gz;
             const R cu2 = cu * cu;
-            const R ev = w * (drho + rho * ((R)4.5 * cu2 - (R)1.5 * usq)) + (R)0.5 * w * ((R)9 * cu * cg - (R)3 * ug);
+            const R ev = w * (dres + rho * ((R)4.5 * cu2 - (R)1.5 * usq)) + (R)0.5 * w * ((R)9 * cu * cg - (R)3 * ug);
             const R od = w * rho * cu * ((R)3 + (R)4.5 * cu2 - (R)4.5 * usq) + (R)1.5 * w * cg;
             ob[r] = Cd::enc(ev + od, enc_scale<P>(a, r));
             ob[r + 1] = Cd::enc(ev - od, enc_scale<P>(a, r + 1));
         }
-        // the collision conserves mass: the density deviation of n* is drho
-        orho = Cd::enc(drho, rho_enc_scale<P>(a));
         if (!(usq <= (R)0.16)) {
             atomicOr(a.status, ST_UNSTABLE);
             atomicMin(a.bad_step, *a.dstep);
@@ -338,6 +436,7 @@ hipError_t launch_lb(const DevArgs& a, LaunchCfg cfg, hipStream_t st) {
         case CGB_P32: return launch_lb_p<CGB_P32>(a, cfg, st);
         case CGB_PMX16: return launch_lb_p<CGB_PMX16>(a, cfg, st);
         case CGB_PMXBF16: return launch_lb_p<CGB_PMXBF16>(a, cfg, st);
+        case CGB_PMX16S: return launch_lb_p<CGB_PMX16S>(a, cfg, st);
         default: return hipErrorInvalidValue;
     }
 }

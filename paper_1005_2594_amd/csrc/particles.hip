@@ -78,6 +78,7 @@ hipError_t launch_clear_cells(const DevArgs& a, hipStream_t st) {
         case CGB_P32: hipLaunchKernelGGL(clear_cells_kernel<CGB_P32>, g, b, 0, st, a); break;
         case CGB_PMX16: hipLaunchKernelGGL(clear_cells_kernel<CGB_PMX16>, g, b, 0, st, a); break;
         case CGB_PMXBF16: hipLaunchKernelGGL(clear_cells_kernel<CGB_PMXBF16>, g, b, 0, st, a); break;
+        case CGB_PMX16S: hipLaunchKernelGGL(clear_cells_kernel<CGB_PMX16S>, g, b, 0, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -344,13 +345,14 @@ __device__ inline void node_links(const DevArgs& a, __amdgpu_buffer_rsrc_t rA, _
 #pragma unroll
     for (int r = 1; r < 19; r++) {
         const bool lk = !((f >> OPP(r)) & 1u);
-        const R rho_x = (R)a.rho0 + Cd::dec(rv[r], rho_dec_scale<P>(a));
+        const R Dx = rho_dec<P>(a, rv[r]);
+        const R rho_x = (R)a.rho0 + Dx;
         R cu = 0;
         if (CX(r)) cu += (R)CX(r) * u0;
         if (CY(r)) cu += (R)CY(r) * u1;
         if (CZ(r)) cu += (R)CZ(r) * u2;
         const R C = (R)(6.0 * WD(r)) * rho_x * cu;
-        const R m = lk ? -((R)2 * Cd::dec(dv[r], dec_scale<P>(a, OPP(r))) + C) : (R)0;
+        const R m = lk ? -((R)2 * pop_dec<P>(a, dv[r], OPP(r), Dx) + C) : (R)0;
         if (CX(r)) m0 += CX(r) * m;
         if (CY(r)) m1 += CY(r) * m;
         if (CZ(r)) m2 += CZ(r) * m;
@@ -428,6 +430,7 @@ hipError_t launch_mem_reduce(const DevArgs& a, hipStream_t st) {
         case CGB_P32: hipLaunchKernelGGL(mem_reduce_kernel<CGB_P32>, g, b, 0, st, a); break;
         case CGB_PMX16: hipLaunchKernelGGL(mem_reduce_kernel<CGB_PMX16>, g, b, 0, st, a); break;
         case CGB_PMXBF16: hipLaunchKernelGGL(mem_reduce_kernel<CGB_PMXBF16>, g, b, 0, st, a); break;
+        case CGB_PMX16S: hipLaunchKernelGGL(mem_reduce_kernel<CGB_PMX16S>, g, b, 0, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -504,13 +507,6 @@ struct LmShape {
     static_assert(NP <= 512, "two positions per thread");
 };
 
-// v in [-1, n + TX - 1] reduced to [0, n)
-__device__ inline int wrap_halo(int v, int n) {
-    if (v < 0) v += n;
-    if (v >= n) v -= n;
-    if (v >= n) v %= n;  // lattices narrower than a patch
-    return v;
-}
 
 // site of halo'd plane position q of the patch at (x0, y0), plane z
 template <int TX>
@@ -678,8 +674,9 @@ __device__ void transition_one(const DevArgs& a, int t, bool book) {
         if (!book) return;
         // covered: the deleted fluid momentum goes to the cell
         double m[3] = {0, 0, 0};
+        const R Ds = rho_dec<P>(a, ((const T*)a.rhoA)[s]);
         for (int r = 0; r < 19; r++) {
-            const double v = (double)Cd::dec(A[r * a.pstride + s], dec_scale<P>(a, r));
+            const double v = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
             m[0] += v * CX(r); m[1] += v * CY(r); m[2] += v * CZ(r);
         }
         double d[3], tq[3];
@@ -706,13 +703,14 @@ __device__ void transition_one(const DevArgs& a, int t, bool book) {
             const double cu = CX(r) * us[0] + CY(r) * us[1] + CZ(r) * us[2];
             const double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq + 4.5 * cu * cu * cu - 4.5 * usq * cu;
             const double eq = WD(r) * (0.0 + a.rho0 * poly);
-            const T stv = Cd::enc((R)eq, enc_scale<P>(a, r));
+            // split codec: the density deviation of the new fluid is 0
+            const T stv = pop_enc<P>(a, (R)eq, r, (R)0);
             A[r * a.pstride + s] = stv;
-            const R back = Cd::dec(stv, dec_scale<P>(a, r));
+            const R back = pop_dec<P>(a, stv, r, (R)0);
             rs += back;
             m[0] += (double)back * CX(r); m[1] += (double)back * CY(r); m[2] += (double)back * CZ(r);
         }
-        ((T*)a.rhoA)[s] = Cd::enc(rs, rho_enc_scale<P>(a));
+        ((T*)a.rhoA)[s] = Cd::enc(Cd::SPLIT ? (R)0 : rs, rho_enc_scale<P>(a));
         double tq[3];
         cross3(d, m, tq);
         double* F = a.FTh + 6 * (long long)o;
@@ -736,6 +734,7 @@ hipError_t launch_transitions(const DevArgs& a, hipStream_t st, bool book) {
         case CGB_P32: hipLaunchKernelGGL(transitions_kernel<CGB_P32>, g, b, 0, st, a, (int)book); break;
         case CGB_PMX16: hipLaunchKernelGGL(transitions_kernel<CGB_PMX16>, g, b, 0, st, a, (int)book); break;
         case CGB_PMXBF16: hipLaunchKernelGGL(transitions_kernel<CGB_PMXBF16>, g, b, 0, st, a, (int)book); break;
+        case CGB_PMX16S: hipLaunchKernelGGL(transitions_kernel<CGB_PMX16S>, g, b, 0, st, a, (int)book); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -221,7 +221,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
     *out = nullptr;
     if (p->nx < 3 || p->ny < 3 || p->nz < 3 || !(p->tau > 0.5) || !(p->rho0 > 0) || p->precision < 0 ||
         p->force_on_particles < 0 || p->force_on_particles > 2 ||
-        p->precision > CGB_PMXBF16 || !(p->R_perp > 0) || !(p->R_par > 0) || !(p->rho_p > 0) || !(p->r_cut > 0))
+        p->precision > CGB_PMX16S || !(p->R_perp > 0) || !(p->R_par > 0) || !(p->rho_p > 0) || !(p->r_cut > 0))
         return CGB_EINVAL;
     {
         // populations and boundary velocities are addressed with 32-bit byte offsets
