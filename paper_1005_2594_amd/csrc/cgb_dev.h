@@ -76,6 +76,8 @@ struct DevArgs {
     double* Xprev;  // n*3, position of the last rasterisation
     double* Hprev;  // n*3, axis-aligned half extents at the last rasterisation
     double* kin;    // n*12: X, V, Omega, axis at the start of the step
+    float* kinf;    // n*12: rigid-body velocity about the nearest node b of X, in FP32:
+                    // U0 = V + Omega x (b - X) (3), Omega (3), b packed (x | y << 16, z), X - b (3), 0
     double* FTh;    // n*6 hydrodynamic force, torque (accumulated)
     double* FTp;    // n*6 potential force, torque
     double M, Ipar, Iperp;

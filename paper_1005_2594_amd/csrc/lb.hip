@@ -210,30 +210,39 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
 // thread fills at most four of them.
 constexpr int RING_NP = 774;
 
+// workgroup barrier that waits for this wave's LDS accesses only: global
+// loads in flight (the next plane of the ring, the next flags) stay in flight
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 template <int P>
 struct DensRing {
+    static_assert(sizeof(typename Codec<P>::T) == 2, "the ring holds 2-byte stored densities");
     using T = typename Codec<P>::T;
-    int hx, np, nthr, t, x0, y0;
-    T pre[4];
-    __device__ DensRing(int bx, int by, int tid, int x0_, int y0_)
-        : hx(bx + 2), np((bx + 2) * (by + 2)), nthr(bx * by), t(tid), x0(x0_), y0(y0_) {}
-    // issue the loads of plane pz (wrapped) into registers
-    __device__ void load(const DevArgs& a, __amdgpu_buffer_rsrc_t rRA, int pz) {
-        constexpr unsigned ES = sizeof(T);
-        const unsigned base = (unsigned)a.nx * (unsigned)a.ny * (unsigned)pz;
+    unsigned off[4];  // in-plane byte offsets of this thread's ring positions (OOB: none)
+    uint32_t pre[4];  // loaded 16-bit values, zero-extended (kept unpacked while in flight)
+    int np, nthr, t;
+    __device__ DensRing(const DevArgs& a, int bx, int by, int tid, int x0, int y0) : np((bx + 2) * (by + 2)), nthr(bx * by), t(tid) {
+        const int hx = bx + 2;
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const int q = t + k * nthr;
             const int xs = wrap_halo(x0 - 1 + q % hx, a.nx), ys = wrap_halo(y0 - 1 + q / hx, a.ny);
-            pre[k] = bload<T>(rRA, q < np ? ES * (base + (unsigned)xs + (unsigned)a.nx * (unsigned)ys) : 0xfffffff0u);
+            off[k] = q < np ? (unsigned)sizeof(T) * ((unsigned)xs + (unsigned)a.nx * (unsigned)ys) : 0xfffffff0u;
         }
+    }
+    // issue the loads of plane pz into registers
+    __device__ void load(const DevArgs& a, __amdgpu_buffer_rsrc_t rRA, int pz) {
+        const unsigned base = (unsigned)sizeof(T) * (unsigned)a.nx * (unsigned)a.ny * (unsigned)pz;
+#pragma unroll
+        for (int k = 0; k < 4; k++)
+            pre[k] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rRA, off[k] == 0xfffffff0u ? off[k] : base + off[k], 0, 0);
     }
     // decode the loaded plane into ring slot sl
     __device__ void put(const DevArgs& a, float* L, int sl) {
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const int q = t + k * nthr;
-            if (q < np) L[sl * RING_NP + q] = (float)rho_dec<P>(a, pre[k]);
+            if (q < np) L[sl * RING_NP + q] = (float)rho_dec<P>(a, __builtin_bit_cast(T, (unsigned short)pre[k]));
         }
     }
 };
@@ -272,7 +281,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
     // split codec: density ring (planes z0 - 1 and z0 now, z0 + 1 in flight)
     __shared__ float Lr[Cd::SPLIT ? 4 * RING_NP : 1];
     const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, bxd = (int)blockDim.x;
-    DensRing<P> ring(bxd, (int)blockDim.y, tx + bxd * ty, (int)blockIdx.x * bxd, (int)blockIdx.y * (int)blockDim.y);
+    DensRing<Cd::SPLIT ? P : CGB_PMX16S> ring(a, bxd, (int)blockDim.y, tx + bxd * ty, (int)blockIdx.x * bxd, (int)blockIdx.y * (int)blockDim.y);
     if constexpr (Cd::SPLIT) {
         ring.load(a, rRA, wrap_halo(z0 - 1, a.nz));
         ring.put(a, Lr, 0);
@@ -292,7 +301,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
             // written here held plane z - 3, which no thread reads any more
             ring.put(a, Lr, (zz + 2) & 3);
             if (zz + 1 < TZ) ring.load(a, rRA, wrap_halo(z + 2, a.nz));
-            __syncthreads();
+            lds_barrier();
         }
         const unsigned i = (unsigned)x + nx * (unsigned)y + plane * (unsigned)z;
         const uint32_t f = fnext;
@@ -311,21 +320,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
         auto src = [&](int r) { return i + (unsigned)(ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1]); };
         const uint32_t links = f & LINKBITS;
 
-        // issue the 19 pulls (non-fluid source: bounce-back), the node's link
-        // moments and its stored density together
-        T v[19];
-#pragma unroll
-        for (int r = 0; r < 19; r++) {
-            const bool bb = (f >> r) & 1u;
-            v[r] = bload<T>(rA, ES * (bb ? (unsigned)OPP(r) * ps + i : (unsigned)r * ps + src(r)));
-        }
-        M km[4];
-#pragma unroll
-        for (int c = 0; c < 4; c++) km[c] = bload<M>(rK, links ? (unsigned)sizeof(M) * ((unsigned)c * ps + i) : OOB);
-        // the node's own stored density (split codec: from the ring)
-        R Down;
+        // split codec: the node's own stored density from the ring
+        R Down = 0;
         if constexpr (Cd::SPLIT) Down = (R)Lr[((zz + 1) & 3) * RING_NP + (ty + 1) * (bxd + 2) + tx + 1];
-        else Down = rho_dec<P>(a, bload<T>(rRA, links ? ES * i : OOB));
 
         R drho = 0, jx = 0, jy = 0, jz = 0;
         if constexpr (Cd::SPLIT) {
@@ -342,7 +339,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
                 if (CY(r)) jy += CY(r) * wd;
                 if (CZ(r)) jz += CZ(r) * wd;
             }
+            // the density parts are summed before the pulls are issued, so
+            // that the LDS reads do not hold registers across the pulls
+            __builtin_amdgcn_sched_barrier(0);
         }
+        // issue the 19 pulls (non-fluid source: bounce-back), the node's link
+        // moments and its stored density together
+        T v[19];
+#pragma unroll
+        for (int r = 0; r < 19; r++) {
+            const bool bb = (f >> r) & 1u;
+            v[r] = bload<T>(rA, ES * (bb ? (unsigned)OPP(r) * ps + i : (unsigned)r * ps + src(r)));
+        }
+        M km[4];
+#pragma unroll
+        for (int c = 0; c < 4; c++) km[c] = bload<M>(rK, links ? (unsigned)sizeof(M) * ((unsigned)c * ps + i) : OOB);
+        if constexpr (!Cd::SPLIT) Down = rho_dec<P>(a, bload<T>(rRA, links ? ES * i : OOB));
 #pragma unroll
         for (int r = 0; r < 19; r++) {
             // split codec: the residual parts (the density parts are summed above)

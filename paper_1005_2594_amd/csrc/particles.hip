@@ -23,6 +23,15 @@
 namespace cgb {
 
 // ------------------------------------------------------------------ prep
+// integer displacement d = s - b of a node from the node b nearest to a cell
+// centre X (f = X - b), moved to the periodic image in which s - X is nearest
+__device__ inline int image_shift(int d, float f, int n) {
+    const float e = (float)d - f;
+    if (e >= 0.5f * (float)n) return d - n;
+    if (e < -0.5f * (float)n) return d + n;
+    return d;
+}
+
 __global__ void prep_kernel(DevArgs a, int zero_forces) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n) return;
@@ -39,6 +48,29 @@ __global__ void prep_kernel(DevArgs a, int zero_forces) {
         k[6 + c] = L[c] / a.Iperp + kk * oL * o[c];
         k[9 + c] = o[c];
     }
+    // FP32 form for the node-velocity stencils: u(s) = U0 + Omega x (s - b)
+    // with b the lattice node nearest to X (s - b a small integer vector)
+    const int L3[3] = {a.nx, a.ny, a.nz};
+    int b[3];
+    double U0[3];
+    double db[3];
+    for (int c = 0; c < 3; c++) {
+        b[c] = (int)floor(k[c] + 0.5);
+        db[c] = (double)b[c] - k[c];
+        if (c == 1 && a.wall_y) continue;  // no periodic image across the walls
+        if (b[c] >= L3[c]) b[c] -= L3[c];
+        if (b[c] < 0) b[c] += L3[c];
+    }
+    cross3(k + 6, db, U0);
+    float* kf = a.kinf + 12 * (long long)p;
+    for (int c = 0; c < 3; c++) {
+        kf[c] = (float)(k[3 + c] + U0[c]);
+        kf[3 + c] = (float)k[6 + c];
+    }
+    kf[6] = __int_as_float(b[0] | (b[1] << 16));
+    kf[7] = __int_as_float(b[2]);
+    for (int c = 0; c < 3; c++) kf[8 + c] = (float)(-db[c]);  // X - b, in [-1/2, 1/2]
+    kf[11] = 0.0f;
     if (zero_forces)
         for (int c = 0; c < 6; c++) { a.FTh[6 * p + c] = 0.0; a.FTp[6 * p + c] = 0.0; }
 }
@@ -461,11 +493,28 @@ __global__ void __launch_bounds__(256) usol_kernel(DevArgs a) {
     if (!wr) return;
     double u[3] = {0, 0, 0};
     if (o >= 0) {
-        const double* k = a.kin + 12 * (long long)o;
-        double d[3];
-        node_disp(a, x, y, z, k, d);
-        cross3(k + 6, d, u);
-        for (int c = 0; c < 3; c++) u[c] += k[3 + c];
+        if constexpr (sizeof(M) == 4) {
+            // FP32 link type: from the compact table, u = U0 + Omega x (s - b),
+            // s - b taken to the periodic image nearest to the cell centre
+            const float* kf = a.kinf + 12 * (long long)o;
+            const float4 k0 = *(const float4*)kf, k1 = *(const float4*)(kf + 4), k2 = *(const float4*)(kf + 8);
+            const int bxy = __float_as_int(k1.z);
+            int d0 = x - (bxy & 0xffff), d1 = y - (bxy >> 16), d2 = z - __float_as_int(k1.w);
+            d0 = image_shift(d0, k2.x, a.nx);
+            if (!a.wall_y) d1 = image_shift(d1, k2.y, a.ny);
+            d2 = image_shift(d2, k2.z, a.nz);
+            const float e0 = (float)d0, e1 = (float)d1, e2 = (float)d2;
+            // Omega = (k0.w, k1.x, k1.y)
+            u[0] = k0.x + (k1.x * e2 - k1.y * e1);
+            u[1] = k0.y + (k1.y * e0 - k0.w * e2);
+            u[2] = k0.z + (k0.w * e1 - k1.x * e0);
+        } else {
+            const double* k = a.kin + 12 * (long long)o;
+            double d[3];
+            node_disp(a, x, y, z, k, d);
+            cross3(k + 6, d, u);
+            for (int c = 0; c < 3; c++) u[c] += k[3 + c];
+        }
     } else if (o == OWN_WALL && a.wall_y) {
         if (y == 0) { u[0] = a.wvb[0]; u[1] = a.wvb[1]; u[2] = a.wvb[2]; }
         else if (y == a.ny - 1) { u[0] = a.wvt[0]; u[1] = a.wvt[1]; u[2] = a.wvt[2]; }
@@ -524,11 +573,28 @@ __device__ inline void lm_vel(const DevArgs& a, M* U, int sl, int q, int o, int 
     using S = LmShape<TX>;
     double u[3] = {0, 0, 0};
     if (o >= 0) {
-        const double* k = a.kin + 12 * (long long)o;
-        double d[3];
-        node_disp(a, x, y, z, k, d);
-        cross3(k + 6, d, u);
-        for (int c = 0; c < 3; c++) u[c] += k[3 + c];
+        if constexpr (sizeof(M) == 4) {
+            // FP32 link type: from the compact table, u = U0 + Omega x (s - b),
+            // s - b taken to the periodic image nearest to the cell centre
+            const float* kf = a.kinf + 12 * (long long)o;
+            const float4 k0 = *(const float4*)kf, k1 = *(const float4*)(kf + 4), k2 = *(const float4*)(kf + 8);
+            const int bxy = __float_as_int(k1.z);
+            int d0 = x - (bxy & 0xffff), d1 = y - (bxy >> 16), d2 = z - __float_as_int(k1.w);
+            d0 = image_shift(d0, k2.x, a.nx);
+            if (!a.wall_y) d1 = image_shift(d1, k2.y, a.ny);
+            d2 = image_shift(d2, k2.z, a.nz);
+            const float e0 = (float)d0, e1 = (float)d1, e2 = (float)d2;
+            // Omega = (k0.w, k1.x, k1.y)
+            u[0] = k0.x + (k1.x * e2 - k1.y * e1);
+            u[1] = k0.y + (k1.y * e0 - k0.w * e2);
+            u[2] = k0.z + (k0.w * e1 - k1.x * e0);
+        } else {
+            const double* k = a.kin + 12 * (long long)o;
+            double d[3];
+            node_disp(a, x, y, z, k, d);
+            cross3(k + 6, d, u);
+            for (int c = 0; c < 3; c++) u[c] += k[3 + c];
+        }
     } else if (o == OWN_WALL && a.wall_y) {
         if (y == 0) { u[0] = a.wvb[0]; u[1] = a.wvb[1]; u[2] = a.wvb[2]; }
         else if (y == a.ny - 1) { u[0] = a.wvt[0]; u[1] = a.wvt[1]; u[2] = a.wvt[2]; }

@@ -189,7 +189,7 @@ static LaunchCfg default_tiles(const DevArgs& a) {
 
 static int alloc_particles(cgb_sim* s, int ncap) {
     DevArgs& a = s->a;
-    void* olds[] = {a.X, a.q, a.V, a.L, a.fixed, a.Xprev, a.Hprev, a.kin, a.crec, a.FTh, a.FTp, a.trans, a.pbin, a.bin_idx, a.Xs, a.body_part};
+    void* olds[] = {a.X, a.q, a.V, a.L, a.fixed, a.Xprev, a.Hprev, a.kin, a.kinf, a.crec, a.FTh, a.FTp, a.trans, a.pbin, a.bin_idx, a.Xs, a.body_part};
     for (void* p : olds) dfree(s, p);
     const size_t n = (size_t)std::max(ncap, 1);
     HIPCHK(s, dalloc(s, &a.X, 3 * n * 8));
@@ -200,6 +200,7 @@ static int alloc_particles(cgb_sim* s, int ncap) {
     HIPCHK(s, dalloc(s, &a.Xprev, 3 * n * 8));
     HIPCHK(s, dalloc(s, &a.Hprev, 3 * n * 8));
     HIPCHK(s, dalloc(s, &a.kin, 12 * n * 8));
+    HIPCHK(s, dalloc(s, &a.kinf, 12 * n * 4));
     HIPCHK(s, dalloc(s, &a.crec, n * sizeof(CellRec)));
     HIPCHK(s, dalloc(s, &a.FTh, 6 * n * 8));
     HIPCHK(s, dalloc(s, &a.FTp, 6 * n * 8));
