@@ -76,25 +76,34 @@ def measured_traffic(prec: str):
     return float(kv["hbm_bytes_per_launch"])
 
 
-def run_gpu(cfg, prec, steps, warmup, profile=True):
+def run_gpu(cfg, prec, steps, warmup, kernel_steps=50, serial=False):
+    """Timed region: `steps` steps with no instrumentation (the independent
+    phases of a step on side streams unless `serial`).  Then a kernel pass:
+    `kernel_steps` more steps with every kernel in sequence on the handle's
+    stream, each bracketed by HIP events (per-kernel times, and the LB launch
+    time of the roofline)."""
     from paper_1005_2594_amd import Sim
     p = cfg["params"]
     sim = Sim(p, precision=prec)
     sim.set_particles(cfg["X"], cfg["q"])
     sim.init_fluid()
+    sim.set_concurrency(not serial)
     sim.step(warmup)
     sim.sync()
     nf0 = sim.observables()["n_fluid"]
-    if profile:
-        sim.profile(True)
-    sim.sync()
     t0 = time.perf_counter()
     sim.step(steps)
     sim.sync()
     t1 = time.perf_counter()
-    kt = sim.kernel_times() if profile else {}
-    if profile:
+    kt = {}
+    if kernel_steps > 0:
+        sim.set_concurrency(False)
+        sim.profile(True)
+        sim.step(kernel_steps)
+        sim.sync()
+        kt = sim.kernel_times()
         sim.profile(False)
+        sim.set_concurrency(not serial)
     ob = sim.observables()
     nf = 0.5 * (nf0 + ob["n_fluid"])
     return dict(seconds=t1 - t0, n_fluid=nf, kernel_times=kt, obs=ob, sim=sim)
@@ -230,6 +239,8 @@ def main():
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--only", default=None, help="run only this precision (profiling)")
+    ap.add_argument("--kernel-steps", type=int, default=50, help="steps of the per-kernel timing pass")
+    ap.add_argument("--serial", action="store_true", help="every kernel in sequence in the timed region too")
     ap.add_argument("--copy-calibrate", action="store_true", help="also run a copy of known size (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -243,7 +254,7 @@ def main():
     ns = args.n ** 3
     results = {}
     for prec in ([args.only] if args.only else [HEAD, "pmx16", "p32"]):
-        r = run_gpu(cfg, prec, args.steps, args.warmup)
+        r = run_gpu(cfg, prec, args.steps, args.warmup, args.kernel_steps, args.serial)
         results[prec] = r
         print(f"# {prec}: {r['seconds'] * 1e3 / args.steps:.3f} ms/step, "
               f"{ns * args.steps / r['seconds'] / 1e6:.0f} MLUPS, kernels "
@@ -278,6 +289,10 @@ def main():
             "fluid_sites": round(r["n_fluid"]),
             "fluid_mlups": round(r["n_fluid"] * args.steps / r["seconds"] / 1e6, 1),
             "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in r["kernel_times"].items()},
+            "kernel_pass": f"{args.kernel_steps} steps after the timed region, every kernel in sequence on the "
+                           "handle's stream, HIP events around each launch",
+            "concurrency": "serial" if args.serial else "cell list + potentials and momentum exchange on two side "
+                                                        "streams beside the lattice kernels, joined before the integrator",
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -152,6 +152,16 @@ int cgb_get_profile_z(cgb_sim* s, double* prof);
 int cgb_profile(cgb_sim* s, int enable);
 int cgb_kernel_times(cgb_sim* s, char* names, double* ms, int64_t* count, int32_t cap, int32_t* n);
 
+/* Concurrency of the phases of a step (on by default for lattices with
+ * cells): the cell list and the pair/wall potentials (Eqs. 15-20), which need
+ * only the cells' positions and axes, and the momentum exchange (Eq. 12),
+ * which reads the populations the LB reads, not those it writes, run on two
+ * side streams of the handle beside the lattice part, joined before the
+ * integrator; results are identical either way.  on = 0 runs every kernel on
+ * the handle's stream in sequence (kernel timing of isolated launches).
+ * Returns CGB_EINVAL for a null handle. */
+int cgb_set_concurrency(cgb_sim* s, int on);
+
 /* ---- Apparent viscosity (Sec. V defines it from the mean flow; for the
  * body-force driven flows here the mean flow is the mixture velocity).
  * cgb_track: after every following step, record on the device the sums over

@@ -83,6 +83,7 @@ def lib():
     L.cgb_get_observables.argtypes = [VP, VP]
     L.cgb_get_profile_z.argtypes = [VP, VP]
     L.cgb_profile.argtypes = [VP, C.c_int]
+    L.cgb_set_concurrency.argtypes = [VP, C.c_int]
     L.cgb_kernel_times.argtypes = [VP, VP, VP, VP, C.c_int32, C.POINTER(C.c_int32)]
     L.cgb_save.argtypes = [VP, C.c_char_p]
     L.cgb_load.argtypes = [VP, C.c_char_p]
@@ -308,6 +309,10 @@ class Sim:
         return ms.value
 
     # -- timing
+    def set_concurrency(self, on=True):
+        """Independent phases of a step on side streams (on) or all kernels in sequence."""
+        self._check(lib().cgb_set_concurrency(self.h, 1 if on else 0))
+
     def profile(self, enable=True):
         self._check(lib().cgb_profile(self.h, 1 if enable else 0))
 

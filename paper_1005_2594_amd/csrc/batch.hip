@@ -101,6 +101,9 @@ int cgb_batch_create(int32_t nch, const cgb_params* ch, cgb_batch** out) {
             cgb_batch_destroy(b);
             return rc;
         }
+        // the channels run concurrently with each other: each steps on its own
+        // stream alone (the captured graph holds one chain per channel)
+        s->fork = false;
         b->ch.push_back(s);
         hipEvent_t e1, e2;
         if (hipEventCreateWithFlags(&e1, hipEventDisableTiming) != hipSuccess) {

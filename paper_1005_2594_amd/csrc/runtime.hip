@@ -87,24 +87,27 @@ static void harvest(cgb_sim* s) {
     s->recs.clear();
 }
 
+// launch(es) f bracketed by timing events on stream st (when profiling)
 template <class F>
-static hipError_t timed(cgb_sim* s, int kind, F&& f) {
+static hipError_t timed_on(cgb_sim* s, int kind, hipStream_t st, F&& f) {
     if (!s->prof) return f();
     if (s->recs.size() > 4096) {
-        hipError_t e = hipStreamSynchronize(s->st);
+        hipError_t e = hipDeviceSynchronize();
         if (e != hipSuccess) return e;
         harvest(s);
     }
     LaunchRec r{kind, take_event(s), take_event(s)};
     if (!r.e0 || !r.e1) return hipErrorOutOfMemory;
-    hipError_t e = hipEventRecord(r.e0, s->st);
+    hipError_t e = hipEventRecord(r.e0, st);
     if (e != hipSuccess) return e;
     e = f();
     if (e != hipSuccess) return e;
-    e = hipEventRecord(r.e1, s->st);
+    e = hipEventRecord(r.e1, st);
     s->recs.push_back(r);
     return e;
 }
+template <class F>
+static hipError_t timed(cgb_sim* s, int kind, F&& f) { return timed_on(s, kind, s->st, f); }
 
 // ---------------------------------------------------------------- helpers
 static void bind_buffers(cgb_sim* s) {
@@ -165,6 +168,10 @@ int64_t cgb_device_bytes(const cgb_sim* s) { return s ? s->dev_bytes : 0; }
 void cgb_destroy(cgb_sim* s) {
     if (!s) return;
     if (s->st) (void)hipStreamSynchronize(s->st);
+    for (hipStream_t q : {s->st_mem, s->st_pot})
+        if (q) { (void)hipStreamSynchronize(q); (void)hipStreamDestroy(q); }
+    for (hipEvent_t e : {s->ev_ras, s->ev_tr, s->ev_mem, s->ev_pot})
+        if (e) (void)hipEventDestroy(e);
     for (auto& r : s->recs) { (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
     for (auto e : s->ev_pool) (void)hipEventDestroy(e);
     for (void* p : s->allocs) (void)hipFree(p);
@@ -267,6 +274,7 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
         if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess) { delete s; return CGB_EDEVICE; }
         s->own_stream = true;
     }
+    s->fork = true;  // side streams are created at the first step that uses them
     int rc = CGB_OK;
 #define CK(call)                                         \
     do {                                                 \
@@ -478,17 +486,48 @@ int cgb_step(cgb_sim* s, int32_t nsteps) {
     DevArgs& a = s->a;
     for (int t = 0; t < nsteps; t++) {
         bind_buffers(s);
+        // with cells, three streams: the cell list and the potentials need
+        // only the positions and axes (after the rasterisation, whose record
+        // kernel reads the previous cell list); the momentum exchange needs
+        // the occupancy after the transitions and the populations the LB
+        // reads (it does not read what the LB writes); the integrator joins
+        const bool fk = s->fork && a.n > 0;
+        if (fk && !s->st_mem) {
+            HIPCHK(s, hipStreamCreateWithFlags(&s->st_mem, hipStreamNonBlocking));
+            HIPCHK(s, hipStreamCreateWithFlags(&s->st_pot, hipStreamNonBlocking));
+            for (hipEvent_t* e : {&s->ev_ras, &s->ev_tr, &s->ev_mem, &s->ev_pot})
+                HIPCHK(s, hipEventCreateWithFlags(e, hipEventDisableTiming));
+        }
+        hipStream_t sm = fk ? s->st_mem : s->st, sp = fk ? s->st_pot : s->st;
         HIPCHK(s, timed(s, K_PREP, [&] { return launch_prep(a, s->st); }));
         HIPCHK(s, timed(s, K_RASTER, [&] { return launch_raster(a, s->st, false); }));
+        if (fk) {
+            HIPCHK(s, hipEventRecord(s->ev_ras, s->st));
+            HIPCHK(s, hipStreamWaitEvent(sp, s->ev_ras, 0));
+            HIPCHK(s, timed_on(s, K_CELLS, sp, [&] { return launch_cells(a, sp); }));
+            HIPCHK(s, timed_on(s, K_POT, sp, [&] { return launch_potentials(a, sp); }));
+            HIPCHK(s, hipEventRecord(s->ev_pot, sp));
+        }
         HIPCHK(s, timed(s, K_TRANS, [&] {
             hipError_t e = launch_transitions(a, s->st, true);
+            if (e == hipSuccess && fk) e = hipEventRecord(s->ev_tr, s->st);
             return e != hipSuccess ? e : (a.lmom ? launch_lmom(a, s->st) : launch_usol(a, s->st, false));
         }));
+        if (fk) {
+            HIPCHK(s, hipStreamWaitEvent(sm, s->ev_tr, 0));
+            HIPCHK(s, timed_on(s, K_MEM, sm, [&] { return launch_mem_reduce(a, sm); }));
+            HIPCHK(s, hipEventRecord(s->ev_mem, sm));
+        }
         HIPCHK(s, timed(s, K_LB, [&] { return launch_lb(a, s->lbcfg, s->st); }));
-        HIPCHK(s, timed(s, K_MEM, [&] { return launch_mem_reduce(a, s->st); }));
+        if (!fk) HIPCHK(s, timed(s, K_MEM, [&] { return launch_mem_reduce(a, s->st); }));
         if (a.track) HIPCHK(s, timed(s, K_TRACK, [&] { return launch_track(a, s->st); }));
-        HIPCHK(s, timed(s, K_CELLS, [&] { return launch_cells(a, s->st); }));
-        HIPCHK(s, timed(s, K_POT, [&] { return launch_potentials(a, s->st); }));
+        if (fk) {
+            HIPCHK(s, hipStreamWaitEvent(s->st, s->ev_mem, 0));
+            HIPCHK(s, hipStreamWaitEvent(s->st, s->ev_pot, 0));
+        } else {
+            HIPCHK(s, timed(s, K_CELLS, [&] { return launch_cells(a, s->st); }));
+            HIPCHK(s, timed(s, K_POT, [&] { return launch_potentials(a, s->st); }));
+        }
         HIPCHK(s, timed(s, K_INT, [&] { return launch_integrate(a, s->st); }));
         s->cur = 1 - s->cur;
         s->step++;
@@ -679,6 +718,13 @@ int cgb_get_profile_z(cgb_sim* s, double* prof) {
     HIPCHK(s, hipMemcpyAsync(h.data(), s->tmp, h.size() * 8, hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     for (int y = 0; y < a.ny; y++) prof[y] = h[(size_t)a.ny + y] > 0 ? h[(size_t)y] / h[(size_t)a.ny + y] : 0.0;
+    return CGB_OK;
+}
+
+int cgb_set_concurrency(cgb_sim* s, int on) {
+    if (!s) return CGB_EINVAL;
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    s->fork = on != 0;
     return CGB_OK;
 }
 

@@ -176,6 +176,33 @@ def test_checkpoint_resume(tmp_path):
     assert np.max(np.abs(a.populations() - b.populations())) < 1e-6
 
 
+def test_concurrent_phases_match_serial():
+    # the cell list and potentials, and the momentum exchange, on side
+    # streams give the results of the all-in-sequence step (up to the order
+    # of the cover/uncover atomics, as between any two runs), and the oracle's
+    c = synth.kolmogorov(32, 7, f0=1e-5)
+    from paper_1005_2594_amd import Sim
+    say("case: concurrent vs serial step phases, p64 32^3, 30 steps")
+    runs = []
+    for on in (True, False):
+        g = Sim(c["params"], precision="p64")
+        g.set_particles(c["X"], c["q"]); g.init_fluid()
+        g.set_concurrency(on)
+        g.step(30)
+        runs.append((g.owner(), g.populations(), g.particles(), g.forces()))
+    (oa, pa, xa, fa), (ob, pb, xb, fb) = runs
+    assert np.array_equal(oa, ob)
+    assert rel_inf(pa, pb) <= 1e-12
+    for x, y in zip(xa, xb):
+        assert rel_inf(x, y) <= 1e-12
+    for x, y in zip(fa, fb):
+        assert rel_inf(x, y) <= 1e-9
+    o = O.Oracle(c["params"])
+    o.set_particles(c["X"], c["q"]); o.init_fluid(); o.step(30)
+    assert np.array_equal(oa, o.owner())
+    assert rel_inf(xa[0], o.particles()[0]) <= 1e-12
+
+
 @pytest.mark.parametrize("prec,tol", [("p64", 1e-12), ("p32", 1e-5)])
 def test_transitions_parity(prec, tol):
     # moving, rotating cells cover and free nodes every few steps: the
