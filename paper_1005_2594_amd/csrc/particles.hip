@@ -165,7 +165,7 @@ __device__ inline bool covers(const DevArgs& a, const CellRec& c, int x, int y, 
 // cell records in cell-list order (the order of the previous cell list; any
 // permutation of the cells is correct)
 __global__ void cellrec_kernel(DevArgs a) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
     if (k >= a.n) return;
     const int p = a.bin_idx[k];
     const double* kp = a.kin + 12 * (long long)p;
@@ -193,7 +193,7 @@ template <bool RESOLVE>
 __global__ void __launch_bounds__(64 * CPW) raster_kernel(DevArgs a) {
     const unsigned nx = (unsigned)a.nx, plane = (unsigned)a.nx * (unsigned)a.ny;
     const int lane = threadIdx.x & 63;
-    const int k = __builtin_amdgcn_readfirstlane(blockIdx.x * CPW + (int)(threadIdx.x >> 6));
+    const int k = __builtin_amdgcn_readfirstlane(xcd_block((int)blockIdx.x, (int)gridDim.x) * CPW + (int)(threadIdx.x >> 6));
     if (k >= a.n) return;
     // cells in cell-list order: neighbouring waves touch neighbouring nodes
     const CellRec cr = ((const CellRec*)a.crec)[k];
@@ -411,7 +411,7 @@ __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
     const auto rRA = make_rsrc(a.rhoA, (unsigned long long)ps * ES);
     const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
     const int wv = threadIdx.x >> 6;
-    const int k0 = 2 * __builtin_amdgcn_readfirstlane(blockIdx.x * CPW + wv);
+    const int k0 = 2 * __builtin_amdgcn_readfirstlane(xcd_block((int)blockIdx.x, (int)gridDim.x) * CPW + wv);
     if (k0 >= a.n) return;
     // the records' boxes (previous and current rasterisation) hold every node of the cells
     const CellRec c0 = ((const CellRec*)a.crec)[k0];
@@ -1099,7 +1099,7 @@ __device__ inline void wall_vec(const DevArgs& a, const double* Xi, unsigned w, 
 // candidates of a bin row are read CB at a time with independent loads.
 constexpr int CB = 2;
 __global__ void potentials_kernel(DevArgs a) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
     if (k >= a.n) return;
     const SortedPos* S = (const SortedPos*)a.Xs;
     const SortedPos me = S[k];
@@ -1155,7 +1155,7 @@ static_assert(PG >= 6 && PG <= 64 && (PG & (PG - 1)) == 0, "a group's lanes 0-5 
 __global__ void __launch_bounds__(POT_BLOCK) potentials_grp_kernel(DevArgs a) {
     // [slot][thread]: a partner j >= 0, or ~t for wall entry t
     __shared__ int plist[PG_LIST][POT_BLOCK];
-    const int k = (int)((blockIdx.x * (unsigned)POT_BLOCK + threadIdx.x) / PG);
+    const int k = (int)(((unsigned)xcd_block((int)blockIdx.x, (int)gridDim.x) * (unsigned)POT_BLOCK + threadIdx.x) / PG);
     const int g = (int)(threadIdx.x % PG);
     const bool live = k < a.n;  // uniform over each group; groups do not meet
     const SortedPos* S = (const SortedPos*)a.Xs;
