@@ -15,7 +15,9 @@ def _series_err(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-@pytest.mark.parametrize("precision,tol", [("p64", 1e-11), ("p32", 2e-5)])
+# split FP16 storage: an FP64 emulation of its rounding on this case moves the
+# series by 5e-5 (A) and 2e-5 (mean velocity)
+@pytest.mark.parametrize("precision,tol", [("p64", 1e-11), ("p32", 2e-5), ("pmx16s", 5e-4)])
 def test_track_kolmogorov_matches_oracle(precision, tol):
     cfg = synth.kolmogorov(32, seed=21, hematocrit=0.3)
     say("track kolmogorov 32^3", len(cfg["X"]), "cells", precision)

@@ -153,18 +153,19 @@ def test_set_populations_roundtrip_and_empty():
         assert g.observables()["step"] == 3
 
 
-def test_checkpoint_resume(tmp_path):
+@pytest.mark.parametrize("prec", ["pmx16", "pmx16s"])
+def test_checkpoint_resume(tmp_path, prec):
     # the restored state is bit-identical to the saved one; continuing from it
-    # matches the uninterrupted run to rounding (per-cell force sums use
-    # atomics, so their order - not their value - varies between runs)
+    # matches the uninterrupted run to rounding (the cover/uncover force sums
+    # use atomics, so their order - not their value - varies between runs)
     c = synth.kolmogorov(32, 6)
     from paper_1005_2594_amd import Sim
-    say("case: checkpoint resume, pmx16 32^3")
-    a = Sim(c["params"], precision="pmx16")
+    say(f"case: checkpoint resume, {prec} 32^3")
+    a = Sim(c["params"], precision=prec)
     a.set_particles(c["X"], c["q"]); a.init_fluid()
     a.step(10)
     a.save(tmp_path / "ck.bin")
-    b = Sim(c["params"], precision="pmx16")
+    b = Sim(c["params"], precision=prec)
     b.load(tmp_path / "ck.bin")
     b.n = a.n
     assert np.array_equal(a.owner(), b.owner())
