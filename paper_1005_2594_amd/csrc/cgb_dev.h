@@ -95,6 +95,7 @@ struct DevArgs {
     int* bin_start; // nbins+1
     int* bin_fill;  // nbins
     int* bin_idx;   // n
+    int* rank;      // n: position of each cell in the cell-list order (inverse of bin_idx)
     double* Xs;     // n*4 positions in cell-list order and the cell index
     int* wall_start;// nbins+1 (surface wall nodes per bin)
     int* wall_idx;  // site indices
@@ -367,7 +368,8 @@ hipError_t launch_lmom(const DevArgs& a, hipStream_t st);
 hipError_t launch_prep(const DevArgs& a, hipStream_t st);
 hipError_t launch_kin(const DevArgs& a, hipStream_t st);
 hipError_t launch_clear_cells(const DevArgs& a, hipStream_t st);
-hipError_t launch_raster(const DevArgs& a, hipStream_t st, bool fresh);
+hipError_t launch_raster(const DevArgs& a, hipStream_t st, bool fresh, bool records = true);
+hipError_t launch_step_prep(const DevArgs& a, hipStream_t st);
 hipError_t launch_cellrec(const DevArgs& a, hipStream_t st);
 hipError_t launch_transitions(const DevArgs& a, hipStream_t st, bool bookkeeping);
 hipError_t launch_cells(const DevArgs& a, hipStream_t st);

@@ -32,9 +32,7 @@ __device__ inline int image_shift(int d, float f, int n) {
     return d;
 }
 
-__global__ void prep_kernel(DevArgs a, int zero_forces) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n) return;
+__device__ void prep_one(const DevArgs& a, int p, bool zero_forces) {
     double q[4] = {a.q[4 * p], a.q[4 * p + 1], a.q[4 * p + 2], a.q[4 * p + 3]};
     double o[3];
     axis_of(q, o);
@@ -73,6 +71,12 @@ __global__ void prep_kernel(DevArgs a, int zero_forces) {
     kf[11] = 0.0f;
     if (zero_forces)
         for (int c = 0; c < 6; c++) { a.FTh[6 * p + c] = 0.0; a.FTp[6 * p + c] = 0.0; }
+}
+
+__global__ void prep_kernel(DevArgs a, int zero_forces) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    prep_one(a, p, zero_forces != 0);
 }
 
 hipError_t launch_prep(const DevArgs& a, hipStream_t st) {
@@ -163,11 +167,8 @@ __device__ inline bool covers(const DevArgs& a, const CellRec& c, int x, int y, 
 }
 
 // cell records in cell-list order (the order of the previous cell list; any
-// permutation of the cells is correct)
-__global__ void cellrec_kernel(DevArgs a) {
-    const int k = xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
-    if (k >= a.n) return;
-    const int p = a.bin_idx[k];
+// permutation of the cells is correct): record k describes cell p
+__device__ void record_one(const DevArgs& a, int k, int p) {
     const double* kp = a.kin + 12 * (long long)p;
     CellRec c;
     for (int i = 0; i < 3; i++) { c.X[i] = kp[i]; c.V[i] = kp[3 + i]; c.W[i] = kp[6 + i]; c.o[i] = kp[9 + i]; }
@@ -175,6 +176,12 @@ __global__ void cellrec_kernel(DevArgs a) {
     c.ok = union_box(a, p, c.lo, c.ext) ? 1 : 0;
     if (!c.ok) for (int i = 0; i < 3; i++) { c.lo[i] = 0; c.ext[i] = 0; }
     ((CellRec*)a.crec)[k] = c;
+}
+
+__global__ void cellrec_kernel(DevArgs a) {
+    const int k = xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
+    if (k >= a.n) return;
+    record_one(a, k, a.bin_idx[k]);
 }
 
 hipError_t launch_cellrec(const DevArgs& a, hipStream_t st) {
@@ -707,10 +714,34 @@ __global__ void step_begin_kernel(int* ntrans, int* dstep, int advance) {
     if (threadIdx.x == 0 && advance) *dstep += 1;
 }
 
-hipError_t launch_raster(const DevArgs& a, hipStream_t st, bool fresh) {
-    hipLaunchKernelGGL(step_begin_kernel, dim3(1), dim3(TSEG), 0, st, a.ntrans, a.dstep, fresh ? 0 : 1);
+// Start of a time step in one launch: clear the transition list and advance
+// the device-side step index (block 0), and for each cell its axis, angular
+// velocity and FP32 velocity table, zeroed force sums and its record, written
+// at the cell's position in the previous cell list (the thread that computes
+// a cell's kinematics writes its record, so the two need no separate passes).
+__global__ void step_prep_kernel(DevArgs a) {
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < TSEG) a.ntrans[threadIdx.x] = 0;
+        if (threadIdx.x == 0) *a.dstep += 1;
+    }
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    prep_one(a, p, true);
+    record_one(a, a.rank[p], p);
+}
+
+hipError_t launch_step_prep(const DevArgs& a, hipStream_t st) {
+    if (a.n == 0) hipLaunchKernelGGL(step_begin_kernel, dim3(1), dim3(TSEG), 0, st, a.ntrans, a.dstep, 1);
+    else hipLaunchKernelGGL(step_prep_kernel, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// records: the set-up path builds the step-begin state and the records here;
+// a time step has them from launch_step_prep
+hipError_t launch_raster(const DevArgs& a, hipStream_t st, bool fresh, bool records) {
+    if (records) hipLaunchKernelGGL(step_begin_kernel, dim3(1), dim3(TSEG), 0, st, a.ntrans, a.dstep, fresh ? 0 : 1);
     if (a.n == 0) return hipGetLastError();
-    hipLaunchKernelGGL(cellrec_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
+    if (records) hipLaunchKernelGGL(cellrec_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
     hipLaunchKernelGGL(raster_kernel<false>, dim3(cell_grid(a.n)), dim3(64 * CPW), 0, st, a);
     hipLaunchKernelGGL(raster_kernel<true>, dim3(cell_grid(a.n)), dim3(64 * CPW), 0, st, a);
     return hipGetLastError();
@@ -952,6 +983,7 @@ __global__ void sorted_pos_kernel(DevArgs a) {
     if (t >= a.n) return;
     const int j = a.bin_idx[t];
     ((SortedPos*)a.Xs)[t] = SortedPos{a.X[3 * j], a.X[3 * j + 1], a.X[3 * j + 2], (double)j};
+    a.rank[j] = t;
 }
 
 hipError_t launch_cells(const DevArgs& a, hipStream_t st) {

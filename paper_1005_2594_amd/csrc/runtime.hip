@@ -196,7 +196,7 @@ static LaunchCfg default_tiles(const DevArgs& a) {
 
 static int alloc_particles(cgb_sim* s, int ncap) {
     DevArgs& a = s->a;
-    void* olds[] = {a.X, a.q, a.V, a.L, a.fixed, a.Xprev, a.Hprev, a.kin, a.kinf, a.crec, a.FTh, a.FTp, a.trans, a.pbin, a.bin_idx, a.Xs, a.body_part};
+    void* olds[] = {a.X, a.q, a.V, a.L, a.fixed, a.Xprev, a.Hprev, a.kin, a.kinf, a.crec, a.FTh, a.FTp, a.trans, a.pbin, a.bin_idx, a.rank, a.Xs, a.body_part};
     for (void* p : olds) dfree(s, p);
     const size_t n = (size_t)std::max(ncap, 1);
     HIPCHK(s, dalloc(s, &a.X, 3 * n * 8));
@@ -213,6 +213,7 @@ static int alloc_particles(cgb_sim* s, int ncap) {
     HIPCHK(s, dalloc(s, &a.FTp, 6 * n * 8));
     HIPCHK(s, dalloc(s, &a.pbin, n * 4));
     HIPCHK(s, dalloc(s, &a.bin_idx, n * 4));
+    HIPCHK(s, dalloc(s, &a.rank, n * 4));
     HIPCHK(s, dalloc(s, &a.Xs, n * 4 * 8));
     HIPCHK(s, dalloc(s, &a.body_part, ((n + 255) / 256) * 3 * 8));
     HIPCHK(s, launch_fill_f64(a.body_part, (long long)((n + 255) / 256) * 3, 0.0, s->st));
@@ -499,8 +500,8 @@ int cgb_step(cgb_sim* s, int32_t nsteps) {
                 HIPCHK(s, hipEventCreateWithFlags(e, hipEventDisableTiming));
         }
         hipStream_t sm = fk ? s->st_mem : s->st, sp = fk ? s->st_pot : s->st;
-        HIPCHK(s, timed(s, K_PREP, [&] { return launch_prep(a, s->st); }));
-        HIPCHK(s, timed(s, K_RASTER, [&] { return launch_raster(a, s->st, false); }));
+        HIPCHK(s, timed(s, K_PREP, [&] { return launch_step_prep(a, s->st); }));
+        HIPCHK(s, timed(s, K_RASTER, [&] { return launch_raster(a, s->st, false, false); }));
         if (fk) {
             HIPCHK(s, hipEventRecord(s->ev_ras, s->st));
             HIPCHK(s, hipStreamWaitEvent(sp, s->ev_ras, 0));
