@@ -291,6 +291,10 @@ def main():
             "kernel_ms_per_step": {k: round(v[0] / max(v[1], 1), 4) for k, v in r["kernel_times"].items()},
             "kernel_pass": f"{args.kernel_steps} steps after the timed region, every kernel in sequence on the "
                            "handle's stream, HIP events around each launch",
+            "paper_context": "the paper reports no absolute throughput; its only performance figures are parallel "
+                             "efficiencies of its CPU code on IBM BlueGene/P (combined LB + particles 95.7 % at "
+                             "16,384 and 85.2 % at 32,768 cores relative to 2,048; pure LB 98.1 % at 32,768) on a "
+                             "1024^2 x 2048 lattice with 4.1e6 cells (Sec. IV)",
             "concurrency": "serial" if args.serial else "cell list + potentials and momentum exchange on two side "
                                                         "streams beside the lattice kernels, joined before the integrator",
         },
