@@ -551,9 +551,10 @@ hipError_t launch_usol(const DevArgs& a, hipStream_t st, bool all) {
 // through sum_r C_r and sum_r C_r c_r, and rho(x) factors out: the node needs
 // K = (sum_r w_r q_r, sum_r w_r c_r q_r), q_r = c_r . u(s_r), over its links.
 // A workgroup covers a TX x (256 / TX) patch and sweeps tz planes; the velocity
-// of the patch and a one-node halo is built in LDS three planes at a time from
-// the owner map and the cells' kinematics (FP64, rounded to the link type as
-// the stored velocity field is), so the link sources are read from LDS.
+// of the patch and a one-node halo is built in LDS from the owner map and the
+// cells' kinematics (the per-cell FP32 table for the FP32 link type, FP64
+// kinematics for FP64), in a ring of four planes (three are read while the
+// next is built), so the link sources are read from LDS.
 // Groups of 32 nodes along x (one 128-byte line of an FP32 plane) that hold a
 // node with links are written whole; layout [4][pstride].
 // patch: TX x (256 / TX) nodes of an x-y plane, swept over tz planes
@@ -633,10 +634,14 @@ __device__ inline void lm_build(const DevArgs& a, M* U, int sl, int x0, int y0, 
     }
 }
 
+// workgroup barrier that waits for this wave's LDS accesses only: global
+// loads in flight (the prefetched owners and flags) stay in flight
+__device__ inline void lm_lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 template <class M, int TX>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(M) == 4 ? 8 : 5))) lmom_kernel(DevArgs a, int tz) {
     using S = LmShape<TX>;
-    __shared__ M U[3 * 3 * S::NP];  // [slot][component][HY][HX]
+    __shared__ M U[4 * 3 * S::NP];  // [slot][component][HY][HX]
     const int tx = (int)(threadIdx.x % TX), ty = (int)(threadIdx.x / TX);
     const int x0 = (int)blockIdx.x * TX, y0 = (int)blockIdx.y * S::TY, z0 = (int)blockIdx.z * tz;
     const int x = x0 + tx, y = y0 + ty;
@@ -645,21 +650,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     M* K = (M*)a.lmom;
     const size_t ps = (size_t)a.pstride;
     const int lane = (int)(threadIdx.x & 63);
-    // plane p lives in slot (p - z0 + 1) mod 3; owners are read one plane ahead
+    const unsigned s0 = (unsigned)x + (unsigned)a.nx * ((unsigned)y + (unsigned)a.ny * (unsigned)z0);
+    const unsigned plane = (unsigned)a.nx * (unsigned)a.ny;
+    // plane p lives in slot (p - z0 + 1) & 3 of a four-plane ring: at step z
+    // planes z - 1, z, z + 1 are read while plane z + 2 is written, so one
+    // barrier per step suffices; owners are read one plane ahead and the
+    // node's flags one step ahead, and stay in flight across the barrier
     int o0, o1, n0, n1;
     lm_owners<TX>(a, x0, y0, wrap_halo(z0 - 1, a.nz), &o0, &o1);
     lm_owners<TX>(a, x0, y0, z0, &n0, &n1);
     lm_build<M, TX>(a, U, 0, x0, y0, wrap_halo(z0 - 1, a.nz), o0, o1);
     lm_owners<TX>(a, x0, y0, wrap_halo(z0 + 1, a.nz), &o0, &o1);
     lm_build<M, TX>(a, U, 1, x0, y0, z0, n0, n1);
+    uint32_t fnext = in ? a.flags[s0] : NONFLUID;
     for (int zz = 0; zz < zend; zz++) {
         const int z = z0 + zz;
-        const unsigned s = (unsigned)x + (unsigned)a.nx * ((unsigned)y + (unsigned)a.ny * (unsigned)z);
-        const uint32_t f = in ? a.flags[s] : NONFLUID;
+        const unsigned s = s0 + plane * (unsigned)zz;
+        const uint32_t f = fnext;
+        fnext = (in && zz + 1 < zend) ? a.flags[s + plane] : NONFLUID;
         if (zz + 1 < zend) lm_owners<TX>(a, x0, y0, wrap_halo(z + 2, a.nz), &n0, &n1);
-        lm_build<M, TX>(a, U, (zz + 2) % 3, x0, y0, wrap_halo(z + 1, a.nz), o0, o1);
+        lm_build<M, TX>(a, U, (zz + 2) & 3, x0, y0, wrap_halo(z + 1, a.nz), o0, o1);
         o0 = n0; o1 = n1;
-        __syncthreads();
+        lm_lds_barrier();
         const bool lk = !(f & NONFLUID) && (f & LINKBITS) != 0u;
         const unsigned long long m = __ballot(lk);
         if (in && ((m >> (lane & ~31)) & 0xffffffffull) != 0ull) {
@@ -667,7 +679,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
             M k0 = 0, k1 = 0, k2 = 0, k3 = 0;
 #pragma unroll
             for (int r = 1; r < 19; r++) {
-                const M* P = U + (size_t)((zz + 1 - CZ(r) + 3) % 3) * 3 * S::NP + (ty + 1 - CY(r)) * S::HX + (tx + 1 - CX(r));
+                const M* P = U + (size_t)((zz + 1 - CZ(r)) & 3) * 3 * S::NP + (ty + 1 - CY(r)) * S::HX + (tx + 1 - CX(r));
                 M q = 0;
                 if (CX(r)) q += (M)CX(r) * P[0];
                 if (CY(r)) q += (M)CY(r) * P[S::NP];
@@ -683,7 +695,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
             K[2 * ps + s] = k2;
             K[3 * ps + s] = k3;
         }
-        __syncthreads();
     }
 }
 
