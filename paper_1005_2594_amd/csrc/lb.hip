@@ -13,7 +13,9 @@
 // sum C_r = 6 rho(x) sum w_r q_r and sum C_r c_r = 6 rho(x) sum w_r c_r q_r
 // (q_r = c_r . u(s_r)): a stencil kernel stores these moments at each fluid
 // node with links after the occupancy update, and the LB reads them with one
-// coalesced load.  For general tau the per-direction values are needed: a
+// coalesced load.  With the split FP16 codec the same kernel also sums, at
+// every fluid node, the density parts w_r D of the pulled populations (D of
+// each population's source node), so that the LB decodes only the residuals.  For general tau the per-direction values are needed: a
 // node-parallel kernel stores u(s) for every cell node and walls hold their
 // plane velocity, and the LB gathers the velocity of each link's source.  In
 // neither case does a link need to know which body is behind it.
@@ -201,52 +203,6 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
     }
 }
 
-// Split codec: every pulled population is decoded with the density of the
-// node it comes from.  The decoded density field of the block's patch plus a
-// one-node halo is kept in LDS for four consecutive planes (a ring: planes
-// z - 1, z, z + 1 are read while z + 2 is written), each plane filled once
-// from one coalesced pass and read 19 times from LDS.  Patches have at most
-// 256 nodes, so a halo'd plane has at most (256 + 2) x 3 positions and each
-// thread fills at most four of them.
-constexpr int RING_NP = 774;
-
-// workgroup barrier that waits for this wave's LDS accesses only: global
-// loads in flight (the next plane of the ring, the next flags) stay in flight
-__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
-template <int P>
-struct DensRing {
-    static_assert(sizeof(typename Codec<P>::T) == 2, "the ring holds 2-byte stored densities");
-    using T = typename Codec<P>::T;
-    unsigned off[4];  // in-plane byte offsets of this thread's ring positions (OOB: none)
-    uint32_t pre[4];  // loaded 16-bit values, zero-extended (kept unpacked while in flight)
-    int np, nthr, t;
-    __device__ DensRing(const DevArgs& a, int bx, int by, int tid, int x0, int y0) : np((bx + 2) * (by + 2)), nthr(bx * by), t(tid) {
-        const int hx = bx + 2;
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const int q = t + k * nthr;
-            const int xs = wrap_halo(x0 - 1 + q % hx, a.nx), ys = wrap_halo(y0 - 1 + q / hx, a.ny);
-            off[k] = q < np ? (unsigned)sizeof(T) * ((unsigned)xs + (unsigned)a.nx * (unsigned)ys) : 0xfffffff0u;
-        }
-    }
-    // issue the loads of plane pz into registers
-    __device__ void load(const DevArgs& a, __amdgpu_buffer_rsrc_t rRA, int pz) {
-        const unsigned base = (unsigned)sizeof(T) * (unsigned)a.nx * (unsigned)a.ny * (unsigned)pz;
-#pragma unroll
-        for (int k = 0; k < 4; k++)
-            pre[k] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(rRA, off[k] == 0xfffffff0u ? off[k] : base + off[k], 0, 0);
-    }
-    // decode the loaded plane into ring slot sl
-    __device__ void put(const DevArgs& a, float* L, int sl) {
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const int q = t + k * nthr;
-            if (q < np) L[sl * RING_NP + q] = (float)rho_dec<P>(a, __builtin_bit_cast(T, (unsigned short)pre[k]));
-        }
-    }
-};
-
 // tau = 1 (the paper's operating point, Sec. IV): the post-collision state is
 // n^eq(rho, u) plus the forcing term, a function of the moments alone, so the
 // pulled populations are folded into rho and j as they arrive.
@@ -278,31 +234,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
     const R gy = a.force_mode == 1 ? (R)a.g[1] : (R)0;
     const R gz = a.force_mode == 1 ? (R)a.g[2] : (a.force_mode == 2 ? (R)(a.f0 * a.ysin[yc]) : (R)0);
 
-    // split codec: density ring (planes z0 - 1 and z0 now, z0 + 1 in flight)
-    __shared__ float Lr[Cd::SPLIT ? 4 * RING_NP : 1];
-    const int tx = (int)threadIdx.x, ty = (int)threadIdx.y, bxd = (int)blockDim.x;
-    DensRing<Cd::SPLIT ? P : CGB_PMX16S> ring(a, bxd, (int)blockDim.y, tx + bxd * ty, (int)blockIdx.x * bxd, (int)blockIdx.y * (int)blockDim.y);
-    if constexpr (Cd::SPLIT) {
-        ring.load(a, rRA, wrap_halo(z0 - 1, a.nz));
-        ring.put(a, Lr, 0);
-        ring.load(a, rRA, wrap_halo(z0, a.nz));
-        ring.put(a, Lr, 1);
-        ring.load(a, rRA, wrap_halo(z0 + 1, a.nz));
-    }
-
     // flags of the first node; each step prefetches the next node's flags
     uint32_t fnext = (inb && z0 < a.nz) ? bload<uint32_t>(rFl, 4u * ((unsigned)x + nx * (unsigned)y + plane * (unsigned)z0)) : NONFLUID;
 #pragma unroll 1
     for (int zz = 0; zz < TZ; zz++) {
         const int z = z0 + zz;
-        if (z >= a.nz) break;  // uniform over the block
-        if constexpr (Cd::SPLIT) {
-            // plane z + 1 into its slot, plane z + 2 in flight; the slot
-            // written here held plane z - 3, which no thread reads any more
-            ring.put(a, Lr, (zz + 2) & 3);
-            if (zz + 1 < TZ) ring.load(a, rRA, wrap_halo(z + 2, a.nz));
-            lds_barrier();
-        }
+        if (z >= a.nz) break;
         const unsigned i = (unsigned)x + nx * (unsigned)y + plane * (unsigned)z;
         const uint32_t f = fnext;
         fnext = (inb && zz + 1 < TZ && z + 1 < a.nz) ? bload<uint32_t>(rFl, 4u * (i + plane)) : NONFLUID;
@@ -320,29 +257,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
         auto src = [&](int r) { return i + (unsigned)(ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1]); };
         const uint32_t links = f & LINKBITS;
 
-        // split codec: the node's own stored density from the ring
-        R Down = 0;
-        if constexpr (Cd::SPLIT) Down = (R)Lr[((zz + 1) & 3) * RING_NP + (ty + 1) * (bxd + 2) + tx + 1];
-
+        R Down = 0;  // the node's stored density deviation (for C; not needed by the split codec)
         R drho = 0, jx = 0, jy = 0, jz = 0;
-        if constexpr (Cd::SPLIT) {
-            // the density parts w_r D of the pulled populations: D of the
-            // source node, or the node's own D for a bounced population
-#pragma unroll
-            for (int r = 0; r < 19; r++) {
-                R Ds = Down;
-                if (r > 0 && !((f >> r) & 1u))
-                    Ds = (R)Lr[((zz + 1 - CZ(r)) & 3) * RING_NP + (ty + 1 - CY(r)) * (bxd + 2) + (tx + 1 - CX(r))];
-                const R wd = (R)WD(r) * Ds;
-                drho += wd;
-                if (CX(r)) jx += CX(r) * wd;
-                if (CY(r)) jy += CY(r) * wd;
-                if (CZ(r)) jz += CZ(r) * wd;
-            }
-            // the density parts are summed before the pulls are issued, so
-            // that the LDS reads do not hold registers across the pulls
-            __builtin_amdgcn_sched_barrier(0);
-        }
         // issue the 19 pulls (non-fluid source: bounce-back), the node's link
         // moments and its stored density together
         T v[19];
@@ -351,20 +267,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
             const bool bb = (f >> r) & 1u;
             v[r] = bload<T>(rA, ES * (bb ? (unsigned)OPP(r) * ps + i : (unsigned)r * ps + src(r)));
         }
+        // link moments; the split codec's moments hold every fluid node's
+        // density parts too (see below)
         M km[4];
 #pragma unroll
-        for (int c = 0; c < 4; c++) km[c] = bload<M>(rK, links ? (unsigned)sizeof(M) * ((unsigned)c * ps + i) : OOB);
+        for (int c = 0; c < 4; c++) km[c] = bload<M>(rK, (links || Cd::SPLIT) ? (unsigned)sizeof(M) * ((unsigned)c * ps + i) : OOB);
         if constexpr (!Cd::SPLIT) Down = rho_dec<P>(a, bload<T>(rRA, links ? ES * i : OOB));
 #pragma unroll
         for (int r = 0; r < 19; r++) {
-            // split codec: the residual parts (the density parts are summed above)
+            // split codec: the residual parts w_r h_r only
             const R dv = pop_dec<P>(a, v[r], r, (R)0);
             drho += dv;
             if (CX(r)) jx += CX(r) * dv;
             if (CY(r)) jy += CY(r) * dv;
             if (CZ(r)) jz += CZ(r) * dv;
         }
-        if (links) {
+        if constexpr (Cd::SPLIT) {
+            // the density parts of the pulled populations (w_r D of each
+            // population's source, the node's own for a bounced one) and the
+            // moving-boundary corrections, summed by the link-moment kernel
+            drho += (R)km[0]; jx += (R)km[1]; jy += (R)km[2]; jz += (R)km[3];
+        } else if (links) {
             // moving-boundary corrections summed over the links:
             // sum C_r = 6 rho(x) K0, sum C_r c_r = 6 rho(x) (K1, K2, K3)
             const M rho6 = (M)6 * ((M)a.rho0 + (M)Down);

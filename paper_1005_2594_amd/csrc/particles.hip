@@ -576,8 +576,9 @@ __device__ inline unsigned lm_site(const DevArgs& a, int q, int x0, int y0, int 
 }
 
 // velocity of position q with owner o, written to the plane in slot sl
-template <class M, int TX>
-__device__ inline void lm_vel(const DevArgs& a, M* U, int sl, int q, int o, int x, int y, int z) {
+// (NC = 4: the decoded stored density deviation dr of the split codec too)
+template <class M, int TX, int NC>
+__device__ inline void lm_vel(const DevArgs& a, M* U, int sl, int q, int o, uint32_t dr, int x, int y, int z) {
     using S = LmShape<TX>;
     double u[3] = {0, 0, 0};
     if (o >= 0) {
@@ -607,30 +608,39 @@ __device__ inline void lm_vel(const DevArgs& a, M* U, int sl, int q, int o, int 
         if (y == 0) { u[0] = a.wvb[0]; u[1] = a.wvb[1]; u[2] = a.wvb[2]; }
         else if (y == a.ny - 1) { u[0] = a.wvt[0]; u[1] = a.wvt[1]; u[2] = a.wvt[2]; }
     }
-    M* P = U + (size_t)sl * 3 * S::NP;
+    M* P = U + (size_t)sl * NC * S::NP;
     P[q] = (M)u[0];
     P[S::NP + q] = (M)u[1];
     P[2 * S::NP + q] = (M)u[2];
+    if constexpr (NC == 4) P[3 * S::NP + q] = (M)((float)__builtin_bit_cast(_Float16, (unsigned short)dr) * a.pmx_inv);
 }
 
-// owners of the two positions of this thread in plane z
-template <int TX>
-__device__ inline void lm_owners(const DevArgs& a, int x0, int y0, int z, int* o0, int* o1) {
+// owners (and, NC = 4, stored FP16 density deviations) of the two positions
+// of this thread in plane z
+template <int TX, int NC>
+__device__ inline void lm_owners(const DevArgs& a, int x0, int y0, int z, int* o0, int* o1, uint32_t* d0, uint32_t* d1) {
     int x, y;
     const int q0 = (int)threadIdx.x, q1 = (int)threadIdx.x + 256;
-    *o0 = a.owner[lm_site<TX>(a, q0, x0, y0, z, &x, &y)];
-    *o1 = q1 < LmShape<TX>::NP ? a.owner[lm_site<TX>(a, q1, x0, y0, z, &x, &y)] : OWN_FLUID;
+    const unsigned s0 = lm_site<TX>(a, q0, x0, y0, z, &x, &y);
+    const unsigned s1 = q1 < LmShape<TX>::NP ? lm_site<TX>(a, q1, x0, y0, z, &x, &y) : s0;
+    *o0 = a.owner[s0];
+    *o1 = q1 < LmShape<TX>::NP ? a.owner[s1] : OWN_FLUID;
+    if constexpr (NC == 4) {
+        const unsigned short* D = (const unsigned short*)a.rhoA;
+        *d0 = D[s0];
+        *d1 = D[s1];
+    }
 }
 
-template <class M, int TX>
-__device__ inline void lm_build(const DevArgs& a, M* U, int sl, int x0, int y0, int z, int o0, int o1) {
+template <class M, int TX, int NC>
+__device__ inline void lm_build(const DevArgs& a, M* U, int sl, int x0, int y0, int z, int o0, int o1, uint32_t d0, uint32_t d1) {
     int x, y;
     const int q0 = (int)threadIdx.x, q1 = (int)threadIdx.x + 256;
     lm_site<TX>(a, q0, x0, y0, z, &x, &y);
-    lm_vel<M, TX>(a, U, sl, q0, o0, x, y, z);
+    lm_vel<M, TX, NC>(a, U, sl, q0, o0, d0, x, y, z);
     if (q1 < LmShape<TX>::NP) {
         lm_site<TX>(a, q1, x0, y0, z, &x, &y);
-        lm_vel<M, TX>(a, U, sl, q1, o1, x, y, z);
+        lm_vel<M, TX, NC>(a, U, sl, q1, o1, d1, x, y, z);
     }
 }
 
@@ -638,10 +648,16 @@ __device__ inline void lm_build(const DevArgs& a, M* U, int sl, int x0, int y0, 
 // loads in flight (the prefetched owners and flags) stay in flight
 __device__ inline void lm_lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-template <class M, int TX>
+// NC = 4 (split FP16 codec): besides the link moments, each fluid node gets
+// the density parts of its pulled populations, T = (sum_r w_r D_r,
+// sum_r w_r c_r D_r) with D_r the stored density deviation of the source of
+// direction r (the node's own for the rest direction and for a bounced
+// population), and stores E = 6 rho(x) K + T, which the LB adds to its sums
+// of the FP16 residuals; every site is written (zeros at non-fluid nodes).
+template <class M, int TX, int NC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(M) == 4 ? 8 : 5))) lmom_kernel(DevArgs a, int tz) {
     using S = LmShape<TX>;
-    __shared__ M U[4 * 3 * S::NP];  // [slot][component][HY][HX]
+    __shared__ M U[4 * NC * S::NP];  // [slot][component][HY][HX]
     const int tx = (int)(threadIdx.x % TX), ty = (int)(threadIdx.x / TX);
     const int x0 = (int)blockIdx.x * TX, y0 = (int)blockIdx.y * S::TY, z0 = (int)blockIdx.z * tz;
     const int x = x0 + tx, y = y0 + ty;
@@ -657,38 +673,61 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     // barrier per step suffices; owners are read one plane ahead and the
     // node's flags one step ahead, and stay in flight across the barrier
     int o0, o1, n0, n1;
-    lm_owners<TX>(a, x0, y0, wrap_halo(z0 - 1, a.nz), &o0, &o1);
-    lm_owners<TX>(a, x0, y0, z0, &n0, &n1);
-    lm_build<M, TX>(a, U, 0, x0, y0, wrap_halo(z0 - 1, a.nz), o0, o1);
-    lm_owners<TX>(a, x0, y0, wrap_halo(z0 + 1, a.nz), &o0, &o1);
-    lm_build<M, TX>(a, U, 1, x0, y0, z0, n0, n1);
+    uint32_t e0 = 0, e1 = 0, m0 = 0, m1 = 0;
+    lm_owners<TX, NC>(a, x0, y0, wrap_halo(z0 - 1, a.nz), &o0, &o1, &e0, &e1);
+    lm_owners<TX, NC>(a, x0, y0, z0, &n0, &n1, &m0, &m1);
+    lm_build<M, TX, NC>(a, U, 0, x0, y0, wrap_halo(z0 - 1, a.nz), o0, o1, e0, e1);
+    lm_owners<TX, NC>(a, x0, y0, wrap_halo(z0 + 1, a.nz), &o0, &o1, &e0, &e1);
+    lm_build<M, TX, NC>(a, U, 1, x0, y0, z0, n0, n1, m0, m1);
     uint32_t fnext = in ? a.flags[s0] : NONFLUID;
     for (int zz = 0; zz < zend; zz++) {
         const int z = z0 + zz;
         const unsigned s = s0 + plane * (unsigned)zz;
         const uint32_t f = fnext;
         fnext = (in && zz + 1 < zend) ? a.flags[s + plane] : NONFLUID;
-        if (zz + 1 < zend) lm_owners<TX>(a, x0, y0, wrap_halo(z + 2, a.nz), &n0, &n1);
-        lm_build<M, TX>(a, U, (zz + 2) & 3, x0, y0, wrap_halo(z + 1, a.nz), o0, o1);
-        o0 = n0; o1 = n1;
+        if (zz + 1 < zend) lm_owners<TX, NC>(a, x0, y0, wrap_halo(z + 2, a.nz), &n0, &n1, &m0, &m1);
+        lm_build<M, TX, NC>(a, U, (zz + 2) & 3, x0, y0, wrap_halo(z + 1, a.nz), o0, o1, e0, e1);
+        o0 = n0; o1 = n1; e0 = m0; e1 = m1;
         lm_lds_barrier();
-        const bool lk = !(f & NONFLUID) && (f & LINKBITS) != 0u;
-        const unsigned long long m = __ballot(lk);
-        if (in && ((m >> (lane & ~31)) & 0xffffffffull) != 0ull) {
+        const bool fl = !(f & NONFLUID);
+        const bool lk = fl && (f & LINKBITS) != 0u;
+        const unsigned long long m = __ballot(NC == 4 ? fl : lk);
+        if (in && (NC == 4 || ((m >> (lane & ~31)) & 0xffffffffull) != 0ull)) {
             // sums over the links (directions that are not links weigh 0)
             M k0 = 0, k1 = 0, k2 = 0, k3 = 0;
+            M t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+            M Dx = 0;
+            if constexpr (NC == 4) {
+                Dx = U[(size_t)((zz + 1) & 3) * NC * S::NP + 3 * S::NP + (ty + 1) * S::HX + (tx + 1)];
+                t0 = (M)(1.0 / 3.0) * Dx;
+            }
 #pragma unroll
             for (int r = 1; r < 19; r++) {
-                const M* P = U + (size_t)((zz + 1 - CZ(r)) & 3) * 3 * S::NP + (ty + 1 - CY(r)) * S::HX + (tx + 1 - CX(r));
+                const M* P = U + (size_t)((zz + 1 - CZ(r)) & 3) * NC * S::NP + (ty + 1 - CY(r)) * S::HX + (tx + 1 - CX(r));
                 M q = 0;
                 if (CX(r)) q += (M)CX(r) * P[0];
                 if (CY(r)) q += (M)CY(r) * P[S::NP];
                 if (CZ(r)) q += (M)CZ(r) * P[2 * S::NP];
-                const M wq = (lk && ((f >> r) & 1u)) ? (M)WD(r) * q : (M)0;
+                const bool bb = (f >> r) & 1u;
+                const M wq = (lk && bb) ? (M)WD(r) * q : (M)0;
                 k0 += wq;
                 if (CX(r)) k1 += (M)CX(r) * wq;
                 if (CY(r)) k2 += (M)CY(r) * wq;
                 if (CZ(r)) k3 += (M)CZ(r) * wq;
+                if constexpr (NC == 4) {
+                    const M wd = (M)WD(r) * (bb ? Dx : P[3 * S::NP]);
+                    t0 += wd;
+                    if (CX(r)) t1 += (M)CX(r) * wd;
+                    if (CY(r)) t2 += (M)CY(r) * wd;
+                    if (CZ(r)) t3 += (M)CZ(r) * wd;
+                }
+            }
+            if constexpr (NC == 4) {
+                const M rho6 = (M)6 * ((M)a.rho0 + Dx);
+                k0 = fl ? rho6 * k0 + t0 : (M)0;
+                k1 = fl ? rho6 * k1 + t1 : (M)0;
+                k2 = fl ? rho6 * k2 + t2 : (M)0;
+                k3 = fl ? rho6 * k3 + t3 : (M)0;
             }
             K[s] = k0;
             K[ps + s] = k1;
@@ -706,11 +745,14 @@ hipError_t launch_lmom(const DevArgs& a, hipStream_t st) {
     const int tz = patches * ((a.nz + 15) / 16) >= 2048 ? 16 : 4;
     const dim3 g((unsigned)((a.nx + tx - 1) / tx), (unsigned)((a.ny + ty - 1) / ty), (unsigned)((a.nz + tz - 1) / tz)), b(256);
     if (a.precision == CGB_P64) {
-        if (tx == 32) hipLaunchKernelGGL((lmom_kernel<double, 32>), g, b, 0, st, a, tz);
-        else hipLaunchKernelGGL((lmom_kernel<double, 64>), g, b, 0, st, a, tz);
+        if (tx == 32) hipLaunchKernelGGL((lmom_kernel<double, 32, 3>), g, b, 0, st, a, tz);
+        else hipLaunchKernelGGL((lmom_kernel<double, 64, 3>), g, b, 0, st, a, tz);
+    } else if (a.precision == CGB_PMX16S) {
+        if (tx == 32) hipLaunchKernelGGL((lmom_kernel<float, 32, 4>), g, b, 0, st, a, tz);
+        else hipLaunchKernelGGL((lmom_kernel<float, 64, 4>), g, b, 0, st, a, tz);
     } else {
-        if (tx == 32) hipLaunchKernelGGL((lmom_kernel<float, 32>), g, b, 0, st, a, tz);
-        else hipLaunchKernelGGL((lmom_kernel<float, 64>), g, b, 0, st, a, tz);
+        if (tx == 32) hipLaunchKernelGGL((lmom_kernel<float, 32, 3>), g, b, 0, st, a, tz);
+        else hipLaunchKernelGGL((lmom_kernel<float, 64, 3>), g, b, 0, st, a, tz);
     }
     return hipGetLastError();
 }

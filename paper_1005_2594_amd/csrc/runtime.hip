@@ -463,6 +463,9 @@ int cgb_init_fluid(cgb_sim* s, const double* rho, const double* u) {
     if (u) { du = s->tmp + a.ns; HIPCHK(s, hipMemcpyAsync(du, u, 3 * nsb, hipMemcpyHostToDevice, s->st)); }
     bind_buffers(s);
     HIPCHK(s, launch_equilibrium_fill(a, drho, du, s->st));
+    // the split codec's link moments carry density parts: rebuild them for
+    // the new state (every step rebuilds them before its LB as well)
+    if (a.lmom && a.precision == CGB_PMX16S) HIPCHK(s, launch_lmom(a, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     s->fluid_ready = true;
     return CGB_OK;
@@ -477,6 +480,7 @@ int cgb_set_populations(cgb_sim* s, const double* d) {
     HIPCHK(s, hipMemcpyAsync(s->tmp, d, bytes, hipMemcpyHostToDevice, s->st));
     bind_buffers(s);
     HIPCHK(s, launch_encode(a, s->tmp, s->st));
+    if (a.lmom && a.precision == CGB_PMX16S) HIPCHK(s, launch_lmom(a, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     return CGB_OK;
 }
