@@ -701,6 +701,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                 Dx = U[(size_t)((zz + 1) & 3) * NC * S::NP + 3 * S::NP + (ty + 1) * S::HX + (tx + 1)];
                 t0 = (M)(1.0 / 3.0) * Dx;
             }
+            if constexpr (NC == 4) {
+                // density parts first, then the link sums (fewer values live at once)
+#pragma unroll
+                for (int r = 1; r < 19; r++) {
+                    const M* P = U + (size_t)((zz + 1 - CZ(r)) & 3) * NC * S::NP + (ty + 1 - CY(r)) * S::HX + (tx + 1 - CX(r));
+                    const M wd = (M)WD(r) * (((f >> r) & 1u) ? Dx : P[3 * S::NP]);
+                    t0 += wd;
+                    if (CX(r)) t1 += (M)CX(r) * wd;
+                    if (CY(r)) t2 += (M)CY(r) * wd;
+                    if (CZ(r)) t3 += (M)CZ(r) * wd;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
 #pragma unroll
             for (int r = 1; r < 19; r++) {
                 const M* P = U + (size_t)((zz + 1 - CZ(r)) & 3) * NC * S::NP + (ty + 1 - CY(r)) * S::HX + (tx + 1 - CX(r));
@@ -714,13 +727,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                 if (CX(r)) k1 += (M)CX(r) * wq;
                 if (CY(r)) k2 += (M)CY(r) * wq;
                 if (CZ(r)) k3 += (M)CZ(r) * wq;
-                if constexpr (NC == 4) {
-                    const M wd = (M)WD(r) * (bb ? Dx : P[3 * S::NP]);
-                    t0 += wd;
-                    if (CX(r)) t1 += (M)CX(r) * wd;
-                    if (CY(r)) t2 += (M)CY(r) * wd;
-                    if (CZ(r)) t3 += (M)CZ(r) * wd;
-                }
             }
             if constexpr (NC == 4) {
                 const M rho6 = (M)6 * ((M)a.rho0 + Dx);
