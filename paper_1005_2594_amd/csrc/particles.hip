@@ -32,17 +32,22 @@ __device__ inline int image_shift(int d, float f, int n) {
     return d;
 }
 
-__device__ void prep_one(const DevArgs& a, int p, bool zero_forces) {
-    double q[4] = {a.q[4 * p], a.q[4 * p + 1], a.q[4 * p + 2], a.q[4 * p + 3]};
-    double o[3];
-    axis_of(q, o);
-    const double* L = a.L + 3 * p;
-    const double oL = o[0] * L[0] + o[1] * L[1] + o[2] * L[2];
-    const double kk = 1.0 / a.Ipar - 1.0 / a.Iperp;
-    double* k = a.kin + 12 * (long long)p;
+// kinematics of cell p into k (X, V, Omega, o) and the tables; every input is
+// loaded before the first store and nothing stored is read back, so the
+// loads of a wave are in flight together
+__device__ void prep_one(const DevArgs& a, int p, bool zero_forces, double* k) {
+    double q[4], L[3];
+    for (int c = 0; c < 4; c++) q[c] = a.q[4 * p + c];
     for (int c = 0; c < 3; c++) {
+        L[c] = a.L[3 * p + c];
         k[c] = a.X[3 * p + c];
         k[3 + c] = a.V[3 * p + c];
+    }
+    double o[3];
+    axis_of(q, o);
+    const double oL = o[0] * L[0] + o[1] * L[1] + o[2] * L[2];
+    const double kk = 1.0 / a.Ipar - 1.0 / a.Iperp;
+    for (int c = 0; c < 3; c++) {
         k[6 + c] = L[c] / a.Iperp + kk * oL * o[c];
         k[9 + c] = o[c];
     }
@@ -60,6 +65,8 @@ __device__ void prep_one(const DevArgs& a, int p, bool zero_forces) {
         if (b[c] < 0) b[c] += L3[c];
     }
     cross3(k + 6, db, U0);
+    double* kd = a.kin + 12 * (long long)p;
+    for (int c = 0; c < 12; c++) kd[c] = k[c];
     float* kf = a.kinf + 12 * (long long)p;
     for (int c = 0; c < 3; c++) {
         kf[c] = (float)(k[3 + c] + U0[c]);
@@ -76,7 +83,8 @@ __device__ void prep_one(const DevArgs& a, int p, bool zero_forces) {
 __global__ void prep_kernel(DevArgs a, int zero_forces) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n) return;
-    prep_one(a, p, zero_forces != 0);
+    double k[12];
+    prep_one(a, p, zero_forces != 0, k);
 }
 
 hipError_t launch_prep(const DevArgs& a, hipStream_t st) {
@@ -129,17 +137,28 @@ __device__ inline void half_extents(const DevArgs& a, const double* o, double* h
     for (int c = 0; c < 3; c++) h[c] = sqrt(fmax(rp2 - (rp2 - rl2) * o[c] * o[c], 0.0)) + 1e-6;
 }
 
-// union of the boxes at the previous rasterisation (Xprev, Hprev) and now.
-// Returns false (and flags instability) for a box that is not finite or wider
-// than a cell moving less than half a node per step can span, so that no
-// state of the cells can send the walk outside the lattice.
-__device__ inline bool union_box(const DevArgs& a, int p, int* lo, int* ext) {
-    const double* k = a.kin + 12 * (long long)p;
+// the box of the previous rasterisation: centre and half extents
+struct PrevBox {
+    double X[3], H[3];
+};
+
+__device__ inline PrevBox prev_box(const DevArgs& a, int p) {
+    PrevBox b;
+    for (int c = 0; c < 3; c++) { b.X[c] = a.Xprev[3 * p + c]; b.H[c] = a.Hprev[3 * p + c]; }
+    return b;
+}
+
+// union of the boxes at the previous rasterisation (pb) and now (k: the
+// cell's kinematics).  Returns false (and flags instability) for a box that
+// is not finite or wider than a cell moving less than half a node per step
+// can span, so that no state of the cells can send the walk outside the
+// lattice.
+__device__ inline bool union_box(const DevArgs& a, const double* k, const PrevBox& pb, int* lo, int* ext) {
     double h[3];
     half_extents(a, k + 9, h);
     const int maxext = 2 * (int)ceil(a.Rb) + 6;
     for (int c = 0; c < 3; c++) {
-        double x0 = a.Xprev[3 * p + c];
+        double x0 = pb.X[c];
         const double x1 = k[c];
         const double Lb = c == 0 ? a.nx : (c == 1 ? a.ny : a.nz);
         if (c != 1 || !a.wall_y) {
@@ -148,7 +167,7 @@ __device__ inline bool union_box(const DevArgs& a, int p, int* lo, int* ext) {
             if (d > 0.5 * Lb) x0 -= Lb;
             else if (d < -0.5 * Lb) x0 += Lb;
         }
-        const double hp = a.Hprev[3 * p + c];
+        const double hp = pb.H[c];
         const double mn = fmin(x0 - hp, x1 - h[c]), mx = fmax(x0 + hp, x1 + h[c]);
         if (!(mn > -Lb && mx < 2.0 * Lb && mx - mn < (double)maxext)) {
             atomicOr(a.status, ST_UNSTABLE);
@@ -167,13 +186,13 @@ __device__ inline bool covers(const DevArgs& a, const CellRec& c, int x, int y, 
 }
 
 // cell records in cell-list order (the order of the previous cell list; any
-// permutation of the cells is correct): record k describes cell p
-__device__ void record_one(const DevArgs& a, int k, int p) {
-    const double* kp = a.kin + 12 * (long long)p;
+// permutation of the cells is correct): record k describes cell p, whose
+// kinematics are kp
+__device__ void record_one(const DevArgs& a, int k, int p, const double* kp, const PrevBox& pb) {
     CellRec c;
     for (int i = 0; i < 3; i++) { c.X[i] = kp[i]; c.V[i] = kp[3 + i]; c.W[i] = kp[6 + i]; c.o[i] = kp[9 + i]; }
     c.p = p;
-    c.ok = union_box(a, p, c.lo, c.ext) ? 1 : 0;
+    c.ok = union_box(a, kp, pb, c.lo, c.ext) ? 1 : 0;
     if (!c.ok) for (int i = 0; i < 3; i++) { c.lo[i] = 0; c.ext[i] = 0; }
     ((CellRec*)a.crec)[k] = c;
 }
@@ -181,7 +200,10 @@ __device__ void record_one(const DevArgs& a, int k, int p) {
 __global__ void cellrec_kernel(DevArgs a) {
     const int k = xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
     if (k >= a.n) return;
-    record_one(a, k, a.bin_idx[k]);
+    const int p = a.bin_idx[k];
+    double kp[12];
+    for (int c = 0; c < 12; c++) kp[c] = a.kin[12 * (long long)p + c];
+    record_one(a, k, p, kp, prev_box(a, p));
 }
 
 hipError_t launch_cellrec(const DevArgs& a, hipStream_t st) {
@@ -785,8 +807,12 @@ __global__ void step_prep_kernel(DevArgs a) {
     }
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n) return;
-    prep_one(a, p, true);
-    record_one(a, a.rank[p], p);
+    // the record's inputs are loaded before prep_one stores
+    const int rk = a.rank[p];
+    const PrevBox pb = prev_box(a, p);
+    double k[12];
+    prep_one(a, p, true, k);
+    record_one(a, rk, p, k, pb);
 }
 
 hipError_t launch_step_prep(const DevArgs& a, hipStream_t st) {
@@ -1416,8 +1442,13 @@ __device__ void integrate_one(const DevArgs& a, int p, double* bf) {
         for (int c = 0; c < 3; c++) { a.V[3 * p + c] = 0.0; a.L[3 * p + c] = 0.0; }
         return;
     }
+    // the state is loaded before the first store (the stores could alias the
+    // loads as far as the compiler knows), so the loads are in flight together
+    double X[3], q[4];
+    for (int c = 0; c < 3; c++) X[c] = a.X[3 * p + c];
+    for (int c = 0; c < 4; c++) q[c] = a.q[4 * p + c];
     double gb[3] = {0, 0, 0};
-    if (a.force_on_particles) body_force(a, a.X[3 * p + 1], gb);
+    if (a.force_on_particles) body_force(a, X[1], gb);
     bool bad = false;
     double Lnew[3], Vn[3];
     for (int c = 0; c < 3; c++) {
@@ -1435,7 +1466,7 @@ __device__ void integrate_one(const DevArgs& a, int p, double* bf) {
     for (int c = 0; c < 3; c++) {
         a.V[3 * p + c] = Vn[c];
         a.L[3 * p + c] = Lnew[c];
-        double xn = a.X[3 * p + c] + Vn[c];
+        double xn = X[c] + Vn[c];
         if (!(c == 1 && a.wall_y)) {
             const double Lb = c == 0 ? a.nx : (c == 1 ? a.ny : a.nz);
             if (xn >= Lb) xn -= Lb;
@@ -1445,7 +1476,6 @@ __device__ void integrate_one(const DevArgs& a, int p, double* bf) {
     }
     bf[0] = a.Mdrive * gb[0]; bf[1] = a.Mdrive * gb[1]; bf[2] = a.Mdrive * gb[2];
     // quaternion: half-step predictor, then full step with the midpoint rate
-    double q[4] = {a.q[4 * p], a.q[4 * p + 1], a.q[4 * p + 2], a.q[4 * p + 3]};
     double o[3], w[3], dq[4], qh[4], qn[4];
     axis_of(q, o);
     omega_sym(a, o, Lnew, w);
