@@ -765,22 +765,53 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     }
 }
 
-// patch width 32 on lattices at most 48 wide; a short sweep when long sweeps
-// would leave the device with few workgroups
+// workgroups of a link-moment kernel resident on the whole device at once
+// (0 if the runtime cannot say); fixed per process
+template <class M, int TX, int NC>
+static int lm_resident() {
+    static const int n = [] {
+        int dev = 0, ncu = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, lmom_kernel<M, TX, NC>, 256, 0) != hipSuccess) return 0;
+        return ncu * per;
+    }();
+    return n;
+}
+
+// patch width 32 on lattices at most 48 wide.  A large lattice is swept in
+// as few slabs as fill the device with one round of resident workgroups (each
+// workgroup builds two planes before its first node, so long sweeps cost
+// less, and a second, partial round would leave the device part idle); a
+// short sweep when long sweeps would leave the device with few workgroups.
+template <class M, int TX, int NC>
+static void lm_launch(const DevArgs& a, hipStream_t st) {
+    const int ty = 256 / TX;
+    const long long patches = (long long)((a.nx + TX - 1) / TX) * ((a.ny + ty - 1) / ty);
+    int tz = 4;
+    if (patches * ((a.nz + 15) / 16) >= 2048) {
+        tz = 16;
+        const long long slabs = lm_resident<M, TX, NC>() / patches;
+        if (slabs >= 1) {
+            const long long t = (a.nz + slabs - 1) / slabs;
+            if (t >= 8) tz = (int)t;
+        }
+    }
+    const dim3 g((unsigned)((a.nx + TX - 1) / TX), (unsigned)((a.ny + ty - 1) / ty), (unsigned)((a.nz + tz - 1) / tz)), b(256);
+    hipLaunchKernelGGL((lmom_kernel<M, TX, NC>), g, b, 0, st, a, tz);
+}
+
 hipError_t launch_lmom(const DevArgs& a, hipStream_t st) {
-    const int tx = a.nx <= 48 ? 32 : 64, ty = 256 / tx;
-    const long long patches = (long long)((a.nx + tx - 1) / tx) * ((a.ny + ty - 1) / ty);
-    const int tz = patches * ((a.nz + 15) / 16) >= 2048 ? 16 : 4;
-    const dim3 g((unsigned)((a.nx + tx - 1) / tx), (unsigned)((a.ny + ty - 1) / ty), (unsigned)((a.nz + tz - 1) / tz)), b(256);
+    const bool narrow = a.nx <= 48;
     if (a.precision == CGB_P64) {
-        if (tx == 32) hipLaunchKernelGGL((lmom_kernel<double, 32, 3>), g, b, 0, st, a, tz);
-        else hipLaunchKernelGGL((lmom_kernel<double, 64, 3>), g, b, 0, st, a, tz);
+        if (narrow) lm_launch<double, 32, 3>(a, st);
+        else lm_launch<double, 64, 3>(a, st);
     } else if (a.precision == CGB_PMX16S) {
-        if (tx == 32) hipLaunchKernelGGL((lmom_kernel<float, 32, 4>), g, b, 0, st, a, tz);
-        else hipLaunchKernelGGL((lmom_kernel<float, 64, 4>), g, b, 0, st, a, tz);
+        if (narrow) lm_launch<float, 32, 4>(a, st);
+        else lm_launch<float, 64, 4>(a, st);
     } else {
-        if (tx == 32) hipLaunchKernelGGL((lmom_kernel<float, 32, 3>), g, b, 0, st, a, tz);
-        else hipLaunchKernelGGL((lmom_kernel<float, 64, 3>), g, b, 0, st, a, tz);
+        if (narrow) lm_launch<float, 32, 3>(a, st);
+        else lm_launch<float, 64, 3>(a, st);
     }
     return hipGetLastError();
 }
