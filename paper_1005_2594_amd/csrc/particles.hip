@@ -330,7 +330,10 @@ __device__ inline void wave_sync() {
 
 // Scan chunk t of a cell's box (8 x 8 columns, ZB planes) with the 64 lanes
 // and append the cell's nodes to the list in (z, lane) order; returns the count.
-__device__ inline int scan_chunk(const DevArgs& a, const CellRec& cr, int t, int lane, unsigned* lst_s, uint32_t* lst_f) {
+// Only the owners are read here: a listed node's flags are read with its
+// links, so that the scan issues one load per box node (the momentum
+// exchange is bound by the memory requests it issues).
+__device__ inline int scan_chunk(const DevArgs& a, const CellRec& cr, int t, int lane, unsigned* lst_s) {
     const unsigned nx = (unsigned)a.nx, plane = (unsigned)a.nx * (unsigned)a.ny;
     const int cx = (cr.ext[0] + 7) / 8, cy = (cr.ext[1] + 7) / 8;
     const int bx = 8 * (t % cx), by = 8 * ((t / cx) % cy), z0 = ZB * (t / (cx * cy));
@@ -342,24 +345,20 @@ __device__ inline int scan_chunk(const DevArgs& a, const CellRec& cr, int t, int
     else y = wrap(y, a.ny);
     unsigned sj[ZB];
     int ow[ZB];
-    uint32_t fl[ZB];
 #pragma unroll
     for (int j = 0; j < ZB; j++) {
         const bool ok = col && z0 + j < cr.ext[2];
         sj[j] = (unsigned)x + nx * (unsigned)y + plane * (unsigned)wrap(cr.lo[2] + z0 + j, a.nz);
         ow[j] = ok ? a.owner[sj[j]] : OWN_WALL;
-        fl[j] = ok ? a.flags[sj[j]] : 0u;
     }
     int cnt = 0;
 #pragma unroll
     for (int j = 0; j < ZB; j++) {
-        // a node whose 18 neighbours are all non-fluid carries no link
-        const bool mine = ow[j] == cr.p && (fl[j] & LINKBITS) != LINKBITS;
+        const bool mine = ow[j] == cr.p;
         const unsigned long long m = __ballot(mine);
         if (mine) {
             const int e = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
             lst_s[e] = sj[j];
-            lst_f[e] = fl[j];
         }
         cnt += __popcll(m);
     }
@@ -374,7 +373,8 @@ __device__ inline int cell_chunks(const CellRec& cr) {
 // carried to its cell; X, V, W: the cell's position and rigid-body velocity.
 template <int P>
 __device__ inline void node_links(const DevArgs& a, __amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rRA, unsigned s,
-                                  uint32_t f, const double* X, const double* V, const double* W, double* FT) {
+                                  const double* X, const double* V, const double* W, double* FT) {
+    const uint32_t f = a.flags[s];  // bit r set: s - c_r is non-fluid (a node inside the cell has no links)
     using Cd = Codec<P>;
     using T = typename Cd::T;
     using R = typename Cd::R;
@@ -434,7 +434,6 @@ __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
     using T = typename Cd::T;
     constexpr unsigned ES = sizeof(T);
     __shared__ unsigned lst_sa[CPW][2][MR_CAP];
-    __shared__ uint32_t lst_fa[CPW][2][MR_CAP];
     const unsigned ps = (unsigned)a.pstride;
     const auto rA = make_rsrc(a.A, 19ull * ps * ES);
     const auto rRA = make_rsrc(a.rhoA, (unsigned long long)ps * ES);
@@ -459,14 +458,14 @@ __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
     double FT[6] = {0, 0, 0, 0, 0, 0};
     const int nch = n0 > n1 ? n0 : n1;
     for (int t = 0; t < nch; t++) {
-        const int cnt0 = t < n0 ? scan_chunk(a, c0, t, lane, lst_sa[wv][0], lst_fa[wv][0]) : 0;
-        const int cnt1 = t < n1 ? scan_chunk(a, c1, t, lane, lst_sa[wv][1], lst_fa[wv][1]) : 0;
+        const int cnt0 = t < n0 ? scan_chunk(a, c0, t, lane, lst_sa[wv][0]) : 0;
+        const int cnt1 = t < n1 ? scan_chunk(a, c1, t, lane, lst_sa[wv][1]) : 0;
         wave_sync();
         const int mycnt = half ? cnt1 : cnt0;
         const int rounds = ((cnt0 > cnt1 ? cnt0 : cnt1) + 31) / 32;
         for (int rd = 0; rd < rounds; rd++) {
             const int e = 32 * rd + hl;
-            if (e < mycnt) node_links<P>(a, rA, rRA, lst_sa[wv][half][e], lst_fa[wv][half][e], X, V, W, FT);
+            if (e < mycnt) node_links<P>(a, rA, rRA, lst_sa[wv][half][e], X, V, W, FT);
         }
         wave_sync();
     }
