@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import oracle as O
 from parity_util import compare_state, make_pair, rel_inf, say
 
 pytestmark = pytest.mark.gpu
@@ -36,13 +37,16 @@ def _rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def test_fullsize_p64_matches_oracle():
-    g, o = _start("p64")
+# FP64 to the rounding of a different summation order; FP32 storage and
+# collision to the velocity bound stated for FP32 (1e-5 relative)
+@pytest.mark.parametrize("precision,tol_pop,tol_part", [("p64", 1e-10, 1e-9), ("p32", 1e-5, 1e-5)])
+def test_fullsize_matches_oracle(precision, tol_pop, tol_part):
+    g, o = _start(precision)
     for t in range(2):
         g.step(1)
         o.step(1)
-        rep = compare_state(g, o, tol_pop=1e-10, tol_part=1e-9)
-        say("  p64 step", t + 1, {k: float(f"{v:.3g}") for k, v in rep.items()})
+        rep = compare_state(g, o, tol_pop=tol_pop, tol_part=tol_part)
+        say(" ", precision, "step", t + 1, {k: float(f"{v:.3g}") for k, v in rep.items()})
     g.close()
 
 
@@ -93,3 +97,52 @@ def test_fullsize_pmx16s_matches_oracle():
     assert e3 <= 1e-3
     assert pos <= 1e-6
     g.close()
+
+
+def test_fullsize_batch_channels_match_oracle():
+    """The 64-channel ensemble at its full size (FP16 deviations per
+    direction, autotuned tiles, one replayed graph of two steps); the
+    smallest, the largest and the densest channel against the oracle."""
+    from paper_1005_2594_amd import Batch
+    chans = synth.config4()
+    sites = [c["params"]["nx"] * c["params"]["ny"] * c["params"]["nz"] for c in chans]
+    pick = sorted({int(np.argmin(sites)), int(np.argmax(sites)), int(np.argmax([c["hematocrit"] for c in chans]))})
+    say("batch 64 channels,", sum(sites), "sites; compared:", [(c, chans[c]["width"], chans[c]["length"]) for c in pick])
+    b = Batch([c["params"] for c in chans], precision="pmx16")
+    rng = np.random.default_rng(13)
+    start = {}
+    try:
+        for c, (s, ch) in enumerate(zip(b.channels, chans)):
+            n = len(ch["X"])
+            V = 1e-3 * rng.standard_normal((n, 3))
+            L = 1e-2 * rng.standard_normal((n, 3))
+            s.set_particles(ch["X"], ch["q"], V, L)
+            s.init_fluid(None, 2e-3 * rng.standard_normal((sites[c], 3)))
+            if c in pick:
+                start[c] = (V, L, s.populations())
+        b.autotune(reps=2)
+        b.capture(2)
+        b.run(2)
+        b.sync()
+        for c in pick:
+            ch, (V, L, d0) = chans[c], start[c]
+            o = O.Oracle(ch["params"])
+            o.set_particles(ch["X"], ch["q"], V, L)
+            o.init_fluid()
+            o.set_deviations(d0)
+            o.step(2)
+            g = b.channels[c]
+            np.testing.assert_array_equal(g.owner(), o.owner())
+            fl = o.owner() == -1
+            # two steps of per-direction FP16 storage (each stored value
+            # rounded to 2^-11 of itself, the first step's rounding carried
+            # through the second): the mixed-precision bar of 1e-3 relative
+            ep = _rel_l2(g.populations()[:, fl], o.deviations()[:, fl])
+            eu = _rel_l2(g.fields()[1][fl], o.fields()[1][fl])
+            ex = float(np.max(np.abs(g.particles()[0] - o.particles()[0])))
+            say("  channel", c, "population rel L2", ep, "velocity rel L2", eu, "max position error", ex)
+            assert ep <= 1e-3
+            assert eu <= 1e-3
+            assert ex <= 1e-8
+    finally:
+        b.close()
