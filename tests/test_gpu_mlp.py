@@ -39,6 +39,43 @@ def test_forward_matches_oracle():
     net.close()
 
 
+def test_forward_full_batch_matches_oracle_on_samples():
+    # the inference workload: 2^20 query points through all five members in
+    # one call; 4096 sampled outputs per member against the reference
+    from paper_1005_2594_amd import Mlp
+    rng = np.random.default_rng(12)
+    p = _params(rng, 5)
+    n = 1 << 20
+    x = rng.standard_normal((n, 3)).astype(np.float32)
+    net = Mlp(5)
+    net.set_params(p)
+    y = net.forward(x)
+    assert y.shape == (5, n) and np.all(np.isfinite(y))
+    idx = np.sort(rng.choice(n, 4096, replace=False))
+    idx[0], idx[-1] = 0, n - 1  # first and last rows included
+    for m in range(5):
+        xs = x[idx].astype(np.float64)
+        yo, it = M.forward(p[m], xs, bf16_ops=True, keep=True)
+        scale = np.max(np.abs(yo))
+        err = np.abs(y[m, idx] - yo)
+        # the device sums in FP32 in another order, so where a first-layer
+        # activation lies at a BF16 rounding boundary the two sides may round
+        # it to neighbouring BF16 values, one unit in the last place apart;
+        # to first order that moves the output by dy/dh1_k times that unit.
+        # Bound: every activation of the point flipped, plus FP32 rounding
+        dydh = (it["W3"] * M.dsilu(it["z2"])) @ it["W2"]
+        ulp = np.ldexp(1.0, np.frexp(it["h1"])[1] - 8)
+        bound = np.sum(np.abs(dydh) * ulp, axis=1) + 2e-5 * scale
+        ex = np.max(np.abs(y[m, idx] - M.forward(p[m], xs))) / scale
+        ok = float(np.mean(err < 2e-5 * scale))
+        say(f"member {m}, 2^20 points, 4096 sampled: vs bf16 reference max {err.max() / scale:.2e} "
+            f"(of the flip bound {np.max(err / bound):.2f}), share within 2e-5 {ok:.4f}; vs exact FP64 {ex:.2e}")
+        assert np.all(err <= bound)
+        assert ok >= 0.99  # flips are rare: all other outputs agree to FP32 rounding
+        assert ex < 3e-2
+    net.close()
+
+
 def test_gradient_matches_oracle():
     from paper_1005_2594_amd import Mlp
     rng = np.random.default_rng(11)
