@@ -1,14 +1,14 @@
 // particles.hip -- cell-side kernels of the time step.
 //
 //  prep         axis o = R(q) e_z and space-frame angular velocity of each cell
-//  raster       two passes over each cell's bounding box: (1) every node inside
+//  raster       (1) claims, over each cell's bounding box: every node inside
 //               the discretised ellipsoid (Sec. II: half axes R_par along o,
-//               R_perp across) records the lowest covering index; (2) each
-//               node is resolved once, by its current owner or by the lowest
-//               coverer of a fluid node: the owner keeps a node while it is
-//               still inside it (single occupancy, first arrival keeps the
-//               node), otherwise the lowest coverer takes it, otherwise it
-//               becomes fluid.  Changes go to a transition list.
+//               R_perp across) that the cell does not own records the lowest
+//               covering index; (2) resolve, one thread per node: the owner
+//               keeps a node while it is still inside it (single occupancy,
+//               first arrival keeps the node), otherwise the lowest claimer
+//               takes it, otherwise it becomes fluid; a claimed fluid node
+//               goes to the lowest claimer.  Changes go to a transition list.
 //  transitions  apply owner changes, update node flags, and balance the deleted
 //               (covered) or created (freed, Eq. 5 at rho0 and the rigid-body
 //               velocity) fluid momentum with a force and torque on the cell.
@@ -149,13 +149,11 @@ __device__ inline PrevBox prev_box(const DevArgs& a, int p) {
 }
 
 // union of the boxes at the previous rasterisation (pb) and now (k: the
-// cell's kinematics).  Returns false (and flags instability) for a box that
-// is not finite or wider than a cell moving less than half a node per step
-// can span, so that no state of the cells can send the walk outside the
-// lattice.
-__device__ inline bool union_box(const DevArgs& a, const double* k, const PrevBox& pb, int* lo, int* ext) {
-    double h[3];
-    half_extents(a, k + 9, h);
+// cell's kinematics, h: its half extents).  Returns false (and flags
+// instability) for a box that is not finite or wider than a cell moving less
+// than half a node per step can span, so that no state of the cells can send
+// the walk outside the lattice.
+__device__ inline bool union_box(const DevArgs& a, const double* k, const double* h, const PrevBox& pb, int* lo, int* ext) {
     const int maxext = 2 * (int)ceil(a.Rb) + 6;
     for (int c = 0; c < 3; c++) {
         double x0 = pb.X[c];
@@ -187,13 +185,20 @@ __device__ inline bool covers(const DevArgs& a, const CellRec& c, int x, int y, 
 
 // cell records in cell-list order (the order of the previous cell list; any
 // permutation of the cells is correct): record k describes cell p, whose
-// kinematics are kp
+// kinematics are kp and whose previous box is pb (loaded by the caller
+// before this overwrites it with the box of this rasterisation)
 __device__ void record_one(const DevArgs& a, int k, int p, const double* kp, const PrevBox& pb) {
     CellRec c;
     for (int i = 0; i < 3; i++) { c.X[i] = kp[i]; c.V[i] = kp[3 + i]; c.W[i] = kp[6 + i]; c.o[i] = kp[9 + i]; }
     c.p = p;
-    c.ok = union_box(a, kp, pb, c.lo, c.ext) ? 1 : 0;
-    if (!c.ok) for (int i = 0; i < 3; i++) { c.lo[i] = 0; c.ext[i] = 0; }
+    double h[3];
+    half_extents(a, kp + 9, h);
+    c.ok = union_box(a, kp, h, pb, c.lo, c.ext) ? 1 : 0;
+    if (!c.ok) {
+        for (int i = 0; i < 3; i++) { c.lo[i] = 0; c.ext[i] = 0; }
+    } else {
+        for (int i = 0; i < 3; i++) { a.Xprev[3 * p + i] = kp[i]; a.Hprev[3 * p + i] = h[i]; }
+    }
     ((CellRec*)a.crec)[k] = c;
 }
 
@@ -203,7 +208,8 @@ __global__ void cellrec_kernel(DevArgs a) {
     const int p = a.bin_idx[k];
     double kp[12];
     for (int c = 0; c < 12; c++) kp[c] = a.kin[12 * (long long)p + c];
-    record_one(a, k, p, kp, prev_box(a, p));
+    const PrevBox pb = prev_box(a, p);
+    record_one(a, k, p, kp, pb);
 }
 
 hipError_t launch_cellrec(const DevArgs& a, hipStream_t st) {
@@ -212,14 +218,15 @@ hipError_t launch_cellrec(const DevArgs& a, hipStream_t st) {
     return hipGetLastError();
 }
 
-// one wave per cell, CPW cells (waves) per workgroup: lane (ix, iy) of an
-// 8 x 8 footprint walks z in slabs of ZB nodes whose loads are issued
-// together.  The waves of a workgroup work independently.
+// Claim pass: one wave per cell, CPW cells (waves) per workgroup: lane
+// (ix, iy) of an 8 x 8 footprint walks z in slabs of ZB nodes whose loads are
+// issued together.  Every node inside the cell that it does not own records
+// the lowest covering index (the owner keeps a node it still covers, so it
+// needs no claim).  The waves of a workgroup work independently.
 constexpr int ZB = 8;
 constexpr int CPW = 4;
 
-template <bool RESOLVE>
-__global__ void __launch_bounds__(64 * CPW) raster_kernel(DevArgs a) {
+__global__ void __launch_bounds__(64 * CPW) claim_kernel(DevArgs a) {
     const unsigned nx = (unsigned)a.nx, plane = (unsigned)a.nx * (unsigned)a.ny;
     const int lane = threadIdx.x & 63;
     const int k = __builtin_amdgcn_readfirstlane(xcd_block((int)blockIdx.x, (int)gridDim.x) * CPW + (int)(threadIdx.x >> 6));
@@ -240,64 +247,67 @@ __global__ void __launch_bounds__(64 * CPW) raster_kernel(DevArgs a) {
             else y = wrap(y, a.ny);
             for (int z0 = 0; z0 < ext[2]; z0 += ZB) {
                 unsigned sj[ZB];
-                int ow[ZB], cd[ZB];
+                int ow[ZB];
 #pragma unroll
                 for (int j = 0; j < ZB; j++) {
                     const bool ok = col && z0 + j < ext[2];
                     sj[j] = (unsigned)x + nx * (unsigned)y + plane * (unsigned)wrap(lo[2] + z0 + j, a.nz);
                     ow[j] = ok ? a.owner[sj[j]] : OWN_WALL;
-                    if (RESOLVE) cd[j] = ok ? a.cand[sj[j]] : NO_CAND;
                 }
 #pragma unroll
                 for (int j = 0; j < ZB; j++) {
                     const int o = ow[j];
-                    const unsigned s = sj[j];
                     const int z = wrap(lo[2] + z0 + j, a.nz);
-                    if (!RESOLVE) {
-                        // the owner keeps a node it still covers: no claim needed
-                        if (o != OWN_WALL && o != p && covers(a, cr, x, y, z)) atomicMin(a.cand + s, p);
-                        continue;
-                    }
-                    const int c = cd[j];
-                    const bool mine = o != OWN_WALL && ((o == p) || (o == OWN_FLUID && c == p));
-                    int nw = o;
-                    if (mine) {
-                        const bool keep = (o == p) && covers(a, cr, x, y, z);
-                        nw = keep ? p : (c != NO_CAND ? c : OWN_FLUID);
-                        if (c != NO_CAND) a.cand[s] = NO_CAND;
-                    }
-                    // transitions: one list reservation per wave and slab
-                    const bool tr = nw != o;
-                    const unsigned long long m = __ballot(tr);
-                    if (m) {
-                        const int first = __ffsll((long long)m) - 1;
-                        int base = 0;
-                        const int seg = (int)(blockIdx.x % TSEG);
-                        if (lane == first) base = atomicAdd(a.ntrans + seg, __popcll(m));
-                        base = __shfl(base, first, 64);
-                        if (tr) {
-                            const int t = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                            if (t < a.trans_cap) {
-                                const long long e = (long long)seg * a.trans_cap + t;
-                                a.trans[3 * e] = (int)s;
-                                a.trans[3 * e + 1] = o;
-                                a.trans[3 * e + 2] = nw;
-                            } else {
-                                atomicOr(a.status, ST_TRANS_OVERFLOW);
-                            }
-                        }
-                    }
+                    if (o != OWN_WALL && o != p && covers(a, cr, x, y, z)) atomicMin(a.cand + sj[j], p);
                 }
             }
         }
-    if (RESOLVE) {
-        // the wave read this cell's previous box at its start; record the new one
-        if (lane < 3) {
-            double h[3];
-            half_extents(a, cr.o, h);
-            // lane-indexed values picked by selects (no dynamic indexing of locals)
-            a.Xprev[3 * p + lane] = lane == 0 ? cr.X[0] : (lane == 1 ? cr.X[1] : cr.X[2]);
-            a.Hprev[3 * p + lane] = lane == 0 ? h[0] : (lane == 1 ? h[1] : h[2]);
+}
+
+// Resolve pass, one thread per node, after every cell's claims: a cell node
+// stays with its owner while the owner still covers it (single occupancy,
+// first arrival keeps the node), otherwise goes to the lowest claimer,
+// otherwise becomes fluid; a claimed fluid node goes to the lowest claimer.
+// Changes go to the transition list (one reservation per wave) and the claims
+// are cleared for the next step.  Every node a cell owns or claims is visited
+// once, in lattice order, so the loads are coalesced and no box is walked.
+__global__ void __launch_bounds__(256) resolve_kernel(DevArgs a) {
+    const long long si = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool in = si < a.ns;
+    const unsigned s = in ? (unsigned)si : 0u;
+    const int o = in ? a.owner[s] : OWN_WALL;
+    const int c = in ? a.cand[s] : NO_CAND;
+    int nw = o;
+    if (o >= 0) {
+        const double* k = a.kin + 12 * (long long)o;
+        const double X[3] = {k[0], k[1], k[2]}, ax[3] = {k[9], k[10], k[11]};
+        const unsigned nx = (unsigned)a.nx, ny = (unsigned)a.ny;
+        double d[3];
+        node_disp(a, (int)(s % nx), (int)((s / nx) % ny), (int)(s / (nx * ny)), X, d);
+        nw = inside_test(a, d, ax) ? o : (c != NO_CAND ? c : OWN_FLUID);
+    } else if (o == OWN_FLUID && c != NO_CAND) {
+        nw = c;
+    }
+    if (c != NO_CAND) a.cand[s] = NO_CAND;
+    const bool tr = nw != o;
+    const unsigned long long m = __ballot(tr);
+    if (m) {
+        const int first = __ffsll((long long)m) - 1;
+        int base = 0;
+        const int seg = (int)(blockIdx.x % TSEG);
+        if (lane == first) base = atomicAdd(a.ntrans + seg, __popcll(m));
+        base = __shfl(base, first, 64);
+        if (tr) {
+            const int t = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            if (t < a.trans_cap) {
+                const long long e = (long long)seg * a.trans_cap + t;
+                a.trans[3 * e] = (int)s;
+                a.trans[3 * e + 1] = o;
+                a.trans[3 * e + 2] = nw;
+            } else {
+                atomicOr(a.status, ST_TRANS_OVERFLOW);
+            }
         }
     }
 }
@@ -857,8 +867,8 @@ hipError_t launch_raster(const DevArgs& a, hipStream_t st, bool fresh, bool reco
     if (records) hipLaunchKernelGGL(step_begin_kernel, dim3(1), dim3(TSEG), 0, st, a.ntrans, a.dstep, fresh ? 0 : 1);
     if (a.n == 0) return hipGetLastError();
     if (records) hipLaunchKernelGGL(cellrec_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
-    hipLaunchKernelGGL(raster_kernel<false>, dim3(cell_grid(a.n)), dim3(64 * CPW), 0, st, a);
-    hipLaunchKernelGGL(raster_kernel<true>, dim3(cell_grid(a.n)), dim3(64 * CPW), 0, st, a);
+    hipLaunchKernelGGL(claim_kernel, dim3(cell_grid(a.n)), dim3(64 * CPW), 0, st, a);
+    hipLaunchKernelGGL(resolve_kernel, dim3((unsigned)((a.ns + 255) / 256)), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
