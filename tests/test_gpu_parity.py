@@ -248,3 +248,28 @@ def test_transitions_parity(prec, tol):
         say(f"  step {5 * (t + 1)}: u {err_u:.2e} Fh {err_F:.2e} V {err_V:.2e} transitions so far {moved}")
         assert err_u <= tol and err_V <= tol
     assert moved > 100
+
+
+def test_ragged_box_moving_cells_p64():
+    # a periodic box whose site count (33 x 29 x 27 = 25,839) is not a
+    # multiple of the workgroup size, dense moving and spinning cells: the
+    # node-parallel passes' last, partial workgroup and the occupancy rule
+    # against the oracle step by step
+    p = synth.params(33, 29, 27, force_mode=2, f0=1e-5, rho_p=synth.RHO_P_DENSE, force_on_particles=2)
+    rng = np.random.default_rng(17)
+    n = synth.cell_count(0.35, 33 * 29 * 27, p["R_perp"], p["R_par"])
+    X = synth.uniform_positions(rng, n, (33, 29, 27))
+    q = synth.random_quaternions(rng, n)
+    V = 4e-3 * rng.standard_normal((n, 3))
+    L = 0.3 * rng.standard_normal((n, 3))
+    say(f"case: ragged 33x29x27 periodic, {n} moving cells, p64, 20 steps")
+    g, o = make_pair(p, X, q, V=V, L=L)
+    moved = 0
+    for t in range(4):
+        own0 = o.owner()
+        g.step(5); o.step(5)
+        moved += int((o.owner() != own0).sum())
+        compare_state(g, o, 1e-10, 1e-9)
+    say("  owner changes over 20 steps:", moved)
+    assert moved > 0
+    g.close()
