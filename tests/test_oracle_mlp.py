@@ -68,3 +68,37 @@ def test_fits_a_smooth_function():
         L, g = M.loss_and_grad(opt.p, x, t)
         opt.step(g)
     assert L < 0.02 * L0
+
+
+def test_forward_by_hand():
+    # A network whose output is worked out by hand, using sigma(ln 3) = 3/4:
+    # W1 rows (1, 0, 0) and (0, -1, 0); input (ln 3, ln 3, 5) gives
+    # z1 = (ln 3, -ln 3, 0, ...), h1 = (3/4 ln 3, -1/4 ln 3, 0, ...);
+    # W2[0] = (2, 2, 0, ...) gives z2_0 = ln 3 and h2_0 = 3/4 ln 3;
+    # W2[1] = (-4, 0, ...) gives z2_1 = -3 ln 3 and h2_1 = -3 ln 3 / 28
+    # (sigma(-3 ln 3) = 1/28); W3 = (1, 14, 0, ...), b3 = 1/2:
+    # y = 3/4 ln 3 - 3/2 ln 3 + 1/2 = 1/2 - 3/4 ln 3.  A zero input gives b3
+    # plus the second layer's biases through SiLU: b2 = (0, 0, 2, ...) and
+    # W3[2] = 1 add silu(2) = 2 / (1 + e^-2) to every output.
+    d = {name: np.zeros(shape) for name, shape in M.SIZES}
+    d["W1"][0] = (1, 0, 0)
+    d["W1"][1] = (0, -1, 0)
+    d["W2"][0, :2] = (2, 2)
+    d["W2"][1, 0] = -4
+    d["b2"][2] = 2.0
+    d["W3"][:3] = (1, 14, 1)
+    d["b3"][0] = 0.5
+    p = M.pack(d)
+    l3 = np.log(3.0)
+    x = np.array([[l3, l3, 5.0], [0.0, 0.0, 0.0]])
+    extra = 2.0 / (1.0 + np.exp(-2.0))
+    want = np.array([0.5 - 0.75 * l3 + extra, 0.5 + extra])
+    y = M.forward(p, x)
+    assert np.max(np.abs(y - want)) < 1e-15
+    # the device's operand rounding: W entries here are exact in bfloat16, so
+    # only h1 = (3/4 ln 3, -1/4 ln 3) changes, to its nearest bfloat16 value
+    h0, h1 = M.bf16(0.75 * l3), M.bf16(-0.25 * l3)
+    z2 = 2 * (h0 + h1)
+    z21 = -4 * h0
+    want_bf = 0.5 + z2 / (1 + np.exp(-z2)) + 14 * z21 / (1 + np.exp(-z21)) + extra
+    assert abs(M.forward(p, x, bf16_ops=True)[0] - want_bf) < 1e-15
