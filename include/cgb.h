@@ -17,7 +17,8 @@
  *  - Populations cross the ABI as FP64 deviations d_r = n*_r - w_r*rho0 of the
  *    post-collision populations, whatever the storage precision.
  *  - All pointer arguments of cgb_set_* / cgb_get_* are HOST pointers owned by
- *    the caller, with the sizes stated.  Device memory is owned by the handle.
+ *    the caller, with the sizes stated.  Device memory is owned by the handle
+ *    (cgb_create) or provided by the caller (cgb_query_sizes, cgb_create_in).
  *  - cgb_step is asynchronous on the handle's stream; device-side failures
  *    (instability, overflow of a work list) surface at the next cgb_sync or
  *    cgb_get_* call.
@@ -84,11 +85,36 @@ typedef struct cgb_sim cgb_sim;
  * units (tau = 1, rho0 = 1, eps = eps_w = 0.05, sigma_w = 1/2). */
 int cgb_params_default(cgb_params* p);
 
+/* Device memory a lattice needs when the caller provides it (for instance
+ * PyTorch tensors; the library then allocates no device memory of its own). */
+typedef struct cgb_sizes {
+    int64_t arena_bytes;    /* every state array of the lattice and its cells   */
+    int64_t staging_bytes;  /* FP64 staging of the host transfers (19 nsites x 8) */
+    int32_t cell_cap;       /* cells the arena holds                            */
+    int32_t track_cap;      /* steps cgb_track can record                       */
+} cgb_sizes;
+/* Fills *out for parameters p, walls wall_mask (as cgb_create), room for
+ * cell_cap cells and a track record of track_cap steps.  CGB_EINVAL for
+ * parameters cgb_create refuses. */
+int cgb_query_sizes(const cgb_params* p, const uint8_t* wall_mask, int32_t cell_cap, int32_t track_cap,
+                    cgb_sizes* out);
+
 /* Creates a lattice.  wall_mask: nullable host array of nx*ny*nz bytes,
  * nonzero = wall node (added to the planes selected by wall_y).
  * stream: a hipStream_t to run on, or NULL to create a private stream.
  * All lattice nodes start as fluid at rest with rho0. */
 int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_sim** out);
+/* As cgb_create, on device memory the caller owns: arena (256-byte aligned)
+ * and staging (8-byte aligned) DEVICE pointers of at least the sizes that
+ * cgb_query_sizes gives for the same p, wall_mask, sz->cell_cap and
+ * sz->track_cap (*sz as it filled them).  Every device array of the handle is
+ * a piece of these two buffers: no call on the handle allocates device
+ * memory; cgb_set_particles / cgb_load refuse more than cell_cap cells and
+ * cgb_track more than track_cap steps (CGB_EINVAL).  The buffers must outlive
+ * the handle; their initial contents do not matter.  Results are identical
+ * to a handle made by cgb_create. */
+int cgb_create_in(const cgb_params* p, const uint8_t* wall_mask, void* stream, const cgb_sizes* sz, void* arena,
+                  void* staging, cgb_sim** out);
 void cgb_destroy(cgb_sim* s);
 const char* cgb_last_error(const cgb_sim* s);
 /* device bytes held by the handle */
@@ -186,7 +212,8 @@ int cgb_get_track(cgb_sim* s, double* out, int32_t cap, int32_t* n);
  * mean velocity is g (N_f^2 + 8 (tau - 1/2)^2 - 1)/(12 nu), N_f = ny - 2, nu =
  * (2 tau - 1)/6; mu_rel = that / mean(ubar[first .. n-1]).
  * cgb_mu_rel picks the estimator from the handle's driving (CGB_EINVAL for
- * any other) and applies it to the handle's record. */
+ * any other, and for Kolmogorov driving at tau != 1, where the one-step map
+ * above does not hold) and applies it to the handle's record. */
 int cgb_mu_rel_kolmogorov(const double* A, int32_t n, int32_t first, double f0, double rho0, int32_t ny, double* mu);
 int cgb_mu_rel_slit(const double* ubar, int32_t n, int32_t first, double g, double tau, int32_t ny, double* mu);
 int cgb_mu_rel(cgb_sim* s, int32_t first, double* mu);

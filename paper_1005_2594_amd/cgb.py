@@ -35,6 +35,11 @@ class CgbParams(C.Structure):
     ]
 
 
+class CgbSizes(C.Structure):
+    _fields_ = [("arena_bytes", C.c_int64), ("staging_bytes", C.c_int64),
+                ("cell_cap", C.c_int32), ("track_cap", C.c_int32)]
+
+
 class CgbError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"cgb {ERRORS.get(code, code)}: {msg}")
@@ -62,6 +67,8 @@ def lib():
     L = C.CDLL(LIB_PATH)
     L.cgb_params_default.argtypes = [C.POINTER(CgbParams)]
     L.cgb_create.argtypes = [C.POINTER(CgbParams), VP, VP, C.POINTER(VP)]
+    L.cgb_query_sizes.argtypes = [C.POINTER(CgbParams), VP, C.c_int32, C.c_int32, C.POINTER(CgbSizes)]
+    L.cgb_create_in.argtypes = [C.POINTER(CgbParams), VP, VP, C.POINTER(CgbSizes), VP, VP, C.POINTER(VP)]
     L.cgb_destroy.argtypes = [VP]
     L.cgb_destroy.restype = None
     L.cgb_last_error.argtypes = [VP]
@@ -153,10 +160,26 @@ def make_params(d: dict, precision=None) -> CgbParams:
     return p
 
 
-class Sim:
-    """One lattice with its cells on the GPU (one ``cgb_sim`` handle)."""
+def query_sizes(params: dict, wall_mask=None, cell_cap=0, track_cap=0, precision=None) -> CgbSizes:
+    """Device bytes a lattice needs on caller-provided memory (``cgb_query_sizes``)."""
+    p = make_params(params, precision)
+    wm = None if wall_mask is None else np.ascontiguousarray(wall_mask, dtype=np.uint8).reshape(-1)
+    sz = CgbSizes()
+    rc = lib().cgb_query_sizes(C.byref(p), _ptr(wm), int(cell_cap), int(track_cap), C.byref(sz))
+    if rc != 0:
+        raise CgbError(rc, "cgb_query_sizes failed")
+    return sz
 
-    def __init__(self, params: dict, wall_mask=None, precision=None, stream=None, _handle=None):
+
+class Sim:
+    """One lattice with its cells on the GPU (one ``cgb_sim`` handle).
+
+    With ``cell_cap`` set, the handle's device memory is two PyTorch tensors
+    sized by ``cgb_query_sizes`` (kept alive by this object) and passed to
+    ``cgb_create_in``; otherwise the library allocates it."""
+
+    def __init__(self, params: dict, wall_mask=None, precision=None, stream=None, _handle=None,
+                 cell_cap=None, track_cap=0):
         self._p = make_params(params, precision)
         self.nx, self.ny, self.nz = self._p.nx, self._p.ny, self._p.nz
         self.ns = self.nx * self.ny * self.nz
@@ -168,7 +191,18 @@ class Sim:
         h = VP()
         wm = None if wall_mask is None else np.ascontiguousarray(wall_mask, dtype=np.uint8).reshape(-1)
         st = None if stream is None else VP(int(stream))
-        rc = lib().cgb_create(C.byref(self._p), _ptr(wm), st, C.byref(h))
+        if cell_cap is None:
+            rc = lib().cgb_create(C.byref(self._p), _ptr(wm), st, C.byref(h))
+        else:
+            import torch
+            sz = CgbSizes()
+            rc = lib().cgb_query_sizes(C.byref(self._p), _ptr(wm), int(cell_cap), int(track_cap), C.byref(sz))
+            if rc == 0:
+                self._arena = torch.empty(int(sz.arena_bytes), dtype=torch.uint8, device="cuda")
+                self._staging = torch.empty(int(sz.staging_bytes), dtype=torch.uint8, device="cuda")
+                torch.cuda.synchronize()
+                rc = lib().cgb_create_in(C.byref(self._p), _ptr(wm), st, C.byref(sz), VP(self._arena.data_ptr()),
+                                         VP(self._staging.data_ptr()), C.byref(h))
         if rc != 0:
             raise CgbError(rc, "cgb_create failed")
         self.h = h

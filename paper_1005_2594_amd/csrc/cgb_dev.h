@@ -40,6 +40,7 @@ constexpr int32_t NO_CAND = 0x7fffffff;
 constexpr int ST_UNSTABLE = 1;
 constexpr int ST_TRANS_OVERFLOW = 2;
 constexpr int ST_PAIR_OVERFLOW = 4;
+constexpr int ST_LIST_OVERFLOW = 8;
 
 constexpr int TSEG = 64;  // segments of the transition list
 
@@ -78,8 +79,13 @@ struct DevArgs {
     double* kin;    // n*12: X, V, Omega, axis at the start of the step
     float* kinf;    // n*12: rigid-body velocity about the nearest node b of X, in FP32:
                     // U0 = V + Omega x (b - X) (3), Omega (3), b packed (x | y << 16, z), X - b (3), 0
-    double* FTh;    // n*6 hydrodynamic force, torque (accumulated)
+    double* FTh;    // n*6 hydrodynamic force, torque of the step
     double* FTp;    // n*6 potential force, torque
+    unsigned long long* FTt;  // n*12 cover/uncover force and torque of the step in
+                              // two-word fixed point (fx_add): order-independent sums
+    unsigned* clist;  // [n][lcap] nodes each cell covers at this step's rasterisation
+    int* ccount;      // n: entries of each list
+    int lcap;         // list capacity (bound on the nodes inside one cell)
     double M, Ipar, Iperp;
     double Mdrive;   // mass the body force acts on: M, or rho0 times the cell volume
     double iRpar2, iRperp2, Rb;
@@ -344,6 +350,24 @@ __device__ inline void cross3(const double* a, const double* b, double* c) {
     c[0] = a[1] * b[2] - a[2] * b[1];
     c[1] = a[2] * b[0] - a[0] * b[2];
     c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Order-independent accumulation of doubles: v is split into hi = round(v 2^24)
+// and lo = round((v - hi 2^-24) 2^76) (the remainder is exact, |lo| <= 2^51),
+// and the two integers are added with 64-bit integer atomics, whose sums do
+// not depend on the order of the additions.  fx_value returns
+// sum(hi) 2^-24 + sum(lo) 2^-76: the exact sum of the v rounded to multiples
+// of 2^-76, up to the last rounding of that expression.  Valid for |v| < 2^27
+// and fewer than 2^11 terms per accumulator.
+__device__ inline void fx_add(unsigned long long* acc, double v) {
+    const long long hi = __double2ll_rn(v * 0x1p24);
+    const double r = v - (double)hi * 0x1p-24;
+    const long long lo = __double2ll_rn(r * 0x1p76);
+    atomicAdd(acc, (unsigned long long)hi);
+    atomicAdd(acc + 1, (unsigned long long)lo);
+}
+__device__ inline double fx_value(const unsigned long long* acc) {
+    return (double)(long long)acc[0] * 0x1p-24 + (double)(long long)acc[1] * 0x1p-76;
 }
 
 // 64-lane sum of a double (all lanes receive the total)

@@ -6,11 +6,13 @@
 // b1 [64], W2 [64][64], b2 [64], W3 [64], b3.  The weights enter the
 // arithmetic rounded to bfloat16 (round to nearest even); the 64 x 64 layer
 // and its two backward products run on the matrix cores
-// (v_mfma_f32_16x16x16bf16_1k, FP32 accumulation), the 3-wide and 1-wide
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation), the 3-wide and 1-wide
 // layers on the vector ALUs in FP32.
 //
-// Matrix-core tile (one wave, 16 x 16 x 16): lane l supplies A[l%16][4(l/16)+j]
-// and B[4(l/16)+j][l%16], j = 0..3, and receives D[4(l/16)+r][l%16], r = 0..3.
+// Matrix-core tile (one wave, 16 x 16 x 32): lane l supplies A[l%16][k] and
+// B[k][l%16] for the eight k = 8(l/16) + j, j = 0..7, and receives
+// D[4(l/16)+r][l%16], r = 0..3.  (Which eight k a lane holds only has to be
+// the same for A and B: the product sums over all of them.)
 //
 // Inputs are (hematocrit, log shear rate, width / R_perp); the network maps
 // standardised inputs to the standardised log of the relative apparent
@@ -34,7 +36,8 @@ constexpr int OW1 = 0, OB1 = 192, OW2 = 256, OB2 = 4352, OW3 = 4416, OB3 = 4480,
 constexpr int TB = 128;  // training batch (8 tiles of 16 points)
 constexpr int MAXM = 6;  // members (their staged weights share one workgroup's LDS in inference)
 
-typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 __device__ inline unsigned short to_bf16(float f) {
@@ -48,7 +51,9 @@ __device__ inline float dsilu(float z) {
     const float s = 1.0f / (1.0f + __expf(-z));
     return s * (1.0f + z * (1.0f - s));
 }
-__device__ inline f4 mfma(s4 a, s4 b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0); }
+__device__ inline f4 mfma(s8 a, s8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, a), __builtin_bit_cast(b8, b), c, 0, 0, 0);
+}
 
 struct Norm {
     float in_mean[NIN], in_std[NIN], out_mean, out_std;
@@ -76,17 +81,17 @@ __device__ void stage_member(Stage& S, const float* p, int tid, int nthr) {
 // standardised.  Returns y for points 4(l/16) + r in all lanes of the group;
 // optionally keeps h1 (A-operand layout), z2 (D layout) for the backward pass.
 struct Fwd {
-    s4 a[4];     // h1 as bf16, chunk kc: k = 16 kc + 4 (l/16) + j, point l%16
+    s8 a[2];     // h1 as bf16, chunk kc: k = 32 kc + 8 (l/16) + j, point l%16
     f4 z2[4];    // pre-activation of layer 2, block ob: point 4(l/16)+r, o = 16 ob + l%16
     float y[4];  // outputs of points 4(l/16) + r
 };
 
 __device__ void forward_tile(const Stage& S, const float* x, int l, Fwd& F) {
 #pragma unroll
-    for (int kc = 0; kc < 4; kc++)
+    for (int kc = 0; kc < 2; kc++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int k = 16 * kc + 4 * (l / 16) + j;
+        for (int j = 0; j < 8; j++) {
+            const int k = 32 * kc + 8 * (l / 16) + j;
             const float z = S.w1[3 * k] * x[0] + S.w1[3 * k + 1] * x[1] + S.w1[3 * k + 2] * x[2] + S.b1[k];
             F.a[kc][j] = (short)to_bf16(silu(z));
         }
@@ -94,10 +99,10 @@ __device__ void forward_tile(const Stage& S, const float* x, int l, Fwd& F) {
     for (int ob = 0; ob < 4; ob++) {
         f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kc = 0; kc < 4; kc++) {
-            s4 b;
+        for (int kc = 0; kc < 2; kc++) {
+            s8 b;
 #pragma unroll
-            for (int j = 0; j < 4; j++) b[j] = (short)S.w2[(16 * ob + l % 16) * H + 16 * kc + 4 * (l / 16) + j];
+            for (int j = 0; j < 8; j++) b[j] = (short)S.w2[(16 * ob + l % 16) * H + 32 * kc + 8 * (l / 16) + j];
             acc = mfma(F.a[kc], b, acc);
         }
         const float bb = S.b2[16 * ob + l % 16];
@@ -190,6 +195,18 @@ __global__ void __launch_bounds__(256) forward_kernel(const float* __restrict__ 
 // per wave).  Backward: dy = 2 (y - t) / B; dW3 = dy . h2; dz2 = dy W3 silu'(z2);
 // dW2 = dz2^T h1 and dh1 = dz2 W2 on the matrix cores; dz1 = dh1 silu'(z1);
 // dW1 = dz1^T x.  mode 0: write the gradient and the loss; mode 1: Adam step.
+// Every sum over the batch runs in a fixed order (over the 4 points of a lane,
+// the 4 lane groups of a tile by shuffles, then the 8 tiles from LDS), so a
+// step's result does not depend on scheduling.
+constexpr int NTILE = TB / 16;
+
+// sum over the 4 lane groups of a wave (points 4 g + r of a tile); every
+// lane receives the same value
+__device__ inline float group_sum(float v) {
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
 struct Adam {
     float lr, b1, b2, eps, c1, c2;  // c1 = 1 - b1^t, c2 = 1 - b2^t
 };
@@ -210,7 +227,8 @@ __global__ void __launch_bounds__(256) train_kernel(float* __restrict__ params, 
     __shared__ Stage S;
     __shared__ unsigned short H1[TB * H], DZ2[TB * H];
     __shared__ float xs[TB * NIN], ts[TB];
-    __shared__ float gw1[H * NIN], gb1[H], gb2[H], gw3[H], gb3, lsum;
+    // per-tile partial sums of the gradients of W1, b1, b2, W3, b3 and of the loss
+    __shared__ float pw1[NTILE][H * NIN], pb1[NTILE][H], pb2[NTILE][H], pw3[NTILE][H], pb3[NTILE], ploss[NTILE];
     const int m = blockIdx.x;
     const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
     float* P = params + (size_t)m * NP;
@@ -220,9 +238,6 @@ __global__ void __launch_bounds__(256) train_kernel(float* __restrict__ params, 
         for (int c = 0; c < NIN; c++) xs[NIN * i + c] = xn[NIN * q + c];
         ts[i] = tn[q];
     }
-    for (int i = tid; i < H * NIN; i += blockDim.x) gw1[i] = 0.f;
-    for (int i = tid; i < H; i += blockDim.x) { gb1[i] = 0.f; gb2[i] = 0.f; gw3[i] = 0.f; }
-    if (tid == 0) { gb3 = 0.f; lsum = 0.f; }
     __syncthreads();
 
     // forward and the output-layer part of the backward pass
@@ -232,16 +247,20 @@ __global__ void __launch_bounds__(256) train_kernel(float* __restrict__ params, 
         Fwd F;
         forward_tile(S, xs + NIN * pl, l, F);
 #pragma unroll
-        for (int kc = 0; kc < 4; kc++)
+        for (int kc = 0; kc < 2; kc++)
 #pragma unroll
-            for (int j = 0; j < 4; j++) H1[pl * H + 16 * kc + 4 * (l / 16) + j] = (unsigned short)F.a[kc][j];
-        float dy[4];
+            for (int j = 0; j < 8; j++) H1[pl * H + 32 * kc + 8 * (l / 16) + j] = (unsigned short)F.a[kc][j];
+        float dy[4], ls = 0.f, gd = 0.f;
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             const float res = F.y[r] - ts[16 * tile + 4 * (l / 16) + r];
             dy[r] = 2.f * res / TB;
-            if (l % 16 == 0) { atomicAdd(&lsum, res * res); atomicAdd(&gb3, dy[r]); }
+            ls += res * res;
+            gd += dy[r];
         }
+        ls = group_sum(ls);
+        gd = group_sum(gd);
+        if (l == 0) { ploss[tile] = ls; pb3[tile] = gd; }
 #pragma unroll
         for (int ob = 0; ob < 4; ob++) {
             const int o = 16 * ob + l % 16;
@@ -254,8 +273,9 @@ __global__ void __launch_bounds__(256) train_kernel(float* __restrict__ params, 
                 g2 += dz;
                 DZ2[(16 * tile + 4 * (l / 16) + r) * H + o] = to_bf16(dz);
             }
-            atomicAdd(&gw3[o], g3);
-            atomicAdd(&gb2[o], g2);
+            g3 = group_sum(g3);
+            g2 = group_sum(g2);
+            if (l < 16) { pw3[tile][o] = g3; pb2[tile][o] = g2; }
         }
     }
     __syncthreads();
@@ -266,11 +286,11 @@ __global__ void __launch_bounds__(256) train_kernel(float* __restrict__ params, 
 #pragma unroll
         for (int kb = 0; kb < 4; kb++) {
             f4 acc = {0.f, 0.f, 0.f, 0.f};
-            for (int s = 0; s < TB / 16; s++) {
-                s4 a, b;
+            for (int s = 0; s < TB / 32; s++) {
+                s8 a, b;
 #pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    const int p = 16 * s + 4 * (l / 16) + j;
+                for (int j = 0; j < 8; j++) {
+                    const int p = 32 * s + 8 * (l / 16) + j;
                     a[j] = (short)DZ2[p * H + 16 * ob + l % 16];
                     b[j] = (short)H1[p * H + 16 * kb + l % 16];
                 }
@@ -292,11 +312,11 @@ __global__ void __launch_bounds__(256) train_kernel(float* __restrict__ params, 
         for (int kb = 0; kb < 4; kb++) {
             f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int s = 0; s < 4; s++) {
-                s4 a, b;
+            for (int s = 0; s < 2; s++) {
+                s8 a, b;
 #pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    const int o = 16 * s + 4 * (l / 16) + j;
+                for (int j = 0; j < 8; j++) {
+                    const int o = 32 * s + 8 * (l / 16) + j;
                     a[j] = (short)DZ2[(16 * tile + l % 16) * H + o];
                     b[j] = (short)S.w2[o * H + 16 * kb + l % 16];
                 }
@@ -313,24 +333,32 @@ __global__ void __launch_bounds__(256) train_kernel(float* __restrict__ params, 
                 gb += dz;
                 g1[0] += dz * x[0]; g1[1] += dz * x[1]; g1[2] += dz * x[2];
             }
-            atomicAdd(&gb1[k], gb);
-            for (int c = 0; c < 3; c++) atomicAdd(&gw1[3 * k + c], g1[c]);
+            gb = group_sum(gb);
+            for (int c = 0; c < 3; c++) g1[c] = group_sum(g1[c]);
+            if (l < 16) {
+                pb1[tile][k] = gb;
+                for (int c = 0; c < 3; c++) pw1[tile][3 * k + c] = g1[c];
+            }
         }
     }
     __syncthreads();
     // the remaining parameters
     for (int i = tid; i < NP - H * H; i += blockDim.x) {
         int pi;
-        float g;
-        if (i < H * NIN) { pi = OW1 + i; g = gw1[i]; }
-        else if (i < H * NIN + H) { pi = OB1 + (i - H * NIN); g = gb1[i - H * NIN]; }
-        else if (i < H * NIN + 2 * H) { pi = OB2 + (i - H * NIN - H); g = gb2[i - H * NIN - H]; }
-        else if (i < H * NIN + 3 * H) { pi = OW3 + (i - H * NIN - 2 * H); g = gw3[i - H * NIN - 2 * H]; }
-        else { pi = OB3; g = gb3; }
+        float g = 0.f;
+        if (i < H * NIN) { pi = OW1 + i; for (int t = 0; t < NTILE; t++) g += pw1[t][i]; }
+        else if (i < H * NIN + H) { pi = OB1 + (i - H * NIN); for (int t = 0; t < NTILE; t++) g += pb1[t][i - H * NIN]; }
+        else if (i < H * NIN + 2 * H) { pi = OB2 + (i - H * NIN - H); for (int t = 0; t < NTILE; t++) g += pb2[t][i - H * NIN - H]; }
+        else if (i < H * NIN + 3 * H) { pi = OW3 + (i - H * NIN - 2 * H); for (int t = 0; t < NTILE; t++) g += pw3[t][i - H * NIN - 2 * H]; }
+        else { pi = OB3; for (int t = 0; t < NTILE; t++) g += pb3[t]; }
         if (mode == 0) grad[(size_t)m * NP + pi] = g;
         else adam_one(P, am + (size_t)m * NP, av + (size_t)m * NP, pi, g, A);
     }
-    if (tid == 0 && loss) loss[(size_t)m * loss_stride + loss_col] = lsum / TB;
+    if (tid == 0 && loss) {
+        float ls = 0.f;
+        for (int t = 0; t < NTILE; t++) ls += ploss[t];
+        loss[(size_t)m * loss_stride + loss_col] = ls / TB;
+    }
 }
 
 // standardise inputs and targets on the device: xn = (x - mean)/std,
@@ -341,6 +369,7 @@ __global__ void standardise_kernel(Norm nm, int n, const float* x, const float* 
     for (int c = 0; c < NIN; c++) xn[NIN * i + c] = (x[NIN * i + c] - nm.in_mean[c]) / nm.in_std[c];
     if (mu) tn[i] = (logf(mu[i]) - nm.out_mean) / nm.out_std;
 }
+
 
 }  // namespace
 
@@ -460,6 +489,25 @@ int cgb_mlp_forward(cgb_mlp* h, int64_t n, const float* xn, float* y) {
     return CGB_OK;
 }
 
+// `steps` training launches on device buffers: standardised inputs xn [n][3]
+// and targets tn [n], indices [M][steps][TB], losses [M][steps]
+static int train_steps(cgb_mlp* h, const float* xn, const float* tn, const int* idx, float* loss, int32_t steps,
+                       float lr, int mode) {
+    const int M = h->members;
+    for (int s = 0; s < steps; s++) {
+        Adam A{lr, 0.9f, 0.999f, 1e-8f, 0.f, 0.f};
+        if (mode == 1) {
+            h->adam_t++;
+            A.c1 = (float)(1.0 - pow(0.9, (double)h->adam_t));
+            A.c2 = (float)(1.0 - pow(0.999, (double)h->adam_t));
+        }
+        hipLaunchKernelGGL(train_kernel, dim3(M), dim3(256), 0, h->st, h->params, h->am, h->av, h->grad, loss, steps,
+                           s, xn, tn, idx + (size_t)s * TB, steps * TB, mode, A);
+        MCHK(h, hipGetLastError());
+    }
+    return CGB_OK;
+}
+
 static int run_train(cgb_mlp* h, int32_t n, const float* xn_h, const float* tn_h, int32_t steps, const int32_t* idx_h,
                      float lr, float* loss_h, int mode) {
     const int M = h->members;
@@ -472,18 +520,8 @@ static int run_train(cgb_mlp* h, int32_t n, const float* xn_h, const float* tn_h
     MCHK(h, hipMemcpyAsync(dt.p, tn_h, (size_t)n * 4, hipMemcpyHostToDevice, h->st));
     // idx_h: [M][steps][TB]; the kernel of step s reads member m's row at m * steps * TB + s * TB
     MCHK(h, hipMemcpyAsync(di.p, idx_h, (size_t)M * steps * TB * 4, hipMemcpyHostToDevice, h->st));
-    for (int s = 0; s < steps; s++) {
-        Adam A{lr, 0.9f, 0.999f, 1e-8f, 0.f, 0.f};
-        if (mode == 1) {
-            h->adam_t++;
-            A.c1 = (float)(1.0 - pow(0.9, (double)h->adam_t));
-            A.c2 = (float)(1.0 - pow(0.999, (double)h->adam_t));
-        }
-        hipLaunchKernelGGL(train_kernel, dim3(M), dim3(256), 0, h->st, h->params, h->am, h->av, h->grad,
-                           dl.as<float>(), steps, s, dx.as<float>(), dt.as<float>(), di.as<int>() + (size_t)s * TB,
-                           steps * TB, mode, A);
-        MCHK(h, hipGetLastError());
-    }
+    int rc = train_steps(h, dx.as<float>(), dt.as<float>(), di.as<int>(), dl.as<float>(), steps, lr, mode);
+    if (rc) return rc;
     if (loss_h) MCHK(h, hipMemcpyAsync(loss_h, dl.p, (size_t)M * steps * 4, hipMemcpyDeviceToHost, h->st));
     MCHK(h, hipStreamSynchronize(h->st));
     return CGB_OK;

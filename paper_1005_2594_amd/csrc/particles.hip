@@ -76,8 +76,10 @@ __device__ void prep_one(const DevArgs& a, int p, bool zero_forces, double* k) {
     kf[7] = __int_as_float(b[2]);
     for (int c = 0; c < 3; c++) kf[8 + c] = (float)(-db[c]);  // X - b, in [-1/2, 1/2]
     kf[11] = 0.0f;
-    if (zero_forces)
+    if (zero_forces) {
         for (int c = 0; c < 6; c++) { a.FTh[6 * p + c] = 0.0; a.FTp[6 * p + c] = 0.0; }
+        for (int c = 0; c < 12; c++) a.FTt[12 * (long long)p + c] = 0ull;
+    }
 }
 
 __global__ void prep_kernel(DevArgs a, int zero_forces) {
@@ -148,12 +150,12 @@ __device__ inline PrevBox prev_box(const DevArgs& a, int p) {
     return b;
 }
 
-// union of the boxes at the previous rasterisation (pb) and now (k: the
-// cell's kinematics, h: its half extents).  Returns false (and flags
-// instability) for a box that is not finite or wider than a cell moving less
-// than half a node per step can span, so that no state of the cells can send
-// the walk outside the lattice.
-__device__ inline bool union_box(const DevArgs& a, const double* k, const double* h, const PrevBox& pb, int* lo, int* ext) {
+// Node box of the current rasterisation (k: the cell's kinematics, h: its
+// half extents) in lo, ext.  Returns false (and flags instability) when the
+// union of that box with the box of the previous rasterisation (pb) is not
+// finite or wider than a cell moving less than half a node per step can
+// span, so that no state of the cells can send a walk outside the lattice.
+__device__ inline bool cell_box(const DevArgs& a, const double* k, const double* h, const PrevBox& pb, int* lo, int* ext) {
     const int maxext = 2 * (int)ceil(a.Rb) + 6;
     for (int c = 0; c < 3; c++) {
         double x0 = pb.X[c];
@@ -171,8 +173,8 @@ __device__ inline bool union_box(const DevArgs& a, const double* k, const double
             atomicOr(a.status, ST_UNSTABLE);
             return false;
         }
-        lo[c] = (int)floor(mn);
-        ext[c] = (int)ceil(mx) - lo[c] + 1;
+        lo[c] = (int)floor(x1 - h[c]);
+        ext[c] = (int)ceil(x1 + h[c]) - lo[c] + 1;
     }
     return true;
 }
@@ -184,7 +186,7 @@ __device__ inline bool covers(const DevArgs& a, const CellRec& c, int x, int y, 
 }
 
 // cell records in cell-list order (the order of the previous cell list; any
-// permutation of the cells is correct): record k describes cell p, whose
+// permutation of the cells gives the same results): record k describes cell p, whose
 // kinematics are kp and whose previous box is pb (loaded by the caller
 // before this overwrites it with the box of this rasterisation)
 __device__ void record_one(const DevArgs& a, int k, int p, const double* kp, const PrevBox& pb) {
@@ -193,7 +195,7 @@ __device__ void record_one(const DevArgs& a, int k, int p, const double* kp, con
     c.p = p;
     double h[3];
     half_extents(a, kp + 9, h);
-    c.ok = union_box(a, kp, h, pb, c.lo, c.ext) ? 1 : 0;
+    c.ok = cell_box(a, kp, h, pb, c.lo, c.ext) ? 1 : 0;
     if (!c.ok) {
         for (int i = 0; i < 3; i++) { c.lo[i] = 0; c.ext[i] = 0; }
     } else {
@@ -222,7 +224,11 @@ hipError_t launch_cellrec(const DevArgs& a, hipStream_t st) {
 // (ix, iy) of an 8 x 8 footprint walks z in slabs of ZB nodes whose loads are
 // issued together.  Every node inside the cell that it does not own records
 // the lowest covering index (the owner keeps a node it still covers, so it
-// needs no claim).  The waves of a workgroup work independently.
+// needs no claim), and every node inside the cell is appended to the cell's
+// list, in the fixed order (footprint, slab, plane, lane): after the resolve
+// pass the nodes a cell owns are the listed nodes whose owner it is, which
+// the momentum exchange walks instead of the box.  The waves of a workgroup
+// work independently.
 constexpr int ZB = 8;
 constexpr int CPW = 4;
 
@@ -237,6 +243,8 @@ __global__ void __launch_bounds__(64 * CPW) claim_kernel(DevArgs a) {
     const int p = cr.p;
     const int lo[3] = {cr.lo[0], cr.lo[1], cr.lo[2]};
     const int ext[3] = {cr.ext[0], cr.ext[1], cr.ext[2]};
+    unsigned* lst = a.clist + (size_t)p * (size_t)a.lcap;
+    int cnt = 0;  // the same in every lane
     for (int bx = 0; bx < ext[0]; bx += 8)
         for (int by = 0; by < ext[1]; by += 8) {
             const int ix = bx + (lane & 7), iy = by + (lane >> 3);
@@ -258,10 +266,21 @@ __global__ void __launch_bounds__(64 * CPW) claim_kernel(DevArgs a) {
                 for (int j = 0; j < ZB; j++) {
                     const int o = ow[j];
                     const int z = wrap(lo[2] + z0 + j, a.nz);
-                    if (o != OWN_WALL && o != p && covers(a, cr, x, y, z)) atomicMin(a.cand + sj[j], p);
+                    const bool in = o != OWN_WALL && covers(a, cr, x, y, z);
+                    if (in && o != p) atomicMin(a.cand + sj[j], p);
+                    const unsigned long long m = __ballot(in);
+                    if (in) {
+                        const int e = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                        if (e < a.lcap) lst[e] = sj[j];
+                    }
+                    cnt += __popcll(m);
                 }
             }
         }
+    if (lane == 0) {
+        a.ccount[p] = cnt < a.lcap ? cnt : a.lcap;
+        if (cnt > a.lcap) atomicOr(a.status, ST_LIST_OVERFLOW);
+    }
 }
 
 // Resolve pass, one thread per node, after every cell's claims: a cell node
@@ -326,65 +345,17 @@ static inline unsigned cell_grid(int n) { return (unsigned)((n + CPW - 1) / CPW)
 // set (the sums of w c and (s - X) x w c over the outward links of any node
 // set vanish).  Torque: the transferred momentum is parallel to c_r, so any
 // point of the link line is a lever point; s is used.
-// One wave per cell: lanes cover an 8 x 8 patch of the cell's box and sweep
-// z; the cell's nodes are compacted in lane order (deterministic) and then
-// processed 64 at a time with the loads of a node's 18 links issued together.
-constexpr int MR_CAP = 64 * ZB;
-
-// wave-local ordering of LDS accesses (the waves of a workgroup do not meet)
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Scan chunk t of a cell's box (8 x 8 columns, ZB planes) with the 64 lanes
-// and append the cell's nodes to the list in (z, lane) order; returns the count.
-// Only the owners are read here: a listed node's flags are read with its
-// links, so that the scan issues one load per box node (the momentum
-// exchange is bound by the memory requests it issues).
-__device__ inline int scan_chunk(const DevArgs& a, const CellRec& cr, int t, int lane, unsigned* lst_s) {
-    const unsigned nx = (unsigned)a.nx, plane = (unsigned)a.nx * (unsigned)a.ny;
-    const int cx = (cr.ext[0] + 7) / 8, cy = (cr.ext[1] + 7) / 8;
-    const int bx = 8 * (t % cx), by = 8 * ((t / cx) % cy), z0 = ZB * (t / (cx * cy));
-    const int ix = bx + (lane & 7), iy = by + (lane >> 3);
-    bool col = ix < cr.ext[0] && iy < cr.ext[1];
-    const int x = wrap(cr.lo[0] + ix, a.nx);
-    int y = cr.lo[1] + iy;
-    if (a.wall_y) col = col && y >= 0 && y < a.ny;
-    else y = wrap(y, a.ny);
-    unsigned sj[ZB];
-    int ow[ZB];
-#pragma unroll
-    for (int j = 0; j < ZB; j++) {
-        const bool ok = col && z0 + j < cr.ext[2];
-        sj[j] = (unsigned)x + nx * (unsigned)y + plane * (unsigned)wrap(cr.lo[2] + z0 + j, a.nz);
-        ow[j] = ok ? a.owner[sj[j]] : OWN_WALL;
-    }
-    int cnt = 0;
-#pragma unroll
-    for (int j = 0; j < ZB; j++) {
-        const bool mine = ow[j] == cr.p;
-        const unsigned long long m = __ballot(mine);
-        if (mine) {
-            const int e = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-            lst_s[e] = sj[j];
-        }
-        cnt += __popcll(m);
-    }
-    return cnt;
-}
-
-__device__ inline int cell_chunks(const CellRec& cr) {
-    return ((cr.ext[0] + 7) / 8) * ((cr.ext[1] + 7) / 8) * ((cr.ext[2] + ZB - 1) / ZB);
-}
-
-// Momentum (along x, y, z, in the compute precision) the links of node s
-// carried to its cell; X, V, W: the cell's position and rigid-body velocity.
+// The populations and densities are decoded in the storage codec's
+// precision (the values the LB bounced); C, the link momenta and every sum
+// are formed in FP64.
+// Two cells per wave (lanes 0-31 and 32-63), cells in cell-list order: each
+// half walks its cell's list of covered nodes (written by the claim pass),
+// keeps the nodes the cell owns after the resolve pass and issues the loads
+// of a node's 18 links together; sums in list order, then over the half.
 template <int P>
 __device__ inline void node_links(const DevArgs& a, __amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rRA, unsigned s,
-                                  const double* X, const double* V, const double* W, double* FT) {
-    const uint32_t f = a.flags[s];  // bit r set: s - c_r is non-fluid (a node inside the cell has no links)
+                                  uint32_t f, const double* X, const double* V, const double* W, double* FT) {
+    // f: the node's flags; bit r set: s - c_r is non-fluid
     using Cd = Codec<P>;
     using T = typename Cd::T;
     using R = typename Cd::R;
@@ -409,86 +380,69 @@ __device__ inline void node_links(const DevArgs& a, __amdgpu_buffer_rsrc_t rA, _
     }
     double d[3];
     node_disp(a, sx, sy, sz, X, d);
-    double ud[3];
-    cross3(W, d, ud);
-    const R u0 = (R)(ud[0] + V[0]), u1 = (R)(ud[1] + V[1]), u2 = (R)(ud[2] + V[2]);
-    R m0 = 0, m1 = 0, m2 = 0;
+    double u[3];
+    cross3(W, d, u);
+    for (int c = 0; c < 3; c++) u[c] += V[c];
+    double m0 = 0, m1 = 0, m2 = 0;
 #pragma unroll
     for (int r = 1; r < 19; r++) {
         const bool lk = !((f >> OPP(r)) & 1u);
         const R Dx = rho_dec<P>(a, rv[r]);
-        const R rho_x = (R)a.rho0 + Dx;
-        R cu = 0;
-        if (CX(r)) cu += (R)CX(r) * u0;
-        if (CY(r)) cu += (R)CY(r) * u1;
-        if (CZ(r)) cu += (R)CZ(r) * u2;
-        const R C = (R)(6.0 * WD(r)) * rho_x * cu;
-        const R m = lk ? -((R)2 * pop_dec<P>(a, dv[r], OPP(r), Dx) + C) : (R)0;
+        const double rho_x = a.rho0 + (double)Dx;
+        double cu = 0;
+        if (CX(r)) cu += CX(r) * u[0];
+        if (CY(r)) cu += CY(r) * u[1];
+        if (CZ(r)) cu += CZ(r) * u[2];
+        const double C = 6.0 * WD(r) * rho_x * cu;
+        const double m = lk ? -(2.0 * (double)pop_dec<P>(a, dv[r], OPP(r), Dx) + C) : 0.0;
         if (CX(r)) m0 += CX(r) * m;
         if (CY(r)) m1 += CY(r) * m;
         if (CZ(r)) m2 += CZ(r) * m;
     }
-    const double g0 = (double)m0, g1 = (double)m1, g2 = (double)m2;
-    FT[0] += g0; FT[1] += g1; FT[2] += g2;
-    FT[3] += d[1] * g2 - d[2] * g1;
-    FT[4] += d[2] * g0 - d[0] * g2;
-    FT[5] += d[0] * g1 - d[1] * g0;
+    FT[0] += m0; FT[1] += m1; FT[2] += m2;
+    FT[3] += d[1] * m2 - d[2] * m1;
+    FT[4] += d[2] * m0 - d[0] * m2;
+    FT[5] += d[0] * m1 - d[1] * m0;
 }
 
-// Two cells per wave: both boxes are scanned by all 64 lanes, then lanes
-// 0-31 take the first cell's nodes and lanes 32-63 the second's (a cell has
-// ~26 nodes), and each half reduces its sums.
+// Writes each cell's hydrodynamic force and torque of the step: its link
+// sums plus the cover/uncover sums of the transitions kernel.
 template <int P>
 __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
     using Cd = Codec<P>;
     using T = typename Cd::T;
     constexpr unsigned ES = sizeof(T);
-    __shared__ unsigned lst_sa[CPW][2][MR_CAP];
     const unsigned ps = (unsigned)a.pstride;
     const auto rA = make_rsrc(a.A, 19ull * ps * ES);
     const auto rRA = make_rsrc(a.rhoA, (unsigned long long)ps * ES);
     const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
     const int wv = threadIdx.x >> 6;
-    const int k0 = 2 * __builtin_amdgcn_readfirstlane(xcd_block((int)blockIdx.x, (int)gridDim.x) * CPW + wv);
-    if (k0 >= a.n) return;
-    // the records' boxes (previous and current rasterisation) hold every node of the cells
-    const CellRec c0 = ((const CellRec*)a.crec)[k0];
-    CellRec c1 = c0;
-    const bool has1 = k0 + 1 < a.n;
-    if (has1) c1 = ((const CellRec*)a.crec)[k0 + 1];
-    const int n0 = c0.ok ? cell_chunks(c0) : 0, n1 = (has1 && c1.ok) ? cell_chunks(c1) : 0;
-    // this lane's cell (for processing)
-    double X[3], V[3], W[3];
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-        X[c] = half ? c1.X[c] : c0.X[c];
-        V[c] = half ? c1.V[c] : c0.V[c];
-        W[c] = half ? c1.W[c] : c0.W[c];
-    }
+    const int k = 2 * __builtin_amdgcn_readfirstlane(xcd_block((int)blockIdx.x, (int)gridDim.x) * CPW + wv) + half;
+    if (2 * (k >> 1) >= a.n) return;  // whole wave: no cell
+    const bool live = k < a.n;        // the second half of the last wave may have none
+    const CellRec cr = ((const CellRec*)a.crec)[live ? k : k - 1];
+    const int p = cr.p;
+    // the record kernel flags a cell whose box is not valid; its list was not written
+    int cnt = (live && cr.ok) ? a.ccount[p] : 0;
+    if (cnt > a.lcap) cnt = a.lcap;
+    const unsigned* lst = a.clist + (size_t)p * (size_t)a.lcap;
     double FT[6] = {0, 0, 0, 0, 0, 0};
-    const int nch = n0 > n1 ? n0 : n1;
-    for (int t = 0; t < nch; t++) {
-        const int cnt0 = t < n0 ? scan_chunk(a, c0, t, lane, lst_sa[wv][0]) : 0;
-        const int cnt1 = t < n1 ? scan_chunk(a, c1, t, lane, lst_sa[wv][1]) : 0;
-        wave_sync();
-        const int mycnt = half ? cnt1 : cnt0;
-        const int rounds = ((cnt0 > cnt1 ? cnt0 : cnt1) + 31) / 32;
-        for (int rd = 0; rd < rounds; rd++) {
-            const int e = 32 * rd + hl;
-            if (e < mycnt) node_links<P>(a, rA, rRA, lst_sa[wv][half][e], X, V, W, FT);
-        }
-        wave_sync();
+    for (int e = hl; e < cnt; e += 32) {
+        const unsigned s = lst[e];
+        const int o = a.owner[s];
+        const uint32_t f = a.flags[s];
+        if (o == p) node_links<P>(a, rA, rRA, s, f, cr.X, cr.V, cr.W, FT);
     }
     // sums over each half of the wave
 #pragma unroll
     for (int c = 0; c < 6; c++)
 #pragma unroll
         for (int off = 16; off >= 1; off >>= 1) FT[c] += __shfl_xor(FT[c], off, 64);
-    if (hl == 0 && (half == 0 ? n0 > 0 : n1 > 0)) {
-        const int p = half ? c1.p : c0.p;
+    if (hl == 0 && live) {
         double* F = a.FTh + 6 * (long long)p;
+        const unsigned long long* Ft = a.FTt + 12 * (long long)p;
 #pragma unroll
-        for (int c = 0; c < 6; c++) F[c] += FT[c];
+        for (int c = 0; c < 6; c++) F[c] = FT[c] + fx_value(Ft + 2 * c);
     }
 }
 
@@ -904,8 +858,8 @@ __device__ void transition_one(const DevArgs& a, int t, bool book) {
         double d[3], tq[3];
         node_disp(a, x, y, z, a.kin + 12 * (long long)nw, d);
         cross3(d, m, tq);
-        double* F = a.FTh + 6 * (long long)nw;
-        for (int c = 0; c < 3; c++) { unsafeAtomicAdd(F + c, m[c]); unsafeAtomicAdd(F + 3 + c, tq[c]); }
+        unsigned long long* F = a.FTt + 12 * (long long)nw;
+        for (int c = 0; c < 3; c++) { fx_add(F + 2 * c, m[c]); fx_add(F + 6 + 2 * c, tq[c]); }
     } else if (!was_fluid && is_fluid) {
         if (!book) {
             for (int r = 0; r < 19; r++) A[r * a.pstride + s] = Cd::enc((R)0, enc_scale<P>(a, r));
@@ -935,8 +889,8 @@ __device__ void transition_one(const DevArgs& a, int t, bool book) {
         ((T*)a.rhoA)[s] = Cd::enc(Cd::SPLIT ? (R)0 : rs, rho_enc_scale<P>(a));
         double tq[3];
         cross3(d, m, tq);
-        double* F = a.FTh + 6 * (long long)o;
-        for (int c = 0; c < 3; c++) { unsafeAtomicAdd(F + c, -m[c]); unsafeAtomicAdd(F + 3 + c, -tq[c]); }
+        unsigned long long* F = a.FTt + 12 * (long long)o;
+        for (int c = 0; c < 3; c++) { fx_add(F + 2 * c, -m[c]); fx_add(F + 6 + 2 * c, -tq[c]); }
     }
 }
 

@@ -35,8 +35,19 @@ static const char* kKindNames[] = {"prep", "raster", "transitions", "lb", "mem_r
         if (_e != hipSuccess) FAIL(s, CGB_EDEVICE, "%s: %s", #call, hipGetErrorString(_e)); \
     } while (0)
 
+// Device memory of a handle: its own allocations (MEM_OWN), 256-byte aligned
+// pieces of a caller's arena (MEM_ARENA), or only counted (MEM_COUNT, the size
+// query: the pointers are placeholders that nothing dereferences).
 template <class T>
 static hipError_t dalloc(cgb_sim* s, T** p, size_t bytes) {
+    if (s->mem_mode != MEM_OWN) {
+        const size_t b = bytes ? (bytes + 255) & ~(size_t)255 : 256;
+        if (s->mem_mode == MEM_ARENA && s->arena_used + b > s->arena_bytes) return hipErrorOutOfMemory;
+        *p = (T*)(s->mem_mode == MEM_ARENA ? s->arena + s->arena_used : (char*)nullptr + 4096 + s->arena_used);
+        s->arena_used += b;
+        s->dev_bytes += (int64_t)bytes;
+        return hipSuccess;
+    }
     void* v = nullptr;
     hipError_t e = hipMalloc(&v, bytes ? bytes : 8);
     if (e != hipSuccess) return e;
@@ -46,11 +57,26 @@ static hipError_t dalloc(cgb_sim* s, T** p, size_t bytes) {
     return hipSuccess;
 }
 
+// frees an own allocation; pieces of an arena stay where they are
 static void dfree(cgb_sim* s, void* p) {
-    if (!p) return;
+    if (!p || s->mem_mode != MEM_OWN) return;
     auto it = std::find(s->allocs.begin(), s->allocs.end(), p);
     if (it != s->allocs.end()) s->allocs.erase(it);
     (void)hipFree(p);
+}
+
+// Bound on the lattice nodes strictly inside one ellipsoid with half axes
+// (R_perp, R_perp, R_par): the unit cubes centred on those nodes are disjoint
+// and lie within distance rho = sqrt(3)/2 of the ellipsoid, and that
+// neighbourhood lies inside the ellipsoid with every half axis grown by t,
+// t^2 + (a_min - rho) t - rho a_max = 0 (from |e + v|_A' <= |e|_A' + |v|_A'
+// in the norm of the grown ellipsoid), so the count is below its volume.
+static int inside_bound(double Rp, double Rl) {
+    const double rho = 0.8660254037844386 + 1e-3;
+    const double amin = std::min(Rp, Rl), amax = std::max(Rp, Rl);
+    const double t = 0.5 * (-(amin - rho) + sqrt((amin - rho) * (amin - rho) + 4.0 * rho * amax));
+    const double v = (4.0 / 3.0) * M_PI * (Rp + t) * (Rp + t) * (Rl + t);
+    return (int)std::min(v + 1.0, 1e8);
 }
 
 static double wall_range(const cgb_params& P) {
@@ -120,6 +146,7 @@ static void bind_buffers(cgb_sim* s) {
 
 static int ensure_tmp(cgb_sim* s, size_t bytes) {
     if (bytes <= s->tmp_bytes) return CGB_OK;
+    if (s->mem_mode != MEM_OWN) FAIL(s, CGB_ENOMEM, "staging buffer of %zu bytes is smaller than %zu", s->tmp_bytes, bytes);
     dfree(s, s->tmp);
     s->tmp = nullptr;
     s->tmp_bytes = 0;
@@ -134,6 +161,7 @@ static int check_status(cgb_sim* s) {
     HIPCHK(s, hipMemcpyAsync(&bad, s->a.bad_step, sizeof(int), hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     if (st & ST_TRANS_OVERFLOW) FAIL(s, CGB_ENOMEM, "transition list overflow (capacity %d per segment)", s->a.trans_cap);
+    if (st & ST_LIST_OVERFLOW) FAIL(s, CGB_ENOMEM, "covered-node list overflow (capacity %d per cell)", s->a.lcap);
     if (st & ST_UNSTABLE) FAIL(s, CGB_EUNSTABLE, "unstable at step %d: non-finite state, |u| > 0.4 or |V| >= 0.5", bad);
     return CGB_OK;
 }
@@ -194,9 +222,11 @@ static LaunchCfg default_tiles(const DevArgs& a) {
     return c;
 }
 
+// allocation only (the size query runs it too); init_particle_buffers clears
 static int alloc_particles(cgb_sim* s, int ncap) {
     DevArgs& a = s->a;
-    void* olds[] = {a.X, a.q, a.V, a.L, a.fixed, a.Xprev, a.Hprev, a.kin, a.kinf, a.crec, a.FTh, a.FTp, a.trans, a.pbin, a.bin_idx, a.rank, a.Xs, a.body_part};
+    void* olds[] = {a.X, a.q, a.V, a.L, a.fixed, a.Xprev, a.Hprev, a.kin, a.kinf, a.crec, a.FTh, a.FTp, a.FTt,
+                    a.clist, a.ccount, a.trans, a.pbin, a.bin_idx, a.rank, a.Xs, a.body_part};
     for (void* p : olds) dfree(s, p);
     const size_t n = (size_t)std::max(ncap, 1);
     HIPCHK(s, dalloc(s, &a.X, 3 * n * 8));
@@ -211,12 +241,14 @@ static int alloc_particles(cgb_sim* s, int ncap) {
     HIPCHK(s, dalloc(s, &a.crec, n * sizeof(CellRec)));
     HIPCHK(s, dalloc(s, &a.FTh, 6 * n * 8));
     HIPCHK(s, dalloc(s, &a.FTp, 6 * n * 8));
+    HIPCHK(s, dalloc(s, &a.FTt, 12 * n * 8));
+    HIPCHK(s, dalloc(s, &a.clist, n * (size_t)a.lcap * 4));
+    HIPCHK(s, dalloc(s, &a.ccount, n * 4));
     HIPCHK(s, dalloc(s, &a.pbin, n * 4));
     HIPCHK(s, dalloc(s, &a.bin_idx, n * 4));
     HIPCHK(s, dalloc(s, &a.rank, n * 4));
     HIPCHK(s, dalloc(s, &a.Xs, n * 4 * 8));
     HIPCHK(s, dalloc(s, &a.body_part, ((n + 255) / 256) * 3 * 8));
-    HIPCHK(s, launch_fill_f64(a.body_part, (long long)((n + 255) / 256) * 3, 0.0, s->st));
     long long cap = 96LL * (long long)n + 65536;
     if (cap > s->a.ns + 65536) cap = s->a.ns + 65536;
     a.trans_cap = (int)(cap / TSEG + 4096);  // per segment
@@ -225,21 +257,35 @@ static int alloc_particles(cgb_sim* s, int ncap) {
     return CGB_OK;
 }
 
-int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_sim** out) {
-    if (!p || !out) return CGB_EINVAL;
-    *out = nullptr;
+static int init_particle_buffers(cgb_sim* s) {
+    DevArgs& a = s->a;
+    const long long n = std::max(s->ncap, 1);
+    HIPCHK(s, launch_fill_i32(a.ccount, n, 0, s->st));
+    HIPCHK(s, launch_fill_f64(a.body_part, ((n + 255) / 256) * 3, 0.0, s->st));
+    return CGB_OK;
+}
+
+// host-side state of a new handle that the device set-up uploads
+struct HostInit {
+    std::vector<int32_t> own;   // owner map: walls and fluid
+    std::vector<double> ysin;   // sin(2 pi y / ny)
+    std::vector<int> wstart, widx;  // surface wall nodes per cell-list bin
+};
+
+static bool params_ok(const cgb_params* p) {
     if (p->nx < 3 || p->ny < 3 || p->nz < 3 || !(p->tau > 0.5) || !(p->rho0 > 0) || p->precision < 0 ||
         p->force_on_particles < 0 || p->force_on_particles > 2 ||
         p->precision > CGB_PMX16S || !(p->R_perp > 0) || !(p->R_par > 0) || !(p->rho_p > 0) || !(p->r_cut > 0))
-        return CGB_EINVAL;
-    {
-        // populations and boundary velocities are addressed with 32-bit byte offsets
-        const double esz = p->precision == CGB_P64 ? 8.0 : (p->precision == CGB_P32 ? 4.0 : 2.0);
-        const double msz = p->precision == CGB_P64 ? 8.0 : 4.0;
-        const double pst = (double)(((long long)p->nx * p->ny * p->nz + 255) / 256 * 256);
-        if (19.0 * esz * pst >= 4294901760.0 || 4.0 * msz * pst >= 4294901760.0) return CGB_EINVAL;
-    }
-    cgb_sim* s = new cgb_sim();
+        return false;
+    // populations and boundary velocities are addressed with 32-bit byte offsets
+    const double esz = p->precision == CGB_P64 ? 8.0 : (p->precision == CGB_P32 ? 4.0 : 2.0);
+    const double msz = p->precision == CGB_P64 ? 8.0 : 4.0;
+    const double pst = (double)(((long long)p->nx * p->ny * p->nz + 255) / 256 * 256);
+    return !(19.0 * esz * pst >= 4294901760.0 || 4.0 * msz * pst >= 4294901760.0);
+}
+
+// parameters, constants and the host-side geometry (no device work)
+static int setup_host(cgb_sim* s, const cgb_params* p, const uint8_t* wall_mask, HostInit& hi) {
     s->P = *p;
     if (s->P.pmx_scale == 0.0) s->P.pmx_scale = 32768.0;
     DevArgs& a = s->a;
@@ -263,136 +309,216 @@ int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_
     a.iRpar2 = 1.0 / (p->R_par * p->R_par);
     a.iRperp2 = 1.0 / (p->R_perp * p->R_perp);
     a.Rb = std::max(p->R_perp, p->R_par);
+    a.lcap = inside_bound(p->R_perp, p->R_par);
     a.r_cut2 = p->r_cut * p->r_cut;
     const double wr = wall_range(*p);
     a.wall_range2 = wr * wr;
     a.sig_perp = p->sig_perp; a.sig_par = p->sig_par; a.sig_w = p->sig_w; a.eps = p->eps; a.eps_w = p->eps_w;
     s->esize = p->precision == CGB_P64 ? 8 : (p->precision == CGB_P32 ? 4 : 2);
+    // owner map: walls from the mask and the wall planes
+    hi.own.assign((size_t)a.ns, OWN_FLUID);
+    for (long long i = 0; i < a.ns; i++) {
+        const int y = (int)((i / a.nx) % a.ny);
+        bool w = wall_mask ? wall_mask[i] != 0 : false;
+        if (p->wall_y && (y == 0 || y == a.ny - 1)) w = true;
+        if (w) hi.own[(size_t)i] = OWN_WALL;
+    }
+    s->n_nonwall = 0;
+    for (long long i = 0; i < a.ns; i++) s->n_nonwall += hi.own[(size_t)i] != OWN_WALL ? 1.0 : 0.0;
+    hi.ysin.resize((size_t)a.ny);
+    for (int y = 0; y < a.ny; y++) hi.ysin[(size_t)y] = sin(2.0 * M_PI * y / (double)a.ny);
+    // cell-list geometry: bin edge >= max(cut-off, wall potential range)
+    const double Lb[3] = {(double)a.nx, (double)a.ny, (double)a.nz};
+    const double emin = std::max(p->r_cut, wr);
+    long long nbins = 1;
+    for (int c = 0; c < 3; c++) {
+        a.nb[c] = std::max(1, (int)floor(Lb[c] / emin));
+        a.bedge[c] = Lb[c] / a.nb[c];
+        nbins *= a.nb[c];
+    }
+    if (nbins > (1LL << 30)) FAIL(s, CGB_EINVAL, "too many cell-list bins");
+    a.nbins = (int)nbins;
+    // surface wall nodes (wall nodes with a non-wall neighbour), binned
+    std::vector<std::vector<int>> per((size_t)nbins);
+    long long nsw = 0;
+    for (long long i = 0; i < a.ns; i++) {
+        if (hi.own[(size_t)i] != OWN_WALL) continue;
+        const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / ((long long)a.nx * a.ny));
+        bool surf = false;
+        for (int r = 1; r < 19 && !surf; r++) {
+            int yn = y + CY(r);
+            if (p->wall_y) { if (yn < 0 || yn >= a.ny) continue; }
+            else yn = wrap(yn, a.ny);
+            const long long j = wrap(x + CX(r), a.nx) + (long long)a.nx * (yn + (long long)a.ny * wrap(z + CZ(r), a.nz));
+            if (hi.own[(size_t)j] != OWN_WALL) surf = true;
+        }
+        if (!surf) continue;
+        int bc[3] = {x, y, z};
+        for (int c = 0; c < 3; c++) {
+            int b = (int)floor(bc[c] / a.bedge[c]);
+            bc[c] = std::min(std::max(b, 0), a.nb[c] - 1);
+        }
+        per[(size_t)(bc[0] + a.nb[0] * (bc[1] + (long long)a.nb[1] * bc[2]))].push_back((int)i);
+        nsw++;
+    }
+    hi.wstart.assign((size_t)nbins + 1, 0);
+    hi.widx.clear();
+    hi.widx.reserve((size_t)nsw);
+    for (long long b = 0; b < nbins; b++) {
+        hi.wstart[(size_t)b] = (int)hi.widx.size();
+        for (int v : per[(size_t)b]) hi.widx.push_back(v);
+    }
+    hi.wstart[(size_t)nbins] = (int)hi.widx.size();
+    a.nsw = (int)nsw;
+    return CGB_OK;
+}
 
+// Every device buffer of the handle.  cell_cap < 0: own memory, the cell
+// arrays grow with the cells; otherwise (arena, size query) the cell arrays,
+// the pair buffer and the track record are sized once for cell_cap cells and
+// track_cap steps, and the FP64 staging buffer is allocated too.
+static int alloc_state(cgb_sim* s, int cell_cap, int track_cap) {
+    DevArgs& a = s->a;
+    const size_t popb = 19 * (size_t)a.pstride * s->esize;
+    HIPCHK(s, dalloc(s, &s->pop[0], popb));
+    HIPCHK(s, dalloc(s, &s->pop[1], popb));
+    HIPCHK(s, dalloc(s, &s->rho[0], (size_t)a.pstride * s->esize));
+    HIPCHK(s, dalloc(s, &s->rho[1], (size_t)a.pstride * s->esize));
+    HIPCHK(s, dalloc(s, &a.owner, (size_t)a.ns * 4));
+    const size_t msz = s->P.precision == CGB_P64 ? 8 : 4;
+    if (s->P.tau == 1.0) HIPCHK(s, dalloc(s, &a.lmom, 4 * (size_t)a.pstride * msz));
+    else HIPCHK(s, dalloc(s, &a.usol, 3 * (size_t)a.pstride * msz));
+    HIPCHK(s, dalloc(s, &a.flags, (size_t)a.ns * 4));
+    HIPCHK(s, dalloc(s, &a.cand, (size_t)a.ns * 4));
+    HIPCHK(s, dalloc(s, &a.ntrans, TSEG * 4));
+    HIPCHK(s, dalloc(s, &a.status, 16));
+    HIPCHK(s, dalloc(s, &a.bad_step, 16));
+    HIPCHK(s, dalloc(s, &a.dstep, 16));
+    HIPCHK(s, dalloc(s, &s->obs_partial, (size_t)s->obs_nblk * 8 * 8));
+    HIPCHK(s, dalloc(s, &a.ysin, (size_t)a.ny * 8));
+    HIPCHK(s, dalloc(s, &a.track_part, (size_t)TRACK_BLOCKS * 2 * 8));
+    HIPCHK(s, dalloc(s, &a.track_n, 16));
+    HIPCHK(s, dalloc(s, &a.bin_count, (size_t)a.nbins * 4));
+    HIPCHK(s, dalloc(s, &a.bin_start, (size_t)(a.nbins + 1) * 4));
+    HIPCHK(s, dalloc(s, &a.bin_fill, (size_t)a.nbins * 4));
+    HIPCHK(s, dalloc(s, &a.scan_tmp, (size_t)((a.nbins + 4095) / 4096 + 1) * 4));
+    HIPCHK(s, dalloc(s, &a.wall_start, (size_t)(a.nbins + 1) * 4));
+    HIPCHK(s, dalloc(s, &a.wall_idx, (size_t)std::max(a.nsw, 1) * 4));
+    int rc = alloc_particles(s, std::max(cell_cap, 0));
+    if (rc) return rc;
+    if (cell_cap >= 0) {
+        s->cell_cap = cell_cap;
+        s->pair_cap = std::max(1024, 64 * cell_cap);
+        HIPCHK(s, dalloc(s, &s->pair_cnt, 16));
+        HIPCHK(s, dalloc(s, &s->pair_buf, (size_t)s->pair_cap * 2 * 4));
+        s->track_max = std::max(track_cap, 0);
+        HIPCHK(s, dalloc(s, &s->track_buf, 2 * (size_t)std::max(s->track_max, 1) * 8));
+        s->arena_state = s->arena_used;
+    }
+    return CGB_OK;
+}
+
+// uploads and set-up kernels of a new handle (fluid at rest everywhere)
+static int init_device(cgb_sim* s, const HostInit& hi) {
+    DevArgs& a = s->a;
+    const size_t msz = s->P.precision == CGB_P64 ? 8 : 4;
+    if (a.lmom) HIPCHK(s, launch_fill_i32((int*)a.lmom, (long long)(4 * (size_t)a.pstride * msz / 4), 0, s->st));
+    HIPCHK(s, hipMemcpyAsync(a.owner, hi.own.data(), (size_t)a.ns * 4, hipMemcpyHostToDevice, s->st));
+    if (a.usol) HIPCHK(s, launch_usol(a, s->st, true));
+    HIPCHK(s, hipMemcpyAsync(a.ysin, hi.ysin.data(), (size_t)a.ny * 8, hipMemcpyHostToDevice, s->st));
+    HIPCHK(s, hipMemcpyAsync(a.wall_start, hi.wstart.data(), hi.wstart.size() * 4, hipMemcpyHostToDevice, s->st));
+    if (!hi.widx.empty())
+        HIPCHK(s, hipMemcpyAsync(a.wall_idx, hi.widx.data(), hi.widx.size() * 4, hipMemcpyHostToDevice, s->st));
+    HIPCHK(s, launch_fill_i32(a.cand, a.ns, NO_CAND, s->st));
+    HIPCHK(s, launch_fill_i32(a.status, 4, 0, s->st));
+    HIPCHK(s, launch_fill_i32(a.bad_step, 4, 0x7fffffff, s->st));
+    HIPCHK(s, launch_fill_i32(a.dstep, 1, -1, s->st));
+    HIPCHK(s, launch_fill_i32(a.track_n, 4, 0, s->st));
+    int rc = init_particle_buffers(s);
+    if (rc) return rc;
+    set_tiles(s, default_tiles(a));
+    a.n = 0;
+    bind_buffers(s);
+    HIPCHK(s, launch_equilibrium_fill(a, nullptr, nullptr, s->st));
+    HIPCHK(s, launch_flags_rebuild(a, s->st));
+    if (a.lmom) HIPCHK(s, launch_lmom(a, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));  // the host vectors are temporaries
+    s->fluid_ready = true;
+    return CGB_OK;
+}
+
+static int make_stream(cgb_sim* s, void* stream) {
     if (stream) {
         s->st = (hipStream_t)stream;
     } else {
-        if (hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking) != hipSuccess) { delete s; return CGB_EDEVICE; }
+        HIPCHK(s, hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
         s->own_stream = true;
     }
     s->fork = true;  // side streams are created at the first step that uses them
-    int rc = CGB_OK;
-#define CK(call)                                         \
-    do {                                                 \
-        hipError_t _e = (call);                          \
-        if (_e != hipSuccess) { rc = CGB_EDEVICE; s->err = hipGetErrorString(_e); goto fail; } \
-    } while (0)
-    {
-        const size_t popb = 19 * (size_t)a.pstride * s->esize;
-        CK(dalloc(s, &s->pop[0], popb));
-        CK(dalloc(s, &s->pop[1], popb));
-        CK(dalloc(s, &s->rho[0], (size_t)a.pstride * s->esize));
-        CK(dalloc(s, &s->rho[1], (size_t)a.pstride * s->esize));
-        CK(dalloc(s, &a.owner, (size_t)a.ns * 4));
-        const size_t msz = p->precision == CGB_P64 ? 8 : 4;
-        if (p->tau == 1.0) {
-            CK(dalloc(s, &a.lmom, 4 * (size_t)a.pstride * msz));
-            CK(hipMemsetAsync(a.lmom, 0, 4 * (size_t)a.pstride * msz, s->st));
-        } else {
-            CK(dalloc(s, &a.usol, 3 * (size_t)a.pstride * msz));
-        }
-        CK(dalloc(s, &a.flags, (size_t)a.ns * 4));
-        CK(dalloc(s, &a.cand, (size_t)a.ns * 4));
-        CK(dalloc(s, &a.ntrans, TSEG * 4));
-        CK(dalloc(s, &a.status, 16));
-        CK(dalloc(s, &a.bad_step, 16));
-        CK(dalloc(s, &a.dstep, 16));
-        CK(dalloc(s, &s->obs_partial, (size_t)s->obs_nblk * 8 * 8));
-        // owner map: walls from the mask and the wall planes
-        std::vector<int32_t> own((size_t)a.ns, OWN_FLUID);
-        for (long long i = 0; i < a.ns; i++) {
-            const int y = (int)((i / a.nx) % a.ny);
-            bool w = wall_mask ? wall_mask[i] != 0 : false;
-            if (p->wall_y && (y == 0 || y == a.ny - 1)) w = true;
-            if (w) own[(size_t)i] = OWN_WALL;
-        }
-        CK(hipMemcpyAsync(a.owner, own.data(), (size_t)a.ns * 4, hipMemcpyHostToDevice, s->st));
-        if (a.usol) CK(launch_usol(a, s->st, true));
-        for (long long i = 0; i < a.ns; i++) s->n_nonwall += own[(size_t)i] != OWN_WALL ? 1.0 : 0.0;
-        {
-            std::vector<double> ys((size_t)a.ny);
-            for (int y = 0; y < a.ny; y++) ys[(size_t)y] = sin(2.0 * M_PI * y / (double)a.ny);
-            CK(dalloc(s, &a.ysin, (size_t)a.ny * 8));
-            CK(hipMemcpyAsync(a.ysin, ys.data(), (size_t)a.ny * 8, hipMemcpyHostToDevice, s->st));
-            CK(hipStreamSynchronize(s->st));  // ys is a host temporary
-        }
-        CK(dalloc(s, &a.track_part, (size_t)TRACK_BLOCKS * 2 * 8));
-        CK(dalloc(s, &a.track_n, 16));
-        // cell-list geometry: bin edge >= max(cut-off, wall potential range)
-        const double Lb[3] = {(double)a.nx, (double)a.ny, (double)a.nz};
-        const double emin = std::max(p->r_cut, wr);
-        long long nbins = 1;
-        for (int c = 0; c < 3; c++) {
-            a.nb[c] = std::max(1, (int)floor(Lb[c] / emin));
-            a.bedge[c] = Lb[c] / a.nb[c];
-            nbins *= a.nb[c];
-        }
-        if (nbins > (1LL << 30)) { rc = CGB_EINVAL; s->err = "too many cell-list bins"; goto fail; }
-        a.nbins = (int)nbins;
-        CK(dalloc(s, &a.bin_count, (size_t)nbins * 4));
-        CK(dalloc(s, &a.bin_start, (size_t)(nbins + 1) * 4));
-        CK(dalloc(s, &a.bin_fill, (size_t)nbins * 4));
-        CK(dalloc(s, &a.scan_tmp, (size_t)((nbins + 4095) / 4096 + 1) * 4));
-        // surface wall nodes (wall nodes with a non-wall neighbour), binned
-        std::vector<std::vector<int>> per((size_t)nbins);
-        long long nsw = 0;
-        for (long long i = 0; i < a.ns; i++) {
-            if (own[(size_t)i] != OWN_WALL) continue;
-            const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / ((long long)a.nx * a.ny));
-            bool surf = false;
-            for (int r = 1; r < 19 && !surf; r++) {
-                int yn = y + CY(r);
-                if (p->wall_y) { if (yn < 0 || yn >= a.ny) continue; }
-                else yn = wrap(yn, a.ny);
-                const long long j = wrap(x + CX(r), a.nx) + (long long)a.nx * (yn + (long long)a.ny * wrap(z + CZ(r), a.nz));
-                if (own[(size_t)j] != OWN_WALL) surf = true;
-            }
-            if (!surf) continue;
-            int bc[3] = {x, y, z};
-            for (int c = 0; c < 3; c++) {
-                int b = (int)floor(bc[c] / a.bedge[c]);
-                bc[c] = std::min(std::max(b, 0), a.nb[c] - 1);
-            }
-            per[(size_t)(bc[0] + a.nb[0] * (bc[1] + (long long)a.nb[1] * bc[2]))].push_back((int)i);
-            nsw++;
-        }
-        std::vector<int> wstart((size_t)nbins + 1), widx;
-        widx.reserve((size_t)nsw);
-        for (long long b = 0; b < nbins; b++) {
-            wstart[(size_t)b] = (int)widx.size();
-            for (int v : per[(size_t)b]) widx.push_back(v);
-        }
-        wstart[(size_t)nbins] = (int)widx.size();
-        a.nsw = (int)nsw;
-        CK(dalloc(s, &a.wall_start, (size_t)(nbins + 1) * 4));
-        CK(dalloc(s, &a.wall_idx, (size_t)std::max<long long>(nsw, 1) * 4));
-        CK(hipMemcpyAsync(a.wall_start, wstart.data(), wstart.size() * 4, hipMemcpyHostToDevice, s->st));
-        if (nsw) CK(hipMemcpyAsync(a.wall_idx, widx.data(), widx.size() * 4, hipMemcpyHostToDevice, s->st));
-        CK(launch_fill_i32(a.cand, a.ns, NO_CAND, s->st));
-        CK(launch_fill_i32(a.status, 4, 0, s->st));
-        CK(launch_fill_i32(a.bad_step, 4, 0x7fffffff, s->st));
-        CK(launch_fill_i32(a.dstep, 1, -1, s->st));
-        set_tiles(s, default_tiles(a));
-        if (alloc_particles(s, 0) != CGB_OK) { rc = CGB_EDEVICE; goto fail; }
-        a.n = 0;
-        bind_buffers(s);
-        CK(launch_equilibrium_fill(a, nullptr, nullptr, s->st));
-        CK(launch_flags_rebuild(a, s->st));
-        if (a.lmom) CK(launch_lmom(a, s->st));
-        CK(hipStreamSynchronize(s->st));
-        s->fluid_ready = true;
+    return CGB_OK;
+}
+
+int cgb_create(const cgb_params* p, const uint8_t* wall_mask, void* stream, cgb_sim** out) {
+    if (!p || !out) return CGB_EINVAL;
+    *out = nullptr;
+    if (!params_ok(p)) return CGB_EINVAL;
+    cgb_sim* s = new cgb_sim();
+    HostInit hi;
+    int rc = setup_host(s, p, wall_mask, hi);
+    if (!rc) rc = make_stream(s, stream);
+    if (!rc) rc = alloc_state(s, -1, 0);
+    if (!rc) rc = init_device(s, hi);
+    if (rc) {
+        cgb_destroy(s);
+        return rc;
     }
-#undef CK
     *out = s;
     return CGB_OK;
-fail:
-    cgb_destroy(s);
-    return rc;
+}
+
+int cgb_query_sizes(const cgb_params* p, const uint8_t* wall_mask, int32_t cell_cap, int32_t track_cap,
+                    cgb_sizes* out) {
+    if (!p || !out || cell_cap < 0 || track_cap < 0 || !params_ok(p)) return CGB_EINVAL;
+    cgb_sim s;
+    s.mem_mode = MEM_COUNT;
+    HostInit hi;
+    int rc = setup_host(&s, p, wall_mask, hi);
+    if (!rc) rc = alloc_state(&s, cell_cap, track_cap);
+    if (rc) return rc;
+    out->arena_bytes = (int64_t)s.arena_used;
+    // FP64 staging of the largest host transfer: 19 deviations per site
+    out->staging_bytes = (int64_t)(19 * (size_t)s.a.ns * 8);
+    out->cell_cap = cell_cap;
+    out->track_cap = track_cap;
+    return CGB_OK;
+}
+
+int cgb_create_in(const cgb_params* p, const uint8_t* wall_mask, void* stream, const cgb_sizes* sz, void* arena,
+                  void* staging, cgb_sim** out) {
+    if (!p || !sz || !arena || !staging || !out) return CGB_EINVAL;
+    *out = nullptr;
+    cgb_sizes want;
+    int rc = cgb_query_sizes(p, wall_mask, sz->cell_cap, sz->track_cap, &want);
+    if (rc) return rc;
+    if (sz->arena_bytes < want.arena_bytes || sz->staging_bytes < want.staging_bytes) return CGB_EINVAL;
+    if (((uintptr_t)arena & 255) != 0 || ((uintptr_t)staging & 7) != 0) return CGB_EINVAL;
+    cgb_sim* s = new cgb_sim();
+    s->mem_mode = MEM_ARENA;
+    s->arena = (char*)arena;
+    s->arena_bytes = (size_t)sz->arena_bytes;
+    s->tmp = (double*)staging;
+    s->tmp_bytes = (size_t)sz->staging_bytes;
+    HostInit hi;
+    rc = setup_host(s, p, wall_mask, hi);
+    if (!rc) rc = make_stream(s, stream);
+    if (!rc) rc = alloc_state(s, sz->cell_cap, sz->track_cap);
+    if (!rc) rc = init_device(s, hi);
+    if (rc) {
+        cgb_destroy(s);
+        return rc;
+    }
+    *out = s;
+    return CGB_OK;
 }
 
 int cgb_set_particles(cgb_sim* s, int32_t n, const double* X, const double* q, const double* V, const double* L,
@@ -415,7 +541,9 @@ int cgb_set_particles(cgb_sim* s, int32_t n, const double* X, const double* q, c
     }
     HIPCHK(s, hipStreamSynchronize(s->st));
     if (n > s->ncap) {
+        if (s->mem_mode != MEM_OWN) FAIL(s, CGB_EINVAL, "%d cells exceed the arena's %d", n, s->ncap);
         int rc = alloc_particles(s, n);
+        if (!rc) rc = init_particle_buffers(s);
         if (rc) return rc;
     }
     a.n = n;
@@ -639,7 +767,7 @@ int cgb_get_pairs(cgb_sim* s, int32_t* ij, int64_t cap, int64_t* n) {
     if (rc && rc != CGB_EUNSTABLE) return rc;
     DevArgs& a = s->a;
     const int want = std::max(1024, 64 * a.n);
-    if (want > s->pair_cap) {
+    if (want > s->pair_cap && s->mem_mode == MEM_OWN) {
         dfree(s, s->pair_buf);
         s->pair_buf = nullptr;
         if (!s->pair_cnt) HIPCHK(s, dalloc(s, &s->pair_cnt, 16));
@@ -800,12 +928,18 @@ int cgb_track(cgb_sim* s, int32_t cap) {
     if (!s || cap < 0) return CGB_EINVAL;
     HIPCHK(s, hipStreamSynchronize(s->st));
     DevArgs& a = s->a;
-    dfree(s, a.track);
-    a.track = nullptr;
-    a.track_cap = 0;
-    if (cap > 0) {
-        HIPCHK(s, dalloc(s, &a.track, 2 * (size_t)cap * 8));
+    if (s->mem_mode != MEM_OWN) {
+        if (cap > s->track_max) FAIL(s, CGB_EINVAL, "%d steps exceed the arena's record of %d", cap, s->track_max);
+        a.track = cap > 0 ? s->track_buf : nullptr;
         a.track_cap = cap;
+    } else {
+        dfree(s, a.track);
+        a.track = nullptr;
+        a.track_cap = 0;
+        if (cap > 0) {
+            HIPCHK(s, dalloc(s, &a.track, 2 * (size_t)cap * 8));
+            a.track_cap = cap;
+        }
     }
     HIPCHK(s, launch_fill_i32(a.track_n, 1, 0, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
@@ -856,6 +990,9 @@ int cgb_mu_rel(cgb_sim* s, int32_t first, double* mu) {
     const bool kolm = P.force_mode == 2 && !P.wall_y;
     const bool slit = P.force_mode == 1 && P.wall_y && P.g[0] == 0.0 && P.g[1] == 0.0 && P.g[2] != 0.0;
     if (!kolm && !slit) FAIL(s, CGB_EINVAL, "no apparent-viscosity estimator for this driving");
+    // the Kolmogorov estimator's one-step map (decay (1 - cos k)/3, forcing
+    // (5 + cos k)/6) is the exact map at tau = 1 only
+    if (kolm && P.tau != 1.0) FAIL(s, CGB_EINVAL, "the Kolmogorov estimator holds at tau = 1 only (tau = %g)", P.tau);
     int n = 0;
     int rc = cgb_get_track(s, nullptr, 0, &n);
     if (rc) return rc;
@@ -926,7 +1063,9 @@ int cgb_load(cgb_sim* s, const char* path) {
         FAIL(s, CGB_EINVAL, "checkpoint %s does not match this lattice", path);
     }
     if (n > s->ncap) {
+        if (s->mem_mode != MEM_OWN) { fclose(f); FAIL(s, CGB_EINVAL, "%d cells exceed the arena's %d", n, s->ncap); }
         int rc = alloc_particles(s, n);
+        if (!rc) rc = init_particle_buffers(s);
         if (rc) { fclose(f); return rc; }
     }
     a.n = n;

@@ -13,6 +13,9 @@ struct LaunchRec {
 
 enum { K_PREP, K_RASTER, K_TRANS, K_LB, K_MEM, K_CELLS, K_POT, K_INT, K_TRACK, K_NKIND };
 
+// where a handle's device memory comes from
+enum { MEM_OWN = 0, MEM_ARENA = 1, MEM_COUNT = 2 };
+
 struct cgb_sim {
     double n_nonwall = 0;  // non-wall nodes (normalisation of the tracked sums)
     cgb_params P;
@@ -36,6 +39,14 @@ struct cgb_sim {
     std::string err;
     int64_t dev_bytes = 0;
     std::vector<void*> allocs;
+    // MEM_ARENA: every device array is a piece of the caller's arena, sized
+    // once at creation for cell_cap cells and track_max recorded steps
+    int mem_mode = MEM_OWN;
+    char* arena = nullptr;
+    size_t arena_bytes = 0, arena_used = 0, arena_state = 0;
+    int cell_cap = -1;
+    int track_max = 0;
+    double* track_buf = nullptr;
     double* tmp = nullptr;  // FP64 staging for uploads/downloads
     size_t tmp_bytes = 0;
     double* obs_partial = nullptr;

@@ -32,7 +32,7 @@ def rel_inf(a, b):
     return num / den if den > 0 else num
 
 
-def oracle_sensitivity(params, X, q, steps, walls=None):
+def oracle_sensitivity(params, X, q, steps, walls=None, V=None, L=None, u0=None):
     """Conditioning of the problem itself: how far the oracle's own state
     moves after ``steps`` when every initial x coordinate is perturbed by one
     unit in the last place.  Two correct FP64 implementations that round
@@ -42,8 +42,8 @@ def oracle_sensitivity(params, X, q, steps, walls=None):
         o = O.Oracle(params, walls)
         Xp = np.array(X, dtype=np.float64).copy()
         Xp[:, 0] *= 1.0 + eps
-        o.set_particles(Xp, q)
-        o.init_fluid()
+        o.set_particles(Xp, q, V, L)
+        o.init_fluid(None, u0)
         o.step(steps)
         runs.append(o)
     a, b = runs

@@ -49,3 +49,26 @@ def test_estimators_match_the_oracle():
     u = 1e-4 * (1.0 + 0.1 * rng.random(50))
     for tau in (1.0, 0.8):
         assert cgb.mu_rel_slit(u, 1e-6, tau, 40, 9) == pytest.approx(O.mu_rel_slit(u, 1e-6, tau, 40, 9), rel=1e-13)
+
+
+def test_query_sizes_without_a_device():
+    # cgb_query_sizes is host arithmetic: the arena grows with the cell
+    # capacity and the track record, staging holds 19 FP64 per site
+    import synth
+    from paper_1005_2594_amd import cgb
+    p = synth.params(32, 24, 40)
+    s0 = cgb.query_sizes(p, None, 0, 0, precision="pmx16s")
+    s1 = cgb.query_sizes(p, None, 1000, 0, precision="pmx16s")
+    s2 = cgb.query_sizes(p, None, 2000, 0, precision="pmx16s")
+    s3 = cgb.query_sizes(p, None, 2000, 500, precision="pmx16s")
+    assert s0.staging_bytes == 19 * 32 * 24 * 40 * 8
+    assert s0.arena_bytes > 19 * 2 * 2 * 32 * 24 * 40
+    assert s0.arena_bytes < s1.arena_bytes < s2.arena_bytes
+    # at least the per-cell state: X, q, V, L, forces, kinematics, list of covered nodes
+    assert s2.arena_bytes - s1.arena_bytes >= 1000 * (8 * (3 + 4 + 3 + 3 + 6 + 6 + 12) + 4 * 154)
+    # 16 bytes per recorded step, in 256-byte pieces (one piece without a record)
+    assert s3.arena_bytes - s2.arena_bytes == (500 * 16 + 255) // 256 * 256 - 256
+    # FP64 storage needs more than FP16
+    assert cgb.query_sizes(p, None, 0, 0, precision="p64").arena_bytes > s0.arena_bytes
+    with pytest.raises(cgb.CgbError):
+        cgb.query_sizes(dict(p, tau=0.4), None, 0, 0)
