@@ -253,6 +253,17 @@ int cgb_mlp_grad(cgb_mlp* h, int32_t n, const float* xn, const float* tn, const 
  * step's batch loss. */
 int cgb_mlp_train(cgb_mlp* h, int32_t n, const float* x, const float* mu, int32_t steps, const int32_t* idx, float lr,
                   float* loss);
+/* cgb_mlp_train for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid it): the same
+ * arguments (host pointers) and the same result bit for bit, but no device
+ * memory is allocated or freed: the inputs, their standardised copies, the
+ * indices and the losses are staged in a fixed device array of the library
+ * (one per device, about 5 MB, held until the process ends).  Limits:
+ * n <= 65536 samples and steps <= 1024 per call (CGB_EINVAL beyond).  Every
+ * call on a device shares that device's array: calls that overlap on one
+ * device race.  Synchronous. */
+int cgb_mlp_train_noalloc(cgb_mlp* h, int32_t n, const float* x, const float* mu, int32_t steps,
+                          const int32_t* idx, float lr, float* loss);
 /* ensemble mean of mu and relative spread (sample standard deviation over
  * members / mean) for physical inputs x[n][3] */
 int cgb_mlp_predict(cgb_mlp* h, int64_t n, const float* x, float* mean, float* spread);

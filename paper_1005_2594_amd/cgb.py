@@ -125,6 +125,7 @@ def lib():
     L.cgb_mlp_forward.argtypes = [VP, C.c_int64, VP, VP]
     L.cgb_mlp_grad.argtypes = [VP, C.c_int32, VP, VP, VP, VP, VP]
     L.cgb_mlp_train.argtypes = [VP, C.c_int32, VP, VP, C.c_int32, VP, C.c_float, VP]
+    L.cgb_mlp_train_noalloc.argtypes = [VP, C.c_int32, VP, VP, C.c_int32, VP, C.c_float, VP]
     L.cgb_mlp_predict.argtypes = [VP, C.c_int64, VP, VP, VP]
     L.cgb_mlp_predict_device.argtypes = [VP, C.c_int64, VP, VP, VP, VP]
     _lib = L
@@ -524,6 +525,16 @@ class Mlp:
         steps = idx.shape[1]
         loss = np.empty((self.members, steps), dtype=np.float32)
         self._check(lib().cgb_mlp_train(self.h, len(x), _ptr(x), _ptr(mu), steps, _ptr(idx), float(lr), _ptr(loss)))
+        return loss
+
+    def train_noalloc(self, x, mu, idx, lr):
+        """As train(), through the entry point that allocates no device memory."""
+        x = _f32(x, (-1, 3)); mu = _f32(mu, (-1,))
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        steps = idx.shape[1]
+        loss = np.empty((self.members, steps), dtype=np.float32)
+        self._check(lib().cgb_mlp_train_noalloc(self.h, len(x), _ptr(x), _ptr(mu), steps, _ptr(idx), float(lr),
+                                                _ptr(loss)))
         return loss
 
     def predict(self, x):

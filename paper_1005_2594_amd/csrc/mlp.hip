@@ -23,6 +23,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -371,10 +372,58 @@ __global__ void standardise_kernel(Norm nm, int n, const float* x, const float* 
 }
 
 
+// ---------------------------------------------------------------- allocation-free training
+// Device staging of cgb_mlp_train_noalloc: raw inputs and targets, their
+// standardised copies, the sample indices of every step and the per-step
+// losses, at fixed offsets of one array.  Each device the library runs on
+// holds its own copy until the process ends; every call on a device shares
+// it, so calls that overlap on one device race.  Every section is written
+// before it is read in a call, so nothing needs clearing between calls.
+constexpr int NA_SAMPLES = 65536;  // samples per call
+constexpr int NA_STEPS = 1024;     // Adam steps per call
+constexpr size_t NA_X = 0;                                              // float [NA_SAMPLES][NIN]
+constexpr size_t NA_MU = NA_X + (size_t)NA_SAMPLES * NIN * 4;           // float [NA_SAMPLES]
+constexpr size_t NA_XN = NA_MU + (size_t)NA_SAMPLES * 4;                // float [NA_SAMPLES][NIN]
+constexpr size_t NA_TN = NA_XN + (size_t)NA_SAMPLES * NIN * 4;          // float [NA_SAMPLES]
+constexpr size_t NA_IDX = NA_TN + (size_t)NA_SAMPLES * 4;               // int [MAXM][NA_STEPS][TB]
+constexpr size_t NA_LOSS = NA_IDX + (size_t)MAXM * NA_STEPS * TB * 4;   // float [MAXM][NA_STEPS]
+constexpr size_t NA_BYTES = NA_LOSS + (size_t)MAXM * NA_STEPS * 4;
+static_assert(NA_MU % 256 == 0 && NA_XN % 256 == 0 && NA_TN % 256 == 0 && NA_IDX % 256 == 0 && NA_LOSS % 256 == 0,
+              "aligned sections");
+
+}  // namespace
+
+// In host code this name is a host-side stand-in, not a device address:
+// kernels and copies take the address scratch_ptr() obtains per device.
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[64] = {};  // device address of scratch, per device ordinal
+
+// device address of scratch on the current device (looked up once per device)
+hipError_t scratch_ptr(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
 }  // namespace
 
 struct cgb_mlp {
     int members = 0;
+    void* scratch = nullptr;  // device address of the staging array on the handle's device
     float* params = nullptr;
     float* am = nullptr;
     float* av = nullptr;
@@ -420,6 +469,11 @@ int cgb_mlp_create(int32_t members, cgb_mlp** out) {
         hipMalloc(&h->am, b) != hipSuccess || hipMalloc(&h->av, b) != hipSuccess || hipMalloc(&h->grad, b) != hipSuccess) {
         cgb_mlp_destroy(h);
         return CGB_ENOMEM;
+    }
+    // the staging array of cgb_mlp_train_noalloc on this (the current) device
+    if (scratch_ptr(&h->scratch) != hipSuccess) {
+        cgb_mlp_destroy(h);
+        return CGB_EDEVICE;
     }
     (void)hipMemsetAsync(h->params, 0, b, h->st);
     (void)hipMemsetAsync(h->am, 0, b, h->st);
@@ -567,6 +621,38 @@ int cgb_mlp_train(cgb_mlp* h, int32_t n, const float* x, const float* mu, int32_
     MCHK(h, hipMemcpyAsync(tn.data(), dtn.p, tn.size() * 4, hipMemcpyDeviceToHost, h->st));
     MCHK(h, hipStreamSynchronize(h->st));
     return run_train(h, n, xn.data(), tn.data(), steps, idx, lr, loss, 1);
+}
+
+int cgb_mlp_train_noalloc(cgb_mlp* h, int32_t n, const float* x, const float* mu, int32_t steps, const int32_t* idx,
+                          float lr, float* loss) {
+    if (!h || n < 1 || !x || !mu || steps < 1 || !idx || !(lr > 0.f)) return CGB_EINVAL;
+    if (n > NA_SAMPLES || steps > NA_STEPS)
+        MFAIL(h, CGB_EINVAL, "%d samples / %d steps exceed the staging limits (%d samples, %d steps per call)", n, steps,
+              NA_SAMPLES, NA_STEPS);
+    int rc = check_idx(h, n, steps, idx);
+    if (rc) return rc;
+    for (int i = 0; i < n; i++)
+        if (!(mu[i] > 0.f)) MFAIL(h, CGB_EINVAL, "target %d is not positive", i);
+    if (!h->scratch) MFAIL(h, CGB_EDEVICE, "no staging array on this device");
+    unsigned char* S = (unsigned char*)h->scratch;  // device address, never the host-side name
+    float* dx = (float*)(S + NA_X);
+    float* dmu = (float*)(S + NA_MU);
+    float* dxn = (float*)(S + NA_XN);
+    float* dtn = (float*)(S + NA_TN);
+    int* di = (int*)(S + NA_IDX);
+    float* dl = (float*)(S + NA_LOSS);
+    const int M = h->members;
+    MCHK(h, hipMemcpyAsync(dx, x, (size_t)n * NIN * 4, hipMemcpyHostToDevice, h->st));
+    MCHK(h, hipMemcpyAsync(dmu, mu, (size_t)n * 4, hipMemcpyHostToDevice, h->st));
+    // [M][steps][TB]: the kernel of step s reads member m's row at m * steps * TB + s * TB
+    MCHK(h, hipMemcpyAsync(di, idx, (size_t)M * steps * TB * 4, hipMemcpyHostToDevice, h->st));
+    hipLaunchKernelGGL(standardise_kernel, dim3((n + 255) / 256), dim3(256), 0, h->st, h->nm, n, dx, dmu, dxn, dtn);
+    MCHK(h, hipGetLastError());
+    rc = train_steps(h, dxn, dtn, di, dl, steps, lr, 1);
+    if (rc) return rc;
+    if (loss) MCHK(h, hipMemcpyAsync(loss, dl, (size_t)M * steps * 4, hipMemcpyDeviceToHost, h->st));
+    MCHK(h, hipStreamSynchronize(h->st));
+    return CGB_OK;
 }
 
 int cgb_mlp_predict_device(cgb_mlp* h, int64_t n, const float* x, float* mean, float* spread, void* stream) {
