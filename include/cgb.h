@@ -180,9 +180,9 @@ int cgb_kernel_times(cgb_sim* s, char* names, double* ms, int64_t* count, int32_
 
 /* Concurrency of the phases of a step (on by default for lattices with
  * cells): the cell list and the pair/wall potentials (Eqs. 15-20), which need
- * only the cells' positions and axes, and the momentum exchange (Eq. 12),
- * which reads the populations the LB reads, not those it writes, run on two
- * side streams of the handle beside the lattice part, joined before the
+ * only the cells' positions and axes, run on a side stream of the handle
+ * beside the lattice part (rasterisation, transitions, LB with the link
+ * momenta of the cell nodes, per-cell momentum sums), joined before the
  * integrator; results are identical either way.  on = 0 runs every kernel on
  * the handle's stream in sequence (kernel timing of isolated launches).
  * Returns CGB_EINVAL for a null handle. */

@@ -28,9 +28,10 @@ __host__ __device__ constexpr int CZ(int r) {
 __host__ __device__ constexpr int OPP(int r) { return r == 0 ? 0 : ((r & 1) ? r + 1 : r - 1); }
 __host__ __device__ constexpr double WD(int r) { return r == 0 ? 1.0 / 3.0 : (r <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
-// node flag word: bit 31 = node is not fluid (cell or wall); bit r (1..18) =
-// fluid node whose pull source x - c_r is not fluid
+// node flag word: bit 31 = node is not fluid (cell or wall); bit 30 = wall
+// node; bit r (1..18) = the pull source x - c_r of the node is not fluid
 constexpr uint32_t NONFLUID = 0x80000000u;
+constexpr uint32_t WALLNODE = 0x40000000u;
 constexpr uint32_t LINKBITS = 0x0007FFFEu;
 constexpr int32_t OWN_WALL = -2;
 constexpr int32_t OWN_FLUID = -1;
@@ -124,6 +125,8 @@ struct DevArgs {
                        // node: the rigid-body velocity of its cell at the node,
                        // or the wall velocity
     void* crec;        // [n] CellRec, in cell-list order (per-cell kernels)
+    double* fnode;     // [ns][4] momentum the links of each cell node carried to
+                       // its cell in the step (Eq. 12), written by the LB kernel
     // per-step record of the mixture velocity (apparent viscosity)
     double* track;      // [track_cap][2]: sums of u_z sin(2 pi y/ny) and of u_z
     int* track_n;       // steps recorded (keeps counting past track_cap)

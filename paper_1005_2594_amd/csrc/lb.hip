@@ -20,9 +20,12 @@
 // plane velocity, and the LB gathers the velocity of each link's source.  In
 // neither case does a link need to know which body is behind it.
 //
-// Momentum exchange (Eq. 12) is summed per cell by a separate kernel from
-// the same stored populations and boundary velocities (the bounced
-// populations are the node's own, unchanged by this kernel).
+// Momentum exchange (Eq. 12): the lanes of cell nodes, which have no
+// populations of their own, form the momentum their links carry to the cell,
+// sum_r (2 n*_rbar(x) + C_r) c_rbar over the fluid neighbours x = s + c_r,
+// from the populations and densities the fluid lanes of the same kernel load
+// for their bounce-back (so those lines are on chip), in FP64, and store it
+// per node; a per-cell pass sums the nodes of each cell and their torques.
 //
 // Collision: Eqs. 1, 4, 5 with the Guo forcing term, u = (sum n c + g/2)/rho.
 // Work decomposition: a workgroup of BX x BY threads covers a patch of an x-y
@@ -68,6 +71,88 @@ __device__ inline M link_cu(const LinkVel<M>& lv, int r) {
     M cu = (M)compv(r, comp1(r)) * lv.a[r];
     if (comp2(r) >= 0) cu += (M)compv(r, comp2(r)) * lv.b[r];
     return cu;
+}
+
+// Momentum the links of cell node s (site i, flags f, rigid-body velocity
+// u = V + Omega x (s - X) at the node) carry to its cell in this step
+// (Eq. 12): the fluid neighbour x = s + c_r bounces its own n*_rbar(x) into
+// direction r and the correction C_r = 6 w_r rho(x) (c_r . u) (Eq. 10) is
+// added, so the link transfers (2 n*_rbar(x) + C_r) c_rbar.  Only the part of
+// the deviations d = n* - w rho0 is summed: the constant part 2 w rho0 c_rbar,
+// with the link forces of Eqs. 13-14 between cells and from walls, cancels
+// over the closed surface of any node set.  Populations and densities are
+// decoded in the codec's precision (the values the fluid lanes bounce), C,
+// the link momenta and their sum are FP64.  ox, oy, oz: offsets to x - c along
+// each axis at index c + 1 (so x + c_r is at index 1 - c_r).
+// links R0 <= r < R1 of the cell node: loads issued together, then summed
+template <int P, int R0, int R1>
+__device__ inline void cell_links_part(const DevArgs& a, __amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rRA,
+                                       unsigned i, uint32_t f, const int* ox, const int* oy, const int* oz,
+                                       const double* us, double* m) {
+    using Cd = Codec<P>;
+    using T = typename Cd::T;
+    using R = typename Cd::R;
+    constexpr unsigned ES = sizeof(T);
+    const unsigned ps = (unsigned)a.pstride;
+    T dv[R1 - R0], rv[R1 - R0];
+#pragma unroll
+    for (int r = R0; r < R1; r++) {
+        // s + c_r is fluid: bit OPP(r) of the flags (source s - c_OPP(r)) is clear
+        const bool lk = !((f >> OPP(r)) & 1u);
+        const unsigned xi = i + (unsigned)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)]);
+        dv[r - R0] = bload<T>(rA, lk ? ES * ((unsigned)OPP(r) * ps + xi) : OOB);
+        rv[r - R0] = bload<T>(rRA, lk ? ES * xi : OOB);
+    }
+#pragma unroll
+    for (int r = R0; r < R1; r++) {
+        const bool lk = !((f >> OPP(r)) & 1u);
+        const R Dx = rho_dec<P>(a, rv[r - R0]);
+        const double rho_x = a.rho0 + (double)Dx;
+        double cu = 0;
+        if (CX(r)) cu += CX(r) * us[0];
+        if (CY(r)) cu += CY(r) * us[1];
+        if (CZ(r)) cu += CZ(r) * us[2];
+        const double C = 6.0 * WD(r) * rho_x * cu;
+        const double mr = lk ? -(2.0 * (double)pop_dec<P>(a, dv[r - R0], OPP(r), Dx) + C) : 0.0;
+        if (CX(r)) m[0] += CX(r) * mr;
+        if (CY(r)) m[1] += CY(r) * mr;
+        if (CZ(r)) m[2] += CZ(r) * mr;
+    }
+}
+
+// Momentum the links of cell node s (site i, flags f, rigid-body velocity
+// u = V + Omega x (s - X) at the node) carry to its cell in this step
+// (Eq. 12): the fluid neighbour x = s + c_r bounces its own n*_rbar(x) into
+// direction r and the correction C_r = 6 w_r rho(x) (c_r . u) (Eq. 10) is
+// added, so the link transfers (2 n*_rbar(x) + C_r) c_rbar.  Only the part of
+// the deviations d = n* - w rho0 is summed: the constant part 2 w rho0 c_rbar,
+// with the link forces of Eqs. 13-14 between cells and from walls, cancels
+// over the closed surface of any node set.  Populations and densities are
+// decoded in the codec's precision (the values the fluid lanes bounce), C,
+// the link momenta and their sum are FP64.  ox, oy, oz: offsets to x - c along
+// each axis at index c + 1 (so x + c_r is at index 1 - c_r).  The links are
+// taken in three groups of six, each group's loads in flight together, so that
+// this path needs no more registers than the fluid path beside it.
+template <int P, class M>
+__device__ inline void cell_node_links(const DevArgs& a, __amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rRA,
+                                       unsigned i, uint32_t f, const int* oxi, const int* oyi, const int* oz,
+                                       M u0, M u1, M u2) {
+    // the x and y offsets do not change along a thread's z sweep; made
+    // opaque here, so that the compiler forms the 18 neighbour offsets on
+    // this path instead of keeping them in registers across the whole sweep
+    int ox[3] = {oxi[0], 0, oxi[2]}, oy[3] = {oyi[0], 0, oyi[2]};
+    asm volatile("" : "+v"(ox[0]), "+v"(ox[2]), "+v"(oy[0]), "+v"(oy[2]));
+    const double us[3] = {(double)u0, (double)u1, (double)u2};
+    double m[3] = {0, 0, 0};
+    cell_links_part<P, 1, 7>(a, rA, rRA, i, f, ox, oy, oz, us, m);
+    __builtin_amdgcn_sched_barrier(0);
+    cell_links_part<P, 7, 13>(a, rA, rRA, i, f, ox, oy, oz, us, m);
+    __builtin_amdgcn_sched_barrier(0);
+    cell_links_part<P, 13, 19>(a, rA, rRA, i, f, ox, oy, oz, us, m);
+    double* F = a.fnode + 4 * (size_t)i;
+    F[0] = m[0];
+    F[1] = m[1];
+    F[2] = m[2];
 }
 
 // general tau: populations are kept per direction
@@ -194,6 +279,13 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
             atomicOr(a.status, ST_UNSTABLE);
             atomicMin(a.bad_step, *a.dstep);
         }
+        } else if (inb && !(f & WALLNODE)) {
+            // a cell node: the boundary velocity field holds its rigid-body velocity
+            const int oz[3] = {z == a.nz - 1 ? -(int)((a.nz - 1) * plane) : (int)plane, 0,
+                               z == 0 ? (int)((a.nz - 1) * plane) : -(int)plane};
+            const M u0 = bload<M>(rU, (unsigned)sizeof(M) * i), u1 = bload<M>(rU, (unsigned)sizeof(M) * (ps + i)),
+                    u2 = bload<M>(rU, (unsigned)sizeof(M) * (2 * ps + i));
+            cell_node_links<P, M>(a, rA, rRA, i, f, ox, oy, oz, u0, u1, u2);
         }
         if (inb) {
 #pragma unroll
@@ -207,7 +299,7 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
 // n^eq(rho, u) plus the forcing term, a function of the moments alone, so the
 // pulled populations are folded into rho and j as they arrive.
 template <int P, int TZ>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) lb_kernel_tau1(DevArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) lb_kernel_tau1(DevArgs a) {
     using Cd = Codec<P>;
     using T = typename Cd::T;
     using R = typename Cd::R;
@@ -226,8 +318,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
     const auto rRB = make_rsrc(a.rhoB, (unsigned long long)ps * ES);
     const auto rFl = make_rsrc(a.flags, (unsigned long long)a.ns * 4);
     const auto rK = make_rsrc(a.lmom, 4ull * ps * sizeof(M));
-    const int ox[3] = {x == a.nx - 1 ? -(a.nx - 1) : 1, 0, x == 0 ? a.nx - 1 : -1};
-    const int oy[3] = {y == a.ny - 1 ? -(int)((a.ny - 1) * nx) : (int)nx, 0, y == 0 ? (int)((a.ny - 1) * nx) : -(int)nx};
+    const int oxs[3] = {x == a.nx - 1 ? -(a.nx - 1) : 1, 0, x == 0 ? a.nx - 1 : -1};
+    const int oys[3] = {y == a.ny - 1 ? -(int)((a.ny - 1) * nx) : (int)nx, 0, y == 0 ? (int)((a.ny - 1) * nx) : -(int)nx};
     // body force at this plane: constant, or f0 sin(2 pi y/ny) from the table
     const int yc = y < a.ny ? y : a.ny - 1;
     const R gx = a.force_mode == 1 ? (R)a.g[0] : (R)0;
@@ -247,31 +339,81 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) l
         // below are shared by all lanes of the wave, so that each wave store
         // writes its lines whole (stores issued separately by the fluid and
         // non-fluid lanes would each write part of the same lines)
-        T ob[19], orho;
-#pragma unroll
-        for (int r = 0; r < 19; r++) ob[r] = Cd::enc((R)0, (R)1);
-        orho = Cd::enc((R)0, (R)1);
-        if (!(f & NONFLUID)) {
         const int oz[3] = {z == a.nz - 1 ? -(int)((a.nz - 1) * plane) : (int)plane, 0,
                            z == 0 ? (int)((a.nz - 1) * plane) : -(int)plane};
-        auto src = [&](int r) { return i + (unsigned)(ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1]); };
+        const bool fl = !(f & NONFLUID);
+        const bool cn = inb && (f & NONFLUID) && !(f & WALLNODE);  // a cell node
         const uint32_t links = f & LINKBITS;
-
-        R Down = 0;  // the node's stored density deviation (for C; not needed by the split codec)
-        R drho = 0, jx = 0, jy = 0, jz = 0;
-        // issue the 19 pulls (non-fluid source: bounce-back), the node's link
-        // moments and its stored density together
+        // the x and y offsets do not change along the sweep; made opaque in
+        // each step, so that the compiler forms the per-direction offsets here
+        // instead of keeping some thirty of them in registers for the sweep
+        int ox[3] = {oxs[0], 0, oxs[2]}, oy[3] = {oys[0], 0, oys[2]};
+        asm volatile("" : "+v"(ox[0]), "+v"(ox[2]), "+v"(oy[0]), "+v"(oy[2]));
+        // One set of loads serves both kinds of lanes, so that their loads are
+        // in flight together.  Slot r: a fluid lane pulls n*_r(x - c_r), or
+        // bounces its own n*_rbar(x) when the source is not fluid (Eq. 9); a
+        // cell lane loads the population its link along c_r carries,
+        // n*_rbar(s + c_r), when s + c_r is fluid (Eq. 12).
         T v[19];
 #pragma unroll
         for (int r = 0; r < 19; r++) {
             const bool bb = (f >> r) & 1u;
-            v[r] = bload<T>(rA, ES * (bb ? (unsigned)OPP(r) * ps + i : (unsigned)r * ps + src(r)));
+            const unsigned pull = bb ? (unsigned)OPP(r) * ps + i
+                                     : (unsigned)r * ps + i + (unsigned)(ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1]);
+            unsigned off = fl ? ES * pull : OOB;
+            if (r > 0 && cn && !((f >> OPP(r)) & 1u))
+                off = ES * ((unsigned)OPP(r) * ps + i + (unsigned)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)]));
+            v[r] = bload<T>(rA, off);
         }
-        // link moments; the split codec's moments hold every fluid node's
-        // density parts too (see below)
+        // fluid lanes: their link moments (the split codec's hold every fluid
+        // node's density parts too, see below); cell lanes: planes 0-2 hold
+        // the node's rigid-body velocity
         M km[4];
 #pragma unroll
-        for (int c = 0; c < 4; c++) km[c] = bload<M>(rK, (links || Cd::SPLIT) ? (unsigned)sizeof(M) * ((unsigned)c * ps + i) : OOB);
+        for (int c = 0; c < 4; c++)
+            km[c] = bload<M>(rK, ((fl && (links || Cd::SPLIT)) || cn) ? (unsigned)sizeof(M) * ((unsigned)c * ps + i) : OOB);
+        // cell lanes: the densities of their links' fluid nodes
+        T dn[19];
+#pragma unroll
+        for (int r = 1; r < 19; r++)
+            dn[r] = bload<T>(rRA, (cn && !((f >> OPP(r)) & 1u))
+                                      ? ES * (i + (unsigned)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)])) : OOB);
+        if (cn) {
+            // the momentum the node's links carry to its cell (Eq. 12): the
+            // neighbour x = s + c_r bounces n*_rbar(x) into direction r and the
+            // correction C_r = 6 w_r rho(x) (c_r . u(s)) (Eq. 10) is added, so the
+            // link transfers (2 n*_rbar(x) + C_r) c_rbar; deviation part only (the
+            // constant part and the solid links of Eqs. 13-14 cancel over the
+            // closed surface of a node set); FP64 from the decoded values
+            const double us[3] = {(double)km[0], (double)km[1], (double)km[2]};
+            double m0 = 0, m1 = 0, m2 = 0;
+#pragma unroll
+            for (int r = 1; r < 19; r++) {
+                const bool lk = !((f >> OPP(r)) & 1u);
+                const R Dx = rho_dec<P>(a, dn[r]);
+                const double rho_x = a.rho0 + (double)Dx;
+                double cu = 0;
+                if (CX(r)) cu += CX(r) * us[0];
+                if (CY(r)) cu += CY(r) * us[1];
+                if (CZ(r)) cu += CZ(r) * us[2];
+                const double C = 6.0 * WD(r) * rho_x * cu;
+                const double mr = lk ? -(2.0 * (double)pop_dec<P>(a, v[r], OPP(r), Dx) + C) : 0.0;
+                if (CX(r)) m0 += CX(r) * mr;
+                if (CY(r)) m1 += CY(r) * mr;
+                if (CZ(r)) m2 += CZ(r) * mr;
+            }
+            double* F = a.fnode + 4 * (size_t)i;
+            F[0] = m0;
+            F[1] = m1;
+            F[2] = m2;
+        }
+        T ob[19], orho;
+#pragma unroll
+        for (int r = 0; r < 19; r++) ob[r] = Cd::enc((R)0, (R)1);
+        orho = Cd::enc((R)0, (R)1);
+        if (fl) {
+        R Down = 0;  // the node's stored density deviation (for C; not needed by the split codec)
+        R drho = 0, jx = 0, jy = 0, jz = 0;
         if constexpr (!Cd::SPLIT) Down = rho_dec<P>(a, bload<T>(rRA, links ? ES * i : OOB));
 #pragma unroll
         for (int r = 0; r < 19; r++) {

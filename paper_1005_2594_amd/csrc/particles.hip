@@ -334,87 +334,19 @@ __global__ void __launch_bounds__(256) resolve_kernel(DevArgs a) {
 static inline unsigned cell_grid(int n) { return (unsigned)((n + CPW - 1) / CPW); }
 
 // ------------------------------------------------------------------ momentum exchange
-// Force and torque on each cell from its links (Eq. 12).  A link joins a
-// node s of the cell to a fluid node x = s + c_r; the LB kernel bounced the
-// fluid node's own population n*_rbar(x) into direction r and added
-// C_r = 6 w_r rho(x) (c_r . u(s)), u(s) = V + Omega x (s - X) (Eq. 10), so
-// the link carried (2 n*_rbar(x) + C_r) c_rbar to the cell.  Only the part
-// that depends on the deviations d = n* - w rho0 is summed: the constant part
-// 2 w rho0 c_rbar, together with the link forces of Eqs. 13-14 between cells
-// and from walls, sums to zero over the closed surface of the cell's node
-// set (the sums of w c and (s - X) x w c over the outward links of any node
-// set vanish).  Torque: the transferred momentum is parallel to c_r, so any
-// point of the link line is a lever point; s is used.
-// The populations and densities are decoded in the storage codec's
-// precision (the values the LB bounced); C, the link momenta and every sum
-// are formed in FP64.
+// Force and torque on each cell from its links (Eq. 12).  The LB kernel has
+// stored, at every cell node s, the momentum m_s the links of s carried to the
+// cell in this step (the deviation part of sum_r (2 n*_rbar + C_r) c_rbar over
+// its fluid neighbours; the constant part and the solid links of Eqs. 13-14
+// cancel over the closed surface of the cell's node set).  The transferred
+// momentum of a link is parallel to c_r, so any point of the link line is a
+// lever point; s is used: the torque is sum_s (s - X) x m_s.
 // Two cells per wave (lanes 0-31 and 32-63), cells in cell-list order: each
-// half walks its cell's list of covered nodes (written by the claim pass),
-// keeps the nodes the cell owns after the resolve pass and issues the loads
-// of a node's 18 links together; sums in list order, then over the half.
-template <int P>
-__device__ inline void node_links(const DevArgs& a, __amdgpu_buffer_rsrc_t rA, __amdgpu_buffer_rsrc_t rRA, unsigned s,
-                                  uint32_t f, const double* X, const double* V, const double* W, double* FT) {
-    // f: the node's flags; bit r set: s - c_r is non-fluid
-    using Cd = Codec<P>;
-    using T = typename Cd::T;
-    using R = typename Cd::R;
-    constexpr unsigned ES = sizeof(T);
-    const unsigned ps = (unsigned)a.pstride;
-    const unsigned nx = (unsigned)a.nx, plane = (unsigned)a.nx * (unsigned)a.ny;
-    const int sx = (int)(s % nx), sy = (int)((s / nx) % (unsigned)a.ny), sz = (int)(s / plane);
-    // the bounced population and the density of the fluid node x = s + c_r of every link
-    const int ox[3] = {sx == a.nx - 1 ? -(a.nx - 1) : 1, 0, sx == 0 ? a.nx - 1 : -1};
-    const int oy[3] = {sy == a.ny - 1 ? -(int)((a.ny - 1) * nx) : (int)nx, 0, sy == 0 ? (int)((a.ny - 1) * nx) : -(int)nx};
-    const int oz[3] = {sz == a.nz - 1 ? -(int)((a.nz - 1) * plane) : (int)plane, 0,
-                       sz == 0 ? (int)((a.nz - 1) * plane) : -(int)plane};
-    T dv[19], rv[19];
-#pragma unroll
-    for (int r = 1; r < 19; r++) {
-        // fluid at s + c_r: bit OPP(r) of s's flags (source s - c_OPP(r)) is clear
-        const bool lk = !((f >> OPP(r)) & 1u);
-        // offsets index c = +1 at 0 and c = -1 at 2: x = s + c_r
-        const unsigned xi = s + (unsigned)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)]);
-        dv[r] = bload<T>(rA, lk ? ES * ((unsigned)OPP(r) * ps + xi) : 0xfffffff0u);
-        rv[r] = bload<T>(rRA, lk ? ES * xi : 0xfffffff0u);
-    }
-    double d[3];
-    node_disp(a, sx, sy, sz, X, d);
-    double u[3];
-    cross3(W, d, u);
-    for (int c = 0; c < 3; c++) u[c] += V[c];
-    double m0 = 0, m1 = 0, m2 = 0;
-#pragma unroll
-    for (int r = 1; r < 19; r++) {
-        const bool lk = !((f >> OPP(r)) & 1u);
-        const R Dx = rho_dec<P>(a, rv[r]);
-        const double rho_x = a.rho0 + (double)Dx;
-        double cu = 0;
-        if (CX(r)) cu += CX(r) * u[0];
-        if (CY(r)) cu += CY(r) * u[1];
-        if (CZ(r)) cu += CZ(r) * u[2];
-        const double C = 6.0 * WD(r) * rho_x * cu;
-        const double m = lk ? -(2.0 * (double)pop_dec<P>(a, dv[r], OPP(r), Dx) + C) : 0.0;
-        if (CX(r)) m0 += CX(r) * m;
-        if (CY(r)) m1 += CY(r) * m;
-        if (CZ(r)) m2 += CZ(r) * m;
-    }
-    FT[0] += m0; FT[1] += m1; FT[2] += m2;
-    FT[3] += d[1] * m2 - d[2] * m1;
-    FT[4] += d[2] * m0 - d[0] * m2;
-    FT[5] += d[0] * m1 - d[1] * m0;
-}
-
-// Writes each cell's hydrodynamic force and torque of the step: its link
-// sums plus the cover/uncover sums of the transitions kernel.
-template <int P>
+// half walks its cell's list of covered nodes (written by the claim pass) and
+// keeps the nodes the cell owns after the resolve pass; FP64 sums in list
+// order, then over the half (the order is fixed: the result does not depend
+// on scheduling).  The cover/uncover sums of the transitions are added.
 __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
-    using Cd = Codec<P>;
-    using T = typename Cd::T;
-    constexpr unsigned ES = sizeof(T);
-    const unsigned ps = (unsigned)a.pstride;
-    const auto rA = make_rsrc(a.A, 19ull * ps * ES);
-    const auto rRA = make_rsrc(a.rhoA, (unsigned long long)ps * ES);
     const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
     const int wv = threadIdx.x >> 6;
     const int k = 2 * __builtin_amdgcn_readfirstlane(xcd_block((int)blockIdx.x, (int)gridDim.x) * CPW + wv) + half;
@@ -426,12 +358,20 @@ __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
     int cnt = (live && cr.ok) ? a.ccount[p] : 0;
     if (cnt > a.lcap) cnt = a.lcap;
     const unsigned* lst = a.clist + (size_t)p * (size_t)a.lcap;
+    const unsigned nx = (unsigned)a.nx, plane = (unsigned)a.nx * (unsigned)a.ny;
     double FT[6] = {0, 0, 0, 0, 0, 0};
     for (int e = hl; e < cnt; e += 32) {
         const unsigned s = lst[e];
         const int o = a.owner[s];
-        const uint32_t f = a.flags[s];
-        if (o == p) node_links<P>(a, rA, rRA, s, f, cr.X, cr.V, cr.W, FT);
+        const double2 m01 = *(const double2*)(a.fnode + 4 * (size_t)s);
+        const double m2 = a.fnode[4 * (size_t)s + 2];
+        if (o != p) continue;
+        double d[3];
+        node_disp(a, (int)(s % nx), (int)((s / nx) % (unsigned)a.ny), (int)(s / plane), cr.X, d);
+        FT[0] += m01.x; FT[1] += m01.y; FT[2] += m2;
+        FT[3] += d[1] * m2 - d[2] * m01.y;
+        FT[4] += d[2] * m01.x - d[0] * m2;
+        FT[5] += d[0] * m01.y - d[1] * m01.x;
     }
     // sums over each half of the wave
 #pragma unroll
@@ -448,15 +388,7 @@ __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
 
 hipError_t launch_mem_reduce(const DevArgs& a, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
-    const dim3 g(cell_grid((a.n + 1) / 2)), b(64 * CPW);
-    switch (a.precision) {
-        case CGB_P64: hipLaunchKernelGGL(mem_reduce_kernel<CGB_P64>, g, b, 0, st, a); break;
-        case CGB_P32: hipLaunchKernelGGL(mem_reduce_kernel<CGB_P32>, g, b, 0, st, a); break;
-        case CGB_PMX16: hipLaunchKernelGGL(mem_reduce_kernel<CGB_PMX16>, g, b, 0, st, a); break;
-        case CGB_PMXBF16: hipLaunchKernelGGL(mem_reduce_kernel<CGB_PMXBF16>, g, b, 0, st, a); break;
-        case CGB_PMX16S: hipLaunchKernelGGL(mem_reduce_kernel<CGB_PMX16S>, g, b, 0, st, a); break;
-        default: return hipErrorInvalidValue;
-    }
+    hipLaunchKernelGGL(mem_reduce_kernel, dim3(cell_grid((a.n + 1) / 2)), dim3(64 * CPW), 0, st, a);
     return hipGetLastError();
 }
 
@@ -540,8 +472,10 @@ hipError_t launch_usol(const DevArgs& a, hipStream_t st, bool all) {
 // cells' kinematics (the per-cell FP32 table for the FP32 link type, FP64
 // kinematics for FP64), in a ring of four planes (three are read while the
 // next is built), so the link sources are read from LDS.
+// At a cell node the first three planes hold instead the rigid-body velocity
+// u(s) of the node (the LB kernel's momentum exchange reads it there).
 // Groups of 32 nodes along x (one 128-byte line of an FP32 plane) that hold a
-// node with links are written whole; layout [4][pstride].
+// node with links or a cell node are written whole; layout [4][pstride].
 // patch: TX x (256 / TX) nodes of an x-y plane, swept over tz planes
 template <int TX>
 struct LmShape {
@@ -676,7 +610,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         lm_lds_barrier();
         const bool fl = !(f & NONFLUID);
         const bool lk = fl && (f & LINKBITS) != 0u;
-        const unsigned long long m = __ballot(NC == 4 ? fl : lk);
+        const bool cn = (f & NONFLUID) && !(f & WALLNODE);  // a cell node (lanes outside read NONFLUID | 0)
+        const unsigned long long m = __ballot(NC == 4 ? fl : (lk || (in && cn)));
         if (in && (NC == 4 || ((m >> (lane & ~31)) & 0xffffffffull) != 0ull)) {
             // sums over the links (directions that are not links weigh 0)
             M k0 = 0, k1 = 0, k2 = 0, k3 = 0;
@@ -719,6 +654,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                 k1 = fl ? rho6 * k1 + t1 : (M)0;
                 k2 = fl ? rho6 * k2 + t2 : (M)0;
                 k3 = fl ? rho6 * k3 + t3 : (M)0;
+            }
+            if (cn) {
+                const M* P = U + (size_t)((zz + 1) & 3) * NC * S::NP + (ty + 1) * S::HX + (tx + 1);
+                k0 = P[0]; k1 = P[S::NP]; k2 = P[2 * S::NP]; k3 = (M)0;
             }
             K[s] = k0;
             K[ps + s] = k1;
@@ -921,7 +860,9 @@ __global__ void flags_rebuild_kernel(DevArgs a) {
     const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (s >= a.ns) return;
     const int x = (int)(s % a.nx), y = (int)((s / a.nx) % a.ny), z = (int)(s / ((long long)a.nx * a.ny));
-    uint32_t f = (a.owner[s] != OWN_FLUID) ? NONFLUID : 0u;
+    const int own = a.owner[s];
+    uint32_t f = (own != OWN_FLUID) ? NONFLUID : 0u;
+    if (own == OWN_WALL) f |= WALLNODE;
     for (int r = 1; r < 19; r++) {
         const int xs = wrap(x - CX(r), a.nx), ys = wrap(y - CY(r), a.ny), zs = wrap(z - CZ(r), a.nz);
         if (a.owner[xs + (long long)a.nx * (ys + (long long)a.ny * zs)] != OWN_FLUID) f |= 1u << r;

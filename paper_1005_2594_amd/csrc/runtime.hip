@@ -196,9 +196,8 @@ int64_t cgb_device_bytes(const cgb_sim* s) { return s ? s->dev_bytes : 0; }
 void cgb_destroy(cgb_sim* s) {
     if (!s) return;
     if (s->st) (void)hipStreamSynchronize(s->st);
-    for (hipStream_t q : {s->st_mem, s->st_pot})
-        if (q) { (void)hipStreamSynchronize(q); (void)hipStreamDestroy(q); }
-    for (hipEvent_t e : {s->ev_ras, s->ev_tr, s->ev_mem, s->ev_pot})
+    if (s->st_pot) { (void)hipStreamSynchronize(s->st_pot); (void)hipStreamDestroy(s->st_pot); }
+    for (hipEvent_t e : {s->ev_ras, s->ev_pot})
         if (e) (void)hipEventDestroy(e);
     for (auto& r : s->recs) { (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
     for (auto e : s->ev_pool) (void)hipEventDestroy(e);
@@ -281,7 +280,7 @@ static bool params_ok(const cgb_params* p) {
     const double esz = p->precision == CGB_P64 ? 8.0 : (p->precision == CGB_P32 ? 4.0 : 2.0);
     const double msz = p->precision == CGB_P64 ? 8.0 : 4.0;
     const double pst = (double)(((long long)p->nx * p->ny * p->nz + 255) / 256 * 256);
-    return !(19.0 * esz * pst >= 4294901760.0 || 4.0 * msz * pst >= 4294901760.0);
+    return !(19.0 * esz * pst >= 4294901760.0 || 4.0 * msz * pst >= 4294901760.0 || 32.0 * pst >= 4294901760.0);
 }
 
 // parameters, constants and the host-side geometry (no device work)
@@ -390,6 +389,7 @@ static int alloc_state(cgb_sim* s, int cell_cap, int track_cap) {
     else HIPCHK(s, dalloc(s, &a.usol, 3 * (size_t)a.pstride * msz));
     HIPCHK(s, dalloc(s, &a.flags, (size_t)a.ns * 4));
     HIPCHK(s, dalloc(s, &a.cand, (size_t)a.ns * 4));
+    HIPCHK(s, dalloc(s, &a.fnode, 32 * (size_t)a.ns));
     HIPCHK(s, dalloc(s, &a.ntrans, TSEG * 4));
     HIPCHK(s, dalloc(s, &a.status, 16));
     HIPCHK(s, dalloc(s, &a.bad_step, 16));
@@ -619,19 +619,16 @@ int cgb_step(cgb_sim* s, int32_t nsteps) {
     DevArgs& a = s->a;
     for (int t = 0; t < nsteps; t++) {
         bind_buffers(s);
-        // with cells, three streams: the cell list and the potentials need
-        // only the positions and axes (after the rasterisation, whose record
-        // kernel reads the previous cell list); the momentum exchange needs
-        // the occupancy after the transitions and the populations the LB
-        // reads (it does not read what the LB writes); the integrator joins
+        // with cells, two streams: the cell list and the potentials need only
+        // the positions and axes (after the rasterisation, whose record kernel
+        // reads the previous cell list) and run beside the lattice part; the
+        // integrator joins
         const bool fk = s->fork && a.n > 0;
-        if (fk && !s->st_mem) {
-            HIPCHK(s, hipStreamCreateWithFlags(&s->st_mem, hipStreamNonBlocking));
+        if (fk && !s->st_pot) {
             HIPCHK(s, hipStreamCreateWithFlags(&s->st_pot, hipStreamNonBlocking));
-            for (hipEvent_t* e : {&s->ev_ras, &s->ev_tr, &s->ev_mem, &s->ev_pot})
-                HIPCHK(s, hipEventCreateWithFlags(e, hipEventDisableTiming));
+            for (hipEvent_t* e : {&s->ev_ras, &s->ev_pot}) HIPCHK(s, hipEventCreateWithFlags(e, hipEventDisableTiming));
         }
-        hipStream_t sm = fk ? s->st_mem : s->st, sp = fk ? s->st_pot : s->st;
+        hipStream_t sp = fk ? s->st_pot : s->st;
         HIPCHK(s, timed(s, K_PREP, [&] { return launch_step_prep(a, s->st); }));
         HIPCHK(s, timed(s, K_RASTER, [&] { return launch_raster(a, s->st, false, false); }));
         if (fk) {
@@ -643,19 +640,14 @@ int cgb_step(cgb_sim* s, int32_t nsteps) {
         }
         HIPCHK(s, timed(s, K_TRANS, [&] {
             hipError_t e = launch_transitions(a, s->st, true);
-            if (e == hipSuccess && fk) e = hipEventRecord(s->ev_tr, s->st);
             return e != hipSuccess ? e : (a.lmom ? launch_lmom(a, s->st) : launch_usol(a, s->st, false));
         }));
-        if (fk) {
-            HIPCHK(s, hipStreamWaitEvent(sm, s->ev_tr, 0));
-            HIPCHK(s, timed_on(s, K_MEM, sm, [&] { return launch_mem_reduce(a, sm); }));
-            HIPCHK(s, hipEventRecord(s->ev_mem, sm));
-        }
+        // the LB kernel also stores the link momenta of every cell node; the
+        // per-cell pass sums them
         HIPCHK(s, timed(s, K_LB, [&] { return launch_lb(a, s->lbcfg, s->st); }));
-        if (!fk) HIPCHK(s, timed(s, K_MEM, [&] { return launch_mem_reduce(a, s->st); }));
+        HIPCHK(s, timed(s, K_MEM, [&] { return launch_mem_reduce(a, s->st); }));
         if (a.track) HIPCHK(s, timed(s, K_TRACK, [&] { return launch_track(a, s->st); }));
         if (fk) {
-            HIPCHK(s, hipStreamWaitEvent(s->st, s->ev_mem, 0));
             HIPCHK(s, hipStreamWaitEvent(s->st, s->ev_pot, 0));
         } else {
             HIPCHK(s, timed(s, K_CELLS, [&] { return launch_cells(a, s->st); }));

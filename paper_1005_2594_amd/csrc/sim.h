@@ -22,13 +22,12 @@ struct cgb_sim {
     cgb::DevArgs a;
     hipStream_t st = nullptr;
     bool own_stream = false;
-    // phases of a step that do not depend on each other run on side streams:
-    // the momentum exchange (reads the populations before the LB) beside the
-    // link moments and the LB, the cell list and the potentials beside the
-    // whole lattice part; events order them (default priorities throughout)
+    // the cell list and the potentials, which need only the cells' positions
+    // and axes, run on a side stream beside the lattice part of the step;
+    // events order them (default priorities throughout)
     bool fork = false;
-    hipStream_t st_mem = nullptr, st_pot = nullptr;
-    hipEvent_t ev_ras = nullptr, ev_tr = nullptr, ev_mem = nullptr, ev_pot = nullptr;
+    hipStream_t st_pot = nullptr;
+    hipEvent_t ev_ras = nullptr, ev_pot = nullptr;
     int cur = 0;
     void* pop[2] = {nullptr, nullptr};
     void* rho[2] = {nullptr, nullptr};
