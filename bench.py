@@ -2,18 +2,20 @@
 
 Workload: 256^3 periodic box, Kolmogorov body force f_z = 1e-6 sin(2 pi y/256),
 hematocrit 0.4 (256,337 cells with half axes (2.5, 1.0)), tau = 1.  The
-headline number is the mixed-precision path that meets the 1e-3 velocity
-error bar: the deviations n*_r - w_r rho0 stored in FP16 as a per-node part
-(the density deviation) plus per-direction residuals, FP32 collision, FP64
-momentum exchange and integration.  Beside it: FP16 deviations stored per
+headline number is the mixed-precision path: the deviations n*_r - w_r rho0
+stored in FP16 as a per-node part (the density deviation) plus per-direction
+residuals, FP32 collision, link momenta (Eq. 12) and per-cell sums in FP64
+from the decoded populations, FP64 integration.  Beside it: FP16 deviations stored per
 direction alone (the same storage size, ~8x the velocity error) and the
 FP32-storage path.  One step = every kernel of the time
 step (rasterisation, cover/uncover, fused LB, momentum-exchange reduction,
 cell list, pair and wall forces, integration).  Inputs are resident in HBM
 before the timed region.
 
-Also reported (in "config"): the error of the mixed and FP32 paths against
-the FP64 path on the 64^3 companion workload, the batched ensemble of 64
+Also reported (in "config"): the error of every path against the FP64
+oracle on the 64^3 companion workload, stepped in lockstep on the host cores,
+with the oracle's own response to perturbed inputs beside it; the
+whole-step effective and counter bandwidths; the batched ensemble of 64
 uneven channels (one replayed HIP graph, autotuned LB tiles, apparent
 viscosity per channel), and the oracle on the host cores ("cpu_baseline").
 
@@ -38,7 +40,6 @@ import synth  # noqa: E402
 METRIC = "MLUPS at 256³ Ht=0.4, mixed vs FP32 at stated error; % of HBM peak"
 HBM_PEAK_GBS = 8000.0
 STORE_BYTES = {"p64": 8, "p32": 4, "pmx16": 2, "pmxbf16": 2, "pmx16s": 2}
-LB_SOURCE = os.path.join(ROOT, "paper_1005_2594_amd", "csrc", "lb.hip")
 HEAD = "pmx16s"
 STORE_DESC = {
     "pmx16s": "FP16 deviations n*_r - w_r rho0 split into a per-node FP16 density part and per-direction "
@@ -46,10 +47,6 @@ STORE_DESC = {
     "pmx16": "FP16 deviations (n*_r - w_r rho0)/w_r per direction (2 B per population), FP32 collision (pmx16)",
     "p32": "FP32 deviations, FP32 collision (p32)",
 }
-
-
-def traffic_file(prec: str) -> str:
-    return os.path.join(ROOT, "profiles", f"lb_traffic_{prec}_256.txt")
 
 
 def lb_algorithmic_bytes(n_fluid: float, n_sites: int, prec: str) -> float:
@@ -60,20 +57,39 @@ def lb_algorithmic_bytes(n_fluid: float, n_sites: int, prec: str) -> float:
     return n_fluid * (2 * 19 * s + 2 * s) + 4.0 * n_sites
 
 
-def measured_traffic(prec: str):
-    """HBM bytes per LB launch from the committed rocprofv3 counter summary,
-    or None when it was taken on another version of the kernel source."""
-    if not os.path.exists(traffic_file(prec)):
+CSRC = os.path.join(ROOT, "paper_1005_2594_amd", "csrc")
+
+
+def csrc_sha256() -> str:
+    """Hash of every HIP source of the library (the step's kernels)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()
+
+
+def step_algorithmic_bytes(n_fluid: float, n_sites: int, n_cells: int, prec: str) -> float:
+    """Bytes one whole step must move: the LB's (populations of every fluid
+    node read and written, density, flags) and about 200 bytes per cell (its
+    state read and written, forces); link-level data stays on chip."""
+    return lb_algorithmic_bytes(n_fluid, n_sites, prec) + 200.0 * n_cells
+
+
+def counter_summary(prec: str):
+    """The committed rocprofv3 counter summary of the 256^3 workload
+    (profiles/step_traffic_<prec>_256.txt) as a dict, or None when it was
+    taken on other kernel sources than these."""
+    path = os.path.join(ROOT, "profiles", f"step_traffic_{prec}_256.txt")
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(traffic_file(prec)):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    src = hashlib.sha256(open(LB_SOURCE, "rb").read()).hexdigest()
-    if kv.get("lb_source_sha256") != src or "hbm_bytes_per_launch" not in kv:
-        return None
-    return float(kv["hbm_bytes_per_launch"])
+    return kv if kv.get("csrc_sha256") == csrc_sha256() else None
 
 
 def run_gpu(cfg, prec, steps, warmup, kernel_steps=50, serial=False):
@@ -110,53 +126,86 @@ def run_gpu(cfg, prec, steps, warmup, kernel_steps=50, serial=False):
 
 
 def error_report_64(seed=3, horizons=(100, 250, 500)):
-    """Mixed and FP32 paths against the FP64 path of the same kernels on the
-    64^3 companion workload (same cell density; the FP64 path matches the
-    oracle to ~1e-14 in the parity tests).  Pointwise velocity errors are
-    taken at the first horizon, before discrete events (a node changing
-    owner, a pair crossing the cut-off) happen at different steps in
-    different precisions; the plane-averaged mixture velocity profile and
-    the apparent viscosity (Kolmogorov estimator, last half of the run) are
-    the long-horizon measures."""
+    """The GPU paths (FP64, FP32, FP16 per direction, split FP16) against the
+    FP64 oracle on the 64^3 companion workload (same cell density, 4,005
+    cells), all stepped in lockstep: the oracle on the host cores, so this
+    is also the oracle's full 64^3 run of the CPU baseline.  At each horizon:
+    relative L2 error of the fluid velocity (nodes fluid in both), RMS error
+    of the cell positions, relative L2 error of the cell velocities; every
+    step: the number of nodes whose owner differs from the oracle's (a node
+    covered or freed one step apart), accumulated.  Beside them, from
+    tests/golden/conditioning_64cube.json (written by the oracle alone): the
+    oracle's own response to relative perturbations of the cell positions,
+    which puts the errors in proportion.  Apparent viscosity: Kolmogorov
+    estimator over the last half of the run."""
+    from oracle import oracle as O
     from paper_1005_2594_amd import Sim
     cfg = synth.config3_companion(seed=seed)
+    p = cfg["params"]
     precs = ("p64", "p32", "pmx16", "pmx16s")
-    sims = {p: Sim(cfg["params"], precision=p) for p in precs}
+    sims = {q: Sim(p, precision=q) for q in precs}
     for s in sims.values():
         s.set_particles(cfg["X"], cfg["q"])
         s.init_fluid()
         s.track(horizons[-1])
-    res = {p: {} for p in precs[1:]}
-    done = 0
-    for t in horizons:
-        for s in sims.values():
-            s.step(t - done)
-        done = t
-        own64 = sims["p64"].owner()
-        _, u64 = sims["p64"].fields()
-        X64 = sims["p64"].particles()[0]
-        pr64 = sims["p64"].profile_z()
-        for p in precs[1:]:
-            own = sims[p].owner()
-            _, u = sims[p].fields()
-            X = sims[p].particles()[0]
-            m = (own == -1) & (own64 == -1)
-            pr = sims[p].profile_z()
-            d = np.sqrt(np.sum((X - X64) ** 2, axis=1))
-            res[p][f"step{t}"] = dict(
-                rel_l2_u=float(np.linalg.norm(u[m] - u64[m]) / np.linalg.norm(u64[m])),
-                rel_l2_profile=float(np.linalg.norm(pr - pr64) / np.linalg.norm(pr64)),
-                pos_rms=float(np.sqrt(np.mean(d ** 2))),
-                owner_flips=int((own != own64).sum()))
-    first = horizons[-1] // 2
-    mu = {p: sims[p].mu_rel(first=first) for p in precs}
-    for p in precs[1:]:
-        res[p]["mu_rel"] = mu[p]
-        res[p]["mu_rel_rel_err"] = abs(mu[p] - mu["p64"]) / abs(mu["p64"])
-    res["p64_mu_rel"] = mu["p64"]
-    res["mu_rel_window"] = [first, horizons[-1] - 1]
-    for s in sims.values():
+    o = O.Oracle(p)
+    o.set_particles(cfg["X"], cfg["q"])
+    o.init_fluid()
+    n_box = p["nx"]
+    res = {q: {} for q in precs}
+    mism = {q: 0 for q in precs}
+    first = {q: None for q in precs}
+    A_orc = np.empty(horizons[-1])
+    t_orc = 0.0
+    for t in range(1, horizons[-1] + 1):
+        t0 = time.perf_counter()
+        o.step(1)
+        t_orc += time.perf_counter() - t0
+        A_orc[t - 1] = o.mixture()[0]
+        own_o = o.owner()
+        for q, s in sims.items():
+            s.step(1)
+            d = int((s.owner() != own_o).sum())
+            if d and first[q] is None:
+                first[q] = t
+            mism[q] += d
+        if t not in horizons:
+            continue
+        _, u_o = o.fields()
+        X_o, _, V_o, _ = o.particles()
+        for q, s in sims.items():
+            own = s.owner()
+            _, u = s.fields()
+            X, _, V, _ = s.particles()
+            m = (own == -1) & (own_o == -1)
+            dX = X - X_o
+            dX -= n_box * np.round(dX / n_box)
+            res[q][f"step{t}"] = dict(
+                rel_l2_u=float(np.linalg.norm(u[m] - u_o[m]) / np.linalg.norm(u_o[m])),
+                pos_rms=float(np.sqrt(np.mean(np.sum(dX * dX, axis=1)))),
+                rel_l2_V=float(np.linalg.norm(V - V_o) / np.linalg.norm(V_o)),
+                owner_mismatch_node_steps=mism[q])
+    first_step = horizons[-1] // 2
+    mu_o = O.mu_rel_kolmogorov(A_orc, p["f0"], p["rho0"], p["ny"], first_step)
+    for q, s in sims.items():
+        mu = s.mu_rel(first=first_step)
+        res[q]["mu_rel"] = mu
+        res[q]["mu_rel_rel_err"] = abs(mu - mu_o) / abs(mu_o)
+        res[q]["first_owner_mismatch_step"] = first[q]
         s.close()
+    res["oracle_mu_rel"] = mu_o
+    res["mu_rel_window"] = [first_step, horizons[-1] - 1]
+    ns = p["nx"] * p["ny"] * p["nz"]
+    res["oracle_run"] = {"steps": horizons[-1], "seconds": round(t_orc, 1), "cores": O.num_threads(),
+                         "mlups": round(ns * horizons[-1] / t_orc / 1e6, 3)}
+    cond = os.path.join(ROOT, "tests", "golden", "conditioning_64cube.json")
+    if os.path.exists(cond):
+        c = json.load(open(cond))
+        res["oracle_conditioning"] = {
+            "source": "tests/golden/conditioning_64cube.json (the oracle against itself with the cell x "
+                      "coordinates scaled by 1 + eps)",
+            **{f"step{h}": [{k: r[k] for k in ("eps", "rel_l2_u", "pos_rms", "owner_mismatch_node_steps")}
+                            for r in c["steps"][str(h)]] for h in horizons if str(h) in c["steps"]}}
     return res
 
 
@@ -268,7 +317,8 @@ def main():
     lb_avg_s = lb_ms / max(lb_cnt, 1) / 1e3
     algo = lb_algorithmic_bytes(r["n_fluid"], ns, head)
     achieved = algo / lb_avg_s / 1e9
-    traffic = measured_traffic(head) if args.n == 256 else None
+    cs = counter_summary(head) if args.n == 256 else None
+    traffic = None if cs is None else float(cs["lb_fetch_bytes_per_launch"]) + float(cs["lb_write_bytes_per_launch"])
     line = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -295,8 +345,8 @@ def main():
                              "efficiencies of its CPU code on IBM BlueGene/P (combined LB + particles 95.7 % at "
                              "16,384 and 85.2 % at 32,768 cores relative to 2,048; pure LB 98.1 % at 32,768) on a "
                              "1024^2 x 2048 lattice with 4.1e6 cells (Sec. IV)",
-            "concurrency": "serial" if args.serial else "cell list + potentials and momentum exchange on two side "
-                                                        "streams beside the lattice kernels, joined before the integrator",
+            "concurrency": "serial" if args.serial else "cell list + potentials on a side stream beside the lattice "
+                                                        "kernels, joined before the integrator",
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -309,6 +359,18 @@ def main():
     }
     # the other storage precisions of the same workload: FP32, and FP16
     # deviations stored per direction alone
+    # the whole step: algorithmic bytes per step over the step time, and the
+    # counter bytes of every kernel of a step over the step time
+    sa = step_algorithmic_bytes(r["n_fluid"], ns, len(cfg["X"]), head)
+    step_s = r["seconds"] / args.steps
+    line["config"]["step_algorithmic_bytes"] = round(sa)
+    line["config"]["step_effective_gbs"] = round(sa / step_s / 1e9, 1)
+    line["config"]["step_effective_frac"] = round(sa / step_s / 1e9 / HBM_PEAK_GBS, 4)
+    if cs is not None:
+        sb = float(cs["step_fetch_bytes"]) + float(cs["step_write_bytes"])
+        line["config"]["step_counter_bytes"] = round(sb)
+        line["config"]["step_counter_gbs"] = round(sb / step_s / 1e9, 1)
+        line["config"]["step_counter_frac"] = round(sb / step_s / 1e9 / HBM_PEAK_GBS, 4)
     for other in ("p32", "pmx16"):
         if other not in results or other == head:
             continue
@@ -320,7 +382,7 @@ def main():
         line["config"][f"{other}_lb_frac"] = round(lb_algorithmic_bytes(ro["n_fluid"], ns, other) /
                                                    (lo / max(co, 1) / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     if not args.no_error:
-        line["config"]["error_vs_p64_64cube"] = error_report_64()
+        line["config"]["error_vs_oracle_64cube"] = error_report_64()
     if not args.no_batch:
         line["config"]["batch"] = batch_leg(steps=args.batch_steps)
     if not args.no_cpu:

@@ -77,6 +77,14 @@ typedef struct cgb_params {
     double pmx_scale;           /* PMX: stored value = d_r / w_r * pmx_scale
                                    (PMX16S: (d_r / w_r - D) * pmx_scale, and the
                                    density field D * pmx_scale); 0 selects 32768 */
+    double le_u;                /* plane-Couette viscometer (Sec. IV): velocity
+                                   offset U along z across the periodic seam of x
+                                   (Lees-Edwards: the image beyond x = nx - 1
+                                   moves at +U e_z, shifted by U t along z);
+                                   cells are reflected at the sheared planes
+                                   x = 0 and nx - 1.  0 = plain periodic x.
+                                   Needs wall_y = 0 and a storage precision other
+                                   than CGB_PMX16S (CGB_EINVAL otherwise)         */
 } cgb_params;
 
 typedef struct cgb_sim cgb_sim;
@@ -170,6 +178,8 @@ int cgb_get_observables(cgb_sim* s, double* out /* 13 */);
 /* mean over non-wall nodes of the z velocity of the mixture, per y plane
  * (fluid u_z, or the rigid velocity of the owning cell): prof[ny]. */
 int cgb_get_profile_z(cgb_sim* s, double* prof);
+/* the same along any axis (0: x, 1: y, 2: z): prof[n_axis] */
+int cgb_get_profile(cgb_sim* s, int32_t axis, double* prof);
 
 /* Kernel timing with HIP events on the handle's stream.  enable = 1 starts
  * recording, 0 stops.  cgb_kernel_times: for each of up to cap kernel names
@@ -217,6 +227,21 @@ int cgb_get_track(cgb_sim* s, double* out, int32_t cap, int32_t* n);
 int cgb_mu_rel_kolmogorov(const double* A, int32_t n, int32_t first, double f0, double rho0, int32_t ny, double* mu);
 int cgb_mu_rel_slit(const double* ubar, int32_t n, int32_t first, double g, double tau, int32_t ny, double* mu);
 int cgb_mu_rel(cgb_sim* s, int32_t first, double* mu);
+/* Plane-Couette viscometer (Sec. IV, Eq. 23): mu_app = Delta p_LE,z /
+ * (l_y l_z gammadot).  cgb_track also records, with le_u != 0, Delta p_LE,z
+ * of every step: the z momentum carried across the Lees-Edwards seam in -x,
+ * the mean of its values in the frames of the two sides of the seam;
+ * cgb_get_le_flux returns that record (out[k], k < min(cap, recorded);
+ * *n = steps recorded up to the record's capacity).
+ * cgb_mu_app_le: gammadot is the slope of the least-squares line through the
+ * plane-averaged mixture velocity prof_x[nx] (cgb_get_profile, axis 0) over
+ * the central half of the planes, x in [nx/4, 3 nx/4); Delta p_LE,z is the
+ * mean of flux[first .. n-1]; *mu_rel = mu_app / (rho0 nu), nu =
+ * (2 tau - 1)/6.  cgb_mu_rel uses it for a handle with le_u != 0, with the
+ * handle's current profile. */
+int cgb_get_le_flux(cgb_sim* s, double* out, int32_t cap, int32_t* n);
+int cgb_mu_app_le(const double* flux, int32_t n, int32_t first, const double* prof_x, int32_t nx, int32_t ny,
+                  int32_t nz, double rho0, double tau, double* mu_rel);
 
 /* ---- Learned closure: ensemble of MLPs 3 -> 64 -> 64 -> 1 (SiLU) mapping
  * (hematocrit, log shear rate, width / R_perp) to the relative apparent

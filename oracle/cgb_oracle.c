@@ -68,6 +68,7 @@ struct orc_sim {
     int32_t* sw;         /* surface wall nodes (site indices, ascending) */
     int64_t nsw;
     double body_last[3];
+    double le_flux;      /* Delta p_LE,z of the last step (Sec. IV, Eq. 23) */
     int64_t step;
     char err[256];
 };
@@ -240,6 +241,7 @@ int orc_create(const orc_params* p, const uint8_t* wall_mask, orc_sim** out) {
     init_tables();
     if (!p || !out) return ORC_EINVAL;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->tau <= 0.5 || p->rho0 <= 0) return ORC_EINVAL;
+    if (p->le_u != 0.0 && (p->wall_y || p->nx < 2)) return ORC_EINVAL;
     if (p->wall_y && p->ny < 3) return ORC_EINVAL;
     orc_sim* s = (orc_sim*)calloc(1, sizeof(orc_sim));
     if (!s) return ORC_ENOMEM;
@@ -406,6 +408,46 @@ static const double* wall_velocity(const orc_sim* s, int y) {
     if (y == 0) return s->P.wall_v_bot;
     if (y == s->P.ny - 1) return s->P.wall_v_top;
     return zero;
+}
+
+/* ---- plane-Couette viscometer (Sec. IV): Lees-Edwards seam in x ----
+ * Reading: the image of the box beyond x = nx - 1 moves at +U e_z and is
+ * shifted by Delta = U t along z (t: steps completed before this one); the
+ * image below x = 0 moves at -U e_z, shifted by -Delta.  A population pulled
+ * across the seam -- into x = 0 along c_x = +1, or into x = nx - 1 along
+ * c_x = -1 -- comes from the image: its source is the node (nx - 1 or 0,
+ * y - c_y) at z - c_z + Delta (resp. - Delta), linearly interpolated between
+ * the two nodes that bracket that z, and it is carried into this box's frame
+ * by the Galilean shift n^eq(rho_s, u_s -/+ U e_z) - n^eq(rho_s, u_s), with
+ * rho_s, u_s the moments of the interpolated source populations.  Returns
+ * the deviation to pull; *orig receives the population before the shift. */
+static double le_pull(const orc_sim* s, const double* A, int r, int x, int y, int z, double* orig) {
+    const orc_params* P = &s->P;
+    const int nx = P->nx, ny = P->ny, nz = P->nz;
+    const double delta = fmod(P->le_u * (double)s->step, (double)nz);
+    const int from_below = (x == 0 && CV[r][0] == 1);
+    const int xs = from_below ? nx - 1 : 0;
+    const int ys = wrapi(y - CV[r][1], ny);
+    double zf = (double)(z - CV[r][2]) + (from_below ? delta : -delta);
+    zf = fmod(zf, (double)nz);
+    if (zf < 0.0) zf += nz;
+    const double zl = floor(zf);
+    const double w = zf - zl;
+    const int64_t i0 = sid(s, xs, ys, wrapi((int)zl, nz)), i1 = sid(s, xs, ys, wrapi((int)zl + 1, nz));
+    double n[19], drho = 0.0, j[3] = {0, 0, 0};
+    for (int q = 0; q < 19; q++) {
+        n[q] = (1.0 - w) * A[q * s->ns + i0] + w * A[q * s->ns + i1];
+        drho += n[q];
+        for (int a = 0; a < 3; a++) j[a] += n[q] * CV[q][a];
+    }
+    const double rho = P->rho0 + drho;
+    double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+    double e0[19], e1[19];
+    feq_dev(P->rho0, rho, u, e0);
+    u[2] += from_below ? -P->le_u : P->le_u;
+    feq_dev(P->rho0, rho, u, e1);
+    *orig = n[r];
+    return n[r] + (e1[r] - e0[r]);
 }
 
 /* Correction term of Eq. 10 for the population arriving at fluid node x along
@@ -656,6 +698,11 @@ static int one_step(orc_sim* s) {
 
     /* 2. rasterise and apply the occupancy rule */
     cover_scan(s);
+    if (P->le_u != 0.0)
+        for (int z = 0; z < nz; z++)
+            for (int y = 0; y < ny; y++)
+                if (s->cover_min[sid(s, 0, y, z)] != NO_OWNER || s->cover_min[sid(s, nx - 1, y, z)] != NO_OWNER)
+                    return fail(s, ORC_EUNSTABLE, "a cell covers a node of a sheared plane");
 
     /* 3. cover / uncover in site order (Sec. II: deleted or created fluid
      *    momentum is balanced by a force on the cell; torque likewise) */
@@ -755,10 +802,13 @@ static int one_step(orc_sim* s) {
         for (int a = 0; a < 3; a++) s->Th[3 * p + a] += c36 * ((double)s->Bint[3 * p + a] - XA[a]);
     }
 
-    /* 5. stream (pull) + bounce-back (Eqs. 2, 9, 11) + collide */
+    /* 5. stream (pull) + bounce-back (Eqs. 2, 9, 11) + collide; with the
+     *    viscometer's seam, pulls across it come from the sheared image, and
+     *    the z momentum they carry across the seam is recorded */
     int unstable = 0;
     double bodyf[3] = {0, 0, 0};
-#pragma omp parallel for reduction(| : unstable) reduction(+ : bodyf[:3]) schedule(static)
+    double le_flux = 0.0;
+#pragma omp parallel for reduction(| : unstable) reduction(+ : bodyf[:3], le_flux) schedule(static)
     for (int z = 0; z < nz; z++)
         for (int y = 0; y < ny; y++)
             for (int x = 0; x < nx; x++) {
@@ -770,6 +820,15 @@ static int one_step(orc_sim* s) {
                 double d[19], out[19], g[3];
                 double rho_x = -1.0;
                 for (int r = 0; r < 19; r++) {
+                    if (P->le_u != 0.0 && ((x == 0 && CV[r][0] == 1) || (x == nx - 1 && CV[r][0] == -1))) {
+                        /* Delta p_LE,z: the z momentum crossing in -x, the
+                         * mean of its values in the frames of the two sides
+                         * (before and after the Galilean shift) */
+                        double orig;
+                        d[r] = le_pull(s, A, r, x, y, z, &orig);
+                        le_flux += -0.5 * CV[r][0] * CV[r][2] * (orig + d[r]);
+                        continue;
+                    }
                     int xs = wrapi(x - CV[r][0], nx), ys = wrapi(y - CV[r][1], ny), zs = wrapi(z - CV[r][2], nz);
                     int64_t j = sid(s, xs, ys, zs);
                     int32_t o = s->owner[j];
@@ -790,6 +849,7 @@ static int one_step(orc_sim* s) {
                 for (int r = 0; r < 19; r++) B[r * ns + i] = out[r];
             }
     s->dA = B; s->dB = A;
+    s->le_flux = le_flux;
     if (unstable) return fail(s, ORC_EUNSTABLE, "fluid velocity non-finite or |u| > 0.4");
 
     /* 6. pair and wall potentials (Sec. III) */
@@ -853,6 +913,15 @@ static int one_step(orc_sim* s) {
             }
             s->X[3 * p + a] = xn;
         }
+        /* viscometer (Sec. IV): a cell whose centre has come closer than
+         * sigma_perp to one of the sheared side planes (reading: the node
+         * planes x = 0 and x = nx - 1) while moving towards it has its
+         * normal velocity negated */
+        if (P->le_u != 0.0) {
+            const double xc = s->X[3 * p];
+            if ((xc < P->sig_perp && s->V[3 * p] < 0.0) || (nx - 1 - xc < P->sig_perp && s->V[3 * p] > 0.0))
+                s->V[3 * p] = -s->V[3 * p];
+        }
         double qn[4];
         orc_rotate(&s->q[4 * p], &s->L[3 * p], s->Ipar, s->Iperp, 1.0, qn);
         for (int a = 0; a < 4; a++) s->q[4 * p + a] = qn[a];
@@ -914,6 +983,8 @@ int orc_mixture_sums(const orc_sim* s, double* out) {
     out[0] = ssin; out[1] = sone; out[2] = cnt;
     return ORC_OK;
 }
+double orc_le_flux(const orc_sim* s) { return s->le_flux; }
+
 int orc_get_deviations(const orc_sim* s, double* d) {
     memcpy(d, s->dA, sizeof(double) * 19 * s->ns);
     return ORC_OK;

@@ -39,6 +39,11 @@ typedef struct orc_params {
     double eps, eps_w;          /* potential strengths eps-bar, eps-bar_w           */
     double r_cut;               /* pair cut-off (hard truncation of Eq. 15)         */
     double rho_p;               /* cell mass density                                */
+    double le_u;                /* plane-Couette viscometer (Sec. IV): Lees-Edwards
+                                   offset U of the z velocity across the periodic
+                                   seam of x (the image beyond x = nx - 1 moves at
+                                   +U e_z, shifted by U t); 0 = plain periodic x.
+                                   Needs wall_y = 0.                               */
 } orc_params;
 
 typedef struct orc_sim orc_sim;
@@ -58,6 +63,9 @@ int  orc_set_particles(orc_sim* s, int32_t n, const double* X, const double* q,
                        const double* V, const double* L, const uint8_t* fixed);
 int  orc_init_fluid(orc_sim* s, const double* rho /*nullable*/, const double* u /*nullable, sites*3*/);
 int  orc_set_deviations(orc_sim* s, const double* d /* 19*nsites */);
+/* z momentum carried across the Lees-Edwards seam in -x during the last step
+ * (Delta p_LE,z of Eq. 23); 0 when le_u = 0 */
+double orc_le_flux(const orc_sim* s);
 int  orc_step(orc_sim* s, int32_t nsteps);
 
 int  orc_get_deviations(const orc_sim* s, double* d);

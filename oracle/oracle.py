@@ -44,7 +44,7 @@ class OrcParams(C.Structure):
         ("R_perp", C.c_double), ("R_par", C.c_double),
         ("sig_perp", C.c_double), ("sig_par", C.c_double), ("sig_w", C.c_double),
         ("eps", C.c_double), ("eps_w", C.c_double),
-        ("r_cut", C.c_double), ("rho_p", C.c_double),
+        ("r_cut", C.c_double), ("rho_p", C.c_double), ("le_u", C.c_double),
     ]
 
 
@@ -99,6 +99,8 @@ def lib():
         L.orc_rotate.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p]
         L.orc_inside.argtypes = [C.POINTER(OrcParams), C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_num_threads.restype = C.c_int
+        L.orc_le_flux.argtypes = [C.c_void_p]
+        L.orc_le_flux.restype = C.c_double
         del dp
     return _lib
 
@@ -224,6 +226,11 @@ class Oracle:
         return {"mass": o[0], "fluid_momentum": o[1:4].copy(), "particle_momentum": o[4:7].copy(),
                 "n_fluid": int(o[7]), "body_force_last": o[8:11].copy(), "step": int(o[11])}
 
+    def le_flux(self):
+        """Delta p_LE,z of the last step: z momentum carried across the
+        Lees-Edwards seam in -x (Eq. 23)."""
+        return float(lib().orc_le_flux(self.h))
+
     def mass_props(self):
         o = np.empty(3)
         lib().orc_mass_props(self.h, _ptr(o))
@@ -316,6 +323,21 @@ def mu_rel_kolmogorov(A, f0, rho0, ny, first):
     t = np.arange(first, len(A) - 1)
     mu = (f0 * (5.0 + np.cos(k)) / (6.0 * rho0) - (A[t + 1] - A[t])) / (A[t] * (1.0 - np.cos(k)) / 3.0)
     return float(np.mean(mu))
+
+
+def mu_app_le(flux, first, prof_x, ny, nz, rho0, tau):
+    """Relative apparent viscosity of the plane-Couette viscometer (Sec. IV,
+    Eq. 23): mu_app = Delta p_LE,z / (l_y l_z gammadot), with Delta p_LE,z the
+    mean of the recorded per-step momentum transfers flux[first:] and
+    gammadot the slope of a linear fit of the plane-averaged velocity profile
+    v_z(x) over the central half of the planes, x in [nx/4, 3 nx/4); divided
+    by the plasma's dynamic viscosity rho0 nu, nu = (2 tau - 1)/6."""
+    prof_x = np.asarray(prof_x, dtype=np.float64)
+    nx = len(prof_x)
+    xs = np.arange(nx // 4, 3 * nx // 4)
+    gd = np.polyfit(xs.astype(np.float64), prof_x[xs], 1)[0]
+    dp = float(np.mean(np.asarray(flux, dtype=np.float64)[first:]))
+    return dp / (ny * nz * gd) / (rho0 * (2.0 * tau - 1.0) / 6.0)
 
 
 def mu_rel_slit(ubar, g, tau, ny, first):

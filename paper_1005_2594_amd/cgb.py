@@ -31,7 +31,7 @@ class CgbParams(C.Structure):
         ("sig_perp", C.c_double), ("sig_par", C.c_double), ("sig_w", C.c_double),
         ("eps", C.c_double), ("eps_w", C.c_double),
         ("r_cut", C.c_double), ("rho_p", C.c_double),
-        ("precision", C.c_int32), ("pmx_scale", C.c_double),
+        ("precision", C.c_int32), ("pmx_scale", C.c_double), ("le_u", C.c_double),
     ]
 
 
@@ -89,6 +89,10 @@ def lib():
     L.cgb_get_pairs.argtypes = [VP, VP, C.c_int64, C.POINTER(C.c_int64)]
     L.cgb_get_observables.argtypes = [VP, VP]
     L.cgb_get_profile_z.argtypes = [VP, VP]
+    L.cgb_get_profile.argtypes = [VP, C.c_int32, VP]
+    L.cgb_get_le_flux.argtypes = [VP, VP, C.c_int32, C.POINTER(C.c_int32)]
+    L.cgb_mu_app_le.argtypes = [VP, C.c_int32, C.c_int32, VP, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                C.c_double, C.POINTER(C.c_double)]
     L.cgb_profile.argtypes = [VP, C.c_int]
     L.cgb_set_concurrency.argtypes = [VP, C.c_int]
     L.cgb_kernel_times.argtypes = [VP, VP, VP, VP, C.c_int32, C.POINTER(C.c_int32)]
@@ -310,6 +314,21 @@ class Sim:
         self._check(lib().cgb_get_profile_z(self.h, _ptr(p)))
         return p
 
+    def plane_profile(self, axis):
+        """Mean mixture z velocity per plane normal to axis (0: x, 1: y, 2: z)."""
+        n = (self.nx, self.ny, self.nz)[axis]
+        p = np.empty(n)
+        self._check(lib().cgb_get_profile(self.h, int(axis), _ptr(p)))
+        return p
+
+    def le_flux(self):
+        """Recorded Delta p_LE,z per step (viscometer lattices)."""
+        n = C.c_int32()
+        self._check(lib().cgb_get_le_flux(self.h, None, 0, C.byref(n)))
+        out = np.empty(max(n.value, 1))
+        self._check(lib().cgb_get_le_flux(self.h, _ptr(out), n.value, C.byref(n)))
+        return out[: n.value]
+
     # -- launch shape of the fused LB kernel
     def set_tiles(self, bx, by, tz):
         self._check(lib().cgb_set_tiles(self.h, int(bx), int(by), int(tz)))
@@ -444,6 +463,17 @@ def mu_rel_kolmogorov(A, f0, rho0, ny, first):
     rc = lib().cgb_mu_rel_kolmogorov(_ptr(A), len(A), int(first), float(f0), float(rho0), int(ny), C.byref(mu))
     if rc:
         raise CgbError(rc, "cgb_mu_rel_kolmogorov")
+    return mu.value
+
+
+def mu_app_le(flux, first, prof_x, ny, nz, rho0, tau):
+    f = np.ascontiguousarray(flux, dtype=np.float64)
+    px = np.ascontiguousarray(prof_x, dtype=np.float64)
+    mu = C.c_double()
+    rc = lib().cgb_mu_app_le(_ptr(f), len(f), int(first), _ptr(px), len(px), int(ny), int(nz), float(rho0),
+                             float(tau), C.byref(mu))
+    if rc:
+        raise CgbError(rc, "cgb_mu_app_le")
     return mu.value
 
 

@@ -42,6 +42,7 @@ constexpr int ST_UNSTABLE = 1;
 constexpr int ST_TRANS_OVERFLOW = 2;
 constexpr int ST_PAIR_OVERFLOW = 4;
 constexpr int ST_LIST_OVERFLOW = 8;
+constexpr int ST_LE_SEAM = 16;  // a cell covers a node of a sheared plane of the viscometer
 
 constexpr int TSEG = 64;  // segments of the transition list
 
@@ -133,6 +134,12 @@ struct DevArgs {
     int track_cap;
     double* track_part; // per-block partial sums [TRACK_BLOCKS][2]
     double* ysin;       // [ny] sin(2 pi y / ny)
+    // plane-Couette viscometer: Lees-Edwards seam of x (le_u = 0: off)
+    double le_u;
+    void* le_buf;       // [2][5][ny*nz] (compute precision) populations pulled across the
+                        // seam: side 0 into x = 0 along c_x = +1, side 1 into x = nx-1 along c_x = -1
+    double* le_part;    // per-block partial sums of Delta p_LE,z
+    double* le_rec;     // [track_cap] Delta p_LE,z per recorded step (with the track record)
     int tile[3];       // LB launch shape the kernels were configured for
     int* scan_tmp;     // block totals of the bin scan
     int nbody_blk;     // blocks of the integrate kernel (body_part has 3 per block)
@@ -410,7 +417,10 @@ hipError_t launch_decode(const DevArgs& a, double* d, hipStream_t st);
 hipError_t launch_equilibrium_fill(const DevArgs& a, const double* rho, const double* u, hipStream_t st);
 hipError_t launch_fields(const DevArgs& a, double* rho, double* u, hipStream_t st);
 hipError_t launch_observables(const DevArgs& a, double* partial, int nblk, hipStream_t st);
-hipError_t launch_profile_z(const DevArgs& a, double* prof, double* cnt, hipStream_t st);
+hipError_t launch_profile_z(const DevArgs& a, double* prof, double* cnt, hipStream_t st, int axis);
+hipError_t launch_le(const DevArgs& a, hipStream_t st);
+constexpr int LE_BLOCK = 256;
+static inline int le_blocks(const DevArgs& a) { return (2 * a.ny * a.nz + LE_BLOCK - 1) / LE_BLOCK; }
 constexpr int TRACK_BLOCKS = 1024;
 hipError_t launch_track(const DevArgs& a, hipStream_t st);
 hipError_t launch_pairs(const DevArgs& a, int* out, int* count, int cap, hipStream_t st);

@@ -135,9 +135,9 @@ __global__ void __launch_bounds__(256) observables_kernel(DevArgs a, double* par
         for (int k = 0; k < 8; k++) partial[8 * blockIdx.x + k] = red[k][0];
 }
 
-// mixture z velocity summed per y plane, and the node count per plane
+// mixture z velocity summed per plane normal to `axis`, and the node count per plane
 template <int P>
-__global__ void profile_kernel(DevArgs a, double* prof, double* cnt) {
+__global__ void profile_kernel(DevArgs a, double* prof, double* cnt, int axis) {
     using Cd = Codec<P>;
     using T = typename Cd::T;
     const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -164,8 +164,9 @@ __global__ void profile_kernel(DevArgs a, double* prof, double* cnt) {
         node_disp(a, x, y, z, k, d);
         uz = k[5] + (k[6] * d[1] - k[7] * d[0]);
     }
-    unsafeAtomicAdd(prof + y, uz);
-    unsafeAtomicAdd(cnt + y, 1.0);
+    const int pl = axis == 0 ? x : (axis == 1 ? y : z);
+    unsafeAtomicAdd(prof + pl, uz);
+    unsafeAtomicAdd(cnt + pl, 1.0);
 }
 
 #define CGB_DISPATCH(KERNEL, GRID, BLOCK, ...)                                                       \
@@ -291,8 +292,8 @@ hipError_t launch_observables(const DevArgs& a, double* partial, int nblk, hipSt
     CGB_DISPATCH(observables_kernel, dim3(nblk), dim3(256), a, partial);
     return hipGetLastError();
 }
-hipError_t launch_profile_z(const DevArgs& a, double* prof, double* cnt, hipStream_t st) {
-    CGB_DISPATCH(profile_kernel, site_grid(a), dim3(256), a, prof, cnt);
+hipError_t launch_profile_z(const DevArgs& a, double* prof, double* cnt, hipStream_t st, int axis) {
+    CGB_DISPATCH(profile_kernel, site_grid(a), dim3(256), a, prof, cnt, axis);
     return hipGetLastError();
 }
 

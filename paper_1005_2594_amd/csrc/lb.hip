@@ -155,6 +155,125 @@ __device__ inline void cell_node_links(const DevArgs& a, __amdgpu_buffer_rsrc_t 
     F[2] = m[2];
 }
 
+// ---------------------------------------------------------------- viscometer seam
+// Plane-Couette viscometer (Sec. IV): Lees-Edwards shear across the periodic
+// seam of x.  The image of the box beyond x = nx - 1 moves at +U e_z and is
+// shifted by Delta = U t along z (t: steps completed before this one); the
+// image below x = 0 moves at -U e_z, shifted by -Delta.  A population pulled
+// across the seam comes from the image: into x = 0 along c_x = +1 from the
+// node (nx - 1, y - c_y) at z - c_z + Delta, into x = nx - 1 along c_x = -1
+// from (0, y - c_y) at z - c_z - Delta, linearly interpolated between the two
+// nodes that bracket that z, and carried into this box's frame by the
+// Galilean shift n^eq(rho_s, u_s -/+ U e_z) - n^eq(rho_s, u_s) of the
+// interpolated source's moments.  The sheared planes never hold cell nodes
+// (cells are reflected before they reach them), so every source is fluid.
+// One thread per node of the two seam planes computes its five crossing
+// populations (FP64, stored in the compute precision) and its share of
+// Delta p_LE,z: the z momentum carried across the seam in -x, the mean of its
+// values before and after the shift (the frames of the two sides).
+
+// the directions with c_x = +1 (side 0) and c_x = -1 (side 1), k = 0..4
+__host__ __device__ constexpr int le_dir(int side, int k) {
+    constexpr int d0[5] = {1, 7, 9, 11, 13}, d1[5] = {2, 8, 10, 12, 14};
+    return side == 0 ? d0[k] : d1[k];
+}
+// the index k of direction r among its side's crossing directions
+__host__ __device__ constexpr int le_slot(int r) {
+    return (r == 1 || r == 2) ? 0 : ((r == 7 || r == 8) ? 1 : ((r == 9 || r == 10) ? 2 : ((r == 11 || r == 12) ? 3 : 4)));
+}
+
+template <int P>
+__global__ void __launch_bounds__(LE_BLOCK) le_kernel(DevArgs a) {
+    using Cd = Codec<P>;
+    using T = typename Cd::T;
+    using R = typename Cd::R;
+    __shared__ double red[LE_BLOCK];
+    const int nyz = a.ny * a.nz;
+    const int t = (int)(blockIdx.x * LE_BLOCK + threadIdx.x);
+    double flux = 0.0;
+    if (t < 2 * nyz) {
+        const int side = t / nyz, rem = t % nyz;
+        const int y = rem % a.ny, z = rem / a.ny;
+        const int xs = side == 0 ? a.nx - 1 : 0;
+        const double delta = fmod(a.le_u * (double)(*a.dstep), (double)a.nz);
+        const T* A = (const T*)a.A;
+        const T* RA = (const T*)a.rhoA;
+        R* out = (R*)a.le_buf;
+        for (int k = 0; k < 5; k++) {
+            const int r = le_dir(side, k);
+            const int ys = wrap(y - CY(r), a.ny);
+            double zf = fmod((double)(z - CZ(r)) + (side == 0 ? delta : -delta), (double)a.nz);
+            if (zf < 0.0) zf += a.nz;
+            const double zl = floor(zf), w = zf - zl;
+            const int z0 = wrap((int)zl, a.nz), z1 = wrap((int)zl + 1, a.nz);
+            const long long i0 = xs + (long long)a.nx * (ys + (long long)a.ny * z0);
+            const long long i1 = xs + (long long)a.nx * (ys + (long long)a.ny * z1);
+            const R D0 = rho_dec<P>(a, RA[i0]), D1 = rho_dec<P>(a, RA[i1]);
+            double drho = 0.0, j[3] = {0.0, 0.0, 0.0}, nr = 0.0;
+            for (int q = 0; q < 19; q++) {
+                const double v0 = (double)pop_dec<P>(a, A[q * a.pstride + i0], q, D0);
+                const double v1 = (double)pop_dec<P>(a, A[q * a.pstride + i1], q, D1);
+                const double n = (1.0 - w) * v0 + w * v1;
+                drho += n;
+                j[0] += CX(q) * n; j[1] += CY(q) * n; j[2] += CZ(q) * n;
+                if (q == r) nr = n;
+            }
+            const double rho = a.rho0 + drho;
+            const double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
+            const double du = side == 0 ? -a.le_u : a.le_u;
+            // n^eq(rho, u + du e_z) - n^eq(rho, u) of direction r (Eq. 5)
+            const double cu0 = CX(r) * u[0] + CY(r) * u[1] + CZ(r) * u[2];
+            const double cu1 = cu0 + CZ(r) * du;
+            const double us0 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            const double us1 = u[0] * u[0] + u[1] * u[1] + (u[2] + du) * (u[2] + du);
+            const double p0 = 3.0 * cu0 + 4.5 * cu0 * cu0 - 1.5 * us0 + 4.5 * cu0 * cu0 * cu0 - 4.5 * us0 * cu0;
+            const double p1 = 3.0 * cu1 + 4.5 * cu1 * cu1 - 1.5 * us1 + 4.5 * cu1 * cu1 * cu1 - 4.5 * us1 * cu1;
+            const double shifted = nr + WD(r) * rho * (p1 - p0);
+            out[(size_t)(side * 5 + k) * nyz + rem] = (R)shifted;
+            flux += -0.5 * CX(r) * CZ(r) * (nr + shifted);
+        }
+    }
+    red[threadIdx.x] = flux;
+    __syncthreads();
+    for (int off = LE_BLOCK / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.le_part[blockIdx.x] = red[0];
+}
+
+// Delta p_LE,z of the step into the record (at the track record's next slot;
+// the track kernels advance the count after this)
+__global__ void le_finish_kernel(DevArgs a, int nblk) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; b++) s += a.le_part[b];
+    const int n = *a.track_n;
+    if (a.le_rec && n < a.track_cap) a.le_rec[n] = s;
+}
+
+hipError_t launch_le(const DevArgs& a, hipStream_t st) {
+    if (a.le_u == 0.0) return hipSuccess;
+    const dim3 g((unsigned)le_blocks(a)), b(LE_BLOCK);
+    switch (a.precision) {
+        case CGB_P64: hipLaunchKernelGGL(le_kernel<CGB_P64>, g, b, 0, st, a); break;
+        case CGB_P32: hipLaunchKernelGGL(le_kernel<CGB_P32>, g, b, 0, st, a); break;
+        case CGB_PMX16: hipLaunchKernelGGL(le_kernel<CGB_PMX16>, g, b, 0, st, a); break;
+        case CGB_PMXBF16: hipLaunchKernelGGL(le_kernel<CGB_PMXBF16>, g, b, 0, st, a); break;
+        default: return hipErrorInvalidValue;  // the split codec is refused at creation
+    }
+    if (a.track) hipLaunchKernelGGL(le_finish_kernel, dim3(1), dim3(64), 0, st, a, le_blocks(a));
+    return hipGetLastError();
+}
+
+// the seam side of a node (0: x = 0, 1: x = nx - 1) when the viscometer is on, else -1
+__device__ inline int le_side(const DevArgs& a, int x) {
+    if (a.le_u == 0.0) return -1;
+    return x == 0 ? 0 : (x == a.nx - 1 ? 1 : -1);
+}
+// direction r crosses the seam into a node of side `side`
+__host__ __device__ constexpr bool le_crosses(int side, int r) { return side == 0 ? CX(r) == 1 : CX(r) == -1; }
+
 // general tau: populations are kept per direction
 template <int P, int TZ>
 __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
@@ -231,6 +350,15 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
             R Ds = Down;
             if constexpr (Cd::SPLIT) if (r > 0 && !((f >> r) & 1u)) Ds = rho_dec<P>(a, vs[r]);
             d[r] = pop_dec<P>(a, v[r], r, Ds);
+        }
+        // viscometer seam: the populations pulled across it come from the sheared image
+        const int side = le_side(a, x);
+        if (side >= 0) {
+            const R* L = (const R*)a.le_buf;
+            const size_t nyz = (size_t)a.ny * a.nz, q = (size_t)y + (size_t)a.ny * z;
+#pragma unroll
+            for (int r = 1; r < 19; r++)
+                if (le_crosses(side, r)) d[r] = L[(size_t)(side * 5 + le_slot(r)) * nyz + q];
         }
         if (links) {
             const M rho_x = (M)a.rho0 + (M)Down;
@@ -415,10 +543,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) l
         R Down = 0;  // the node's stored density deviation (for C; not needed by the split codec)
         R drho = 0, jx = 0, jy = 0, jz = 0;
         if constexpr (!Cd::SPLIT) Down = rho_dec<P>(a, bload<T>(rRA, links ? ES * i : OOB));
+        // viscometer seam: the populations pulled across it come from the
+        // sheared image (the split codec is refused with the viscometer)
+        const int side = le_side(a, x);
+        const R* L = (const R*)a.le_buf;
+        const size_t nyz = (size_t)a.ny * a.nz, q = (size_t)y + (size_t)a.ny * z;
 #pragma unroll
         for (int r = 0; r < 19; r++) {
             // split codec: the residual parts w_r h_r only
-            const R dv = pop_dec<P>(a, v[r], r, (R)0);
+            R dv = pop_dec<P>(a, v[r], r, (R)0);
+            if (r > 0 && side >= 0 && le_crosses(side, r)) dv = L[(size_t)(side * 5 + le_slot(r)) * nyz + q];
             drho += dv;
             if (CX(r)) jx += CX(r) * dv;
             if (CY(r)) jy += CY(r) * dv;

@@ -268,6 +268,8 @@ __global__ void __launch_bounds__(64 * CPW) claim_kernel(DevArgs a) {
                     const int z = wrap(lo[2] + z0 + j, a.nz);
                     const bool in = o != OWN_WALL && covers(a, cr, x, y, z);
                     if (in && o != p) atomicMin(a.cand + sj[j], p);
+                    // the viscometer's sheared planes must stay fluid
+                    if (in && a.le_u != 0.0 && (x == 0 || x == a.nx - 1)) atomicOr(a.status, ST_LE_SEAM);
                     const unsigned long long m = __ballot(in);
                     if (in) {
                         const int e = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -1408,6 +1410,14 @@ __device__ void integrate_one(const DevArgs& a, int p, double* bf) {
             else if (xn < 0.0) xn += Lb;
         }
         a.X[3 * p + c] = xn;
+    }
+    // viscometer (Sec. IV): a cell whose centre has come closer than sigma_perp
+    // to one of the sheared side planes (the node planes x = 0 and nx - 1)
+    // while moving towards it has its normal velocity negated
+    if (a.le_u != 0.0) {
+        const double xc = a.X[3 * p];
+        if ((xc < a.sig_perp && Vn[0] < 0.0) || ((double)(a.nx - 1) - xc < a.sig_perp && Vn[0] > 0.0))
+            a.V[3 * p] = -Vn[0];
     }
     bf[0] = a.Mdrive * gb[0]; bf[1] = a.Mdrive * gb[1]; bf[2] = a.Mdrive * gb[2];
     // quaternion: half-step predictor, then full step with the midpoint rate

@@ -162,6 +162,7 @@ static int check_status(cgb_sim* s) {
     HIPCHK(s, hipStreamSynchronize(s->st));
     if (st & ST_TRANS_OVERFLOW) FAIL(s, CGB_ENOMEM, "transition list overflow (capacity %d per segment)", s->a.trans_cap);
     if (st & ST_LIST_OVERFLOW) FAIL(s, CGB_ENOMEM, "covered-node list overflow (capacity %d per cell)", s->a.lcap);
+    if (st & ST_LE_SEAM) FAIL(s, CGB_EUNSTABLE, "a cell covers a node of a sheared plane of the viscometer");
     if (st & ST_UNSTABLE) FAIL(s, CGB_EUNSTABLE, "unstable at step %d: non-finite state, |u| > 0.4 or |V| >= 0.5", bad);
     return CGB_OK;
 }
@@ -279,6 +280,7 @@ static bool params_ok(const cgb_params* p) {
     // populations and boundary velocities are addressed with 32-bit byte offsets
     const double esz = p->precision == CGB_P64 ? 8.0 : (p->precision == CGB_P32 ? 4.0 : 2.0);
     const double msz = p->precision == CGB_P64 ? 8.0 : 4.0;
+    if (p->le_u != 0.0 && (p->wall_y || p->precision == CGB_PMX16S || !(fabs(p->le_u) < 0.5))) return false;
     const double pst = (double)(((long long)p->nx * p->ny * p->nz + 255) / 256 * 256);
     return !(19.0 * esz * pst >= 4294901760.0 || 4.0 * msz * pst >= 4294901760.0 || 32.0 * pst >= 4294901760.0);
 }
@@ -298,6 +300,7 @@ static int setup_host(cgb_sim* s, const cgb_params* p, const uint8_t* wall_mask,
                                    p->wall_v_top[0] != 0 || p->wall_v_top[1] != 0 || p->wall_v_top[2] != 0);
     a.tau = p->tau; a.rho0 = p->rho0;
     a.force_mode = p->force_mode; a.f0 = p->f0; a.force_on_particles = p->force_on_particles;
+    a.le_u = p->le_u;
     a.precision = p->precision;
     a.pmx_scale = (float)s->P.pmx_scale;
     a.pmx_inv = (float)(1.0 / s->P.pmx_scale);
@@ -404,6 +407,10 @@ static int alloc_state(cgb_sim* s, int cell_cap, int track_cap) {
     HIPCHK(s, dalloc(s, &a.scan_tmp, (size_t)((a.nbins + 4095) / 4096 + 1) * 4));
     HIPCHK(s, dalloc(s, &a.wall_start, (size_t)(a.nbins + 1) * 4));
     HIPCHK(s, dalloc(s, &a.wall_idx, (size_t)std::max(a.nsw, 1) * 4));
+    if (a.le_u != 0.0) {
+        HIPCHK(s, dalloc(s, &a.le_buf, 2 * 5 * (size_t)a.ny * a.nz * (s->P.precision == CGB_P64 ? 8 : 4)));
+        HIPCHK(s, dalloc(s, &a.le_part, (size_t)le_blocks(a) * 8));
+    }
     int rc = alloc_particles(s, std::max(cell_cap, 0));
     if (rc) return rc;
     if (cell_cap >= 0) {
@@ -413,6 +420,7 @@ static int alloc_state(cgb_sim* s, int cell_cap, int track_cap) {
         HIPCHK(s, dalloc(s, &s->pair_buf, (size_t)s->pair_cap * 2 * 4));
         s->track_max = std::max(track_cap, 0);
         HIPCHK(s, dalloc(s, &s->track_buf, 2 * (size_t)std::max(s->track_max, 1) * 8));
+        if (a.le_u != 0.0) HIPCHK(s, dalloc(s, &s->le_rec_buf, (size_t)std::max(s->track_max, 1) * 8));
         s->arena_state = s->arena_used;
     }
     return CGB_OK;
@@ -640,7 +648,9 @@ int cgb_step(cgb_sim* s, int32_t nsteps) {
         }
         HIPCHK(s, timed(s, K_TRANS, [&] {
             hipError_t e = launch_transitions(a, s->st, true);
-            return e != hipSuccess ? e : (a.lmom ? launch_lmom(a, s->st) : launch_usol(a, s->st, false));
+            if (e == hipSuccess) e = a.lmom ? launch_lmom(a, s->st) : launch_usol(a, s->st, false);
+            // the viscometer's seam: the populations pulled across it and Delta p_LE,z
+            return e != hipSuccess ? e : launch_le(a, s->st);
         }));
         // the LB kernel also stores the link momenta of every cell node; the
         // per-cell pass sums them
@@ -828,21 +838,56 @@ int cgb_get_observables(cgb_sim* s, double* out) {
     return CGB_OK;
 }
 
-int cgb_get_profile_z(cgb_sim* s, double* prof) {
-    if (!s || !prof) return CGB_EINVAL;
+int cgb_get_profile(cgb_sim* s, int32_t axis, double* prof) {
+    if (!s || !prof || axis < 0 || axis > 2) return CGB_EINVAL;
     int rc = cgb_sync(s);
     if (rc && rc != CGB_EUNSTABLE) return rc;
     DevArgs& a = s->a;
-    int rc2 = ensure_tmp(s, 2 * (size_t)a.ny * 8);
+    const int np = axis == 0 ? a.nx : (axis == 1 ? a.ny : a.nz);
+    int rc2 = ensure_tmp(s, 2 * (size_t)np * 8);
     if (rc2) return rc2;
     bind_buffers(s);
     HIPCHK(s, launch_kin(a, s->st));
-    HIPCHK(s, launch_fill_f64(s->tmp, 2 * (long long)a.ny, 0.0, s->st));
-    HIPCHK(s, launch_profile_z(a, s->tmp, s->tmp + a.ny, s->st));
-    std::vector<double> h(2 * (size_t)a.ny);
+    HIPCHK(s, launch_fill_f64(s->tmp, 2 * (long long)np, 0.0, s->st));
+    HIPCHK(s, launch_profile_z(a, s->tmp, s->tmp + np, s->st, axis));
+    std::vector<double> h(2 * (size_t)np);
     HIPCHK(s, hipMemcpyAsync(h.data(), s->tmp, h.size() * 8, hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
-    for (int y = 0; y < a.ny; y++) prof[y] = h[(size_t)a.ny + y] > 0 ? h[(size_t)y] / h[(size_t)a.ny + y] : 0.0;
+    for (int k = 0; k < np; k++) prof[k] = h[(size_t)np + k] > 0 ? h[(size_t)k] / h[(size_t)np + k] : 0.0;
+    return CGB_OK;
+}
+
+int cgb_get_profile_z(cgb_sim* s, double* prof) { return cgb_get_profile(s, 1, prof); }
+
+int cgb_get_le_flux(cgb_sim* s, double* out, int32_t cap, int32_t* n) {
+    if (!s || !n || cap < 0 || (cap > 0 && !out)) return CGB_EINVAL;
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    const DevArgs& a = s->a;
+    if (a.le_u == 0.0) FAIL(s, CGB_EINVAL, "not a viscometer lattice (le_u = 0)");
+    int cnt = 0;
+    HIPCHK(s, hipMemcpy(&cnt, a.track_n, 4, hipMemcpyDeviceToHost));
+    *n = std::min(cnt, a.track_cap);
+    const int m = std::min(*n, (int)cap);
+    if (m > 0 && a.le_rec) HIPCHK(s, hipMemcpy(out, a.le_rec, (size_t)m * 8, hipMemcpyDeviceToHost));
+    return CGB_OK;
+}
+
+int cgb_mu_app_le(const double* flux, int32_t n, int32_t first, const double* prof_x, int32_t nx, int32_t ny,
+                  int32_t nz, double rho0, double tau, double* mu_rel) {
+    if (!flux || !prof_x || !mu_rel || first < 0 || n <= first || nx < 4 || ny < 1 || nz < 1 || !(rho0 > 0) ||
+        !(tau > 0.5))
+        return CGB_EINVAL;
+    // least-squares slope of the profile over the central half of the planes
+    const int x0 = nx / 4, x1 = 3 * nx / 4;
+    double sx = 0, sy = 0, sxx = 0, sxy = 0;
+    const double m = x1 - x0;
+    for (int x = x0; x < x1; x++) { sx += x; sy += prof_x[x]; sxx += (double)x * x; sxy += x * prof_x[x]; }
+    const double gd = (m * sxy - sx * sy) / (m * sxx - sx * sx);
+    double dp = 0;
+    for (int t = first; t < n; t++) dp += flux[t];
+    dp /= (n - first);
+    const double nu = (2.0 * tau - 1.0) / 6.0;
+    *mu_rel = dp / ((double)ny * nz * gd) / (rho0 * nu);
     return CGB_OK;
 }
 
@@ -923,13 +968,17 @@ int cgb_track(cgb_sim* s, int32_t cap) {
     if (s->mem_mode != MEM_OWN) {
         if (cap > s->track_max) FAIL(s, CGB_EINVAL, "%d steps exceed the arena's record of %d", cap, s->track_max);
         a.track = cap > 0 ? s->track_buf : nullptr;
+        a.le_rec = cap > 0 ? s->le_rec_buf : nullptr;
         a.track_cap = cap;
     } else {
         dfree(s, a.track);
+        dfree(s, a.le_rec);
         a.track = nullptr;
+        a.le_rec = nullptr;
         a.track_cap = 0;
         if (cap > 0) {
             HIPCHK(s, dalloc(s, &a.track, 2 * (size_t)cap * 8));
+            if (a.le_u != 0.0) HIPCHK(s, dalloc(s, &a.le_rec, (size_t)cap * 8));
             a.track_cap = cap;
         }
     }
@@ -979,6 +1028,18 @@ int cgb_mu_rel_slit(const double* ubar, int32_t n, int32_t first, double g, doub
 int cgb_mu_rel(cgb_sim* s, int32_t first, double* mu) {
     if (!s || !mu) return CGB_EINVAL;
     const cgb_params& P = s->P;
+    if (P.le_u != 0.0) {
+        int n = 0;
+        int rc = cgb_get_le_flux(s, nullptr, 0, &n);
+        if (rc) return rc;
+        std::vector<double> fl((size_t)std::max(n, 1)), prof((size_t)P.nx);
+        rc = cgb_get_le_flux(s, fl.data(), n, &n);
+        if (!rc) rc = cgb_get_profile(s, 0, prof.data());
+        if (rc) return rc;
+        rc = cgb_mu_app_le(fl.data(), n, first, prof.data(), P.nx, P.ny, P.nz, P.rho0, P.tau, mu);
+        if (rc) FAIL(s, rc, "too few recorded steps (%d) after step %d", n, first);
+        return CGB_OK;
+    }
     const bool kolm = P.force_mode == 2 && !P.wall_y;
     const bool slit = P.force_mode == 1 && P.wall_y && P.g[0] == 0.0 && P.g[1] == 0.0 && P.g[2] != 0.0;
     if (!kolm && !slit) FAIL(s, CGB_EINVAL, "no apparent-viscosity estimator for this driving");

@@ -46,6 +46,7 @@ struct cgb_sim {
     int cell_cap = -1;
     int track_max = 0;
     double* track_buf = nullptr;
+    double* le_rec_buf = nullptr;
     double* tmp = nullptr;  // FP64 staging for uploads/downloads
     size_t tmp_bytes = 0;
     double* obs_partial = nullptr;

@@ -72,3 +72,14 @@ def test_query_sizes_without_a_device():
     assert cgb.query_sizes(p, None, 0, 0, precision="p64").arena_bytes > s0.arena_bytes
     with pytest.raises(cgb.CgbError):
         cgb.query_sizes(dict(p, tau=0.4), None, 0, 0)
+
+
+def test_viscometer_estimator_matches_the_oracle():
+    from oracle import oracle as O
+    from paper_1005_2594_amd import cgb
+    rng = np.random.default_rng(5)
+    flux = 1e-3 * (1 + 0.05 * rng.random(40))
+    prof = 0.01 * np.arange(32) / 32 + 1e-5 * rng.standard_normal(32)
+    for tau in (1.0, 0.8):
+        assert cgb.mu_app_le(flux, 10, prof, 8, 9, 1.0, tau) == pytest.approx(
+            O.mu_app_le(flux, 10, prof, 8, 9, 1.0, tau), rel=1e-12)
