@@ -248,6 +248,35 @@ def batch_leg(steps=2000, seed=4, prec="pmx16"):
     }
 
 
+def paper_scale_leg(steps=20, warmup=3, kernel_steps=5, prec="pmx16s"):
+    """The paper's largest system (Sec. IV: 1024^2 x 2048 sites, 4.1e6 cells)
+    on this one GPU, in the large-lattice layout (64-bit lane addresses, cell
+    nodes' momenta in their own unused population slots)."""
+    import torch
+    free, total = torch.cuda.mem_get_info()
+    if free < 250e9:
+        return {"skipped": f"needs about 250 GB of free device memory, {free / 1e9:.0f} GB free"}
+    cfg = synth.paper_scale_suspension()
+    t0 = time.perf_counter()
+    r = run_gpu(cfg, prec, steps, warmup, kernel_steps=kernel_steps)
+    sim = r["sim"]
+    nx, ny, nz = synth.PAPER_SCALE
+    ns = nx * ny * nz
+    out = {
+        "workload": cfg["name"] + f", Ht 0.05, tau=1, f0=1e-6; {prec}, large-lattice layout",
+        "sites": ns, "cells": len(cfg["X"]), "steps": steps,
+        "ms_per_step": round(r["seconds"] / steps * 1e3, 3),
+        "mlups": round(ns * steps / r["seconds"] / 1e6, 1),
+        "fluid_mlups": round(r["n_fluid"] * steps / r["seconds"] / 1e6, 1),
+        "device_bytes": int(sim.device_bytes()),
+        "device_total_bytes": int(total),
+        "kernel_ms_per_step": {k: round(t / max(c, 1), 4) for k, (t, c) in r["kernel_times"].items()},
+        "wall_seconds_with_setup": round(time.perf_counter() - t0, 1),
+    }
+    sim.close()
+    return out
+
+
 def cpu_baseline(cfg, steps):
     """The FP64 oracle on the same 256^3 workload for a few steps (host cores)."""
     from oracle import oracle as O
@@ -287,6 +316,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-paper-scale", action="store_true")
     ap.add_argument("--only", default=None, help="run only this precision (profiling)")
     ap.add_argument("--kernel-steps", type=int, default=50, help="steps of the per-kernel timing pass")
     ap.add_argument("--serial", action="store_true", help="every kernel in sequence in the timed region too")
@@ -385,6 +415,8 @@ def main():
         line["config"]["error_vs_oracle_64cube"] = error_report_64()
     if not args.no_batch:
         line["config"]["batch"] = batch_leg(steps=args.batch_steps)
+    if not args.no_paper_scale:
+        line["config"]["paper_scale"] = paper_scale_leg()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
     print(json.dumps(line), flush=True)

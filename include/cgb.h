@@ -85,6 +85,16 @@ typedef struct cgb_params {
                                    x = 0 and nx - 1.  0 = plain periodic x.
                                    Needs wall_y = 0 and a storage precision other
                                    than CGB_PMX16S (CGB_EINVAL otherwise)         */
+    int32_t mem_layout;         /* 0: chosen by size; 1: the large-lattice layout
+                                   at any size.  The large-lattice layout (used
+                                   when a population array passes 4 GB, e.g. the
+                                   paper's 1024^2 x 2048 system, Sec. IV) addresses
+                                   the lattice with 64-bit offsets and keeps each
+                                   cell node's momentum (Eq. 12) in the node's own
+                                   unused population slots instead of a separate
+                                   32-byte-per-site array; results are identical.
+                                   It needs tau = 1, le_u = 0 and LB sweeps of 16
+                                   nodes (cgb_set_tiles tz = 16; the default)      */
 } cgb_params;
 
 typedef struct cgb_sim cgb_sim;
@@ -154,6 +164,15 @@ int cgb_step(cgb_sim* s, int32_t nsteps);
 /* Waits for the stream; returns CGB_EUNSTABLE if any step tripped the
  * instability check (the first such step is in cgb_get_observables out[12]). */
 int cgb_sync(cgb_sim* s);
+
+/* The populations and owners of the sub-box lo + [0, ext) of the lattice (no
+ * wrap: lo + ext <= (nx, ny, nz)), for lattices too large for the
+ * whole-lattice getters: d (nullable) receives 19 * nb FP64 deviations,
+ * d[r * nb + k], 0 at non-fluid nodes; owner (nullable) nb owners (cell
+ * index, -1 fluid, -2 wall); k = x' + ext[0] * (y' + ext[1] * z'),
+ * nb = ext[0] * ext[1] * ext[2].  Host arrays; device staging of the box
+ * only.  CGB_EINVAL for a box outside the lattice. */
+int cgb_get_box(cgb_sim* s, const int32_t* lo, const int32_t* ext, double* d, int32_t* owner);
 
 /* Read-out (synchronises first; returns the current state and CGB_OK even
  * after an instability, which cgb_sync reports).  Sizes: d 19*nsites; rho nsites; u nsites*3

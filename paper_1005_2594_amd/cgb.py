@@ -31,7 +31,7 @@ class CgbParams(C.Structure):
         ("sig_perp", C.c_double), ("sig_par", C.c_double), ("sig_w", C.c_double),
         ("eps", C.c_double), ("eps_w", C.c_double),
         ("r_cut", C.c_double), ("rho_p", C.c_double),
-        ("precision", C.c_int32), ("pmx_scale", C.c_double), ("le_u", C.c_double),
+        ("precision", C.c_int32), ("pmx_scale", C.c_double), ("le_u", C.c_double), ("mem_layout", C.c_int32),
     ]
 
 
@@ -82,6 +82,7 @@ def lib():
     L.cgb_sync.argtypes = [VP]
     L.cgb_get_populations.argtypes = [VP, VP]
     L.cgb_get_fields.argtypes = [VP, VP, VP]
+    L.cgb_get_box.argtypes = [VP, VP, VP, VP, VP]
     L.cgb_get_particles.argtypes = [VP, VP, VP, VP, VP]
     L.cgb_get_forces.argtypes = [VP, VP, VP, VP, VP]
     L.cgb_get_owner.argtypes = [VP, VP]
@@ -268,6 +269,17 @@ class Sim:
         d = np.empty((19, self.ns))
         self._check(lib().cgb_get_populations(self.h, _ptr(d)))
         return d
+
+    def box(self, lo, ext):
+        """Populations (19, ext_z, ext_y, ext_x) and owners (ext_z, ext_y, ext_x)
+        of the sub-box lo + [0, ext) (``cgb_get_box``)."""
+        lo3 = np.ascontiguousarray(lo, dtype=np.int32)
+        ex3 = np.ascontiguousarray(ext, dtype=np.int32)
+        nb = int(np.prod(ex3.astype(np.int64)))
+        d = np.empty((19, nb)); own = np.empty(nb, dtype=np.int32)
+        self._check(lib().cgb_get_box(self.h, _ptr(lo3), _ptr(ex3), _ptr(d), _ptr(own)))
+        shp = (int(ex3[2]), int(ex3[1]), int(ex3[0]))
+        return d.reshape((19,) + shp), own.reshape(shp)
 
     def fields(self):
         rho = np.empty(self.ns); u = np.empty((self.ns, 3))

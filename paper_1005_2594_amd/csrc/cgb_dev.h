@@ -128,6 +128,15 @@ struct DevArgs {
     void* crec;        // [n] CellRec, in cell-list order (per-cell kernels)
     double* fnode;     // [ns][4] momentum the links of each cell node carried to
                        // its cell in the step (Eq. 12), written by the LB kernel
+                       // (not allocated with the large-lattice layout, see big)
+    // Large-lattice layout (lattices whose arrays pass 4 GB, or on request):
+    // the LB kernel addresses memory with 64-bit lane addresses instead of
+    // 32-bit buffer offsets, and a cell node's momentum is stored in the
+    // node's own output population slots (dead at non-fluid nodes) instead of
+    // fnode: slot k of the written populations holds bytes [k ES, (k+1) ES)
+    // of the three doubles (ES: the storage element size)
+    int big;
+    const void* zero;  // 256 zeroed bytes: the source of a 64-bit-addressed load a lane skips
     // per-step record of the mixture velocity (apparent viscosity)
     double* track;      // [track_cap][2]: sums of u_z sin(2 pi y/ny) and of u_z
     int* track_n;       // steps recorded (keeps counting past track_cap)
@@ -196,6 +205,33 @@ template <> __device__ inline void bstore<_Float16>(_Float16 v, __amdgpu_buffer_
 }
 template <> __device__ inline void bstore<uint16_t>(uint16_t v, __amdgpu_buffer_rsrc_t r, unsigned off) {
     __builtin_amdgcn_raw_buffer_store_b16(v, r, off, 0, 0);
+}
+
+// A cell node's momentum in its own output slots (large-lattice layout):
+// slot k holds bytes [k ES, (k + 1) ES) of the three doubles (m0, m1, m2).
+template <class T>
+__device__ inline T mom_piece(const double* m, int k) {
+    constexpr int ES = (int)sizeof(T), PER = 8 / ES;
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, m[k / PER]);
+    if constexpr (ES == 8) return __builtin_bit_cast(T, b);
+    else if constexpr (ES == 4) return __builtin_bit_cast(T, (unsigned)(b >> (32 * (k % PER))));
+    else return __builtin_bit_cast(T, (unsigned short)(b >> (16 * (k % PER))));
+}
+// component c of the momentum of cell node s from the slots of the
+// populations B (element size es bytes, direction planes ps elements apart)
+__device__ inline double mom_from_slots(const void* B, int es, long long ps, unsigned s, int c) {
+    unsigned long long b = 0;
+    if (es == 8) {
+        b = ((const unsigned long long*)B)[(size_t)c * ps + s];
+    } else if (es == 4) {
+        const unsigned* P = (const unsigned*)B;
+        b = (unsigned long long)P[(size_t)(2 * c) * ps + s] | ((unsigned long long)P[(size_t)(2 * c + 1) * ps + s] << 32);
+    } else {
+        const unsigned short* P = (const unsigned short*)B;
+#pragma unroll
+        for (int k = 0; k < 4; k++) b |= (unsigned long long)P[(size_t)(4 * c + k) * ps + s] << (16 * k);
+    }
+    return __builtin_bit_cast(double, b);
 }
 
 // Workgroup b of a launch of nb runs on XCD b mod 8 (the device deals
@@ -416,6 +452,7 @@ hipError_t launch_encode(const DevArgs& a, const double* d, hipStream_t st);
 hipError_t launch_decode(const DevArgs& a, double* d, hipStream_t st);
 hipError_t launch_equilibrium_fill(const DevArgs& a, const double* rho, const double* u, hipStream_t st);
 hipError_t launch_fields(const DevArgs& a, double* rho, double* u, hipStream_t st);
+hipError_t launch_decode_box(const DevArgs& a, const int* lo, const int* ext, double* d, int* own, hipStream_t st);
 hipError_t launch_observables(const DevArgs& a, double* partial, int nblk, hipStream_t st);
 hipError_t launch_profile_z(const DevArgs& a, double* prof, double* cnt, hipStream_t st, int axis);
 hipError_t launch_le(const DevArgs& a, hipStream_t st);

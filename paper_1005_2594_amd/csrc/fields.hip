@@ -38,8 +38,36 @@ __global__ void decode_kernel(DevArgs a, double* d) {
     const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (s >= a.ns) return;
     const T* A = (const T*)a.A;
+    // non-fluid nodes hold no populations (their slots are never read; with
+    // the large-lattice layout a cell node's slots carry its momentum)
+    if (a.owner[s] != OWN_FLUID) {
+        for (int r = 0; r < 19; r++) d[r * a.ns + s] = 0.0;
+        return;
+    }
     const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[s]);
     for (int r = 0; r < 19; r++) d[r * a.ns + s] = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
+}
+
+// the populations (FP64 deviations, 0 at non-fluid nodes) and the owners of
+// the box lo + [0, ext): out[r * nb + k] and own[k], k = x' + ext0 (y' + ext1 z')
+template <int P>
+__global__ void decode_box_kernel(DevArgs a, int lx, int ly, int lz, int ex, int ey, int ez, double* out, int* own) {
+    using Cd = Codec<P>;
+    using T = typename Cd::T;
+    const long long nb = (long long)ex * ey * ez;
+    const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (k >= nb) return;
+    const int x = lx + (int)(k % ex), y = ly + (int)((k / ex) % ey), z = lz + (int)(k / ((long long)ex * ey));
+    const long long s = x + (long long)a.nx * (y + (long long)a.ny * z);
+    const int o = a.owner[s];
+    own[k] = o;
+    if (o != OWN_FLUID) {
+        for (int r = 0; r < 19; r++) out[r * nb + k] = 0.0;
+        return;
+    }
+    const T* A = (const T*)a.A;
+    const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[s]);
+    for (int r = 0; r < 19; r++) out[r * nb + k] = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
 }
 
 // Eq. 5 at (rho, u) on every non-wall node, written as n^eq - w rho0
@@ -284,6 +312,13 @@ hipError_t launch_equilibrium_fill(const DevArgs& a, const double* rho, const do
     CGB_DISPATCH(equilibrium_kernel, site_grid(a), dim3(256), a, rho, u);
     return hipGetLastError();
 }
+hipError_t launch_decode_box(const DevArgs& a, const int* lo, const int* ext, double* d, int* own, hipStream_t st) {
+    const long long nb = (long long)ext[0] * ext[1] * ext[2];
+    const dim3 g((unsigned)((nb + 255) / 256)), b(256);
+    CGB_DISPATCH(decode_box_kernel, g, b, a, lo[0], lo[1], lo[2], ext[0], ext[1], ext[2], d, own);
+    return hipGetLastError();
+}
+
 hipError_t launch_fields(const DevArgs& a, double* rho, double* u, hipStream_t st) {
     CGB_DISPATCH(fields_kernel, site_grid(a), dim3(256), a, rho, u);
     return hipGetLastError();

@@ -423,31 +423,58 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
     }
 }
 
+// Memory access of the tau = 1 kernel.  Narrow: raw buffer accesses, one
+// scalar resource per array and a 32-bit byte offset per lane; a lane that
+// loads nothing passes an offset past the buffer and reads 0.  Wide (the
+// large-lattice layout, arrays past 4 GB): global accesses with a 64-bit
+// address per lane; a lane that loads nothing reads a zeroed word instead.
+// Element indices are 32-bit in the narrow form and 64-bit in the wide one.
+template <bool W> struct LbMem;
+template <> struct LbMem<false> {
+    using I = unsigned;
+    __amdgpu_buffer_rsrc_t r;
+    __device__ LbMem(const void* p, unsigned long long bytes, const void*) : r(make_rsrc(p, bytes)) {}
+    template <class T> __device__ T ld(I e, bool on) const { return bload<T>(r, on ? e * (I)sizeof(T) : OOB); }
+    template <class T> __device__ void st(T v, I e) const { bstore<T>(v, r, e * (I)sizeof(T)); }
+};
+template <> struct LbMem<true> {
+    using I = unsigned long long;
+    char* p;
+    const char* z;
+    __device__ LbMem(const void* q, unsigned long long, const void* zero)
+        : p((char*)const_cast<void*>(q)), z((const char*)zero) {}
+    template <class T> __device__ T ld(I e, bool on) const { return *(const T*)(on ? p + e * sizeof(T) : z); }
+    template <class T> __device__ void st(T v, I e) const { *(T*)(p + e * sizeof(T)) = v; }
+};
+
 // tau = 1 (the paper's operating point, Sec. IV): the post-collision state is
 // n^eq(rho, u) plus the forcing term, a function of the moments alone, so the
-// pulled populations are folded into rho and j as they arrive.
-template <int P, int TZ>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) lb_kernel_tau1(DevArgs a) {
+// pulled populations are folded into rho and j as they arrive.  BIG: the
+// large-lattice layout (64-bit lane addresses; a cell node's momentum goes to
+// its own output slots instead of the node-momentum array).
+template <int P, int TZ, bool BIG>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BIG ? 3 : 4))) lb_kernel_tau1(DevArgs a) {
     using Cd = Codec<P>;
     using T = typename Cd::T;
     using R = typename Cd::R;
     using M = R;
+    using Mem = LbMem<BIG>;
+    using I = typename Mem::I;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z0 = blockIdx.z * TZ;
     const bool inb = (x < a.nx) && (y < a.ny);
-    const unsigned nx = (unsigned)a.nx;
-    const unsigned plane = (unsigned)a.nx * (unsigned)a.ny;
-    const unsigned ps = (unsigned)a.pstride;  // every buffer below is addressed with 32-bit byte offsets (checked at create)
-    constexpr unsigned ES = sizeof(T);
-    const auto rA = make_rsrc(a.A, 19ull * ps * ES);
-    const auto rB = make_rsrc(a.B, 19ull * ps * ES);
-    const auto rRA = make_rsrc(a.rhoA, (unsigned long long)ps * ES);
-    const auto rRB = make_rsrc(a.rhoB, (unsigned long long)ps * ES);
-    const auto rFl = make_rsrc(a.flags, (unsigned long long)a.ns * 4);
-    const auto rK = make_rsrc(a.lmom, 4ull * ps * sizeof(M));
+    const I nx = (I)a.nx;
+    const I plane = (I)a.nx * (I)a.ny;
+    const I ps = (I)a.pstride;  // narrow: every offset fits 32 bits (checked at create)
+    const Mem mA(a.A, 19ull * (unsigned long long)a.pstride * sizeof(T), a.zero);
+    const Mem mB(a.B, 19ull * (unsigned long long)a.pstride * sizeof(T), a.zero);
+    const Mem mRA(a.rhoA, (unsigned long long)a.pstride * sizeof(T), a.zero);
+    const Mem mRB(a.rhoB, (unsigned long long)a.pstride * sizeof(T), a.zero);
+    const Mem mFl(a.flags, (unsigned long long)a.ns * 4, a.zero);
+    const Mem mK(a.lmom, 4ull * (unsigned long long)a.pstride * sizeof(M), a.zero);
     const int oxs[3] = {x == a.nx - 1 ? -(a.nx - 1) : 1, 0, x == 0 ? a.nx - 1 : -1};
-    const int oys[3] = {y == a.ny - 1 ? -(int)((a.ny - 1) * nx) : (int)nx, 0, y == 0 ? (int)((a.ny - 1) * nx) : -(int)nx};
+    const int oys[3] = {y == a.ny - 1 ? -(int)((a.ny - 1) * a.nx) : a.nx, 0, y == 0 ? (int)((a.ny - 1) * a.nx) : -a.nx};
     // body force at this plane: constant, or f0 sin(2 pi y/ny) from the table
     const int yc = y < a.ny ? y : a.ny - 1;
     const R gx = a.force_mode == 1 ? (R)a.g[0] : (R)0;
@@ -455,18 +482,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) l
     const R gz = a.force_mode == 1 ? (R)a.g[2] : (a.force_mode == 2 ? (R)(a.f0 * a.ysin[yc]) : (R)0);
 
     // flags of the first node; each step prefetches the next node's flags
-    uint32_t fnext = (inb && z0 < a.nz) ? bload<uint32_t>(rFl, 4u * ((unsigned)x + nx * (unsigned)y + plane * (unsigned)z0)) : NONFLUID;
+    const bool f0on = inb && z0 < a.nz;
+    const uint32_t f0v = mFl.template ld<uint32_t>((I)x + nx * (I)y + plane * (I)z0, f0on);
+    uint32_t fnext = f0on ? f0v : NONFLUID;
 #pragma unroll 1
     for (int zz = 0; zz < TZ; zz++) {
         const int z = z0 + zz;
         if (z >= a.nz) break;
-        const unsigned i = (unsigned)x + nx * (unsigned)y + plane * (unsigned)z;
+        const I i = (I)x + nx * (I)y + plane * (I)z;
         const uint32_t f = fnext;
-        fnext = (inb && zz + 1 < TZ && z + 1 < a.nz) ? bload<uint32_t>(rFl, 4u * (i + plane)) : NONFLUID;
-        // outputs of the node; a non-fluid node stores zeros.  The stores
-        // below are shared by all lanes of the wave, so that each wave store
-        // writes its lines whole (stores issued separately by the fluid and
-        // non-fluid lanes would each write part of the same lines)
+        const bool fnon = inb && zz + 1 < TZ && z + 1 < a.nz;
+        const uint32_t fnv = mFl.template ld<uint32_t>(i + plane, fnon);
+        fnext = fnon ? fnv : NONFLUID;
+        // outputs of the node; a non-fluid node stores zeros (a cell node in
+        // the large-lattice layout its momentum).  The stores below are shared
+        // by all lanes of the wave, so that each wave store writes its lines
+        // whole (stores issued separately by the fluid and non-fluid lanes
+        // would each write part of the same lines)
         const int oz[3] = {z == a.nz - 1 ? -(int)((a.nz - 1) * plane) : (int)plane, 0,
                            z == 0 ? (int)((a.nz - 1) * plane) : -(int)plane};
         const bool fl = !(f & NONFLUID);
@@ -486,26 +518,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) l
 #pragma unroll
         for (int r = 0; r < 19; r++) {
             const bool bb = (f >> r) & 1u;
-            const unsigned pull = bb ? (unsigned)OPP(r) * ps + i
-                                     : (unsigned)r * ps + i + (unsigned)(ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1]);
-            unsigned off = fl ? ES * pull : OOB;
-            if (r > 0 && cn && !((f >> OPP(r)) & 1u))
-                off = ES * ((unsigned)OPP(r) * ps + i + (unsigned)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)]));
-            v[r] = bload<T>(rA, off);
+            I e = bb ? (I)OPP(r) * ps + i : (I)r * ps + i + (I)(ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1]);
+            bool on = fl;
+            if (r > 0 && cn && !((f >> OPP(r)) & 1u)) {
+                e = (I)OPP(r) * ps + i + (I)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)]);
+                on = true;
+            }
+            v[r] = mA.template ld<T>(e, on);
         }
         // fluid lanes: their link moments (the split codec's hold every fluid
         // node's density parts too, see below); cell lanes: planes 0-2 hold
         // the node's rigid-body velocity
         M km[4];
+        const bool kon = (fl && (links || Cd::SPLIT)) || cn;
 #pragma unroll
-        for (int c = 0; c < 4; c++)
-            km[c] = bload<M>(rK, ((fl && (links || Cd::SPLIT)) || cn) ? (unsigned)sizeof(M) * ((unsigned)c * ps + i) : OOB);
+        for (int c = 0; c < 4; c++) km[c] = mK.template ld<M>((I)c * ps + i, kon);
         // cell lanes: the densities of their links' fluid nodes
         T dn[19];
 #pragma unroll
         for (int r = 1; r < 19; r++)
-            dn[r] = bload<T>(rRA, (cn && !((f >> OPP(r)) & 1u))
-                                      ? ES * (i + (unsigned)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)])) : OOB);
+            dn[r] = mRA.template ld<T>(i + (I)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)]), cn && !((f >> OPP(r)) & 1u));
+        double m0 = 0, m1 = 0, m2 = 0;
         if (cn) {
             // the momentum the node's links carry to its cell (Eq. 12): the
             // neighbour x = s + c_r bounces n*_rbar(x) into direction r and the
@@ -514,7 +547,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) l
             // constant part and the solid links of Eqs. 13-14 cancel over the
             // closed surface of a node set); FP64 from the decoded values
             const double us[3] = {(double)km[0], (double)km[1], (double)km[2]};
-            double m0 = 0, m1 = 0, m2 = 0;
 #pragma unroll
             for (int r = 1; r < 19; r++) {
                 const bool lk = !((f >> OPP(r)) & 1u);
@@ -530,19 +562,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) l
                 if (CY(r)) m1 += CY(r) * mr;
                 if (CZ(r)) m2 += CZ(r) * mr;
             }
-            double* F = a.fnode + 4 * (size_t)i;
-            F[0] = m0;
-            F[1] = m1;
-            F[2] = m2;
+            if constexpr (!BIG) {
+                double* F = a.fnode + 4 * (size_t)i;
+                F[0] = m0;
+                F[1] = m1;
+                F[2] = m2;
+            }
         }
         T ob[19], orho;
 #pragma unroll
         for (int r = 0; r < 19; r++) ob[r] = Cd::enc((R)0, (R)1);
         orho = Cd::enc((R)0, (R)1);
+        if constexpr (BIG) {
+            if (cn) {
+                const double m[3] = {m0, m1, m2};
+#pragma unroll
+                for (int k = 0; k < 24 / (int)sizeof(T); k++) ob[k] = mom_piece<T>(m, k);
+            }
+        }
         if (fl) {
         R Down = 0;  // the node's stored density deviation (for C; not needed by the split codec)
         R drho = 0, jx = 0, jy = 0, jz = 0;
-        if constexpr (!Cd::SPLIT) Down = rho_dec<P>(a, bload<T>(rRA, links ? ES * i : OOB));
+        if constexpr (!Cd::SPLIT) Down = rho_dec<P>(a, mRA.template ld<T>(i, links != 0u));
         // viscometer seam: the populations pulled across it come from the
         // sheared image (the split codec is refused with the viscometer)
         const int side = le_side(a, x);
@@ -607,8 +648,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) l
         }
         if (inb) {
 #pragma unroll
-            for (int r = 0; r < 19; r++) bstore<T>(ob[r], rB, ES * ((unsigned)r * ps + i));
-            bstore<T>(orho, rRB, ES * i);
+            for (int r = 0; r < 19; r++) mB.template st<T>(ob[r], (I)r * ps + i);
+            mRB.template st<T>(orho, i);
         }
     }
 }
@@ -618,21 +659,28 @@ static hipError_t launch_lb_p(const DevArgs& a, LaunchCfg cfg, hipStream_t st) {
     dim3 blk(cfg.bx, cfg.by, 1);
     dim3 grd((a.nx + cfg.bx - 1) / cfg.bx, (a.ny + cfg.by - 1) / cfg.by, (a.nz + cfg.tz - 1) / cfg.tz);
     const bool t1 = a.tau == 1.0;
+    if (a.big) {
+        // the large-lattice layout: tau = 1 and 16-node sweeps only (checked
+        // when the handle is created and when tiles are set)
+        if (!t1 || cfg.tz != 16) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((lb_kernel_tau1<P, 16, true>), grd, blk, 0, st, a);
+        return hipGetLastError();
+    }
     switch (cfg.tz) {
         case 4:
-            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 4>), grd, blk, 0, st, a);
+            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 4, false>), grd, blk, 0, st, a);
             else hipLaunchKernelGGL((lb_kernel_tau<P, 4>), grd, blk, 0, st, a);
             break;
         case 8:
-            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 8>), grd, blk, 0, st, a);
+            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 8, false>), grd, blk, 0, st, a);
             else hipLaunchKernelGGL((lb_kernel_tau<P, 8>), grd, blk, 0, st, a);
             break;
         case 16:
-            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 16>), grd, blk, 0, st, a);
+            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 16, false>), grd, blk, 0, st, a);
             else hipLaunchKernelGGL((lb_kernel_tau<P, 16>), grd, blk, 0, st, a);
             break;
         case 32:
-            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 32>), grd, blk, 0, st, a);
+            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 32, false>), grd, blk, 0, st, a);
             else hipLaunchKernelGGL((lb_kernel_tau<P, 32>), grd, blk, 0, st, a);
             break;
         default: return hipErrorInvalidValue;

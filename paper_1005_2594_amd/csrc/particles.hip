@@ -365,8 +365,19 @@ __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
     for (int e = hl; e < cnt; e += 32) {
         const unsigned s = lst[e];
         const int o = a.owner[s];
-        const double2 m01 = *(const double2*)(a.fnode + 4 * (size_t)s);
-        const double m2 = a.fnode[4 * (size_t)s + 2];
+        double2 m01;
+        double m2;
+        if (a.big) {
+            // large-lattice layout: the LB kernel left the momentum in the
+            // node's own output slots
+            const int es = a.precision == CGB_P64 ? 8 : (a.precision == CGB_P32 ? 4 : 2);
+            m01.x = mom_from_slots(a.B, es, a.pstride, s, 0);
+            m01.y = mom_from_slots(a.B, es, a.pstride, s, 1);
+            m2 = mom_from_slots(a.B, es, a.pstride, s, 2);
+        } else {
+            m01 = *(const double2*)(a.fnode + 4 * (size_t)s);
+            m2 = a.fnode[4 * (size_t)s + 2];
+        }
         if (o != p) continue;
         double d[3];
         node_disp(a, (int)(s % nx), (int)((s / nx) % (unsigned)a.ny), (int)(s / plane), cr.X, d);

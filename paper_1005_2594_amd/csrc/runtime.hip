@@ -218,7 +218,7 @@ static LaunchCfg default_tiles(const DevArgs& a) {
     LaunchCfg c{a.nx >= 256 ? 256 : (a.nx >= 128 ? 128 : 64), a.nx >= 256 ? 1 : (a.nx >= 128 ? 2 : 4), 16};
     if (a.nx < 48) c = LaunchCfg{32, 8, 16};
     if (a.nx < 24) c = LaunchCfg{16, 16, 16};
-    if (a.nz < 32) c.tz = 8;
+    if (a.nz < 32 && !a.big) c.tz = 8;  // the large-lattice layout sweeps 16 nodes
     return c;
 }
 
@@ -272,17 +272,30 @@ struct HostInit {
     std::vector<int> wstart, widx;  // surface wall nodes per cell-list bin
 };
 
+// The narrow layout addresses the population, density, flag and link-moment
+// arrays with 32-bit byte offsets; lattices past that (or a request) take the
+// large-lattice layout (64-bit lane addresses, node momenta in the nodes' own
+// unused population slots)
+static bool big_layout(const cgb_params* p) {
+    if (p->mem_layout == 1) return true;
+    const double esz = p->precision == CGB_P64 ? 8.0 : (p->precision == CGB_P32 ? 4.0 : 2.0);
+    const double msz = p->precision == CGB_P64 ? 8.0 : 4.0;
+    const double pst = (double)(((long long)p->nx * p->ny * p->nz + 255) / 256 * 256);
+    return 19.0 * esz * pst >= 4294901760.0 || 4.0 * msz * pst >= 4294901760.0;
+}
+
 static bool params_ok(const cgb_params* p) {
     if (p->nx < 3 || p->ny < 3 || p->nz < 3 || !(p->tau > 0.5) || !(p->rho0 > 0) || p->precision < 0 ||
         p->force_on_particles < 0 || p->force_on_particles > 2 ||
         p->precision > CGB_PMX16S || !(p->R_perp > 0) || !(p->R_par > 0) || !(p->rho_p > 0) || !(p->r_cut > 0))
         return false;
-    // populations and boundary velocities are addressed with 32-bit byte offsets
-    const double esz = p->precision == CGB_P64 ? 8.0 : (p->precision == CGB_P32 ? 4.0 : 2.0);
-    const double msz = p->precision == CGB_P64 ? 8.0 : 4.0;
     if (p->le_u != 0.0 && (p->wall_y || p->precision == CGB_PMX16S || !(fabs(p->le_u) < 0.5))) return false;
-    const double pst = (double)(((long long)p->nx * p->ny * p->nz + 255) / 256 * 256);
-    return !(19.0 * esz * pst >= 4294901760.0 || 4.0 * msz * pst >= 4294901760.0 || 32.0 * pst >= 4294901760.0);
+    // site indices are 32-bit (signed in the transition records)
+    if ((long long)p->nx * p->ny * p->nz > (1ll << 31)) return false;
+    if (p->mem_layout < 0 || p->mem_layout > 1) return false;
+    // the large-lattice layout has the tau = 1 kernel only, without the viscometer
+    if (big_layout(p) && (p->tau != 1.0 || p->le_u != 0.0)) return false;
+    return true;
 }
 
 // parameters, constants and the host-side geometry (no device work)
@@ -301,6 +314,7 @@ static int setup_host(cgb_sim* s, const cgb_params* p, const uint8_t* wall_mask,
     a.tau = p->tau; a.rho0 = p->rho0;
     a.force_mode = p->force_mode; a.f0 = p->f0; a.force_on_particles = p->force_on_particles;
     a.le_u = p->le_u;
+    a.big = big_layout(p) ? 1 : 0;
     a.precision = p->precision;
     a.pmx_scale = (float)s->P.pmx_scale;
     a.pmx_inv = (float)(1.0 / s->P.pmx_scale);
@@ -319,14 +333,17 @@ static int setup_host(cgb_sim* s, const cgb_params* p, const uint8_t* wall_mask,
     s->esize = p->precision == CGB_P64 ? 8 : (p->precision == CGB_P32 ? 4 : 2);
     // owner map: walls from the mask and the wall planes
     hi.own.assign((size_t)a.ns, OWN_FLUID);
-    for (long long i = 0; i < a.ns; i++) {
-        const int y = (int)((i / a.nx) % a.ny);
-        bool w = wall_mask ? wall_mask[i] != 0 : false;
-        if (p->wall_y && (y == 0 || y == a.ny - 1)) w = true;
-        if (w) hi.own[(size_t)i] = OWN_WALL;
+    s->n_nonwall = (double)a.ns;
+    if (wall_mask || p->wall_y) {
+        for (long long i = 0; i < a.ns; i++) {
+            const int y = (int)((i / a.nx) % a.ny);
+            bool w = wall_mask ? wall_mask[i] != 0 : false;
+            if (p->wall_y && (y == 0 || y == a.ny - 1)) w = true;
+            if (w) hi.own[(size_t)i] = OWN_WALL;
+        }
+        s->n_nonwall = 0;
+        for (long long i = 0; i < a.ns; i++) s->n_nonwall += hi.own[(size_t)i] != OWN_WALL ? 1.0 : 0.0;
     }
-    s->n_nonwall = 0;
-    for (long long i = 0; i < a.ns; i++) s->n_nonwall += hi.own[(size_t)i] != OWN_WALL ? 1.0 : 0.0;
     hi.ysin.resize((size_t)a.ny);
     for (int y = 0; y < a.ny; y++) hi.ysin[(size_t)y] = sin(2.0 * M_PI * y / (double)a.ny);
     // cell-list geometry: bin edge >= max(cut-off, wall potential range)
@@ -341,9 +358,10 @@ static int setup_host(cgb_sim* s, const cgb_params* p, const uint8_t* wall_mask,
     if (nbins > (1LL << 30)) FAIL(s, CGB_EINVAL, "too many cell-list bins");
     a.nbins = (int)nbins;
     // surface wall nodes (wall nodes with a non-wall neighbour), binned
-    std::vector<std::vector<int>> per((size_t)nbins);
+    const bool any_wall = wall_mask || p->wall_y;
+    std::vector<std::vector<int>> per(any_wall ? (size_t)nbins : 0);
     long long nsw = 0;
-    for (long long i = 0; i < a.ns; i++) {
+    for (long long i = 0; any_wall && i < a.ns; i++) {
         if (hi.own[(size_t)i] != OWN_WALL) continue;
         const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / ((long long)a.nx * a.ny));
         bool surf = false;
@@ -366,7 +384,7 @@ static int setup_host(cgb_sim* s, const cgb_params* p, const uint8_t* wall_mask,
     hi.wstart.assign((size_t)nbins + 1, 0);
     hi.widx.clear();
     hi.widx.reserve((size_t)nsw);
-    for (long long b = 0; b < nbins; b++) {
+    for (long long b = 0; any_wall && b < nbins; b++) {
         hi.wstart[(size_t)b] = (int)hi.widx.size();
         for (int v : per[(size_t)b]) hi.widx.push_back(v);
     }
@@ -392,7 +410,9 @@ static int alloc_state(cgb_sim* s, int cell_cap, int track_cap) {
     else HIPCHK(s, dalloc(s, &a.usol, 3 * (size_t)a.pstride * msz));
     HIPCHK(s, dalloc(s, &a.flags, (size_t)a.ns * 4));
     HIPCHK(s, dalloc(s, &a.cand, (size_t)a.ns * 4));
-    HIPCHK(s, dalloc(s, &a.fnode, 32 * (size_t)a.ns));
+    if (!a.big) HIPCHK(s, dalloc(s, &a.fnode, 32 * (size_t)a.ns));
+    HIPCHK(s, dalloc(s, &s->zero_buf, 256));
+    a.zero = s->zero_buf;
     HIPCHK(s, dalloc(s, &a.ntrans, TSEG * 4));
     HIPCHK(s, dalloc(s, &a.status, 16));
     HIPCHK(s, dalloc(s, &a.bad_step, 16));
@@ -438,6 +458,7 @@ static int init_device(cgb_sim* s, const HostInit& hi) {
     if (!hi.widx.empty())
         HIPCHK(s, hipMemcpyAsync(a.wall_idx, hi.widx.data(), hi.widx.size() * 4, hipMemcpyHostToDevice, s->st));
     HIPCHK(s, launch_fill_i32(a.cand, a.ns, NO_CAND, s->st));
+    HIPCHK(s, launch_fill_i32((int*)s->zero_buf, 64, 0, s->st));
     HIPCHK(s, launch_fill_i32(a.status, 4, 0, s->st));
     HIPCHK(s, launch_fill_i32(a.bad_step, 4, 0x7fffffff, s->st));
     HIPCHK(s, launch_fill_i32(a.dstep, 1, -1, s->st));
@@ -591,8 +612,10 @@ int cgb_init_fluid(cgb_sim* s, const double* rho, const double* u) {
     if (!s) return CGB_EINVAL;
     DevArgs& a = s->a;
     const size_t nsb = (size_t)a.ns * 8;
-    int rc = ensure_tmp(s, 4 * nsb);
-    if (rc) return rc;
+    if (rho || u) {
+        int rc = ensure_tmp(s, 4 * nsb);
+        if (rc) return rc;
+    }
     double* drho = nullptr;
     double* du = nullptr;
     if (rho) { drho = s->tmp; HIPCHK(s, hipMemcpyAsync(drho, rho, nsb, hipMemcpyHostToDevice, s->st)); }
@@ -689,6 +712,28 @@ int cgb_get_populations(cgb_sim* s, double* d) {
     bind_buffers(s);
     HIPCHK(s, launch_decode(a, s->tmp, s->st));
     HIPCHK(s, hipMemcpyAsync(d, s->tmp, bytes, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return CGB_OK;
+}
+
+int cgb_get_box(cgb_sim* s, const int32_t* lo, const int32_t* ext, double* d, int32_t* owner) {
+    if (!s || !lo || !ext) return CGB_EINVAL;
+    DevArgs& a = s->a;
+    const int L[3] = {a.nx, a.ny, a.nz};
+    for (int c = 0; c < 3; c++)
+        if (lo[c] < 0 || ext[c] < 1 || (long long)lo[c] + ext[c] > L[c]) FAIL(s, CGB_EINVAL, "box outside the lattice");
+    int rc = cgb_sync(s);
+    if (rc && rc != CGB_EUNSTABLE) return rc;
+    const long long nb = (long long)ext[0] * ext[1] * ext[2];
+    const size_t bytes = 19 * (size_t)nb * 8 + (size_t)nb * 4;
+    int rc2 = ensure_tmp(s, bytes);
+    if (rc2) return rc2;
+    bind_buffers(s);
+    const int lo3[3] = {lo[0], lo[1], lo[2]}, ex3[3] = {ext[0], ext[1], ext[2]};
+    int* own = (int*)(s->tmp + 19 * nb);
+    HIPCHK(s, launch_decode_box(a, lo3, ex3, s->tmp, own, s->st));
+    if (d) HIPCHK(s, hipMemcpyAsync(d, s->tmp, 19 * (size_t)nb * 8, hipMemcpyDeviceToHost, s->st));
+    if (owner) HIPCHK(s, hipMemcpyAsync(owner, own, (size_t)nb * 4, hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     return CGB_OK;
 }
@@ -928,6 +973,7 @@ int cgb_set_tiles(cgb_sim* s, int32_t bx, int32_t by, int32_t tz) {
     if (!s) return CGB_EINVAL;
     if (bx < 1 || by < 1 || bx * by > 256 || (bx * by) % 64 != 0 || !(tz == 4 || tz == 8 || tz == 16 || tz == 32))
         FAIL(s, CGB_EINVAL, "tile %dx%dx%d: need bx*by a multiple of 64, at most 256, tz in {4,8,16,32}", bx, by, tz);
+    if (s->a.big && tz != 16) FAIL(s, CGB_EINVAL, "tile %dx%dx%d: the large-lattice layout sweeps 16 nodes (tz = 16)", bx, by, tz);
     HIPCHK(s, hipStreamSynchronize(s->st));
     set_tiles(s, LaunchCfg{bx, by, tz});
     return CGB_OK;

@@ -48,6 +48,7 @@ struct cgb_sim {
     double* track_buf = nullptr;
     double* le_rec_buf = nullptr;
     double* tmp = nullptr;  // FP64 staging for uploads/downloads
+    void* zero_buf = nullptr;  // 256 zeroed bytes (large-lattice layout)
     size_t tmp_bytes = 0;
     double* obs_partial = nullptr;
     int obs_nblk = 512;

@@ -160,3 +160,57 @@ def config4(seed=4, n_channels=64, w_range=(32, 96), lz_range=(64, 192)):
         q = random_quaternions(rng, N)
         chans.append(dict(params=p, X=X, q=q, hematocrit=Ht, g=g, width=W, length=Lz))
     return chans
+
+
+# The paper's largest system (Sec. IV): a quasi-homogeneous suspension of
+# 1024^2 x 2048 sites and 4.1e6 cells.  Built as 16 x 16 x 32 copies of one
+# periodic 64^3 tile of 500 cells (4,096,000 cells, Ht 0.05), so that a run of
+# the whole lattice can be checked against a run of the tile: positions on a
+# 2^-10 grid keep every copy's coordinates exact in FP64.
+PAPER_SCALE = (1024, 1024, 2048)
+PAPER_TILE = 64
+PAPER_TILE_CELLS = 500
+
+
+def paper_scale_tile(seed=5, f=1e-6):
+    """The 64^3 periodic tile: 500 cells (2.5, 1.0) placed by random
+    sequential addition with bounding spheres apart (no two cells share a
+    node, so no occupancy conflict depends on the cells' indices), positions
+    on a 2^-10 grid, uniform orientations, random translational and angular
+    momenta, constant body force f z on plasma and cells."""
+    n = PAPER_TILE
+    p = params(n, n, n, force_mode=1, g=(0.0, 0.0, f), rho_p=RHO_P_DENSE, force_on_particles=2)
+    rng = np.random.default_rng(seed)
+    X = rsa_positions(rng, PAPER_TILE_CELLS, (n, n, n), 2.0 * p["R_perp"] + 0.01)
+    X = np.floor(X * 1024.0) / 1024.0
+    q = random_quaternions(rng, PAPER_TILE_CELLS)
+    V = 2e-3 * rng.standard_normal((PAPER_TILE_CELLS, 3))
+    L = 0.1 * rng.standard_normal((PAPER_TILE_CELLS, 3))
+    return dict(params=p, X=X, q=q, V=V, L=L)
+
+
+def tile_copies(tile, reps):
+    """Cells of reps = (kx, ky, kz) copies of a periodic tile, copy-major
+    (cell i of copy (a, b, c) at index i + N (a + kx (b + ky c))), and the
+    parameters of the whole lattice."""
+    n = tile["params"]["nx"]
+    kx, ky, kz = reps
+    c, b, a = np.meshgrid(np.arange(kz), np.arange(ky), np.arange(kx), indexing="ij")
+    off = n * np.stack([a.ravel(), b.ravel(), c.ravel()], axis=1).astype(np.float64)
+    X = (off[:, None, :] + tile["X"][None, :, :]).reshape(-1, 3)
+    rep = lambda v: np.tile(v, (kx * ky * kz, 1))
+    p = dict(tile["params"], nx=n * kx, ny=n * ky, nz=n * kz)
+    return dict(params=p, X=X, q=rep(tile["q"]), V=rep(tile["V"]), L=rep(tile["L"]))
+
+
+def paper_scale_suspension(seed=6, f0=1e-6):
+    """The paper's largest system as a random suspension: 1024^2 x 2048
+    periodic, 4.1e6 cells (2.5, 1.0) at uniform positions and orientations
+    (overlaps allowed, Ht 0.05), f_z = f0 sin(2 pi y / ny)."""
+    nx, ny, nz = PAPER_SCALE
+    p = params(nx, ny, nz, force_mode=2, f0=f0, rho_p=RHO_P_DENSE, force_on_particles=2)
+    rng = np.random.default_rng(seed)
+    N = 4_100_000
+    X = uniform_positions(rng, N, (nx, ny, nz))
+    q = random_quaternions(rng, N)
+    return dict(params=p, X=X, q=q, name=f"kolmogorov {nx}x{ny}x{nz}, {N} cells")
