@@ -268,12 +268,14 @@ def paper_scale_leg(steps=20, warmup=3, kernel_steps=5, prec="pmx16s"):
         "ms_per_step": round(r["seconds"] / steps * 1e3, 3),
         "mlups": round(ns * steps / r["seconds"] / 1e6, 1),
         "fluid_mlups": round(r["n_fluid"] * steps / r["seconds"] / 1e6, 1),
-        "device_bytes": int(sim.device_bytes()),
+        "device_bytes": int(sim.device_bytes),
         "device_total_bytes": int(total),
         "kernel_ms_per_step": {k: round(t / max(c, 1), 4) for k, (t, c) in r["kernel_times"].items()},
         "wall_seconds_with_setup": round(time.perf_counter() - t0, 1),
     }
     sim.close()
+    print(f"# paper scale: {out['ms_per_step']:.2f} ms/step, {out['mlups']:.0f} MLUPS, "
+          f"{out['device_bytes'] / 1e9:.1f} GB", flush=True)
     return out
 
 

@@ -95,6 +95,12 @@ typedef struct cgb_params {
                                    32-byte-per-site array; results are identical.
                                    It needs tau = 1, le_u = 0 and LB sweeps of 16
                                    nodes (cgb_set_tiles tz = 16; the default)      */
+    int32_t force_zlo, force_zhi; /* force_mode 1 only: the constant body force
+                                   acts on the nodes with force_zlo <= z <
+                                   force_zhi (and on cells whose centre lies
+                                   there), e.g. the entrance region of the
+                                   bifurcation runs (Sec. IV); force_zhi <=
+                                   force_zlo: everywhere                          */
 } cgb_params;
 
 typedef struct cgb_sim cgb_sim;
@@ -173,6 +179,16 @@ int cgb_sync(cgb_sim* s);
  * nb = ext[0] * ext[1] * ext[2].  Host arrays; device staging of the box
  * only.  CGB_EINVAL for a box outside the lattice. */
 int cgb_get_box(cgb_sim* s, const int32_t* lo, const int32_t* ext, double* d, int32_t* owner);
+
+/* The mixture velocity on the sub-box lo + [0, ext) (bounds as cgb_get_box):
+ * u[3 k + c] (host array of 3 * nb doubles).  Fluid nodes: the velocity of
+ * the last collision, (sum n* c - g/2) / rho (Eq. 1 with the forcing);
+ * cell nodes: the rigid-body velocity V + Omega x (s - X) of their cell as
+ * the last bounce-back used it (Eq. 10); walls: 0.  Summed over a plane
+ * normal to an axis it gives the volumetric flow rate through that plane
+ * (Q of the vessel runs, Sec. IV), over part of a plane the flow rate of a
+ * branch. */
+int cgb_get_mixture_box(cgb_sim* s, const int32_t* lo, const int32_t* ext, double* u);
 
 /* Read-out (synchronises first; returns the current state and CGB_OK even
  * after an instability, which cgb_sync reports).  Sizes: d 19*nsites; rho nsites; u nsites*3

@@ -102,9 +102,14 @@ static void disp(const orc_sim* s, const double* node, const double* X, double* 
 }
 
 /* ---- external force field (Sec. IV: body force on plasma and cells) ---- */
-static void force_at(const orc_params* P, double y, double* g) {
+static void force_at(const orc_params* P, double y, double z, double* g) {
     g[0] = g[1] = g[2] = 0.0;
-    if (P->force_mode == 1) { g[0] = P->g[0]; g[1] = P->g[1]; g[2] = P->g[2]; }
+    /* a constant force may be confined to a slab of z (the entrance region
+     * of the bifurcation runs, Sec. IV) */
+    const int region = P->force_zhi > P->force_zlo;
+    if (P->force_mode == 1 && (!region || (z >= P->force_zlo && z < P->force_zhi))) {
+        g[0] = P->g[0]; g[1] = P->g[1]; g[2] = P->g[2];
+    }
     else if (P->force_mode == 2) { g[2] = P->f0 * sin(2.0 * M_PI * y / (double)P->ny); }
 }
 
@@ -842,7 +847,7 @@ static int one_step(orc_sim* s) {
                     }
                     d[r] = A[rb * ns + i] + C;
                 }
-                force_at(P, (double)y, g);
+                force_at(P, (double)y, (double)z, g);
                 double usq = collide(P, d, g, out);
                 if (!(usq <= 0.16)) unstable = 1;
                 for (int a = 0; a < 3; a++) bodyf[a] += g[a];
@@ -889,7 +894,7 @@ static int one_step(orc_sim* s) {
             continue;
         }
         double gb[3] = {0, 0, 0};
-        if (P->force_on_particles) force_at(P, s->X[3 * p + 1], gb);
+        if (P->force_on_particles) force_at(P, s->X[3 * p + 1], s->X[3 * p + 2], gb);
         /* C14: the body force acts on the cells too; mode 2 gives them the
          * force on the plasma they displace (rho0 times their volume), so
          * that a cell made heavier for the stability of the explicit coupling
@@ -968,7 +973,7 @@ int orc_mixture_sums(const orc_sim* s, double* out) {
                 jz += v * CV[r][2];
             }
             double g[3];
-            force_at(P, (double)y, g);
+            force_at(P, (double)y, (double)z, g);
             uz = (jz - 0.5 * g[2]) / (P->rho0 + drho);
         } else {
             double node[3] = {x, y, z}, d[3], w[3]; int k[3];
@@ -983,6 +988,34 @@ int orc_mixture_sums(const orc_sim* s, double* out) {
     out[0] = ssin; out[1] = sone; out[2] = cnt;
     return ORC_OK;
 }
+int orc_mixture_field(const orc_sim* s, double* u) {
+    const orc_params* P = &s->P;
+    for (int64_t i = 0; i < s->ns; i++) {
+        double* ui = u + 3 * i;
+        ui[0] = ui[1] = ui[2] = 0.0;
+        if (s->wall[i]) continue;
+        int x = (int)(i % P->nx), y = (int)((i / P->nx) % P->ny), z = (int)(i / ((int64_t)P->nx * P->ny));
+        int32_t o = s->owner[i];
+        if (o == -1) {
+            double drho = 0.0, j[3] = {0, 0, 0};
+            for (int r = 0; r < 19; r++) {
+                double v = s->dA[r * s->ns + i];
+                drho += v;
+                for (int a = 0; a < 3; a++) j[a] += v * CV[r][a];
+            }
+            double g[3];
+            force_at(P, (double)y, (double)z, g);
+            for (int a = 0; a < 3; a++) ui[a] = (j[a] - 0.5 * g[a]) / (P->rho0 + drho);
+        } else {
+            double node[3] = {x, y, z}, d[3], w[3]; int k[3];
+            disp(s, node, &s->Xl[3 * o], d, k);
+            cross(&s->Om[3 * o], d, w);
+            for (int a = 0; a < 3; a++) ui[a] = s->Vl[3 * o + a] + w[a];
+        }
+    }
+    return ORC_OK;
+}
+
 double orc_le_flux(const orc_sim* s) { return s->le_flux; }
 
 int orc_get_deviations(const orc_sim* s, double* d) {
@@ -1007,7 +1040,7 @@ int orc_get_fields(const orc_sim* s, double* rho, double* u) {
         }
         double rr = s->P.rho0 + drho;
         double g[3];
-        force_at(&s->P, (double)((i / s->P.nx) % s->P.ny), g);
+        force_at(&s->P, (double)((i / s->P.nx) % s->P.ny), (double)(i / ((int64_t)s->P.nx * s->P.ny)), g);
         if (rho) rho[i] = rr;
         if (u) for (int a = 0; a < 3; a++) u[3 * i + a] = (j[a] - 0.5 * g[a]) / rr;
     }

@@ -44,6 +44,11 @@ typedef struct orc_params {
                                    seam of x (the image beyond x = nx - 1 moves at
                                    +U e_z, shifted by U t); 0 = plain periodic x.
                                    Needs wall_y = 0.                               */
+    int32_t force_zlo, force_zhi; /* force_mode 1 only: the constant body force acts
+                                   on the nodes with force_zlo <= z < force_zhi (and
+                                   on cells whose centre lies there), e.g. an
+                                   entrance region (Sec. IV bifurcation runs);
+                                   force_zhi <= force_zlo: everywhere             */
 } orc_params;
 
 typedef struct orc_sim orc_sim;
@@ -87,6 +92,8 @@ int  orc_mass_props(const orc_sim* s, double* out /* M, I_par, I_perp */);
  * its cell as the last bounce-back used it): out[0] weighted by
  * sin(2 pi y/ny), out[1] unweighted, out[2] node count */
 int  orc_mixture_sums(const orc_sim* s, double* out /* 3 */);
+/* the same mixture velocity, all three components, at every site (0 at walls) */
+int  orc_mixture_field(const orc_sim* s, double* u /* nsites*3 */);
 
 /* Pure functions for pins */
 void orc_d3q19(int32_t* c /* 19*3 */, double* w /* 19 */, int32_t* opp /* 19 */);

@@ -45,6 +45,7 @@ class OrcParams(C.Structure):
         ("sig_perp", C.c_double), ("sig_par", C.c_double), ("sig_w", C.c_double),
         ("eps", C.c_double), ("eps_w", C.c_double),
         ("r_cut", C.c_double), ("rho_p", C.c_double), ("le_u", C.c_double),
+        ("force_zlo", C.c_int32), ("force_zhi", C.c_int32),
     ]
 
 
@@ -91,6 +92,7 @@ def lib():
         L.orc_get_observables.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_mass_props.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_mixture_sums.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_mixture_field.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_d3q19.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_equilibrium.argtypes = [C.c_double, C.c_void_p, C.c_void_p]
         L.orc_bp_pair.argtypes = [C.POINTER(OrcParams)] + [C.c_void_p] * 7
@@ -243,6 +245,14 @@ class Oracle:
         o = np.empty(3)
         lib().orc_mixture_sums(self.h, _ptr(o))
         return 2.0 * o[0] / o[2], o[1] / o[2]
+
+    def mixture_field(self):
+        """Mixture velocity (ns, 3) after the last step: fluid nodes the
+        velocity of the last collision, cell nodes the rigid-body velocity
+        the last bounce-back used, 0 at walls."""
+        u = np.empty((self.ns, 3))
+        lib().orc_mixture_field(self.h, _ptr(u))
+        return u
 
     def track(self, nsteps):
         """Steps nsteps times, recording mixture() after every step: (nsteps, 2)."""

@@ -32,6 +32,7 @@ class CgbParams(C.Structure):
         ("eps", C.c_double), ("eps_w", C.c_double),
         ("r_cut", C.c_double), ("rho_p", C.c_double),
         ("precision", C.c_int32), ("pmx_scale", C.c_double), ("le_u", C.c_double), ("mem_layout", C.c_int32),
+        ("force_zlo", C.c_int32), ("force_zhi", C.c_int32),
     ]
 
 
@@ -83,6 +84,7 @@ def lib():
     L.cgb_get_populations.argtypes = [VP, VP]
     L.cgb_get_fields.argtypes = [VP, VP, VP]
     L.cgb_get_box.argtypes = [VP, VP, VP, VP, VP]
+    L.cgb_get_mixture_box.argtypes = [VP, VP, VP, VP]
     L.cgb_get_particles.argtypes = [VP, VP, VP, VP, VP]
     L.cgb_get_forces.argtypes = [VP, VP, VP, VP, VP]
     L.cgb_get_owner.argtypes = [VP, VP]
@@ -280,6 +282,16 @@ class Sim:
         self._check(lib().cgb_get_box(self.h, _ptr(lo3), _ptr(ex3), _ptr(d), _ptr(own)))
         shp = (int(ex3[2]), int(ex3[1]), int(ex3[0]))
         return d.reshape((19,) + shp), own.reshape(shp)
+
+    def mixture_box(self, lo, ext):
+        """Mixture velocity (ext_z, ext_y, ext_x, 3) of the sub-box lo + [0, ext)
+        (``cgb_get_mixture_box``)."""
+        lo3 = np.ascontiguousarray(lo, dtype=np.int32)
+        ex3 = np.ascontiguousarray(ext, dtype=np.int32)
+        nb = int(np.prod(ex3.astype(np.int64)))
+        u = np.empty((nb, 3))
+        self._check(lib().cgb_get_mixture_box(self.h, _ptr(lo3), _ptr(ex3), _ptr(u)))
+        return u.reshape(int(ex3[2]), int(ex3[1]), int(ex3[0]), 3)
 
     def fields(self):
         rho = np.empty(self.ns); u = np.empty((self.ns, 3))

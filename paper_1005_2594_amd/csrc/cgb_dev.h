@@ -58,6 +58,7 @@ struct DevArgs {
     int force_mode;
     double g[3];
     double f0;
+    int fregion, fzlo, fzhi;  // force_mode 1 confined to fzlo <= z < fzhi (fregion = 1)
     int force_on_particles;
     // storage
     int precision;
@@ -386,9 +387,9 @@ __device__ inline bool inside_test(const DevArgs& a, const double* d, const doub
     return val < 1.0;
 }
 
-__device__ inline void body_force(const DevArgs& a, double y, double* g) {
+__device__ inline void body_force(const DevArgs& a, double y, double z, double* g) {
     g[0] = g[1] = g[2] = 0.0;
-    if (a.force_mode == 1) { g[0] = a.g[0]; g[1] = a.g[1]; g[2] = a.g[2]; }
+    if (a.force_mode == 1 && (!a.fregion || (z >= a.fzlo && z < a.fzhi))) { g[0] = a.g[0]; g[1] = a.g[1]; g[2] = a.g[2]; }
     else if (a.force_mode == 2) g[2] = a.f0 * sin(2.0 * M_PI * y / (double)a.ny);
 }
 
@@ -453,6 +454,7 @@ hipError_t launch_decode(const DevArgs& a, double* d, hipStream_t st);
 hipError_t launch_equilibrium_fill(const DevArgs& a, const double* rho, const double* u, hipStream_t st);
 hipError_t launch_fields(const DevArgs& a, double* rho, double* u, hipStream_t st);
 hipError_t launch_decode_box(const DevArgs& a, const int* lo, const int* ext, double* d, int* own, hipStream_t st);
+hipError_t launch_mixture_box(const DevArgs& a, const int* lo, const int* ext, double* u, hipStream_t st);
 hipError_t launch_observables(const DevArgs& a, double* partial, int nblk, hipStream_t st);
 hipError_t launch_profile_z(const DevArgs& a, double* prof, double* cnt, hipStream_t st, int axis);
 hipError_t launch_le(const DevArgs& a, hipStream_t st);

@@ -70,6 +70,43 @@ __global__ void decode_box_kernel(DevArgs a, int lx, int ly, int lz, int ex, int
     for (int r = 0; r < 19; r++) out[r * nb + k] = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
 }
 
+// the mixture velocity of the box lo + [0, ext): fluid nodes the velocity of
+// the last collision, (sum n c - g/2) / rho; cell nodes the rigid-body
+// velocity of their cell as the last bounce-back used it, V + Omega x (s - X);
+// walls 0.  u[3 k + c], k = x' + ext0 (y' + ext1 z')
+template <int P>
+__global__ void mixture_box_kernel(DevArgs a, int lx, int ly, int lz, int ex, int ey, int ez, double* u) {
+    using Cd = Codec<P>;
+    using T = typename Cd::T;
+    const long long nb = (long long)ex * ey * ez;
+    const long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (k >= nb) return;
+    const int x = lx + (int)(k % ex), y = ly + (int)((k / ex) % ey), z = lz + (int)(k / ((long long)ex * ey));
+    const long long s = x + (long long)a.nx * (y + (long long)a.ny * z);
+    const int o = a.owner[s];
+    double v[3] = {0.0, 0.0, 0.0};
+    if (o == OWN_FLUID) {
+        const T* A = (const T*)a.A;
+        const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[s]);
+        double drho = 0, j[3] = {0, 0, 0};
+        for (int r = 0; r < 19; r++) {
+            const double d = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
+            drho += d;
+            j[0] += d * CX(r); j[1] += d * CY(r); j[2] += d * CZ(r);
+        }
+        double g[3];
+        body_force(a, (double)y, (double)z, g);
+        for (int c = 0; c < 3; c++) v[c] = (j[c] - 0.5 * g[c]) / (a.rho0 + drho);
+    } else if (o >= 0) {
+        const double* kp = a.kin + 12 * (long long)o;
+        double d[3], w[3];
+        node_disp(a, x, y, z, kp, d);
+        cross3(kp + 6, d, w);
+        for (int c = 0; c < 3; c++) v[c] = kp[3 + c] + w[c];
+    }
+    for (int c = 0; c < 3; c++) u[3 * k + c] = v[c];
+}
+
 // Eq. 5 at (rho, u) on every non-wall node, written as n^eq - w rho0
 template <int P>
 __global__ void equilibrium_kernel(DevArgs a, const double* rho, const double* u) {
@@ -124,7 +161,7 @@ __global__ void fields_kernel(DevArgs a, double* rho, double* u) {
     }
     const double rr = a.rho0 + drho;
     double g[3];
-    body_force(a, (double)((s / a.nx) % a.ny), g);
+    body_force(a, (double)((s / a.nx) % a.ny), (double)(s / ((long long)a.nx * a.ny)), g);
     if (rho) rho[s] = rr;
     if (u) for (int c = 0; c < 3; c++) u[3 * s + c] = (j[c] - 0.5 * g[c]) / rr;
 }
@@ -149,7 +186,7 @@ __global__ void __launch_bounds__(256) observables_kernel(DevArgs a, double* par
         acc[0] += a.rho0 + drho;
         acc[4] += 1.0;
         double g[3];
-        body_force(a, (double)((s / a.nx) % a.ny), g);
+        body_force(a, (double)((s / a.nx) % a.ny), (double)(s / ((long long)a.nx * a.ny)), g);
         acc[5] += g[0]; acc[6] += g[1]; acc[7] += g[2];
     }
     for (int k = 0; k < 8; k++) red[k][threadIdx.x] = acc[k];
@@ -184,7 +221,7 @@ __global__ void profile_kernel(DevArgs a, double* prof, double* cnt, int axis) {
             jz += v * CZ(r);
         }
         double g[3];
-        body_force(a, (double)y, g);
+        body_force(a, (double)y, (double)z, g);
         uz = (jz - 0.5 * g[2]) / (a.rho0 + drho);
     } else {
         const double* k = a.kin + 12 * (long long)o;
@@ -237,7 +274,9 @@ __global__ void __launch_bounds__(256) track_kernel(DevArgs a) {
             for (int r = 5; r < 19; r++)
                 if (CZ(r)) jz += CZ(r) * (double)pop_dec<P>(a, B[r * a.pstride + s], r, Ds);
             const double drho = (double)Ds;
-            const double gz = a.force_mode == 1 ? a.g[2] : (a.force_mode == 2 ? a.f0 * a.ysin[y] : 0.0);
+            double g[3];
+            body_force(a, (double)y, (double)((unsigned)s / ((unsigned)a.nx * (unsigned)a.ny)), g);
+            const double gz = g[2];
             uz = (jz - 0.5 * gz) / (a.rho0 + drho);
         } else {
             // the rigid-body velocity of the node's cell
@@ -316,6 +355,13 @@ hipError_t launch_decode_box(const DevArgs& a, const int* lo, const int* ext, do
     const long long nb = (long long)ext[0] * ext[1] * ext[2];
     const dim3 g((unsigned)((nb + 255) / 256)), b(256);
     CGB_DISPATCH(decode_box_kernel, g, b, a, lo[0], lo[1], lo[2], ext[0], ext[1], ext[2], d, own);
+    return hipGetLastError();
+}
+
+hipError_t launch_mixture_box(const DevArgs& a, const int* lo, const int* ext, double* u, hipStream_t st) {
+    const long long nb = (long long)ext[0] * ext[1] * ext[2];
+    const dim3 g((unsigned)((nb + 255) / 256)), b(256);
+    CGB_DISPATCH(mixture_box_kernel, g, b, a, lo[0], lo[1], lo[2], ext[0], ext[1], ext[2], u);
     return hipGetLastError();
 }
 

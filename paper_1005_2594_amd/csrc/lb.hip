@@ -300,9 +300,9 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
     const int oy[3] = {y == a.ny - 1 ? -(int)((a.ny - 1) * nx) : (int)nx, 0, y == 0 ? (int)((a.ny - 1) * nx) : -(int)nx};
     // body force at this plane: constant, or f0 sin(2 pi y/ny) from the table
     const int yc = y < a.ny ? y : a.ny - 1;
-    const R gx = a.force_mode == 1 ? (R)a.g[0] : (R)0;
-    const R gy = a.force_mode == 1 ? (R)a.g[1] : (R)0;
-    const R gz = a.force_mode == 1 ? (R)a.g[2] : (a.force_mode == 2 ? (R)(a.f0 * a.ysin[yc]) : (R)0);
+    const R gx0 = a.force_mode == 1 ? (R)a.g[0] : (R)0;
+    const R gy0 = a.force_mode == 1 ? (R)a.g[1] : (R)0;
+    const R gz0 = a.force_mode == 1 ? (R)a.g[2] : (a.force_mode == 2 ? (R)(a.f0 * a.ysin[yc]) : (R)0);
     const R omega = (R)(1.0 / a.tau);
     const R pref = (R)(1.0 - 0.5 / a.tau);
 
@@ -310,6 +310,9 @@ __global__ void __launch_bounds__(256) lb_kernel_tau(DevArgs a) {
     for (int zz = 0; zz < TZ; zz++) {
         const int z = z0 + zz;
         if (z >= a.nz) break;
+        // a constant force confined to a slab of z acts there only (uniform over the step)
+        const bool fon = !a.fregion || (z >= a.fzlo && z < a.fzhi);
+        const R gx = fon ? gx0 : (R)0, gy = fon ? gy0 : (R)0, gz = fon ? gz0 : (R)0;
         const unsigned i = (unsigned)x + nx * (unsigned)y + plane * (unsigned)z;
         const uint32_t f = inb ? a.flags[i] : NONFLUID;
         // outputs of the node; a non-fluid node stores zeros.  The stores
@@ -477,9 +480,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BIG ? 
     const int oys[3] = {y == a.ny - 1 ? -(int)((a.ny - 1) * a.nx) : a.nx, 0, y == 0 ? (int)((a.ny - 1) * a.nx) : -a.nx};
     // body force at this plane: constant, or f0 sin(2 pi y/ny) from the table
     const int yc = y < a.ny ? y : a.ny - 1;
-    const R gx = a.force_mode == 1 ? (R)a.g[0] : (R)0;
-    const R gy = a.force_mode == 1 ? (R)a.g[1] : (R)0;
-    const R gz = a.force_mode == 1 ? (R)a.g[2] : (a.force_mode == 2 ? (R)(a.f0 * a.ysin[yc]) : (R)0);
+    const R gx0 = a.force_mode == 1 ? (R)a.g[0] : (R)0;
+    const R gy0 = a.force_mode == 1 ? (R)a.g[1] : (R)0;
+    const R gz0 = a.force_mode == 1 ? (R)a.g[2] : (a.force_mode == 2 ? (R)(a.f0 * a.ysin[yc]) : (R)0);
 
     // flags of the first node; each step prefetches the next node's flags
     const bool f0on = inb && z0 < a.nz;
@@ -489,6 +492,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BIG ? 
     for (int zz = 0; zz < TZ; zz++) {
         const int z = z0 + zz;
         if (z >= a.nz) break;
+        // a constant force confined to a slab of z acts there only (uniform over the step)
+        const bool fon = !a.fregion || (z >= a.fzlo && z < a.fzhi);
+        const R gx = fon ? gx0 : (R)0, gy = fon ? gy0 : (R)0, gz = fon ? gz0 : (R)0;
         const I i = (I)x + nx * (I)y + plane * (I)z;
         const uint32_t f = fnext;
         const bool fnon = inb && zz + 1 < TZ && z + 1 < a.nz;

@@ -1396,7 +1396,7 @@ __device__ void integrate_one(const DevArgs& a, int p, double* bf) {
     for (int c = 0; c < 3; c++) X[c] = a.X[3 * p + c];
     for (int c = 0; c < 4; c++) q[c] = a.q[4 * p + c];
     double gb[3] = {0, 0, 0};
-    if (a.force_on_particles) body_force(a, X[1], gb);
+    if (a.force_on_particles) body_force(a, X[1], X[2], gb);
     bool bad = false;
     double Lnew[3], Vn[3];
     for (int c = 0; c < 3; c++) {

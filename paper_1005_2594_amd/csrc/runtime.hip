@@ -313,6 +313,8 @@ static int setup_host(cgb_sim* s, const cgb_params* p, const uint8_t* wall_mask,
                                    p->wall_v_top[0] != 0 || p->wall_v_top[1] != 0 || p->wall_v_top[2] != 0);
     a.tau = p->tau; a.rho0 = p->rho0;
     a.force_mode = p->force_mode; a.f0 = p->f0; a.force_on_particles = p->force_on_particles;
+    a.fregion = (p->force_mode == 1 && p->force_zhi > p->force_zlo) ? 1 : 0;
+    a.fzlo = p->force_zlo; a.fzhi = p->force_zhi;
     a.le_u = p->le_u;
     a.big = big_layout(p) ? 1 : 0;
     a.precision = p->precision;
@@ -738,6 +740,25 @@ int cgb_get_box(cgb_sim* s, const int32_t* lo, const int32_t* ext, double* d, in
     return CGB_OK;
 }
 
+int cgb_get_mixture_box(cgb_sim* s, const int32_t* lo, const int32_t* ext, double* u) {
+    if (!s || !lo || !ext || !u) return CGB_EINVAL;
+    DevArgs& a = s->a;
+    const int L[3] = {a.nx, a.ny, a.nz};
+    for (int c = 0; c < 3; c++)
+        if (lo[c] < 0 || ext[c] < 1 || (long long)lo[c] + ext[c] > L[c]) FAIL(s, CGB_EINVAL, "box outside the lattice");
+    int rc = cgb_sync(s);
+    if (rc && rc != CGB_EUNSTABLE) return rc;
+    const long long nb = (long long)ext[0] * ext[1] * ext[2];
+    int rc2 = ensure_tmp(s, 3 * (size_t)nb * 8);
+    if (rc2) return rc2;
+    bind_buffers(s);
+    const int lo3[3] = {lo[0], lo[1], lo[2]}, ex3[3] = {ext[0], ext[1], ext[2]};
+    HIPCHK(s, launch_mixture_box(a, lo3, ex3, s->tmp, s->st));
+    HIPCHK(s, hipMemcpyAsync(u, s->tmp, 3 * (size_t)nb * 8, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    return CGB_OK;
+}
+
 int cgb_get_fields(cgb_sim* s, double* rho, double* u) {
     if (!s) return CGB_EINVAL;
     int rc = cgb_sync(s);
@@ -1087,7 +1108,8 @@ int cgb_mu_rel(cgb_sim* s, int32_t first, double* mu) {
         return CGB_OK;
     }
     const bool kolm = P.force_mode == 2 && !P.wall_y;
-    const bool slit = P.force_mode == 1 && P.wall_y && P.g[0] == 0.0 && P.g[1] == 0.0 && P.g[2] != 0.0;
+    const bool slit = P.force_mode == 1 && P.wall_y && P.g[0] == 0.0 && P.g[1] == 0.0 && P.g[2] != 0.0 &&
+                      !(P.force_zhi > P.force_zlo);
     if (!kolm && !slit) FAIL(s, CGB_EINVAL, "no apparent-viscosity estimator for this driving");
     // the Kolmogorov estimator's one-step map (decay (1 - cos k)/3, forcing
     // (5 + cos k)/6) is the exact map at tau = 1 only

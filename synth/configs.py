@@ -214,3 +214,100 @@ def paper_scale_suspension(seed=6, f0=1e-6):
     X = uniform_positions(rng, N, (nx, ny, nz))
     q = random_quaternions(rng, N)
     return dict(params=p, X=X, q=q, name=f"kolmogorov {nx}x{ny}x{nz}, {N} cells")
+
+
+# ---------------------------------------------------------------- vessels
+# Wall masks (1 = wall node) of the paper's vessel geometries (Sec. IV):
+# a straight cylinder, and a bifurcation of cylindrical capillaries whose
+# daughter branches rejoin before the periodic end, one of them with a
+# stenosis.  Layout [z][y][x], axis along z, periodic in z.
+def cylinder_mask(R, L):
+    """Cylinder of radius R about the box axis, box (2 ceil(R) + 3)^2 x L."""
+    n = 2 * int(math.ceil(R)) + 3
+    c = (n - 1) / 2.0
+    y, x = np.mgrid[0:n, 0:n]
+    wall2d = ((x - c) ** 2 + (y - c) ** 2) >= R * R
+    return np.broadcast_to(wall2d, (L, n, n)).astype(np.uint8).copy()
+
+
+def bifurcation_mask(Rp, Rd, D, L, stenosis=None):
+    """A parent tube of radius Rp along z splits into two daughter tubes of
+    radius Rd whose axes move apart to x offsets -D and +D and back, so that
+    the two branches rejoin before the periodic end.  Segments along z:
+    parent [0, L/4), opening [L/4, 3L/8), branches [3L/8, 5L/8), closing
+    [5L/8, 3L/4), parent [3L/4, L).  stenosis = (Rs, length): the +x branch
+    narrows to radius Rs over `length` nodes at the middle of the branch
+    segment.  The box is mirror symmetric in x (centre (nx - 1)/2)."""
+    nx = 2 * int(math.ceil(D + Rd)) + 3
+    ny = 2 * int(math.ceil(max(Rp, Rd))) + 3
+    cx, cy = (nx - 1) / 2.0, (ny - 1) / 2.0
+    y, x = np.mgrid[0:ny, 0:nx]
+    m = np.ones((L, ny, nx), dtype=np.uint8)
+    q = L / 8.0
+
+    def tube(tx, r):
+        return ((x - tx) ** 2 + (y - cy) ** 2) < r * r
+
+    for z in range(L):
+        if z < 2 * q or z >= 6 * q:
+            fluid = tube(cx, Rp)
+        else:
+            if z < 3 * q:
+                f = (z - 2 * q) / q
+            elif z < 5 * q:
+                f = 1.0
+            else:
+                f = (6 * q - 1 - z) / q
+            f = min(max(f, 0.0), 1.0)
+            r = Rp + (Rd - Rp) * f
+            rp = r
+            if stenosis is not None and abs(z - 4 * q) < stenosis[1] / 2.0:
+                rp = stenosis[0]
+            # the +x branch is the mirror image of a -x branch of radius rp,
+            # so that equal branches give an exactly mirror-symmetric mask
+            fluid = tube(cx - D * f, r) | tube(cx - D * f, rp)[:, ::-1]
+        m[z][fluid] = 0
+    return m
+
+
+def vessel_cells(mask, n, R_perp, seed, clear=1.0, min_dist=None):
+    """n cell centres placed by random sequential addition inside the non-wall
+    region, every node within R_perp + clear of a centre being non-wall, and
+    centres at least min_dist apart (default 2 R_perp + 0.01: no two cells
+    share a node); positions on a 2^-10 grid; uniform orientations."""
+    rng = np.random.default_rng(seed)
+    L, ny, nx = mask.shape
+    rr = R_perp + clear
+    k = int(math.ceil(rr))
+    off = np.array([(a, b, c) for a in range(-k, k + 1) for b in range(-k, k + 1) for c in range(-k, k + 1)
+                    if a * a + b * b + c * c <= rr * rr + 1e-9])
+    md = 2.0 * R_perp + 0.01 if min_dist is None else min_dist
+    X = []
+    tries = 0
+    while len(X) < n:
+        tries += 1
+        if tries > 200000:
+            raise RuntimeError("cell placement did not converge")
+        p = np.floor(rng.random(3) * np.array([nx, ny, L]) * 1024.0) / 1024.0
+        nodes = np.round(p).astype(int)[None, :] + off
+        zz = nodes[:, 2] % L
+        if (nodes[:, 0] < 0).any() or (nodes[:, 0] >= nx).any() or (nodes[:, 1] < 0).any() or (nodes[:, 1] >= ny).any():
+            continue
+        if mask[zz, nodes[:, 1], nodes[:, 0]].any():
+            continue
+        ok = True
+        for q in X:
+            d = p - q
+            d[2] -= L * np.round(d[2] / L)
+            if d @ d < md * md:
+                ok = False
+                break
+        if ok:
+            X.append(p)
+    return np.array(X), random_quaternions(rng, n)
+
+
+def vessel_params(mask, **kw):
+    """Parameters of a lattice holding the mask (walls from the mask only)."""
+    L, ny, nx = mask.shape
+    return params(nx, ny, L, **kw)
