@@ -101,6 +101,15 @@ typedef struct cgb_params {
                                    there), e.g. the entrance region of the
                                    bifurcation runs (Sec. IV); force_zhi <=
                                    force_zlo: everywhere                          */
+    int32_t indexed;            /* 1: the indexed layout for sparse geometries
+                                   (vessel networks, Sec. IV): populations,
+                                   densities, link moments and node momenta are
+                                   stored for the non-wall nodes only, reached
+                                   through a per-site index map; owner, flags
+                                   and claims stay per site.  Results are
+                                   identical to the dense layout.  Needs tau = 1,
+                                   le_u = 0, a lattice within the 32-bit layout
+                                   and LB sweeps of 16 nodes (tz = 16)            */
 } cgb_params;
 
 typedef struct cgb_sim cgb_sim;

@@ -32,7 +32,7 @@ class CgbParams(C.Structure):
         ("eps", C.c_double), ("eps_w", C.c_double),
         ("r_cut", C.c_double), ("rho_p", C.c_double),
         ("precision", C.c_int32), ("pmx_scale", C.c_double), ("le_u", C.c_double), ("mem_layout", C.c_int32),
-        ("force_zlo", C.c_int32), ("force_zhi", C.c_int32),
+        ("force_zlo", C.c_int32), ("force_zhi", C.c_int32), ("indexed", C.c_int32),
     ]
 
 

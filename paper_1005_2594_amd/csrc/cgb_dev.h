@@ -137,7 +137,12 @@ struct DevArgs {
     // fnode: slot k of the written populations holds bytes [k ES, (k+1) ES)
     // of the three doubles (ES: the storage element size)
     int big;
-    const void* zero;  // 256 zeroed bytes: the source of a 64-bit-addressed load a lane skips
+    const void* zero;
+    // Indexed layout (sparse geometries such as vessel networks): the
+    // populations, densities, link moments and node momenta are stored for
+    // the non-wall nodes only, in lattice order; cidx[s] is the storage index
+    // of site s (-1 at a wall).  Null: dense storage (index = site).
+    const int32_t* cidx;  // 256 zeroed bytes: the source of a 64-bit-addressed load a lane skips
     // per-step record of the mixture velocity (apparent viscosity)
     double* track;      // [track_cap][2]: sums of u_z sin(2 pi y/ny) and of u_z
     int* track_n;       // steps recorded (keeps counting past track_cap)
@@ -154,6 +159,9 @@ struct DevArgs {
     int* scan_tmp;     // block totals of the bin scan
     int nbody_blk;     // blocks of the integrate kernel (body_part has 3 per block)
 };
+
+// storage index of site s (see cidx); -1 at a wall of the indexed layout
+__device__ inline long long sidx(const DevArgs& a, long long s) { return a.cidx ? (long long)a.cidx[s] : s; }
 
 __host__ __device__ inline int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 

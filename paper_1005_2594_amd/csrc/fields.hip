@@ -12,6 +12,8 @@ __global__ void encode_kernel(DevArgs a, const double* d) {
     using R = typename Cd::R;
     const long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (s >= a.ns) return;
+    const long long c = sidx(a, s);
+    if (c < 0) return;  // a wall of the indexed layout holds nothing
     T* A = (T*)a.A;
     R Dq = 0;
     if constexpr (Cd::SPLIT) {
@@ -19,16 +21,16 @@ __global__ void encode_kernel(DevArgs a, const double* d) {
         double dr = 0;
         for (int r = 0; r < 19; r++) dr += d[r * a.ns + s];
         const T st = Cd::enc((R)dr, rho_enc_scale<P>(a));
-        ((T*)a.rhoA)[s] = st;
+        ((T*)a.rhoA)[c] = st;
         Dq = rho_dec<P>(a, st);
     }
     R rs = 0;
     for (int r = 0; r < 19; r++) {
         const T v = pop_enc<P>(a, (R)d[r * a.ns + s], r, Dq);
-        A[r * a.pstride + s] = v;
+        A[r * a.pstride + c] = v;
         rs += pop_dec<P>(a, v, r, Dq);
     }
-    if constexpr (!Cd::SPLIT) ((T*)a.rhoA)[s] = Cd::enc(rs, rho_enc_scale<P>(a));
+    if constexpr (!Cd::SPLIT) ((T*)a.rhoA)[c] = Cd::enc(rs, rho_enc_scale<P>(a));
 }
 
 template <int P>
@@ -44,8 +46,9 @@ __global__ void decode_kernel(DevArgs a, double* d) {
         for (int r = 0; r < 19; r++) d[r * a.ns + s] = 0.0;
         return;
     }
-    const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[s]);
-    for (int r = 0; r < 19; r++) d[r * a.ns + s] = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
+    const long long c = sidx(a, s);
+    const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[c]);
+    for (int r = 0; r < 19; r++) d[r * a.ns + s] = (double)pop_dec<P>(a, A[r * a.pstride + c], r, Ds);
 }
 
 // the populations (FP64 deviations, 0 at non-fluid nodes) and the owners of
@@ -66,8 +69,9 @@ __global__ void decode_box_kernel(DevArgs a, int lx, int ly, int lz, int ex, int
         return;
     }
     const T* A = (const T*)a.A;
-    const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[s]);
-    for (int r = 0; r < 19; r++) out[r * nb + k] = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
+    const long long c = sidx(a, s);
+    const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[c]);
+    for (int r = 0; r < 19; r++) out[r * nb + k] = (double)pop_dec<P>(a, A[r * a.pstride + c], r, Ds);
 }
 
 // the mixture velocity of the box lo + [0, ext): fluid nodes the velocity of
@@ -87,10 +91,11 @@ __global__ void mixture_box_kernel(DevArgs a, int lx, int ly, int lz, int ex, in
     double v[3] = {0.0, 0.0, 0.0};
     if (o == OWN_FLUID) {
         const T* A = (const T*)a.A;
-        const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[s]);
+        const long long c = sidx(a, s);
+        const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[c]);
         double drho = 0, j[3] = {0, 0, 0};
         for (int r = 0; r < 19; r++) {
-            const double d = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
+            const double d = (double)pop_dec<P>(a, A[r * a.pstride + c], r, Ds);
             drho += d;
             j[0] += d * CX(r); j[1] += d * CY(r); j[2] += d * CZ(r);
         }
@@ -117,6 +122,8 @@ __global__ void equilibrium_kernel(DevArgs a, const double* rho, const double* u
     if (s >= a.ns) return;
     T* A = (T*)a.A;
     const bool wall = a.owner[s] == OWN_WALL;
+    const long long c = sidx(a, s);
+    if (c < 0) return;  // a wall of the indexed layout holds nothing
     const double rr = rho ? rho[s] : a.rho0;
     const double ux = u ? u[3 * s] : 0.0, uy = u ? u[3 * s + 1] : 0.0, uz = u ? u[3 * s + 2] : 0.0;
     const double usq = ux * ux + uy * uy + uz * uz;
@@ -124,7 +131,7 @@ __global__ void equilibrium_kernel(DevArgs a, const double* rho, const double* u
     if constexpr (Cd::SPLIT) {
         // Eq. 5 conserves the density: the density deviation is rho - rho0
         const T st = Cd::enc(wall ? (R)0 : (R)(rr - a.rho0), rho_enc_scale<P>(a));
-        ((T*)a.rhoA)[s] = st;
+        ((T*)a.rhoA)[c] = st;
         Dq = rho_dec<P>(a, st);
     }
     R rs = 0;
@@ -133,10 +140,10 @@ __global__ void equilibrium_kernel(DevArgs a, const double* rho, const double* u
         const double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * usq + 4.5 * cu * cu * cu - 4.5 * usq * cu;
         const double eq = wall ? 0.0 : WD(r) * ((rr - a.rho0) + rr * poly);
         const T v = pop_enc<P>(a, (R)eq, r, Dq);
-        A[r * a.pstride + s] = v;
+        A[r * a.pstride + c] = v;
         rs += pop_dec<P>(a, v, r, Dq);
     }
-    if constexpr (!Cd::SPLIT) ((T*)a.rhoA)[s] = Cd::enc(rs, rho_enc_scale<P>(a));
+    if constexpr (!Cd::SPLIT) ((T*)a.rhoA)[c] = Cd::enc(rs, rho_enc_scale<P>(a));
 }
 
 // rho = rho0 + sum d, u = (sum d c - g/2) / rho on fluid nodes
@@ -152,10 +159,11 @@ __global__ void fields_kernel(DevArgs a, double* rho, double* u) {
         return;
     }
     const T* A = (const T*)a.A;
-    const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[s]);
+    const long long c = sidx(a, s);
+    const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[c]);
     double drho = 0, j[3] = {0, 0, 0};
     for (int r = 0; r < 19; r++) {
-        const double v = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
+        const double v = (double)pop_dec<P>(a, A[r * a.pstride + c], r, Ds);
         drho += v;
         j[0] += v * CX(r); j[1] += v * CY(r); j[2] += v * CZ(r);
     }
@@ -176,10 +184,11 @@ __global__ void __launch_bounds__(256) observables_kernel(DevArgs a, double* par
     const T* A = (const T*)a.A;
     for (long long s = blockIdx.x * (long long)blockDim.x + threadIdx.x; s < a.ns; s += (long long)gridDim.x * blockDim.x) {
         if (a.owner[s] != OWN_FLUID) continue;
-        const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[s]);
+        const long long c = sidx(a, s);
+        const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[c]);
         double drho = 0;
         for (int r = 0; r < 19; r++) {
-            const double v = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
+            const double v = (double)pop_dec<P>(a, A[r * a.pstride + c], r, Ds);
             drho += v;
             acc[1] += v * CX(r); acc[2] += v * CY(r); acc[3] += v * CZ(r);
         }
@@ -213,10 +222,11 @@ __global__ void profile_kernel(DevArgs a, double* prof, double* cnt, int axis) {
     double uz;
     if (o == OWN_FLUID) {
         const T* A = (const T*)a.A;
-        const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[s]);
+        const long long c = sidx(a, s);
+        const auto Ds = rho_dec<P>(a, ((const T*)a.rhoA)[c]);
         double drho = 0, jz = 0;
         for (int r = 0; r < 19; r++) {
-            const double v = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
+            const double v = (double)pop_dec<P>(a, A[r * a.pstride + c], r, Ds);
             drho += v;
             jz += v * CZ(r);
         }
@@ -269,10 +279,11 @@ __global__ void __launch_bounds__(256) track_kernel(DevArgs a) {
         double uz;
         if (o == OWN_FLUID) {
             double jz = 0.0;
-            const M Ds = rho_dec<P>(a, RB[s]);
+            const long long c = sidx(a, s);
+            const M Ds = rho_dec<P>(a, RB[c]);
 #pragma unroll
             for (int r = 5; r < 19; r++)
-                if (CZ(r)) jz += CZ(r) * (double)pop_dec<P>(a, B[r * a.pstride + s], r, Ds);
+                if (CZ(r)) jz += CZ(r) * (double)pop_dec<P>(a, B[r * a.pstride + c], r, Ds);
             const double drho = (double)Ds;
             double g[3];
             body_force(a, (double)y, (double)((unsigned)s / ((unsigned)a.nx * (unsigned)a.ny)), g);

@@ -452,15 +452,21 @@ template <> struct LbMem<true> {
 
 // tau = 1 (the paper's operating point, Sec. IV): the post-collision state is
 // n^eq(rho, u) plus the forcing term, a function of the moments alone, so the
-// pulled populations are folded into rho and j as they arrive.  BIG: the
-// large-lattice layout (64-bit lane addresses; a cell node's momentum goes to
-// its own output slots instead of the node-momentum array).
-template <int P, int TZ, bool BIG>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BIG ? 3 : 4))) lb_kernel_tau1(DevArgs a) {
+// pulled populations are folded into rho and j as they arrive.  LAY: the
+// storage layout.  LAY_DENSE: every site stored.  LAY_BIG, the large-lattice
+// layout: 64-bit lane addresses; a cell node's momentum goes to its own
+// output slots instead of the node-momentum array.  LAY_IDX, the indexed
+// layout of sparse geometries: only non-wall nodes are stored, each site's
+// storage index comes from the map cidx (one load per neighbour), walls
+// store nothing.
+constexpr int LAY_DENSE = 0, LAY_BIG = 1, LAY_IDX = 2;
+template <int P, int TZ, int LAY>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LAY == LAY_DENSE ? 4 : 3))) lb_kernel_tau1(DevArgs a) {
     using Cd = Codec<P>;
     using T = typename Cd::T;
     using R = typename Cd::R;
     using M = R;
+    constexpr bool BIG = LAY == LAY_BIG, IDX = LAY == LAY_IDX;
     using Mem = LbMem<BIG>;
     using I = typename Mem::I;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -476,6 +482,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BIG ? 
     const Mem mRB(a.rhoB, (unsigned long long)a.pstride * sizeof(T), a.zero);
     const Mem mFl(a.flags, (unsigned long long)a.ns * 4, a.zero);
     const Mem mK(a.lmom, 4ull * (unsigned long long)a.pstride * sizeof(M), a.zero);
+    const Mem mC(a.cidx, (unsigned long long)a.ns * 4, a.zero);
     const int oxs[3] = {x == a.nx - 1 ? -(a.nx - 1) : 1, 0, x == 0 ? a.nx - 1 : -1};
     const int oys[3] = {y == a.ny - 1 ? -(int)((a.ny - 1) * a.nx) : a.nx, 0, y == 0 ? (int)((a.ny - 1) * a.nx) : -a.nx};
     // body force at this plane: constant, or f0 sin(2 pi y/ny) from the table
@@ -520,15 +527,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BIG ? 
         // bounces its own n*_rbar(x) when the source is not fluid (Eq. 9); a
         // cell lane loads the population its link along c_r carries,
         // n*_rbar(s + c_r), when s + c_r is fluid (Eq. 12).
+        // indexed layout: the node's storage index (-1 at a wall or outside)
+        I ci = i;
+        int cw = 0;
+        if constexpr (IDX) {
+            const int cv = mC.template ld<int>(i, inb);
+            cw = inb ? cv : -1;
+            ci = (I)cw;
+        }
         T v[19];
+        int nbi[19];  // indexed layout: storage index of each cell-lane link's fluid node
 #pragma unroll
         for (int r = 0; r < 19; r++) {
             const bool bb = (f >> r) & 1u;
-            I e = bb ? (I)OPP(r) * ps + i : (I)r * ps + i + (I)(ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1]);
-            bool on = fl;
-            if (r > 0 && cn && !((f >> OPP(r)) & 1u)) {
-                e = (I)OPP(r) * ps + i + (I)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)]);
-                on = true;
+            const bool lnk = r > 0 && cn && !((f >> OPP(r)) & 1u);
+            I e;
+            bool on;
+            if constexpr (IDX) {
+                const int offp = ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1];
+                const int offc = ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)];
+                const bool pl = fl && !bb;
+                const int nb = mC.template ld<int>(i + (I)(lnk ? offc : offp), pl || lnk);
+                nbi[r] = nb;
+                e = lnk ? (I)OPP(r) * ps + (I)nb : (bb ? (I)OPP(r) * ps + ci : (I)r * ps + (I)nb);
+                on = lnk || fl;
+            } else {
+                e = bb ? (I)OPP(r) * ps + i : (I)r * ps + i + (I)(ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1]);
+                on = fl;
+                if (lnk) {
+                    e = (I)OPP(r) * ps + i + (I)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)]);
+                    on = true;
+                }
             }
             v[r] = mA.template ld<T>(e, on);
         }
@@ -538,12 +567,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BIG ? 
         M km[4];
         const bool kon = (fl && (links || Cd::SPLIT)) || cn;
 #pragma unroll
-        for (int c = 0; c < 4; c++) km[c] = mK.template ld<M>((I)c * ps + i, kon);
+        for (int c = 0; c < 4; c++) km[c] = mK.template ld<M>((I)c * ps + ci, kon);
         // cell lanes: the densities of their links' fluid nodes
         T dn[19];
 #pragma unroll
-        for (int r = 1; r < 19; r++)
-            dn[r] = mRA.template ld<T>(i + (I)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)]), cn && !((f >> OPP(r)) & 1u));
+        for (int r = 1; r < 19; r++) {
+            const bool lnk = cn && !((f >> OPP(r)) & 1u);
+            if constexpr (IDX) dn[r] = mRA.template ld<T>((I)nbi[r], lnk);
+            else dn[r] = mRA.template ld<T>(i + (I)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)]), lnk);
+        }
         double m0 = 0, m1 = 0, m2 = 0;
         if (cn) {
             // the momentum the node's links carry to its cell (Eq. 12): the
@@ -569,7 +601,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BIG ? 
                 if (CZ(r)) m2 += CZ(r) * mr;
             }
             if constexpr (!BIG) {
-                double* F = a.fnode + 4 * (size_t)i;
+                double* F = a.fnode + 4 * (size_t)ci;
                 F[0] = m0;
                 F[1] = m1;
                 F[2] = m2;
@@ -589,7 +621,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BIG ? 
         if (fl) {
         R Down = 0;  // the node's stored density deviation (for C; not needed by the split codec)
         R drho = 0, jx = 0, jy = 0, jz = 0;
-        if constexpr (!Cd::SPLIT) Down = rho_dec<P>(a, mRA.template ld<T>(i, links != 0u));
+        if constexpr (!Cd::SPLIT) Down = rho_dec<P>(a, mRA.template ld<T>(ci, links != 0u));
         // viscometer seam: the populations pulled across it come from the
         // sheared image (the split codec is refused with the viscometer)
         const int side = le_side(a, x);
@@ -652,10 +684,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BIG ? 
             atomicMin(a.bad_step, *a.dstep);
         }
         }
-        if (inb) {
+        if (inb && cw >= 0) {  // (walls of the indexed layout store nothing)
 #pragma unroll
-            for (int r = 0; r < 19; r++) mB.template st<T>(ob[r], (I)r * ps + i);
-            mRB.template st<T>(orho, i);
+            for (int r = 0; r < 19; r++) mB.template st<T>(ob[r], (I)r * ps + ci);
+            mRB.template st<T>(orho, ci);
         }
     }
 }
@@ -665,28 +697,29 @@ static hipError_t launch_lb_p(const DevArgs& a, LaunchCfg cfg, hipStream_t st) {
     dim3 blk(cfg.bx, cfg.by, 1);
     dim3 grd((a.nx + cfg.bx - 1) / cfg.bx, (a.ny + cfg.by - 1) / cfg.by, (a.nz + cfg.tz - 1) / cfg.tz);
     const bool t1 = a.tau == 1.0;
-    if (a.big) {
-        // the large-lattice layout: tau = 1 and 16-node sweeps only (checked
-        // when the handle is created and when tiles are set)
+    if (a.big || a.cidx) {
+        // the large-lattice and indexed layouts: tau = 1 and 16-node sweeps
+        // only (checked when the handle is created and when tiles are set)
         if (!t1 || cfg.tz != 16) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((lb_kernel_tau1<P, 16, true>), grd, blk, 0, st, a);
+        if (a.big) hipLaunchKernelGGL((lb_kernel_tau1<P, 16, LAY_BIG>), grd, blk, 0, st, a);
+        else hipLaunchKernelGGL((lb_kernel_tau1<P, 16, LAY_IDX>), grd, blk, 0, st, a);
         return hipGetLastError();
     }
     switch (cfg.tz) {
         case 4:
-            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 4, false>), grd, blk, 0, st, a);
+            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 4, LAY_DENSE>), grd, blk, 0, st, a);
             else hipLaunchKernelGGL((lb_kernel_tau<P, 4>), grd, blk, 0, st, a);
             break;
         case 8:
-            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 8, false>), grd, blk, 0, st, a);
+            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 8, LAY_DENSE>), grd, blk, 0, st, a);
             else hipLaunchKernelGGL((lb_kernel_tau<P, 8>), grd, blk, 0, st, a);
             break;
         case 16:
-            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 16, false>), grd, blk, 0, st, a);
+            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 16, LAY_DENSE>), grd, blk, 0, st, a);
             else hipLaunchKernelGGL((lb_kernel_tau<P, 16>), grd, blk, 0, st, a);
             break;
         case 32:
-            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 32, false>), grd, blk, 0, st, a);
+            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 32, LAY_DENSE>), grd, blk, 0, st, a);
             else hipLaunchKernelGGL((lb_kernel_tau<P, 32>), grd, blk, 0, st, a);
             break;
         default: return hipErrorInvalidValue;

@@ -113,8 +113,9 @@ __global__ void clear_cells_kernel(DevArgs a) {
     if (a.owner[s] < 0) return;
     a.owner[s] = OWN_FLUID;
     T* A = (T*)a.A;
-    for (int r = 0; r < 19; r++) A[r * a.pstride + s] = Cd::enc((R)0, enc_scale<P>(a, r));
-    ((T*)a.rhoA)[s] = Cd::enc((R)0, rho_enc_scale<P>(a));
+    const long long c = sidx(a, s);
+    for (int r = 0; r < 19; r++) A[r * a.pstride + c] = Cd::enc((R)0, enc_scale<P>(a, r));
+    ((T*)a.rhoA)[c] = Cd::enc((R)0, rho_enc_scale<P>(a));
 }
 
 hipError_t launch_clear_cells(const DevArgs& a, hipStream_t st) {
@@ -375,8 +376,9 @@ __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
             m01.y = mom_from_slots(a.B, es, a.pstride, s, 1);
             m2 = mom_from_slots(a.B, es, a.pstride, s, 2);
         } else {
-            m01 = *(const double2*)(a.fnode + 4 * (size_t)s);
-            m2 = a.fnode[4 * (size_t)s + 2];
+            const size_t c = (size_t)sidx(a, s);
+            m01 = *(const double2*)(a.fnode + 4 * c);
+            m2 = a.fnode[4 * c + 2];
         }
         if (o != p) continue;
         double d[3];
@@ -558,9 +560,12 @@ __device__ inline void lm_owners(const DevArgs& a, int x0, int y0, int z, int* o
     *o0 = a.owner[s0];
     *o1 = q1 < LmShape<TX>::NP ? a.owner[s1] : OWN_FLUID;
     if constexpr (NC == 4) {
+        // (walls of the indexed layout hold no density: 0, like the stored
+        // zeros of a wall in the dense layout)
         const unsigned short* D = (const unsigned short*)a.rhoA;
-        *d0 = D[s0];
-        *d1 = D[s1];
+        const long long c0 = sidx(a, s0), c1 = sidx(a, s1);
+        *d0 = c0 >= 0 ? D[c0] : 0u;
+        *d1 = c1 >= 0 ? D[c1] : 0u;
     }
 }
 
@@ -672,10 +677,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                 const M* P = U + (size_t)((zz + 1) & 3) * NC * S::NP + (ty + 1) * S::HX + (tx + 1);
                 k0 = P[0]; k1 = P[S::NP]; k2 = P[2 * S::NP]; k3 = (M)0;
             }
-            K[s] = k0;
-            K[ps + s] = k1;
-            K[2 * ps + s] = k2;
-            K[3 * ps + s] = k3;
+            const long long c = sidx(a, s);
+            if (c >= 0) {
+                K[c] = k0;
+                K[ps + c] = k1;
+                K[2 * ps + c] = k2;
+                K[3 * ps + c] = k3;
+            }
         }
     }
 }
@@ -788,6 +796,7 @@ __device__ void transition_one(const DevArgs& a, int t, bool book) {
     const int o = a.trans[3 * t + 1], nw = a.trans[3 * t + 2];
     const int x = (int)(s % a.nx), y = (int)((s / a.nx) % a.ny), z = (int)(s / ((long long)a.nx * a.ny));
     T* A = (T*)a.A;
+    const long long c = sidx(a, s);  // storage index (a transition never involves a wall)
     a.owner[s] = nw;
     const bool was_fluid = (o == OWN_FLUID), is_fluid = (nw == OWN_FLUID);
     if (was_fluid != is_fluid) {
@@ -802,9 +811,9 @@ __device__ void transition_one(const DevArgs& a, int t, bool book) {
         if (!book) return;
         // covered: the deleted fluid momentum goes to the cell
         double m[3] = {0, 0, 0};
-        const R Ds = rho_dec<P>(a, ((const T*)a.rhoA)[s]);
+        const R Ds = rho_dec<P>(a, ((const T*)a.rhoA)[c]);
         for (int r = 0; r < 19; r++) {
-            const double v = (double)pop_dec<P>(a, A[r * a.pstride + s], r, Ds);
+            const double v = (double)pop_dec<P>(a, A[r * a.pstride + c], r, Ds);
             m[0] += v * CX(r); m[1] += v * CY(r); m[2] += v * CZ(r);
         }
         double d[3], tq[3];
@@ -814,8 +823,8 @@ __device__ void transition_one(const DevArgs& a, int t, bool book) {
         for (int c = 0; c < 3; c++) { fx_add(F + 2 * c, m[c]); fx_add(F + 6 + 2 * c, tq[c]); }
     } else if (!was_fluid && is_fluid) {
         if (!book) {
-            for (int r = 0; r < 19; r++) A[r * a.pstride + s] = Cd::enc((R)0, enc_scale<P>(a, r));
-            ((T*)a.rhoA)[s] = Cd::enc((R)0, rho_enc_scale<P>(a));
+            for (int r = 0; r < 19; r++) A[r * a.pstride + c] = Cd::enc((R)0, enc_scale<P>(a, r));
+            ((T*)a.rhoA)[c] = Cd::enc((R)0, rho_enc_scale<P>(a));
             return;
         }
         // freed: fluid at rho0 with the rigid-body velocity of the cell
@@ -833,12 +842,12 @@ __device__ void transition_one(const DevArgs& a, int t, bool book) {
             const double eq = WD(r) * (0.0 + a.rho0 * poly);
             // split codec: the density deviation of the new fluid is 0
             const T stv = pop_enc<P>(a, (R)eq, r, (R)0);
-            A[r * a.pstride + s] = stv;
+            A[r * a.pstride + c] = stv;
             const R back = pop_dec<P>(a, stv, r, (R)0);
             rs += back;
             m[0] += (double)back * CX(r); m[1] += (double)back * CY(r); m[2] += (double)back * CZ(r);
         }
-        ((T*)a.rhoA)[s] = Cd::enc(Cd::SPLIT ? (R)0 : rs, rho_enc_scale<P>(a));
+        ((T*)a.rhoA)[c] = Cd::enc(Cd::SPLIT ? (R)0 : rs, rho_enc_scale<P>(a));
         double tq[3];
         cross3(d, m, tq);
         unsigned long long* F = a.FTt + 12 * (long long)o;

@@ -218,7 +218,7 @@ static LaunchCfg default_tiles(const DevArgs& a) {
     LaunchCfg c{a.nx >= 256 ? 256 : (a.nx >= 128 ? 128 : 64), a.nx >= 256 ? 1 : (a.nx >= 128 ? 2 : 4), 16};
     if (a.nx < 48) c = LaunchCfg{32, 8, 16};
     if (a.nx < 24) c = LaunchCfg{16, 16, 16};
-    if (a.nz < 32 && !a.big) c.tz = 8;  // the large-lattice layout sweeps 16 nodes
+    if (a.nz < 32 && !a.big && !a.cidx) c.tz = 8;  // the large-lattice and indexed layouts sweep 16 nodes
     return c;
 }
 
@@ -268,6 +268,7 @@ static int init_particle_buffers(cgb_sim* s) {
 // host-side state of a new handle that the device set-up uploads
 struct HostInit {
     std::vector<int32_t> own;   // owner map: walls and fluid
+    std::vector<int32_t> cidx;  // indexed layout: storage index of each site (-1 at walls)
     std::vector<double> ysin;   // sin(2 pi y / ny)
     std::vector<int> wstart, widx;  // surface wall nodes per cell-list bin
 };
@@ -295,6 +296,9 @@ static bool params_ok(const cgb_params* p) {
     if (p->mem_layout < 0 || p->mem_layout > 1) return false;
     // the large-lattice layout has the tau = 1 kernel only, without the viscometer
     if (big_layout(p) && (p->tau != 1.0 || p->le_u != 0.0)) return false;
+    // so has the indexed layout, within the 32-bit layout
+    if (p->indexed < 0 || p->indexed > 1) return false;
+    if (p->indexed && (p->tau != 1.0 || p->le_u != 0.0 || big_layout(p))) return false;
     return true;
 }
 
@@ -345,6 +349,15 @@ static int setup_host(cgb_sim* s, const cgb_params* p, const uint8_t* wall_mask,
         }
         s->n_nonwall = 0;
         for (long long i = 0; i < a.ns; i++) s->n_nonwall += hi.own[(size_t)i] != OWN_WALL ? 1.0 : 0.0;
+    }
+    if (p->indexed) {
+        // storage for the non-wall nodes only, in lattice order
+        hi.cidx.assign((size_t)a.ns, -1);
+        long long nc = 0;
+        for (long long i = 0; i < a.ns; i++)
+            if (hi.own[(size_t)i] != OWN_WALL) hi.cidx[(size_t)i] = (int32_t)nc++;
+        a.pstride = (std::max(nc, 1ll) + 255) / 256 * 256;
+        s->n_stored = nc;
     }
     hi.ysin.resize((size_t)a.ny);
     for (int y = 0; y < a.ny; y++) hi.ysin[(size_t)y] = sin(2.0 * M_PI * y / (double)a.ny);
@@ -412,7 +425,8 @@ static int alloc_state(cgb_sim* s, int cell_cap, int track_cap) {
     else HIPCHK(s, dalloc(s, &a.usol, 3 * (size_t)a.pstride * msz));
     HIPCHK(s, dalloc(s, &a.flags, (size_t)a.ns * 4));
     HIPCHK(s, dalloc(s, &a.cand, (size_t)a.ns * 4));
-    if (!a.big) HIPCHK(s, dalloc(s, &a.fnode, 32 * (size_t)a.ns));
+    if (!a.big) HIPCHK(s, dalloc(s, &a.fnode, 32 * (size_t)(s->P.indexed ? a.pstride : a.ns)));
+    if (s->P.indexed) HIPCHK(s, dalloc(s, (int32_t**)&a.cidx, (size_t)a.ns * 4));
     HIPCHK(s, dalloc(s, &s->zero_buf, 256));
     a.zero = s->zero_buf;
     HIPCHK(s, dalloc(s, &a.ntrans, TSEG * 4));
@@ -454,6 +468,8 @@ static int init_device(cgb_sim* s, const HostInit& hi) {
     const size_t msz = s->P.precision == CGB_P64 ? 8 : 4;
     if (a.lmom) HIPCHK(s, launch_fill_i32((int*)a.lmom, (long long)(4 * (size_t)a.pstride * msz / 4), 0, s->st));
     HIPCHK(s, hipMemcpyAsync(a.owner, hi.own.data(), (size_t)a.ns * 4, hipMemcpyHostToDevice, s->st));
+    if (a.cidx)
+        HIPCHK(s, hipMemcpyAsync(const_cast<int32_t*>(a.cidx), hi.cidx.data(), (size_t)a.ns * 4, hipMemcpyHostToDevice, s->st));
     if (a.usol) HIPCHK(s, launch_usol(a, s->st, true));
     HIPCHK(s, hipMemcpyAsync(a.ysin, hi.ysin.data(), (size_t)a.ny * 8, hipMemcpyHostToDevice, s->st));
     HIPCHK(s, hipMemcpyAsync(a.wall_start, hi.wstart.data(), hi.wstart.size() * 4, hipMemcpyHostToDevice, s->st));
@@ -994,7 +1010,8 @@ int cgb_set_tiles(cgb_sim* s, int32_t bx, int32_t by, int32_t tz) {
     if (!s) return CGB_EINVAL;
     if (bx < 1 || by < 1 || bx * by > 256 || (bx * by) % 64 != 0 || !(tz == 4 || tz == 8 || tz == 16 || tz == 32))
         FAIL(s, CGB_EINVAL, "tile %dx%dx%d: need bx*by a multiple of 64, at most 256, tz in {4,8,16,32}", bx, by, tz);
-    if (s->a.big && tz != 16) FAIL(s, CGB_EINVAL, "tile %dx%dx%d: the large-lattice layout sweeps 16 nodes (tz = 16)", bx, by, tz);
+    if ((s->a.big || s->a.cidx) && tz != 16)
+        FAIL(s, CGB_EINVAL, "tile %dx%dx%d: the large-lattice and indexed layouts sweep 16 nodes (tz = 16)", bx, by, tz);
     HIPCHK(s, hipStreamSynchronize(s->st));
     set_tiles(s, LaunchCfg{bx, by, tz});
     return CGB_OK;

@@ -49,6 +49,7 @@ struct cgb_sim {
     double* le_rec_buf = nullptr;
     double* tmp = nullptr;  // FP64 staging for uploads/downloads
     void* zero_buf = nullptr;  // 256 zeroed bytes (large-lattice layout)
+    long long n_stored = 0;    // indexed layout: stored (non-wall) nodes
     size_t tmp_bytes = 0;
     double* obs_partial = nullptr;
     int obs_nblk = 512;

@@ -83,3 +83,21 @@ def test_viscometer_estimator_matches_the_oracle():
     for tau in (1.0, 0.8):
         assert cgb.mu_app_le(flux, 10, prof, 8, 9, 1.0, tau) == pytest.approx(
             O.mu_app_le(flux, 10, prof, 8, 9, 1.0, tau), rel=1e-12)
+
+
+def test_indexed_layout_needs_less_memory():
+    # sparse geometry: the indexed layout stores populations and link data
+    # for the non-wall nodes only
+    import synth
+    from paper_1005_2594_amd import cgb
+    m = synth.bifurcation_mask(5, 4, 5, 64)
+    p = synth.vessel_params(m, force_mode=1, g=(0.0, 0.0, 1e-4))
+    ns, nc = m.size, int((1 - m).sum())
+    dense = cgb.query_sizes(p, wall_mask=m, cell_cap=10, precision="pmx16s").arena_bytes
+    idx = cgb.query_sizes(dict(p, indexed=1), wall_mask=m, cell_cap=10, precision="pmx16s").arena_bytes
+    # per stored node: populations A, B (2 x 19 x 2 B), densities (2 x 2 B),
+    # link moments (4 x 4 B), node momenta (32 B); plus the 4 B index map per site
+    want = (ns - nc) * (76 + 4 + 16 + 32) - 4 * ns
+    assert abs((dense - idx) - want) < 0.01 * want + 16 * 256
+    with pytest.raises(cgb.CgbError):
+        cgb.query_sizes(dict(p, indexed=1, tau=0.8), wall_mask=m, cell_cap=10, precision="pmx16s")

@@ -83,3 +83,28 @@ def test_cylinder_with_cells_p32():
     o.step(steps)
     compare_state(g, o, 1e-5, 1e-5)
     g.close()
+
+
+@pytest.mark.parametrize("prec", ["p64", "p32", "pmx16s"])
+def test_indexed_layout_matches_dense(prec):
+    # the indexed layout stores the non-wall nodes only (27 % of this box);
+    # every result equals the dense layout's bit for bit
+    from paper_1005_2594_amd import Sim
+    m, p, X, q, V, L = _bifurcation_case(seed=45)
+    L_, ny, nx = m.shape
+    say(f"case: indexed vs dense layout, bifurcation 21x13x48 with {len(X)} cells, {prec}, 30 steps")
+    out = []
+    for idx in (0, 1):
+        g = Sim(dict(p, indexed=idx), m, precision=prec)
+        g.set_particles(X, q, V, L)
+        g.init_fluid()
+        g.step(30)
+        out.append((g.owner(), g.populations(), *g.particles(), *g.forces(),
+                    g.mixture_box((0, 0, 0), (nx, ny, L_))))
+        if idx:
+            assert g.device_bytes < dense_bytes
+        else:
+            dense_bytes = g.device_bytes
+        g.close()
+    for x, y in zip(*out):
+        assert np.array_equal(x, y)
