@@ -279,6 +279,42 @@ def paper_scale_leg(steps=20, warmup=3, kernel_steps=5, prec="pmx16s"):
     return out
 
 
+def vessel_leg(steps=200, warmup=10, prec="pmx16s"):
+    """The bifurcation workload of Sec. IV at a size that fills the GPU, in
+    the dense and the indexed layout (results identical, checked by the GPU
+    tests): time per step, rate per site and per vessel node, device memory,
+    and the flow fraction of the constricted branch at the end."""
+    from paper_1005_2594_amd import Sim
+    cfg = synth.vessel_network()
+    m, p = cfg["mask"], cfg["params"]
+    L_, ny, nx = m.shape
+    ns, nc = m.size, int((1 - m).sum())
+    out = {"workload": cfg["name"] + f", entrance force, {prec}", "sites": ns, "vessel_nodes": nc,
+           "cells": len(cfg["X"]), "steps": steps}
+    xs = np.arange(nx)
+    cx = (nx - 1) / 2.0
+    for idx in (0, 1):
+        g = Sim(dict(p, indexed=idx), m, precision=prec)
+        g.set_particles(cfg["X"], cfg["q"])
+        g.init_fluid()
+        g.step(warmup)
+        g.sync()
+        t0 = time.perf_counter()
+        g.step(steps)
+        g.sync()
+        dt = time.perf_counter() - t0
+        u = g.mixture_box((0, 0, L_ // 2), (nx, ny, 1))[0]
+        q_hat = float(u[:, xs > cx, 2].sum() / u[:, xs != cx, 2].sum())
+        key = "indexed" if idx else "dense"
+        out[key] = {"ms_per_step": round(dt / steps * 1e3, 4), "mlups_sites": round(ns * steps / dt / 1e6, 1),
+                    "mlups_vessel_nodes": round(nc * steps / dt / 1e6, 1), "device_bytes": int(g.device_bytes),
+                    "flow_fraction_constricted": round(q_hat, 6)}
+        g.close()
+    print(f"# vessels: dense {out['dense']['ms_per_step']} ms, indexed {out['indexed']['ms_per_step']} ms per step",
+          flush=True)
+    return out
+
+
 def cpu_baseline(cfg, steps):
     """The FP64 oracle on the same 256^3 workload for a few steps (host cores)."""
     from oracle import oracle as O
@@ -319,6 +355,7 @@ def main():
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-paper-scale", action="store_true")
+    ap.add_argument("--no-vessels", action="store_true")
     ap.add_argument("--only", default=None, help="run only this precision (profiling)")
     ap.add_argument("--kernel-steps", type=int, default=50, help="steps of the per-kernel timing pass")
     ap.add_argument("--serial", action="store_true", help="every kernel in sequence in the timed region too")
@@ -417,6 +454,8 @@ def main():
         line["config"]["error_vs_oracle_64cube"] = error_report_64()
     if not args.no_batch:
         line["config"]["batch"] = batch_leg(steps=args.batch_steps)
+    if not args.no_vessels:
+        line["config"]["vessels"] = vessel_leg()
     if not args.no_paper_scale:
         line["config"]["paper_scale"] = paper_scale_leg()
     if not args.no_cpu:

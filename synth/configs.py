@@ -282,32 +282,54 @@ def vessel_cells(mask, n, R_perp, seed, clear=1.0, min_dist=None):
     off = np.array([(a, b, c) for a in range(-k, k + 1) for b in range(-k, k + 1) for c in range(-k, k + 1)
                     if a * a + b * b + c * c <= rr * rr + 1e-9])
     md = 2.0 * R_perp + 0.01 if min_dist is None else min_dist
-    X = []
+    # large boxes: draw candidates among the vessel nodes
+    cand = np.argwhere(mask == 0) if mask.size > 1_000_000 else None
+    X = np.empty((n, 3))
+    k_acc = 0
     tries = 0
-    while len(X) < n:
+    while k_acc < n:
         tries += 1
-        if tries > 200000:
+        if tries > 50 * n + 200000:
             raise RuntimeError("cell placement did not converge")
         p = np.floor(rng.random(3) * np.array([nx, ny, L]) * 1024.0) / 1024.0
+        if cand is not None:
+            # a random vessel node, jittered within its unit cell
+            j = cand[rng.integers(len(cand))]
+            p = np.floor((np.array([j[2], j[1], j[0]], dtype=np.float64) + rng.random(3) - 0.5) * 1024.0) / 1024.0
+            p[2] %= L
         nodes = np.round(p).astype(int)[None, :] + off
         zz = nodes[:, 2] % L
         if (nodes[:, 0] < 0).any() or (nodes[:, 0] >= nx).any() or (nodes[:, 1] < 0).any() or (nodes[:, 1] >= ny).any():
             continue
         if mask[zz, nodes[:, 1], nodes[:, 0]].any():
             continue
-        ok = True
-        for q in X:
-            d = p - q
-            d[2] -= L * np.round(d[2] / L)
-            if d @ d < md * md:
-                ok = False
-                break
-        if ok:
-            X.append(p)
-    return np.array(X), random_quaternions(rng, n)
+        if k_acc:
+            d = X[:k_acc] - p
+            d[:, 2] -= L * np.round(d[:, 2] / L)
+            if np.min(np.einsum("ij,ij->i", d, d)) < md * md:
+                continue
+        X[k_acc] = p
+        k_acc += 1
+    return X, random_quaternions(rng, n)
 
 
 def vessel_params(mask, **kw):
     """Parameters of a lattice holding the mask (walls from the mask only)."""
     L, ny, nx = mask.shape
     return params(nx, ny, L, **kw)
+
+
+def vessel_network(seed=7, Ht=0.1):
+    """A bifurcation with a stenosis at a size that fills the GPU: parent
+    radius 16, branch radius 12, branch axes 18 apart from the middle,
+    stenosis radius 8 over 64 nodes, length 2048 (periodic), cells at
+    hematocrit Ht of the vessel volume, body force on the fluid of the
+    entrance region (the first 128 planes)."""
+    m = bifurcation_mask(16, 12, 18, 2048, stenosis=(8.0, 64))
+    p = vessel_params(m, force_mode=1, g=(0.0, 0.0, 2e-5), force_zlo=0, force_zhi=128, rho_p=RHO_P_DENSE,
+                      force_on_particles=0)
+    nc = int((1 - m).sum())
+    N = cell_count(Ht, nc, p["R_perp"], p["R_par"])
+    X, q = vessel_cells(m, N, p["R_perp"], seed, clear=0.0, min_dist=2.5)
+    return dict(params=p, mask=m, X=X, q=q, name=f"bifurcation with stenosis {p['nx']}x{p['ny']}x{p['nz']}, "
+                f"{nc} vessel nodes, {N} cells (overlaps allowed)")
