@@ -325,9 +325,35 @@ def cpu_baseline(cfg, steps):
     o.step(steps)
     dt = time.perf_counter() - t0
     ns = cfg["params"]["nx"] * cfg["params"]["ny"] * cfg["params"]["nz"]
-    return {"value": round(ns * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"{steps} steps of the 256^3 Ht=0.4 workload in FP64 (all sites), set-up excluded",
-            "seconds": round(dt, 2)}
+    cores = O.num_threads()
+    out = {"value": round(ns * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+           "sample": f"{steps} steps of the 256^3 Ht=0.4 workload in FP64 (all sites), set-up excluded",
+           "seconds": round(dt, 2)}
+    # the 64^3 companion on one core and on all of them, and the host CPU
+    c64 = synth.config3_companion()
+    rates = {}
+    for nt in (1, cores):
+        O.set_num_threads(nt)
+        o = O.Oracle(c64["params"])
+        o.set_particles(c64["X"], c64["q"])
+        o.init_fluid()
+        k = 5 if nt == 1 else 20
+        t0 = time.perf_counter()
+        o.step(k)
+        rates[nt] = 64 ** 3 * k / (time.perf_counter() - t0) / 1e6
+    O.set_num_threads(cores)
+    out["mlups_64cube_1core"] = round(rates[1], 3)
+    out[f"mlups_64cube_{cores}cores"] = round(rates[cores], 3)
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    out["cpu_model"] = cpu
+    return out
 
 
 def copy_calibration(nbytes=1 << 31, reps=4):

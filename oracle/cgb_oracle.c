@@ -220,6 +220,13 @@ int orc_num_threads(void) {
     return 1;
 #endif
 }
+void orc_set_num_threads(int32_t n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
 
 static void rebuild_surface_walls(orc_sim* s) {
     free(s->sw);

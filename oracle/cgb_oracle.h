@@ -59,6 +59,7 @@ int  orc_create(const orc_params* p, const uint8_t* wall_mask /* nullable, nsite
 void orc_destroy(orc_sim* s);
 const char* orc_last_error(const orc_sim* s);
 int  orc_num_threads(void);
+void orc_set_num_threads(int32_t n);  /* host threads of the OpenMP loops (n > 0) */
 
 /* Particle state: X n*3, q n*4 (scalar first), V n*3 (t-1/2), L n*3 (space-frame
  * angular momentum at t-1/2), fixed n (1 = held at rest).  Rasterises the

@@ -101,6 +101,7 @@ def lib():
         L.orc_rotate.argtypes = [C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_void_p]
         L.orc_inside.argtypes = [C.POINTER(OrcParams), C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int32]
         L.orc_le_flux.argtypes = [C.c_void_p]
         L.orc_le_flux.restype = C.c_double
         del dp
@@ -312,6 +313,10 @@ def inside(params: dict, X, o, node):
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n):
+    lib().orc_set_num_threads(int(n))
 
 
 # ---- apparent viscosity estimators (body-force driven flows) ----
