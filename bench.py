@@ -107,8 +107,20 @@ def run_gpu(cfg, prec, steps, warmup, kernel_steps=50, serial=False):
     sim.step(warmup)
     sim.sync()
     nf0 = sim.observables()["n_fluid"]
+    # eager: one launch per kernel
     t0 = time.perf_counter()
     sim.step(steps)
+    sim.sync()
+    eager_s = time.perf_counter() - t0
+    # graph replay of a two-step capture (cgb_capture / cgb_replay): the
+    # same kernels, launched as one sequence
+    sim.capture(2)
+    sim.replay(2)
+    sim.sync()
+    t0 = time.perf_counter()
+    sim.replay(steps - steps % 2)
+    if steps % 2:
+        sim.step(1)
     sim.sync()
     t1 = time.perf_counter()
     kt = {}
@@ -122,7 +134,7 @@ def run_gpu(cfg, prec, steps, warmup, kernel_steps=50, serial=False):
         sim.set_concurrency(not serial)
     ob = sim.observables()
     nf = 0.5 * (nf0 + ob["n_fluid"])
-    return dict(seconds=t1 - t0, n_fluid=nf, kernel_times=kt, obs=ob, sim=sim)
+    return dict(seconds=t1 - t0, eager_seconds=eager_s, n_fluid=nf, kernel_times=kt, obs=ob, sim=sim)
 
 
 def error_report_64(seed=3, horizons=(100, 250, 500)):
@@ -442,6 +454,9 @@ def main():
                              "1024^2 x 2048 lattice with 4.1e6 cells (Sec. IV)",
             "concurrency": "serial" if args.serial else "cell list + potentials on a side stream beside the lattice "
                                                         "kernels, joined before the integrator",
+            "launch": "timed steps replayed from a HIP graph of a two-step capture (cgb_capture / cgb_replay)",
+            "eager_ms_per_step": round(r["eager_seconds"] * 1e3 / args.steps, 4),
+            "eager_mlups": round(ns * args.steps / r["eager_seconds"] / 1e6, 1),
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

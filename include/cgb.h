@@ -176,6 +176,19 @@ int cgb_set_populations(cgb_sim* s, const double* d);
  * exactly) -> cell list -> pair and wall potentials (Eqs. 15-20) -> FP64
  * leap-frog with quaternion rotation. */
 int cgb_step(cgb_sim* s, int32_t nsteps);
+/* Captures `steps` (even, >= 2) time steps into a HIP graph on the handle's
+ * stream, for cgb_replay: a replay launches the whole step sequence (its
+ * side stream included) at once instead of one launch per kernel, which
+ * removes the launch gaps of long runs.  Nothing is stepped.  The capture
+ * holds while the handle's launches stay the same: cgb_set_particles,
+ * cgb_set_tiles, cgb_set_concurrency, cgb_track, cgb_load or an odd number of
+ * eager steps make cgb_replay refuse (CGB_ESTATE) until the next capture.
+ * CGB_ESTATE while kernel timing (cgb_profile) is on: replays record none. */
+int cgb_capture(cgb_sim* s, int32_t steps);
+/* Replays the captured steps nsteps / steps times (nsteps a multiple of the
+ * captured count); asynchronous like cgb_step, results identical to it. */
+int cgb_replay(cgb_sim* s, int32_t nsteps);
+
 /* Waits for the stream; returns CGB_EUNSTABLE if any step tripped the
  * instability check (the first such step is in cgb_get_observables out[12]). */
 int cgb_sync(cgb_sim* s);

@@ -84,6 +84,8 @@ def lib():
     L.cgb_get_populations.argtypes = [VP, VP]
     L.cgb_get_fields.argtypes = [VP, VP, VP]
     L.cgb_get_box.argtypes = [VP, VP, VP, VP, VP]
+    L.cgb_capture.argtypes = [VP, C.c_int32]
+    L.cgb_replay.argtypes = [VP, C.c_int32]
     L.cgb_get_mixture_box.argtypes = [VP, VP, VP, VP]
     L.cgb_get_particles.argtypes = [VP, VP, VP, VP, VP]
     L.cgb_get_forces.argtypes = [VP, VP, VP, VP, VP]
@@ -271,6 +273,14 @@ class Sim:
         d = np.empty((19, self.ns))
         self._check(lib().cgb_get_populations(self.h, _ptr(d)))
         return d
+
+    def capture(self, steps=2):
+        """Records `steps` (even) steps as a HIP graph (``cgb_capture``)."""
+        self._check(lib().cgb_capture(self.h, int(steps)))
+
+    def replay(self, nsteps):
+        """Replays the captured steps (``cgb_replay``), asynchronous."""
+        self._check(lib().cgb_replay(self.h, int(nsteps)))
 
     def box(self, lo, ext):
         """Populations (19, ext_z, ext_y, ext_x) and owners (ext_z, ext_y, ext_x)

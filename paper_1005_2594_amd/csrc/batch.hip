@@ -39,12 +39,6 @@ struct cgb_batch {
     std::string err;
 };
 
-static bool same_args(const DevArgs& live, const DevArgs& snap) {
-    DevArgs t;
-    memcpy(&t, &live, sizeof t);
-    t.step = snap.step;  // host-side step index, not used by the kernels
-    return memcmp(&t, &snap, sizeof t) == 0;
-}
 
 #define BFAIL(b, code, ...)                         \
     do {                                            \
@@ -216,7 +210,7 @@ int cgb_batch_run(cgb_batch* b, int32_t nsteps) {
     for (size_t c = 0; c < b->ch.size(); c++) {
         cgb_sim* s = b->ch[c];
         const LaunchCfg& k = b->cap_cfg[c];
-        if (!same_args(s->a, b->cap_args[c]) || s->lbcfg.bx != k.bx || s->lbcfg.by != k.by || s->lbcfg.tz != k.tz)
+        if (!sim_same_args(s->a, b->cap_args[c]) || s->lbcfg.bx != k.bx || s->lbcfg.by != k.by || s->lbcfg.tz != k.tz)
             BFAIL(b, CGB_ESTATE, "channel %zu changed since the capture (odd eager steps, new cells or tiles); capture again", c);
         // the channel streams may hold eager work issued since the last replay
         BCHK(b, hipEventRecord(b->pre[c], s->st));

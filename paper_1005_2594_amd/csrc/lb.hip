@@ -15,7 +15,8 @@
 // node with links after the occupancy update, and the LB reads them with one
 // coalesced load.  With the split FP16 codec the same kernel also sums, at
 // every fluid node, the density parts w_r D of the pulled populations (D of
-// each population's source node), so that the LB decodes only the residuals.  For general tau the per-direction values are needed: a
+// each population's source node), so that the LB decodes only the residuals.
+// For general tau the per-direction values are needed: a
 // node-parallel kernel stores u(s) for every cell node and walls hold their
 // plane velocity, and the LB gathers the velocity of each link's source.  In
 // neither case does a link need to know which body is behind it.

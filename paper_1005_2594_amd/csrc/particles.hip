@@ -232,6 +232,7 @@ hipError_t launch_cellrec(const DevArgs& a, hipStream_t st) {
 // work independently.
 constexpr int ZB = 8;
 constexpr int CPW = 4;
+constexpr unsigned LIST_OWNED = 0x80000000u;  // list entry of a node its cell already owned
 
 __global__ void __launch_bounds__(64 * CPW) claim_kernel(DevArgs a) {
     const unsigned nx = (unsigned)a.nx, plane = (unsigned)a.nx * (unsigned)a.ny;
@@ -273,8 +274,11 @@ __global__ void __launch_bounds__(64 * CPW) claim_kernel(DevArgs a) {
                     if (in && a.le_u != 0.0 && (x == 0 || x == a.nx - 1)) atomicOr(a.status, ST_LE_SEAM);
                     const unsigned long long m = __ballot(in);
                     if (in) {
+                        // bit 31 marks a node the cell already owns: it keeps it
+                        // (it still covers it), so the momentum exchange need not
+                        // look its owner up (sites < 2^31)
                         const int e = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                        if (e < a.lcap) lst[e] = sj[j];
+                        if (e < a.lcap) lst[e] = sj[j] | (o == p ? LIST_OWNED : 0u);
                     }
                     cnt += __popcll(m);
                 }
@@ -364,8 +368,9 @@ __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
     const unsigned nx = (unsigned)a.nx, plane = (unsigned)a.nx * (unsigned)a.ny;
     double FT[6] = {0, 0, 0, 0, 0, 0};
     for (int e = hl; e < cnt; e += 32) {
-        const unsigned s = lst[e];
-        const int o = a.owner[s];
+        const unsigned ent = lst[e];
+        const unsigned s = ent & ~LIST_OWNED;
+        const int o = (ent & LIST_OWNED) ? p : a.owner[s];
         double2 m01;
         double m2;
         if (a.big) {

@@ -194,9 +194,12 @@ int cgb_params_default(cgb_params* p) {
 const char* cgb_last_error(const cgb_sim* s) { return s ? s->err.c_str() : "null handle"; }
 int64_t cgb_device_bytes(const cgb_sim* s) { return s ? s->dev_bytes : 0; }
 
+static void drop_step_graph(cgb_sim* s);
+
 void cgb_destroy(cgb_sim* s) {
     if (!s) return;
     if (s->st) (void)hipStreamSynchronize(s->st);
+    drop_step_graph(s);
     if (s->st_pot) { (void)hipStreamSynchronize(s->st_pot); (void)hipStreamDestroy(s->st_pot); }
     for (hipEvent_t e : {s->ev_ras, s->ev_pot})
         if (e) (void)hipEventDestroy(e);
@@ -662,6 +665,21 @@ int cgb_set_populations(cgb_sim* s, const double* d) {
     return CGB_OK;
 }
 
+// the side stream of the step and its two events (default priority)
+static int make_side_stream(cgb_sim* s) {
+    HIPCHK(s, hipStreamCreateWithFlags(&s->st_pot, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&s->ev_ras, &s->ev_pot}) HIPCHK(s, hipEventCreateWithFlags(e, hipEventDisableTiming));
+    return CGB_OK;
+}
+
+static void drop_step_graph(cgb_sim* s) {
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->gexec = nullptr;
+    s->graph = nullptr;
+    s->graph_steps = 0;
+}
+
 int cgb_step(cgb_sim* s, int32_t nsteps) {
     if (!s || nsteps < 0) return CGB_EINVAL;
     if (!s->fluid_ready) FAIL(s, CGB_ESTATE, "fluid not initialised");
@@ -674,8 +692,8 @@ int cgb_step(cgb_sim* s, int32_t nsteps) {
         // integrator joins
         const bool fk = s->fork && a.n > 0;
         if (fk && !s->st_pot) {
-            HIPCHK(s, hipStreamCreateWithFlags(&s->st_pot, hipStreamNonBlocking));
-            for (hipEvent_t* e : {&s->ev_ras, &s->ev_pot}) HIPCHK(s, hipEventCreateWithFlags(e, hipEventDisableTiming));
+            const int rc = make_side_stream(s);
+            if (rc) return rc;
         }
         hipStream_t sp = fk ? s->st_pot : s->st;
         HIPCHK(s, timed(s, K_PREP, [&] { return launch_step_prep(a, s->st); }));
@@ -709,6 +727,55 @@ int cgb_step(cgb_sim* s, int32_t nsteps) {
         s->step++;
     }
     bind_buffers(s);
+    return CGB_OK;
+}
+
+// Captures `steps` (even) steps into a HIP graph on the handle's stream; the
+// state is left as it was.  A replay launches the whole sequence, side stream
+// included, at once, instead of one launch per kernel.
+int cgb_capture(cgb_sim* s, int32_t steps) {
+    if (!s || steps < 2 || (steps & 1)) return CGB_EINVAL;
+    if (!s->fluid_ready) FAIL(s, CGB_ESTATE, "fluid not initialised");
+    if (s->prof) FAIL(s, CGB_ESTATE, "kernel timing is on: a captured sequence records none; turn it off first");
+    drop_step_graph(s);
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    if (s->fork && s->a.n > 0 && !s->st_pot) {
+        const int rc = make_side_stream(s);
+        if (rc) return rc;
+    }
+    const int cur = s->cur;
+    const long long stp = s->step;
+    HIPCHK(s, hipStreamBeginCapture(s->st, hipStreamCaptureModeRelaxed));
+    const int rc = cgb_step(s, steps);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s->st, &g);
+    s->cur = cur;
+    s->step = stp;
+    bind_buffers(s);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e2 != hipSuccess) FAIL(s, CGB_EDEVICE, "end capture: %s", hipGetErrorString(e2));
+    s->graph = g;
+    HIPCHK(s, hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
+    s->graph_steps = steps;
+    memcpy(&s->cap_args, &s->a, sizeof(DevArgs));
+    s->cap_cfg = s->lbcfg;
+    s->cap_fork = s->fork;
+    return CGB_OK;
+}
+
+// Replays the captured sequence nsteps / graph_steps times (asynchronous).
+int cgb_replay(cgb_sim* s, int32_t nsteps) {
+    if (!s || nsteps < 0) return CGB_EINVAL;
+    if (!s->gexec) FAIL(s, CGB_ESTATE, "no captured steps");
+    if (nsteps % s->graph_steps) FAIL(s, CGB_EINVAL, "steps must be a multiple of %d", s->graph_steps);
+    if (!sim_same_args(s->a, s->cap_args) || s->lbcfg.bx != s->cap_cfg.bx || s->lbcfg.by != s->cap_cfg.by ||
+        s->lbcfg.tz != s->cap_cfg.tz || s->fork != s->cap_fork)
+        FAIL(s, CGB_ESTATE, "the handle changed since the capture (cells, tiles, record, concurrency, odd eager steps); capture again");
+    for (int k = 0; k < nsteps / s->graph_steps; k++) HIPCHK(s, hipGraphLaunch(s->gexec, s->st));
+    s->step += nsteps;
     return CGB_OK;
 }
 

@@ -1,6 +1,7 @@
 // sim.h -- internal definition of the lattice handle shared by the runtime
 // translation units (runtime.hip, batch.hip).
 #pragma once
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -49,6 +50,14 @@ struct cgb_sim {
     double* le_rec_buf = nullptr;
     double* tmp = nullptr;  // FP64 staging for uploads/downloads
     void* zero_buf = nullptr;  // 256 zeroed bytes (large-lattice layout)
+    // a captured step sequence (cgb_capture / cgb_replay) and what it was
+    // captured with
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_steps = 0;
+    cgb::DevArgs cap_args{};
+    cgb::LaunchCfg cap_cfg{0, 0, 0};
+    bool cap_fork = false;
     long long n_stored = 0;    // indexed layout: stored (non-wall) nodes
     size_t tmp_bytes = 0;
     double* obs_partial = nullptr;
@@ -70,3 +79,12 @@ namespace cgb {
 int sim_set_tiles(cgb_sim* s, LaunchCfg cfg);
 void sim_bind(cgb_sim* s);
 }  // namespace cgb
+
+// the device arguments a launch sequence was recorded with still hold (the
+// host-side step index aside, which no kernel reads)
+inline bool sim_same_args(const cgb::DevArgs& live, const cgb::DevArgs& snap) {
+    cgb::DevArgs t;
+    memcpy(&t, &live, sizeof t);
+    t.step = snap.step;
+    return memcmp(&t, &snap, sizeof t) == 0;
+}
