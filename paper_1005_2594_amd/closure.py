@@ -133,13 +133,72 @@ def evaluate(net, X, mu, threshold=0.05):
                 median_spread=float(np.median(spread)))
 
 
-def predict_or_simulate(net, chans, threshold=0.05, steps=2000):
+def local_noise(Xtr, mutr, X, k=8):
+    """Scatter of the plain method's own answers near each query: the sample
+    standard deviation of ln mu over the k training samples nearest to it in
+    standardised inputs.  Where the plain method's answers scatter, no
+    surrogate can be trusted, whatever its members agree on."""
+    ok = np.isfinite(mutr) & (mutr > 0)
+    Xtr, lm = Xtr[ok], np.log(mutr[ok])
+    m, sd = Xtr.mean(0), np.maximum(Xtr.std(0), 1e-12)
+    A, B = (Xtr - m) / sd, (np.asarray(X, dtype=np.float64) - m) / sd
+    d2 = (B * B).sum(1)[:, None] + (A * A).sum(1)[None, :] - 2.0 * B @ A.T
+    nn = np.argpartition(d2, k, axis=1)[:, :k]
+    return lm[nn].std(axis=1, ddof=1)
+
+
+def fallback_analysis(net, X, mu, Xtr=None, mutr=None, thresholds=(0.05, 0.03, 0.02, 0.01, 0.005),
+                      noise_thresholds=(0.3, 0.2, 0.15, 0.1)):
+    """How well the members' spread predicts the error on held-out samples:
+    the rank correlation of spread and error, and for each spread threshold
+    the fraction sent to the plain method and the error of the rest; the
+    inputs of the worst answers."""
+    ok = np.isfinite(mu)
+    X, mu = X[ok], mu[ok]
+    mean, spread = net.predict(X)
+    err = np.abs(mean - mu) / mu
+    rank = lambda v: np.argsort(np.argsort(v)).astype(np.float64)  # noqa: E731
+    rs, re = rank(spread), rank(err)
+    rho = float(np.corrcoef(rs, re)[0, 1])
+    sweep = []
+    for t in thresholds:
+        acc = spread <= t
+        sweep.append(dict(threshold=t, fallback_fraction=float(1 - acc.mean()),
+                          p90_rel_err_accepted=float(np.quantile(err[acc], 0.9)) if acc.any() else None,
+                          max_rel_err_accepted=float(err[acc].max()) if acc.any() else None))
+    worst = np.argsort(err)[::-1][:5]
+    out = dict(spearman_spread_error=rho, sweep=sweep,
+               worst=[dict(inputs=[float(v) for v in X[k]], mu=float(mu[k]), predicted=float(mean[k]),
+                           rel_err=float(err[k]), spread=float(spread[k])) for k in worst])
+    if Xtr is not None:
+        # the alternative criterion: the local scatter of the plain method
+        nz = local_noise(Xtr, mutr, X)
+        out["spearman_local_noise_error"] = float(np.corrcoef(rank(nz), re)[0, 1])
+        out["local_noise_sweep"] = []
+        for t in noise_thresholds:
+            acc = (nz <= t) & (spread <= 0.05)
+            out["local_noise_sweep"].append(dict(
+                threshold=t, fallback_fraction=float(1 - acc.mean()),
+                median_rel_err_accepted=float(np.median(err[acc])) if acc.any() else None,
+                p90_rel_err_accepted=float(np.quantile(err[acc], 0.9)) if acc.any() else None,
+                max_rel_err_accepted=float(err[acc].max()) if acc.any() else None))
+        for w, k in zip(out["worst"], worst):
+            w["local_noise"] = float(nz[k])
+    return out
+
+
+def predict_or_simulate(net, chans, threshold=0.05, steps=2000, train=None, noise_threshold=None):
     """mu_rel for channels: the ensemble mean where the members agree within
-    threshold, the plain method elsewhere.  Returns (mu, used_plain mask)."""
+    threshold (and, given the training samples train = (X, mu) and
+    noise_threshold, where the plain method's own answers near the query
+    scatter by at most noise_threshold in ln mu), the plain method
+    elsewhere.  Returns (mu, used_plain mask)."""
     X = np.stack([features(c) for c in chans]).astype(np.float32)
     mean, spread = net.predict(X)
     mu = mean.astype(np.float64)
     plain = spread > threshold
+    if train is not None and noise_threshold is not None:
+        plain |= local_noise(train[0], train[1], X) > noise_threshold
     if plain.any():
         sub = [c for c, f in zip(chans, plain) if f]
         mu_p, _ = simulate(sub, steps)
@@ -206,7 +265,7 @@ def main(argv=None):
     plain_s = sum(float(d["seconds"]) for d in tr + te) / (len(mtr) + len(mte))
     net, info = train_ensemble(Xtr, mtr, a.members, a.epochs, a.lr)
     rep = dict(features=FEATURES, train=info, test=evaluate(net, Xte, mte), inference=time_inference(net, Xtr),
-               plain_seconds_per_sample=plain_s)
+               fallback=fallback_analysis(net, Xte, mte, Xtr, mtr), plain_seconds_per_sample=plain_s)
     rep["gain"] = dict(plain_seconds_per_sample=plain_s,
                        surrogate_seconds_per_sample=rep["inference"]["ms"] * 1e-3 / rep["inference"]["points"])
     with open(a.out, "w") as fh:
