@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "sim.h"
@@ -37,6 +38,14 @@ struct cgb_batch {
     std::vector<DevArgs> cap_args;
     std::vector<LaunchCfg> cap_cfg;
     std::string err;
+    // One launch per kernel for every channel (the captured graph holds the
+    // step's kernels once, not once per channel): the launches in step
+    // order, their per-channel block tables, and each channel's device
+    // arguments for the two roles of its population buffers.
+    std::vector<MultiLaunch> plan;
+    void* plan_mem = nullptr;  // [2][nch] DevArgs, then the ChanGrid tables
+    size_t plan_bytes = 0;
+    const DevArgs* plan_args[2] = {nullptr, nullptr};
 };
 
 
@@ -53,12 +62,159 @@ struct cgb_batch {
         if (_e != hipSuccess) BFAIL(b, CGB_EDEVICE, "%s: %s", #call, hipGetErrorString(_e)); \
     } while (0)
 
+namespace cgb {
+bool multi_grid(int kind, const DevArgs& a, LaunchCfg lb, int* variant, unsigned* bx, unsigned* by, dim3* grid,
+                int* arg) {
+    if (kind == MK_LB) {
+        *arg = 0;
+        return multi_grid_lb(a, lb, variant, bx, by, grid);
+    }
+    if (kind == MK_TRACK || kind == MK_TRACK_FIN) return multi_grid_fields(kind, a, variant, bx, by, grid, arg);
+    return multi_grid_particles(kind, a, variant, bx, by, grid, arg);
+}
+hipError_t launch_multi(const MultiLaunch& m, const DevArgs* args, hipStream_t st) {
+    if (m.kind == MK_LB) return launch_multi_lb(m, args, st);
+    if (m.kind == MK_TRACK || m.kind == MK_TRACK_FIN) return launch_multi_fields(m, args, st);
+    return launch_multi_particles(m, args, st);
+}
+}  // namespace cgb
+
+// kernels of one channel's step in the order cgb_step launches them (a
+// batch's channels step alone on their streams: no side stream)
+static const int kStepKinds[] = {MK_PREP, MK_CLAIM, MK_RESOLVE, MK_TRANS, MK_LMOM, MK_LB, MK_MEM, MK_TRACK,
+                                 MK_TRACK_FIN, MK_BIN_CLEAR, MK_BIN_COUNT, MK_SCAN_LOCAL, MK_SCAN_TOP, MK_SCAN_ADD,
+                                 MK_BIN_FILL, MK_BIN_SORT, MK_SORTED_POS, MK_POT, MK_INT};
+
+static void drop_plan(cgb_batch* b) {
+    if (b->plan_mem) (void)hipFree(b->plan_mem);
+    b->plan_mem = nullptr;
+    b->plan_bytes = 0;
+    b->plan.clear();
+    b->plan_args[0] = b->plan_args[1] = nullptr;
+}
+
+// every channel can take the one-launch-per-kernel step: the tau = 1 dense
+// kernel, one precision, no viscometer
+static bool fusable(const cgb_batch* b) {
+    for (const cgb_sim* s : b->ch) {
+        const DevArgs& a = s->a;
+        if (a.tau != 1.0 || a.big || a.cidx || a.le_u != 0.0 || !a.lmom || a.precision != b->ch[0]->a.precision)
+            return false;
+    }
+    return true;
+}
+
 static void drop_graph(cgb_batch* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
     b->graph_steps = 0;
+    drop_plan(b);
+}
+
+// The launch plan of the current channel states: per kernel of the step,
+// the channels grouped by kernel variant and block shape, each group one
+// launch whose blocks are the channels' own grids back to back.
+static int build_plan(cgb_batch* b) {
+    drop_plan(b);
+    const int nch = (int)b->ch.size();
+    struct Group {
+        int kind, variant;
+        unsigned bx, by;
+        std::vector<ChanGrid> cg;
+        std::vector<int> chans;
+    };
+    std::vector<Group> groups;
+    for (int kind : kStepKinds) {
+        std::map<std::tuple<int, unsigned, unsigned>, size_t> at;
+        for (int c = 0; c < nch; c++) {
+            const cgb_sim* s = b->ch[(size_t)c];
+            int variant = 0, arg = 0;
+            unsigned bx = 0, by = 0;
+            dim3 g;
+            if (!multi_grid(kind, s->a, s->lbcfg, &variant, &bx, &by, &g, &arg)) continue;
+            const auto key = std::make_tuple(variant, bx, by);
+            auto it = at.find(key);
+            if (it == at.end()) {
+                at[key] = groups.size();
+                groups.push_back(Group{kind, variant, bx, by, {}, {}});
+                it = at.find(key);
+            }
+            Group& G = groups[it->second];
+            const unsigned start = G.cg.empty() ? 0u : G.cg.back().start + G.cg.back().gx * G.cg.back().gy * G.cg.back().gz;
+            G.cg.push_back(ChanGrid{start, g.x, g.y, g.z, arg, {0, 0, 0}});
+            G.chans.push_back(c);
+        }
+    }
+    // device memory: both argument arrays, then every group's table (with its
+    // own argument arrays, since a group holds a subset of the channels)
+    size_t ntab = 0, tab_bytes = 0;
+    for (const Group& G : groups) {
+        ntab += G.cg.size();
+        const unsigned blocks = G.cg.back().start + G.cg.back().gx * G.cg.back().gy * G.cg.back().gz;
+        // the group's table, its block -> channel list, rounded to whole entries
+        tab_bytes += G.cg.size() * sizeof(ChanGrid) + ((size_t)blocks * 4 + sizeof(ChanGrid) - 1) / sizeof(ChanGrid) * sizeof(ChanGrid);
+    }
+    const size_t args_bytes = 2 * (size_t)nch * sizeof(DevArgs);
+    const size_t grp_args = 2 * ntab * sizeof(DevArgs);
+    b->plan_bytes = args_bytes + grp_args + tab_bytes;
+    BCHK(b, hipMalloc(&b->plan_mem, b->plan_bytes));
+    std::vector<char> host(b->plan_bytes);
+    DevArgs* ha = (DevArgs*)host.data();
+    for (int q = 0; q < 2; q++)
+        for (int c = 0; c < nch; c++) {
+            cgb_sim* s = b->ch[(size_t)c];
+            const int cur = s->cur;
+            s->cur = (cur + q) & 1;
+            sim_bind(s);
+            memcpy(&ha[(size_t)q * nch + c], &s->a, sizeof(DevArgs));
+            s->cur = cur;
+            sim_bind(s);
+        }
+    char* dev = (char*)b->plan_mem;
+    DevArgs* garg = (DevArgs*)(host.data() + args_bytes);
+    size_t off = 0, toff = args_bytes + grp_args;
+    for (const Group& G : groups) {
+        const size_t k = G.cg.size();
+        for (int q = 0; q < 2; q++)
+            for (size_t j = 0; j < k; j++) garg[(size_t)q * ntab + off + j] = ha[(size_t)q * nch + G.chans[j]];
+        MultiLaunch m;
+        m.kind = G.kind;
+        m.variant = G.variant;
+        m.bx = G.bx;
+        m.by = G.by;
+        m.blocks = G.cg.back().start + G.cg.back().gx * G.cg.back().gy * G.cg.back().gz;
+        m.nch = (int)k;
+        ChanGrid* tab = (ChanGrid*)(host.data() + toff);
+        memcpy(tab, G.cg.data(), k * sizeof(ChanGrid));
+        int* blk = (int*)(tab + k);
+        for (size_t j = 0; j < k; j++) {
+            const unsigned nb = G.cg[j].gx * G.cg[j].gy * G.cg[j].gz;
+            for (unsigned t = 0; t < nb; t++) blk[G.cg[j].start + t] = (int)j;
+        }
+        m.cg = (const ChanGrid*)(dev + toff);
+        b->plan.push_back(m);
+        off += k;
+        toff += k * sizeof(ChanGrid) + ((size_t)m.blocks * 4 + sizeof(ChanGrid) - 1) / sizeof(ChanGrid) * sizeof(ChanGrid);
+    }
+    BCHK(b, hipMemcpy(b->plan_mem, host.data(), b->plan_bytes, hipMemcpyHostToDevice));
+    // per launch: the argument array of its group (offset into the group arrays)
+    b->plan_args[0] = (const DevArgs*)(dev + args_bytes);
+    b->plan_args[1] = (const DevArgs*)(dev + args_bytes) + ntab;
+    return CGB_OK;
+}
+
+// one time step of every channel: the plan's launches with the arguments of
+// buffer role q
+static int fused_step(cgb_batch* b, int q) {
+    size_t off = 0;
+    for (const MultiLaunch& m : b->plan) {
+        const DevArgs* args = b->plan_args[q] + off;
+        BCHK(b, launch_multi(m, args, b->master));
+        off += (size_t)m.nch;
+    }
+    return CGB_OK;
 }
 
 extern "C" {
@@ -168,6 +324,27 @@ int cgb_batch_capture(cgb_batch* b, int32_t steps) {
     std::vector<int> cur(b->ch.size());
     std::vector<long long> stp(b->ch.size());
     for (size_t c = 0; c < b->ch.size(); c++) { cur[c] = b->ch[c]->cur; stp[c] = b->ch[c]->step; }
+    if (fusable(b)) {
+        // one launch per kernel for every channel
+        int rc = build_plan(b);
+        if (rc) return rc;
+        BCHK(b, hipStreamBeginCapture(b->master, hipStreamCaptureModeRelaxed));
+        for (int k = 0; k < steps && rc == CGB_OK; k++) rc = fused_step(b, k & 1);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(b->master, &g);
+        if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+        if (e2 != hipSuccess) BFAIL(b, CGB_EDEVICE, "end capture: %s", hipGetErrorString(e2));
+        b->graph = g;
+        BCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->graph_steps = steps;
+        b->cap_args.resize(b->ch.size());
+        b->cap_cfg.resize(b->ch.size());
+        for (size_t c = 0; c < b->ch.size(); c++) {
+            memcpy(&b->cap_args[c], &b->ch[c]->a, sizeof(DevArgs));
+            b->cap_cfg[c] = b->ch[c]->lbcfg;
+        }
+        return CGB_OK;
+    }
     BCHK(b, hipStreamBeginCapture(b->master, hipStreamCaptureModeRelaxed));
     hipError_t e = hipEventRecord(b->fork, b->master);
     int rc = CGB_OK;

@@ -160,6 +160,47 @@ struct DevArgs {
     int nbody_blk;     // blocks of the integrate kernel (body_part has 3 per block)
 };
 
+// Block coordinates a kernel body works with.  A launch over one lattice
+// passes the hardware's; a launch over every channel of a batch (one launch
+// per kernel for all channels) passes each block its channel's share, found
+// from the per-channel table of first blocks and grids (ChanGrid).
+struct KCtx {
+    unsigned bx, by, bz, gx, gy, gz;
+};
+__device__ __forceinline__ KCtx hw_ctx() {
+    return KCtx{blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y, gridDim.z};
+}
+struct ChanGrid {
+    unsigned start, gx, gy, gz;  // first block of the channel in the launch, its grid
+    int arg;                     // a per-channel scalar of the kernel (the link-moment sweep depth)
+    int pad[3];
+};
+// The channel of this block: the launch's table of nch entries is followed by
+// one channel index per block of the launch (one load instead of a search).
+__device__ __forceinline__ int chan_of(const ChanGrid* cg, int nch) {
+    const int* blk = (const int*)(cg + nch);
+    return __builtin_amdgcn_readfirstlane(blk[blockIdx.x]);
+}
+__device__ __forceinline__ KCtx chan_ctx(const ChanGrid& q) {
+    const unsigned l = blockIdx.x - q.start;
+    return KCtx{l % q.gx, (l / q.gx) % q.gy, l / (q.gx * q.gy), q.gx, q.gy, q.gz};
+}
+
+// A batch advanced by one launch per kernel for every channel: the step's
+// kernels in the order one lattice's step launches them.
+enum MultiKind {
+    MK_PREP, MK_CLAIM, MK_RESOLVE, MK_TRANS, MK_LMOM, MK_LB, MK_MEM, MK_TRACK, MK_TRACK_FIN,
+    MK_BIN_CLEAR, MK_BIN_COUNT, MK_SCAN_LOCAL, MK_SCAN_TOP, MK_SCAN_ADD, MK_BIN_FILL, MK_BIN_SORT,
+    MK_SORTED_POS, MK_POT, MK_INT, MK_COUNT
+};
+// one launch: channels that share the kernel variant and block shape
+struct MultiLaunch {
+    int kind, variant;
+    unsigned bx, by, blocks;
+    int nch;
+    const ChanGrid* cg;  // device table, nch entries sorted by first block
+};
+
 // storage index of site s (see cidx); -1 at a wall of the indexed layout
 __device__ inline long long sidx(const DevArgs& a, long long s) { return a.cidx ? (long long)a.cidx[s] : s; }
 
@@ -441,6 +482,18 @@ struct LaunchCfg {
     int tz;      // nodes swept along z by each thread
 };
 hipError_t launch_lb(const DevArgs& a, LaunchCfg cfg, hipStream_t st);
+// Per channel, the grid of kind's launch in a lattice's own step (the same
+// work decomposition), its launch group (variant, block shape) and scalar
+// argument; false when the channel's step does not launch it.
+bool multi_grid(int kind, const DevArgs& a, LaunchCfg lb, int* variant, unsigned* bx, unsigned* by, dim3* grid,
+                int* arg);
+hipError_t launch_multi(const MultiLaunch& m, const DevArgs* args, hipStream_t st);
+bool multi_grid_particles(int kind, const DevArgs& a, int* variant, unsigned* bx, unsigned* by, dim3* grid, int* arg);
+hipError_t launch_multi_particles(const MultiLaunch& m, const DevArgs* args, hipStream_t st);
+bool multi_grid_fields(int kind, const DevArgs& a, int* variant, unsigned* bx, unsigned* by, dim3* grid, int* arg);
+hipError_t launch_multi_fields(const MultiLaunch& m, const DevArgs* args, hipStream_t st);
+bool multi_grid_lb(const DevArgs& a, LaunchCfg lb, int* variant, unsigned* bx, unsigned* by, dim3* grid);
+hipError_t launch_multi_lb(const MultiLaunch& m, const DevArgs* args, hipStream_t st);
 hipError_t launch_mem_reduce(const DevArgs& a, hipStream_t st);
 hipError_t launch_usol(const DevArgs& a, hipStream_t st, bool all);
 hipError_t launch_lmom(const DevArgs& a, hipStream_t st);
@@ -469,6 +522,11 @@ hipError_t launch_le(const DevArgs& a, hipStream_t st);
 constexpr int LE_BLOCK = 256;
 static inline int le_blocks(const DevArgs& a) { return (2 * a.ny * a.nz + LE_BLOCK - 1) / LE_BLOCK; }
 constexpr int TRACK_BLOCKS = 1024;
+// blocks of a lattice's mixture record: one per 4096 sites, at most TRACK_BLOCKS
+__host__ __device__ inline int track_blocks(long long ns) {
+    const long long b = (ns + 4095) / 4096;
+    return b < 1 ? 1 : (b > TRACK_BLOCKS ? TRACK_BLOCKS : (int)b);
+}
 hipError_t launch_track(const DevArgs& a, hipStream_t st);
 hipError_t launch_pairs(const DevArgs& a, int* out, int* count, int cap, hipStream_t st);
 }  // namespace cgb

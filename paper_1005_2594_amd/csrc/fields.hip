@@ -264,7 +264,7 @@ static dim3 site_grid(const DevArgs& a) { return dim3((unsigned)((a.ns + 255) / 
 // fixed per-thread site sets, block partials reduced in a fixed order: the
 // sums are deterministic.
 template <int P>
-__global__ void __launch_bounds__(256) track_kernel(DevArgs a) {
+__device__ __forceinline__ void track_kernel_body(const DevArgs& a, const KCtx& G) {
     using Cd = Codec<P>;
     using T = typename Cd::T;
     using M = typename Cd::R;
@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(256) track_kernel(DevArgs a) {
     const T* B = (const T*)a.B;
     const T* RB = (const T*)a.rhoB;
     double ss = 0.0, s1 = 0.0;
-    for (long long s = blockIdx.x * 256LL + threadIdx.x; s < a.ns; s += (long long)TRACK_BLOCKS * 256) {
+    for (long long s = G.bx * 256LL + threadIdx.x; s < a.ns; s += (long long)G.gx * 256) {
         const int o = a.owner[s];
         if (o == OWN_WALL) continue;
         const int y = (int)(((unsigned)s / (unsigned)a.nx) % (unsigned)a.ny);  // sites < 2^32 (checked at create)
@@ -311,15 +311,23 @@ __global__ void __launch_bounds__(256) track_kernel(DevArgs a) {
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        a.track_part[2 * blockIdx.x] = red[0][0];
-        a.track_part[2 * blockIdx.x + 1] = red[1][0];
+        a.track_part[2 * G.bx] = red[0][0];
+        a.track_part[2 * G.bx + 1] = red[1][0];
     }
 }
+template <int P>
+__global__ void __launch_bounds__(256) track_kernel(DevArgs a) { track_kernel_body<P>(a, hw_ctx()); }
+template <int P>
+__global__ void __launch_bounds__(256) track_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    track_kernel_body<P>(as[c], chan_ctx(cg[c]));
+}
 
-__global__ void __launch_bounds__(256) track_finish_kernel(DevArgs a) {
+
+__device__ __forceinline__ void track_finish_kernel_body(const DevArgs& a, const KCtx& G) {
     __shared__ double red[2][256];
     double ss = 0.0, s1 = 0.0;
-    for (int b = threadIdx.x; b < TRACK_BLOCKS; b += 256) {
+    for (int b = threadIdx.x; b < track_blocks(a.ns); b += 256) {
         ss += a.track_part[2 * b];
         s1 += a.track_part[2 * b + 1];
     }
@@ -342,11 +350,45 @@ __global__ void __launch_bounds__(256) track_finish_kernel(DevArgs a) {
         *a.track_n = n + 1;
     }
 }
+__global__ void __launch_bounds__(256) track_finish_kernel(DevArgs a) { track_finish_kernel_body(a, hw_ctx()); }
+__global__ void __launch_bounds__(256) track_finish_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    track_finish_kernel_body(as[c], chan_ctx(cg[c]));
+}
+
 
 hipError_t launch_track(const DevArgs& a, hipStream_t st) {
     if (!a.track) return hipSuccess;
-    CGB_DISPATCH(track_kernel, dim3(TRACK_BLOCKS), dim3(256), a);
+    CGB_DISPATCH(track_kernel, dim3(track_blocks(a.ns)), dim3(256), a);
     hipLaunchKernelGGL(track_finish_kernel, dim3(1), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// batch: the mixture record of every channel
+bool multi_grid_fields(int kind, const DevArgs& a, int* variant, unsigned* bx, unsigned* by, dim3* grid, int* arg) {
+    *variant = a.precision;
+    *bx = 256;
+    *by = 1;
+    *arg = 0;
+    if (!a.track) return false;
+    if (kind == MK_TRACK) { *grid = dim3(track_blocks(a.ns)); return true; }
+    if (kind == MK_TRACK_FIN) { *grid = dim3(1); return true; }
+    return false;
+}
+
+hipError_t launch_multi_fields(const MultiLaunch& m, const DevArgs* args, hipStream_t st) {
+    if (m.kind == MK_TRACK_FIN) {
+        hipLaunchKernelGGL(track_finish_kernel_multi, dim3(m.blocks), dim3(256), 0, st, args, m.cg, m.nch);
+        return hipGetLastError();
+    }
+    switch (m.variant) {
+        case CGB_P64: hipLaunchKernelGGL(track_kernel_multi<CGB_P64>, dim3(m.blocks), dim3(256), 0, st, args, m.cg, m.nch); break;
+        case CGB_P32: hipLaunchKernelGGL(track_kernel_multi<CGB_P32>, dim3(m.blocks), dim3(256), 0, st, args, m.cg, m.nch); break;
+        case CGB_PMX16: hipLaunchKernelGGL(track_kernel_multi<CGB_PMX16>, dim3(m.blocks), dim3(256), 0, st, args, m.cg, m.nch); break;
+        case CGB_PMXBF16: hipLaunchKernelGGL(track_kernel_multi<CGB_PMXBF16>, dim3(m.blocks), dim3(256), 0, st, args, m.cg, m.nch); break;
+        case CGB_PMX16S: hipLaunchKernelGGL(track_kernel_multi<CGB_PMX16S>, dim3(m.blocks), dim3(256), 0, st, args, m.cg, m.nch); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -462,7 +462,7 @@ template <> struct LbMem<true> {
 // store nothing.
 constexpr int LAY_DENSE = 0, LAY_BIG = 1, LAY_IDX = 2;
 template <int P, int TZ, int LAY>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LAY == LAY_DENSE ? 4 : 3))) lb_kernel_tau1(DevArgs a) {
+__device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx& G) {
     using Cd = Codec<P>;
     using T = typename Cd::T;
     using R = typename Cd::R;
@@ -470,9 +470,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LAY ==
     constexpr bool BIG = LAY == LAY_BIG, IDX = LAY == LAY_IDX;
     using Mem = LbMem<BIG>;
     using I = typename Mem::I;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z0 = blockIdx.z * TZ;
+    const int x = G.bx * blockDim.x + threadIdx.x;
+    const int y = G.by * blockDim.y + threadIdx.y;
+    const int z0 = G.bz * TZ;
     const bool inb = (x < a.nx) && (y < a.ny);
     const I nx = (I)a.nx;
     const I plane = (I)a.nx * (I)a.ny;
@@ -692,6 +692,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LAY ==
         }
     }
 }
+template <int P, int TZ, int LAY>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LAY == LAY_DENSE ? 4 : 3))) lb_kernel_tau1(DevArgs a) { lb_kernel_tau1_body<P, TZ, LAY>(a, hw_ctx()); }
+template <int P, int TZ, int LAY>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LAY == LAY_DENSE ? 4 : 3))) lb_kernel_tau1_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    lb_kernel_tau1_body<P, TZ, LAY>(as[c], chan_ctx(cg[c]));
+}
+
 
 template <int P>
 static hipError_t launch_lb_p(const DevArgs& a, LaunchCfg cfg, hipStream_t st) {
@@ -726,6 +734,42 @@ static hipError_t launch_lb_p(const DevArgs& a, LaunchCfg cfg, hipStream_t st) {
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// batch: the dense tau = 1 kernel for every channel of a tile group; the
+// variant is (precision, sweep depth)
+bool multi_grid_lb(const DevArgs& a, LaunchCfg cfg, int* variant, unsigned* bx, unsigned* by, dim3* grid) {
+    if (a.tau != 1.0 || a.big || a.cidx || a.le_u != 0.0) return false;
+    *variant = a.precision * 64 + cfg.tz;
+    *bx = (unsigned)cfg.bx;
+    *by = (unsigned)cfg.by;
+    *grid = dim3((a.nx + cfg.bx - 1) / cfg.bx, (a.ny + cfg.by - 1) / cfg.by, (a.nz + cfg.tz - 1) / cfg.tz);
+    return true;
+}
+
+template <int P>
+static hipError_t launch_multi_lb_p(const MultiLaunch& m, const DevArgs* args, hipStream_t st, int tz) {
+    const dim3 g(m.blocks), b(m.bx, m.by);
+    switch (tz) {
+        case 4: hipLaunchKernelGGL((lb_kernel_tau1_multi<P, 4, LAY_DENSE>), g, b, 0, st, args, m.cg, m.nch); break;
+        case 8: hipLaunchKernelGGL((lb_kernel_tau1_multi<P, 8, LAY_DENSE>), g, b, 0, st, args, m.cg, m.nch); break;
+        case 16: hipLaunchKernelGGL((lb_kernel_tau1_multi<P, 16, LAY_DENSE>), g, b, 0, st, args, m.cg, m.nch); break;
+        case 32: hipLaunchKernelGGL((lb_kernel_tau1_multi<P, 32, LAY_DENSE>), g, b, 0, st, args, m.cg, m.nch); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_multi_lb(const MultiLaunch& m, const DevArgs* args, hipStream_t st) {
+    const int tz = m.variant % 64;
+    switch (m.variant / 64) {
+        case CGB_P64: return launch_multi_lb_p<CGB_P64>(m, args, st, tz);
+        case CGB_P32: return launch_multi_lb_p<CGB_P32>(m, args, st, tz);
+        case CGB_PMX16: return launch_multi_lb_p<CGB_PMX16>(m, args, st, tz);
+        case CGB_PMXBF16: return launch_multi_lb_p<CGB_PMXBF16>(m, args, st, tz);
+        case CGB_PMX16S: return launch_multi_lb_p<CGB_PMX16S>(m, args, st, tz);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_lb(const DevArgs& a, LaunchCfg cfg, hipStream_t st) {

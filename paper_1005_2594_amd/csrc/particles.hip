@@ -234,10 +234,10 @@ constexpr int ZB = 8;
 constexpr int CPW = 4;
 constexpr unsigned LIST_OWNED = 0x80000000u;  // list entry of a node its cell already owned
 
-__global__ void __launch_bounds__(64 * CPW) claim_kernel(DevArgs a) {
+__device__ __forceinline__ void claim_kernel_body(const DevArgs& a, const KCtx& G) {
     const unsigned nx = (unsigned)a.nx, plane = (unsigned)a.nx * (unsigned)a.ny;
     const int lane = threadIdx.x & 63;
-    const int k = __builtin_amdgcn_readfirstlane(xcd_block((int)blockIdx.x, (int)gridDim.x) * CPW + (int)(threadIdx.x >> 6));
+    const int k = __builtin_amdgcn_readfirstlane(xcd_block((int)G.bx, (int)G.gx) * CPW + (int)(threadIdx.x >> 6));
     if (k >= a.n) return;
     // cells in cell-list order: neighbouring waves touch neighbouring nodes
     const CellRec cr = ((const CellRec*)a.crec)[k];
@@ -289,6 +289,12 @@ __global__ void __launch_bounds__(64 * CPW) claim_kernel(DevArgs a) {
         if (cnt > a.lcap) atomicOr(a.status, ST_LIST_OVERFLOW);
     }
 }
+__global__ void __launch_bounds__(64 * CPW) claim_kernel(DevArgs a) { claim_kernel_body(a, hw_ctx()); }
+__global__ void __launch_bounds__(64 * CPW) claim_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    claim_kernel_body(as[c], chan_ctx(cg[c]));
+}
+
 
 // Resolve pass, one thread per node, after every cell's claims: a cell node
 // stays with its owner while the owner still covers it (single occupancy,
@@ -297,8 +303,8 @@ __global__ void __launch_bounds__(64 * CPW) claim_kernel(DevArgs a) {
 // Changes go to the transition list (one reservation per wave) and the claims
 // are cleared for the next step.  Every node a cell owns or claims is visited
 // once, in lattice order, so the loads are coalesced and no box is walked.
-__global__ void __launch_bounds__(256) resolve_kernel(DevArgs a) {
-    const long long si = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void resolve_kernel_body(const DevArgs& a, const KCtx& G) {
+    const long long si = (long long)G.bx * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const bool in = si < a.ns;
     const unsigned s = in ? (unsigned)si : 0u;
@@ -321,7 +327,7 @@ __global__ void __launch_bounds__(256) resolve_kernel(DevArgs a) {
     if (m) {
         const int first = __ffsll((long long)m) - 1;
         int base = 0;
-        const int seg = (int)(blockIdx.x % TSEG);
+        const int seg = (int)(G.bx % TSEG);
         if (lane == first) base = atomicAdd(a.ntrans + seg, __popcll(m));
         base = __shfl(base, first, 64);
         if (tr) {
@@ -337,6 +343,12 @@ __global__ void __launch_bounds__(256) resolve_kernel(DevArgs a) {
         }
     }
 }
+__global__ void __launch_bounds__(256) resolve_kernel(DevArgs a) { resolve_kernel_body(a, hw_ctx()); }
+__global__ void __launch_bounds__(256) resolve_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    resolve_kernel_body(as[c], chan_ctx(cg[c]));
+}
+
 
 static inline unsigned cell_grid(int n) { return (unsigned)((n + CPW - 1) / CPW); }
 
@@ -353,10 +365,10 @@ static inline unsigned cell_grid(int n) { return (unsigned)((n + CPW - 1) / CPW)
 // keeps the nodes the cell owns after the resolve pass; FP64 sums in list
 // order, then over the half (the order is fixed: the result does not depend
 // on scheduling).  The cover/uncover sums of the transitions are added.
-__global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
+__device__ __forceinline__ void mem_reduce_kernel_body(const DevArgs& a, const KCtx& G) {
     const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
     const int wv = threadIdx.x >> 6;
-    const int k = 2 * __builtin_amdgcn_readfirstlane(xcd_block((int)blockIdx.x, (int)gridDim.x) * CPW + wv) + half;
+    const int k = 2 * __builtin_amdgcn_readfirstlane(xcd_block((int)G.bx, (int)G.gx) * CPW + wv) + half;
     if (2 * (k >> 1) >= a.n) return;  // whole wave: no cell
     const bool live = k < a.n;        // the second half of the last wave may have none
     const CellRec cr = ((const CellRec*)a.crec)[live ? k : k - 1];
@@ -405,6 +417,12 @@ __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) {
         for (int c = 0; c < 6; c++) F[c] = FT[c] + fx_value(Ft + 2 * c);
     }
 }
+__global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) { mem_reduce_kernel_body(a, hw_ctx()); }
+__global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    mem_reduce_kernel_body(as[c], chan_ctx(cg[c]));
+}
+
 
 hipError_t launch_mem_reduce(const DevArgs& a, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
@@ -597,11 +615,11 @@ __device__ inline void lm_lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\t
 // population), and stores E = 6 rho(x) K + T, which the LB adds to its sums
 // of the FP16 residuals; every site is written (zeros at non-fluid nodes).
 template <class M, int TX, int NC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(M) == 4 ? 8 : 5))) lmom_kernel(DevArgs a, int tz) {
+__device__ __forceinline__ void lmom_kernel_body(const DevArgs& a, const KCtx& G, int tz) {
     using S = LmShape<TX>;
     __shared__ M U[4 * NC * S::NP];  // [slot][component][HY][HX]
     const int tx = (int)(threadIdx.x % TX), ty = (int)(threadIdx.x / TX);
-    const int x0 = (int)blockIdx.x * TX, y0 = (int)blockIdx.y * S::TY, z0 = (int)blockIdx.z * tz;
+    const int x0 = (int)G.bx * TX, y0 = (int)G.by * S::TY, z0 = (int)G.bz * tz;
     const int x = x0 + tx, y = y0 + ty;
     const bool in = x < a.nx && y < a.ny;
     const int zend = a.nz - z0 < tz ? a.nz - z0 : tz;
@@ -692,6 +710,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         }
     }
 }
+template <class M, int TX, int NC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(M) == 4 ? 8 : 5))) lmom_kernel(DevArgs a, int tz) { lmom_kernel_body<M, TX, NC>(a, hw_ctx(), tz); }
+template <class M, int TX, int NC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(M) == 4 ? 8 : 5))) lmom_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    lmom_kernel_body<M, TX, NC>(as[c], chan_ctx(cg[c]), cg[c].arg);
+}
+
 
 // workgroups of a link-moment kernel resident on the whole device at once
 // (0 if the runtime cannot say); fixed per process
@@ -713,8 +739,14 @@ static int lm_resident() {
 // less, and a second, partial round would leave the device part idle); a
 // short sweep when long sweeps would leave the device with few workgroups.
 template <class M, int TX, int NC>
-static void lm_launch(const DevArgs& a, hipStream_t st) {
+static dim3 lm_grid(const DevArgs& a, int* tzo, bool batch = false) {
     const int ty = 256 / TX;
+    if (batch) {
+        // a launch for every channel of a batch fills the device by itself:
+        // sweeps of 16 planes (each node's moments do not depend on the sweep)
+        *tzo = 16;
+        return dim3((unsigned)((a.nx + TX - 1) / TX), (unsigned)((a.ny + ty - 1) / ty), (unsigned)((a.nz + 15) / 16));
+    }
     const long long patches = (long long)((a.nx + TX - 1) / TX) * ((a.ny + ty - 1) / ty);
     int tz = 4;
     if (patches * ((a.nz + 15) / 16) >= 2048) {
@@ -725,8 +757,15 @@ static void lm_launch(const DevArgs& a, hipStream_t st) {
             if (t >= 8) tz = (int)t;
         }
     }
-    const dim3 g((unsigned)((a.nx + TX - 1) / TX), (unsigned)((a.ny + ty - 1) / ty), (unsigned)((a.nz + tz - 1) / tz)), b(256);
-    hipLaunchKernelGGL((lmom_kernel<M, TX, NC>), g, b, 0, st, a, tz);
+    *tzo = tz;
+    return dim3((unsigned)((a.nx + TX - 1) / TX), (unsigned)((a.ny + ty - 1) / ty), (unsigned)((a.nz + tz - 1) / tz));
+}
+
+template <class M, int TX, int NC>
+static void lm_launch(const DevArgs& a, hipStream_t st) {
+    int tz = 0;
+    const dim3 g = lm_grid<M, TX, NC>(a, &tz);
+    hipLaunchKernelGGL((lmom_kernel<M, TX, NC>), g, dim3(256), 0, st, a, tz);
 }
 
 hipError_t launch_lmom(const DevArgs& a, hipStream_t st) {
@@ -759,12 +798,12 @@ __global__ void step_begin_kernel(int* ntrans, int* dstep, int advance) {
 // velocity and FP32 velocity table, zeroed force sums and its record, written
 // at the cell's position in the previous cell list (the thread that computes
 // a cell's kinematics writes its record, so the two need no separate passes).
-__global__ void step_prep_kernel(DevArgs a) {
-    if (blockIdx.x == 0) {
+__device__ __forceinline__ void step_prep_kernel_body(const DevArgs& a, const KCtx& G) {
+    if (G.bx == 0) {
         if (threadIdx.x < TSEG) a.ntrans[threadIdx.x] = 0;
         if (threadIdx.x == 0) *a.dstep += 1;
     }
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = G.bx * blockDim.x + threadIdx.x;
     if (p >= a.n) return;
     // the record's inputs are loaded before prep_one stores
     const int rk = a.rank[p];
@@ -773,6 +812,12 @@ __global__ void step_prep_kernel(DevArgs a) {
     prep_one(a, p, true, k);
     record_one(a, rk, p, k, pb);
 }
+__global__ void step_prep_kernel(DevArgs a) { step_prep_kernel_body(a, hw_ctx()); }
+__global__ void step_prep_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    step_prep_kernel_body(as[c], chan_ctx(cg[c]));
+}
+
 
 hipError_t launch_step_prep(const DevArgs& a, hipStream_t st) {
     if (a.n == 0) hipLaunchKernelGGL(step_begin_kernel, dim3(1), dim3(TSEG), 0, st, a.ntrans, a.dstep, 1);
@@ -862,12 +907,20 @@ __device__ void transition_one(const DevArgs& a, int t, bool book) {
 
 // TSEG x 8 blocks: block b takes segment b % TSEG
 template <int P>
-__global__ void transitions_kernel(DevArgs a, int book) {
-    const int seg = blockIdx.x % TSEG, part = blockIdx.x / TSEG, nparts = gridDim.x / TSEG;
+__device__ __forceinline__ void transitions_kernel_body(const DevArgs& a, const KCtx& G, int book) {
+    const int seg = G.bx % TSEG, part = G.bx / TSEG, nparts = G.gx / TSEG;
     const int cnt = min(a.ntrans[seg], a.trans_cap);
     for (int t = part * blockDim.x + threadIdx.x; t < cnt; t += nparts * blockDim.x)
         transition_one<P>(a, (int)((long long)seg * a.trans_cap + t), book != 0);
 }
+template <int P>
+__global__ void transitions_kernel(DevArgs a, int book) { transitions_kernel_body<P>(a, hw_ctx(), book); }
+template <int P>
+__global__ void transitions_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch, int book) {
+    const int c = chan_of(cg, nch);
+    transitions_kernel_body<P>(as[c], chan_ctx(cg[c]), book);
+}
+
 
 hipError_t launch_transitions(const DevArgs& a, hipStream_t st, bool book) {
     dim3 g(TSEG * 8), b(256);
@@ -933,22 +986,40 @@ __device__ inline int bin_coord(const DevArgs& a, int c, double v) {
     return b;
 }
 
-__global__ void bin_count_kernel(DevArgs a) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void bin_clear_kernel_body(const DevArgs& a, const KCtx& G) {
+    const int b = G.bx * blockDim.x + threadIdx.x;
+    if (b < a.nbins) a.bin_count[b] = 0;
+}
+__global__ void bin_clear_kernel(DevArgs a) { bin_clear_kernel_body(a, hw_ctx()); }
+__global__ void bin_clear_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    bin_clear_kernel_body(as[c], chan_ctx(cg[c]));
+}
+
+
+__device__ __forceinline__ void bin_count_kernel_body(const DevArgs& a, const KCtx& G) {
+    const int p = G.bx * blockDim.x + threadIdx.x;
     if (p >= a.n) return;
     const int bx = bin_coord(a, 0, a.X[3 * p]), by = bin_coord(a, 1, a.X[3 * p + 1]), bz = bin_coord(a, 2, a.X[3 * p + 2]);
     const int b = bx + a.nb[0] * (by + a.nb[1] * bz);
     a.pbin[p] = b;
     atomicAdd(a.bin_count + b, 1);
 }
+__global__ void bin_count_kernel(DevArgs a) { bin_count_kernel_body(a, hw_ctx()); }
+__global__ void bin_count_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    bin_count_kernel_body(as[c], chan_ctx(cg[c]));
+}
+
 
 // exclusive scan of bin_count into bin_start[0..nbins]: (1) each block of 256
 // threads scans 4096 bins (16 per thread) and records its total, (2) one block
 // scans the block totals, (3) each block adds its offset
 constexpr int SCAN_PER_BLOCK = 4096;
-__global__ void __launch_bounds__(256) scan_local_kernel(DevArgs a, int* block_tot) {
+__device__ __forceinline__ void scan_local_kernel_body(const DevArgs& a, const KCtx& G) {
     __shared__ int tot[256];
-    const int base = blockIdx.x * SCAN_PER_BLOCK + threadIdx.x * 16;
+    int* block_tot = a.scan_tmp;
+    const int base = G.bx * SCAN_PER_BLOCK + threadIdx.x * 16;
     int v[16], s = 0;
     for (int k = 0; k < 16; k++) {
         const int b = base + k;
@@ -969,11 +1040,20 @@ __global__ void __launch_bounds__(256) scan_local_kernel(DevArgs a, int* block_t
         if (b < a.nbins) { a.bin_start[b] = run; a.bin_fill[b] = 0; }
         run += v[k];
     }
-    if (threadIdx.x == 255) block_tot[blockIdx.x] = tot[255];
+    if (threadIdx.x == 255) block_tot[G.bx] = tot[255];
+}
+__global__ void __launch_bounds__(256) scan_local_kernel(DevArgs a) { scan_local_kernel_body(a, hw_ctx()); }
+__global__ void __launch_bounds__(256) scan_local_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    scan_local_kernel_body(as[c], chan_ctx(cg[c]));
 }
 
-__global__ void __launch_bounds__(1024) scan_top_kernel(int* block_tot, int nblk, int* total_out) {
+
+__device__ __forceinline__ void scan_top_kernel_body(const DevArgs& a, const KCtx& G) {
     __shared__ int tot[1024];
+    int* block_tot = a.scan_tmp;
+    const int nblk = (a.nbins + SCAN_PER_BLOCK - 1) / SCAN_PER_BLOCK;
+    int* total_out = a.bin_start + a.nbins;
     const int chunk = (nblk + 1023) / 1024;
     const int t = threadIdx.x;
     int s = 0;
@@ -993,22 +1073,41 @@ __global__ void __launch_bounds__(1024) scan_top_kernel(int* block_tot, int nblk
     }
     if (t == 1023) *total_out = tot[1023];
 }
-
-__global__ void scan_add_kernel(DevArgs a, const int* block_off) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < a.nbins) a.bin_start[b] += block_off[b / SCAN_PER_BLOCK];
+__global__ void __launch_bounds__(1024) scan_top_kernel(DevArgs a) { scan_top_kernel_body(a, hw_ctx()); }
+__global__ void __launch_bounds__(1024) scan_top_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    scan_top_kernel_body(as[c], chan_ctx(cg[c]));
 }
 
-__global__ void bin_fill_kernel(DevArgs a) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+
+__device__ __forceinline__ void scan_add_kernel_body(const DevArgs& a, const KCtx& G) {
+    const int* block_off = a.scan_tmp;
+    const int b = G.bx * blockDim.x + threadIdx.x;
+    if (b < a.nbins) a.bin_start[b] += block_off[b / SCAN_PER_BLOCK];
+}
+__global__ void scan_add_kernel(DevArgs a) { scan_add_kernel_body(a, hw_ctx()); }
+__global__ void scan_add_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    scan_add_kernel_body(as[c], chan_ctx(cg[c]));
+}
+
+
+__device__ __forceinline__ void bin_fill_kernel_body(const DevArgs& a, const KCtx& G) {
+    const int p = G.bx * blockDim.x + threadIdx.x;
     if (p >= a.n) return;
     const int b = a.pbin[p];
     const int pos = a.bin_start[b] + atomicAdd(a.bin_fill + b, 1);
     a.bin_idx[pos] = p;
 }
+__global__ void bin_fill_kernel(DevArgs a) { bin_fill_kernel_body(a, hw_ctx()); }
+__global__ void bin_fill_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    bin_fill_kernel_body(as[c], chan_ctx(cg[c]));
+}
 
-__global__ void bin_sort_kernel(DevArgs a) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+
+__device__ __forceinline__ void bin_sort_kernel_body(const DevArgs& a, const KCtx& G) {
+    const int b = G.bx * blockDim.x + threadIdx.x;
     if (b >= a.nbins) return;
     const int s = a.bin_start[b], e = a.bin_start[b + 1];
     for (int i = s + 1; i < e; i++) {
@@ -1018,6 +1117,12 @@ __global__ void bin_sort_kernel(DevArgs a) {
         a.bin_idx[j + 1] = v;
     }
 }
+__global__ void bin_sort_kernel(DevArgs a) { bin_sort_kernel_body(a, hw_ctx()); }
+__global__ void bin_sort_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    bin_sort_kernel_body(as[c], chan_ctx(cg[c]));
+}
+
 
 // positions in cell-list order with the cell's index (exact in a double), so
 // that a candidate is one independent 32-byte load
@@ -1025,23 +1130,28 @@ struct alignas(32) SortedPos {
     double x, y, z, id;
 };
 
-__global__ void sorted_pos_kernel(DevArgs a) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void sorted_pos_kernel_body(const DevArgs& a, const KCtx& G) {
+    const int t = G.bx * blockDim.x + threadIdx.x;
     if (t >= a.n) return;
     const int j = a.bin_idx[t];
     ((SortedPos*)a.Xs)[t] = SortedPos{a.X[3 * j], a.X[3 * j + 1], a.X[3 * j + 2], (double)j};
     a.rank[j] = t;
 }
+__global__ void sorted_pos_kernel(DevArgs a) { sorted_pos_kernel_body(a, hw_ctx()); }
+__global__ void sorted_pos_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    sorted_pos_kernel_body(as[c], chan_ctx(cg[c]));
+}
+
 
 hipError_t launch_cells(const DevArgs& a, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
-    hipError_t e = launch_fill_i32(a.bin_count, a.nbins, 0, st);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bin_clear_kernel, dim3((a.nbins + 255) / 256), dim3(256), 0, st, a);
     hipLaunchKernelGGL(bin_count_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
     const int nblk = (a.nbins + SCAN_PER_BLOCK - 1) / SCAN_PER_BLOCK;
-    hipLaunchKernelGGL(scan_local_kernel, dim3(nblk), dim3(256), 0, st, a, a.scan_tmp);
-    hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, st, a.scan_tmp, nblk, a.bin_start + a.nbins);
-    hipLaunchKernelGGL(scan_add_kernel, dim3((a.nbins + 255) / 256), dim3(256), 0, st, a, (const int*)a.scan_tmp);
+    hipLaunchKernelGGL(scan_local_kernel, dim3(nblk), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, st, a);
+    hipLaunchKernelGGL(scan_add_kernel, dim3((a.nbins + 255) / 256), dim3(256), 0, st, a);
     hipLaunchKernelGGL(bin_fill_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
     hipLaunchKernelGGL(bin_sort_kernel, dim3((a.nbins + 255) / 256), dim3(256), 0, st, a);
     hipLaunchKernelGGL(sorted_pos_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
@@ -1177,8 +1287,8 @@ __device__ inline void wall_vec(const DevArgs& a, const double* Xi, unsigned w, 
 // cells in cell-list order (neighbouring threads share neighbour bins).  The
 // candidates of a bin row are read CB at a time with independent loads.
 constexpr int CB = 2;
-__global__ void potentials_kernel(DevArgs a) {
-    const int k = xcd_block((int)blockIdx.x, (int)gridDim.x) * (int)blockDim.x + (int)threadIdx.x;
+__device__ __forceinline__ void potentials_kernel_body(const DevArgs& a, const KCtx& G) {
+    const int k = xcd_block((int)G.bx, (int)G.gx) * (int)blockDim.x + (int)threadIdx.x;
     if (k >= a.n) return;
     const SortedPos* S = (const SortedPos*)a.Xs;
     const SortedPos me = S[k];
@@ -1219,6 +1329,12 @@ __global__ void potentials_kernel(DevArgs a) {
         }
     for (int c = 0; c < 3; c++) { a.FTp[6 * i + c] = F[c]; a.FTp[6 * i + 3 + c] = T[c]; }
 }
+__global__ void potentials_kernel(DevArgs a) { potentials_kernel_body(a, hw_ctx()); }
+__global__ void potentials_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    potentials_kernel_body(as[c], chan_ctx(cg[c]));
+}
+
 
 // Pair and wall forces (Eqs. 16-20) on lattices with walls, PG lanes per
 // cell: a cell next to a wall screens some hundred wall nodes of its
@@ -1231,10 +1347,10 @@ constexpr int PG = 8;
 constexpr int PG_LIST = 8;
 static_assert(PG >= 6 && PG <= 64 && (PG & (PG - 1)) == 0, "a group's lanes 0-5 write the six sums");
 
-__global__ void __launch_bounds__(POT_BLOCK) potentials_grp_kernel(DevArgs a) {
+__device__ __forceinline__ void potentials_grp_kernel_body(const DevArgs& a, const KCtx& G) {
     // [slot][thread]: a partner j >= 0, or ~t for wall entry t
     __shared__ int plist[PG_LIST][POT_BLOCK];
-    const int k = (int)(((unsigned)xcd_block((int)blockIdx.x, (int)gridDim.x) * (unsigned)POT_BLOCK + threadIdx.x) / PG);
+    const int k = (int)(((unsigned)xcd_block((int)G.bx, (int)G.gx) * (unsigned)POT_BLOCK + threadIdx.x) / PG);
     const int g = (int)(threadIdx.x % PG);
     const bool live = k < a.n;  // uniform over each group; groups do not meet
     const SortedPos* S = (const SortedPos*)a.Xs;
@@ -1312,6 +1428,12 @@ __global__ void __launch_bounds__(POT_BLOCK) potentials_grp_kernel(DevArgs a) {
         a.FTp[6 * i + g] = v;
     }
 }
+__global__ void __launch_bounds__(POT_BLOCK) potentials_grp_kernel(DevArgs a) { potentials_grp_kernel_body(a, hw_ctx()); }
+__global__ void __launch_bounds__(POT_BLOCK) potentials_grp_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    potentials_grp_kernel_body(as[c], chan_ctx(cg[c]));
+}
+
 
 hipError_t launch_potentials(const DevArgs& a, hipStream_t st) {
     if (a.n == 0) return hipSuccess;
@@ -1383,9 +1505,9 @@ __device__ void integrate_one(const DevArgs& a, int p, double* bf);
 
 // one thread per cell; the body force added to the cells is reduced per block
 // (no same-address atomics) into body_part[3 * block]
-__global__ void __launch_bounds__(256) integrate_kernel(DevArgs a) {
+__device__ __forceinline__ void integrate_kernel_body(const DevArgs& a, const KCtx& G) {
     __shared__ double red[3][256];
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = G.bx * blockDim.x + threadIdx.x;
     double bf[3] = {0, 0, 0};
     if (p < a.n) integrate_one(a, p, bf);
     for (int c = 0; c < 3; c++) red[c][threadIdx.x] = bf[c];
@@ -1396,8 +1518,14 @@ __global__ void __launch_bounds__(256) integrate_kernel(DevArgs a) {
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int c = 0; c < 3; c++) a.body_part[3 * blockIdx.x + c] = red[c][0];
+        for (int c = 0; c < 3; c++) a.body_part[3 * G.bx + c] = red[c][0];
 }
+__global__ void __launch_bounds__(256) integrate_kernel(DevArgs a) { integrate_kernel_body(a, hw_ctx()); }
+__global__ void __launch_bounds__(256) integrate_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+    const int c = chan_of(cg, nch);
+    integrate_kernel_body(as[c], chan_ctx(cg[c]));
+}
+
 
 __device__ void integrate_one(const DevArgs& a, int p, double* bf) {
     if (a.fixed[p]) {
@@ -1469,5 +1597,114 @@ hipError_t launch_integrate(const DevArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(integrate_kernel, dim3((a.n + 255) / 256), dim3(256), 0, st, a);
     return hipGetLastError();
 }
+
+}  // namespace cgb
+
+namespace cgb {
+
+// ------------------------------------------------------------ batch launches
+// lmom variant: link type and patch width as the single launch chooses them
+static int lm_variant(const DevArgs& a) {
+    const int w = a.nx <= 48 ? 0 : 1;
+    if (a.precision == CGB_P64) return w;
+    if (a.precision == CGB_PMX16S) return 2 + w;
+    return 4 + w;
+}
+
+bool multi_grid_particles(int kind, const DevArgs& a, int* variant, unsigned* bx, unsigned* by, dim3* grid, int* arg) {
+    *variant = 0;
+    *bx = 256;
+    *by = 1;
+    *arg = 0;
+    const unsigned n = (unsigned)a.n;
+    switch (kind) {
+        case MK_PREP: *grid = dim3(n ? (n + 255) / 256 : 1); return true;  // block 0 also starts the step
+        case MK_CLAIM: *bx = 64 * CPW; *grid = dim3(cell_grid(a.n)); return n > 0;
+        case MK_RESOLVE: *grid = dim3((unsigned)((a.ns + 255) / 256)); return n > 0;
+        case MK_TRANS: *variant = a.precision; *grid = dim3(TSEG * 8); return true;
+        case MK_LMOM: {
+            if (!a.lmom) return false;
+            const int v = lm_variant(a);
+            *variant = v;
+            int tz = 0;
+            switch (v) {
+                case 0: *grid = lm_grid<double, 32, 3>(a, &tz, true); break;
+                case 1: *grid = lm_grid<double, 64, 3>(a, &tz, true); break;
+                case 2: *grid = lm_grid<float, 32, 4>(a, &tz, true); break;
+                case 3: *grid = lm_grid<float, 64, 4>(a, &tz, true); break;
+                case 4: *grid = lm_grid<float, 32, 3>(a, &tz, true); break;
+                default: *grid = lm_grid<float, 64, 3>(a, &tz, true); break;
+            }
+            *arg = tz;
+            return true;
+        }
+        case MK_MEM: *bx = 64 * CPW; *grid = dim3(cell_grid((a.n + 1) / 2)); return n > 0;
+        case MK_BIN_CLEAR: *grid = dim3((unsigned)((a.nbins + 255) / 256)); return n > 0;
+        case MK_BIN_COUNT: *grid = dim3((n + 255) / 256); return n > 0;
+        case MK_SCAN_LOCAL: *grid = dim3((unsigned)((a.nbins + SCAN_PER_BLOCK - 1) / SCAN_PER_BLOCK)); return n > 0;
+        case MK_SCAN_TOP: *bx = 1024; *grid = dim3(1); return n > 0;
+        case MK_SCAN_ADD: *grid = dim3((unsigned)((a.nbins + 255) / 256)); return n > 0;
+        case MK_BIN_FILL: *grid = dim3((n + 255) / 256); return n > 0;
+        case MK_BIN_SORT: *grid = dim3((unsigned)((a.nbins + 255) / 256)); return n > 0;
+        case MK_SORTED_POS: *grid = dim3((n + 255) / 256); return n > 0;
+        case MK_POT:
+            *bx = POT_BLOCK;
+            *variant = a.nsw > 0 ? 1 : 0;
+            *grid = a.nsw > 0 ? dim3((unsigned)(((long long)a.n * PG + POT_BLOCK - 1) / POT_BLOCK))
+                              : dim3((n + POT_BLOCK - 1) / POT_BLOCK);
+            return n > 0;
+        case MK_INT: *grid = dim3((n + 255) / 256); return n > 0;
+        default: return false;
+    }
+}
+
+#define CGB_MULTI_GO(K) hipLaunchKernelGGL(K, dim3(m.blocks), dim3(m.bx, m.by), 0, st, args, m.cg, m.nch)
+hipError_t launch_multi_particles(const MultiLaunch& m, const DevArgs* args, hipStream_t st) {
+    switch (m.kind) {
+        case MK_PREP: CGB_MULTI_GO(step_prep_kernel_multi); break;
+        case MK_CLAIM: CGB_MULTI_GO(claim_kernel_multi); break;
+        case MK_RESOLVE: CGB_MULTI_GO(resolve_kernel_multi); break;
+        case MK_TRANS:
+            switch (m.variant) {
+                case CGB_P64: hipLaunchKernelGGL(transitions_kernel_multi<CGB_P64>, dim3(m.blocks), dim3(m.bx), 0, st, args, m.cg, m.nch, 1); break;
+                case CGB_P32: hipLaunchKernelGGL(transitions_kernel_multi<CGB_P32>, dim3(m.blocks), dim3(m.bx), 0, st, args, m.cg, m.nch, 1); break;
+                case CGB_PMX16: hipLaunchKernelGGL(transitions_kernel_multi<CGB_PMX16>, dim3(m.blocks), dim3(m.bx), 0, st, args, m.cg, m.nch, 1); break;
+                case CGB_PMXBF16: hipLaunchKernelGGL(transitions_kernel_multi<CGB_PMXBF16>, dim3(m.blocks), dim3(m.bx), 0, st, args, m.cg, m.nch, 1); break;
+                case CGB_PMX16S: hipLaunchKernelGGL(transitions_kernel_multi<CGB_PMX16S>, dim3(m.blocks), dim3(m.bx), 0, st, args, m.cg, m.nch, 1); break;
+                default: return hipErrorInvalidValue;
+            }
+            break;
+        case MK_LMOM:
+            switch (m.variant) {
+                case 0: CGB_MULTI_GO((lmom_kernel_multi<double, 32, 3>)); break;
+                case 1: CGB_MULTI_GO((lmom_kernel_multi<double, 64, 3>)); break;
+                case 2: CGB_MULTI_GO((lmom_kernel_multi<float, 32, 4>)); break;
+                case 3: CGB_MULTI_GO((lmom_kernel_multi<float, 64, 4>)); break;
+                case 4: CGB_MULTI_GO((lmom_kernel_multi<float, 32, 3>)); break;
+                default: CGB_MULTI_GO((lmom_kernel_multi<float, 64, 3>)); break;
+            }
+            break;
+        case MK_MEM: CGB_MULTI_GO(mem_reduce_kernel_multi); break;
+        case MK_BIN_CLEAR: CGB_MULTI_GO(bin_clear_kernel_multi); break;
+        case MK_BIN_COUNT: CGB_MULTI_GO(bin_count_kernel_multi); break;
+        case MK_SCAN_LOCAL: CGB_MULTI_GO(scan_local_kernel_multi); break;
+        case MK_SCAN_TOP: CGB_MULTI_GO(scan_top_kernel_multi); break;
+        case MK_SCAN_ADD: CGB_MULTI_GO(scan_add_kernel_multi); break;
+        case MK_BIN_FILL: CGB_MULTI_GO(bin_fill_kernel_multi); break;
+        case MK_BIN_SORT: CGB_MULTI_GO(bin_sort_kernel_multi); break;
+        case MK_SORTED_POS: CGB_MULTI_GO(sorted_pos_kernel_multi); break;
+        case MK_POT:
+            if (m.variant) {
+                CGB_MULTI_GO(potentials_grp_kernel_multi);
+            } else {
+                CGB_MULTI_GO(potentials_kernel_multi);
+            }
+            break;
+        case MK_INT: CGB_MULTI_GO(integrate_kernel_multi); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+#undef CGB_MULTI_GO
 
 }  // namespace cgb
