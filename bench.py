@@ -398,6 +398,8 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=50, help="steps of the per-kernel timing pass")
     ap.add_argument("--serial", action="store_true", help="every kernel in sequence in the timed region too")
     ap.add_argument("--copy-calibrate", action="store_true", help="also run a copy of known size (counter scaling)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the 64-channel ensemble and print its record (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
@@ -405,6 +407,10 @@ def main():
         sys.exit(2)
     if args.copy_calibrate:
         copy_calibration()
+    if args.batch_only:
+        r = batch_leg(steps=args.batch_steps)
+        print(json.dumps({k: v for k, v in r.items() if k != "mu_rel"}), flush=True)
+        return
 
     cfg = synth.config3(n=args.n)
     ns = args.n ** 3

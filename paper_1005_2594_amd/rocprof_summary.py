@@ -71,7 +71,10 @@ def traffic(fetch_csv, write_csv, out, title):
     f_scale = COPY_BYTES / (statistics.median(cf) * 1024.0)
     w_scale = COPY_BYTES / (statistics.median(cw) * 1024.0)
     lb = [k for k in fe if "lb_kernel" in k]
-    steps = max(len(fe[k]) for k in lb)
+    if len(lb) != 1:
+        # per-step figures assume one workload: one LB variant, one launch a step
+        sys.exit(f"expected one LB kernel in the counter run, found {len(lb)}: {lb}")
+    steps = len(fe[lb[0]])
     lines = [f"# {title}", "#",
              "# kernel | dispatches | per step | median fetch KiB | median write KiB | fetch MB per step | write MB per step"]
     tf = tw = 0.0
@@ -88,10 +91,10 @@ def traffic(fetch_csv, write_csv, out, title):
         tf += bf
         tw += bw
         lines.append(f"# {short(k)} | {n} | {per_step} | {mf:.0f} | {mw:.0f} | {bf / 1e6:.1f} | {bw / 1e6:.1f}")
-    for k in lb:  # the fused LB kernel alone, per launch (the roofline's kernel)
-        lines += [f"lb_kernel: {k}",
-                  f"lb_fetch_bytes_per_launch: {statistics.median(fe[k]) * 1024.0 * f_scale:.0f}",
-                  f"lb_write_bytes_per_launch: {statistics.median(wr[k]) * 1024.0 * w_scale:.0f}"]
+    k = lb[0]  # the fused LB kernel alone, per launch (the roofline's kernel)
+    lines += [f"lb_kernel: {k}",
+              f"lb_fetch_bytes_per_launch: {statistics.median(fe[k]) * 1024.0 * f_scale:.0f}",
+              f"lb_write_bytes_per_launch: {statistics.median(wr[k]) * 1024.0 * w_scale:.0f}"]
     lines += ["#", f"copy_bytes: {COPY_BYTES}",
               f"copy_fetch_kib_per_launch: {statistics.median(cf):.0f}",
               f"copy_write_kib_per_launch: {statistics.median(cw):.0f}",
