@@ -147,7 +147,8 @@ struct DevArgs {
     double* track;      // [track_cap][2]: sums of u_z sin(2 pi y/ny) and of u_z
     int* track_n;       // steps recorded (keeps counting past track_cap)
     int track_cap;
-    double* track_part; // per-block partial sums [TRACK_BLOCKS][2]
+    double* track_part; // per-block partial sums [track_slots][2]
+    int track_slots;    // partials track_part holds
     double* ysin;       // [ny] sin(2 pi y / ny)
     // plane-Couette viscometer: Lees-Edwards seam of x (le_u = 0: off)
     double le_u;
@@ -526,6 +527,17 @@ constexpr int TRACK_BLOCKS = 1024;
 __host__ __device__ inline int track_blocks(long long ns) {
     const long long b = (ns + 4095) / 4096;
     return b < 1 ? 1 : (b > TRACK_BLOCKS ? TRACK_BLOCKS : (int)b);
+}
+// blocks of the lattice's LB launch (its tile)
+__host__ __device__ inline long long lb_blocks(const DevArgs& a) {
+    if (a.tile[0] < 1 || a.tile[1] < 1 || a.tile[2] < 1) return 1LL << 62;
+    return (long long)((a.nx + a.tile[0] - 1) / a.tile[0]) * ((a.ny + a.tile[1] - 1) / a.tile[1]) *
+           ((a.nz + a.tile[2] - 1) / a.tile[2]);
+}
+// the tau = 1 LB kernel sums the mixture record itself, one partial per
+// block, when its blocks' partials fit; otherwise a pass of its own does
+__host__ __device__ inline bool track_in_lb(const DevArgs& a) {
+    return a.track && a.tau == 1.0 && lb_blocks(a) <= a.track_slots;
 }
 hipError_t launch_track(const DevArgs& a, hipStream_t st);
 hipError_t launch_pairs(const DevArgs& a, int* out, int* count, int cap, hipStream_t st);

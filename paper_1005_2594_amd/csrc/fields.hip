@@ -262,7 +262,9 @@ static dim3 site_grid(const DevArgs& a) { return dim3((unsigned)((a.ns + 255) / 
 // exactly g to sum n* c), cell nodes the rigid-body velocity of their cell
 // that the bounce-back used (from the cell's kinematics, FP64).  Fixed grid and
 // fixed per-thread site sets, block partials reduced in a fixed order: the
-// sums are deterministic.
+// sums are deterministic.  This pass serves the general-tau kernel (and a
+// tile whose blocks outnumber the partial slots); the tau = 1 kernel sums the
+// same quantity from the velocity of its own collision.
 template <int P>
 __device__ __forceinline__ void track_kernel_body(const DevArgs& a, const KCtx& G) {
     using Cd = Codec<P>;
@@ -327,7 +329,8 @@ __global__ void __launch_bounds__(256) track_kernel_multi(const DevArgs* __restr
 __device__ __forceinline__ void track_finish_kernel_body(const DevArgs& a, const KCtx& G) {
     __shared__ double red[2][256];
     double ss = 0.0, s1 = 0.0;
-    for (int b = threadIdx.x; b < track_blocks(a.ns); b += 256) {
+    const long long nparts = track_in_lb(a) ? lb_blocks(a) : track_blocks(a.ns);
+    for (long long b = threadIdx.x; b < nparts; b += 256) {
         ss += a.track_part[2 * b];
         s1 += a.track_part[2 * b + 1];
     }
@@ -359,7 +362,7 @@ __global__ void __launch_bounds__(256) track_finish_kernel_multi(const DevArgs* 
 
 hipError_t launch_track(const DevArgs& a, hipStream_t st) {
     if (!a.track) return hipSuccess;
-    CGB_DISPATCH(track_kernel, dim3(track_blocks(a.ns)), dim3(256), a);
+    if (!track_in_lb(a)) CGB_DISPATCH(track_kernel, dim3(track_blocks(a.ns)), dim3(256), a);
     hipLaunchKernelGGL(track_finish_kernel, dim3(1), dim3(256), 0, st, a);
     return hipGetLastError();
 }
@@ -371,7 +374,11 @@ bool multi_grid_fields(int kind, const DevArgs& a, int* variant, unsigned* bx, u
     *by = 1;
     *arg = 0;
     if (!a.track) return false;
-    if (kind == MK_TRACK) { *grid = dim3(track_blocks(a.ns)); return true; }
+    if (kind == MK_TRACK) {
+        if (track_in_lb(a)) return false;  // the LB kernel sums this channel's record
+        *grid = dim3(track_blocks(a.ns));
+        return true;
+    }
     if (kind == MK_TRACK_FIN) { *grid = dim3(1); return true; }
     return false;
 }

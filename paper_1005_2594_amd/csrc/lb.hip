@@ -461,6 +461,39 @@ template <> struct LbMem<true> {
 // storage index comes from the map cidx (one load per neighbour), walls
 // store nothing.
 constexpr int LAY_DENSE = 0, LAY_BIG = 1, LAY_IDX = 2;
+
+// The block's share of the mixture record (the quantity of the track pass:
+// u_z of the collision at fluid nodes, the cell's rigid-body u_z at cell
+// nodes, summed over the non-wall nodes with weights sin(2 pi y/ny) and 1):
+// t is the thread's sum over its sweep at row y.  Butterfly sums within each
+// wave, then the waves in order: a fixed order, so the record is
+// deterministic.  Partial slot: the block's index in its lattice's grid.
+__device__ __forceinline__ void lb_track_partial(const DevArgs& a, const KCtx& G, double t, int y) {
+    __shared__ double red[2][4];
+    double p0 = t * a.ysin[y], p1 = t;
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        p0 += __shfl_xor(p0, m, 64);
+        p1 += __shfl_xor(p1, m, 64);
+    }
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    const int nw = (blockDim.x * blockDim.y) / 64;
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = p0;
+        red[1][tid >> 6] = p1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int w = 0; w < nw; w++) {
+            s0 += red[0][w];
+            s1 += red[1][w];
+        }
+        const long long slot = G.bx + (long long)G.gx * (G.by + (long long)G.gy * G.bz);
+        a.track_part[2 * slot] = s0;
+        a.track_part[2 * slot + 1] = s1;
+    }
+}
 template <int P, int TZ, int LAY>
 __device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx& G) {
     using Cd = Codec<P>;
@@ -496,6 +529,8 @@ __device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx
     const bool f0on = inb && z0 < a.nz;
     const uint32_t f0v = mFl.template ld<uint32_t>((I)x + nx * (I)y + plane * (I)z0, f0on);
     uint32_t fnext = f0on ? f0v : NONFLUID;
+    // mixture record: this thread's sum of u_z over its nodes (y is fixed)
+    R tacc = 0;
 #pragma unroll 1
     for (int zz = 0; zz < TZ; zz++) {
         const int z = z0 + zz;
@@ -607,6 +642,7 @@ __device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx
                 F[1] = m1;
                 F[2] = m2;
             }
+            tacc += (R)km[2];  // the rigid-body u_z the bounce-back used
         }
         T ob[19], orho;
 #pragma unroll
@@ -658,6 +694,7 @@ __device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx
         const R ux = (jx + (R)0.5 * gx) * irho, uy = (jy + (R)0.5 * gy) * irho, uz = (jz + (R)0.5 * gz) * irho;
         const R usq = ux * ux + uy * uy + uz * uz;
         const R ug = ux * gx + uy * gy + uz * gz;
+        tacc += uz;
         // the collision conserves mass: the density deviation of n* is drho.
         // Split codec: the stored outputs are n*_r - w_r (rho0 + Dq), with Dq
         // the decoded stored density, so drho enters as drho - Dq
@@ -691,6 +728,7 @@ __device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx
             mRB.template st<T>(orho, ci);
         }
     }
+    if (track_in_lb(a)) lb_track_partial(a, G, inb ? (double)tacc : 0.0, yc);
 }
 template <int P, int TZ, int LAY>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LAY == LAY_DENSE ? 4 : 3))) lb_kernel_tau1(DevArgs a) { lb_kernel_tau1_body<P, TZ, LAY>(a, hw_ctx()); }

@@ -438,7 +438,14 @@ static int alloc_state(cgb_sim* s, int cell_cap, int track_cap) {
     HIPCHK(s, dalloc(s, &a.dstep, 16));
     HIPCHK(s, dalloc(s, &s->obs_partial, (size_t)s->obs_nblk * 8 * 8));
     HIPCHK(s, dalloc(s, &a.ysin, (size_t)a.ny * 8));
-    HIPCHK(s, dalloc(s, &a.track_part, (size_t)TRACK_BLOCKS * 2 * 8));
+    {
+        // partials of the mixture record: one per LB block (the tau = 1
+        // kernel sums the record), at least the track pass's
+        const LaunchCfg d = default_tiles(a);
+        const long long nb = (long long)((a.nx + d.bx - 1) / d.bx) * ((a.ny + d.by - 1) / d.by) * ((a.nz + d.tz - 1) / d.tz);
+        a.track_slots = (int)std::max<long long>(TRACK_BLOCKS, nb);
+        HIPCHK(s, dalloc(s, &a.track_part, (size_t)a.track_slots * 2 * 8));
+    }
     HIPCHK(s, dalloc(s, &a.track_n, 16));
     HIPCHK(s, dalloc(s, &a.bin_count, (size_t)a.nbins * 4));
     HIPCHK(s, dalloc(s, &a.bin_start, (size_t)(a.nbins + 1) * 4));
@@ -1081,6 +1088,16 @@ int cgb_set_tiles(cgb_sim* s, int32_t bx, int32_t by, int32_t tz) {
         FAIL(s, CGB_EINVAL, "tile %dx%dx%d: the large-lattice and indexed layouts sweep 16 nodes (tz = 16)", bx, by, tz);
     HIPCHK(s, hipStreamSynchronize(s->st));
     set_tiles(s, LaunchCfg{bx, by, tz});
+    // more LB blocks than mixture-record partials: own memory grows; in
+    // caller-provided memory the record falls back to its own pass
+    const long long nb = lb_blocks(s->a);
+    if (s->mem_mode == MEM_OWN && nb > s->a.track_slots && nb < (1LL << 31)) {
+        double* np = nullptr;
+        HIPCHK(s, dalloc(s, &np, (size_t)nb * 2 * 8));
+        dfree(s, s->a.track_part);
+        s->a.track_part = np;
+        s->a.track_slots = (int)nb;
+    }
     return CGB_OK;
 }
 
