@@ -1,14 +1,19 @@
 // batch.hip -- ensemble of independent, uneven lattices advanced together.
 //
-// Each channel is a full lattice handle with its own stream.  The time steps
-// of all channels are captured once into a HIP graph: a fork event on the
-// master stream fans out to the channel streams, each channel enqueues its
-// step sequence, and join events fan back in, so the replayed graph runs the
-// channels concurrently with one launch.  An even number of steps is captured
-// so that the two population buffers of every channel are back in their
-// starting roles after each replay; the step index lives in device memory,
-// so replays advance it.  The autotuner times the fused LB kernel for a set
-// of tile shapes on one channel of each width class and applies the fastest.
+// Each channel is a full lattice handle.  When every channel runs the dense
+// tau = 1 path in one storage precision, a step is one launch per kernel for
+// all channels: the channels are grouped by kernel variant and block shape,
+// and a group's launch holds the channels' own grids back to back; each block
+// finds its channel in a block table and works on that channel's device
+// arguments (both roles of the population buffers are uploaded once, so the
+// launches alternate between two argument tables).  Otherwise each channel
+// enqueues its own step sequence on its own stream between a fork and join
+// events.  Either form is captured into one HIP graph.  An even number of
+// steps is captured so that the two population buffers of every channel are
+// back in their starting roles after each replay; the step index lives in
+// device memory, so replays advance it.  The autotuner times the fused LB
+// kernel for a set of tile shapes on one channel of each width class and
+// applies the fastest.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
