@@ -297,6 +297,26 @@ __device__ inline int xcd_block(int b, int nb) {
     return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
+// A launch over every channel of a batch, likewise: the block index goes
+// through xcd_block before the channel table is read, so each XCD takes a
+// contiguous run of each channel's tiles.  The LB tiles of the batch's
+// narrow channels are 32 or 64 nodes wide, so every pull along x reads a
+// line its neighbouring tile reads too; with neighbouring tiles on one XCD
+// that line is fetched into one L2 (the 64-channel ensemble steps 4 % faster);
+// the link-moment patches share their halo rows the same way.
+// A lattice 256 nodes wide, swept in whole rows, shares lines only at
+// bounced populations, and its launch keeps the hardware order (there the
+// mapping costs 2 %).
+__device__ __forceinline__ int chan_of_xcd(const ChanGrid* cg, int nch, unsigned* t) {
+    *t = (unsigned)xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int* blk = (const int*)(cg + nch);
+    return __builtin_amdgcn_readfirstlane(blk[*t]);
+}
+__device__ __forceinline__ KCtx chan_ctx_at(const ChanGrid& q, unsigned t) {
+    const unsigned l = t - q.start;
+    return KCtx{l % q.gx, (l / q.gx) % q.gy, l / (q.gx * q.gy), q.gx, q.gy, q.gz};
+}
+
 // v in [-1, n + patch width - 1] reduced to [0, n)
 __device__ inline int wrap_halo(int v, int n) {
     if (v < 0) v += n;

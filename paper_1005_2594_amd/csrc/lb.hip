@@ -734,8 +734,9 @@ template <int P, int TZ, int LAY>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LAY == LAY_DENSE ? 4 : 3))) lb_kernel_tau1(DevArgs a) { lb_kernel_tau1_body<P, TZ, LAY>(a, hw_ctx()); }
 template <int P, int TZ, int LAY>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LAY == LAY_DENSE ? 4 : 3))) lb_kernel_tau1_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
-    const int c = chan_of(cg, nch);
-    lb_kernel_tau1_body<P, TZ, LAY>(as[c], chan_ctx(cg[c]));
+    unsigned t;
+    const int c = chan_of_xcd(cg, nch, &t);
+    lb_kernel_tau1_body<P, TZ, LAY>(as[c], chan_ctx_at(cg[c], t));
 }
 
 

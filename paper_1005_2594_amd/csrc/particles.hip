@@ -714,8 +714,9 @@ template <class M, int TX, int NC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(M) == 4 ? 8 : 5))) lmom_kernel(DevArgs a, int tz) { lmom_kernel_body<M, TX, NC>(a, hw_ctx(), tz); }
 template <class M, int TX, int NC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(M) == 4 ? 8 : 5))) lmom_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
-    const int c = chan_of(cg, nch);
-    lmom_kernel_body<M, TX, NC>(as[c], chan_ctx(cg[c]), cg[c].arg);
+    unsigned t;
+    const int c = chan_of_xcd(cg, nch, &t);
+    lmom_kernel_body<M, TX, NC>(as[c], chan_ctx_at(cg[c], t), cg[c].arg);
 }
 
 

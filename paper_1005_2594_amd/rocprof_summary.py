@@ -2,6 +2,7 @@
 
     python -m paper_1005_2594_amd.rocprof_summary trace <kernel_trace.csv> <out.md> <title>
     python -m paper_1005_2594_amd.rocprof_summary traffic <fetch_counter.csv> <write_counter.csv> <out.txt> <title>
+    python -m paper_1005_2594_amd.rocprof_summary sizes <rdreq_counter.csv> <out.md> <title>
 
 trace: per kernel, calls and the average, minimum, maximum and median
 duration of its dispatches.
@@ -11,6 +12,8 @@ step; kernels of the set-up only round to none and are left out); the counters (
 into bytes with the factor a plain device copy of 2^31 bytes gives in the
 same run (the largest copy dispatches); the per-step sums over all kernels,
 and the hash of the library's HIP sources they belong to.
+sizes: per kernel, the read requests split by size (32, 64, 128 bytes) and
+the exact read bytes they make.
 """
 from __future__ import annotations
 
@@ -106,10 +109,43 @@ def traffic(fetch_csv, write_csv, out, title):
     open(out, "w").write("\n".join(lines) + "\n")
 
 
+def sizes(csv_path, out, title):
+    """Read bytes per kernel from the request-size counters (TCC_EA0_RDREQ
+    split into 32-, 64- and 128-byte requests): exact bytes with no scaling,
+    a check of the copy-scaled FETCH_SIZE (which counts a 128-byte request
+    as 64 bytes on this device)."""
+    per = defaultdict(lambda: defaultdict(list))
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            per[row["Kernel_Name"]][row["Counter_Name"]].append(float(row["Counter_Value"]))
+    names = ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum")
+    lines = [f"# {title}", "",
+             "| kernel | dispatches | median requests | 128 B | 64 B | 32 B | read MB (exact) | share of 128 B requests |",
+             "|---|---|---|---|---|---|---|---|"]
+    rows = []
+    for k, c in per.items():
+        if not all(n in c for n in names):
+            continue
+        if "copyBuffer" in k:  # the calibration copies only (the largest dispatches)
+            idx = sorted(range(len(c[names[0]])), key=lambda i: c[names[0]][i])[-4:]
+            med = {n: statistics.median(c[n][i] for i in idx) for n in names}
+        else:
+            med = {n: statistics.median(c[n]) for n in names}
+        byts = 32 * med[names[1]] + 64 * med[names[2]] + 128 * med[names[3]]
+        rows.append((byts, k, len(c[names[0]]), med))
+    for byts, k, n, med in sorted(rows, reverse=True)[:16]:
+        tot = max(med[names[0]], 1.0)
+        lines.append(f"| `{short(k)}` | {n} | {med[names[0]]:.0f} | {med[names[3]]:.0f} | {med[names[2]]:.0f} | "
+                     f"{med[names[1]]:.0f} | {byts / 1e6:.1f} | {med[names[3]] / tot:.4f} |")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "trace":
         trace(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5])
+    elif sys.argv[1] == "sizes":
+        sizes(sys.argv[2], sys.argv[3], sys.argv[4])
     else:
         raise SystemExit(__doc__)
