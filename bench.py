@@ -232,7 +232,7 @@ def batch_leg(steps=2000, seed=4, prec="pmx16"):
     for s, c in zip(b.channels, chans):
         s.set_particles(c["X"], c["q"])
         s.init_fluid()
-    tiles = b.autotune(reps=5)
+    tiles = b.autotune(reps=20)
     b.track(steps)
     b.capture(2)
     b.sync()

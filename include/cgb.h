@@ -359,9 +359,15 @@ int cgb_load(cgb_sim* s, const char* path);
 
 /* Launch shape of the fused LB kernel: bx*by threads per block (a multiple
  * of 64, at most 256) covering a bx x by patch of an x-y plane, each thread
- * sweeping tz consecutive z nodes (tz in {4, 8, 16, 32}).  Results do not
- * depend on the shape except for the summation order of the per-cell FP64
- * force sums.  cgb_get_tiles: t[3] = (bx, by, tz). */
+ * sweeping tz consecutive z nodes (tz in {4, 8, 16, 32}).  by = 0 (tau = 1
+ * only): bx threads per block cover bx consecutive sites of the flattened
+ * x-y plane (index x + nx*y), so every lane has a node whatever nx is; the
+ * form for narrow lattices, whose rows a 2-D patch covers only in part.
+ * The populations and forces do not depend on the shape; the mixture record
+ * (cgb_track) depends on it through the summation order of its per-block
+ * partials.  Errors: CGB_EINVAL for a shape outside these sets, by = 0 at
+ * tau != 1, or tz != 16 in the large-lattice and indexed layouts.
+ * cgb_get_tiles: t[3] = (bx, by, tz). */
 int cgb_set_tiles(cgb_sim* s, int32_t bx, int32_t by, int32_t tz);
 int cgb_get_tiles(cgb_sim* s, int32_t* t);
 /* Average duration in milliseconds (HIP events on the handle's stream) of

@@ -282,38 +282,98 @@ int cgb_batch_channel(cgb_batch* b, int32_t c, cgb_sim** out) {
     return CGB_OK;
 }
 
-// Times the fused LB kernel (which only reads the current state and writes
-// buffers every step rewrites) for candidate tile shapes on the first channel
-// of each width class and applies the fastest to the whole class.
+// The LB launches of the fused plan alone, for the current tiles: they read
+// the current populations and write only buffers that every step rewrites
+// before reading them (the other population buffer and its densities, the
+// cell nodes' momenta, the mixture partials), so the state is unchanged.
+static int time_fused_lb(cgb_batch* b, int reps, double* ms_avg) {
+    int rc = build_plan(b);
+    if (rc) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    auto lb_pass = [&]() {
+        size_t off = 0;
+        for (const MultiLaunch& m : b->plan) {
+            if (m.kind == MK_LB && e == hipSuccess) e = launch_multi(m, b->plan_args[0] + off, b->master);
+            off += (size_t)m.nch;
+        }
+    };
+    for (int k = 0; k < 2; k++) lb_pass();
+    if (e == hipSuccess) e = hipEventRecord(e0, b->master);
+    for (int k = 0; k < reps; k++) lb_pass();
+    if (e == hipSuccess) e = hipEventRecord(e1, b->master);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    drop_plan(b);
+    if (e != hipSuccess) BFAIL(b, CGB_EDEVICE, "LB timing: %s", hipGetErrorString(e));
+    *ms_avg = (double)ms / reps;
+    return CGB_OK;
+}
+
+// Chooses the LB tile shape per width class of the channels.  Fused batches
+// (one launch per kernel for every channel): what counts is the time of the
+// whole fused LB launch, so each class in turn tries every candidate with the
+// other classes' shapes fixed, and keeps the one whose fused launches take
+// least.  Otherwise: the LB kernel alone on the first channel of each class.
 // chosen: nullable, nch*3 ints (bx, by, tz).
 int cgb_batch_autotune(cgb_batch* b, int32_t reps, int32_t* chosen) {
     if (!b || reps < 1) return CGB_EINVAL;
     drop_graph(b);
-    static const LaunchCfg cand[] = {{64, 4, 8}, {64, 4, 16}, {32, 8, 8}, {32, 8, 16}, {16, 16, 16}, {64, 2, 16}, {32, 4, 16}};
     std::map<int, std::vector<int>> classes;  // width class -> channels
     for (size_t c = 0; c < b->ch.size(); c++) {
         const int w = b->ch[c]->a.nx;
         classes[w < 48 ? 0 : (w < 80 ? 1 : 2)].push_back((int)c);
     }
     int rc = CGB_OK;
-    for (auto& kv : classes) {
-        cgb_sim* s = b->ch[(size_t)kv.second[0]];
-        LaunchCfg best = s->lbcfg;
-        double best_ms = 1e30;
-        for (const LaunchCfg& cf : cand) {
-            if ((rc = sim_set_tiles(s, cf)) != CGB_OK) break;
-            double ms = 0.0;
-            if ((rc = cgb_time_lb(s, reps, &ms)) != CGB_OK) break;
-            if (ms < best_ms) { best_ms = ms; best = cf; }
+    if (fusable(b)) {
+        // plane-linear tiles (by = 0) keep every lane busy on rows of any width
+        static const LaunchCfg fcand[] = {{64, 0, 8}, {128, 0, 8}, {256, 0, 8}, {64, 0, 16}, {256, 0, 16},
+                                          {32, 8, 8}, {64, 4, 8}, {32, 8, 16}, {64, 4, 16}};
+        for (cgb_sim* s : b->ch) BCHK(b, hipStreamSynchronize(s->st));
+        for (auto& kv : classes) {
+            LaunchCfg best = b->ch[(size_t)kv.second[0]]->lbcfg;
+            double best_ms = 1e30;
+            for (const LaunchCfg& cf : fcand) {
+                for (int c : kv.second)
+                    if ((rc = sim_set_tiles(b->ch[(size_t)c], cf)) != CGB_OK) break;
+                if (rc) break;
+                double ms = 0.0;
+                if ((rc = time_fused_lb(b, reps, &ms)) != CGB_OK) return rc;
+                if (ms < best_ms) { best_ms = ms; best = cf; }
+            }
+            if (rc) break;
+            for (int c : kv.second)
+                if ((rc = sim_set_tiles(b->ch[(size_t)c], best)) != CGB_OK) break;
+            if (rc) break;
         }
-        if (rc) break;
-        for (int c : kv.second) {
-            if ((rc = sim_set_tiles(b->ch[(size_t)c], best)) != CGB_OK) break;
-            if (chosen) { chosen[3 * c] = best.bx; chosen[3 * c + 1] = best.by; chosen[3 * c + 2] = best.tz; }
+    } else {
+        static const LaunchCfg cand[] = {{64, 4, 8}, {64, 4, 16}, {32, 8, 8}, {32, 8, 16}, {16, 16, 16}, {64, 2, 16}, {32, 4, 16}};
+        for (auto& kv : classes) {
+            cgb_sim* s = b->ch[(size_t)kv.second[0]];
+            LaunchCfg best = s->lbcfg;
+            double best_ms = 1e30;
+            for (const LaunchCfg& cf : cand) {
+                if ((rc = sim_set_tiles(s, cf)) != CGB_OK) break;
+                double ms = 0.0;
+                if ((rc = cgb_time_lb(s, reps, &ms)) != CGB_OK) break;
+                if (ms < best_ms) { best_ms = ms; best = cf; }
+            }
+            if (rc) break;
+            for (int c : kv.second)
+                if ((rc = sim_set_tiles(b->ch[(size_t)c], best)) != CGB_OK) break;
+            if (rc) break;
         }
-        if (rc) break;
     }
     if (rc) BFAIL(b, rc, "autotune failed: %s", cgb_last_error(b->ch[0]));
+    if (chosen)
+        for (size_t c = 0; c < b->ch.size(); c++) {
+            const LaunchCfg& k = b->ch[c]->lbcfg;
+            chosen[3 * c] = k.bx; chosen[3 * c + 1] = k.by; chosen[3 * c + 2] = k.tz;
+        }
     return CGB_OK;
 }
 

@@ -550,9 +550,11 @@ __host__ __device__ inline int track_blocks(long long ns) {
 }
 // blocks of the lattice's LB launch (its tile)
 __host__ __device__ inline long long lb_blocks(const DevArgs& a) {
-    if (a.tile[0] < 1 || a.tile[1] < 1 || a.tile[2] < 1) return 1LL << 62;
-    return (long long)((a.nx + a.tile[0] - 1) / a.tile[0]) * ((a.ny + a.tile[1] - 1) / a.tile[1]) *
-           ((a.nz + a.tile[2] - 1) / a.tile[2]);
+    if (a.tile[0] < 1 || a.tile[1] < 0 || a.tile[2] < 1) return 1LL << 62;
+    const long long nz = (a.nz + a.tile[2] - 1) / a.tile[2];
+    if (a.tile[1] == 0)  // plane-linear: bx consecutive sites of the x-y plane per block
+        return ((long long)a.nx * a.ny + a.tile[0] - 1) / a.tile[0] * nz;
+    return (long long)((a.nx + a.tile[0] - 1) / a.tile[0]) * ((a.ny + a.tile[1] - 1) / a.tile[1]) * nz;
 }
 // the tau = 1 LB kernel sums the mixture record itself, one partial per
 // block, when its blocks' partials fit; otherwise a pass of its own does

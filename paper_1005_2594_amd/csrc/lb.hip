@@ -503,10 +503,21 @@ __device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx
     constexpr bool BIG = LAY == LAY_BIG, IDX = LAY == LAY_IDX;
     using Mem = LbMem<BIG>;
     using I = typename Mem::I;
-    const int x = G.bx * blockDim.x + threadIdx.x;
-    const int y = G.by * blockDim.y + threadIdx.y;
+    // the thread's column (x, y): from a bx x by patch, or (plane-linear
+    // tiles, by = 0) from bx consecutive sites of the flattened x-y plane
+    int x, y;
+    bool inb;
+    if (a.tile[1] == 0) {
+        const int q = (int)(G.bx * blockDim.x + threadIdx.x);
+        y = q / a.nx;
+        x = q - y * a.nx;
+        inb = y < a.ny;
+    } else {
+        x = (int)(G.bx * blockDim.x + threadIdx.x);
+        y = (int)(G.by * blockDim.y + threadIdx.y);
+        inb = (x < a.nx) && (y < a.ny);
+    }
     const int z0 = G.bz * TZ;
-    const bool inb = (x < a.nx) && (y < a.ny);
     const I nx = (I)a.nx;
     const I plane = (I)a.nx * (I)a.ny;
     const I ps = (I)a.pstride;  // narrow: every offset fits 32 bits (checked at create)
@@ -742,9 +753,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LAY ==
 
 template <int P>
 static hipError_t launch_lb_p(const DevArgs& a, LaunchCfg cfg, hipStream_t st) {
-    dim3 blk(cfg.bx, cfg.by, 1);
-    dim3 grd((a.nx + cfg.bx - 1) / cfg.bx, (a.ny + cfg.by - 1) / cfg.by, (a.nz + cfg.tz - 1) / cfg.tz);
+    const bool lin = cfg.by == 0;  // plane-linear tiles (tau = 1, checked when set)
+    dim3 blk(cfg.bx, lin ? 1 : cfg.by, 1);
+    dim3 grd(lin ? (unsigned)(((long long)a.nx * a.ny + cfg.bx - 1) / cfg.bx) : (unsigned)((a.nx + cfg.bx - 1) / cfg.bx),
+             lin ? 1u : (unsigned)((a.ny + cfg.by - 1) / cfg.by), (a.nz + cfg.tz - 1) / cfg.tz);
     const bool t1 = a.tau == 1.0;
+    if (lin && !t1) return hipErrorInvalidValue;
     if (a.big || a.cidx) {
         // the large-lattice and indexed layouts: tau = 1 and 16-node sweeps
         // only (checked when the handle is created and when tiles are set)
@@ -781,14 +795,17 @@ bool multi_grid_lb(const DevArgs& a, LaunchCfg cfg, int* variant, unsigned* bx, 
     if (a.tau != 1.0 || a.big || a.cidx || a.le_u != 0.0) return false;
     *variant = a.precision * 64 + cfg.tz;
     *bx = (unsigned)cfg.bx;
-    *by = (unsigned)cfg.by;
-    *grid = dim3((a.nx + cfg.bx - 1) / cfg.bx, (a.ny + cfg.by - 1) / cfg.by, (a.nz + cfg.tz - 1) / cfg.tz);
+    *by = (unsigned)cfg.by;  // 0: plane-linear tiles (a launch of its own, blocks of bx x 1)
+    if (cfg.by == 0)
+        *grid = dim3((unsigned)(((long long)a.nx * a.ny + cfg.bx - 1) / cfg.bx), 1, (a.nz + cfg.tz - 1) / cfg.tz);
+    else
+        *grid = dim3((a.nx + cfg.bx - 1) / cfg.bx, (a.ny + cfg.by - 1) / cfg.by, (a.nz + cfg.tz - 1) / cfg.tz);
     return true;
 }
 
 template <int P>
 static hipError_t launch_multi_lb_p(const MultiLaunch& m, const DevArgs* args, hipStream_t st, int tz) {
-    const dim3 g(m.blocks), b(m.bx, m.by);
+    const dim3 g(m.blocks), b(m.bx, m.by ? m.by : 1);
     switch (tz) {
         case 4: hipLaunchKernelGGL((lb_kernel_tau1_multi<P, 4, LAY_DENSE>), g, b, 0, st, args, m.cg, m.nch); break;
         case 8: hipLaunchKernelGGL((lb_kernel_tau1_multi<P, 8, LAY_DENSE>), g, b, 0, st, args, m.cg, m.nch); break;

@@ -1082,8 +1082,11 @@ int cgb_kernel_times(cgb_sim* s, char* names, double* ms, int64_t* count, int32_
 // ---------------------------------------------------------------- tiles
 int cgb_set_tiles(cgb_sim* s, int32_t bx, int32_t by, int32_t tz) {
     if (!s) return CGB_EINVAL;
-    if (bx < 1 || by < 1 || bx * by > 256 || (bx * by) % 64 != 0 || !(tz == 4 || tz == 8 || tz == 16 || tz == 32))
-        FAIL(s, CGB_EINVAL, "tile %dx%dx%d: need bx*by a multiple of 64, at most 256, tz in {4,8,16,32}", bx, by, tz);
+    const int nt = by == 0 ? bx : bx * by;  // by = 0: plane-linear tiles of bx sites
+    if (bx < 1 || by < 0 || nt > 256 || nt % 64 != 0 || !(tz == 4 || tz == 8 || tz == 16 || tz == 32))
+        FAIL(s, CGB_EINVAL, "tile %dx%dx%d: need bx*by (bx when by = 0) a multiple of 64, at most 256, tz in {4,8,16,32}", bx, by, tz);
+    if (by == 0 && s->a.tau != 1.0)
+        FAIL(s, CGB_EINVAL, "tile %dx0x%d: plane-linear tiles need tau = 1", bx, tz);
     if ((s->a.big || s->a.cidx) && tz != 16)
         FAIL(s, CGB_EINVAL, "tile %dx%dx%d: the large-lattice and indexed layouts sweep 16 nodes (tz = 16)", bx, by, tz);
     HIPCHK(s, hipStreamSynchronize(s->st));
