@@ -9,15 +9,19 @@ from the decoded populations, FP64 integration.  Beside it: FP16 deviations stor
 direction alone (the same storage size, ~8x the velocity error) and the
 FP32-storage path.  One step = every kernel of the time
 step (rasterisation, cover/uncover, fused LB, momentum-exchange reduction,
-cell list, pair and wall forces, integration).  Inputs are resident in HBM
-before the timed region.
+cell list, pair and wall forces, integration, the per-step mixture record of
+the apparent viscosity).  Inputs are resident in HBM before the timed region.
 
 Also reported (in "config"): the error of every path against the FP64
 oracle on the 64^3 companion workload, stepped in lockstep on the host cores,
 with the oracle's own response to perturbed inputs beside it; the
 whole-step effective and counter bandwidths; the batched ensemble of 64
-uneven channels (one replayed HIP graph, autotuned LB tiles, apparent
-viscosity per channel), and the oracle on the host cores ("cpu_baseline").
+uneven channels (one launch per kernel for all channels, one replayed HIP
+graph, LB tiles tuned on the fused launch, apparent viscosity per channel);
+the vessel bifurcation with stenosis in the dense and the indexed layouts;
+the paper's 1024^2 x 2048 system with 4.1e6 cells in the large-lattice
+layout (when the device has the memory free); and the oracle on the host
+cores ("cpu_baseline").
 
 Prints one JSON line.  --gpus N > 1 exits: this build runs on one GPU.
 """
