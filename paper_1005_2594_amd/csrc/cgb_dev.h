@@ -361,7 +361,15 @@ template <> struct Codec<CGB_PMX16> {
     using R = float;
     static constexpr bool SPLIT = false;
     __device__ static R dec(T v, R s) { return (float)v * s; }
-    __device__ static T enc(R v, R s) { return (_Float16)(v * s); }
+    __device__ static T enc(R v, R s) {
+        // the product rounded to FP32, then to FP16 (RNE), in every kernel.
+        // Without the barrier the compiler may fuse the two into one
+        // mixed-precision rounding (v_fma_mixlo_f16) in some kernel variants
+        // and not in others, and halfway cases then round differently.
+        float p = v * s;
+        asm volatile("" : "+v"(p));
+        return (_Float16)p;
+    }
 };
 template <> struct Codec<CGB_PMXBF16> {
     using T = uint16_t;

@@ -542,6 +542,22 @@ __device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx
     uint32_t fnext = f0on ? f0v : NONFLUID;
     // mixture record: this thread's sum of u_z over its nodes (y is fixed)
     R tacc = 0;
+    // indexed layout: the storage indices a node needs, loaded one node
+    // ahead.  mc[0] is the node's own, mc[q] that of its neighbour x - c_q: a
+    // fluid lane pulls direction r from mc[r], a cell lane's link along c_r
+    // reads the node x + c_r = mc[rbar].  The set does not depend on the
+    // node's flags, so the next node's loads are issued while this node is
+    // computed (masked at walls by the prefetched flag word).
+    int mc[19];
+    // (ox, oy: the x and y offsets of x - c, index c + 1; their middle entries are 0)
+    auto map_loads = [&](const int* ox, const int* oy, I iq, int zq, bool on, int* out) {
+        const int ozq[3] = {zq == a.nz - 1 ? -(int)((a.nz - 1) * plane) : (int)plane, 0,
+                            zq == 0 ? (int)((a.nz - 1) * plane) : -(int)plane};
+#pragma unroll
+        for (int q = 0; q < 19; q++)
+            out[q] = mC.template ld<int>(iq + (I)(ox[CX(q) + 1] + oy[CY(q) + 1] + ozq[CZ(q) + 1]), on);
+    };
+    if constexpr (IDX) map_loads(oxs, oys, (I)x + nx * (I)y + plane * (I)z0, z0, f0on && !(f0v & WALLNODE), mc);
 #pragma unroll 1
     for (int zz = 0; zz < TZ; zz++) {
         const int z = z0 + zz;
@@ -578,12 +594,10 @@ __device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx
         I ci = i;
         int cw = 0;
         if constexpr (IDX) {
-            const int cv = mC.template ld<int>(i, inb);
-            cw = inb ? cv : -1;
+            cw = (inb && !(f & WALLNODE)) ? mc[0] : -1;
             ci = (I)cw;
         }
         T v[19];
-        int nbi[19];  // indexed layout: storage index of each cell-lane link's fluid node
 #pragma unroll
         for (int r = 0; r < 19; r++) {
             const bool bb = (f >> r) & 1u;
@@ -591,11 +605,7 @@ __device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx
             I e;
             bool on;
             if constexpr (IDX) {
-                const int offp = ox[CX(r) + 1] + oy[CY(r) + 1] + oz[CZ(r) + 1];
-                const int offc = ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)];
-                const bool pl = fl && !bb;
-                const int nb = mC.template ld<int>(i + (I)(lnk ? offc : offp), pl || lnk);
-                nbi[r] = nb;
+                const int nb = lnk ? mc[OPP(r)] : mc[r];
                 e = lnk ? (I)OPP(r) * ps + (I)nb : (bb ? (I)OPP(r) * ps + ci : (I)r * ps + (I)nb);
                 on = lnk || fl;
             } else {
@@ -620,11 +630,16 @@ __device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx
 #pragma unroll
         for (int r = 1; r < 19; r++) {
             const bool lnk = cn && !((f >> OPP(r)) & 1u);
-            if constexpr (IDX) dn[r] = mRA.template ld<T>((I)nbi[r], lnk);
+            if constexpr (IDX) dn[r] = mRA.template ld<T>((I)mc[OPP(r)], lnk);
             else dn[r] = mRA.template ld<T>(i + (I)(ox[1 - CX(r)] + oy[1 - CY(r)] + oz[1 - CZ(r)]), lnk);
         }
+        int mn[19];
+        if constexpr (IDX) map_loads(ox, oy, i + plane, z + 1, fnon && !(fnv & WALLNODE), mn);
         double m0 = 0, m1 = 0, m2 = 0;
         if (cn) {
+            // fused multiply-adds only within one expression, so that every
+            // compiled variant of this kernel rounds the sums below alike
+#pragma clang fp contract(on)
             // the momentum the node's links carry to its cell (Eq. 12): the
             // neighbour x = s + c_r bounces n*_rbar(x) into direction r and the
             // correction C_r = 6 w_r rho(x) (c_r . u(s)) (Eq. 10) is added, so the
@@ -737,6 +752,10 @@ __device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx
 #pragma unroll
             for (int r = 0; r < 19; r++) mB.template st<T>(ob[r], (I)r * ps + ci);
             mRB.template st<T>(orho, ci);
+        }
+        if constexpr (IDX) {
+#pragma unroll
+            for (int q = 0; q < 19; q++) mc[q] = mn[q];
         }
     }
     if (track_in_lb(a)) lb_track_partial(a, G, inb ? (double)tacc : 0.0, yc);
