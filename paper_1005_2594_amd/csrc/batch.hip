@@ -318,7 +318,8 @@ static int time_fused_lb(cgb_batch* b, int reps, double* ms_avg) {
 // (one launch per kernel for every channel): what counts is the time of the
 // whole fused LB launch, so each class in turn tries every candidate with the
 // other classes' shapes fixed, and keeps the one whose fused launches take
-// least.  Otherwise: the LB kernel alone on the first channel of each class.
+// least; then every candidate for all channels at once is timed against that
+// result.  Otherwise: the LB kernel alone on the first channel of each class.
 // chosen: nullable, nch*3 ints (bx, by, tz).
 int cgb_batch_autotune(cgb_batch* b, int32_t reps, int32_t* chosen) {
     if (!b || reps < 1) return CGB_EINVAL;
@@ -349,6 +350,25 @@ int cgb_batch_autotune(cgb_batch* b, int32_t reps, int32_t* chosen) {
             for (int c : kv.second)
                 if ((rc = sim_set_tiles(b->ch[(size_t)c], best)) != CGB_OK) break;
             if (rc) break;
+        }
+        // one shape for every channel (one LB launch): a change no single
+        // class's step above can make once the classes' shapes differ
+        if (!rc && classes.size() > 1) {
+            std::vector<LaunchCfg> tuned;
+            for (cgb_sim* s : b->ch) tuned.push_back(s->lbcfg);
+            double best_ms = 0.0;
+            if ((rc = time_fused_lb(b, reps, &best_ms)) != CGB_OK) return rc;
+            const LaunchCfg* uni = nullptr;
+            for (const LaunchCfg& cf : fcand) {
+                for (cgb_sim* s : b->ch)
+                    if ((rc = sim_set_tiles(s, cf)) != CGB_OK) break;
+                if (rc) break;
+                double ms = 0.0;
+                if ((rc = time_fused_lb(b, reps, &ms)) != CGB_OK) return rc;
+                if (ms < best_ms) { best_ms = ms; uni = &cf; }
+            }
+            for (size_t c = 0; c < b->ch.size() && !rc; c++)
+                rc = sim_set_tiles(b->ch[c], uni ? *uni : tuned[c]);
         }
     } else {
         static const LaunchCfg cand[] = {{64, 4, 8}, {64, 4, 16}, {32, 8, 8}, {32, 8, 16}, {16, 16, 16}, {64, 2, 16}, {32, 4, 16}};

@@ -326,35 +326,56 @@ __global__ void __launch_bounds__(256) track_kernel_multi(const DevArgs* __restr
 }
 
 
+// One workgroup of FIN_THREADS adds the partials: thread t the partials t,
+// t + FIN_THREADS, ... in that order (loads issued eight at a time), then the
+// threads in a fixed tree: the record is deterministic.
+constexpr int FIN_THREADS = 1024;
 __device__ __forceinline__ void track_finish_kernel_body(const DevArgs& a, const KCtx& G) {
-    __shared__ double red[2][256];
+    __shared__ double red[2][FIN_THREADS / 64];
     double ss = 0.0, s1 = 0.0;
     const long long nparts = track_in_lb(a) ? lb_blocks(a) : track_blocks(a.ns);
-    for (long long b = threadIdx.x; b < nparts; b += 256) {
-        ss += a.track_part[2 * b];
-        s1 += a.track_part[2 * b + 1];
-    }
-    red[0][threadIdx.x] = ss;
-    red[1][threadIdx.x] = s1;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + off];
-            red[1][threadIdx.x] += red[1][threadIdx.x + off];
+    const double2* P = (const double2*)a.track_part;
+    long long b = threadIdx.x;
+    for (; b + 7LL * FIN_THREADS < nparts; b += 8LL * FIN_THREADS) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = P[b + (long long)u * FIN_THREADS];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            ss += v[u].x;
+            s1 += v[u].y;
         }
-        __syncthreads();
     }
+    for (; b < nparts; b += FIN_THREADS) {
+        ss += P[b].x;
+        s1 += P[b].y;
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        ss += __shfl_xor(ss, m, 64);
+        s1 += __shfl_xor(s1, m, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = ss;
+        red[1][threadIdx.x >> 6] = s1;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        double t0 = 0.0, t1 = 0.0;
+        for (int w = 0; w < FIN_THREADS / 64; w++) {
+            t0 += red[0][w];
+            t1 += red[1][w];
+        }
         const int n = *a.track_n;
         if (n < a.track_cap) {
-            a.track[2 * n] = red[0][0];
-            a.track[2 * n + 1] = red[1][0];
+            a.track[2 * n] = t0;
+            a.track[2 * n + 1] = t1;
         }
         *a.track_n = n + 1;
     }
 }
-__global__ void __launch_bounds__(256) track_finish_kernel(DevArgs a) { track_finish_kernel_body(a, hw_ctx()); }
-__global__ void __launch_bounds__(256) track_finish_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+__global__ void __launch_bounds__(FIN_THREADS) track_finish_kernel(DevArgs a) { track_finish_kernel_body(a, hw_ctx()); }
+__global__ void __launch_bounds__(FIN_THREADS) track_finish_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
     const int c = chan_of(cg, nch);
     track_finish_kernel_body(as[c], chan_ctx(cg[c]));
 }
@@ -363,7 +384,7 @@ __global__ void __launch_bounds__(256) track_finish_kernel_multi(const DevArgs* 
 hipError_t launch_track(const DevArgs& a, hipStream_t st) {
     if (!a.track) return hipSuccess;
     if (!track_in_lb(a)) CGB_DISPATCH(track_kernel, dim3(track_blocks(a.ns)), dim3(256), a);
-    hipLaunchKernelGGL(track_finish_kernel, dim3(1), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(track_finish_kernel, dim3(1), dim3(FIN_THREADS), 0, st, a);
     return hipGetLastError();
 }
 
@@ -379,13 +400,13 @@ bool multi_grid_fields(int kind, const DevArgs& a, int* variant, unsigned* bx, u
         *grid = dim3(track_blocks(a.ns));
         return true;
     }
-    if (kind == MK_TRACK_FIN) { *grid = dim3(1); return true; }
+    if (kind == MK_TRACK_FIN) { *bx = FIN_THREADS; *grid = dim3(1); return true; }
     return false;
 }
 
 hipError_t launch_multi_fields(const MultiLaunch& m, const DevArgs* args, hipStream_t st) {
     if (m.kind == MK_TRACK_FIN) {
-        hipLaunchKernelGGL(track_finish_kernel_multi, dim3(m.blocks), dim3(256), 0, st, args, m.cg, m.nch);
+        hipLaunchKernelGGL(track_finish_kernel_multi, dim3(m.blocks), dim3(FIN_THREADS), 0, st, args, m.cg, m.nch);
         return hipGetLastError();
     }
     switch (m.variant) {
