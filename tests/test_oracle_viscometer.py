@@ -102,3 +102,79 @@ def test_suspension_mu_app_exceeds_plasma():
     prof = np.nanmean(uz, axis=(0, 1))
     mu = O.mu_app_le(flux, 0, prof, ny, nz, 1.0, 1.0)
     assert mu > 1.05
+
+
+def _d3q19():
+    # the textbook D3Q19 set (Sec. II, Eq. 6): rest 1/3, axes 1/18, face diagonals 1/36
+    c = [(0, 0, 0)]
+    for a in range(3):
+        for s in (1, -1):
+            v = [0, 0, 0]
+            v[a] = s
+            c.append(tuple(v))
+    for a, b in ((0, 1), (0, 2), (1, 2)):
+        for sa in (1, -1):
+            for sb in (1, -1):
+                v = [0, 0, 0]
+                v[a], v[b] = sa, sb
+                c.append(tuple(v))
+    w = [1 / 3] + [1 / 18] * 6 + [1 / 36] * 12
+    return np.array(c), np.array(w)
+
+
+def test_seam_interpolates_a_field_varying_in_z():
+    # Pins the seam's linear interpolation and Galilean shift (reading R29)
+    # where the field varies in z.  A fluid at rest whose density is a
+    # triangle wave in z with its kinks on nodes has populations w_r rho(z),
+    # linear between any two neighbouring nodes, so interpolating them at
+    # the sheared offset is exact: the population pulled across the seam
+    # must be w_r rho_s shifted by the equilibrium change for the image's
+    # velocity -/+ U e_z (Eq. 6 with u = -/+U e_z, u = 0),
+    #   d_r = w_r (rho_s - rho0) + w_r rho_s (3 c.u + 4.5 (c.u)^2 - 1.5 u^2),
+    # with rho_s the triangle wave at z - c_z +/- Delta, Delta = U t for
+    # t steps completed.  After one step at tau = 1 the density and z
+    # momentum of every node are these pulled sums (the collision keeps
+    # them).  A wrong offset (its sign, t + 1 for t, the interpolation
+    # weights swapped) or a wrong shift fails this at 1e-14.
+    nx, ny, nz, U, k, A, rho0 = 6, 3, 8, 0.05, 7, 1e-2, 1.0
+    p = synth.params(nx, ny, nz, le_u=U, tau=1.0)
+    o = O.Oracle(p)
+    o.set_particles(*EMPTY)
+    o.init_fluid()
+    o.step(k)  # Delta = U k = 0.35 at the next step
+
+    def g(z):  # triangle wave of period nz, kinks at 0 and nz/2
+        t = np.mod(z, nz) / nz
+        return 1.0 - np.abs(2.0 * t - 1.0)
+
+    z = np.arange(nz)
+    rho_z = rho0 + A * g(z)
+    rho = np.broadcast_to(rho_z[:, None, None], (nz, ny, nx)).reshape(-1)
+    o.init_fluid(rho, np.zeros((nx * ny * nz, 3)))
+    o.step(1)
+    r_o, u_o = o.fields()
+    r_o = r_o.reshape(nz, ny, nx)
+    jz_o = (r_o.reshape(-1) * u_o[:, 2]).reshape(nz, ny, nx)
+    c, w = _d3q19()
+    delta = U * k
+    for x, sign in ((0, +1), (nx - 1, -1)):  # into x = 0 along c_x = +1; into nx - 1 along c_x = -1
+        rho_e = np.full(nz, rho0)
+        jz_e = np.zeros(nz)
+        for cr, wr in zip(c, w):
+            if cr[0] == sign:
+                rs = rho0 + A * g(z - cr[2] + sign * delta)
+                uz = -sign * U
+                cu = cr[2] * uz
+                d = wr * (rs - rho0) + wr * rs * (3 * cu + 4.5 * cu * cu - 1.5 * uz * uz)
+            else:
+                d = wr * A * g(z - cr[2])
+            rho_e += d
+            jz_e += d * cr[2]
+        for y in range(ny):
+            assert np.abs(r_o[:, y, x] - rho_e).max() < 1e-14
+            assert np.abs(jz_o[:, y, x] - jz_e).max() < 1e-14
+    # interior columns: plain streaming of the density wave
+    for x in range(1, nx - 1):
+        rho_i = rho0 + sum(wr * A * g(z - cr[2]) for cr, wr in zip(c, w))
+        assert np.abs(r_o[:, 0, x] - rho_i).max() < 1e-14
+    o.close()
