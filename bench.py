@@ -371,6 +371,14 @@ def cpu_baseline(cfg, steps):
         o.step(k)
         rates[nt] = 64 ** 3 * k / (time.perf_counter() - t0) / 1e6
     O.set_num_threads(cores)
+    # the 24 x 24 x 48 channel with 20 cells (P64 parity workload), 100 steps
+    c1 = synth.config1()
+    o = O.Oracle(c1["params"], c1.get("walls"))
+    o.set_particles(c1["X"], c1["q"])
+    o.init_fluid()
+    t0 = time.perf_counter()
+    o.step(100)
+    out["channel_24x24x48_100_steps_seconds"] = round(time.perf_counter() - t0, 3)
     out["mlups_64cube_1core"] = round(rates[1], 3)
     out[f"mlups_64cube_{cores}cores"] = round(rates[cores], 3)
     cpu = "unknown"
@@ -383,6 +391,27 @@ def cpu_baseline(cfg, steps):
         pass
     out["cpu_model"] = cpu
     return out
+
+
+def copy_ceiling(nbytes=1 << 31, reps=10):
+    """The bandwidth a plain device-to-device copy reaches on this GPU (bytes
+    read plus bytes written per second), the practical ceiling beside the
+    vendor peak: HIP events on torch's stream, around reps copies."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    s = e0.elapsed_time(e1) / 1e3
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes * reps / s / 1e9
 
 
 def copy_calibration(nbytes=1 << 31, reps=4):
@@ -493,6 +522,10 @@ def main():
             "avg_launch_ms": round(lb_avg_s * 1e3, 5),
         },
     }
+    # the practical ceiling: a plain copy's bandwidth on this GPU
+    ceil_gbs = copy_ceiling()
+    line["roofline"]["copy_ceiling_gbs"] = round(ceil_gbs, 1)
+    line["roofline"]["frac_of_copy_ceiling"] = round(achieved / ceil_gbs, 4)
     # the other storage precisions of the same workload: FP32, and FP16
     # deviations stored per direction alone
     # the whole step: algorithmic bytes per step over the step time, and the
