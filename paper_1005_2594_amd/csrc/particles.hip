@@ -734,7 +734,11 @@ static int lm_resident() {
     return n;
 }
 
-// patch width 32 on lattices at most 48 wide.  A large lattice is swept in
+// Patches 32 nodes wide and 8 rows deep on every lattice: against 64 x 4
+// they build fewer halo nodes per node (340 against 396 per 256) and leave
+// no more lanes idle on any width (fewer on widths between 65 and 96, the
+// batch's wider channels: its step took 3.25 against 3.33 ms; at 256^3 the
+// two tie).  A large lattice is swept in
 // as few slabs as fill the device with one round of resident workgroups (each
 // workgroup builds two planes before its first node, so long sweeps cost
 // less, and a second, partial round would leave the device part idle); a
@@ -770,17 +774,9 @@ static void lm_launch(const DevArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_lmom(const DevArgs& a, hipStream_t st) {
-    const bool narrow = a.nx <= 48;
-    if (a.precision == CGB_P64) {
-        if (narrow) lm_launch<double, 32, 3>(a, st);
-        else lm_launch<double, 64, 3>(a, st);
-    } else if (a.precision == CGB_PMX16S) {
-        if (narrow) lm_launch<float, 32, 4>(a, st);
-        else lm_launch<float, 64, 4>(a, st);
-    } else {
-        if (narrow) lm_launch<float, 32, 3>(a, st);
-        else lm_launch<float, 64, 3>(a, st);
-    }
+    if (a.precision == CGB_P64) lm_launch<double, 32, 3>(a, st);
+    else if (a.precision == CGB_PMX16S) lm_launch<float, 32, 4>(a, st);
+    else lm_launch<float, 32, 3>(a, st);
     return hipGetLastError();
 }
 
@@ -1604,12 +1600,11 @@ hipError_t launch_integrate(const DevArgs& a, hipStream_t st) {
 namespace cgb {
 
 // ------------------------------------------------------------ batch launches
-// lmom variant: link type and patch width as the single launch chooses them
+// lmom variant: the link-moment type as the single launch chooses it
 static int lm_variant(const DevArgs& a) {
-    const int w = a.nx <= 48 ? 0 : 1;
-    if (a.precision == CGB_P64) return w;
-    if (a.precision == CGB_PMX16S) return 2 + w;
-    return 4 + w;
+    if (a.precision == CGB_P64) return 0;
+    if (a.precision == CGB_PMX16S) return 1;
+    return 2;
 }
 
 bool multi_grid_particles(int kind, const DevArgs& a, int* variant, unsigned* bx, unsigned* by, dim3* grid, int* arg) {
@@ -1630,11 +1625,8 @@ bool multi_grid_particles(int kind, const DevArgs& a, int* variant, unsigned* bx
             int tz = 0;
             switch (v) {
                 case 0: *grid = lm_grid<double, 32, 3>(a, &tz, true); break;
-                case 1: *grid = lm_grid<double, 64, 3>(a, &tz, true); break;
-                case 2: *grid = lm_grid<float, 32, 4>(a, &tz, true); break;
-                case 3: *grid = lm_grid<float, 64, 4>(a, &tz, true); break;
-                case 4: *grid = lm_grid<float, 32, 3>(a, &tz, true); break;
-                default: *grid = lm_grid<float, 64, 3>(a, &tz, true); break;
+                case 1: *grid = lm_grid<float, 32, 4>(a, &tz, true); break;
+                default: *grid = lm_grid<float, 32, 3>(a, &tz, true); break;
             }
             *arg = tz;
             return true;
@@ -1678,11 +1670,8 @@ hipError_t launch_multi_particles(const MultiLaunch& m, const DevArgs* args, hip
         case MK_LMOM:
             switch (m.variant) {
                 case 0: CGB_MULTI_GO((lmom_kernel_multi<double, 32, 3>)); break;
-                case 1: CGB_MULTI_GO((lmom_kernel_multi<double, 64, 3>)); break;
-                case 2: CGB_MULTI_GO((lmom_kernel_multi<float, 32, 4>)); break;
-                case 3: CGB_MULTI_GO((lmom_kernel_multi<float, 64, 4>)); break;
-                case 4: CGB_MULTI_GO((lmom_kernel_multi<float, 32, 3>)); break;
-                default: CGB_MULTI_GO((lmom_kernel_multi<float, 64, 3>)); break;
+                case 1: CGB_MULTI_GO((lmom_kernel_multi<float, 32, 4>)); break;
+                default: CGB_MULTI_GO((lmom_kernel_multi<float, 32, 3>)); break;
             }
             break;
         case MK_MEM: CGB_MULTI_GO(mem_reduce_kernel_multi); break;
