@@ -127,7 +127,7 @@ struct DevArgs {
                        // node: the rigid-body velocity of its cell at the node,
                        // or the wall velocity
     void* crec;        // [n] CellRec, in cell-list order (per-cell kernels)
-    double* fnode;     // [ns][4] momentum the links of each cell node carried to
+    double* fnode;     // [ns][3] momentum the links of each cell node carried to
                        // its cell in the step (Eq. 12), written by the LB kernel
                        // (not allocated with the large-lattice layout, see big)
     // Large-lattice layout (lattices whose arrays pass 4 GB, or on request):

@@ -150,7 +150,7 @@ __device__ inline void cell_node_links(const DevArgs& a, __amdgpu_buffer_rsrc_t 
     cell_links_part<P, 7, 13>(a, rA, rRA, i, f, ox, oy, oz, us, m);
     __builtin_amdgcn_sched_barrier(0);
     cell_links_part<P, 13, 19>(a, rA, rRA, i, f, ox, oy, oz, us, m);
-    double* F = a.fnode + 4 * (size_t)i;
+    double* F = a.fnode + 3 * (size_t)i;
     F[0] = m[0];
     F[1] = m[1];
     F[2] = m[2];
@@ -663,7 +663,7 @@ __device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx
                 if (CZ(r)) m2 += CZ(r) * mr;
             }
             if constexpr (!BIG) {
-                double* F = a.fnode + 4 * (size_t)ci;
+                double* F = a.fnode + 3 * (size_t)ci;
                 F[0] = m0;
                 F[1] = m1;
                 F[2] = m2;

@@ -393,9 +393,10 @@ __device__ __forceinline__ void mem_reduce_kernel_body(const DevArgs& a, const K
             m01.y = mom_from_slots(a.B, es, a.pstride, s, 1);
             m2 = mom_from_slots(a.B, es, a.pstride, s, 2);
         } else {
-            const size_t c = (size_t)sidx(a, s);
-            m01 = *(const double2*)(a.fnode + 4 * c);
-            m2 = a.fnode[4 * c + 2];
+            const double* Fn = a.fnode + 3 * (size_t)sidx(a, s);
+            m01.x = Fn[0];
+            m01.y = Fn[1];
+            m2 = Fn[2];
         }
         if (o != p) continue;
         double d[3];

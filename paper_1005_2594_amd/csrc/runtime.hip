@@ -428,7 +428,7 @@ static int alloc_state(cgb_sim* s, int cell_cap, int track_cap) {
     else HIPCHK(s, dalloc(s, &a.usol, 3 * (size_t)a.pstride * msz));
     HIPCHK(s, dalloc(s, &a.flags, (size_t)a.ns * 4));
     HIPCHK(s, dalloc(s, &a.cand, (size_t)a.ns * 4));
-    if (!a.big) HIPCHK(s, dalloc(s, &a.fnode, 32 * (size_t)(s->P.indexed ? a.pstride : a.ns)));
+    if (!a.big) HIPCHK(s, dalloc(s, &a.fnode, 24 * (size_t)(s->P.indexed ? a.pstride : a.ns)));
     if (s->P.indexed) HIPCHK(s, dalloc(s, (int32_t**)&a.cidx, (size_t)a.ns * 4));
     HIPCHK(s, dalloc(s, &s->zero_buf, 256));
     a.zero = s->zero_buf;

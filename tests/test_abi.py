@@ -96,8 +96,8 @@ def test_indexed_layout_needs_less_memory():
     dense = cgb.query_sizes(p, wall_mask=m, cell_cap=10, precision="pmx16s").arena_bytes
     idx = cgb.query_sizes(dict(p, indexed=1), wall_mask=m, cell_cap=10, precision="pmx16s").arena_bytes
     # per stored node: populations A, B (2 x 19 x 2 B), densities (2 x 2 B),
-    # link moments (4 x 4 B), node momenta (32 B); plus the 4 B index map per site
-    want = (ns - nc) * (76 + 4 + 16 + 32) - 4 * ns
+    # link moments (4 x 4 B), node momenta (24 B); plus the 4 B index map per site
+    want = (ns - nc) * (76 + 4 + 16 + 24) - 4 * ns
     assert abs((dense - idx) - want) < 0.01 * want + 16 * 256
     with pytest.raises(cgb.CgbError):
         cgb.query_sizes(dict(p, indexed=1, tau=0.8), wall_mask=m, cell_cap=10, precision="pmx16s")
