@@ -31,6 +31,11 @@ using namespace cgb;
 struct cgb_batch {
     std::vector<cgb_sim*> ch;
     hipStream_t master = nullptr;
+    // fused step: the cell list and pair forces run on a side stream beside
+    // the lattice kernels, between a fork after the rasterisation and a join
+    // before the integrator
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fk = nullptr, ev_jn = nullptr;
     hipEvent_t fork = nullptr, done = nullptr;  // captured fork; end of replays
     std::vector<hipEvent_t> join, pre;          // captured joins; eager work before a replay
     hipGraph_t graph = nullptr;
@@ -212,12 +217,38 @@ static int build_plan(cgb_batch* b) {
 
 // one time step of every channel: the plan's launches with the arguments of
 // buffer role q
+// (the cell list and the pair forces need only the step start's positions
+// and kinematics, and write arrays the lattice kernels do not read: the same
+// split as one lattice's step)
+static bool on_side(int kind) { return kind >= MK_BIN_CLEAR && kind <= MK_POT; }
 static int fused_step(cgb_batch* b, int q) {
     size_t off = 0;
+    bool forked = false, side_open = false;
     for (const MultiLaunch& m : b->plan) {
         const DevArgs* args = b->plan_args[q] + off;
-        BCHK(b, launch_multi(m, args, b->master));
         off += (size_t)m.nch;
+        if (!forked && m.kind > MK_RESOLVE) {
+            BCHK(b, hipEventRecord(b->ev_fk, b->master));
+            forked = true;
+        }
+        if (on_side(m.kind)) {
+            if (!side_open) {
+                BCHK(b, hipStreamWaitEvent(b->side, b->ev_fk, 0));
+                side_open = true;
+            }
+            BCHK(b, launch_multi(m, args, b->side));
+            continue;
+        }
+        if (m.kind == MK_INT && side_open) {
+            BCHK(b, hipEventRecord(b->ev_jn, b->side));
+            BCHK(b, hipStreamWaitEvent(b->master, b->ev_jn, 0));
+            side_open = false;
+        }
+        BCHK(b, launch_multi(m, args, b->master));
+    }
+    if (side_open) {
+        BCHK(b, hipEventRecord(b->ev_jn, b->side));
+        BCHK(b, hipStreamWaitEvent(b->master, b->ev_jn, 0));
     }
     return CGB_OK;
 }
@@ -227,12 +258,16 @@ extern "C" {
 void cgb_batch_destroy(cgb_batch* b) {
     if (!b) return;
     if (b->master) (void)hipStreamSynchronize(b->master);
+    if (b->side) (void)hipStreamSynchronize(b->side);
     drop_graph(b);
     for (cgb_sim* s : b->ch) cgb_destroy(s);
     for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
     for (hipEvent_t e : b->pre) (void)hipEventDestroy(e);
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->done) (void)hipEventDestroy(b->done);
+    if (b->ev_fk) (void)hipEventDestroy(b->ev_fk);
+    if (b->ev_jn) (void)hipEventDestroy(b->ev_jn);
+    if (b->side) (void)hipStreamDestroy(b->side);
     if (b->master) (void)hipStreamDestroy(b->master);
     delete b;
 }
@@ -244,8 +279,11 @@ int cgb_batch_create(int32_t nch, const cgb_params* ch, cgb_batch** out) {
     *out = nullptr;
     cgb_batch* b = new cgb_batch();
     if (hipStreamCreateWithFlags(&b->master, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_fk, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_jn, hipEventDisableTiming) != hipSuccess) {
         cgb_batch_destroy(b);
         return CGB_EDEVICE;
     }
