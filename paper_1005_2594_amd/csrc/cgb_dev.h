@@ -86,8 +86,9 @@ struct DevArgs {
     double* FTp;    // n*6 potential force, torque
     unsigned long long* FTt;  // n*12 cover/uncover force and torque of the step in
                               // two-word fixed point (fx_add): order-independent sums
-    unsigned* clist;  // [n][lcap] nodes each cell covers at this step's rasterisation
-    int* ccount;      // n: entries of each list
+    unsigned* clist;  // [n][lcap] nodes each cell covers at this step's rasterisation,
+                      // at the cell's record position (cell-list order)
+    int* ccount;      // n: entries of each list (by record position)
     int lcap;         // list capacity (bound on the nodes inside one cell)
     double M, Ipar, Iperp;
     double Mdrive;   // mass the body force acts on: M, or rho0 times the cell volume

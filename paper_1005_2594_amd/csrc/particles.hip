@@ -226,7 +226,9 @@ hipError_t launch_cellrec(const DevArgs& a, hipStream_t st) {
 // issued together.  Every node inside the cell that it does not own records
 // the lowest covering index (the owner keeps a node it still covers, so it
 // needs no claim), and every node inside the cell is appended to the cell's
-// list, in the fixed order (footprint, slab, plane, lane): after the resolve
+// list (kept at the cell's record position, so that the momentum sum can load
+// it without waiting for the record), in the fixed order (footprint, slab,
+// plane, lane): after the resolve
 // pass the nodes a cell owns are the listed nodes whose owner it is, which
 // the momentum exchange walks instead of the box.  The waves of a workgroup
 // work independently.
@@ -245,7 +247,7 @@ __device__ __forceinline__ void claim_kernel_body(const DevArgs& a, const KCtx& 
     const int p = cr.p;
     const int lo[3] = {cr.lo[0], cr.lo[1], cr.lo[2]};
     const int ext[3] = {cr.ext[0], cr.ext[1], cr.ext[2]};
-    unsigned* lst = a.clist + (size_t)p * (size_t)a.lcap;
+    unsigned* lst = a.clist + (size_t)k * (size_t)a.lcap;
     int cnt = 0;  // the same in every lane
     for (int bx = 0; bx < ext[0]; bx += 8)
         for (int by = 0; by < ext[1]; by += 8) {
@@ -285,7 +287,7 @@ __device__ __forceinline__ void claim_kernel_body(const DevArgs& a, const KCtx& 
             }
         }
     if (lane == 0) {
-        a.ccount[p] = cnt < a.lcap ? cnt : a.lcap;
+        a.ccount[k] = cnt < a.lcap ? cnt : a.lcap;
         if (cnt > a.lcap) atomicOr(a.status, ST_LIST_OVERFLOW);
     }
 }
@@ -371,16 +373,31 @@ __device__ __forceinline__ void mem_reduce_kernel_body(const DevArgs& a, const K
     const int k = 2 * __builtin_amdgcn_readfirstlane(xcd_block((int)G.bx, (int)G.gx) * CPW + wv) + half;
     if (2 * (k >> 1) >= a.n) return;  // whole wave: no cell
     const bool live = k < a.n;        // the second half of the last wave may have none
-    const CellRec cr = ((const CellRec*)a.crec)[live ? k : k - 1];
+    const int kr = live ? k : k - 1;
+    // the record, the list length and the first 32 list entries sit at the
+    // record position: their loads go out together (entries past the length
+    // are loaded and not used)
+    const unsigned* lst = a.clist + (size_t)kr * (size_t)a.lcap;
+    const unsigned ent0 = hl < a.lcap ? lst[hl] : 0u;
+    const int cnt0 = a.ccount[kr];
+    const CellRec cr = ((const CellRec*)a.crec)[kr];
     const int p = cr.p;
     // the record kernel flags a cell whose box is not valid; its list was not written
-    int cnt = (live && cr.ok) ? a.ccount[p] : 0;
+    int cnt = (live && cr.ok) ? cnt0 : 0;
     if (cnt > a.lcap) cnt = a.lcap;
-    const unsigned* lst = a.clist + (size_t)p * (size_t)a.lcap;
+    // the cover/uncover sums of the transitions, loaded beside the node momenta
+    double ftt[6];
+    {
+        const unsigned long long* Ft = a.FTt + 12 * (long long)p;
+#pragma unroll
+        for (int c = 0; c < 6; c++) ftt[c] = fx_value(Ft + 2 * c);
+    }
     const unsigned nx = (unsigned)a.nx, plane = (unsigned)a.nx * (unsigned)a.ny;
     double FT[6] = {0, 0, 0, 0, 0, 0};
+    unsigned nxt = ent0;
     for (int e = hl; e < cnt; e += 32) {
-        const unsigned ent = lst[e];
+        const unsigned ent = nxt;
+        if (e + 32 < cnt) nxt = lst[e + 32];  // the lane's next entry, one pass ahead
         const unsigned s = ent & ~LIST_OWNED;
         const int o = (ent & LIST_OWNED) ? p : a.owner[s];
         double2 m01;
@@ -413,9 +430,8 @@ __device__ __forceinline__ void mem_reduce_kernel_body(const DevArgs& a, const K
         for (int off = 16; off >= 1; off >>= 1) FT[c] += __shfl_xor(FT[c], off, 64);
     if (hl == 0 && live) {
         double* F = a.FTh + 6 * (long long)p;
-        const unsigned long long* Ft = a.FTt + 12 * (long long)p;
 #pragma unroll
-        for (int c = 0; c < 6; c++) F[c] = FT[c] + fx_value(Ft + 2 * c);
+        for (int c = 0; c < 6; c++) F[c] = FT[c] + ftt[c];
     }
 }
 __global__ void __launch_bounds__(64 * CPW) mem_reduce_kernel(DevArgs a) { mem_reduce_kernel_body(a, hw_ctx()); }
