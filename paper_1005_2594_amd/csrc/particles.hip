@@ -1299,8 +1299,13 @@ __device__ inline void wall_vec(const DevArgs& a, const double* Xi, unsigned w, 
 
 // Pair forces (Eqs. 16-18) on lattices without walls: one thread per cell,
 // cells in cell-list order (neighbouring threads share neighbour bins).  The
-// candidates of a bin row are read CB at a time with independent loads.
+// bounds of the up to 18 candidate ranges (9 bin rows, each in one or two
+// parts) are loaded together; the candidates of all ranges are then walked
+// as one sequence, CB at a time with independent loads.  The walk keeps the
+// order (z row, y row, part, position) of a row-by-row walk, so the sums are
+// the same.
 constexpr int CB = 2;
+constexpr int NRANGE = 18;
 __device__ __forceinline__ void potentials_kernel_body(const DevArgs& a, const KCtx& G) {
     const int k = xcd_block((int)G.bx, (int)G.gx) * (int)blockDim.x + (int)threadIdx.x;
     if (k >= a.n) return;
@@ -1313,38 +1318,51 @@ __device__ __forceinline__ void potentials_kernel_body(const DevArgs& a, const K
     double F[3] = {0, 0, 0}, T[3] = {0, 0, 0};
     const int b = a.pbin[i];
     const int bxi = b % a.nb[0], byi = (b / a.nb[0]) % a.nb[1], bzi = b / (a.nb[0] * a.nb[1]);
-    int xr[4], ly[3], lz[3];
+    int xr[4], ly[3] = {0, 0, 0}, lz[3] = {0, 0, 0};
     row_xranges(a, bxi, xr);
     const int nyb = axis_bins(a, 1, byi, ly), nzb = axis_bins(a, 2, bzi, lz);
-    for (int iz = 0; iz < nzb; iz++)
-        for (int iy = 0; iy < nyb; iy++) {
-            const int row = a.nb[0] * (pick3(ly, iy) + a.nb[1] * pick3(lz, iz));
-            for (int h = 0; h < 2; h++) {
-                const int x0 = h ? xr[2] : xr[0], x1 = h ? xr[3] : xr[1];
-                if (x1 <= x0) continue;
-                const int t0 = a.bin_start[row + x0], t1 = a.bin_start[row + x1];
-                for (int t = t0; t < t1; t += CB) {
-                    SortedPos e[CB];
+    // range q = 6 iz + 2 iy + h: first list position and start in the sequence
+    int t0[NRANGE], pre[NRANGE + 1];
 #pragma unroll
-                    for (int q = 0; q < CB; q++) e[q] = S[t + q < t1 ? t + q : t1 - 1];
+    for (int q = 0; q < NRANGE; q++) {
+        const int iz = q / 6, iy = (q / 2) % 3, h = q & 1;
+        const int x0 = h ? xr[2] : xr[0], x1 = h ? xr[3] : xr[1];
+        const int row = a.nb[0] * (pick3(ly, iy) + a.nb[1] * pick3(lz, iz));
+        const bool on = iz < nzb && iy < nyb && x1 > x0;
+        t0[q] = on ? a.bin_start[row + x0] : 0;
+        pre[q + 1] = on ? a.bin_start[row + x1] : 0;  // end, until the prefix below
+    }
+    pre[0] = 0;
 #pragma unroll
-                    for (int q = 0; q < CB; q++) {
-                        const int j = (int)e[q].id;
-                        if (t + q >= t1 || j == i) continue;
-                        double rv[3];
-                        pair_rv(a, Xi, e[q], rv);
-                        if (!(dist2_exact(rv) < a.r_cut2)) continue;
-                        const double* kj = a.kin + 12 * (long long)j;
-                        const double oj[3] = {kj[9], kj[10], kj[11]};
-                        pair_term(a, rv, oi, oj, F, T);
-                    }
-                }
-            }
+    for (int q = 0; q < NRANGE; q++) pre[q + 1] = pre[q] + (pre[q + 1] - t0[q]);
+    const int total = pre[NRANGE];
+    for (int u = 0; u < total; u += CB) {
+        SortedPos e[CB];
+#pragma unroll
+        for (int c = 0; c < CB; c++) {
+            const int w = u + c;
+            int t = k;  // past the sequence: the cell's own entry, not used
+#pragma unroll
+            for (int q = 0; q < NRANGE; q++)
+                if (w >= pre[q] && w < pre[q + 1]) t = t0[q] + (w - pre[q]);
+            e[c] = S[t];
         }
+#pragma unroll
+        for (int c = 0; c < CB; c++) {
+            const int j = (int)e[c].id;
+            if (u + c >= total || j == i) continue;
+            double rv[3];
+            pair_rv(a, Xi, e[c], rv);
+            if (!(dist2_exact(rv) < a.r_cut2)) continue;
+            const double* kj = a.kin + 12 * (long long)j;
+            const double oj[3] = {kj[9], kj[10], kj[11]};
+            pair_term(a, rv, oi, oj, F, T);
+        }
+    }
     for (int c = 0; c < 3; c++) { a.FTp[6 * i + c] = F[c]; a.FTp[6 * i + 3 + c] = T[c]; }
 }
-__global__ void potentials_kernel(DevArgs a) { potentials_kernel_body(a, hw_ctx()); }
-__global__ void potentials_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+__global__ void __launch_bounds__(POT_BLOCK) potentials_kernel(DevArgs a) { potentials_kernel_body(a, hw_ctx()); }
+__global__ void __launch_bounds__(POT_BLOCK) potentials_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
     const int c = chan_of(cg, nch);
     potentials_kernel_body(as[c], chan_ctx(cg[c]));
 }
