@@ -1208,6 +1208,9 @@ __device__ inline double dist2_exact(const double* rv) {
 // a = r.o_i, b = r.o_j, g = o_i.o_j.  Returns -dU/dX_i and -o_i x dU/do_i.
 __device__ void pair_term(const DevArgs& a, const double* rv, const double* oi, const double* oj,
                           double* F, double* Ti) {
+    // fused multiply-adds only within one expression, so that the term rounds
+    // alike wherever it is inlined
+#pragma clang fp contract(on)
     const double r2 = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
     if (r2 == 0.0) return;
     const double r = sqrt(r2);
@@ -1245,6 +1248,7 @@ __device__ void pair_term(const DevArgs& a, const double* rv, const double* oi, 
 
 // cell-wall term for rvec = X_i - x_wall (Eqs. 19-20)
 __device__ void wall_term(const DevArgs& a, const double* rv, const double* o, double* F, double* Ti) {
+#pragma clang fp contract(on)  // as in pair_term
     const double r2 = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
     if (r2 == 0.0) return;
     const double r = sqrt(r2);
@@ -1301,14 +1305,20 @@ __device__ inline void wall_vec(const DevArgs& a, const double* Xi, unsigned w, 
 // cells in cell-list order (neighbouring threads share neighbour bins).  The
 // bounds of the up to 18 candidate ranges (9 bin rows, each in one or two
 // parts) are loaded together; the candidates of all ranges are then walked
-// as one sequence, CB at a time with independent loads.  The walk keeps the
-// order (z row, y row, part, position) of a row-by-row walk, so the sums are
-// the same.
+// as one sequence, CB at a time with independent loads, in the order (z row,
+// y row, part, position).  The partners in range are listed first (LDS, per
+// thread) and evaluated after the walk in that order, so that a wave runs the
+// pair term about as often as its busiest cell has partners, not once per
+// candidate; a full list is evaluated on the spot, in order.
 constexpr int CB = 2;
 constexpr int NRANGE = 18;
+constexpr int PLIST = 16;
 __device__ __forceinline__ void potentials_kernel_body(const DevArgs& a, const KCtx& G) {
-    const int k = xcd_block((int)G.bx, (int)G.gx) * (int)blockDim.x + (int)threadIdx.x;
-    if (k >= a.n) return;
+    __shared__ int plt[PLIST][POT_BLOCK];  // [slot][thread]: list position of a partner
+    __shared__ int plj[PLIST][POT_BLOCK];  // and its cell index
+    const int tid = (int)threadIdx.x;
+    const int k = xcd_block((int)G.bx, (int)G.gx) * (int)blockDim.x + tid;
+    if (k >= a.n) return;  // no barrier below: each thread uses its own list column
     const SortedPos* S = (const SortedPos*)a.Xs;
     const SortedPos me = S[k];
     const int i = (int)me.id;
@@ -1336,8 +1346,22 @@ __device__ __forceinline__ void potentials_kernel_body(const DevArgs& a, const K
 #pragma unroll
     for (int q = 0; q < NRANGE; q++) pre[q + 1] = pre[q] + (pre[q + 1] - t0[q]);
     const int total = pre[NRANGE];
+    int np = 0;
+    // the listed partners, in list order
+    auto evaluate = [&]() {
+        for (int s = 0; s < np; s++) {
+            const SortedPos e = S[plt[s][tid]];
+            const double* kj = a.kin + 12 * (long long)plj[s][tid];
+            const double oj[3] = {kj[9], kj[10], kj[11]};
+            double rv[3];
+            pair_rv(a, Xi, e, rv);
+            pair_term(a, rv, oi, oj, F, T);
+        }
+        np = 0;
+    };
     for (int u = 0; u < total; u += CB) {
         SortedPos e[CB];
+        int tc[CB];
 #pragma unroll
         for (int c = 0; c < CB; c++) {
             const int w = u + c;
@@ -1345,6 +1369,7 @@ __device__ __forceinline__ void potentials_kernel_body(const DevArgs& a, const K
 #pragma unroll
             for (int q = 0; q < NRANGE; q++)
                 if (w >= pre[q] && w < pre[q + 1]) t = t0[q] + (w - pre[q]);
+            tc[c] = t;
             e[c] = S[t];
         }
 #pragma unroll
@@ -1354,11 +1379,13 @@ __device__ __forceinline__ void potentials_kernel_body(const DevArgs& a, const K
             double rv[3];
             pair_rv(a, Xi, e[c], rv);
             if (!(dist2_exact(rv) < a.r_cut2)) continue;
-            const double* kj = a.kin + 12 * (long long)j;
-            const double oj[3] = {kj[9], kj[10], kj[11]};
-            pair_term(a, rv, oi, oj, F, T);
+            if (np == PLIST) evaluate();
+            plt[np][tid] = tc[c];
+            plj[np][tid] = j;
+            np++;
         }
     }
+    evaluate();
     for (int c = 0; c < 3; c++) { a.FTp[6 * i + c] = F[c]; a.FTp[6 * i + 3 + c] = T[c]; }
 }
 __global__ void __launch_bounds__(POT_BLOCK) potentials_kernel(DevArgs a) { potentials_kernel_body(a, hw_ctx()); }
