@@ -1248,7 +1248,6 @@ __device__ void pair_term(const DevArgs& a, const double* rv, const double* oi, 
 
 // cell-wall term for rvec = X_i - x_wall (Eqs. 19-20)
 __device__ void wall_term(const DevArgs& a, const double* rv, const double* o, double* F, double* Ti) {
-#pragma clang fp contract(on)  // as in pair_term
     const double r2 = rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
     if (r2 == 0.0) return;
     const double r = sqrt(r2);

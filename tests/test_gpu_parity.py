@@ -282,3 +282,32 @@ def test_ragged_box_moving_cells_p64():
     say("  owner changes over 20 steps:", moved)
     assert moved > 0
     g.close()
+
+
+def test_crowded_cell_pair_forces_p64():
+    # a tight cluster: some cells have more partners in range than the pair
+    # kernel's per-thread list holds (16), so it evaluates full lists during
+    # the walk as well as after it; pair forces and torques against the
+    # oracle after one step (fluid at rest: the hydrodynamic parts are
+    # covered by the suspension tests)
+    p = synth.params(24, 24, 24)
+    rng = np.random.default_rng(29)
+    n_in, n_out = 34, 20
+    d = rng.standard_normal((n_in, 3))
+    d *= (3.4 * rng.random((n_in, 1)) ** (1 / 3)) / np.linalg.norm(d, axis=1, keepdims=True)
+    X = np.vstack([12.0 + d, synth.uniform_positions(rng, n_out, (24, 24, 24))])
+    q = synth.random_quaternions(rng, len(X))
+    # partners within the cut-off, minimum image on the periodic box
+    r = X[:, None, :] - X[None, :, :]
+    r -= 24.0 * np.round(r / 24.0)
+    close = (np.sum(r * r, axis=2) < p["r_cut"] ** 2).sum(axis=1) - 1
+    say(f"case: crowded cluster, {len(X)} cells, most partners of one cell {close.max()}")
+    assert close.max() > 16
+    g, o = make_pair(p, X, q)
+    g.step(1); o.step(1)
+    assert np.array_equal(g.pairs(), o.pairs())
+    for name, a, b in zip(("force", "torque"), g.forces()[2:], o.forces()[2:]):
+        e = rel_inf(a, b)
+        say(f"  pair {name}: {e:.2e}")
+        assert np.max(np.abs(b)) > 0
+        assert e <= 1e-12
