@@ -23,7 +23,7 @@ the paper's 1024^2 x 2048 system with 4.1e6 cells in the large-lattice
 layout (when the device has the memory free); and the oracle on the host
 cores ("cpu_baseline").
 
-Prints one JSON line.  --gpus N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -448,7 +448,7 @@ def main():
                     help="run only the 64-channel ensemble and print its record (profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "the benchmark runs on one GPU; runs on several GPUs are not supported",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     if args.copy_calibrate:
