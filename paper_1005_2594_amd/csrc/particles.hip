@@ -727,10 +727,15 @@ __device__ __forceinline__ void lmom_kernel_body(const DevArgs& a, const KCtx& G
         }
     }
 }
+// waves per SIMD each form holds without spilling (the split codec's form
+// needs 80 registers: asking for 6 keeps it there, where 8 left it at 81 and
+// so at 5 waves)
+template <class M, int NC>
+constexpr int LM_WAVES = sizeof(M) == 4 ? (NC == 4 ? 6 : 8) : 5;
 template <class M, int TX, int NC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(M) == 4 ? 8 : 5))) lmom_kernel(DevArgs a, int tz) { lmom_kernel_body<M, TX, NC>(a, hw_ctx(), tz); }
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LM_WAVES<M, NC>))) lmom_kernel(DevArgs a, int tz) { lmom_kernel_body<M, TX, NC>(a, hw_ctx(), tz); }
 template <class M, int TX, int NC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(M) == 4 ? 8 : 5))) lmom_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LM_WAVES<M, NC>))) lmom_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
     unsigned t;
     const int c = chan_of_xcd(cg, nch, &t);
     lmom_kernel_body<M, TX, NC>(as[c], chan_ctx_at(cg[c], t), cg[c].arg);
