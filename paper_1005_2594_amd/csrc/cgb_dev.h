@@ -157,6 +157,10 @@ struct DevArgs {
                         // seam: side 0 into x = 0 along c_x = +1, side 1 into x = nx-1 along c_x = -1
     double* le_part;    // per-block partial sums of Delta p_LE,z
     double* le_rec;     // [track_cap] Delta p_LE,z per recorded step (with the track record)
+    int nt_out;        // 1: the populations outgrow the 256 MB last-level cache, where the next
+                       // launch would find nothing of them cached anyway: the LB (dense and
+                       // large-lattice layouts) and the split codec's link moments are launched
+                       // in their forms with non-temporal output stores
     int tile[3];       // LB launch shape the kernels were configured for
     int* scan_tmp;     // block totals of the bin scan
     int nbody_blk;     // blocks of the integrate kernel (body_part has 3 per block)
@@ -257,6 +261,17 @@ template <> __device__ inline void bstore<_Float16>(_Float16 v, __amdgpu_buffer_
 }
 template <> __device__ inline void bstore<uint16_t>(uint16_t v, __amdgpu_buffer_rsrc_t r, unsigned off) {
     __builtin_amdgcn_raw_buffer_store_b16(v, r, off, 0, 0);
+}
+// the same store with the non-temporal cache policy (NT, policy bit 1): for
+// streamed output that no wave of the launch reads back, so that it does not
+// take the L2 lines the launch's loads reuse
+template <class T> __device__ inline void bstore_nt(T v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0, 0)), v), r, off, 0, 2);
+    else if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 2);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, 0, 2);
 }
 
 // A cell node's momentum in its own output slots (large-lattice layout):

@@ -440,6 +440,7 @@ template <> struct LbMem<false> {
     __device__ LbMem(const void* p, unsigned long long bytes, const void*) : r(make_rsrc(p, bytes)) {}
     template <class T> __device__ T ld(I e, bool on) const { return bload<T>(r, on ? e * (I)sizeof(T) : OOB); }
     template <class T> __device__ void st(T v, I e) const { bstore<T>(v, r, e * (I)sizeof(T)); }
+    template <class T> __device__ void stnt(T v, I e) const { bstore_nt<T>(v, r, e * (I)sizeof(T)); }
 };
 template <> struct LbMem<true> {
     using I = unsigned long long;
@@ -449,6 +450,7 @@ template <> struct LbMem<true> {
         : p((char*)const_cast<void*>(q)), z((const char*)zero) {}
     template <class T> __device__ T ld(I e, bool on) const { return *(const T*)(on ? p + e * sizeof(T) : z); }
     template <class T> __device__ void st(T v, I e) const { *(T*)(p + e * sizeof(T)) = v; }
+    template <class T> __device__ void stnt(T v, I e) const { __builtin_nontemporal_store(v, (T*)(p + e * sizeof(T))); }
 };
 
 // tau = 1 (the paper's operating point, Sec. IV): the post-collision state is
@@ -494,7 +496,9 @@ __device__ __forceinline__ void lb_track_partial(const DevArgs& a, const KCtx& G
         a.track_part[2 * slot + 1] = s1;
     }
 }
-template <int P, int TZ, int LAY>
+// NT: the populations and densities are stored non-temporally (lattices
+// whose output outgrows the last-level cache, see nt_out)
+template <int P, int TZ, int LAY, bool NT = false>
 __device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx& G) {
     using Cd = Codec<P>;
     using T = typename Cd::T;
@@ -749,9 +753,15 @@ __device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx
         }
         }
         if (inb && cw >= 0) {  // (walls of the indexed layout store nothing)
+            if constexpr (NT) {
 #pragma unroll
-            for (int r = 0; r < 19; r++) mB.template st<T>(ob[r], (I)r * ps + ci);
-            mRB.template st<T>(orho, ci);
+                for (int r = 0; r < 19; r++) mB.template stnt<T>(ob[r], (I)r * ps + ci);
+                mRB.template stnt<T>(orho, ci);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 19; r++) mB.template st<T>(ob[r], (I)r * ps + ci);
+                mRB.template st<T>(orho, ci);
+            }
         }
         if constexpr (IDX) {
 #pragma unroll
@@ -760,8 +770,8 @@ __device__ __forceinline__ void lb_kernel_tau1_body(const DevArgs& a, const KCtx
     }
     if (track_in_lb(a)) lb_track_partial(a, G, inb ? (double)tacc : 0.0, yc);
 }
-template <int P, int TZ, int LAY>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LAY == LAY_DENSE ? 4 : 3))) lb_kernel_tau1(DevArgs a) { lb_kernel_tau1_body<P, TZ, LAY>(a, hw_ctx()); }
+template <int P, int TZ, int LAY, bool NT = false>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LAY == LAY_DENSE ? 4 : 3))) lb_kernel_tau1(DevArgs a) { lb_kernel_tau1_body<P, TZ, LAY, NT>(a, hw_ctx()); }
 template <int P, int TZ, int LAY>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LAY == LAY_DENSE ? 4 : 3))) lb_kernel_tau1_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
     unsigned t;
@@ -782,25 +792,30 @@ static hipError_t launch_lb_p(const DevArgs& a, LaunchCfg cfg, hipStream_t st) {
         // the large-lattice and indexed layouts: tau = 1 and 16-node sweeps
         // only (checked when the handle is created and when tiles are set)
         if (!t1 || cfg.tz != 16) return hipErrorInvalidValue;
-        if (a.big) hipLaunchKernelGGL((lb_kernel_tau1<P, 16, LAY_BIG>), grd, blk, 0, st, a);
+        if (a.big && a.nt_out) hipLaunchKernelGGL((lb_kernel_tau1<P, 16, LAY_BIG, true>), grd, blk, 0, st, a);
+        else if (a.big) hipLaunchKernelGGL((lb_kernel_tau1<P, 16, LAY_BIG>), grd, blk, 0, st, a);
         else hipLaunchKernelGGL((lb_kernel_tau1<P, 16, LAY_IDX>), grd, blk, 0, st, a);
         return hipGetLastError();
     }
     switch (cfg.tz) {
         case 4:
-            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 4, LAY_DENSE>), grd, blk, 0, st, a);
+            if (t1 && a.nt_out) hipLaunchKernelGGL((lb_kernel_tau1<P, 4, LAY_DENSE, true>), grd, blk, 0, st, a);
+            else if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 4, LAY_DENSE>), grd, blk, 0, st, a);
             else hipLaunchKernelGGL((lb_kernel_tau<P, 4>), grd, blk, 0, st, a);
             break;
         case 8:
-            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 8, LAY_DENSE>), grd, blk, 0, st, a);
+            if (t1 && a.nt_out) hipLaunchKernelGGL((lb_kernel_tau1<P, 8, LAY_DENSE, true>), grd, blk, 0, st, a);
+            else if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 8, LAY_DENSE>), grd, blk, 0, st, a);
             else hipLaunchKernelGGL((lb_kernel_tau<P, 8>), grd, blk, 0, st, a);
             break;
         case 16:
-            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 16, LAY_DENSE>), grd, blk, 0, st, a);
+            if (t1 && a.nt_out) hipLaunchKernelGGL((lb_kernel_tau1<P, 16, LAY_DENSE, true>), grd, blk, 0, st, a);
+            else if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 16, LAY_DENSE>), grd, blk, 0, st, a);
             else hipLaunchKernelGGL((lb_kernel_tau<P, 16>), grd, blk, 0, st, a);
             break;
         case 32:
-            if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 32, LAY_DENSE>), grd, blk, 0, st, a);
+            if (t1 && a.nt_out) hipLaunchKernelGGL((lb_kernel_tau1<P, 32, LAY_DENSE, true>), grd, blk, 0, st, a);
+            else if (t1) hipLaunchKernelGGL((lb_kernel_tau1<P, 32, LAY_DENSE>), grd, blk, 0, st, a);
             else hipLaunchKernelGGL((lb_kernel_tau<P, 32>), grd, blk, 0, st, a);
             break;
         default: return hipErrorInvalidValue;

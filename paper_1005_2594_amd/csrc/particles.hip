@@ -631,7 +631,10 @@ __device__ inline void lm_lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\t
 // direction r (the node's own for the rest direction and for a bounced
 // population), and stores E = 6 rho(x) K + T, which the LB adds to its sums
 // of the FP16 residuals; every site is written (zeros at non-fluid nodes).
-template <class M, int TX, int NC>
+// NT: the moments are stored non-temporally (the split codec's form, which
+// writes every site, on lattices whose output outgrows the last-level cache,
+// see nt_out); the LB, a later launch, reads them
+template <class M, int TX, int NC, bool NT = false>
 __device__ __forceinline__ void lmom_kernel_body(const DevArgs& a, const KCtx& G, int tz) {
     using S = LmShape<TX>;
     __shared__ M U[4 * NC * S::NP];  // [slot][component][HY][HX]
@@ -719,10 +722,17 @@ __device__ __forceinline__ void lmom_kernel_body(const DevArgs& a, const KCtx& G
             }
             const long long c = sidx(a, s);
             if (c >= 0) {
-                K[c] = k0;
-                K[ps + c] = k1;
-                K[2 * ps + c] = k2;
-                K[3 * ps + c] = k3;
+                if constexpr (NT) {
+                    __builtin_nontemporal_store(k0, K + c);
+                    __builtin_nontemporal_store(k1, K + ps + c);
+                    __builtin_nontemporal_store(k2, K + 2 * ps + c);
+                    __builtin_nontemporal_store(k3, K + 3 * ps + c);
+                } else {
+                    K[c] = k0;
+                    K[ps + c] = k1;
+                    K[2 * ps + c] = k2;
+                    K[3 * ps + c] = k3;
+                }
             }
         }
     }
@@ -732,8 +742,8 @@ __device__ __forceinline__ void lmom_kernel_body(const DevArgs& a, const KCtx& G
 // so at 5 waves)
 template <class M, int NC>
 constexpr int LM_WAVES = sizeof(M) == 4 ? (NC == 4 ? 6 : 8) : 5;
-template <class M, int TX, int NC>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LM_WAVES<M, NC>))) lmom_kernel(DevArgs a, int tz) { lmom_kernel_body<M, TX, NC>(a, hw_ctx(), tz); }
+template <class M, int TX, int NC, bool NT = false>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LM_WAVES<M, NC>))) lmom_kernel(DevArgs a, int tz) { lmom_kernel_body<M, TX, NC, NT>(a, hw_ctx(), tz); }
 template <class M, int TX, int NC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LM_WAVES<M, NC>))) lmom_kernel_multi(const DevArgs* __restrict__ as, const ChanGrid* __restrict__ cg, int nch) {
     unsigned t;
@@ -792,7 +802,8 @@ template <class M, int TX, int NC>
 static void lm_launch(const DevArgs& a, hipStream_t st) {
     int tz = 0;
     const dim3 g = lm_grid<M, TX, NC>(a, &tz);
-    hipLaunchKernelGGL((lmom_kernel<M, TX, NC>), g, dim3(256), 0, st, a, tz);
+    if (NC == 4 && a.nt_out) hipLaunchKernelGGL((lmom_kernel<M, TX, NC, true>), g, dim3(256), 0, st, a, tz);
+    else hipLaunchKernelGGL((lmom_kernel<M, TX, NC>), g, dim3(256), 0, st, a, tz);
 }
 
 hipError_t launch_lmom(const DevArgs& a, hipStream_t st) {

@@ -362,6 +362,10 @@ static int setup_host(cgb_sim* s, const cgb_params* p, const uint8_t* wall_mask,
         a.pstride = (std::max(nc, 1ll) + 255) / 256 * 256;
         s->n_stored = nc;
     }
+    // streamed outputs bypass the caches only where the populations outgrow
+    // the 256 MB last-level cache (smaller lattices find last step's output
+    // there)
+    a.nt_out = 19.0 * (double)a.pstride * (double)s->esize > 256.0 * 1024 * 1024 ? 1 : 0;
     hi.ysin.resize((size_t)a.ny);
     for (int y = 0; y < a.ny; y++) hi.ysin[(size_t)y] = sin(2.0 * M_PI * y / (double)a.ny);
     // cell-list geometry: bin edge >= max(cut-off, wall potential range)
